@@ -1,0 +1,172 @@
+/*
+ * lorax.h - C ABI of liblorax.so: hierarchical factorization of a sparse matrix
+ * with low-rank compression of well-separated fill-in (extended sparsification),
+ * its forward/backward solve, and GMRES preconditioned by that solve, on one
+ * AMD MI355X (gfx950).
+ *
+ * The operations follow Pouransari, Coulier, Darve, "Fast hierarchical solvers
+ * for sparse matrices using extended sparsification and low-rank approximation":
+ *   lrx_factor  Algorithm 1 (Sec. 4): level-by-level MergeRedNodes, Compress,
+ *               Eliminate(super-node), Eliminate(black node) on the H-tree of
+ *               Def. "hierarchical tree", truncation by eqn. cutOff1.
+ *   lrx_solve   Algorithms 2-4 (Sec. 4.5): SetRHS, forward SolveL, backward
+ *               SolveU and SplitVar; x ~ A^{-1} b.
+ *   lrx_gmres   Sec. 6.2: GMRES with the solve as preconditioner.
+ *
+ * Conventions for every call
+ *   - Every call returns an lrx_status; nothing throws or aborts across the ABI.
+ *     On an error the outputs are left untouched (except where stated) and
+ *     lrx_last_error() returns a message for the calling thread.
+ *   - Host pointers are plain CPU memory owned by the caller; the caller may free
+ *     them as soon as the call returns.  Device pointers (the *_dev calls) are
+ *     HBM allocations of the caller on the current HIP device.
+ *   - A handle owns all device memory it allocates and releases it in lrx_free.
+ *     Solves on one handle may run concurrently on different streams only if
+ *     each stream has its own handle; calls on one handle are not thread-safe.
+ *   - Matrices are CSR, 0-based, int64 row pointers, int32 column indices,
+ *     columns sorted and unique within each row, FP64 values, all finite.
+ */
+#ifndef LORAX_H
+#define LORAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LRX_OK = 0,
+    LRX_EINVAL = 1,     /* malformed argument: CSR, tree, options, sizes, NaN/Inf, stale handle */
+    LRX_ENOMEM = 2,     /* device allocation failed or the factor exceeds hbm_budget_bytes */
+    LRX_ESINGULAR = 3,  /* a pivot block is exactly singular after partial pivoting */
+    LRX_ENOCONV = 4,    /* GMRES reached maxit before tol (best x, iters, relres returned) */
+    LRX_EDEVICE = 5,    /* HIP runtime error or no usable gfx950 device */
+    LRX_EBUSY = 6       /* reserved */
+} lrx_status;
+
+typedef enum { LRX_FP64 = 0 } lrx_precision;
+typedef enum { LRX_COLORED = 0, LRX_NATURAL = 1 } lrx_order;
+
+typedef struct lrx_handle_s* lrx_handle;     /* opaque */
+
+/* Sparse matrix A (n x n) in CSR form, host memory. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t* row_ptr;   /* n+1 entries, row_ptr[0] = 0, row_ptr[n] = nnz */
+    const int32_t* col_idx;   /* nnz entries, sorted and unique within a row */
+    const double* val;        /* nnz entries */
+} lrx_csr;
+
+/* Nested binary partitionings P_0..P_depth (Def. "nested partitionings"):
+ * perm[t] is the original row/column at tree position t; leaf c holds tree
+ * positions [leaf_ptr[c], leaf_ptr[c+1]); cluster j of level i is the union of
+ * leaves [j*2^(depth-i), (j+1)*2^(depth-i)).  Leaves must be non-empty,
+ * depth >= 1, 2^depth + 1 entries in leaf_ptr. */
+typedef struct {
+    int32_t depth;
+    const int32_t* perm;
+    const int32_t* leaf_ptr;
+} lrx_tree;
+
+typedef struct {
+    double epsilon;            /* truncation: keep sigma_k >= epsilon * sigma_0 (eqn. cutOff1);
+                                  0 <= epsilon < 1; 0 keeps every singular value (exact) */
+    int32_t precision;         /* lrx_precision */
+    int32_t order;             /* lrx_order: order of the super-nodes inside a level */
+    int64_t hbm_budget_bytes;  /* 0 = no limit; otherwise LRX_ENOMEM when exceeded */
+    void* stream;              /* hipStream_t used by the handle, or NULL for the null stream */
+} lrx_opts;
+
+/* Counters of a factorization (sizes in elements/bytes, times in ms). */
+typedef struct {
+    int32_t depth;
+    int32_t n_compressions;
+    int32_t n_colour_steps;        /* sum over levels of colours */
+    int32_t max_rank;
+    double mean_rank;
+    int32_t rank_max_by_level[32]; /* index = level, 0..depth */
+    double rank_mean_by_level[32];
+    double mean_node_size_by_level[32];
+    int64_t extended_size;         /* n + auxiliary variables */
+    int64_t factor_bytes;          /* device bytes of stored blocks */
+    int64_t solve_bytes;           /* bytes one solve reads from stored blocks */
+    int64_t factor_flops;          /* algorithmic flops of the factorization */
+    double t_plan_ms;              /* host symbolic planning */
+    double t_factor_ms;            /* whole lrx_factor call */
+} lrx_stats_t;
+
+/* Symbolic counts, computed on the host without any device call. */
+typedef struct {
+    int32_t depth;
+    int32_t n_supernodes;          /* super-nodes over all levels (= 2^depth - 1) */
+    int32_t n_colour_steps;
+    int32_t colours_by_level[32];
+    int64_t n_candidates;          /* well-separated neighbours over all compressions */
+    int64_t n_schur_pairs;         /* (in-neighbour, out-neighbour) updates over all eliminations */
+    int64_t n_edges_created;
+    int64_t candidates_by_level[32];
+} lrx_plan_info;
+
+/* Algorithm 1.  Copies A and T; runs the symbolic plan on the host and the
+ * numeric factorization on the device.  On success *out is a new handle.
+ * Errors: LRX_EINVAL (bad CSR/tree/options, non-finite values), LRX_ESINGULAR,
+ * LRX_ENOMEM, LRX_EDEVICE. */
+lrx_status lrx_factor(const lrx_csr* A, const lrx_tree* T, const lrx_opts* o, lrx_handle* out);
+
+/* Algorithms 2-4 for nrhs right-hand sides, host memory, column-major:
+ * b[k*ldb + i] is entry i of right-hand side k (ldb >= n); x likewise (ldx >= n).
+ * Synchronous. */
+lrx_status lrx_solve(lrx_handle h, int32_t nrhs, const double* b, int64_t ldb,
+                     double* x, int64_t ldx);
+
+/* Same on device memory, enqueued on the handle's stream, no host sync.
+ * b and x are n x nrhs with leading dimension n, column-major, may not alias. */
+lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev);
+
+/* GMRES(restart) with the solve as right preconditioner, x_0 = 0, for nrhs
+ * right-hand sides (host, column-major, leading dimension n).  A must be the
+ * matrix the handle was factored from (n and nnz are checked).  Stops each
+ * right-hand side when its true relative residual ||b - A x|| / ||b|| <= tol.
+ * iters[k] and relres[k] (nrhs entries each, may be NULL) receive the
+ * iteration count and final true relative residual.  Returns LRX_ENOCONV if any
+ * right-hand side reached maxit; x, iters and relres are then still filled. */
+lrx_status lrx_gmres(const lrx_csr* A, lrx_handle h, int32_t nrhs, const double* b,
+                     double* x, double tol, int32_t restart, int32_t maxit,
+                     int32_t* iters, double* relres);
+
+/* Same on device memory (b, x: n x nrhs column-major in HBM) on the handle's
+ * stream; uses the handle's resident copy of A.  Synchronises the stream once
+ * per Arnoldi step (the Hessenberg column goes to the host). */
+lrx_status lrx_gmres_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev,
+                         double tol, int32_t restart, int32_t maxit,
+                         int32_t* iters, double* relres);
+
+/* Releases every resource of the handle.  NULL is accepted.  A handle that was
+ * already freed gives LRX_EINVAL. */
+lrx_status lrx_free(lrx_handle h);
+
+/* Fills *s with the counters of the factorization. */
+lrx_status lrx_stats(lrx_handle h, lrx_stats_t* s);
+
+/* Ranks of all compressions in processing order (level l..1, then the order
+ * inside the level); ranks must hold n_compressions entries; levels and js
+ * (same length, may be NULL) receive the level i and super-node index j. */
+lrx_status lrx_ranks(lrx_handle h, int32_t* ranks, int32_t* levels, int32_t* js);
+
+/* Host-only symbolic plan of Algorithm 1 for (A, T, order): no device call. */
+lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order,
+                            lrx_plan_info* info);
+
+/* Message of the last error on this thread ("" if none). */
+const char* lrx_last_error(void);
+
+/* Library version string. */
+const char* lrx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LORAX_H */

@@ -31,6 +31,13 @@ Readings where the paper leaves a choice (each one stated in the design notes):
     value (exact);
   * V carries no singular values: V has orthonormal columns (right singular
     vectors) and [R;Q] = B V, so B - [R;Q] V^T = B (I - V V^T);
+  * compress='rrqr' (the rank-revealing QR option the paper lists among
+    alternative low-rank methods in Sec. 7): column-pivoted Householder QR of
+    B^T, i.e. pivoting over the rows of B (largest remaining norm, lowest index
+    on ties, norms recomputed at every step); stop at the first k with
+    ||R22||_F <= epsilon * |R11|, R11 the first pivot.  Then V = the first k
+    columns of the orthogonal factor, and ||B - B V V^T||_2 = ||R22||_2 <=
+    epsilon * ||B||_2 since |R11| <= ||B||_2;
   * both A_k and B_k are always stacked (no symmetric shortcut);
   * pivot blocks are factored by LU with partial pivoting inside the block
     (LAPACK getrf); an exactly zero pivot is an error;
@@ -82,7 +89,7 @@ class CompressionRecord:
     rows: int                 # height of the stacked B
     m: int                    # width of B (size of the super-node)
     rank: int
-    sigma: np.ndarray         # all singular values of B (descending)
+    sigma: np.ndarray         # svd: singular values of B; rrqr: ||R22^(k)||_F, k = 0..
     candidates: list          # the well-separated neighbours p_1..p_t
     B: np.ndarray | None = None
     V: np.ndarray | None = None
@@ -166,8 +173,10 @@ def _key(node):
 
 
 def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored",
-           forced_ranks=None, check=True, keep_blocks=False):
+           forced_ranks=None, check=True, keep_blocks=False, compress="svd"):
     """Algorithm 1.  Inputs are a CSR matrix (0-based) and the cluster tree.
+
+    compress:     'svd' (eqn. cutOff1, as in the paper's experiments) or 'rrqr'.
 
     forced_ranks: optional {(level, j): rank} to replay ranks decided elsewhere.
     keep_blocks:  keep every stacked B and V in the compression records (tests).
@@ -258,7 +267,7 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
             forced = None
             if forced_ranks is not None and (i, j) in forced_ranks:
                 forced = int(forced_ranks[(i, j)])
-            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks)
+            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress)
             rec.level, rec.j = i, j
             compressions.append(rec)
 
@@ -273,7 +282,53 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
                          events, dict(G.size), compressions, order_index, level_colours)
 
 
-def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False):
+def rrqr_rows(B, epsilon, forced_rank=None):
+    """Column-pivoted Householder QR of B^T (pivots are rows of B), truncated at
+    the first k with ||R22||_F <= epsilon |R11|.  Returns (k, V, pivots, tails)
+    with V (m x k) orthonormal, tails[k] = ||R22^(k)||_F."""
+    X = np.array(B, dtype=np.float64).T.copy()          # m x M
+    m, M = X.shape
+    kmax = min(m, M)
+    pivoted = np.zeros(M, dtype=bool)
+    vs, betas, piv, tails = [], [], [], []
+    r11 = 0.0
+    k = 0
+    while k < kmax:
+        nrm2 = np.sum(X[k:, :] ** 2, axis=0)
+        nrm2[pivoted] = 0.0
+        T = float(np.sqrt(np.sum(nrm2)))
+        tails.append(T)
+        p = int(np.argmax(nrm2))                        # first index of the maximum
+        if k == 0:
+            r11 = float(np.sqrt(nrm2[p]))
+        if forced_rank is not None:
+            if k >= forced_rank:
+                break
+        elif T == 0.0 or T <= epsilon * r11:
+            break
+        x = X[k:, p].copy()
+        alpha = -np.copysign(np.sqrt(np.sum(x * x)), x[0])
+        v = x
+        v[0] -= alpha
+        beta = float(v @ v)
+        if beta > 0.0:
+            X[k:, :] -= np.outer(v, (2.0 / beta) * (v @ X[k:, :]))
+        vs.append(v)
+        betas.append(beta)
+        piv.append(p)
+        pivoted[p] = True
+        k += 1
+    if k == kmax:
+        tails.append(0.0)
+    V = np.eye(m)[:, :k].copy()
+    for t in range(k - 1, -1, -1):                      # V = H_1 ... H_k I[:, :k]
+        if betas[t] > 0.0:
+            V[t:, :] -= np.outer(vs[t], (2.0 / betas[t]) * (vs[t] @ V[t:, :]))
+    return k, V, piv, tails
+
+
+def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
+              method="svd"):
     """Compress(s): replace the well-separated edges of s by low-rank edges through
     its black node b and the parent red node P = P(b) (Sec. 4.3, eqn. lra,
     eqn. anterpol, eqn. interpol and the edge-update list)."""
@@ -287,17 +342,26 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False):
         B = np.vstack(parts)
     else:
         B = np.zeros((0, m))
-    if B.shape[0] > 0 and m > 0:
-        _, sig, Vt = np.linalg.svd(B, full_matrices=False)
+    if method == "svd":
+        if B.shape[0] > 0 and m > 0:
+            _, sig, Vt = np.linalg.svd(B, full_matrices=False)
+        else:
+            sig, Vt = np.zeros(0), np.zeros((0, m))
+        if forced_rank is not None:
+            r = forced_rank
+        elif len(sig) == 0 or sig[0] == 0.0:
+            r = 0
+        else:
+            r = int(np.count_nonzero(sig >= epsilon * sig[0]))   # eqn. cutOff1
+        V = Vt[:r].T.copy()                           # m x r, orthonormal columns
+    elif method == "rrqr":
+        if B.shape[0] > 0 and m > 0:
+            r, V, _, sig = rrqr_rows(B, epsilon, forced_rank)
+            sig = np.asarray(sig)                     # ||R22^(k)||_F for k = 0..r
+        else:
+            r, V, sig = 0, np.zeros((m, 0)), np.zeros(0)
     else:
-        sig, Vt = np.zeros(0), np.zeros((0, m))
-    if forced_rank is not None:
-        r = forced_rank
-    elif len(sig) == 0 or sig[0] == 0.0:
-        r = 0
-    else:
-        r = int(np.count_nonzero(sig >= epsilon * sig[0]))       # eqn. cutOff1
-    V = Vt[:r].T.copy()                               # m x r, orthonormal columns
+        raise ValueError(method)
     RQ = B @ V                                         # [R_1;..;R_t;Q_1;..;Q_t]
     rec = CompressionRecord(0, 0, B.shape[0], m, r, sig, list(cand),
                             B.copy() if keep_blocks else None,

@@ -56,14 +56,15 @@ def _relerr(x, y):
 
 
 # --------------------------------------------------------------------------- exactness
+@pytest.mark.parametrize("method", ["svd", "rrqr"])
 @pytest.mark.parametrize("order", ["colored", "natural"])
 @pytest.mark.parametrize("kind,nx,leaf", [("poisson2d", 32, 16), ("varcoef2d", 16, 8),
                                           ("convdiff3d", 8, 8), ("lognormal3d", 6, 4)])
-def test_eps0_equals_dense_solve(kind, nx, leaf, order):
+def test_eps0_equals_dense_solve(kind, nx, leaf, order, method):
     csr, n, perm, lp, depth, rng = _grid_problem(kind, nx, leaf)
     A = _dense(csr, n)
     b = rng.uniform(-1, 1, (n, 2))
-    F = oracle.factor(*csr, perm, lp, depth, 0.0, order=order)
+    F = oracle.factor(*csr, perm, lp, depth, 0.0, order=order, compress=method)
     x = oracle.solve(F, b)
     assert _relerr(x, np.linalg.solve(A, b)) <= 1e-12
 
@@ -238,12 +239,52 @@ def test_every_compression_meets_bound_and_is_minimal(eps):
     assert checked > 10
 
 
-def test_symmetric_matrix_gives_symmetric_operator():
+@pytest.mark.parametrize("method", ["svd", "rrqr"])
+def test_symmetric_matrix_gives_symmetric_operator(method):
     csr, n, perm, lp, depth, _ = _grid_problem("varcoef2d", 16, 8)
-    F = oracle.factor(*csr, perm, lp, depth, 1e-2)
+    F = oracle.factor(*csr, perm, lp, depth, 1e-2, compress=method)
     assert any(c.rank > 0 and c.rank < c.m for c in F.compressions)
     M = oracle.solve(F, np.eye(n))
     assert np.linalg.norm(M - M.T) / np.linalg.norm(M) <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-8])
+def test_every_rrqr_compression_meets_bound(eps):
+    """RRQR truncation: ||B - B V V^T||_F equals the stopping tail ||R22||_F,
+    which is <= eps * |R11| <= eps * ||B||_2; one step fewer would not stop."""
+    csr, n, perm, lp, depth, _ = _grid_problem("convdiff3d", 8, 8)
+    F = oracle.factor(*csr, perm, lp, depth, eps, keep_blocks=True, compress="rrqr")
+    checked = 0
+    for c in F.compressions:
+        if c.B.shape[0] == 0 or c.m == 0 or not np.any(c.B):
+            assert c.rank == 0
+            continue
+        B, V, r = c.B, c.V, c.rank
+        r11 = np.max(np.linalg.norm(B, axis=1))
+        nB = _gram_norm2(B)
+        assert np.allclose(V.T @ V, np.eye(r), atol=1e-12)
+        E = B - B @ V @ V.T
+        assert abs(np.linalg.norm(E) - c.sigma[r]) <= 1e-10 * np.linalg.norm(B)
+        assert _gram_norm2(E) <= eps * nB * (1 + 1e-9)
+        assert c.sigma[r] <= eps * r11 * (1 + 1e-12) or r == min(B.shape)
+        if r > 0:
+            assert c.sigma[r - 1] > eps * r11
+        checked += 1
+    assert checked > 10
+
+
+def test_rrqr_pivot_rule_on_handmade_matrix():
+    # rows with distinct norms: first pivot is the largest row; the rank of an
+    # exactly rank-2 matrix is 2 at any eps small enough
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((9, 2)) @ rng.standard_normal((2, 6))
+    B[4] *= 10.0
+    from oracle.factor import rrqr_rows
+    r, V, piv, tails = rrqr_rows(B, 1e-10)
+    assert r == 2 and piv[0] == 4
+    assert tails[2] <= 1e-10 * np.linalg.norm(B[4])
+    r0, _, _, _ = rrqr_rows(np.zeros((4, 3)), 0.1)
+    assert r0 == 0
 
 
 def test_solve_is_linear():
