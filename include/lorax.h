@@ -8,7 +8,8 @@
  * for sparse matrices using extended sparsification and low-rank approximation":
  *   lrx_factor  Algorithm 1 (Sec. 4): level-by-level MergeRedNodes, Compress,
  *               Eliminate(super-node), Eliminate(black node) on the H-tree of
- *               Def. "hierarchical tree", truncation by eqn. cutOff1.
+ *               Def. "hierarchical tree"; truncated SVD with the cut-off of
+ *               eqn. cutOff1, or rank-revealing QR (Sec. 7 lists both).
  *   lrx_solve   Algorithms 2-4 (Sec. 4.5): SetRHS, forward SolveL, backward
  *               SolveU and SplitVar; x ~ A^{-1} b.
  *   lrx_gmres   Sec. 6.2: GMRES with the solve as preconditioner.
@@ -47,6 +48,7 @@ typedef enum {
 
 typedef enum { LRX_FP64 = 0 } lrx_precision;
 typedef enum { LRX_COLORED = 0, LRX_NATURAL = 1 } lrx_order;
+typedef enum { LRX_SVD = 0, LRX_RRQR = 1 } lrx_compress;
 
 typedef struct lrx_handle_s* lrx_handle;     /* opaque */
 
@@ -71,9 +73,13 @@ typedef struct {
 } lrx_tree;
 
 typedef struct {
-    double epsilon;            /* truncation: keep sigma_k >= epsilon * sigma_0 (eqn. cutOff1);
-                                  0 <= epsilon < 1; 0 keeps every singular value (exact) */
+    double epsilon;            /* truncation tolerance, 0 <= epsilon < 1; 0 keeps everything (exact).
+                                  LRX_SVD: keep sigma_k >= epsilon * sigma_0 of the stacked block B
+                                  (eqn. cutOff1), so ||B - B V V^T||_2 < epsilon ||B||_2.
+                                  LRX_RRQR: row-pivoted QR of B stopped at the first k with
+                                  ||R22||_F <= epsilon |R11|, so ||B - B V V^T||_2 <= epsilon ||B||_2. */
     int32_t precision;         /* lrx_precision */
+    int32_t compress;          /* lrx_compress: low-rank method of Compress (Sec. 4.3) */
     int32_t order;             /* lrx_order: order of the super-nodes inside a level */
     int64_t hbm_budget_bytes;  /* 0 = no limit; otherwise LRX_ENOMEM when exceeded */
     void* stream;              /* hipStream_t used by the handle, or NULL for the null stream */
@@ -90,6 +96,9 @@ typedef struct {
     double rank_mean_by_level[32];
     double mean_node_size_by_level[32];
     int64_t extended_size;         /* n + auxiliary variables */
+    double max_compression_error;  /* max over compressions of ||B - B V V^T||_2 / ||B||_2
+                                      (SVD: sigma_r / sigma_0) or of its bound ||R22||_F / |R11|
+                                      (RRQR); at most epsilon */
     int64_t factor_bytes;          /* device bytes of stored blocks */
     int64_t solve_bytes;           /* bytes one solve reads from stored blocks */
     int64_t factor_flops;          /* algorithmic flops of the factorization */
@@ -114,6 +123,13 @@ typedef struct {
  * Errors: LRX_EINVAL (bad CSR/tree/options, non-finite values), LRX_ESINGULAR,
  * LRX_ENOMEM, LRX_EDEVICE. */
 lrx_status lrx_factor(const lrx_csr* A, const lrx_tree* T, const lrx_opts* o, lrx_handle* out);
+
+/* Same as lrx_factor with the values already in HBM: A supplies the pattern
+ * (row_ptr, col_idx on the host, used by the symbolic plan; A->val is ignored)
+ * and val_dev holds the nnz values in device memory (read-only, in CSR order).
+ * Non-finite values give LRX_EINVAL. */
+lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tree* T,
+                          const lrx_opts* o, lrx_handle* out);
 
 /* Algorithms 2-4 for nrhs right-hand sides, host memory, column-major:
  * b[k*ldb + i] is entry i of right-hand side k (ldb >= n); x likewise (ldx >= n).
@@ -155,9 +171,45 @@ lrx_status lrx_stats(lrx_handle h, lrx_stats_t* s);
  * (same length, may be NULL) receive the level i and super-node index j. */
 lrx_status lrx_ranks(lrx_handle h, int32_t* ranks, int32_t* levels, int32_t* js);
 
+/* Truncation data of compression idx (same order as lrx_ranks).
+ * LRX_SVD:  out[0] = sigma_0, out[1..c] = all singular values of the stacked
+ *           block in descending order (c = its number of non-zero columns);
+ *           *len = c + 1.
+ * LRX_RRQR: out[0] = |R11| (largest row norm of B), out[1 + k] = ||R22||_F before
+ *           pivot step k, k = 0..rank; *len = rank + 2.
+ * At most cap values are written. */
+lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t cap, int32_t* len);
+
 /* Host-only symbolic plan of Algorithm 1 for (A, T, order): no device call. */
 lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order,
                             lrx_plan_info* info);
+
+/* Optional event timing of kernel launches, accumulated by kernel class over
+ * all handles until read with reset.  lrx_timing_enable takes a bit mask of
+ * classes (1 << LRX_K_...; 0 turns timing off, the default); every timed launch
+ * adds two event records to its stream. */
+typedef enum {
+    LRX_K_COMPRESS = 0,       /* stacked-block assembly + truncated SVD / RRQR (Sec. 4.3) */
+    LRX_K_FACTOR_NODE = 1,    /* projection, rewiring, Eliminate(s), Eliminate(b) (Sec. 4.4) */
+    LRX_K_SOLVE_FWD = 2,      /* SolveL sweep of one colour step (Algorithm 3) */
+    LRX_K_SOLVE_BWD = 3,      /* SolveU sweep of one colour step (Algorithm 4) */
+    LRX_K_SPMV = 4,           /* A times the preconditioned vectors (GMRES) */
+    LRX_K_CLASSES = 8
+} lrx_kernel_class;
+
+typedef struct {
+    int64_t launches;
+    double total_ms;          /* sum of event-measured durations */
+    double bytes;             /* algorithmic bytes (stored blocks / matrix read), summed */
+    double flops;             /* algorithmic flops, summed */
+} lrx_kernel_time;
+
+typedef struct {
+    lrx_kernel_time k[LRX_K_CLASSES];
+} lrx_timing_t;
+
+void lrx_timing_enable(int32_t class_mask);
+lrx_status lrx_timing_read(lrx_timing_t* t, int32_t reset);
 
 /* Message of the last error on this thread ("" if none). */
 const char* lrx_last_error(void);

@@ -1,0 +1,870 @@
+// HIP kernels for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// Factorization kernels run one work-group (256 threads = 4 wavefronts) per
+// super-node of a colour step: nodes of one colour are at distance >= 3 in the
+// cluster adjacency graph and share no block, so work-groups never touch the
+// same memory and no atomics are needed.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace lrx {
+
+namespace {
+
+constexpr int NT = kFactorThreads;
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int imap_at(const int32_t* imap, int32_t map, int t) {
+    return map < 0 ? t : imap[map + t];
+}
+
+// Block-wide (max value, lowest index) and sum; every thread receives the result.
+__device__ void block_argmax_sum(double& best, int& bi, double& sum, double* s_d, int* s_i,
+                                 double* s_s) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        double ob = __shfl_down(best, o);
+        int oi = __shfl_down(bi, o);
+        double os = __shfl_down(sum, o);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        sum += os;
+    }
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    if (lane == 0) { s_d[w] = best; s_i[w] = bi; s_s[w] = sum; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = s_d[0], s = s_s[0];
+        int i = s_i[0];
+        for (int k = 1; k < NT / WAVE; ++k) {
+            if (s_d[k] > b || (s_d[k] == b && s_i[k] < i)) { b = s_d[k]; i = s_i[k]; }
+            s += s_s[k];
+        }
+        s_d[NT / WAVE] = b; s_i[NT / WAVE] = i; s_s[NT / WAVE] = s;
+    }
+    __syncthreads();
+    best = s_d[NT / WAVE]; bi = s_i[NT / WAVE]; sum = s_s[NT / WAVE];
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- scatter / merge
+__global__ void k_scatter(double* __restrict__ dst, const int64_t* __restrict__ idx,
+                          const double* __restrict__ val, int64_t nnz) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) dst[idx[e]] = val[e];
+}
+
+__global__ void k_merge(const DMerge* __restrict__ t) {
+    const DMerge M = t[blockIdx.x];
+    const int nr = M.src.nr, nc = M.src.nc;
+    for (int e = threadIdx.x; e < nr * nc; e += blockDim.x) {
+        int a = e % nr, b = e / nr;
+        M.dst.p[(M.r0 + a) + (int64_t)(M.c0 + b) * M.dst.nr] = M.src.p[e];
+    }
+}
+
+// ------------------------------------------------------------------ compress
+// Column-pivoted Householder QR of B^T (pivots are rows of B), truncated at the
+// first k with ||R22||_F <= eps |R11| (|R11| = largest row norm of B <= ||B||_2),
+// so that ||B - B V V^T||_2 <= ||R22||_F <= eps ||B||_2.  Norms of the remaining
+// rows are recomputed at every step; ties go to the lowest row index.
+__global__ __launch_bounds__(NT) void k_compress(const DCompress* __restrict__ tasks,
+                                                 const DPiece* __restrict__ pieces,
+                                                 const int32_t* __restrict__ imap) {
+    const DCompress T = tasks[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x;
+    double* __restrict__ B = T.B;
+    __shared__ double s_d[NT / WAVE + 1], s_s[NT / WAVE + 1];
+    __shared__ int s_i[NT / WAVE + 1];
+    extern __shared__ double s_dyn[];
+    double* s_v = s_dyn;          // c
+    double* s_beta = s_dyn + c;   // c
+
+    if (M == 0 || c == 0) {
+        if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; T.tails[1] = 0.0; }
+        return;
+    }
+    for (int64_t e = tid; e < (int64_t)M * c; e += NT) B[e] = 0.0;
+    __syncthreads();
+    for (int q = 0; q < T.npieces; ++q) {
+        const DPiece pc = pieces[T.piece0 + q];
+        const int nr = pc.blk.nr, nc = pc.blk.nc;
+        for (int e = tid; e < nr * nc; e += NT) {
+            const int a = e % nr, b = e / nr;
+            const double v = pc.blk.p[e];
+            if (!pc.trans) B[(int64_t)(pc.row0 + a) * c + imap_at(imap, pc.map, b)] = v;
+            else           B[(int64_t)(pc.row0 + b) * c + imap_at(imap, pc.map, a)] = v;
+        }
+    }
+    __syncthreads();
+
+    const int kmax = M < c ? M : c;
+    double r11 = 0.0;
+    int k = 0;
+    for (; k < kmax; ++k) {
+        double best = -1.0, sum = 0.0;
+        int bi = INT_MAX;
+        for (int i = tid; i < M; i += NT) {
+            const double* row = B + (int64_t)i * c;
+            double s2 = 0.0;
+            for (int j = k; j < c; ++j) s2 += row[j] * row[j];
+            sum += s2;
+            if (s2 > best) { best = s2; bi = i; }
+        }
+        block_argmax_sum(best, bi, sum, s_d, s_i, s_s);
+        if (bi < 0 || bi >= M) break;              // no finite row left (non-finite data)
+        const double tail = sqrt(sum);
+        if (k == 0) r11 = sqrt(best);
+        if (tid == 0) { T.tails[0] = r11; T.tails[1 + k] = tail; }
+        if (tail == 0.0 || tail <= T.eps * r11) break;
+        const int p = bi;
+        double* rowp = B + (int64_t)p * c;
+        const double xnorm = sqrt(best);
+        const double x0 = rowp[k];
+        const double alpha = -copysign(xnorm, x0);
+        for (int j = tid; j < c - k; j += NT) s_v[j] = rowp[k + j];
+        __syncthreads();
+        if (tid == 0) {
+            s_v[0] = x0 - alpha;
+            s_beta[k] = 2.0 * (xnorm * xnorm + fabs(x0) * xnorm);   // v.v
+        }
+        __syncthreads();
+        const double beta = s_beta[k];
+        for (int j = tid; j < c - k; j += NT) T.hv[(int64_t)k * c + j] = s_v[j];
+        if (beta > 0.0) {
+            const double tau = 2.0 / beta;
+            for (int i = tid; i < M; i += NT) {
+                if (i == p) continue;
+                double* row = B + (int64_t)i * c + k;
+                double w = 0.0;
+                for (int j = 0; j < c - k; ++j) w += s_v[j] * row[j];
+                w *= tau;
+                for (int j = 0; j < c - k; ++j) row[j] -= w * s_v[j];
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < c - k; j += NT) rowp[k + j] = (j == 0) ? alpha : 0.0;
+        __syncthreads();
+    }
+    const int r = k;
+    if (tid == 0 && r == kmax) T.tails[1 + r] = 0.0;
+    // V = H_0 ... H_{r-1} I[:, :r]  (c x r, column-major, ld c); one column per thread
+    for (int col = tid; col < r; col += NT) {
+        double* vc = T.V + (int64_t)col * c;
+        for (int a = 0; a < c; ++a) vc[a] = (a == col) ? 1.0 : 0.0;
+        for (int t = r - 1; t >= 0; --t) {
+            const double beta = s_beta[t];
+            if (!(beta > 0.0)) continue;
+            const double* v = T.hv + (int64_t)t * c;
+            double w = 0.0;
+            for (int j = 0; j < c - t; ++j) w += v[j] * vc[t + j];
+            w *= 2.0 / beta;
+            for (int j = 0; j < c - t; ++j) vc[t + j] -= w * v[j];
+        }
+    }
+    if (tid == 0) *T.rank_out = r;
+}
+
+// Truncated SVD of the stacked block (eqn. lra with the cut-off of eqn.
+// cutOff1): Householder QR of B (M x c, column-major) to the c x c triangle R,
+// one-sided Jacobi (Hestenes) SVD of R with the rotations accumulated in V,
+// singular values sorted in descending order, rank = #{sigma_k >= eps sigma_0}.
+// R and V live in LDS when `lds_mat` is set (2 c^2 doubles), otherwise in the
+// task's workspace.
+constexpr int JG = 16;                         // lanes per Jacobi pair
+
+__device__ __forceinline__ double group_sum16(double v) {
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// position of value k in a descending order of sv[0..c) (ties: lower index first)
+__device__ __forceinline__ int desc_pos(const double* sv, int c, int k) {
+    const double x = sv[k];
+    int pos = 0;
+    for (int j = 0; j < c; ++j) pos += (sv[j] > x) || (sv[j] == x && j < k);
+    return pos;
+}
+
+__device__ double block_sum(double v, double* s_s) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    __syncthreads();
+    if (lane == 0) s_s[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < NT / WAVE; ++k) t += s_s[k];
+    return t;
+}
+
+__global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict__ tasks,
+                                                     const DPiece* __restrict__ pieces,
+                                                     const int32_t* __restrict__ imap,
+                                                     int lds_mat) {
+    const DCompress T = tasks[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x;
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    __shared__ double s_s[NT / WAVE + 1];
+    __shared__ int s_rot;
+    extern __shared__ double s_dyn[];
+    if (M == 0 || c == 0) {
+        if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; }
+        return;
+    }
+    double* __restrict__ B = T.B;
+    double* __restrict__ W = T.Bw;
+    // ---- assemble B (column-major, ld M)
+    for (int64_t e = tid; e < (int64_t)M * c; e += NT) B[e] = 0.0;
+    __syncthreads();
+    for (int q = 0; q < T.npieces; ++q) {
+        const DPiece pc = pieces[T.piece0 + q];
+        const int nr = pc.blk.nr, nc = pc.blk.nc;
+        for (int e = tid; e < nr * nc; e += NT) {
+            const int a = e % nr, b = e / nr;
+            const double v = pc.blk.p[e];
+            if (!pc.trans) B[(pc.row0 + a) + (int64_t)imap_at(imap, pc.map, b) * M] = v;
+            else           B[(pc.row0 + b) + (int64_t)imap_at(imap, pc.map, a) * M] = v;
+        }
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)M * c; e += NT) W[e] = B[e];
+    __syncthreads();
+    // ---- Householder QR of W by columns; R ends in the upper triangle of W's
+    //      first c rows, with the diagonal kept in `rdiag` (the v's are below)
+    double* Rm = lds_mat ? s_dyn : T.hv;                 // c x c
+    double* Vm = lds_mat ? s_dyn + (size_t)c * c : T.V;  // c x c
+    const int kq = M < c ? M : c;
+    for (int e = tid; e < c * c; e += NT) Rm[e] = 0.0;
+    for (int j = 0; j < kq; ++j) {
+        double part = 0.0;
+        for (int i = j + tid; i < M; i += NT) { const double x = W[i + (int64_t)j * M]; part += x * x; }
+        const double s2 = block_sum(part, s_s);
+        const double x0 = W[j + (int64_t)j * M];
+        const double xn = sqrt(s2);
+        const double alpha = xn == 0.0 ? 0.0 : -copysign(xn, x0);
+        const double beta = 2.0 * (s2 + fabs(x0) * xn);          // v.v
+        __syncthreads();
+        if (tid == 0) {
+            W[j + (int64_t)j * M] = x0 - alpha;
+            Rm[j + (int64_t)j * c] = alpha;
+        }
+        __syncthreads();
+        if (beta > 0.0) {
+            const double tau = 2.0 / beta;
+            const double* v = W + (int64_t)j * M;
+            for (int k = j + 1 + wv; k < c; k += NT / WAVE) {
+                double* col = W + (int64_t)k * M;
+                double w = 0.0;
+                for (int i = j + lane; i < M; i += WAVE) w += v[i] * col[i];
+                w = wave_sum(w) * tau;
+                for (int i = j + lane; i < M; i += WAVE) col[i] -= w * v[i];
+            }
+        }
+        __syncthreads();
+    }
+    // R: strict upper part from W, diagonal already written; rows >= kq are zero
+    for (int e = tid; e < c * c; e += NT) {
+        const int a = e % c, k = e / c;
+        if (a < k && a < kq) Rm[e] = W[a + (int64_t)k * M];
+        Vm[e] = (a == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // ---- one-sided Jacobi on the columns of R; V accumulates the rotations
+    const int n2 = c + (c & 1);
+    const int g = tid / JG, gl = tid % JG;
+    const double tol = 4.0e-16 * (double)c;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int t = 0; t < n2 - 1; ++t) {
+            for (int i = g; i < n2 / 2; i += NT / JG) {
+                int a = (t + i) % (n2 - 1);
+                int b = i == 0 ? n2 - 1 : (t - i + n2 - 1) % (n2 - 1);
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                if (q >= c) continue;
+                double* cp = Rm + (size_t)p * c;
+                double* cq = Rm + (size_t)q * c;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int r = gl; r < c; r += JG) {
+                    const double x = cp[r], y = cq[r];
+                    al += x * x; be += y * y; ga += x * y;
+                }
+                al = group_sum16(al); be = group_sum16(be); ga = group_sum16(ga);
+                if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) continue;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                for (int r = gl; r < c; r += JG) {
+                    const double x = cp[r], y = cq[r];
+                    cp[r] = cs * x - sn * y;
+                    cq[r] = sn * x + cs * y;
+                }
+                double* vp = Vm + (size_t)p * c;
+                double* vq = Vm + (size_t)q * c;
+                for (int r = gl; r < c; r += JG) {
+                    const double x = vp[r], y = vq[r];
+                    vp[r] = cs * x - sn * y;
+                    vq[r] = sn * x + cs * y;
+                }
+                if (gl == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        const int rot = s_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    // ---- singular values = column norms of the rotated R (scratch after R in hv)
+    double* sv = T.hv + (size_t)c * c;
+    for (int k = wv; k < c; k += NT / WAVE) {
+        double s2 = 0.0;
+        for (int r = lane; r < c; r += WAVE) { const double x = Rm[r + (size_t)k * c]; s2 += x * x; }
+        s2 = wave_sum(s2);
+        if (lane == 0) sv[k] = sqrt(s2);
+    }
+    __syncthreads();
+    // descending order, ties by column index
+    for (int k = tid; k < c; k += NT) T.tails[1 + desc_pos(sv, c, k)] = sv[k];
+    __syncthreads();
+    const double smax = T.tails[1];
+    int r = 0;
+    if (smax > 0.0)
+        for (int k = 0; k < c; ++k) r += (T.tails[1 + k] >= T.eps * smax) ? 1 : 0;
+    // V (c x r): output column pos(k) is column k of the accumulated rotations
+    const double* Vsrc = Vm;
+    if (!lds_mat) {                       // Vm is T.V itself: stage it in hv (R is done)
+        for (int e = tid; e < c * c; e += NT) T.hv[e] = Vm[e];
+        __syncthreads();
+        Vsrc = T.hv;
+    }
+    for (int e = tid; e < c * c; e += NT) {
+        const int a = e % c, k = e / c;
+        const int pos = desc_pos(sv, c, k);
+        if (pos < r) T.V[a + (size_t)pos * c] = Vsrc[a + (size_t)k * c];
+    }
+    if (tid == 0) {
+        T.tails[0] = smax;
+        *T.rank_out = r;
+    }
+}
+
+// ------------------------------------------------------------------ elimination
+// In-place inverse of the m x m column-major block by Gauss-Jordan elimination
+// with partial (row) pivoting inside the block; returns false if a pivot is 0.
+__device__ bool gj_inverse(double* A, int m, double* scol, int* sperm, double* s_d, int* s_i) {
+    const int tid = threadIdx.x;
+    for (int k = 0; k < m; ++k) {
+        if (tid < WAVE) {
+            double best = -1.0;
+            int bi = INT_MAX;
+            for (int i = k + tid; i < m; i += WAVE) {
+                const double v = fabs(A[i + (int64_t)k * m]);
+                if (v > best) { best = v; bi = i; }
+            }
+            for (int o = WAVE / 2; o > 0; o >>= 1) {
+                double ob = __shfl_down(best, o);
+                int oi = __shfl_down(bi, o);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (tid == 0) { sperm[k] = bi; s_d[0] = best; }
+        }
+        __syncthreads();
+        const int p = sperm[k];
+        if (!(s_d[0] > 0.0)) return false;
+        if (p != k)
+            for (int j = tid; j < m; j += NT) {
+                double t = A[k + (int64_t)j * m];
+                A[k + (int64_t)j * m] = A[p + (int64_t)j * m];
+                A[p + (int64_t)j * m] = t;
+            }
+        __syncthreads();
+        const double d = 1.0 / A[k + (int64_t)k * m];
+        for (int i = tid; i < m; i += NT) scol[i] = A[i + (int64_t)k * m];
+        __syncthreads();
+        for (int j = tid; j < m; j += NT)
+            A[k + (int64_t)j * m] = (j == k) ? d : A[k + (int64_t)j * m] * d;
+        __syncthreads();
+        for (int e = tid; e < m * m; e += NT) {
+            const int i = e % m, j = e / m;
+            if (i == k) continue;
+            const double f = scol[i];
+            if (j == k) A[i + (int64_t)k * m] = -f * d;
+            else A[i + (int64_t)j * m] -= f * A[k + (int64_t)j * m];
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < m; i += NT)
+        for (int k = m - 1; k >= 0; --k) {
+            const int p = sperm[k];
+            if (p != k) {
+                double t = A[i + (int64_t)k * m];
+                A[i + (int64_t)k * m] = A[i + (int64_t)p * m];
+                A[i + (int64_t)p * m] = t;
+            }
+        }
+    __syncthreads();
+    return true;
+}
+
+// Block Gauss elimination of one pivot (Sec. 2.2): invert Mat(v->v), form
+// W_k = Mat(v->v)^{-1} Mat(k->v) for every in-edge, then for every pair
+// Mat(k->q) -= Mat(v->q) W_k.
+__device__ void eliminate(const DPivot& P, const DIn* __restrict__ ins,
+                          const DOut* __restrict__ outs, const DPair* __restrict__ pairs,
+                          const int32_t* __restrict__ imap, int32_t* __restrict__ info,
+                          double* scol, int* sperm, double* s_d, int* s_i) {
+    const int tid = threadIdx.x;
+    const int m = P.piv.nr;
+    if (m == 0) return;
+    const double* Si = P.piv.p;
+    if (!gj_inverse(P.piv.p, m, scol, sperm, s_d, s_i)) {
+        if (tid == 0) info[P.info_slot] = 1;
+        return;
+    }
+    for (int i = 0; i < P.nin; ++i) {
+        const DIn I = ins[P.in0 + i];
+        const int nr = I.blk.nr, nc = I.blk.nc;
+        for (int e = tid; e < m * nc; e += NT) {
+            const int a = e % m, b = e / m;
+            double s = 0.0;
+            const double* col = I.blk.p + (int64_t)b * nr;
+            for (int t = 0; t < nr; ++t) s += Si[a + (int64_t)imap_at(imap, I.rmap, t) * m] * col[t];
+            I.W[a + (int64_t)b * m] = s;
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < P.npair; ++q) {
+        const DPair Q = pairs[P.pair0 + q];
+        const DOut O = outs[P.out0 + Q.out_i];
+        const DIn I = ins[P.in0 + Q.in_i];
+        const int nr = O.blk.nr, nc = I.blk.nc, K = O.blk.nc;
+        for (int e = tid; e < nr * nc; e += NT) {
+            const int a = e % nr, b = e / nr;
+            double s = 0.0;
+            const double* Wb = I.W + (int64_t)b * m;
+            for (int t = 0; t < K; ++t) s += O.blk.p[a + (int64_t)t * nr] * Wb[imap_at(imap, O.cmap, t)];
+            const int ra = imap_at(imap, Q.rpos, a), cb = imap_at(imap, Q.cpos, b);
+            Q.tgt.p[ra + (int64_t)cb * Q.tgt.nr] -= s;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(NT) void k_factor_node(const DNode* __restrict__ tasks,
+                                                    const DProj* __restrict__ projs,
+                                                    const DIn* __restrict__ ins,
+                                                    const DOut* __restrict__ outs,
+                                                    const DPair* __restrict__ pairs,
+                                                    const int32_t* __restrict__ imap,
+                                                    int32_t* __restrict__ info, int max_m) {
+    const DNode T = tasks[blockIdx.x];
+    const int tid = threadIdx.x;
+    __shared__ double s_d[NT / WAVE + 1];
+    __shared__ int s_i[NT / WAVE + 1];
+    extern __shared__ double s_dyn[];
+    double* scol = s_dyn;                         // max_m doubles
+    int* sperm = (int*)(s_dyn + max_m);           // max_m ints
+    const int r = T.r, c = T.c;
+    if (r > 0) {
+        for (int q = 0; q < T.nproj; ++q) {
+            const DProj Pj = projs[T.proj0 + q];
+            const int nrow = Pj.nrows;
+            for (int e = tid; e < nrow * r; e += NT) {
+                int a, t;
+                if (!Pj.trans) { a = e % nrow; t = e / nrow; }
+                else           { t = e % r;    a = e / r; }
+                double v;
+                if (T.svd) {                      // (B V)[row0 + a, t]
+                    const double* brow = T.B + (Pj.row0 + a);
+                    const double* vcol = T.V + (int64_t)t * c;
+                    v = 0.0;
+                    for (int j = 0; j < c; ++j) v += brow[(int64_t)j * T.M] * vcol[j];
+                } else {                          // transformed row-pivoted block
+                    v = T.B[(int64_t)(Pj.row0 + a) * c + t];
+                }
+                if (!Pj.trans) Pj.dst.p[imap_at(imap, Pj.map, a) + (int64_t)t * Pj.dst.nr] = v;   // R_k
+                else           Pj.dst.p[t + (int64_t)imap_at(imap, Pj.map, a) * r] = v;           // Q_k^T
+            }
+        }
+        for (int e = tid; e < c * r; e += NT) {
+            T.bs.p[e] = T.V[e];                          // V      (c x r)
+            const int t = e % r, a = e / r;
+            T.sb.p[e] = T.V[a + (int64_t)t * c];         // V^T    (r x c)
+        }
+        for (int e = tid; e < r * r; e += NT) {
+            const double v = (e % r == e / r) ? -1.0 : 0.0;
+            T.bP.p[e] = v;
+            T.Pb.p[e] = v;
+        }
+    }
+    __syncthreads();
+    eliminate(T.ps, ins, outs, pairs, imap, info, scol, sperm, s_d, s_i);
+    __syncthreads();
+    eliminate(T.pb, ins, outs, pairs, imap, info, scol, sperm, s_d, s_i);
+}
+
+// ------------------------------------------------------------------ solve sweeps
+__device__ __forceinline__ int map_abs(const int32_t* imap, int32_t base, int32_t map, int t) {
+    return map < 0 ? base + t : imap[map + t];
+}
+
+// Forward traversal (SolveL, Algorithm 3) for the super-node and its black node.
+// x holds the extended vector with ldx right-hand sides per variable; this
+// launch treats right-hand sides [k0, k0 + nrhs).
+__global__ __launch_bounds__(NT) void k_solve_fwd(const DSNode* __restrict__ nodes,
+                                                  const DSEdge* __restrict__ edges,
+                                                  const int32_t* __restrict__ imap,
+                                                  double* __restrict__ xg, int ldx, int k0, int nrhs) {
+    extern __shared__ double f[];
+    double* x = xg + k0;
+    const DSNode N = nodes[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int w = 0; w < 2; ++w) {
+        const DSPiv P = w == 0 ? N.s : N.b;
+        const int m = P.m;
+        if (m == 0) continue;
+        for (int e = tid; e < m * nrhs; e += NT) {
+            const int a = e / nrhs, k = e % nrhs;
+            double s = 0.0;
+            for (int t = 0; t < m; ++t) s += P.Sinv[a + (int64_t)t * m] * x[(int64_t)(P.off + t) * ldx + k];
+            f[e] = s;
+        }
+        __syncthreads();
+        for (int q = 0; q < P.nout; ++q) {
+            const DSEdge E = edges[P.out0 + q];
+            for (int e = tid; e < E.nr * nrhs; e += NT) {
+                const int a = e / nrhs, k = e % nrhs;
+                double s = 0.0;
+                for (int t = 0; t < E.nc; ++t)
+                    s += E.E[a + (int64_t)t * E.nr] * f[map_abs(imap, E.cbase, E.cmap, t) * nrhs + k];
+                x[(int64_t)map_abs(imap, E.rbase, E.rmap, a) * ldx + k] -= s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Backward traversal (SolveU, Algorithm 4) for the black node, then the super-node.
+__global__ __launch_bounds__(NT) void k_solve_bwd(const DSNode* __restrict__ nodes,
+                                                  const DSEdge* __restrict__ edges,
+                                                  const int32_t* __restrict__ imap,
+                                                  double* __restrict__ xg, int ldx, int k0, int nrhs) {
+    extern __shared__ double y[];
+    double* x = xg + k0;
+    const DSNode N = nodes[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int w = 0; w < 2; ++w) {
+        const DSPiv P = w == 0 ? N.b : N.s;
+        const int m = P.m;
+        if (m == 0) continue;
+        for (int e = tid; e < m * nrhs; e += NT) y[e] = x[(int64_t)(P.off + e / nrhs) * ldx + e % nrhs];
+        __syncthreads();
+        for (int q = 0; q < P.nin; ++q) {
+            const DSEdge E = edges[P.in0 + q];
+            for (int e = tid; e < E.nr * nrhs; e += NT) {
+                const int a = e / nrhs, k = e % nrhs;
+                double s = 0.0;
+                for (int t = 0; t < E.nc; ++t)
+                    s += E.E[a + (int64_t)t * E.nr] * x[(int64_t)map_abs(imap, E.cbase, E.cmap, t) * ldx + k];
+                y[map_abs(imap, E.rbase, E.rmap, a) * nrhs + k] -= s;
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < m * nrhs; e += NT) {
+            const int a = e / nrhs, k = e % nrhs;
+            double s = 0.0;
+            for (int t = 0; t < m; ++t) s += P.Sinv[a + (int64_t)t * m] * y[t * nrhs + k];
+            x[(int64_t)(P.off + a) * ldx + k] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ vectors
+__global__ void k_gather_perm(const double* __restrict__ b, int64_t ldb, const int32_t* __restrict__ perm,
+                              int n, int nrhs, double* __restrict__ xt, int64_t ntot) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntot * nrhs) return;
+    const int64_t t = e / nrhs;
+    const int k = (int)(e % nrhs);
+    xt[e] = t < n ? b[perm[t] + (int64_t)k * ldb] : 0.0;
+}
+
+__global__ void k_scatter_perm(const double* __restrict__ xt, const int32_t* __restrict__ perm, int n,
+                               int nrhs, double* __restrict__ x, int64_t ldx) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * nrhs) return;
+    const int64_t t = e / nrhs;
+    const int k = (int)(e % nrhs);
+    x[perm[t] + (int64_t)k * ldx] = xt[e];
+}
+
+template <bool RES>
+__global__ void k_spmv(int n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const double* __restrict__ v, const double* __restrict__ x,
+                       const double* __restrict__ b, double* __restrict__ y, int nrhs) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * nrhs) return;
+    const int64_t i = e / nrhs;
+    const int k = (int)(e % nrhs);
+    double s = 0.0;
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s += v[q] * x[(int64_t)ci[q] * nrhs + k];
+    y[e] = RES ? b[e] - s : s;
+}
+
+// partial[(j*nrhs + k) * gridDim.x + block]; nrhs <= 256
+__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t ldv, int J,
+                                              const double* __restrict__ w, int n, int nrhs,
+                                              double* __restrict__ partial, int sq) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int rpb = 256 / nrhs;                   // rows per block and pass
+    const int T = rpb * nrhs;
+    const int k = tid % nrhs, r0 = tid / nrhs;
+    for (int j = 0; j < J; ++j) {
+        const double* Vj = sq ? w : V + (int64_t)j * ldv;
+        double s = 0.0;
+        if (tid < T)
+            for (int64_t i = (int64_t)blockIdx.x * rpb + r0; i < n; i += (int64_t)gridDim.x * rpb)
+                s += Vj[i * nrhs + k] * w[i * nrhs + k];
+        red[tid] = s;
+        __syncthreads();
+        if (tid < nrhs) {
+            double t = 0.0;
+            for (int q = 0; q < rpb; ++q) t += red[q * nrhs + tid];
+            partial[((int64_t)j * nrhs + tid) * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int cnt,
+                                  double* __restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)q * nblk + b];
+    out[q] = s;
+}
+
+__global__ void k_mupdate(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
+                          double* __restrict__ w, int n, int nrhs) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * nrhs) return;
+    const int k = (int)(e % nrhs);
+    double s = w[e];
+    for (int j = 0; j < J; ++j) s -= V[(int64_t)j * ldv + e] * h[j * nrhs + k];
+    w[e] = s;
+}
+
+__global__ void k_normalize(const double* __restrict__ src, const double* __restrict__ nrm2,
+                            double* __restrict__ dst, int n, int nrhs) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * nrhs) return;
+    const int k = (int)(e % nrhs);
+    const double q = nrm2[k];
+    dst[e] = q > 0.0 ? src[e] / sqrt(q) : 0.0;
+}
+
+__global__ void k_xupdate(const double* __restrict__ Z, int64_t ldz, int J, const double* __restrict__ y,
+                          double* __restrict__ x, int n, int nrhs) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * nrhs) return;
+    const int k = (int)(e % nrhs);
+    double s = x[e];
+    for (int j = 0; j < J; ++j) s += Z[(int64_t)j * ldz + e] * y[j * nrhs + k];
+    x[e] = s;
+}
+
+__global__ void k_gather_idx(double* __restrict__ dst, const double* __restrict__ src,
+                             const int64_t* __restrict__ idx, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = src[idx[e]];
+}
+
+// Sums per block, then one atomic add per block on a global counter.
+__global__ void k_count_nonfinite(const double* __restrict__ v, int64_t n, unsigned long long* cnt) {
+    __shared__ int s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    int c = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        c += isfinite(v[e]) ? 0 : 1;
+    if (c) atomicAdd(&s, c);
+    __syncthreads();
+    if (threadIdx.x == 0 && s) atomicAdd(cnt, (unsigned long long)s);
+}
+
+inline unsigned nblocks(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_scatter(double* dst_base, const int64_t* idx, const double* val, int64_t nnz,
+                          hipStream_t st) {
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(nnz, 256)), dim3(256), 0, st, dst_base, idx, val, nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_idx(double* dst, const double* src, const int64_t* idx, int64_t n,
+                             hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_idx, dim3(nblocks(n, 256)), dim3(256), 0, st, dst, src, idx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const double* v, int64_t n, int64_t* cnt, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int64_t), st);
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(256), dim3(256), 0, st, v, n, (unsigned long long*)cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const DMerge* t, int n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge, dim3(n), dim3(256), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                           int max_c, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    size_t lds = (size_t)2 * (max_c > 0 ? max_c : 1) * sizeof(double);
+    hipLaunchKernelGGL(k_compress, dim3(n), dim3(NT), lds, st, t, pieces, imap);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                               int max_c, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t need = (size_t)2 * max_c * max_c * sizeof(double);
+    const int lds_mat = need <= 64 * 1024 ? 1 : 0;
+    hipLaunchKernelGGL(k_compress_svd, dim3(n), dim3(NT), lds_mat ? need : 0, st, t, pieces, imap, lds_mat);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DIn* ins,
+                              const DOut* outs, const DPair* pairs, const int32_t* imap,
+                              int32_t* info, int max_m, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    int mm = max_m > 0 ? max_m : 1;
+    size_t lds = (size_t)mm * sizeof(double) + (size_t)mm * sizeof(int);
+    hipLaunchKernelGGL(k_factor_node, dim3(n), dim3(NT), lds, st, t, proj, ins, outs, pairs, imap,
+                       info, mm);
+    return hipGetLastError();
+}
+
+static int rhs_chunk(int max_m, int nrhs) {
+    // keep the per-work-group vector block within 64 KiB of LDS
+    int mm = max_m > 0 ? max_m : 1;
+    int kc = (int)((64 * 1024) / ((size_t)mm * sizeof(double)));
+    if (kc < 1) kc = 1;
+    return kc < nrhs ? kc : nrhs;
+}
+
+hipError_t launch_solve_fwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
+                            double* x, int nrhs, int max_m, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int kc = rhs_chunk(max_m, nrhs);
+    for (int k0 = 0; k0 < nrhs; k0 += kc) {
+        const int nk = (nrhs - k0) < kc ? (nrhs - k0) : kc;
+        size_t lds = (size_t)(max_m > 0 ? max_m : 1) * nk * sizeof(double);
+        hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_bwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
+                            double* x, int nrhs, int max_m, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int kc = rhs_chunk(max_m, nrhs);
+    for (int k0 = 0; k0 < nrhs; k0 += kc) {
+        const int nk = (nrhs - k0) < kc ? (nrhs - k0) : kc;
+        size_t lds = (size_t)(max_m > 0 ? max_m : 1) * nk * sizeof(double);
+        hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_perm(const double* b, int64_t ldb, const int32_t* perm, int n, int nrhs,
+                              double* xt, int64_t ntot, hipStream_t st) {
+    int64_t work = ntot * nrhs;
+    if (work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_perm, dim3(nblocks(work, 256)), dim3(256), 0, st, b, ldb, perm, n, nrhs, xt, ntot);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_perm(const double* xt, const int32_t* perm, int n, int nrhs, double* x,
+                               int64_t ldx, hipStream_t st) {
+    int64_t work = (int64_t)n * nrhs;
+    hipLaunchKernelGGL(k_scatter_perm, dim3(nblocks(work, 256)), dim3(256), 0, st, xt, perm, n, nrhs, x, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(int n, const int64_t* rp, const int32_t* ci, const double* v, const double* x,
+                       double* y, int nrhs, hipStream_t st) {
+    int64_t work = (int64_t)n * nrhs;
+    hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(work, 256)), dim3(256), 0, st, n, rp, ci, v, x,
+                       (const double*)nullptr, y, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int n, const int64_t* rp, const int32_t* ci, const double* v,
+                           const double* x, const double* b, double* y, int nrhs, hipStream_t st) {
+    int64_t work = (int64_t)n * nrhs;
+    hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(work, 256)), dim3(256), 0, st, n, rp, ci, v, x, b, y, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_mdot(const double* V, int64_t ldv, int J, const double* w, int n, int nrhs,
+                       double* partial, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(256), 0, st, V, ldv, J, w, n, nrhs, partial, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int cnt = J * nrhs;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(cnt, 64)), dim3(64), 0, st, partial, kDotBlocks, cnt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mupdate(const double* V, int64_t ldv, int J, const double* h, double* w, int n,
+                          int nrhs, hipStream_t st) {
+    int64_t work = (int64_t)n * nrhs;
+    hipLaunchKernelGGL(k_mupdate, dim3(nblocks(work, 256)), dim3(256), 0, st, V, ldv, J, h, w, n, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqnorm(const double* w, int n, int nrhs, double* partial, double* out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(256), 0, st, w, (int64_t)0, 1, w, n, nrhs, partial, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(nrhs, 64)), dim3(64), 0, st, partial, kDotBlocks, nrhs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const double* src, const double* nrm2, double* dst, int n, int nrhs,
+                            hipStream_t st) {
+    int64_t work = (int64_t)n * nrhs;
+    hipLaunchKernelGGL(k_normalize, dim3(nblocks(work, 256)), dim3(256), 0, st, src, nrm2, dst, n, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_xupdate(const double* Z, int64_t ldz, int J, const double* y, double* x, int n,
+                          int nrhs, hipStream_t st) {
+    int64_t work = (int64_t)n * nrhs;
+    hipLaunchKernelGGL(k_xupdate, dim3(nblocks(work, 256)), dim3(256), 0, st, Z, ldz, J, y, x, n, nrhs);
+    return hipGetLastError();
+}
+
+}  // namespace lrx

@@ -1,0 +1,68 @@
+// Host-side launchers of the HIP kernels (kernels.hip).  All launches are
+// asynchronous on `st`; every pointer is device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dev.hpp"
+
+namespace lrx {
+
+constexpr int kFactorThreads = 256;
+
+// dst_base[idx[e]] = val[e], e < nnz
+hipError_t launch_scatter(double* dst_base, const int64_t* idx, const double* val, int64_t nnz,
+                          hipStream_t st);
+hipError_t launch_merge(const DMerge* t, int n, hipStream_t st);
+// dst[e] = src[idx[e]]
+hipError_t launch_gather_idx(double* dst, const double* src, const int64_t* idx, int64_t n,
+                             hipStream_t st);
+// *cnt = number of non-finite entries of v
+hipError_t launch_count_nonfinite(const double* v, int64_t n, int64_t* cnt, hipStream_t st);
+// lds_bytes: dynamic LDS per work-group
+hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                           int max_c, hipStream_t st);
+hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                               int max_c, hipStream_t st);
+hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DIn* ins,
+                              const DOut* outs, const DPair* pairs, const int32_t* imap,
+                              int32_t* info, int max_m, hipStream_t st);
+hipError_t launch_solve_fwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
+                            double* x, int nrhs, int max_m, hipStream_t st);
+hipError_t launch_solve_bwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
+                            double* x, int nrhs, int max_m, hipStream_t st);
+
+// ---- vectors: layout v[i * nrhs + k] ("row-interleaved") -------------------
+// xt[t*nrhs + k] = b[perm[t] + k*ldb]   (t < n)      and zero xt[n*nrhs .. ntot*nrhs)
+hipError_t launch_gather_perm(const double* b, int64_t ldb, const int32_t* perm, int n, int nrhs,
+                              double* xt, int64_t ntot, hipStream_t st);
+// x[perm[t] + k*ldx] = xt[t*nrhs + k]
+hipError_t launch_scatter_perm(const double* xt, const int32_t* perm, int n, int nrhs, double* x,
+                               int64_t ldx, hipStream_t st);
+// y = A x  (CSR, interleaved vectors)
+hipError_t launch_spmv(int n, const int64_t* rp, const int32_t* ci, const double* v, const double* x,
+                       double* y, int nrhs, hipStream_t st);
+// y = b - A x
+hipError_t launch_residual(int n, const int64_t* rp, const int32_t* ci, const double* v,
+                           const double* x, const double* b, double* y, int nrhs, hipStream_t st);
+// out[j*nrhs + k] = sum_i V_j[i,k] w[i,k], j < J (V_j = V + j*ldv); partial needs
+// J*nrhs*kDotBlocks doubles
+constexpr int kDotBlocks = 240;
+hipError_t launch_mdot(const double* V, int64_t ldv, int J, const double* w, int n, int nrhs,
+                       double* partial, double* out, hipStream_t st);
+// w[i,k] -= sum_j V_j[i,k] h[j*nrhs + k]
+hipError_t launch_mupdate(const double* V, int64_t ldv, int J, const double* h, double* w, int n,
+                          int nrhs, hipStream_t st);
+// out[k] = sum_i w[i,k]^2
+hipError_t launch_sqnorm(const double* w, int n, int nrhs, double* partial, double* out,
+                         hipStream_t st);
+// dst[i,k] = src[i,k] * (nrm2[k] > 0 ? 1/sqrt(nrm2[k]) : 0);  also beta[k] = sqrt(nrm2[k])
+hipError_t launch_normalize(const double* src, const double* nrm2, double* dst, int n, int nrhs,
+                            hipStream_t st);
+// x[i,k] += sum_j Z_j[i,k] y[j*nrhs + k]
+hipError_t launch_xupdate(const double* Z, int64_t ldz, int J, const double* y, double* x, int n,
+                          int nrhs, hipStream_t st);
+
+}  // namespace lrx

@@ -1,0 +1,1347 @@
+// C ABI of liblorax.so: validation, handle registry, numeric driver of the
+// factorization (Algorithm 1), solve program (Algorithms 2-4) and GMRES.
+#include "lorax.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "dev.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace lrx;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    lrx_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(lrx_status st, const std::string& m) { throw Fail{st, m}; }
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            fail(e_ == hipErrorOutOfMemory ? LRX_ENOMEM : LRX_EDEVICE,                    \
+                 std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// --------------------------------------------------------------- device memory
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b) {          // grows; contents are not preserved
+        if (b <= bytes) return;
+        release();
+        size_t nb = std::max(b, (size_t)4096);
+        HIPCHK(hipMalloc(&p, nb));
+        bytes = nb;
+    }
+    template <class T> T* as() const { return (T*)p; }
+};
+
+struct PinBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    PinBuf() = default;
+    PinBuf(const PinBuf&) = delete;
+    PinBuf& operator=(const PinBuf&) = delete;
+    ~PinBuf() { if (p) (void)hipHostFree(p); }
+    void ensure(size_t b) {          // caller guarantees no copy from it is in flight
+        if (b <= bytes) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        size_t nb = std::max(b * 2, (size_t)1 << 16);
+        HIPCHK(hipHostMalloc(&p, nb, hipHostMallocDefault));
+        bytes = nb;
+    }
+};
+
+// Chunked bump allocator for the stored blocks of the factorization.
+struct Arena {
+    std::vector<std::pair<double*, size_t>> chunks;   // pointer, capacity (doubles)
+    size_t used = 0;                                  // in the last chunk
+    int64_t total = 0;                                // doubles handed out
+    int64_t budget_bytes = 0;
+    ~Arena() { for (auto& c : chunks) (void)hipFree(c.first); }
+    double* alloc(size_t n) {
+        n = (n + 31) & ~(size_t)31;                   // 256-byte aligned blocks
+        if (chunks.empty() || used + n > chunks.back().second) {
+            size_t cap = std::max(n, (size_t)(32u << 20));   // 256 MiB chunks
+            double* p = nullptr;
+            HIPCHK(hipMalloc(&p, cap * sizeof(double)));
+            chunks.push_back({p, cap});
+            used = 0;
+        }
+        double* p = chunks.back().first + used;
+        used += n;
+        total += (int64_t)n;
+        if (budget_bytes > 0 && total * 8 > budget_bytes)
+            fail(LRX_ENOMEM, "factor storage exceeds hbm_budget_bytes");
+        return p;
+    }
+    int64_t reserved_bytes() const {
+        int64_t b = 0;
+        for (auto& c : chunks) b += (int64_t)c.second * 8;
+        return b;
+    }
+};
+
+template <class T> size_t append_bytes(std::vector<char>& buf, const std::vector<T>& v) {
+    size_t off = (buf.size() + 255) & ~(size_t)255;
+    buf.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+// per-pivot static maps (offsets into the factor's int table)
+struct PivMaps {
+    std::vector<int32_t> in_rmap, out_cmap, pair_rpos, pair_cpos;
+};
+struct NodeMaps {
+    std::vector<int32_t> a_map, b_map;   // stack pieces: A_k columns, B_k rows -> gamma
+    std::vector<int32_t> ra_map, qb_map; // R_k rows / Q_k^T columns -> their final blocks
+    PivMaps ps, pb;
+};
+
+struct SolveStep {
+    int32_t node0 = 0, nnode = 0, max_m = 0;
+    int64_t bytes_fwd = 0, bytes_bwd = 0;   // algorithmic bytes of one launch (one right-hand side)
+};
+
+// Optional event timing of every launch, by kernel class (lrx_timing_*).
+struct TimedLaunch {
+    int cls;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+std::mutex g_tmu;
+uint32_t g_timing = 0;                 // bit mask of timed kernel classes
+std::vector<TimedLaunch> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+lrx_timing_t g_acc{};
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) { hipEvent_t e = g_event_pool.back(); g_event_pool.pop_back(); return e; }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events when timing is on.
+struct LaunchTimer {
+    TimedLaunch t{};
+    bool on = false;
+    hipStream_t st;
+    LaunchTimer(int cls, hipStream_t s, double bytes, double flops) : st(s) {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        if (!(g_timing & (1u << cls))) return;
+        t.cls = cls; t.bytes = bytes; t.flops = flops;
+        t.a = take_event(); t.b = take_event();
+        if (!t.a || !t.b) return;
+        on = hipEventRecord(t.a, st) == hipSuccess;
+    }
+    ~LaunchTimer() {
+        if (!on) return;
+        (void)hipEventRecord(t.b, st);
+        std::lock_guard<std::mutex> lk(g_tmu);
+        g_pending.push_back(t);
+    }
+};
+
+void resolve_timing() {                  // caller holds g_tmu
+    for (auto& t : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            lrx_kernel_time& k = g_acc.k[t.cls];
+            k.launches += 1;
+            k.total_ms += ms;
+            k.bytes += t.bytes;
+            k.flops += t.flops;
+        }
+        g_event_pool.push_back(t.a);
+        g_event_pool.push_back(t.b);
+    }
+    g_pending.clear();
+}
+
+}  // namespace
+
+struct lrx_handle_s {
+    uint64_t magic = 0x6c72786861646c65ull;
+    Plan plan;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double epsilon = 0;
+    int32_t compress = LRX_SVD;
+    std::vector<int32_t> size;     // per node
+    std::vector<double*> eptr;     // per edge
+    std::vector<int64_t> var_off;  // per node
+    int64_t n_ext = 0;
+    Arena arena;
+    DevBuf d_imap;                 // factor maps
+    // solve program
+    DevBuf d_snodes, d_sedges, d_simap;
+    std::vector<SolveStep> ssteps;
+    DevBuf d_perm;
+    DevBuf d_rp, d_ci, d_val;      // A in tree order
+    int64_t nnz = 0;
+    // scratch
+    DevBuf x_ext, ws_b, ws_x;
+    DevBuf g_basis, g_z, g_w, g_r, g_b, g_x, g_small, g_partial;
+    PinBuf pin_small;
+    // stats
+    lrx_stats_t stats{};
+    std::vector<int32_t> ranks, rank_level, rank_j;
+    std::vector<double> tails;          // per compression: |R11|, ||R22||_F for k = 0..r
+    std::vector<int64_t> tail_off;
+    double max_tail_ratio = 0.0;
+};
+
+namespace {
+
+std::mutex g_reg_mu;
+std::set<lrx_handle> g_live;
+
+void check_handle(lrx_handle h) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    if (!h || !g_live.count(h)) fail(LRX_EINVAL, "invalid or freed handle");
+}
+
+int32_t dim_of(const Support& s, int32_t full) { return s.count(full); }
+
+void check_csr(const lrx_csr* A) {
+    if (!A) fail(LRX_EINVAL, "A is NULL");
+    if (A->n < 1 || A->nnz < 0) fail(LRX_EINVAL, "bad n or nnz");
+    if (!A->row_ptr || !A->col_idx || (!A->val && A->nnz > 0)) fail(LRX_EINVAL, "null CSR array");
+    for (int64_t e = 0; e < A->nnz; ++e)
+        if (!std::isfinite(A->val[e])) fail(LRX_EINVAL, "non-finite value in A");
+}
+
+void ensure_gfx950(int dev) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        fail(LRX_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+}
+
+// ------------------------------------------------------------------ factor driver
+void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
+    Plan& P = h->plan;
+    const hipStream_t st = h->stream;
+    const int32_t n = P.n;
+    h->size.assign(P.nodes.size(), -1);
+    h->eptr.assign(P.edges.size(), nullptr);
+    for (size_t v = 0; v < P.nodes.size(); ++v)
+        if (P.nodes[v].leaf) h->size[v] = P.nodes[v].static_size;
+
+    auto nr_of = [&](int32_t e) { const PEdge& E = P.edges[e]; return dim_of(E.rows, h->size[E.dst]); };
+    auto nc_of = [&](int32_t e) { const PEdge& E = P.edges[e]; return dim_of(E.cols, h->size[E.src]); };
+    auto blk = [&](int32_t e) {
+        DBlk b;
+        if (e < 0) { b.p = nullptr; b.nr = 0; b.nc = 0; return b; }   // empty pivot
+        b.p = h->eptr[e]; b.nr = nr_of(e); b.nc = nc_of(e);
+        return b;
+    };
+    // one contiguous, zeroed region for a group of new blocks (one memset)
+    auto alloc_group = [&](const std::vector<int32_t>& es) {
+        std::vector<size_t> off(es.size());
+        size_t tot = 0;
+        for (size_t q = 0; q < es.size(); ++q) {
+            off[q] = tot;
+            tot += (((size_t)nr_of(es[q]) * nc_of(es[q])) + 31) & ~(size_t)31;
+        }
+        if (es.empty()) return;
+        double* base = h->arena.alloc(std::max<size_t>(tot, 1));
+        for (size_t q = 0; q < es.size(); ++q) h->eptr[es[q]] = base + off[q];
+        HIPCHK(hipMemsetAsync(base, 0, std::max<size_t>(tot, 1) * 8, st));
+    };
+
+    // ---------------- static index maps (depend on supports only)
+    std::vector<int32_t> imap;
+    auto put_map = [&](const std::vector<int32_t>& v) -> int32_t {
+        int32_t off = (int32_t)imap.size();
+        imap.insert(imap.end(), v.begin(), v.end());
+        return off;
+    };
+    auto put_pos = [&](const Support& sub, const Support& sup) -> int32_t {
+        if (sub.all && sup.all) return -1;
+        std::vector<int32_t> v = positions(sub, sup, 0);
+        if (!sub.all && !sub.idx.empty() && (v.size() != sub.idx.size() || v[0] < 0))
+            fail(LRX_EDEVICE, "internal: support is not contained in its target");
+        if (sub.all) fail(LRX_EDEVICE, "internal: full support with a compact target");
+        return put_map(v);
+    };
+    std::vector<std::vector<NodeMaps>> maps(P.steps.size());
+    auto piv_maps = [&](const PivotPlan& pp, PivMaps& pm) {
+        for (int32_t e : pp.in_edges) {
+            const Support& r = P.edges[e].rows;
+            pm.in_rmap.push_back(r.all ? -1 : put_map(r.idx));
+        }
+        for (int32_t e : pp.out_edges) {
+            const Support& c = P.edges[e].cols;
+            pm.out_cmap.push_back(c.all ? -1 : put_map(c.idx));
+        }
+        for (size_t q = 0; q < pp.pair_edge.size(); ++q) {
+            const PEdge& T = P.edges[pp.pair_edge[q]];
+            const PEdge& O = P.edges[pp.out_edges[pp.pair_out[q]]];
+            const PEdge& I = P.edges[pp.in_edges[pp.pair_in[q]]];
+            // a compact source may land in a full target (e.g. a self block)
+            if ((!T.rows.all && O.rows.all) || (!T.cols.all && I.cols.all))
+                fail(LRX_EDEVICE, "internal: full source with a compact target in a Schur pair");
+            pm.pair_rpos.push_back(put_pos(O.rows, T.rows));
+            pm.pair_cpos.push_back(put_pos(I.cols, T.cols));
+        }
+    };
+    for (size_t si = 0; si < P.steps.size(); ++si) {
+        const ColourStep& cs = P.steps[si];
+        maps[si].resize(cs.nodes.size());
+        for (size_t ni = 0; ni < cs.nodes.size(); ++ni) {
+            const NodeStep& ns = cs.nodes[ni];
+            NodeMaps& nm = maps[si][ni];
+            for (const CandRef& cr : ns.cands) {
+                if (cr.e_sp >= 0) {
+                    nm.a_map.push_back(put_pos(P.edges[cr.e_sp].cols, ns.gamma));
+                    nm.ra_map.push_back(put_pos(P.edges[cr.e_sp].rows, P.edges[cr.e_Pp].rows));
+                } else { nm.a_map.push_back(-2); nm.ra_map.push_back(-2); }
+                if (cr.e_ps >= 0) {
+                    nm.b_map.push_back(put_pos(P.edges[cr.e_ps].rows, ns.gamma));
+                    nm.qb_map.push_back(put_pos(P.edges[cr.e_ps].cols, P.edges[cr.e_pP].cols));
+                } else { nm.b_map.push_back(-2); nm.qb_map.push_back(-2); }
+            }
+            piv_maps(ns.ps, nm.ps);
+            piv_maps(ns.pb, nm.pb);
+        }
+    }
+    h->d_imap.ensure(std::max<size_t>(imap.size(), 1) * sizeof(int32_t));
+    if (!imap.empty())
+        HIPCHK(hipMemcpyAsync(h->d_imap.p, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const int32_t* d_imap = h->d_imap.as<int32_t>();
+
+    // ---------------- initial blocks: A gathered into the leaf super-node blocks
+    {
+        int64_t tot = 0;
+        std::vector<int64_t> eoff(P.init_edges.size());
+        for (size_t q = 0; q < P.init_edges.size(); ++q) {
+            int32_t e = P.init_edges[q];
+            eoff[q] = tot;
+            tot += (((int64_t)nr_of(e) * nc_of(e)) + 31) & ~(int64_t)31;
+        }
+        double* base = h->arena.alloc((size_t)std::max<int64_t>(tot, 1));
+        std::vector<int32_t> slot(P.edges.size(), -1);
+        for (size_t q = 0; q < P.init_edges.size(); ++q) {
+            h->eptr[P.init_edges[q]] = base + eoff[q];
+            slot[P.init_edges[q]] = (int32_t)q;
+        }
+        HIPCHK(hipMemsetAsync(base, 0, (size_t)std::max<int64_t>(tot, 1) * 8, st));
+        // destination of every entry of A
+        std::vector<int32_t> leaf_of(n);
+        const int64_t nleaf = (int64_t)1 << P.depth;
+        for (int64_t c = 0; c < nleaf; ++c)
+            for (int32_t t = P.leaf_ptr[c]; t < P.leaf_ptr[c + 1]; ++t) leaf_of[t] = (int32_t)c;
+        // edge lookup per (src, dst) super pair
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> out_init(P.nodes.size());
+        for (int32_t e : P.init_edges) out_init[P.edges[e].src].push_back({P.edges[e].dst, e});
+        std::vector<int64_t> idx((size_t)A->nnz);
+        for (int32_t r = 0; r < n; ++r) {
+            const int32_t tr = P.pos[r];
+            const int32_t sd = leaf_of[tr] >> 1;
+            const int32_t lr = tr - P.nodes[sd].dof0;
+            for (int64_t q = A->row_ptr[r]; q < A->row_ptr[r + 1]; ++q) {
+                const int32_t tc = P.pos[A->col_idx[q]];
+                const int32_t ss = leaf_of[tc] >> 1;
+                const int32_t lc = tc - P.nodes[ss].dof0;
+                int32_t e = -1;
+                for (auto& pr : out_init[ss]) if (pr.first == sd) { e = pr.second; break; }
+                if (e < 0) fail(LRX_EDEVICE, "internal: missing initial edge");
+                const PEdge& E = P.edges[e];
+                int32_t pr_ = E.rows.all ? lr : (int32_t)(std::lower_bound(E.rows.idx.begin(), E.rows.idx.end(), lr) - E.rows.idx.begin());
+                int32_t pc_ = E.cols.all ? lc : (int32_t)(std::lower_bound(E.cols.idx.begin(), E.cols.idx.end(), lc) - E.cols.idx.begin());
+                idx[q] = eoff[slot[e]] + pr_ + (int64_t)pc_ * nr_of(e);
+            }
+        }
+        DevBuf d_idx, d_val;
+        d_idx.ensure(std::max<size_t>(idx.size(), 1) * 8);
+        if (A->nnz > 0) {
+            HIPCHK(hipMemcpyAsync(d_idx.p, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, st));
+            const double* src = val_dev;
+            if (!src) {
+                d_val.ensure(std::max<size_t>(idx.size(), 1) * 8);
+                HIPCHK(hipMemcpyAsync(d_val.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice, st));
+                src = d_val.as<double>();
+            }
+            HIPCHK(launch_scatter(base, d_idx.as<int64_t>(), src, A->nnz, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));   // d_idx/d_val are released at scope end
+    }
+
+    // ---------------- level loop
+    PinBuf stage_c, stage_n;              // descriptor staging (compress side, node side)
+    DevBuf d_desc_c, d_desc_n;
+    PinBuf pin_ranks;
+    DevBuf d_ranks, d_info;
+    DevBuf& ws = h->ws_b;
+    int32_t info_slots = 0;
+    {
+        int32_t npiv = 0;
+        for (auto& cs : P.steps) npiv += 2 * (int32_t)cs.nodes.size();
+        d_info.ensure(std::max(npiv, 1) * sizeof(int32_t));
+        HIPCHK(hipMemsetAsync(d_info.p, 0, std::max(npiv, 1) * sizeof(int32_t), st));
+    }
+    int64_t flops = 0;
+    for (size_t li = 0; li < P.levels.size(); ++li) {
+        const LevelPlan& L = P.levels[li];
+        if (L.level < P.depth) {
+            for (int32_t s : L.supers) {
+                const PNode& nd = P.nodes[s];
+                h->size[s] = h->size[nd.comp0] + h->size[nd.comp1];
+            }
+            alloc_group(L.merge_edges);
+            std::vector<DMerge> mt;
+            for (const MergePiece& mp : L.merges) {
+                DMerge d;
+                d.src = blk(mp.src_edge);
+                d.dst = blk(mp.dst_edge);
+                const PEdge& D = P.edges[mp.dst_edge];
+                d.r0 = mp.row_hi ? h->size[P.nodes[D.dst].comp0] : 0;
+                d.c0 = mp.col_hi ? h->size[P.nodes[D.src].comp0] : 0;
+                if (d.src.nr * d.src.nc > 0) mt.push_back(d);
+            }
+            if (!mt.empty()) {
+                std::vector<char> buf;
+                size_t o = append_bytes(buf, mt);
+                HIPCHK(hipStreamSynchronize(st));
+                stage_c.ensure(buf.size());
+                std::memcpy(stage_c.p, buf.data(), buf.size());
+                d_desc_c.ensure(buf.size());
+                HIPCHK(hipMemcpyAsync(d_desc_c.p, stage_c.p, buf.size(), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_merge((const DMerge*)(d_desc_c.as<char>() + o), (int)mt.size(), st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
+        }
+        for (int32_t si = L.step0; si < L.step0 + L.nsteps; ++si) {
+            const ColourStep& cs = P.steps[si];
+            const int nn = (int)cs.nodes.size();
+            // ---- compress descriptors
+            std::vector<DCompress> ct(nn);
+            std::vector<DPiece> pieces;
+            std::vector<std::vector<int32_t>> a_row0(nn), b_row0(nn);
+            size_t ws_need = 0;
+            std::vector<size_t> wsB(nn), wsV(nn), wsH(nn), wsT(nn);
+            int max_c = 1;
+            for (int ni = 0; ni < nn; ++ni) {
+                const NodeStep& ns = cs.nodes[ni];
+                const NodeMaps& nm = maps[si][ni];
+                const int32_t ms = h->size[ns.s];
+                DCompress& T = ct[ni];
+                T.piece0 = (int32_t)pieces.size();
+                int32_t row = 0;
+                for (size_t k = 0; k < ns.cands.size(); ++k) {
+                    const CandRef& cr = ns.cands[k];
+                    a_row0[ni].push_back(row);
+                    if (cr.e_sp >= 0) {
+                        DPiece pc{};
+                        pc.blk = blk(cr.e_sp); pc.trans = 0; pc.row0 = row; pc.map = nm.a_map[k];
+                        row += pc.blk.nr;
+                        if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
+                    }
+                }
+                for (size_t k = 0; k < ns.cands.size(); ++k) {
+                    const CandRef& cr = ns.cands[k];
+                    b_row0[ni].push_back(row);
+                    if (cr.e_ps >= 0) {
+                        DPiece pc{};
+                        pc.blk = blk(cr.e_ps); pc.trans = 1; pc.row0 = row; pc.map = nm.b_map[k];
+                        row += pc.blk.nc;
+                        if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
+                    }
+                }
+                T.npieces = (int32_t)pieces.size() - T.piece0;
+                T.M = row;
+                T.c = ns.gamma.count(ms);
+                T.eps = h->epsilon;
+                max_c = std::max(max_c, T.c);
+                const bool svd = h->compress == LRX_SVD;
+                wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
+                wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
+                wsH[ni] = ws_need; ws_need += ((size_t)T.c * T.c + T.c + 31) & ~(size_t)31;
+            }
+            size_t tails_total = 0;
+            for (int ni = 0; ni < nn; ++ni) { wsT[ni] = ws_need + tails_total; tails_total += (size_t)ct[ni].c + 2; }
+            const bool use_svd = h->compress == LRX_SVD;
+            ws_need += (tails_total + 31) & ~(size_t)31;
+            // node-side W workspace is sized after the ranks are known; reserve now
+            // for the worst case r <= c.
+            size_t w_need = 0;
+            for (int ni = 0; ni < nn; ++ni) {
+                const NodeStep& ns = cs.nodes[ni];
+                const int32_t ms = h->size[ns.s];
+                const int32_t rmax = std::min(ct[ni].c, ct[ni].M);
+                size_t sum_nc = 0;
+                for (int32_t e : ns.ps.in_edges) {
+                    const PEdge& E = P.edges[e];
+                    int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
+                    sum_nc += (size_t)dim_of(E.cols, srcsz);
+                }
+                w_need += (((size_t)ms * sum_nc) + 31) & ~(size_t)31;
+                size_t sum_nc_b = 0;
+                for (int32_t e : ns.pb.in_edges) {
+                    const PEdge& E = P.edges[e];
+                    int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
+                    sum_nc_b += (size_t)dim_of(E.cols, srcsz);
+                }
+                w_need += (((size_t)rmax * sum_nc_b) + 31) & ~(size_t)31;
+            }
+            const size_t ws_total = ws_need + w_need;
+            HIPCHK(hipStreamSynchronize(st));      // previous kernels done: buffers reusable
+            if (ws_total * 8 > ws.bytes) ws.ensure(ws_total * 8 + (ws_total * 8) / 2);
+            double* wsp = ws.as<double>();
+            d_ranks.ensure(std::max(nn, 1) * sizeof(int32_t));
+            for (int ni = 0; ni < nn; ++ni) {
+                ct[ni].B = wsp + wsB[ni];
+                ct[ni].Bw = use_svd ? wsp + wsB[ni] + (size_t)ct[ni].M * ct[ni].c : nullptr;
+                ct[ni].V = wsp + wsV[ni];
+                ct[ni].hv = wsp + wsH[ni];
+                ct[ni].tails = wsp + wsT[ni];
+                ct[ni].rank_out = d_ranks.as<int32_t>() + ni;
+            }
+            {
+                std::vector<char> buf;
+                size_t o1 = append_bytes(buf, ct);
+                size_t o2 = append_bytes(buf, pieces);
+                stage_c.ensure(buf.size());
+                std::memcpy(stage_c.p, buf.data(), buf.size());
+                d_desc_c.ensure(buf.size());
+                HIPCHK(hipMemcpyAsync(d_desc_c.p, stage_c.p, buf.size(), hipMemcpyHostToDevice, st));
+                double cfl = 0;
+                for (int ni = 0; ni < nn; ++ni)
+                    cfl += use_svd ? 4.0 * ct[ni].M * ct[ni].c * ct[ni].c + 8.0 * 6.0 * ct[ni].c * ct[ni].c * ct[ni].c
+                                   : 4.0 * ct[ni].M * ct[ni].c * ct[ni].c;
+                LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, cfl);
+                if (use_svd)
+                    HIPCHK(launch_compress_svd((const DCompress*)(d_desc_c.as<char>() + o1), nn,
+                                               (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c, st));
+                else
+                    HIPCHK(launch_compress((const DCompress*)(d_desc_c.as<char>() + o1), nn,
+                                           (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c, st));
+            }
+            pin_ranks.ensure(std::max(nn, 1) * sizeof(int32_t) + tails_total * 8 + 64);
+            HIPCHK(hipMemcpyAsync(pin_ranks.p, d_ranks.p, nn * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            double* tails_h = (double*)((char*)pin_ranks.p + (((size_t)nn * 4 + 63) & ~(size_t)63));
+            if (tails_total)
+                HIPCHK(hipMemcpyAsync(tails_h, wsp + wsT[0], tails_total * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int32_t* rk = (const int32_t*)pin_ranks.p;
+            for (int ni = 0; ni < nn; ++ni) {
+                const NodeStep& ns = cs.nodes[ni];
+                h->size[ns.b] = rk[ni];
+                h->size[ns.P] = rk[ni];
+                h->ranks.push_back(rk[ni]);
+                {
+                    const double* tl = tails_h + (wsT[ni] - wsT[0]);
+                    const bool emptyB = ct[ni].M == 0 || ct[ni].c == 0;
+                    const int len = emptyB ? 1 : (use_svd ? ct[ni].c + 1 : rk[ni] + 2);
+                    h->tail_off.push_back((int64_t)h->tails.size());
+                    h->tails.insert(h->tails.end(), tl, tl + len);
+                    double ratio = 0.0;
+                    if (!emptyB && tl[0] > 0) {
+                        if (use_svd) ratio = rk[ni] < ct[ni].c ? tl[1 + rk[ni]] / tl[0] : 0.0;
+                        else ratio = tl[1 + rk[ni]] / tl[0];
+                    }
+                    h->max_tail_ratio = std::max(h->max_tail_ratio, ratio);
+                }
+                h->rank_level.push_back(cs.level);
+                h->rank_j.push_back(ns.j);
+                // flops of the pivoted QR: ~4 M c r
+                flops += use_svd ? 4ll * ct[ni].M * ct[ni].c * ct[ni].c : 4ll * ct[ni].M * ct[ni].c * rk[ni];
+            }
+            // ---- allocate the blocks created in this step
+            alloc_group(cs.new_edges);
+            // ---- node descriptors
+            const int64_t flops_before_nodes = flops;
+            std::vector<DNode> nt(nn);
+            std::vector<DProj> projs;
+            std::vector<DIn> ins;
+            std::vector<DOut> outs;
+            std::vector<DPair> pairs;
+            size_t wcur = ws_need;
+            int max_m = 1;
+            auto build_piv = [&](const PivotPlan& pp, const PivMaps& pm, DPivot& D) {
+                const int32_t m = h->size[pp.node];
+                D.piv = blk(pp.e_self);
+                D.in0 = (int32_t)ins.size();
+                D.out0 = (int32_t)outs.size();
+                D.pair0 = (int32_t)pairs.size();
+                D.info_slot = info_slots++;
+                max_m = std::max(max_m, m);
+                for (size_t i = 0; i < pp.in_edges.size(); ++i) {
+                    DIn I{};
+                    I.blk = blk(pp.in_edges[i]);
+                    I.rmap = pm.in_rmap[i];
+                    I.W = wsp + wcur;
+                    wcur += (((size_t)m * I.blk.nc) + 31) & ~(size_t)31;
+                    ins.push_back(I);
+                    flops += 2ll * m * I.blk.nr * I.blk.nc;
+                }
+                for (size_t i = 0; i < pp.out_edges.size(); ++i) {
+                    DOut O{};
+                    O.blk = blk(pp.out_edges[i]);
+                    O.cmap = pm.out_cmap[i];
+                    outs.push_back(O);
+                }
+                for (size_t q = 0; q < pp.pair_edge.size(); ++q) {
+                    DPair Q{};
+                    Q.tgt = blk(pp.pair_edge[q]);
+                    Q.in_i = pp.pair_in[q];
+                    Q.out_i = pp.pair_out[q];
+                    Q.rpos = pm.pair_rpos[q];
+                    Q.cpos = pm.pair_cpos[q];
+                    const DOut& O = outs[D.out0 + Q.out_i];
+                    const DIn& I = ins[D.in0 + Q.in_i];
+                    flops += 2ll * O.blk.nr * O.blk.nc * I.blk.nc;
+                    pairs.push_back(Q);
+                }
+                D.nin = (int32_t)pp.in_edges.size();
+                D.nout = (int32_t)pp.out_edges.size();
+                D.npair = (int32_t)pp.pair_edge.size();
+                flops += 2ll * m * m * m;
+            };
+            for (int ni = 0; ni < nn; ++ni) {
+                const NodeStep& ns = cs.nodes[ni];
+                DNode& T = nt[ni];
+                const int32_t r = rk[ni];
+                T.r = r;
+                T.c = ct[ni].c;
+                T.M = ct[ni].M;
+                T.svd = use_svd ? 1 : 0;
+                T.B = ct[ni].B;
+                T.V = ct[ni].V;
+                T.proj0 = (int32_t)projs.size();
+                for (size_t k = 0; k < ns.cands.size(); ++k) {
+                    const CandRef& cr = ns.cands[k];
+                    if (cr.e_sp >= 0) {
+                        DProj pj{};
+                        pj.dst = blk(cr.e_Pp);
+                        pj.row0 = a_row0[ni][k];
+                        pj.nrows = nr_of(cr.e_sp);
+                        pj.trans = 0;
+                        pj.map = maps[si][ni].ra_map[k];
+                        if (pj.nrows > 0 && r > 0) projs.push_back(pj);
+                    }
+                    if (cr.e_ps >= 0) {
+                        DProj pj{};
+                        pj.dst = blk(cr.e_pP);
+                        pj.row0 = b_row0[ni][k];
+                        pj.nrows = nc_of(cr.e_ps);
+                        pj.trans = 1;
+                        pj.map = maps[si][ni].qb_map[k];
+                        if (pj.nrows > 0 && r > 0) projs.push_back(pj);
+                    }
+                }
+                T.nproj = (int32_t)projs.size() - T.proj0;
+                T.sb = blk(ns.e_sb);
+                T.bs = blk(ns.e_bs);
+                T.bP = blk(ns.e_bP);
+                T.Pb = blk(ns.e_Pb);
+                build_piv(ns.ps, maps[si][ni].ps, T.ps);
+                build_piv(ns.pb, maps[si][ni].pb, T.pb);
+            }
+            if (wcur * 8 > ws.bytes) fail(LRX_EDEVICE, "internal: workspace estimate too small");
+            {
+                std::vector<char> buf;
+                size_t o1 = append_bytes(buf, nt);
+                size_t o2 = append_bytes(buf, projs);
+                size_t o3 = append_bytes(buf, ins);
+                size_t o4 = append_bytes(buf, outs);
+                size_t o5 = append_bytes(buf, pairs);
+                stage_n.ensure(buf.size());
+                std::memcpy(stage_n.p, buf.data(), buf.size());
+                d_desc_n.ensure(buf.size());
+                HIPCHK(hipMemcpyAsync(d_desc_n.p, stage_n.p, buf.size(), hipMemcpyHostToDevice, st));
+                char* b = d_desc_n.as<char>();
+                LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)(flops - flops_before_nodes));
+                HIPCHK(launch_factor_node((const DNode*)(b + o1), nn, (const DProj*)(b + o2),
+                                          (const DIn*)(b + o3), (const DOut*)(b + o4),
+                                          (const DPair*)(b + o5), d_imap, d_info.as<int32_t>(), max_m, st));
+            }
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    {
+        std::vector<int32_t> info(std::max(info_slots, 1));
+        HIPCHK(hipMemcpy(info.data(), d_info.p, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int32_t v : info)
+            if (v) fail(LRX_ESINGULAR, "exactly singular pivot block");
+    }
+    h->stats.factor_flops = flops;
+}
+
+// ------------------------------------------------------------------ solve program
+void build_solve_program(lrx_handle h) {
+    Plan& P = h->plan;
+    const int32_t n = P.n;
+    h->var_off.assign(P.nodes.size(), -1);
+    for (size_t v = 0; v < P.nodes.size(); ++v)
+        if (P.nodes[v].leaf) h->var_off[v] = P.nodes[v].dof0;
+    int64_t off = n;
+    // red nodes of each level in index order (siblings adjacent), black nodes after
+    std::vector<std::vector<int32_t>> reds_by_level(P.depth + 1);
+    for (size_t v = 0; v < P.nodes.size(); ++v)
+        if (P.nodes[v].kind == NK_RED) reds_by_level[P.nodes[v].level].push_back((int32_t)v);
+    for (int32_t lev = P.depth - 1; lev >= 0; --lev) {
+        auto& R = reds_by_level[lev];
+        std::sort(R.begin(), R.end(), [&](int32_t a, int32_t b) { return P.nodes[a].idx < P.nodes[b].idx; });
+        for (int32_t v : R) { h->var_off[v] = off; off += std::max(h->size[v], 0); }
+    }
+    for (size_t v = 0; v < P.nodes.size(); ++v)
+        if (P.nodes[v].kind == NK_BLACK) { h->var_off[v] = off; off += std::max(h->size[v], 0); }
+    for (size_t v = 0; v < P.nodes.size(); ++v)
+        if (P.nodes[v].kind == NK_SUPER && !P.nodes[v].leaf) {
+            const PNode& nd = P.nodes[v];
+            h->var_off[v] = h->var_off[nd.comp0];
+            if (h->var_off[nd.comp1] != h->var_off[nd.comp0] + h->size[nd.comp0])
+                fail(LRX_EDEVICE, "internal: sibling red nodes are not adjacent");
+        }
+    h->n_ext = off;
+
+    std::vector<int32_t> simap;
+    std::vector<DSNode> nodes;
+    std::vector<DSEdge> edges;
+    auto abs_list = [&](const Support& s, int32_t node) -> int32_t {
+        if (s.all) return -1;
+        int32_t o = (int32_t)simap.size();
+        for (int32_t i : s.idx) simap.push_back((int32_t)(h->var_off[node] + i));
+        return o;
+    };
+    auto loc_list = [&](const Support& s) -> int32_t {
+        if (s.all) return -1;
+        int32_t o = (int32_t)simap.size();
+        simap.insert(simap.end(), s.idx.begin(), s.idx.end());
+        return o;
+    };
+    int64_t solve_bytes = 0;
+    auto piv = [&](const PivotPlan& pp) {
+        DSPiv D{};
+        const int32_t v = pp.node;
+        D.m = pp.e_self >= 0 ? h->size[v] : 0;
+        D.off = (int32_t)h->var_off[v];
+        D.Sinv = pp.e_self >= 0 ? h->eptr[pp.e_self] : nullptr;
+        solve_bytes += 2ll * D.m * D.m * 8;
+        D.out0 = (int32_t)edges.size();
+        for (size_t i = 0; i < pp.out_edges.size(); ++i) {
+            const int32_t e = pp.out_edges[i];
+            const PEdge& E = P.edges[e];
+            DSEdge s{};
+            s.E = h->eptr[e];
+            s.nr = dim_of(E.rows, h->size[E.dst]);
+            s.nc = dim_of(E.cols, h->size[E.src]);
+            if ((int64_t)s.nr * s.nc == 0) continue;
+            s.rbase = (int32_t)h->var_off[E.dst];
+            s.rmap = abs_list(E.rows, E.dst);
+            s.cbase = 0;
+            s.cmap = loc_list(E.cols);
+            solve_bytes += (int64_t)s.nr * s.nc * 8;
+            edges.push_back(s);
+        }
+        D.nout = (int32_t)edges.size() - D.out0;
+        D.in0 = (int32_t)edges.size();
+        for (size_t i = 0; i < pp.in_edges.size(); ++i) {
+            const int32_t e = pp.in_edges[i];
+            const PEdge& E = P.edges[e];
+            DSEdge s{};
+            s.E = h->eptr[e];
+            s.nr = dim_of(E.rows, h->size[E.dst]);
+            s.nc = dim_of(E.cols, h->size[E.src]);
+            if ((int64_t)s.nr * s.nc == 0) continue;
+            s.rbase = 0;
+            s.rmap = loc_list(E.rows);
+            s.cbase = (int32_t)h->var_off[E.src];
+            s.cmap = abs_list(E.cols, E.src);
+            solve_bytes += (int64_t)s.nr * s.nc * 8;
+            edges.push_back(s);
+        }
+        D.nin = (int32_t)edges.size() - D.in0;
+        return D;
+    };
+    h->ssteps.clear();
+    for (const ColourStep& cs : P.steps) {
+        SolveStep ss;
+        ss.node0 = (int32_t)nodes.size();
+        for (const NodeStep& ns : cs.nodes) {
+            DSNode d;
+            d.s = piv(ns.ps);
+            d.b = piv(ns.pb);
+            for (const DSPiv* pv : {&d.s, &d.b}) {
+                const int64_t pivb = (int64_t)pv->m * pv->m * 8;
+                int64_t ob = 0, ib = 0;
+                for (int32_t q = 0; q < pv->nout; ++q) ob += (int64_t)edges[pv->out0 + q].nr * edges[pv->out0 + q].nc * 8;
+                for (int32_t q = 0; q < pv->nin; ++q) ib += (int64_t)edges[pv->in0 + q].nr * edges[pv->in0 + q].nc * 8;
+                ss.bytes_fwd += pivb + ob;
+                ss.bytes_bwd += pivb + ib;
+            }
+            ss.max_m = std::max(ss.max_m, std::max(d.s.m, d.b.m));
+            nodes.push_back(d);
+        }
+        ss.nnode = (int32_t)nodes.size() - ss.node0;
+        h->ssteps.push_back(ss);
+    }
+    h->d_snodes.ensure(std::max<size_t>(nodes.size(), 1) * sizeof(DSNode));
+    h->d_sedges.ensure(std::max<size_t>(edges.size(), 1) * sizeof(DSEdge));
+    h->d_simap.ensure(std::max<size_t>(simap.size(), 1) * sizeof(int32_t));
+    if (!nodes.empty()) HIPCHK(hipMemcpy(h->d_snodes.p, nodes.data(), nodes.size() * sizeof(DSNode), hipMemcpyHostToDevice));
+    if (!edges.empty()) HIPCHK(hipMemcpy(h->d_sedges.p, edges.data(), edges.size() * sizeof(DSEdge), hipMemcpyHostToDevice));
+    if (!simap.empty()) HIPCHK(hipMemcpy(h->d_simap.p, simap.data(), simap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    h->stats.solve_bytes = solve_bytes;
+}
+
+// x_ext (n_ext x nrhs interleaved) -> in place sweeps
+void sweeps(lrx_handle h, double* xe, int nrhs) {
+    const hipStream_t st = h->stream;
+    const DSNode* nd = h->d_snodes.as<DSNode>();
+    const DSEdge* ed = h->d_sedges.as<DSEdge>();
+    const int32_t* im = h->d_simap.as<int32_t>();
+    for (const SolveStep& s : h->ssteps) {
+        LaunchTimer tm(LRX_K_SOLVE_FWD, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nrhs);
+        HIPCHK(launch_solve_fwd(nd + s.node0, s.nnode, ed, im, xe, nrhs, s.max_m, st));
+    }
+    for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it) {
+        LaunchTimer tm(LRX_K_SOLVE_BWD, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nrhs);
+        HIPCHK(launch_solve_bwd(nd + it->node0, it->nnode, ed, im, xe, nrhs, it->max_m, st));
+    }
+}
+
+// z (tree order, interleaved n x nrhs) = M^{-1} v
+void precond(lrx_handle h, const double* v, double* z, int nrhs) {
+    const hipStream_t st = h->stream;
+    const int64_t n = h->plan.n;
+    h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
+    double* xe = h->x_ext.as<double>();
+    HIPCHK(hipMemcpyAsync(xe, v, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
+    if (h->n_ext > n) HIPCHK(hipMemsetAsync(xe + n * nrhs, 0, (size_t)(h->n_ext - n) * nrhs * 8, st));
+    sweeps(h, xe, nrhs);
+    HIPCHK(hipMemcpyAsync(z, xe, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
+}
+
+void solve_dev(lrx_handle h, int nrhs, const double* b, double* x) {
+    const hipStream_t st = h->stream;
+    const int32_t n = h->plan.n;
+    h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
+    double* xe = h->x_ext.as<double>();
+    HIPCHK(launch_gather_perm(b, n, h->d_perm.as<int32_t>(), n, nrhs, xe, h->n_ext, st));
+    sweeps(h, xe, nrhs);
+    HIPCHK(launch_scatter_perm(xe, h->d_perm.as<int32_t>(), n, nrhs, x, n, st));
+}
+
+// ------------------------------------------------------------------ GMRES
+lrx_status gmres_dev(lrx_handle h, int nrhs, const double* b, double* x, double tol, int restart,
+                     int maxit, int32_t* iters_out, double* relres_out) {
+    const hipStream_t st = h->stream;
+    const int32_t n = h->plan.n;
+    const int64_t nv = (int64_t)n * nrhs;
+    const int m = restart;
+    h->g_basis.ensure((size_t)(m + 1) * nv * 8);
+    h->g_z.ensure((size_t)m * nv * 8);
+    h->g_w.ensure((size_t)nv * 8);
+    h->g_r.ensure((size_t)nv * 8);
+    h->g_b.ensure((size_t)nv * 8);
+    h->g_x.ensure((size_t)nv * 8);
+    const size_t small = (size_t)(3 * (m + 1) * nrhs + 4 * nrhs + 64);
+    h->g_small.ensure(small * 8);
+    h->g_partial.ensure((size_t)(m + 1) * nrhs * kDotBlocks * 8);
+    h->pin_small.ensure(small * 8);
+    double* V = h->g_basis.as<double>();
+    double* Z = h->g_z.as<double>();
+    double* w = h->g_w.as<double>();
+    double* r = h->g_r.as<double>();
+    double* bt = h->g_b.as<double>();
+    double* xt = h->g_x.as<double>();
+    double* d_h1 = h->g_small.as<double>();
+    double* d_h2 = d_h1 + (m + 1) * nrhs;
+    double* d_y = d_h2 + (m + 1) * nrhs;
+    double* d_n2 = d_y + (m + 1) * nrhs;
+    double* part = h->g_partial.as<double>();
+    double* hs = (double*)h->pin_small.p;
+    const int32_t* rp_perm = h->d_perm.as<int32_t>();
+    const int64_t* rp = h->d_rp.as<int64_t>();
+    const int32_t* ci = h->d_ci.as<int32_t>();
+    const double* av = h->d_val.as<double>();
+
+    HIPCHK(launch_gather_perm(b, n, rp_perm, n, nrhs, bt, n, st));
+    HIPCHK(hipMemsetAsync(xt, 0, (size_t)nv * 8, st));
+    HIPCHK(launch_sqnorm(bt, n, nrhs, part, d_n2, st));
+    HIPCHK(hipMemcpyAsync(hs, d_n2, nrhs * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> bnorm(nrhs), relres(nrhs, 0.0);
+    std::vector<int32_t> its(nrhs, 0);
+    std::vector<char> active(nrhs), conv(nrhs, 0);
+    for (int k = 0; k < nrhs; ++k) {
+        bnorm[k] = std::sqrt(hs[k]);
+        active[k] = bnorm[k] > 0.0;
+        if (!active[k]) conv[k] = 1;
+    }
+    std::vector<double> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
+        g((size_t)nrhs * (m + 1));
+    std::vector<int> kk(nrhs);
+    std::vector<char> done(nrhs);
+    while (true) {
+        HIPCHK(launch_residual(n, rp, ci, av, xt, bt, r, nrhs, st));
+        HIPCHK(launch_sqnorm(r, n, nrhs, part, d_n2, st));
+        HIPCHK(hipMemcpyAsync(hs, d_n2, nrhs * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool any = false;
+        for (int k = 0; k < nrhs; ++k) {
+            if (bnorm[k] == 0.0) continue;
+            relres[k] = std::sqrt(hs[k]) / bnorm[k];
+            if (!active[k]) continue;
+            if (relres[k] <= tol) { active[k] = 0; conv[k] = 1; }
+            else if (its[k] >= maxit) active[k] = 0;
+            if (active[k]) any = true;
+        }
+        if (!any) break;
+        // V_0 = r / ||r|| for active right-hand sides, 0 otherwise
+        for (int k = 0; k < nrhs; ++k) hs[k] = active[k] ? hs[k] : 0.0;
+        HIPCHK(hipMemcpyAsync(d_n2, hs, nrhs * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_normalize(r, d_n2, V, n, nrhs, st));
+        for (int k = 0; k < nrhs; ++k) {
+            std::fill(g.begin() + (size_t)k * (m + 1), g.begin() + (size_t)(k + 1) * (m + 1), 0.0);
+            g[(size_t)k * (m + 1)] = active[k] ? std::sqrt(hs[k]) : 0.0;
+            kk[k] = 0;
+            done[k] = !active[k];
+        }
+        for (int j = 0; j < m; ++j) {
+            double* Vj = V + (int64_t)j * nv;
+            double* Zj = Z + (int64_t)j * nv;
+            precond(h, Vj, Zj, nrhs);
+            {
+                LaunchTimer tm(LRX_K_SPMV, st, (double)h->nnz * 12 + (double)(n + 1) * 8 + 2.0 * nv * 8,
+                               2.0 * (double)h->nnz * nrhs);
+                HIPCHK(launch_spmv(n, rp, ci, av, Zj, w, nrhs, st));
+            }
+            // classical Gram-Schmidt, twice
+            HIPCHK(launch_mdot(V, nv, j + 1, w, n, nrhs, part, d_h1, st));
+            HIPCHK(launch_mupdate(V, nv, j + 1, d_h1, w, n, nrhs, st));
+            HIPCHK(launch_mdot(V, nv, j + 1, w, n, nrhs, part, d_h2, st));
+            HIPCHK(launch_mupdate(V, nv, j + 1, d_h2, w, n, nrhs, st));
+            HIPCHK(launch_sqnorm(w, n, nrhs, part, d_n2, st));
+            HIPCHK(launch_normalize(w, d_n2, V + (int64_t)(j + 1) * nv, n, nrhs, st));
+            HIPCHK(hipMemcpyAsync(hs, d_h1, (size_t)(2 * (m + 1) * nrhs) * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hs + 2 * (m + 1) * nrhs, d_n2, nrhs * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double* h1 = hs;
+            const double* h2 = hs + (m + 1) * nrhs;
+            const double* n2 = hs + 2 * (m + 1) * nrhs;
+            bool all_done = true;
+            for (int k = 0; k < nrhs; ++k) {
+                if (done[k]) continue;
+                double* Hk = H.data() + (size_t)k * (m + 1) * m;   // Hk[i*m + j]
+                double* gk = g.data() + (size_t)k * (m + 1);
+                double* ck = cs.data() + (size_t)k * m;
+                double* sk = sn.data() + (size_t)k * m;
+                for (int i = 0; i <= j; ++i) Hk[i * m + j] = h1[i * nrhs + k] + h2[i * nrhs + k];
+                Hk[(j + 1) * m + j] = std::sqrt(std::max(n2[k], 0.0));
+                for (int i = 0; i < j; ++i) {
+                    const double t = ck[i] * Hk[i * m + j] + sk[i] * Hk[(i + 1) * m + j];
+                    Hk[(i + 1) * m + j] = -sk[i] * Hk[i * m + j] + ck[i] * Hk[(i + 1) * m + j];
+                    Hk[i * m + j] = t;
+                }
+                const double a = Hk[j * m + j], bb = Hk[(j + 1) * m + j];
+                const double den = std::hypot(a, bb);
+                ck[j] = den != 0.0 ? a / den : 1.0;
+                sk[j] = den != 0.0 ? bb / den : 0.0;
+                Hk[j * m + j] = den;
+                Hk[(j + 1) * m + j] = 0.0;
+                gk[j + 1] = -sk[j] * gk[j];
+                gk[j] = ck[j] * gk[j];
+                its[k] += 1;
+                kk[k] = j + 1;
+                if (std::fabs(gk[j + 1]) <= tol * bnorm[k] || its[k] >= maxit || den == 0.0) done[k] = 1;
+                else all_done = false;
+            }
+            if (all_done) break;
+        }
+        // y_k from the triangular systems, then x += Z y
+        int J = 0;
+        std::vector<double> y((size_t)(m + 1) * nrhs, 0.0);
+        for (int k = 0; k < nrhs; ++k) {
+            if (!active[k] || kk[k] == 0) continue;
+            const double* Hk = H.data() + (size_t)k * (m + 1) * m;
+            const double* gk = g.data() + (size_t)k * (m + 1);
+            std::vector<double> yk(kk[k]);
+            for (int i = kk[k] - 1; i >= 0; --i) {
+                double s = gk[i];
+                for (int q = i + 1; q < kk[k]; ++q) s -= Hk[i * m + q] * yk[q];
+                yk[i] = Hk[i * m + i] != 0.0 ? s / Hk[i * m + i] : 0.0;
+            }
+            for (int i = 0; i < kk[k]; ++i) y[(size_t)i * nrhs + k] = yk[i];
+            J = std::max(J, kk[k]);
+        }
+        if (J > 0) {
+            std::memcpy(hs, y.data(), (size_t)J * nrhs * 8);
+            HIPCHK(hipMemcpyAsync(d_y, hs, (size_t)J * nrhs * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(launch_xupdate(Z, nv, J, d_y, xt, n, nrhs, st));
+        }
+    }
+    HIPCHK(launch_scatter_perm(xt, rp_perm, n, nrhs, x, n, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool all_conv = true;
+    for (int k = 0; k < nrhs; ++k) {
+        if (iters_out) iters_out[k] = its[k];
+        if (relres_out) relres_out[k] = relres[k];
+        if (!conv[k]) all_conv = false;
+    }
+    return all_conv ? LRX_OK : LRX_ENOCONV;
+}
+
+template <class F> lrx_status guarded(F&& f) {
+    try {
+        g_err.clear();
+        return f();
+    } catch (const Fail& e) {
+        g_err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return LRX_ENOMEM;
+    } catch (...) {
+        g_err = "unexpected exception";
+        return LRX_EDEVICE;
+    }
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* lrx_last_error(void) { return g_err.c_str(); }
+
+const char* lrx_version(void) { return "lorax 0.1 (gfx950)"; }
+
+lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order, lrx_plan_info* info) {
+    return guarded([&]() -> lrx_status {
+        if (!A || !T || !info) fail(LRX_EINVAL, "null argument");
+        if (A->n < 1 || A->nnz < 0 || !A->row_ptr || !A->col_idx) fail(LRX_EINVAL, "bad CSR");
+        Plan P;
+        std::string err = build_plan(A->n, A->nnz, A->row_ptr, A->col_idx, T->depth, T->perm,
+                                     T->leaf_ptr, order, P);
+        if (!err.empty()) fail(LRX_EINVAL, err);
+        std::memset(info, 0, sizeof(*info));
+        info->depth = P.depth;
+        int32_t nsup = 0;
+        for (auto& L : P.levels) {
+            nsup += (int32_t)L.supers.size();
+            if (L.level < 32) {
+                info->colours_by_level[L.level] = L.colours;
+                info->candidates_by_level[L.level] = L.candidates;
+            }
+        }
+        info->n_supernodes = nsup;
+        info->n_colour_steps = (int32_t)P.steps.size();
+        info->n_candidates = P.n_candidates;
+        info->n_schur_pairs = P.n_pairs;
+        int64_t created = 0;
+        for (auto& E : P.edges) if (E.origin != EO_INIT && E.origin != EO_MERGE) ++created;
+        info->n_edges_created = created;
+        return LRX_OK;
+    });
+}
+
+static lrx_status factor_impl(const lrx_csr* A, const double* val_dev, const lrx_tree* T,
+                              const lrx_opts* o, lrx_handle* out) {
+    lrx_handle h = nullptr;
+    lrx_status st = guarded([&]() -> lrx_status {
+        const double t0 = now_ms();
+        if (!out) fail(LRX_EINVAL, "out is NULL");
+        if (!T || !o) fail(LRX_EINVAL, "null tree or options");
+        if (val_dev) {
+            if (!A || A->n < 1 || A->nnz < 0 || !A->row_ptr || !A->col_idx) fail(LRX_EINVAL, "bad CSR pattern");
+        } else {
+            check_csr(A);
+        }
+        if (!(o->epsilon >= 0.0 && o->epsilon < 1.0)) fail(LRX_EINVAL, "epsilon must be in [0, 1)");
+        if (o->precision != LRX_FP64) fail(LRX_EINVAL, "only LRX_FP64 is implemented");
+        if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
+        if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
+        h = new lrx_handle_s();
+        std::string err = build_plan(A->n, A->nnz, A->row_ptr, A->col_idx, T->depth, T->perm,
+                                     T->leaf_ptr, o->order, h->plan);
+        if (!err.empty()) fail(LRX_EINVAL, err);
+        const double t1 = now_ms();
+        HIPCHK(hipGetDevice(&h->device));
+        ensure_gfx950(h->device);
+        h->stream = (hipStream_t)o->stream;
+        h->epsilon = o->epsilon;
+        h->compress = o->compress;
+        h->arena.budget_bytes = o->hbm_budget_bytes;
+        // A in tree order for the GMRES products
+        const int32_t n = A->n;
+        const Plan& P = h->plan;
+        std::vector<int64_t> rp(n + 1, 0);
+        std::vector<int32_t> ci((size_t)A->nnz);
+        std::vector<int64_t> src_of((size_t)A->nnz);
+        for (int32_t t = 0; t < n; ++t) {
+            const int32_t r = P.perm[t];
+            rp[t + 1] = rp[t] + (A->row_ptr[r + 1] - A->row_ptr[r]);
+        }
+        for (int32_t t = 0; t < n; ++t) {
+            const int32_t r = P.perm[t];
+            int64_t q = rp[t];
+            for (int64_t e = A->row_ptr[r]; e < A->row_ptr[r + 1]; ++e, ++q) {
+                ci[q] = P.pos[A->col_idx[e]];
+                src_of[q] = e;
+            }
+        }
+        h->nnz = A->nnz;
+        h->d_rp.ensure(rp.size() * 8);
+        h->d_ci.ensure(std::max<size_t>(ci.size(), 1) * 4);
+        h->d_val.ensure(std::max<size_t>(ci.size(), 1) * 8);
+        h->d_perm.ensure((size_t)n * 4);
+        const hipStream_t s0 = h->stream;
+        HIPCHK(hipMemcpyAsync(h->d_rp.p, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, s0));
+        HIPCHK(hipMemcpyAsync(h->d_perm.p, P.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+        if (A->nnz) {
+            HIPCHK(hipMemcpyAsync(h->d_ci.p, ci.data(), ci.size() * 4, hipMemcpyHostToDevice, s0));
+            DevBuf d_src, d_vh;
+            d_src.ensure(src_of.size() * 8);
+            HIPCHK(hipMemcpyAsync(d_src.p, src_of.data(), src_of.size() * 8, hipMemcpyHostToDevice, s0));
+            const double* vsrc = val_dev;
+            if (!vsrc) {
+                d_vh.ensure((size_t)A->nnz * 8);
+                HIPCHK(hipMemcpyAsync(d_vh.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice, s0));
+                vsrc = d_vh.as<double>();
+            } else {
+                DevBuf d_cnt;
+                d_cnt.ensure(8);
+                HIPCHK(launch_count_nonfinite(vsrc, A->nnz, d_cnt.as<int64_t>(), s0));
+                int64_t bad = 0;
+                HIPCHK(hipMemcpyAsync(&bad, d_cnt.p, 8, hipMemcpyDeviceToHost, s0));
+                HIPCHK(hipStreamSynchronize(s0));
+                if (bad) fail(LRX_EINVAL, "non-finite value in A");
+            }
+            HIPCHK(launch_gather_idx(h->d_val.as<double>(), vsrc, d_src.as<int64_t>(), A->nnz, s0));
+            HIPCHK(hipStreamSynchronize(s0));     // d_src, d_vh go out of scope
+        }
+
+        run_factor(h, A, val_dev);
+        build_solve_program(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        const double t2 = now_ms();
+
+        // statistics
+        lrx_stats_t& S = h->stats;
+        S.depth = P.depth;
+        S.n_compressions = (int32_t)h->ranks.size();
+        S.n_colour_steps = (int32_t)P.steps.size();
+        double rs = 0;
+        int32_t rmax = 0;
+        std::vector<double> lsum(33, 0), lcnt(33, 0), msum(33, 0);
+        for (size_t i = 0; i < h->ranks.size(); ++i) {
+            rs += h->ranks[i];
+            rmax = std::max(rmax, h->ranks[i]);
+            int lv = h->rank_level[i];
+            if (lv < 32) {
+                S.rank_max_by_level[lv] = std::max(S.rank_max_by_level[lv], h->ranks[i]);
+                lsum[lv] += h->ranks[i];
+                lcnt[lv] += 1;
+            }
+        }
+        for (auto& L : P.levels)
+            if (L.level < 32) {
+                double ms = 0;
+                for (int32_t s : L.supers) ms += h->size[s];
+                S.mean_node_size_by_level[L.level] = L.supers.empty() ? 0 : ms / L.supers.size();
+            }
+        for (int lv = 0; lv < 32; ++lv) S.rank_mean_by_level[lv] = lcnt[lv] ? lsum[lv] / lcnt[lv] : 0.0;
+        S.max_rank = rmax;
+        S.mean_rank = h->ranks.empty() ? 0.0 : rs / h->ranks.size();
+        S.extended_size = h->n_ext;
+        S.max_compression_error = h->max_tail_ratio;
+        S.factor_bytes = h->arena.total * 8;
+        S.t_plan_ms = t1 - t0;
+        S.t_factor_ms = t2 - t0;
+        {
+            std::lock_guard<std::mutex> lk(g_reg_mu);
+            g_live.insert(h);
+        }
+        *out = h;
+        return LRX_OK;
+    });
+    if (st != LRX_OK && h) {
+        std::lock_guard<std::mutex> lk(g_reg_mu);
+        if (!g_live.count(h)) delete h;
+    }
+    return st;
+}
+
+lrx_status lrx_factor(const lrx_csr* A, const lrx_tree* T, const lrx_opts* o, lrx_handle* out) {
+    return factor_impl(A, nullptr, T, o, out);
+}
+
+lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tree* T,
+                          const lrx_opts* o, lrx_handle* out) {
+    if (!val_dev) {
+        g_err = "val_dev is NULL";
+        return LRX_EINVAL;
+    }
+    return factor_impl(A, val_dev, T, o, out);
+}
+
+void lrx_timing_enable(int32_t class_mask) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = (uint32_t)class_mask;
+}
+
+lrx_status lrx_timing_read(lrx_timing_t* t, int32_t reset) {
+    return guarded([&]() -> lrx_status {
+        if (!t) fail(LRX_EINVAL, "null timing");
+        std::lock_guard<std::mutex> lk(g_tmu);
+        resolve_timing();
+        *t = g_acc;
+        if (reset) g_acc = lrx_timing_t{};
+        return LRX_OK;
+    });
+}
+
+
+lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+        if (!b_dev || !x_dev || b_dev == x_dev) fail(LRX_EINVAL, "bad b/x pointers");
+        solve_dev(h, nrhs, b_dev, x_dev);
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_solve(lrx_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        const int32_t n = h->plan.n;
+        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+        if (!b || !x || ldb < n || ldx < n) fail(LRX_EINVAL, "bad b/x or leading dimension");
+        for (int k = 0; k < nrhs; ++k)
+            for (int32_t i = 0; i < n; ++i)
+                if (!std::isfinite(b[i + k * ldb])) fail(LRX_EINVAL, "non-finite value in b");
+        DevBuf db, dx;
+        db.ensure((size_t)n * nrhs * 8);
+        dx.ensure((size_t)n * nrhs * 8);
+        HIPCHK(hipMemcpy2DAsync(db.p, (size_t)n * 8, b, (size_t)ldb * 8, (size_t)n * 8, nrhs,
+                                hipMemcpyHostToDevice, h->stream));
+        solve_dev(h, nrhs, db.as<double>(), dx.as<double>());
+        HIPCHK(hipMemcpy2DAsync(x, (size_t)ldx * 8, dx.p, (size_t)n * 8, (size_t)n * 8, nrhs,
+                                hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_gmres_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev, double tol,
+                         int32_t restart, int32_t maxit, int32_t* iters, double* relres) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+        if (!b_dev || !x_dev || b_dev == x_dev) fail(LRX_EINVAL, "bad b/x pointers");
+        if (!(tol > 0.0) || restart < 1 || restart > 200 || maxit < 0) fail(LRX_EINVAL, "bad tol/restart/maxit");
+        return gmres_dev(h, nrhs, b_dev, x_dev, tol, restart, maxit, iters, relres);
+    });
+}
+
+lrx_status lrx_gmres(const lrx_csr* A, lrx_handle h, int32_t nrhs, const double* b, double* x,
+                     double tol, int32_t restart, int32_t maxit, int32_t* iters, double* relres) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (!A || A->n != h->plan.n || A->nnz != h->nnz) fail(LRX_EINVAL, "A does not match the handle");
+        const int32_t n = h->plan.n;
+        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+        if (!b || !x) fail(LRX_EINVAL, "null b/x");
+        if (!(tol > 0.0) || restart < 1 || restart > 200 || maxit < 0) fail(LRX_EINVAL, "bad tol/restart/maxit");
+        for (int64_t i = 0; i < (int64_t)n * nrhs; ++i)
+            if (!std::isfinite(b[i])) fail(LRX_EINVAL, "non-finite value in b");
+        DevBuf db, dx;
+        db.ensure((size_t)n * nrhs * 8);
+        dx.ensure((size_t)n * nrhs * 8);
+        HIPCHK(hipMemcpyAsync(db.p, b, (size_t)n * nrhs * 8, hipMemcpyHostToDevice, h->stream));
+        lrx_status s = gmres_dev(h, nrhs, db.as<double>(), dx.as<double>(), tol, restart, maxit, iters, relres);
+        HIPCHK(hipMemcpyAsync(x, dx.p, (size_t)n * nrhs * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (s == LRX_ENOCONV) g_err = "GMRES reached maxit before tol";
+        return s;
+    });
+}
+
+lrx_status lrx_free(lrx_handle h) {
+    return guarded([&]() -> lrx_status {
+        if (!h) return LRX_OK;
+        {
+            std::lock_guard<std::mutex> lk(g_reg_mu);
+            if (!g_live.count(h)) fail(LRX_EINVAL, "handle already freed or invalid");
+            g_live.erase(h);
+        }
+        (void)hipStreamSynchronize(h->stream);
+        delete h;
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_stats(lrx_handle h, lrx_stats_t* s) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (!s) fail(LRX_EINVAL, "null stats");
+        *s = h->stats;
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t cap, int32_t* len) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (idx < 0 || idx >= (int32_t)h->ranks.size() || !len) fail(LRX_EINVAL, "bad compression index");
+        const int64_t a = h->tail_off[idx];
+        const int64_t b = (idx + 1 < (int32_t)h->tail_off.size()) ? h->tail_off[idx + 1] : (int64_t)h->tails.size();
+        *len = (int32_t)(b - a);
+        if (out) for (int64_t i = a; i < b && i - a < cap; ++i) out[i - a] = h->tails[i];
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_ranks(lrx_handle h, int32_t* ranks, int32_t* levels, int32_t* js) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (!ranks) fail(LRX_EINVAL, "null ranks");
+        for (size_t i = 0; i < h->ranks.size(); ++i) {
+            ranks[i] = h->ranks[i];
+            if (levels) levels[i] = h->rank_level[i];
+            if (js) js[i] = h->rank_j[i];
+        }
+        return LRX_OK;
+    });
+}
+
+}  // extern "C"

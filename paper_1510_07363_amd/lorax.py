@@ -1,0 +1,298 @@
+"""ctypes binding of liblorax.so (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels; this module converts
+NumPy arrays / torch tensors to plain pointers and sizes and raises LoraxError
+on a non-zero status.  Importing it loads liblorax.so and fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblorax.so")
+
+LRX_OK, LRX_EINVAL, LRX_ENOMEM, LRX_ESINGULAR, LRX_ENOCONV, LRX_EDEVICE, LRX_EBUSY = range(7)
+STATUS_NAMES = {0: "LRX_OK", 1: "LRX_EINVAL", 2: "LRX_ENOMEM", 3: "LRX_ESINGULAR",
+                4: "LRX_ENOCONV", 5: "LRX_EDEVICE", 6: "LRX_EBUSY"}
+LRX_FP64 = 0
+LRX_COLORED, LRX_NATURAL = 0, 1
+ORDERS = {"colored": LRX_COLORED, "natural": LRX_NATURAL}
+LRX_SVD, LRX_RRQR = 0, 1
+COMPRESS = {"svd": LRX_SVD, "rrqr": LRX_RRQR}
+
+
+class LoraxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.POINTER(C.c_int64)),
+                ("col_idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
+
+
+class Tree(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("perm", C.POINTER(C.c_int32)),
+                ("leaf_ptr", C.POINTER(C.c_int32))]
+
+
+class Opts(C.Structure):
+    _fields_ = [("epsilon", C.c_double), ("precision", C.c_int32), ("compress", C.c_int32),
+                ("order", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("n_compressions", C.c_int32),
+                ("n_colour_steps", C.c_int32), ("max_rank", C.c_int32),
+                ("mean_rank", C.c_double), ("rank_max_by_level", C.c_int32 * 32),
+                ("rank_mean_by_level", C.c_double * 32),
+                ("mean_node_size_by_level", C.c_double * 32),
+                ("extended_size", C.c_int64), ("max_compression_error", C.c_double),
+                ("factor_bytes", C.c_int64),
+                ("solve_bytes", C.c_int64), ("factor_flops", C.c_int64),
+                ("t_plan_ms", C.c_double), ("t_factor_ms", C.c_double)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("k", KernelTime * 8)]
+
+
+KERNEL_CLASSES = {0: "compress", 1: "factor_node", 2: "solve_fwd", 3: "solve_bwd", 4: "spmv"}
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("depth", C.c_int32), ("n_supernodes", C.c_int32),
+                ("n_colour_steps", C.c_int32), ("colours_by_level", C.c_int32 * 32),
+                ("n_candidates", C.c_int64), ("n_schur_pairs", C.c_int64),
+                ("n_edges_created", C.c_int64), ("candidates_by_level", C.c_int64 * 32)]
+
+
+# every symbol declared in include/lorax.h
+EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev", "lrx_gmres", "lrx_gmres_dev",
+           "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
+           "lrx_last_error", "lrx_version")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "or python -m paper_1510_07363_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    i32p, f64p = P(C.c_int32), P(C.c_double)
+    sig = {
+        "lrx_factor": (C.c_int, [P(Csr), P(Tree), P(Opts), P(C.c_void_p)]),
+        "lrx_factor_dev": (C.c_int, [P(Csr), C.c_void_p, P(Tree), P(Opts), P(C.c_void_p)]),
+        "lrx_timing_enable": (None, [C.c_int32]),
+        "lrx_timing_read": (C.c_int, [P(Timing), C.c_int32]),
+        "lrx_solve": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int64, f64p, C.c_int64]),
+        "lrx_solve_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+        "lrx_gmres": (C.c_int, [P(Csr), C.c_void_p, C.c_int32, f64p, f64p, C.c_double,
+                                C.c_int32, C.c_int32, i32p, f64p]),
+        "lrx_gmres_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_int32, C.c_int32, i32p, f64p]),
+        "lrx_free": (C.c_int, [C.c_void_p]),
+        "lrx_stats": (C.c_int, [C.c_void_p, P(Stats)]),
+        "lrx_ranks": (C.c_int, [C.c_void_p, i32p, i32p, i32p]),
+        "lrx_compression_tails": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int32, i32p]),
+        "lrx_plan_inspect": (C.c_int, [P(Csr), P(Tree), C.c_int32, P(PlanInfo)]),
+        "lrx_last_error": (C.c_char_p, []),
+        "lrx_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status):
+    if status != LRX_OK:
+        raise LoraxError(status, _lib.lrx_last_error().decode())
+
+
+def version():
+    return _lib.lrx_version().decode()
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _CsrArgs:
+    """Holds contiguous copies of the CSR arrays while a call runs."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        self.rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        self.v = np.ascontiguousarray(val, dtype=np.float64)
+        self.s = Csr(len(self.rp) - 1, int(self.rp[-1]), _ptr(self.rp, C.c_int64),
+                     _ptr(self.ci, C.c_int32), _ptr(self.v, C.c_double))
+
+
+class _TreeArgs:
+    def __init__(self, perm, leaf_ptr, depth):
+        self.perm = np.ascontiguousarray(perm, dtype=np.int32)
+        self.lp = np.ascontiguousarray(leaf_ptr, dtype=np.int32)
+        self.s = Tree(int(depth), _ptr(self.perm, C.c_int32), _ptr(self.lp, C.c_int32))
+
+
+def timing_enable(classes=None):
+    """Record HIP events around the launches of the given kernel classes (names
+    of KERNEL_CLASSES; None = all, [] = off)."""
+    if classes is None:
+        mask = 0xFF
+    else:
+        inv = {v: k for k, v in KERNEL_CLASSES.items()}
+        mask = 0
+        for c in classes:
+            mask |= 1 << inv[c]
+    _lib.lrx_timing_enable(mask)
+
+
+def timing_read(reset=True):
+    """Per kernel class: launches, total_ms, bytes, flops (event-measured)."""
+    t = Timing()
+    _check(_lib.lrx_timing_read(C.byref(t), 1 if reset else 0))
+    return {name: dict(launches=int(t.k[i].launches), total_ms=float(t.k[i].total_ms),
+                       bytes=float(t.k[i].bytes), flops=float(t.k[i].flops))
+            for i, name in KERNEL_CLASSES.items()}
+
+
+def plan_inspect(row_ptr, col_idx, perm, leaf_ptr, depth, order="colored"):
+    """Host-only symbolic plan counts (no device call)."""
+    A = _CsrArgs(row_ptr, col_idx, np.zeros(len(col_idx)))
+    T = _TreeArgs(perm, leaf_ptr, depth)
+    info = PlanInfo()
+    _check(_lib.lrx_plan_inspect(C.byref(A.s), C.byref(T.s), ORDERS[order], C.byref(info)))
+    d = int(info.depth)
+    return dict(depth=d, n_supernodes=int(info.n_supernodes),
+                n_colour_steps=int(info.n_colour_steps),
+                colours_by_level={i: int(info.colours_by_level[i]) for i in range(1, d + 1)},
+                candidates_by_level={i: int(info.candidates_by_level[i]) for i in range(1, d + 1)},
+                n_candidates=int(info.n_candidates), n_schur_pairs=int(info.n_schur_pairs),
+                n_edges_created=int(info.n_edges_created))
+
+
+class Factor:
+    """A factorization resident in HBM (wraps lrx_handle)."""
+
+    def __init__(self, row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon,
+                 order="colored", compress="svd", stream=None, hbm_budget_bytes=0,
+                 val_dev=None):
+        """val: host values, or None with val_dev = device address of the values."""
+        if val is None:
+            val = np.zeros(0)
+        self._A = _CsrArgs(row_ptr, col_idx, val)
+        T = _TreeArgs(perm, leaf_ptr, depth)
+        o = Opts(float(epsilon), LRX_FP64, COMPRESS[compress], ORDERS[order],
+                 int(hbm_budget_bytes), C.c_void_p(stream) if stream else None)
+        h = C.c_void_p()
+        if val_dev is not None:
+            _check(_lib.lrx_factor_dev(C.byref(self._A.s), C.c_void_p(val_dev), C.byref(T.s),
+                                       C.byref(o), C.byref(h)))
+        else:
+            _check(_lib.lrx_factor(C.byref(self._A.s), C.byref(T.s), C.byref(o), C.byref(h)))
+        self._h = h
+        self.n = len(self._A.rp) - 1
+
+    # ------------------------------------------------------------ host arrays
+    def solve(self, b):
+        """x ~ A^{-1} b (Algorithms 2-4); b of shape (n,) or (n, nrhs)."""
+        b = np.asarray(b, dtype=np.float64)
+        vec = b.ndim == 1
+        B = np.asfortranarray(b.reshape(self.n, -1))
+        X = np.zeros_like(B, order="F")
+        _check(_lib.lrx_solve(self._h, B.shape[1], _ptr(B, C.c_double), self.n,
+                              _ptr(X, C.c_double), self.n))
+        return X[:, 0] if vec else X
+
+    def gmres(self, b, tol=1e-10, restart=30, maxit=500, raise_on_noconv=True):
+        """Right-preconditioned GMRES; returns (x, iters, relres)."""
+        b = np.asarray(b, dtype=np.float64)
+        vec = b.ndim == 1
+        B = np.asfortranarray(b.reshape(self.n, -1))
+        k = B.shape[1]
+        X = np.zeros_like(B, order="F")
+        its = np.zeros(k, dtype=np.int32)
+        rr = np.zeros(k, dtype=np.float64)
+        st = _lib.lrx_gmres(C.byref(self._A.s), self._h, k, _ptr(B, C.c_double),
+                            _ptr(X, C.c_double), float(tol), int(restart), int(maxit),
+                            _ptr(its, C.c_int32), _ptr(rr, C.c_double))
+        if st != LRX_OK and (st != LRX_ENOCONV or raise_on_noconv):
+            _check(st)
+        return (X[:, 0] if vec else X), its, rr
+
+    # ------------------------------------------------------- device pointers
+    def solve_dev(self, b_ptr, x_ptr, nrhs):
+        """b_ptr, x_ptr: device addresses of n x nrhs column-major FP64 arrays."""
+        _check(_lib.lrx_solve_dev(self._h, int(nrhs), C.c_void_p(b_ptr), C.c_void_p(x_ptr)))
+
+    def gmres_dev(self, b_ptr, x_ptr, nrhs, tol=1e-10, restart=30, maxit=500):
+        its = np.zeros(nrhs, dtype=np.int32)
+        rr = np.zeros(nrhs, dtype=np.float64)
+        st = _lib.lrx_gmres_dev(self._h, int(nrhs), C.c_void_p(b_ptr), C.c_void_p(x_ptr),
+                                float(tol), int(restart), int(maxit), _ptr(its, C.c_int32),
+                                _ptr(rr, C.c_double))
+        if st not in (LRX_OK, LRX_ENOCONV):
+            _check(st)
+        return its, rr, st
+
+    # ------------------------------------------------------------ counters
+    def stats(self):
+        s = Stats()
+        _check(_lib.lrx_stats(self._h, C.byref(s)))
+        d = int(s.depth)
+        return dict(depth=d, n_compressions=int(s.n_compressions),
+                    n_colour_steps=int(s.n_colour_steps), max_rank=int(s.max_rank),
+                    mean_rank=float(s.mean_rank),
+                    rank_max_by_level={i: int(s.rank_max_by_level[i]) for i in range(1, d + 1)},
+                    rank_mean_by_level={i: float(s.rank_mean_by_level[i]) for i in range(1, d + 1)},
+                    mean_node_size_by_level={i: float(s.mean_node_size_by_level[i])
+                                             for i in range(1, d + 1)},
+                    extended_size=int(s.extended_size),
+                    max_compression_error=float(s.max_compression_error),
+                    factor_bytes=int(s.factor_bytes),
+                    solve_bytes=int(s.solve_bytes), factor_flops=int(s.factor_flops),
+                    t_plan_ms=float(s.t_plan_ms), t_factor_ms=float(s.t_factor_ms))
+
+    def ranks(self):
+        n = self.stats()["n_compressions"]
+        r = np.zeros(max(n, 1), dtype=np.int32)
+        lv = np.zeros_like(r)
+        js = np.zeros_like(r)
+        _check(_lib.lrx_ranks(self._h, _ptr(r, C.c_int32), _ptr(lv, C.c_int32), _ptr(js, C.c_int32)))
+        return r[:n], lv[:n], js[:n]
+
+    def tails(self, idx):
+        """SVD: [sigma_0, sigma_0..sigma_{c-1}]; RRQR: [|R11|, ||R22||_F at k = 0..rank]."""
+        n = C.c_int32()
+        _check(_lib.lrx_compression_tails(self._h, int(idx), None, 0, C.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        _check(_lib.lrx_compression_tails(self._h, int(idx), _ptr(out, C.c_double), n.value,
+                                          C.byref(n)))
+        return out[:n.value]
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _check(_lib.lrx_free(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
