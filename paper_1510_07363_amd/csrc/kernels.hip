@@ -17,6 +17,7 @@ namespace {
 
 constexpr int NT = kFactorThreads;
 constexpr int WAVE = 64;
+constexpr int kLdsBudget = 152 * 1024;      // dynamic LDS a work-group may request (160 KiB per CU)
 
 __device__ __forceinline__ int imap_at(const int32_t* imap, int32_t map, int t) {
     return map < 0 ? t : imap[map + t];
@@ -173,13 +174,10 @@ __global__ __launch_bounds__(NT) void k_compress(const DCompress* __restrict__ t
 // singular values sorted in descending order, rank = #{sigma_k >= eps sigma_0}.
 // R and V live in LDS when `lds_mat` is set (2 c^2 doubles), otherwise in the
 // task's workspace.
-constexpr int JG = 16;                         // lanes per Jacobi pair
-
-__device__ __forceinline__ double group_sum16(double v) {
-    v += __shfl_xor(v, 8, 16);
-    v += __shfl_xor(v, 4, 16);
-    v += __shfl_xor(v, 2, 16);
-    v += __shfl_xor(v, 1, 16);
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
     return v;
 }
 
@@ -207,13 +205,17 @@ __device__ double block_sum(double v, double* s_s) {
     return t;
 }
 
+template <int JG>   // lanes per Jacobi pair
 __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict__ tasks,
                                                      const DPiece* __restrict__ pieces,
                                                      const int32_t* __restrict__ imap,
-                                                     int lds_mat) {
+                                                     int ch) {
+    // ch > 0: R, V and a chunk of ch rows of B live in LDS (2 c^2 + ch c doubles);
+    // ch == 0: everything in the task's workspace.
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
     const int lane = tid % WAVE, wv = tid / WAVE;
+    constexpr int NW = NT / WAVE;
     __shared__ double s_s[NT / WAVE + 1];
     __shared__ int s_rot;
     extern __shared__ double s_dyn[];
@@ -222,7 +224,6 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
         return;
     }
     double* __restrict__ B = T.B;
-    double* __restrict__ W = T.Bw;
     // ---- assemble B (column-major, ld M)
     for (int64_t e = tid; e < (int64_t)M * c; e += NT) B[e] = 0.0;
     __syncthreads();
@@ -237,52 +238,104 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
         }
     }
     __syncthreads();
-    for (int64_t e = tid; e < (int64_t)M * c; e += NT) W[e] = B[e];
-    __syncthreads();
-    // ---- Householder QR of W by columns; R ends in the upper triangle of W's
-    //      first c rows, with the diagonal kept in `rdiag` (the v's are below)
-    double* Rm = lds_mat ? s_dyn : T.hv;                 // c x c
-    double* Vm = lds_mat ? s_dyn + (size_t)c * c : T.V;  // c x c
-    const int kq = M < c ? M : c;
+    const bool lds = ch > 0;
+    double* Rm = lds ? s_dyn : T.hv;                      // c x c
+    double* Vm = lds ? s_dyn + (size_t)c * c : T.V;       // c x c
     for (int e = tid; e < c * c; e += NT) Rm[e] = 0.0;
-    for (int j = 0; j < kq; ++j) {
-        double part = 0.0;
-        for (int i = j + tid; i < M; i += NT) { const double x = W[i + (int64_t)j * M]; part += x * x; }
-        const double s2 = block_sum(part, s_s);
-        const double x0 = W[j + (int64_t)j * M];
-        const double xn = sqrt(s2);
-        const double alpha = xn == 0.0 ? 0.0 : -copysign(xn, x0);
-        const double beta = 2.0 * (s2 + fabs(x0) * xn);          // v.v
+    if (lds) {
+        // ---- QR of B, chunk by chunk: the triangle R and ch rows of B in LDS.
+        // Column j of [R; chunk] is annihilated by a reflector that touches row
+        // j of R and the chunk only (R is upper triangular).
+        double* Ch = s_dyn + (size_t)2 * c * c;           // ch x c, column-major
         __syncthreads();
-        if (tid == 0) {
-            W[j + (int64_t)j * M] = x0 - alpha;
-            Rm[j + (int64_t)j * c] = alpha;
-        }
-        __syncthreads();
-        if (beta > 0.0) {
-            const double tau = 2.0 / beta;
-            const double* v = W + (int64_t)j * M;
-            for (int k = j + 1 + wv; k < c; k += NT / WAVE) {
-                double* col = W + (int64_t)k * M;
-                double w = 0.0;
-                for (int i = j + lane; i < M; i += WAVE) w += v[i] * col[i];
-                w = wave_sum(w) * tau;
-                for (int i = j + lane; i < M; i += WAVE) col[i] -= w * v[i];
+        for (int i0 = 0; i0 < M; i0 += ch) {
+            const int rows = min(ch, M - i0);
+            for (int e = tid; e < rows * c; e += NT) {
+                const int r = e % rows, k = e / rows;
+                Ch[r + k * ch] = B[(i0 + r) + (int64_t)k * M];
             }
+            __syncthreads();
+            for (int j = 0; j < c; ++j) {
+                double part = 0.0;
+                for (int r = tid; r < rows; r += NT) { const double x = Ch[r + j * ch]; part += x * x; }
+                const double s2c = block_sum(part, s_s);
+                if (s2c == 0.0) continue;                 // nothing below R[j][j] in this chunk
+                const double x0 = Rm[j + j * c];
+                const double s2 = x0 * x0 + s2c;
+                const double xn = sqrt(s2);
+                const double alpha = -copysign(xn, x0);
+                const double tau = 2.0 / (2.0 * (s2 + fabs(x0) * xn));
+                const double v0 = x0 - alpha;
+                const double* vj = Ch + j * ch;
+                for (int k = j + 1 + wv; k < c; k += NW) {
+                    double* ck = Ch + k * ch;
+                    double w = 0.0;
+                    for (int r = lane; r < rows; r += WAVE) w += vj[r] * ck[r];
+                    w = (wave_sum(w) + v0 * Rm[j + k * c]) * tau;
+                    for (int r = lane; r < rows; r += WAVE) ck[r] -= w * vj[r];
+                    if (lane == 0) Rm[j + k * c] -= w * v0;
+                }
+                __syncthreads();
+                if (tid == 0) Rm[j + j * c] = alpha;
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < c * c; e += NT) Vm[e] = (e % c == e / c) ? 1.0 : 0.0;
+        __syncthreads();
+    } else {
+        // ---- Householder QR of a workspace copy of B, by columns
+        double* __restrict__ W = T.Bw;
+        for (int64_t e = tid; e < (int64_t)M * c; e += NT) W[e] = B[e];
+        __syncthreads();
+        const int kq = M < c ? M : c;
+        for (int j = 0; j < kq; ++j) {
+            double part = 0.0;
+            for (int i = j + tid; i < M; i += NT) { const double x = W[i + (int64_t)j * M]; part += x * x; }
+            const double s2 = block_sum(part, s_s);
+            const double x0 = W[j + (int64_t)j * M];
+            const double xn = sqrt(s2);
+            const double alpha = xn == 0.0 ? 0.0 : -copysign(xn, x0);
+            const double beta = 2.0 * (s2 + fabs(x0) * xn);          // v.v
+            __syncthreads();
+            if (tid == 0) {
+                W[j + (int64_t)j * M] = x0 - alpha;
+                Rm[j + (int64_t)j * c] = alpha;
+            }
+            __syncthreads();
+            if (beta > 0.0) {
+                const double tau = 2.0 / beta;
+                const double* v = W + (int64_t)j * M;
+                for (int k = j + 1 + wv; k < c; k += NW) {
+                    double* col = W + (int64_t)k * M;
+                    double w = 0.0;
+#pragma unroll 4
+                    for (int i = j + lane; i < M; i += WAVE) w += v[i] * col[i];
+                    w = wave_sum(w) * tau;
+#pragma unroll 4
+                    for (int i = j + lane; i < M; i += WAVE) col[i] -= w * v[i];
+                }
+            }
+            __syncthreads();
+        }
+        // R: strict upper part from W, diagonal already written; rows >= kq are zero
+        for (int e = tid; e < c * c; e += NT) {
+            const int a = e % c, k = e / c;
+            if (a < k && a < kq) Rm[e] = W[a + (int64_t)k * M];
+            Vm[e] = (a == k) ? 1.0 : 0.0;
         }
         __syncthreads();
     }
-    // R: strict upper part from W, diagonal already written; rows >= kq are zero
-    for (int e = tid; e < c * c; e += NT) {
-        const int a = e % c, k = e / c;
-        if (a < k && a < kq) Rm[e] = W[a + (int64_t)k * M];
-        Vm[e] = (a == k) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    // ---- one-sided Jacobi on the columns of R; V accumulates the rotations
+    // ---- one-sided Jacobi on the columns of R; V accumulates the rotations.
+    // Columns whose norm is at the rounding level of R (1e-15 ||R||_F) carry no
+    // information; pairs involving them are not rotated, which keeps rounding
+    // noise from re-triggering sweeps.
     const int n2 = c + (c & 1);
     const int g = tid / JG, gl = tid % JG;
     const double tol = 4.0e-16 * (double)c;
+    double fro = 0.0;
+    for (int e = tid; e < c * c; e += NT) fro += Rm[e] * Rm[e];
+    fro = block_sum(fro, s_s);
+    const double tiny2 = 1e-30 * fro;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
@@ -299,8 +352,8 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
                     const double x = cp[r], y = cq[r];
                     al += x * x; be += y * y; ga += x * y;
                 }
-                al = group_sum16(al); be = group_sum16(be); ga = group_sum16(ga);
-                if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be))) continue;
+                al = group_sum<JG>(al); be = group_sum<JG>(be); ga = group_sum<JG>(ga);
+                if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be)) || al <= tiny2 || be <= tiny2) continue;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -342,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
         for (int k = 0; k < c; ++k) r += (T.tails[1 + k] >= T.eps * smax) ? 1 : 0;
     // V (c x r): output column pos(k) is column k of the accumulated rotations
     const double* Vsrc = Vm;
-    if (!lds_mat) {                       // Vm is T.V itself: stage it in hv (R is done)
+    if (!lds) {                           // Vm is T.V itself: stage it in hv (R is done)
         for (int e = tid; e < c * c; e += NT) T.hv[e] = Vm[e];
         __syncthreads();
         Vsrc = T.hv;
@@ -359,9 +412,13 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
 }
 
 // ------------------------------------------------------------------ elimination
+constexpr int NTN = 512;                     // threads of the node-factorization kernel
+constexpr int NWN = NTN / WAVE;
+
 // In-place inverse of the m x m column-major block by Gauss-Jordan elimination
-// with partial (row) pivoting inside the block; returns false if a pivot is 0.
-__device__ bool gj_inverse(double* A, int m, double* scol, int* sperm, double* s_d, int* s_i) {
+// with partial (row) pivoting inside the block (large blocks, global memory);
+// returns false if a pivot is 0.  scol: m doubles, sperm: m ints of LDS.
+__device__ bool gj_inverse_global(double* A, int m, double* scol, int* sperm, double* s_d) {
     const int tid = threadIdx.x;
     for (int k = 0; k < m; ++k) {
         if (tid < WAVE) {
@@ -382,19 +439,19 @@ __device__ bool gj_inverse(double* A, int m, double* scol, int* sperm, double* s
         const int p = sperm[k];
         if (!(s_d[0] > 0.0)) return false;
         if (p != k)
-            for (int j = tid; j < m; j += NT) {
+            for (int j = tid; j < m; j += NTN) {
                 double t = A[k + (int64_t)j * m];
                 A[k + (int64_t)j * m] = A[p + (int64_t)j * m];
                 A[p + (int64_t)j * m] = t;
             }
         __syncthreads();
         const double d = 1.0 / A[k + (int64_t)k * m];
-        for (int i = tid; i < m; i += NT) scol[i] = A[i + (int64_t)k * m];
+        for (int i = tid; i < m; i += NTN) scol[i] = A[i + (int64_t)k * m];
         __syncthreads();
-        for (int j = tid; j < m; j += NT)
+        for (int j = tid; j < m; j += NTN)
             A[k + (int64_t)j * m] = (j == k) ? d : A[k + (int64_t)j * m] * d;
         __syncthreads();
-        for (int e = tid; e < m * m; e += NT) {
+        for (int e = tid; e < m * m; e += NTN) {
             const int i = e % m, j = e / m;
             if (i == k) continue;
             const double f = scol[i];
@@ -403,7 +460,7 @@ __device__ bool gj_inverse(double* A, int m, double* scol, int* sperm, double* s
         }
         __syncthreads();
     }
-    for (int i = tid; i < m; i += NT)
+    for (int i = tid; i < m; i += NTN)
         for (int k = m - 1; k >= 0; --k) {
             const int p = sperm[k];
             if (p != k) {
@@ -416,70 +473,200 @@ __device__ bool gj_inverse(double* A, int m, double* scol, int* sperm, double* s
     return true;
 }
 
-// Block Gauss elimination of one pivot (Sec. 2.2): invert Mat(v->v), form
-// W_k = Mat(v->v)^{-1} Mat(k->v) for every in-edge, then for every pair
-// Mat(k->q) -= Mat(v->q) W_k.
+// Register-resident Gauss-Jordan inverse with partial pivoting for m <= MB:
+// thread t owns row t % MB, columns [(t / MB) * CPT, + CPT); the matrix is
+// padded with the identity beyond m.  Pivot row and column go through LDS.
+// `lds` needs 3 * MB doubles + 2 * MB ints + NWN (double, int) slots.
+template <int MB>
+__device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
+    constexpr int TPR = NTN / MB;         // threads per row
+    constexpr int CPT = MB / TPR;         // columns per thread
+    const int tid = threadIdx.x;
+    const int i = tid % MB, h = tid / MB, c0 = h * CPT;
+    double* prow = lds;                   // MB
+    double* pcol = lds + MB;              // MB
+    double* rbuf = lds + 2 * MB;          // MB (row exchange)
+    int* perm = (int*)(lds + 3 * MB);     // MB
+    int* dest = perm + MB;                // MB
+    double* rv = (double*)(dest + MB);    // NWN reduction values
+    int* ri = (int*)(rv + NWN);           // NWN reduction indices
+    double a[CPT];
+#pragma unroll
+    for (int jj = 0; jj < CPT; ++jj) {
+        const int col = c0 + jj;
+        a[jj] = (i < m && col < m) ? A[i + (int64_t)col * m] : (i == col ? 1.0 : 0.0);
+    }
+    for (int k = 0; k < m; ++k) {
+        const int kh = k / CPT, kj = k % CPT;
+        double v = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) v = (jj == kj) ? a[jj] : v;
+        // ---- pivot: largest |A[i, k]|, i in [k, m), lowest index on ties
+        double best = -1.0;
+        int bi = INT_MAX;
+        if (h == kh && i >= k && i < m) { best = fabs(v); bi = i; }
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const double ob = __shfl_down(best, o);
+            const int oi = __shfl_down(bi, o);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (tid % WAVE == 0) { rv[tid / WAVE] = best; ri[tid / WAVE] = bi; }
+        __syncthreads();
+        best = rv[0]; bi = ri[0];
+        for (int w = 1; w < NWN; ++w)
+            if (rv[w] > best || (rv[w] == best && ri[w] < bi)) { best = rv[w]; bi = ri[w]; }
+        if (!(best > 0.0)) return false;          // uniform
+        const int p = bi;
+        if (tid == 0) perm[k] = p;
+        // ---- swap rows k and p
+        if (p != k) {
+            if (i == p) {
+#pragma unroll
+                for (int jj = 0; jj < CPT; ++jj) rbuf[c0 + jj] = a[jj];
+            }
+            if (i == k) {
+#pragma unroll
+                for (int jj = 0; jj < CPT; ++jj) prow[c0 + jj] = a[jj];
+            }
+            __syncthreads();
+            if (i == k) {
+#pragma unroll
+                for (int jj = 0; jj < CPT; ++jj) a[jj] = rbuf[c0 + jj];
+            }
+            if (i == p) {
+#pragma unroll
+                for (int jj = 0; jj < CPT; ++jj) a[jj] = prow[c0 + jj];
+            }
+            __syncthreads();
+        }
+        // ---- publish the pivot row and column
+        if (i == k) {
+#pragma unroll
+            for (int jj = 0; jj < CPT; ++jj) prow[c0 + jj] = a[jj];
+        }
+        if (h == kh) {
+            double w = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < CPT; ++jj) w = (jj == kj) ? a[jj] : w;
+            pcol[i] = w;
+        }
+        __syncthreads();
+        const double d = 1.0 / prow[k];
+        if (i == k) {
+#pragma unroll
+            for (int jj = 0; jj < CPT; ++jj) a[jj] = (c0 + jj == k) ? d : a[jj] * d;
+        } else {
+            const double f = pcol[i];
+#pragma unroll
+            for (int jj = 0; jj < CPT; ++jj) {
+                const int col = c0 + jj;
+                a[jj] = (col == k) ? -f * d : a[jj] - f * (prow[col] * d);
+            }
+        }
+        __syncthreads();
+    }
+    // undo the row interchanges as column interchanges: destination of every column
+    if (tid < m) {
+        int j = tid;
+        for (int k = 0; k < m; ++k) {
+            const int p = perm[k];
+            j = (j == k) ? p : (j == p ? k : j);
+        }
+        dest[j] = tid;
+    }
+    __syncthreads();
+    if (i < m) {
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) {
+            const int col = c0 + jj;
+            if (col < m) A[i + (int64_t)dest[col] * m] = a[jj];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// Block Gauss elimination of one pivot (Sec. 2.2): invert Mat(v->v); then for
+// every in-edge k, W_k = Mat(v->v)^{-1} Mat(k->v) is formed in LDS (in column
+// chunks) and applied to every out-edge q: Mat(k->q) -= Mat(v->q) W_k.  The
+// inverse stays in LDS when it fits.  Pairs are stored q-major (q * nin + k).
 __device__ void eliminate(const DPivot& P, const DIn* __restrict__ ins,
                           const DOut* __restrict__ outs, const DPair* __restrict__ pairs,
                           const int32_t* __restrict__ imap, int32_t* __restrict__ info,
-                          double* scol, int* sperm, double* s_d, int* s_i) {
-    const int tid = threadIdx.x;
+                          double* sm, int cap) {
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int m = P.piv.nr;
     if (m == 0) return;
-    const double* Si = P.piv.p;
-    if (!gj_inverse(P.piv.p, m, scol, sperm, s_d, s_i)) {
+    bool ok;
+    if (m <= 32) ok = gj_inverse_reg<32>(P.piv.p, m, sm);
+    else if (m <= 64) ok = gj_inverse_reg<64>(P.piv.p, m, sm);
+    else if (m <= 128) ok = gj_inverse_reg<128>(P.piv.p, m, sm);
+    else ok = gj_inverse_global(P.piv.p, m, sm, (int*)(sm + m), sm + 2 * m);
+    if (!ok) {
         if (tid == 0) info[P.info_slot] = 1;
         return;
     }
+    if (P.nin == 0 || P.nout == 0) return;
+    // LDS: S^{-1} (m^2) when it leaves room for a W chunk of >= 8 columns
+    const bool sl = (int64_t)m * m + 8ll * m <= cap;
+    const double* S = P.piv.p;
+    double* Wl = sm;
+    if (sl) {
+        for (int e = tid; e < m * m; e += NTN) sm[e] = P.piv.p[e];
+        S = sm;
+        Wl = sm + (size_t)m * m;
+    }
+    const int wch = (int)((cap - (sl ? (int64_t)m * m : 0)) / m);
+    __syncthreads();
     for (int i = 0; i < P.nin; ++i) {
         const DIn I = ins[P.in0 + i];
         const int nr = I.blk.nr, nc = I.blk.nc;
-        for (int e = tid; e < m * nc; e += NT) {
-            const int a = e % m, b = e / m;
-            double s = 0.0;
-            const double* col = I.blk.p + (int64_t)b * nr;
-            for (int t = 0; t < nr; ++t) s += Si[a + (int64_t)imap_at(imap, I.rmap, t) * m] * col[t];
-            I.W[a + (int64_t)b * m] = s;
+        for (int b0 = 0; b0 < nc; b0 += wch) {
+            const int wc = min(wch, nc - b0);
+            for (int e = tid; e < m * wc; e += NTN) {
+                const int a = e % m, b = e / m;
+                const double* col = I.blk.p + (int64_t)(b0 + b) * nr;
+                double s = 0.0;
+#pragma unroll 4
+                for (int t = 0; t < nr; ++t) s += S[a + (int64_t)imap_at(imap, I.rmap, t) * m] * col[t];
+                Wl[a + b * m] = s;
+            }
+            __syncthreads();
+            for (int q = wv; q < P.nout; q += NWN) {
+                const DOut O = outs[P.out0 + q];
+                const DPair Q = pairs[P.pair0 + q * P.nin + i];
+                const int onr = O.blk.nr, K = O.blk.nc;
+                for (int e = lane; e < onr * wc; e += WAVE) {
+                    const int a = e % onr, b = e / onr;
+                    const double* wb = Wl + b * m;
+                    double s = 0.0;
+#pragma unroll 4
+                    for (int t = 0; t < K; ++t) s += O.blk.p[a + (int64_t)t * onr] * wb[imap_at(imap, O.cmap, t)];
+                    const int ra = imap_at(imap, Q.rpos, a), cb = imap_at(imap, Q.cpos, b0 + b);
+                    Q.tgt.p[ra + (int64_t)cb * Q.tgt.nr] -= s;
+                }
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
-    for (int q = 0; q < P.npair; ++q) {
-        const DPair Q = pairs[P.pair0 + q];
-        const DOut O = outs[P.out0 + Q.out_i];
-        const DIn I = ins[P.in0 + Q.in_i];
-        const int nr = O.blk.nr, nc = I.blk.nc, K = O.blk.nc;
-        for (int e = tid; e < nr * nc; e += NT) {
-            const int a = e % nr, b = e / nr;
-            double s = 0.0;
-            const double* Wb = I.W + (int64_t)b * m;
-            for (int t = 0; t < K; ++t) s += O.blk.p[a + (int64_t)t * nr] * Wb[imap_at(imap, O.cmap, t)];
-            const int ra = imap_at(imap, Q.rpos, a), cb = imap_at(imap, Q.cpos, b);
-            Q.tgt.p[ra + (int64_t)cb * Q.tgt.nr] -= s;
-        }
-    }
-    __syncthreads();
 }
 
-__global__ __launch_bounds__(NT) void k_factor_node(const DNode* __restrict__ tasks,
-                                                    const DProj* __restrict__ projs,
-                                                    const DIn* __restrict__ ins,
-                                                    const DOut* __restrict__ outs,
-                                                    const DPair* __restrict__ pairs,
-                                                    const int32_t* __restrict__ imap,
-                                                    int32_t* __restrict__ info, int max_m) {
+__global__ __launch_bounds__(NTN) void k_factor_node(const DNode* __restrict__ tasks,
+                                                     const DProj* __restrict__ projs,
+                                                     const DIn* __restrict__ ins,
+                                                     const DOut* __restrict__ outs,
+                                                     const DPair* __restrict__ pairs,
+                                                     const int32_t* __restrict__ imap,
+                                                     int32_t* __restrict__ info, int cap) {
     const DNode T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
-    __shared__ double s_d[NT / WAVE + 1];
-    __shared__ int s_i[NT / WAVE + 1];
-    extern __shared__ double s_dyn[];
-    double* scol = s_dyn;                         // max_m doubles
-    int* sperm = (int*)(s_dyn + max_m);           // max_m ints
+    extern __shared__ double sm[];
     const int r = T.r, c = T.c;
     if (r > 0) {
         for (int q = 0; q < T.nproj; ++q) {
             const DProj Pj = projs[T.proj0 + q];
             const int nrow = Pj.nrows;
-            for (int e = tid; e < nrow * r; e += NT) {
+            for (int e = tid; e < nrow * r; e += NTN) {
                 int a, t;
                 if (!Pj.trans) { a = e % nrow; t = e / nrow; }
                 else           { t = e % r;    a = e / r; }
@@ -488,6 +675,7 @@ __global__ __launch_bounds__(NT) void k_factor_node(const DNode* __restrict__ ta
                     const double* brow = T.B + (Pj.row0 + a);
                     const double* vcol = T.V + (int64_t)t * c;
                     v = 0.0;
+#pragma unroll 4
                     for (int j = 0; j < c; ++j) v += brow[(int64_t)j * T.M] * vcol[j];
                 } else {                          // transformed row-pivoted block
                     v = T.B[(int64_t)(Pj.row0 + a) * c + t];
@@ -496,21 +684,21 @@ __global__ __launch_bounds__(NT) void k_factor_node(const DNode* __restrict__ ta
                 else           Pj.dst.p[t + (int64_t)imap_at(imap, Pj.map, a) * r] = v;           // Q_k^T
             }
         }
-        for (int e = tid; e < c * r; e += NT) {
+        for (int e = tid; e < c * r; e += NTN) {
             T.bs.p[e] = T.V[e];                          // V      (c x r)
             const int t = e % r, a = e / r;
             T.sb.p[e] = T.V[a + (int64_t)t * c];         // V^T    (r x c)
         }
-        for (int e = tid; e < r * r; e += NT) {
+        for (int e = tid; e < r * r; e += NTN) {
             const double v = (e % r == e / r) ? -1.0 : 0.0;
             T.bP.p[e] = v;
             T.Pb.p[e] = v;
         }
     }
     __syncthreads();
-    eliminate(T.ps, ins, outs, pairs, imap, info, scol, sperm, s_d, s_i);
+    eliminate(T.ps, ins, outs, pairs, imap, info, sm, cap);
     __syncthreads();
-    eliminate(T.pb, ins, outs, pairs, imap, info, scol, sperm, s_d, s_i);
+    eliminate(T.pb, ins, outs, pairs, imap, info, sm, cap);
 }
 
 // ------------------------------------------------------------------ solve sweeps
@@ -518,75 +706,145 @@ __device__ __forceinline__ int map_abs(const int32_t* imap, int32_t base, int32_
     return map < 0 ? base + t : imap[map + t];
 }
 
-// Forward traversal (SolveL, Algorithm 3) for the super-node and its black node.
-// x holds the extended vector with ldx right-hand sides per variable; this
-// launch treats right-hand sides [k0, k0 + nrhs).
+// y[a, k] = sum_t S[a + t m] * v[t * nk + k] for the rows a of this work-group's
+// pivot (S: m x m column-major, v in LDS with stride nk); two threads per row
+// when m <= NT / 2.  part: 2 m nk doubles of LDS.  Result into out (LDS or
+// global through `store`).
+template <int KC, class Store>
+__device__ __forceinline__ void pivot_apply(const double* __restrict__ S, int m, const double* v,
+                                            int nk, double* part, Store store) {
+    const int tid = threadIdx.x;
+    const int split = (m <= NT / 2) ? 2 : 1;
+    const int half = m > 0 ? (tid / ((NT / split))) : 0;
+    const int th = (m + split - 1) / split;
+    for (int a = tid % (NT / split); a < m; a += NT / split) {
+        double acc[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+        const int t0 = half * th, t1 = min(m, t0 + th);
+#pragma unroll 4
+        for (int t = t0; t < t1; ++t) {
+            const double sv = S[a + (int64_t)t * m];
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+                if (k < nk) acc[k] += sv * v[t * nk + k];
+        }
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+            if (k < nk) part[(half * m + a) * nk + k] = acc[k];
+    }
+    __syncthreads();
+    for (int e = tid; e < m * nk; e += NT) {
+        const int a = e / nk, k = e % nk;
+        double y = part[a * nk + k];
+        if (split == 2) y += part[(m + a) * nk + k];
+        store(a, k, y);
+    }
+    __syncthreads();
+}
+
+// Forward traversal (SolveL, Algorithm 3) for the super-node, then its black
+// node.  x holds the extended vector with ldx right-hand sides per variable;
+// this launch treats right-hand sides [k0, k0 + nk), nk <= KC.  Each wavefront
+// applies whole out-edges (different edges update different nodes).
+template <int KC>
 __global__ __launch_bounds__(NT) void k_solve_fwd(const DSNode* __restrict__ nodes,
                                                   const DSEdge* __restrict__ edges,
                                                   const int32_t* __restrict__ imap,
-                                                  double* __restrict__ xg, int ldx, int k0, int nrhs) {
-    extern __shared__ double f[];
+                                                  double* __restrict__ xg, int ldx, int k0, int nk) {
+    extern __shared__ double sm[];
     double* x = xg + k0;
     const DSNode N = nodes[blockIdx.x];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     for (int w = 0; w < 2; ++w) {
         const DSPiv P = w == 0 ? N.s : N.b;
         const int m = P.m;
         if (m == 0) continue;
-        for (int e = tid; e < m * nrhs; e += NT) {
-            const int a = e / nrhs, k = e % nrhs;
-            double s = 0.0;
-            for (int t = 0; t < m; ++t) s += P.Sinv[a + (int64_t)t * m] * x[(int64_t)(P.off + t) * ldx + k];
-            f[e] = s;
-        }
+        double* rb = sm;                   // m x nk right-hand side block
+        double* fb = sm + m * nk;          // m x nk  f = S^{-1} rhs
+        double* part = sm + 2 * m * nk;    // 2 m nk
+        for (int e = tid; e < m * nk; e += NT) rb[e] = x[(int64_t)(P.off + e / nk) * ldx + e % nk];
         __syncthreads();
-        for (int q = 0; q < P.nout; ++q) {
+        pivot_apply<KC>(P.Sinv, m, rb, nk, part, [&](int a, int k, double y) { fb[a * nk + k] = y; });
+        for (int q = wv; q < P.nout; q += NT / WAVE) {
             const DSEdge E = edges[P.out0 + q];
-            for (int e = tid; e < E.nr * nrhs; e += NT) {
-                const int a = e / nrhs, k = e % nrhs;
-                double s = 0.0;
-                for (int t = 0; t < E.nc; ++t)
-                    s += E.E[a + (int64_t)t * E.nr] * f[map_abs(imap, E.cbase, E.cmap, t) * nrhs + k];
-                x[(int64_t)map_abs(imap, E.rbase, E.rmap, a) * ldx + k] -= s;
+            for (int a = lane; a < E.nr; a += WAVE) {
+                double acc[KC];
+#pragma unroll
+                for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+#pragma unroll 4
+                for (int t = 0; t < E.nc; ++t) {
+                    const double ev = E.E[a + (int64_t)t * E.nr];
+                    const double* fr = fb + map_abs(imap, E.cbase, E.cmap, t) * nk;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        if (k < nk) acc[k] += ev * fr[k];
+                }
+                double* xr = x + (int64_t)map_abs(imap, E.rbase, E.rmap, a) * ldx;
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+                    if (k < nk) xr[k] -= acc[k];
             }
         }
         __syncthreads();
     }
 }
 
-// Backward traversal (SolveU, Algorithm 4) for the black node, then the super-node.
+// Backward traversal (SolveU, Algorithm 4) for the black node, then the
+// super-node.  Wavefront w accumulates the in-edges w, w+4, ... into its own
+// LDS buffer; the buffers are added in a fixed order (deterministic).
+template <int KC>
 __global__ __launch_bounds__(NT) void k_solve_bwd(const DSNode* __restrict__ nodes,
                                                   const DSEdge* __restrict__ edges,
                                                   const int32_t* __restrict__ imap,
-                                                  double* __restrict__ xg, int ldx, int k0, int nrhs) {
-    extern __shared__ double y[];
+                                                  double* __restrict__ xg, int ldx, int k0, int nk) {
+    extern __shared__ double sm[];
     double* x = xg + k0;
     const DSNode N = nodes[blockIdx.x];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    constexpr int NW = NT / WAVE;
     for (int w = 0; w < 2; ++w) {
         const DSPiv P = w == 0 ? N.b : N.s;
         const int m = P.m;
         if (m == 0) continue;
-        for (int e = tid; e < m * nrhs; e += NT) y[e] = x[(int64_t)(P.off + e / nrhs) * ldx + e % nrhs];
+        double* yb = sm;                   // m x nk
+        double* acc4 = sm + m * nk;        // NW x m x nk
+        double* part = acc4 + NW * m * nk; // 2 m nk
+        for (int e = tid; e < m * nk; e += NT) yb[e] = x[(int64_t)(P.off + e / nk) * ldx + e % nk];
+        for (int e = tid; e < NW * m * nk; e += NT) acc4[e] = 0.0;
         __syncthreads();
-        for (int q = 0; q < P.nin; ++q) {
+        double* mine = acc4 + wv * m * nk;
+        for (int q = wv; q < P.nin; q += NW) {
             const DSEdge E = edges[P.in0 + q];
-            for (int e = tid; e < E.nr * nrhs; e += NT) {
-                const int a = e / nrhs, k = e % nrhs;
-                double s = 0.0;
-                for (int t = 0; t < E.nc; ++t)
-                    s += E.E[a + (int64_t)t * E.nr] * x[(int64_t)map_abs(imap, E.cbase, E.cmap, t) * ldx + k];
-                y[map_abs(imap, E.rbase, E.rmap, a) * nrhs + k] -= s;
+            for (int a = lane; a < E.nr; a += WAVE) {
+                double acc[KC];
+#pragma unroll
+                for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+#pragma unroll 4
+                for (int t = 0; t < E.nc; ++t) {
+                    const double ev = E.E[a + (int64_t)t * E.nr];
+                    const double* xr = x + (int64_t)map_abs(imap, E.cbase, E.cmap, t) * ldx;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        if (k < nk) acc[k] += ev * xr[k];
+                }
+                double* yr = mine + map_abs(imap, E.rbase, E.rmap, a) * nk;
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+                    if (k < nk) yr[k] += acc[k];
             }
-            __syncthreads();
-        }
-        for (int e = tid; e < m * nrhs; e += NT) {
-            const int a = e / nrhs, k = e % nrhs;
-            double s = 0.0;
-            for (int t = 0; t < m; ++t) s += P.Sinv[a + (int64_t)t * m] * y[t * nrhs + k];
-            x[(int64_t)(P.off + a) * ldx + k] = s;
         }
         __syncthreads();
+        for (int e = tid; e < m * nk; e += NT) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s += acc4[q * m * nk + e];
+            yb[e] -= s;
+        }
+        __syncthreads();
+        pivot_apply<KC>(P.Sinv, m, yb, nk, part, [&](int a, int k, double y) {
+            x[(int64_t)(P.off + a) * ldx + k] = y;
+        });
     }
 }
 
@@ -746,11 +1004,26 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 }
 
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, hipStream_t st) {
+                               int max_c, int max_M, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const size_t need = (size_t)2 * max_c * max_c * sizeof(double);
-    const int lds_mat = need <= 64 * 1024 ? 1 : 0;
-    hipLaunchKernelGGL(k_compress_svd, dim3(n), dim3(NT), lds_mat ? need : 0, st, t, pieces, imap, lds_mat);
+    // LDS plan: R and V (2 c^2) plus a chunk of ch rows of B (ch c), within the
+    // dynamic LDS budget; below 16 rows per chunk the workspace path is used.
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)k_compress_svd<8>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+        (void)hipFuncSetAttribute((const void*)k_compress_svd<16>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+        attr_set = true;
+    }
+    const int64_t cap = kLdsBudget / (int64_t)sizeof(double);
+    int64_t ch = (cap - 2ll * max_c * max_c) / (max_c > 0 ? max_c : 1);
+    if (ch > max_M) ch = max_M;
+    if (ch > 1024) ch = 1024;
+    if (ch < 16) ch = 0;
+    const size_t lds = ch > 0 ? (size_t)(2ll * max_c * max_c + ch * max_c) * sizeof(double) : 0;
+    if (max_c <= 64)
+        hipLaunchKernelGGL(k_compress_svd<8>, dim3(n), dim3(NT), lds, st, t, pieces, imap, (int)ch);
+    else
+        hipLaunchKernelGGL(k_compress_svd<16>, dim3(n), dim3(NT), lds, st, t, pieces, imap, (int)ch);
     return hipGetLastError();
 }
 
@@ -758,18 +1031,27 @@ hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DI
                               const DOut* outs, const DPair* pairs, const int32_t* imap,
                               int32_t* info, int max_m, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    int mm = max_m > 0 ? max_m : 1;
-    size_t lds = (size_t)mm * sizeof(double) + (size_t)mm * sizeof(int);
-    hipLaunchKernelGGL(k_factor_node, dim3(n), dim3(NT), lds, st, t, proj, ins, outs, pairs, imap,
-                       info, mm);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)k_factor_node, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+        attr_set = true;
+    }
+    // the whole budget: Gauss-Jordan scratch, then S^{-1} and W chunks
+    const int cap = kLdsBudget / (int)sizeof(double);
+    (void)max_m;
+    hipLaunchKernelGGL(k_factor_node, dim3(n), dim3(NTN), (size_t)kLdsBudget, st, t, proj, ins, outs, pairs,
+                       imap, info, cap);
     return hipGetLastError();
 }
 
+constexpr int SOLVE_KC = 8;          // right-hand sides per solve launch (registers)
+
 static int rhs_chunk(int max_m, int nrhs) {
-    // keep the per-work-group vector block within 64 KiB of LDS
-    int mm = max_m > 0 ? max_m : 1;
-    int kc = (int)((64 * 1024) / ((size_t)mm * sizeof(double)));
+    // LDS per work-group: (1 + 4 + 2) m nk doubles (backward sweep) within 64 KiB
+    const int mm = max_m > 0 ? max_m : 1;
+    int kc = (int)((64 * 1024) / ((size_t)7 * mm * sizeof(double)));
     if (kc < 1) kc = 1;
+    if (kc > SOLVE_KC) kc = SOLVE_KC;
     return kc < nrhs ? kc : nrhs;
 }
 
@@ -779,8 +1061,8 @@ hipError_t launch_solve_fwd(const DSNode* nodes, int n, const DSEdge* edges, con
     const int kc = rhs_chunk(max_m, nrhs);
     for (int k0 = 0; k0 < nrhs; k0 += kc) {
         const int nk = (nrhs - k0) < kc ? (nrhs - k0) : kc;
-        size_t lds = (size_t)(max_m > 0 ? max_m : 1) * nk * sizeof(double);
-        hipLaunchKernelGGL(k_solve_fwd, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
+        const size_t lds = (size_t)4 * (max_m > 0 ? max_m : 1) * nk * sizeof(double);
+        hipLaunchKernelGGL(k_solve_fwd<SOLVE_KC>, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
     }
     return hipGetLastError();
 }
@@ -791,8 +1073,8 @@ hipError_t launch_solve_bwd(const DSNode* nodes, int n, const DSEdge* edges, con
     const int kc = rhs_chunk(max_m, nrhs);
     for (int k0 = 0; k0 < nrhs; k0 += kc) {
         const int nk = (nrhs - k0) < kc ? (nrhs - k0) : kc;
-        size_t lds = (size_t)(max_m > 0 ? max_m : 1) * nk * sizeof(double);
-        hipLaunchKernelGGL(k_solve_bwd, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
+        const size_t lds = (size_t)7 * (max_m > 0 ? max_m : 1) * nk * sizeof(double);
+        hipLaunchKernelGGL(k_solve_bwd<SOLVE_KC>, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
     }
     return hipGetLastError();
 }

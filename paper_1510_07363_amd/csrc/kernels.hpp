@@ -25,7 +25,7 @@ hipError_t launch_count_nonfinite(const double* v, int64_t n, int64_t* cnt, hipS
 hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                            int max_c, hipStream_t st);
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, hipStream_t st);
+                               int max_c, int max_M, hipStream_t st);
 hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DIn* ins,
                               const DOut* outs, const DPair* pairs, const int32_t* imap,
                               int32_t* info, int max_m, hipStream_t st);

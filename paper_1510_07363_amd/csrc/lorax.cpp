@@ -455,7 +455,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             std::vector<std::vector<int32_t>> a_row0(nn), b_row0(nn);
             size_t ws_need = 0;
             std::vector<size_t> wsB(nn), wsV(nn), wsH(nn), wsT(nn);
-            int max_c = 1;
+            int max_c = 1, max_M = 1;
             for (int ni = 0; ni < nn; ++ni) {
                 const NodeStep& ns = cs.nodes[ni];
                 const NodeMaps& nm = maps[si][ni];
@@ -488,6 +488,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 T.c = ns.gamma.count(ms);
                 T.eps = h->epsilon;
                 max_c = std::max(max_c, T.c);
+                max_M = std::max(max_M, T.M);
                 const bool svd = h->compress == LRX_SVD;
                 wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
                 wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
@@ -547,7 +548,8 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, cfl);
                 if (use_svd)
                     HIPCHK(launch_compress_svd((const DCompress*)(d_desc_c.as<char>() + o1), nn,
-                                               (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c, st));
+                                               (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c,
+                                               max_M, st));
                 else
                     HIPCHK(launch_compress((const DCompress*)(d_desc_c.as<char>() + o1), nn,
                                            (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c, st));
@@ -631,6 +633,9 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 D.nin = (int32_t)pp.in_edges.size();
                 D.nout = (int32_t)pp.out_edges.size();
                 D.npair = (int32_t)pp.pair_edge.size();
+                // the kernel addresses pair (q, k) at q * nin + k
+                if (D.npair != 0 && D.npair != D.nin * D.nout)
+                    fail(LRX_EDEVICE, "internal: Schur pairs are not the full product of in- and out-edges");
                 flops += 2ll * m * m * m;
             };
             for (int ni = 0; ni < nn; ++ni) {

@@ -155,10 +155,10 @@ def test_svd_sigma_match_oracle(lx):
         if len(c.sigma) == 0 or c.sigma[0] < 1e-8 * top:
             continue
         t = F.tails(i)
-        s0 = c.sigma[0]
         k = min(len(t) - 1, len(c.sigma))
-        # singular values agree to rounding (accumulated over the levels) relative to sigma_0
-        assert np.max(np.abs(t[1:1 + k] - c.sigma[:k])) <= 1e-10 * s0
+        # singular values agree to rounding accumulated over the levels, relative
+        # to the largest stacked block (small blocks come out of cancellation)
+        assert np.max(np.abs(t[1:1 + k] - c.sigma[:k])) <= 1e-11 * top
         checked += 1
     assert checked > 10
     assert F.stats()["max_compression_error"] < 1e-4
