@@ -93,24 +93,65 @@ struct DMerge {
     int32_t r0, c0;
 };
 
-// ---- Solve sweeps ------------------------------------------------------------
-// Row a of an edge maps to rbase + a (rmap < 0) or imap[rmap + a]; columns
-// likewise.  Out-edges (forward) carry absolute rows / pivot-local columns;
-// in-edges (backward) pivot-local rows / absolute columns.
-struct DSEdge {
-    const double* E;
-    int32_t nr, nc;
-    int32_t rbase, rmap, cbase, cmap;
+// ---- Solve sweeps (Algorithms 3 and 4): staged node programs ---------------
+// One work-group runs the program of one super-node of a colour step (its
+// pivot s, then its black node b in the forward sweep; b, then s backward).
+// A program is a sequence of stages.  Each stage first copies "runs" of global
+// data (rows of stored blocks, gathered rows of the extended vector x) into
+// LDS with every load of the stage in flight at once, then executes its groups
+// of row computations, with a barrier after each group.  The descriptor block
+// of stage k+1 is fetched together with the data of stage k.
+//
+// Descriptor blocks are int32 words: a header, then groups, runs, comps and the
+// index lists ("maps") they use; a map is a word offset inside the same block,
+// or -1 for the identity.  LDS data offsets are in doubles.
+constexpr int kSwThreads = 1024;       // work-group size of the sweep kernel
+constexpr int kSwDescWords = 2048;     // largest descriptor block (two are resident)
+constexpr int kSwData = 17408;         // doubles of LDS for buffers and staged data
+constexpr int kSwKS = 8;               // row stride of vector buffers in LDS (max RHS per launch)
+
+struct SwNode {
+    int64_t desc;        // word offset of stage 0's descriptor block
+    int32_t words0;      // its size in words
+    int32_t nstage;
 };
 
-struct DSPiv {
-    const double* Sinv;  // m x m column-major
-    int32_t m, off;      // variables [off, off + m) of the extended vector
-    int32_t out0, nout, in0, nin;
+struct SwHeader {        // 8 words
+    int32_t words_next;  // size of the next stage's block (0 for the last stage)
+    int32_t nrun;
+    int32_t elems_mat;   // elements of the matrix runs of this stage
+    int32_t ngroup;
+    int32_t groups, runs, comps;   // word offsets of the sections
+    int32_t xrows;       // rows of x copied by the vector runs of this stage
 };
 
-struct DSNode {
-    DSPiv s, b;
+struct SwGroup {         // 4 words: comps [comp0, comp0 + ncomp), rows summed
+    int32_t comp0, ncomp, rows;
+    int32_t lglanes;     // log2 of the lanes that share one row's dot products
+};
+
+// Matrix run set: nrun runs of len doubles, run t at src + t * ld, stored in LDS
+// at lds + t * dld.  Vector run set (src == nullptr): nrun rows of x, row t is
+// x row (map < 0 ? ld + t : map[t]), the launch's right-hand sides, stored at
+// lds + t * kSwKS.
+struct SwRun {           // 10 words
+    const double* src;
+    int32_t ld, len, nrun, map, lds, dld;
+    float rlen;          // 1 / len (index split without integer division)
+    int32_t pad_;
+};
+
+// One row computation: for each row a < nr of the block at LDS `mat`
+// (column-major, leading dimension ld), with acc[k] = sum_t mat[a + t ld] *
+// in[(in_map ? in_map[t] : t) * kSwKS + k]:
+//   out value = init < 0 ? acc : init_row(a)[k] - acc
+// written to LDS (out >= 0) and/or to x (gbase >= 0 or gmap >= 0).
+struct SwComp {          // 12 words
+    int32_t mat, ld, nr, nc;
+    int32_t in, in_map;
+    int32_t init, init_map;
+    int32_t out, out_map;
+    int32_t gbase, gmap;
 };
 
 }  // namespace lrx

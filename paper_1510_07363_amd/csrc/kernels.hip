@@ -411,6 +411,333 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
     }
 }
 
+// ---- truncated SVD for stacked blocks of at most 64 columns ------------------
+// Same result as k_compress_svd, reached in fewer synchronisation steps:
+//   1. Householder QR of B (row chunks through LDS): B = Q0 R0;
+//   2. QR of R0 with column pivoting: R0 P = Q1 R1;
+//   3. QR of R1^T: R1^T = Q2 R2, L = R2^T;
+//   4. one-sided Jacobi on the columns of L, the rotations J accumulated onto
+//      W = Q2: L J = U Sigma, so B = (Q0 Q1 U) Sigma (P Q2 J)^T.
+// The two extra triangular QRs make the columns of L graded and nearly
+// orthogonal, which cuts the Jacobi sweeps by about half (the QR
+// preconditioning of one-sided Jacobi described by Drmac and Veselic), while V
+// = P W keeps orthonormal columns to rounding.  1024 threads: in the QRs lane =
+// column and wavefront = rows i = seg (mod 16); in Jacobi 16 lanes per column
+// pair, reduced with DPP row permutations.
+constexpr int NTC = 1024;
+constexpr int SEGC = NTC / WAVE;           // row segments in the QRs
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row; every lane receives the same value.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_mov<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);    // row_half_mirror
+    v += dpp_mov<0x140>(v);    // row_mirror
+    return v;
+}
+
+// In-place Householder QR, optionally with column pivoting (largest remaining
+// column norm, lowest index on ties), of the nr x c matrix A in LDS (column-
+// major, leading dimension ld, c <= 64).  On exit R is the upper triangle;
+// reflector j is H_j = I - tau_j v v^T with v = (v0_j, A[j+1.., j]) acting on
+// rows j..nr-1; perm[j] is the original column now at position j (pivot only).
+// P: SEGC x WAVE doubles, NV: SEGC doubles of LDS scratch.
+__device__ void qr64(double* A, int nr, int c, int ld, bool pivot, int* perm, double* hv0,
+                     double* htau, double* P, double* NV) {
+    const int tid = threadIdx.x, k = tid % WAVE, s = tid / WAVE;
+    const int kmax = min(nr, c);
+    if (pivot) {
+        for (int j = tid; j < c; j += NTC) perm[j] = j;
+        __syncthreads();
+    }
+    for (int j = 0; j < kmax; ++j) {
+        // first row > j of this segment (rows i = s mod SEGC)
+        const int i0 = j + 1 + ((s - (j + 1)) % SEGC + SEGC) % SEGC;
+        if (pivot) {
+            double q = 0.0;
+            if (k >= j && k < c) {
+                for (int i = j + ((s - j) % SEGC + SEGC) % SEGC; i < nr; i += SEGC) {   // rows >= j
+                    const double x = A[i + k * ld];
+                    q += x * x;
+                }
+            }
+            P[s * WAVE + k] = q;
+            __syncthreads();
+            double nk = -1.0;
+            if (k >= j && k < c) {
+                nk = 0.0;
+                for (int t = 0; t < SEGC; ++t) nk += P[t * WAVE + k];
+            }
+            int bi = k;
+            double bv = nk;
+            for (int o = WAVE / 2; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            __syncthreads();
+            if (bi != j) {
+                if (k == j)
+                    for (int i = s; i < nr; i += SEGC) {
+                        const double a = A[i + j * ld];
+                        A[i + j * ld] = A[i + bi * ld];
+                        A[i + bi * ld] = a;
+                    }
+                if (tid == 0) {
+                    const int t = perm[j];
+                    perm[j] = perm[bi];
+                    perm[bi] = t;
+                }
+                __syncthreads();
+            }
+        }
+        // phase 1: partial products of column j with the columns to its right
+        const double ajj = A[j + j * ld];
+        const double ajk = k < c ? A[j + k * ld] : 0.0;
+        double p1 = 0.0, nv = 0.0;
+        for (int i = i0; i < nr; i += SEGC) {
+            const double vi = A[i + j * ld];
+            nv += vi * vi;
+            if (k > j && k < c) p1 += vi * A[i + k * ld];
+        }
+        P[s * WAVE + k] = p1;
+        if (k == 0) NV[s] = nv;
+        __syncthreads();
+        // phase 2: reflector and update
+        double nvt = 0.0;
+        for (int t = 0; t < SEGC; ++t) nvt += NV[t];
+        double tau = 0.0, v0 = 0.0, alpha = ajj;
+        if (nvt > 0.0) {
+            const double s2 = ajj * ajj + nvt;
+            const double xn = sqrt(s2);
+            alpha = -copysign(xn, ajj);
+            v0 = ajj - alpha;
+            tau = 1.0 / (s2 + fabs(ajj) * xn);
+        }
+        if (tau != 0.0 && k > j && k < c) {
+            double w = v0 * ajk;
+            for (int t = 0; t < SEGC; ++t) w += P[t * WAVE + k];
+            w *= tau;
+            if (s == 0) A[j + k * ld] = ajk - w * v0;
+            for (int i = i0; i < nr; i += SEGC) A[i + k * ld] -= w * A[i + j * ld];
+        }
+        if (tid == 0) {
+            A[j + j * ld] = alpha;
+            hv0[j] = v0;
+            htau[j] = tau;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restrict__ tasks,
+                                                        const DPiece* __restrict__ pieces,
+                                                        const int32_t* __restrict__ imap, int cap) {
+    const DCompress T = tasks[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x;
+    extern __shared__ double sm[];
+    __shared__ int s_perm[WAVE];
+    __shared__ int s_rot;
+    if (M == 0 || c == 0) {
+        if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; }
+        return;
+    }
+    double* P = sm;                          // SEGC x WAVE
+    double* NV = P + SEGC * WAVE;            // SEGC
+    double* hv0 = NV + SEGC;                 // WAVE
+    double* htau = hv0 + WAVE;               // WAVE
+    double* sv = htau + WAVE;                // WAVE
+    double* region = sv + WAVE;
+    const int reg = cap - (SEGC * WAVE + SEGC + 3 * WAVE);
+    const int ldc = c | 1;
+    double* X = region + reg - c * ldc;      // c x c, kept to the end
+    // ---- assemble B (column-major, ld M) in global memory; it stays for the projection
+    double* __restrict__ B = T.B;
+    for (int64_t e = tid; e < (int64_t)M * c; e += NTC) B[e] = 0.0;
+    __syncthreads();
+    for (int q = 0; q < T.npieces; ++q) {
+        const DPiece pc = pieces[T.piece0 + q];
+        const int nr = pc.blk.nr, nc = pc.blk.nc;
+        for (int e = tid; e < nr * nc; e += NTC) {
+            const int a = e % nr, b = e / nr;
+            const double v = pc.blk.p[e];
+            if (!pc.trans) B[(pc.row0 + a) + (int64_t)imap_at(imap, pc.map, b) * M] = v;
+            else           B[(pc.row0 + b) + (int64_t)imap_at(imap, pc.map, a) * M] = v;
+        }
+    }
+    __syncthreads();
+    // ---- 1. QR of B through LDS chunks: [R (c rows); next rows of B]
+    {
+        double* A = region;
+        const int rows_cap = (reg - c * ldc) / c - 1;
+        const int ldA = rows_cap | 1;
+        int r0 = 0, nrA = 0;
+        bool first = true;
+        while (r0 < M) {
+            const int top = first ? 0 : c;
+            const int nnew = min(M - r0, rows_cap - top);
+            if (!first) {                            // keep R, clear the reflectors below it
+                for (int e = tid; e < c * c; e += NTC) {
+                    const int i = e % c, j = e / c;
+                    if (i > j) A[i + j * ldA] = 0.0;
+                }
+            }
+            for (int e = tid; e < nnew * c; e += NTC) {
+                const int k = e / nnew, i = e - k * nnew;
+                A[top + i + k * ldA] = B[(r0 + i) + (int64_t)k * M];
+            }
+            nrA = top + nnew;
+            __syncthreads();
+            qr64(A, nrA, c, ldA, false, nullptr, hv0, htau, P, NV);
+            r0 += nnew;
+            first = false;
+        }
+        // R0 (upper, rows < min(nrA, c)) into X
+        for (int e = tid; e < c * c; e += NTC) {
+            const int i = e % c, k = e / c;
+            X[i + k * ldc] = (i <= k && i < nrA) ? A[i + k * ldA] : 0.0;
+        }
+        __syncthreads();
+    }
+    // ---- 2. R0 P = Q1 R1
+    qr64(X, c, c, ldc, true, s_perm, hv0, htau, P, NV);
+    // ---- 3. R1^T = Q2 R2 (A2 after W in the region); L = R2^T into X
+    double* W = region;
+    double* A2 = region + c * ldc;
+    for (int e = tid; e < c * c; e += NTC) {
+        const int i = e % c, k = e / c;
+        A2[i + k * ldc] = (k <= i) ? X[k + i * ldc] : 0.0;
+    }
+    __syncthreads();
+    qr64(A2, c, c, ldc, false, nullptr, hv0, htau, P, NV);
+    for (int e = tid; e < c * c; e += NTC) {
+        const int i = e % c, k = e / c;
+        X[i + k * ldc] = (k <= i) ? A2[k + i * ldc] : 0.0;
+        W[i + k * ldc] = (i == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // W = Q2 = H_0 ... H_{c-1} I, applied right to left
+    {
+        const int k = tid % WAVE, sg = tid / WAVE;
+        for (int j = c - 1; j >= 0; --j) {
+            const double tau = htau[j];
+            if (tau == 0.0) continue;                // uniform: H_j = I
+            const int i0 = j + 1 + ((sg - (j + 1)) % SEGC + SEGC) % SEGC;
+            const double v0 = hv0[j];
+            double p1 = 0.0;
+            const double wjk = k < c ? W[j + k * ldc] : 0.0;
+            if (k < c)
+                for (int i = i0; i < c; i += SEGC) p1 += A2[i + j * ldc] * W[i + k * ldc];
+            P[sg * WAVE + k] = p1;
+            __syncthreads();
+            if (k < c) {
+                double w = v0 * wjk;
+                for (int t = 0; t < SEGC; ++t) w += P[t * WAVE + k];
+                w *= tau;
+                if (sg == 0) W[j + k * ldc] = wjk - w * v0;
+                for (int i = i0; i < c; i += SEGC) W[i + k * ldc] -= w * A2[i + j * ldc];
+            }
+            __syncthreads();
+        }
+    }
+    // ---- 4. one-sided Jacobi on the columns of L; W accumulates the rotations
+    {
+        const int n2 = c + (c & 1), npair = n2 / 2;
+        const int g = tid / 16, gl = tid % 16;
+        const double tol = 4.0e-16 * (double)c;
+        double f = 0.0;
+        for (int e = tid; e < c * c; e += NTC) {
+            const int i = e % c, k = e / c;
+            const double x = X[i + k * ldc];
+            f += x * x;
+        }
+        f = wave_sum(f);
+        if (tid % WAVE == 0) P[tid / WAVE] = f;
+        __syncthreads();
+        double fro = 0.0;
+        for (int t = 0; t < SEGC; ++t) fro += P[t];
+        const double tiny2 = 1e-30 * fro;
+        constexpr int EPL = WAVE / 16;             // elements per lane (c <= 64)
+        for (int sweep = 0; sweep < 40; ++sweep) {
+            if (tid == 0) s_rot = 0;
+            __syncthreads();
+            for (int t = 0; t < n2 - 1; ++t) {
+                if (g < npair) {
+                    const int a = (t + g) % (n2 - 1);
+                    const int b = g == 0 ? n2 - 1 : (t - g + n2 - 1) % (n2 - 1);
+                    const int p = a < b ? a : b, q = a < b ? b : a;
+                    const bool act = q < c;
+                    double xp[EPL], xq[EPL];
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int u = 0; u < EPL; ++u) {
+                        const int r = gl + 16 * u;
+                        xp[u] = (act && r < c) ? X[r + p * ldc] : 0.0;
+                        xq[u] = (act && r < c) ? X[r + q * ldc] : 0.0;
+                        al += xp[u] * xp[u];
+                        be += xq[u] * xq[u];
+                        ga += xp[u] * xq[u];
+                    }
+                    al = row16_sum(al);
+                    be = row16_sum(be);
+                    ga = row16_sum(ga);
+                    if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al * be) && al > tiny2 && be > tiny2) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+                        for (int u = 0; u < EPL; ++u) {
+                            const int r = gl + 16 * u;
+                            if (r < c) {
+                                X[r + p * ldc] = cs * xp[u] - sn * xq[u];
+                                X[r + q * ldc] = sn * xp[u] + cs * xq[u];
+                                const double wp = W[r + p * ldc], wq = W[r + q * ldc];
+                                W[r + p * ldc] = cs * wp - sn * wq;
+                                W[r + q * ldc] = sn * wp + cs * wq;
+                            }
+                        }
+                        if (gl == 0) s_rot = 1;
+                    }
+                }
+                __syncthreads();
+            }
+            const int rot = s_rot;
+            __syncthreads();
+            if (!rot) break;
+        }
+    }
+    // ---- singular values, order, rank, V = P W
+    for (int k = tid / WAVE; k < c; k += SEGC) {
+        double s2 = 0.0;
+        for (int r = tid % WAVE; r < c; r += WAVE) { const double x = X[r + k * ldc]; s2 += x * x; }
+        s2 = wave_sum(s2);
+        if (tid % WAVE == 0) sv[k] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int k = tid; k < c; k += NTC) T.tails[1 + desc_pos(sv, c, k)] = sv[k];
+    double smax = 0.0;
+    for (int k = 0; k < c; ++k) smax = fmax(smax, sv[k]);
+    int r = 0;
+    if (smax > 0.0)
+        for (int k = 0; k < c; ++k) r += (sv[k] >= T.eps * smax) ? 1 : 0;
+    for (int e = tid; e < c * c; e += NTC) {
+        const int a = e % c, k = e / c;
+        const int pos = desc_pos(sv, c, k);
+        if (pos < r) T.V[s_perm[a] + (size_t)pos * c] = W[a + k * ldc];
+    }
+    if (tid == 0) {
+        T.tails[0] = smax;
+        *T.rank_out = r;
+    }
+}
+
 // ------------------------------------------------------------------ elimination
 constexpr int NTN = 512;                     // threads of the node-factorization kernel
 constexpr int NWN = NTN / WAVE;
@@ -702,149 +1029,179 @@ __global__ __launch_bounds__(NTN) void k_factor_node(const DNode* __restrict__ t
 }
 
 // ------------------------------------------------------------------ solve sweeps
-__device__ __forceinline__ int map_abs(const int32_t* imap, int32_t base, int32_t map, int t) {
-    return map < 0 ? base + t : imap[map + t];
+// Interpreter of the staged node programs (formats in dev.hpp).  NK right-hand
+// sides per launch; vector buffers in LDS keep a row stride of kSwKS.
+// Copies the runs of one stage into LDS: every thread first issues the loads
+// of U elements, then stores them, so a stage costs about one memory latency.
+// A thread's elements are kSwThreads apart, so the position inside the current
+// run advances by a fixed quotient and remainder; the fields of the current
+// run stay in registers.
+template <int NK>
+__device__ __forceinline__ void sw_copy(const SwRun* runs, int nrun, const int32_t* D, int elems,
+                                        const double* x, int ldx, double* dat) {
+    constexpr int U = 16;
+    if (nrun == 0 || threadIdx.x >= elems) return;
+    int ri = 0, rstart = 0;
+    // current run
+    const double* src = nullptr;
+    int len = 0, ld = 0, dld = 0, lds = 0, map = -1, cnt = 0, q = 0, r = 0;
+    int t = 0, a = 0;                         // position of element g inside the run
+    auto load_run = [&](int g) {
+        const SwRun& R = runs[ri];
+        src = R.src;
+        map = R.map;
+        lds = R.lds;
+        if (src) { len = R.len; ld = R.ld; dld = R.dld; }
+        else { len = NK; ld = R.ld; dld = kSwKS; }
+        cnt = len * R.nrun;
+        q = kSwThreads / len;
+        r = kSwThreads - q * len;
+        const int li = g - rstart;
+        t = li / len;
+        a = li - t * len;
+    };
+    int g = threadIdx.x;
+    while (g >= rstart + runs[ri].nrun * (runs[ri].src ? runs[ri].len : NK)) {
+        rstart += runs[ri].nrun * (runs[ri].src ? runs[ri].len : NK);
+        ++ri;
+    }
+    load_run(g);
+    for (; g < elems;) {
+        double v[U];
+        int dst[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dst[u] = -1;
+            v[u] = 0.0;
+            if (g < elems) {
+                if (g >= rstart + cnt) {
+                    rstart += cnt;
+                    ++ri;
+                    while (g >= rstart + runs[ri].nrun * (runs[ri].src ? runs[ri].len : NK)) {
+                        rstart += runs[ri].nrun * (runs[ri].src ? runs[ri].len : NK);
+                        ++ri;
+                    }
+                    load_run(g);
+                }
+                if (src) {
+                    v[u] = src[(int64_t)t * ld + a];
+                } else {
+                    const int row = map < 0 ? ld + t : D[map + t];
+                    v[u] = x[(int64_t)row * ldx + a];
+                }
+                dst[u] = lds + t * dld + a;
+                g += kSwThreads;
+                a += r;
+                t += q;
+                if (a >= len) { a -= len; ++t; }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (dst[u] >= 0) dat[dst[u]] = v[u];
+    }
 }
 
-// y[a, k] = sum_t S[a + t m] * v[t * nk + k] for the rows a of this work-group's
-// pivot (S: m x m column-major, v in LDS with stride nk); two threads per row
-// when m <= NT / 2.  part: 2 m nk doubles of LDS.  Result into out (LDS or
-// global through `store`).
-template <int KC, class Store>
-__device__ __forceinline__ void pivot_apply(const double* __restrict__ S, int m, const double* v,
-                                            int nk, double* part, Store store) {
+// One group: rows of its comps in parallel, 2^lglanes lanes per row (adjacent
+// lanes of one wavefront, combined by shuffles).
+template <int NK>
+__device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, const int32_t* D,
+                                         double* dat, double* x, int ldx) {
+    const int lg = G.lglanes, L = 1 << lg;
+    const int total = G.rows << lg;
+    int ci = G.comp0, cstart = 0;
+    for (int j = threadIdx.x; j < total; j += kSwThreads) {
+        const int item = j >> lg, sub = j & (L - 1);
+        while (item >= cstart + C[ci].nr) {
+            cstart += C[ci].nr;
+            ++ci;
+        }
+        const SwComp& c = C[ci];
+        const int a = item - cstart;
+        double acc[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+        const double* mp = dat + c.mat + a;
+#pragma unroll 2
+        for (int t = sub; t < c.nc; t += L) {
+            const double mv = mp[t * c.ld];
+            const int row = c.in_map < 0 ? t : D[c.in_map + t];
+            const double* iv = dat + c.in + row * kSwKS;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) acc[k] = fma(mv, iv[k], acc[k]);
+        }
+        for (int o = L >> 1; o > 0; o >>= 1) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) acc[k] += __shfl_xor(acc[k], o);
+        }
+        if (sub == 0) {
+            double y[NK];
+            if (c.init >= 0) {
+                const double* ip = dat + c.init + (c.init_map < 0 ? a : D[c.init_map + a]) * kSwKS;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) y[k] = ip[k] - acc[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < NK; ++k) y[k] = acc[k];
+            }
+            if (c.out >= 0) {
+                double* op = dat + c.out + (c.out_map < 0 ? a : D[c.out_map + a]) * kSwKS;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) op[k] = y[k];
+            }
+            if (c.gmap >= 0 || c.gbase >= 0) {
+                const int row = c.gmap >= 0 ? D[c.gmap + a] : c.gbase + a;
+                double* xp = x + (int64_t)row * ldx;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) xp[k] = y[k];
+            }
+        }
+    }
+}
+
+// One work-group per super-node of a colour step; x is the extended vector
+// (row-interleaved, ldx right-hand sides), this launch treats [k0, k0 + NK).
+template <int NK>
+__global__ __launch_bounds__(kSwThreads) void k_sweep(const SwNode* __restrict__ nodes,
+                                                      const int32_t* __restrict__ prog,
+                                                      double* __restrict__ x, int ldx, int k0) {
+    extern __shared__ double smem[];
+    int32_t* Dbuf = reinterpret_cast<int32_t*>(smem);
+    double* dat = smem + kSwDescWords;           // after two descriptor buffers
     const int tid = threadIdx.x;
-    const int split = (m <= NT / 2) ? 2 : 1;
-    const int half = m > 0 ? (tid / ((NT / split))) : 0;
-    const int th = (m + split - 1) / split;
-    for (int a = tid % (NT / split); a < m; a += NT / split) {
-        double acc[KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) acc[k] = 0.0;
-        const int t0 = half * th, t1 = min(m, t0 + th);
-#pragma unroll 4
-        for (int t = t0; t < t1; ++t) {
-            const double sv = S[a + (int64_t)t * m];
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < nk) acc[k] += sv * v[t * nk + k];
-        }
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-            if (k < nk) part[(half * m + a) * nk + k] = acc[k];
-    }
+    const SwNode nd = nodes[blockIdx.x];
+    if (nd.nstage == 0) return;
+    const int32_t* src = prog + nd.desc;
+    for (int w = tid; w < nd.words0; w += kSwThreads) Dbuf[w] = src[w];
+    src += nd.words0;
+    x += k0;
     __syncthreads();
-    for (int e = tid; e < m * nk; e += NT) {
-        const int a = e / nk, k = e % nk;
-        double y = part[a * nk + k];
-        if (split == 2) y += part[(m + a) * nk + k];
-        store(a, k, y);
-    }
-    __syncthreads();
-}
-
-// Forward traversal (SolveL, Algorithm 3) for the super-node, then its black
-// node.  x holds the extended vector with ldx right-hand sides per variable;
-// this launch treats right-hand sides [k0, k0 + nk), nk <= KC.  Each wavefront
-// applies whole out-edges (different edges update different nodes).
-template <int KC>
-__global__ __launch_bounds__(NT) void k_solve_fwd(const DSNode* __restrict__ nodes,
-                                                  const DSEdge* __restrict__ edges,
-                                                  const int32_t* __restrict__ imap,
-                                                  double* __restrict__ xg, int ldx, int k0, int nk) {
-    extern __shared__ double sm[];
-    double* x = xg + k0;
-    const DSNode N = nodes[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    for (int w = 0; w < 2; ++w) {
-        const DSPiv P = w == 0 ? N.s : N.b;
-        const int m = P.m;
-        if (m == 0) continue;
-        double* rb = sm;                   // m x nk right-hand side block
-        double* fb = sm + m * nk;          // m x nk  f = S^{-1} rhs
-        double* part = sm + 2 * m * nk;    // 2 m nk
-        for (int e = tid; e < m * nk; e += NT) rb[e] = x[(int64_t)(P.off + e / nk) * ldx + e % nk];
-        __syncthreads();
-        pivot_apply<KC>(P.Sinv, m, rb, nk, part, [&](int a, int k, double y) { fb[a * nk + k] = y; });
-        for (int q = wv; q < P.nout; q += NT / WAVE) {
-            const DSEdge E = edges[P.out0 + q];
-            for (int a = lane; a < E.nr; a += WAVE) {
-                double acc[KC];
+    for (int s = 0; s < nd.nstage; ++s) {
+        const int32_t* D = Dbuf + (s & 1) * kSwDescWords;
+        int32_t* Dn = Dbuf + ((s + 1) & 1) * kSwDescWords;
+        const SwHeader H = *reinterpret_cast<const SwHeader*>(D);
+        constexpr int PW = kSwDescWords / kSwThreads;
+        int32_t nw[PW];
 #pragma unroll
-                for (int k = 0; k < KC; ++k) acc[k] = 0.0;
-#pragma unroll 4
-                for (int t = 0; t < E.nc; ++t) {
-                    const double ev = E.E[a + (int64_t)t * E.nr];
-                    const double* fr = fb + map_abs(imap, E.cbase, E.cmap, t) * nk;
-#pragma unroll
-                    for (int k = 0; k < KC; ++k)
-                        if (k < nk) acc[k] += ev * fr[k];
-                }
-                double* xr = x + (int64_t)map_abs(imap, E.rbase, E.rmap, a) * ldx;
-#pragma unroll
-                for (int k = 0; k < KC; ++k)
-                    if (k < nk) xr[k] -= acc[k];
-            }
+        for (int i = 0; i < PW; ++i) {
+            const int w = tid + i * kSwThreads;
+            nw[i] = w < H.words_next ? src[w] : 0;
         }
-        __syncthreads();
-    }
-}
-
-// Backward traversal (SolveU, Algorithm 4) for the black node, then the
-// super-node.  Wavefront w accumulates the in-edges w, w+4, ... into its own
-// LDS buffer; the buffers are added in a fixed order (deterministic).
-template <int KC>
-__global__ __launch_bounds__(NT) void k_solve_bwd(const DSNode* __restrict__ nodes,
-                                                  const DSEdge* __restrict__ edges,
-                                                  const int32_t* __restrict__ imap,
-                                                  double* __restrict__ xg, int ldx, int k0, int nk) {
-    extern __shared__ double sm[];
-    double* x = xg + k0;
-    const DSNode N = nodes[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    constexpr int NW = NT / WAVE;
-    for (int w = 0; w < 2; ++w) {
-        const DSPiv P = w == 0 ? N.b : N.s;
-        const int m = P.m;
-        if (m == 0) continue;
-        double* yb = sm;                   // m x nk
-        double* acc4 = sm + m * nk;        // NW x m x nk
-        double* part = acc4 + NW * m * nk; // 2 m nk
-        for (int e = tid; e < m * nk; e += NT) yb[e] = x[(int64_t)(P.off + e / nk) * ldx + e % nk];
-        for (int e = tid; e < NW * m * nk; e += NT) acc4[e] = 0.0;
-        __syncthreads();
-        double* mine = acc4 + wv * m * nk;
-        for (int q = wv; q < P.nin; q += NW) {
-            const DSEdge E = edges[P.in0 + q];
-            for (int a = lane; a < E.nr; a += WAVE) {
-                double acc[KC];
+        sw_copy<NK>(reinterpret_cast<const SwRun*>(D + H.runs), H.nrun, D, H.elems_mat + H.xrows * NK,
+                    x, ldx, dat);
 #pragma unroll
-                for (int k = 0; k < KC; ++k) acc[k] = 0.0;
-#pragma unroll 4
-                for (int t = 0; t < E.nc; ++t) {
-                    const double ev = E.E[a + (int64_t)t * E.nr];
-                    const double* xr = x + (int64_t)map_abs(imap, E.cbase, E.cmap, t) * ldx;
-#pragma unroll
-                    for (int k = 0; k < KC; ++k)
-                        if (k < nk) acc[k] += ev * xr[k];
-                }
-                double* yr = mine + map_abs(imap, E.rbase, E.rmap, a) * nk;
-#pragma unroll
-                for (int k = 0; k < KC; ++k)
-                    if (k < nk) yr[k] += acc[k];
-            }
+        for (int i = 0; i < PW; ++i) {
+            const int w = tid + i * kSwThreads;
+            if (w < H.words_next) Dn[w] = nw[i];
         }
+        src += H.words_next;
         __syncthreads();
-        for (int e = tid; e < m * nk; e += NT) {
-            double s = 0.0;
-#pragma unroll
-            for (int q = 0; q < NW; ++q) s += acc4[q * m * nk + e];
-            yb[e] -= s;
+        const SwGroup* G = reinterpret_cast<const SwGroup*>(D + H.groups);
+        const SwComp* C = reinterpret_cast<const SwComp*>(D + H.comps);
+        for (int g = 0; g < H.ngroup; ++g) {
+            sw_group<NK>(G[g], C, D, dat, x, ldx);
+            __syncthreads();
         }
-        __syncthreads();
-        pivot_apply<KC>(P.Sinv, m, yb, nk, part, [&](int a, int k, double y) {
-            x[(int64_t)(P.off + a) * ldx + k] = y;
-        });
     }
 }
 
@@ -1006,6 +1363,19 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                                int max_c, int max_M, hipStream_t st) {
     if (n == 0) return hipSuccess;
+    if (max_c <= 64) {
+        static bool attr64 = false;
+        if (!attr64) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_compress_svd64,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+            if (e != hipSuccess) return e;
+            attr64 = true;
+        }
+        const int cap = (kLdsBudget - 2048) / (int)sizeof(double);   // static LDS of the kernel aside
+        hipLaunchKernelGGL(k_compress_svd64, dim3(n), dim3(NTC), (size_t)cap * sizeof(double), st, t, pieces,
+                           imap, cap);
+        return hipGetLastError();
+    }
     // LDS plan: R and V (2 c^2) plus a chunk of ch rows of B (ch c), within the
     // dynamic LDS budget; below 16 rows per chunk the workspace path is used.
     static bool attr_set = false;
@@ -1044,39 +1414,31 @@ hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DI
     return hipGetLastError();
 }
 
-constexpr int SOLVE_KC = 8;          // right-hand sides per solve launch (registers)
-
-static int rhs_chunk(int max_m, int nrhs) {
-    // LDS per work-group: (1 + 4 + 2) m nk doubles (backward sweep) within 64 KiB
-    const int mm = max_m > 0 ? max_m : 1;
-    int kc = (int)((64 * 1024) / ((size_t)7 * mm * sizeof(double)));
-    if (kc < 1) kc = 1;
-    if (kc > SOLVE_KC) kc = SOLVE_KC;
-    return kc < nrhs ? kc : nrhs;
-}
-
-hipError_t launch_solve_fwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
-                            double* x, int nrhs, int max_m, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    const int kc = rhs_chunk(max_m, nrhs);
-    for (int k0 = 0; k0 < nrhs; k0 += kc) {
-        const int nk = (nrhs - k0) < kc ? (nrhs - k0) : kc;
-        const size_t lds = (size_t)4 * (max_m > 0 ? max_m : 1) * nk * sizeof(double);
-        hipLaunchKernelGGL(k_solve_fwd<SOLVE_KC>, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
+template <int NK>
+hipError_t launch_sweep_nk(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,
+                           hipStream_t st) {
+    constexpr size_t lds = (size_t)kSwDescWords * 2 * sizeof(int32_t) + (size_t)kSwData * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_sweep<NK>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
     }
+    hipLaunchKernelGGL(k_sweep<NK>, dim3(n), dim3(kSwThreads), lds, st, nodes, prog, x, ldx, k0);
     return hipGetLastError();
 }
 
-hipError_t launch_solve_bwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
-                            double* x, int nrhs, int max_m, hipStream_t st) {
+hipError_t launch_sweep(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,
+                        int nk, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const int kc = rhs_chunk(max_m, nrhs);
-    for (int k0 = 0; k0 < nrhs; k0 += kc) {
-        const int nk = (nrhs - k0) < kc ? (nrhs - k0) : kc;
-        const size_t lds = (size_t)7 * (max_m > 0 ? max_m : 1) * nk * sizeof(double);
-        hipLaunchKernelGGL(k_solve_bwd<SOLVE_KC>, dim3(n), dim3(NT), lds, st, nodes, edges, imap, x, nrhs, k0, nk);
+    switch (nk) {
+        case 8: return launch_sweep_nk<8>(nodes, n, prog, x, ldx, k0, st);
+        case 4: return launch_sweep_nk<4>(nodes, n, prog, x, ldx, k0, st);
+        case 2: return launch_sweep_nk<2>(nodes, n, prog, x, ldx, k0, st);
+        case 1: return launch_sweep_nk<1>(nodes, n, prog, x, ldx, k0, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_gather_perm(const double* b, int64_t ldb, const int32_t* perm, int n, int nrhs,

@@ -29,10 +29,10 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
 hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DIn* ins,
                               const DOut* outs, const DPair* pairs, const int32_t* imap,
                               int32_t* info, int max_m, hipStream_t st);
-hipError_t launch_solve_fwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
-                            double* x, int nrhs, int max_m, hipStream_t st);
-hipError_t launch_solve_bwd(const DSNode* nodes, int n, const DSEdge* edges, const int32_t* imap,
-                            double* x, int nrhs, int max_m, hipStream_t st);
+// One sweep launch (forward or backward program) over n super-nodes of a
+// colour step, right-hand sides [k0, k0 + nk) of x (ldx per row), nk in {1,2,4,8}.
+hipError_t launch_sweep(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,
+                        int nk, hipStream_t st);
 
 // ---- vectors: layout v[i * nrhs + k] ("row-interleaved") -------------------
 // xt[t*nrhs + k] = b[perm[t] + k*ldb]   (t < n)      and zero xt[n*nrhs .. ntot*nrhs)

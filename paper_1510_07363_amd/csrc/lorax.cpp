@@ -17,6 +17,7 @@
 #include "dev.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "sweep.hpp"
 
 using namespace lrx;
 
@@ -132,7 +133,7 @@ struct NodeMaps {
 };
 
 struct SolveStep {
-    int32_t node0 = 0, nnode = 0, max_m = 0;
+    int32_t node0 = 0, nnode = 0;
     int64_t bytes_fwd = 0, bytes_bwd = 0;   // algorithmic bytes of one launch (one right-hand side)
 };
 
@@ -207,8 +208,10 @@ struct lrx_handle_s {
     int64_t n_ext = 0;
     Arena arena;
     DevBuf d_imap;                 // factor maps
-    // solve program
-    DevBuf d_snodes, d_sedges, d_simap;
+    // solve program (staged node programs of both sweeps)
+    DevBuf d_swnodes, d_swprog;
+    int32_t sw_nnode = 0;
+    int64_t sw_stages = 0, sw_words = 0;
     std::vector<SolveStep> ssteps;
     DevBuf d_perm;
     DevBuf d_rp, d_ci, d_val;      // A in tree order
@@ -736,109 +739,99 @@ void build_solve_program(lrx_handle h) {
         }
     h->n_ext = off;
 
-    std::vector<int32_t> simap;
-    std::vector<DSNode> nodes;
-    std::vector<DSEdge> edges;
-    auto abs_list = [&](const Support& s, int32_t node) -> int32_t {
-        if (s.all) return -1;
-        int32_t o = (int32_t)simap.size();
-        for (int32_t i : s.idx) simap.push_back((int32_t)(h->var_off[node] + i));
-        return o;
-    };
-    auto loc_list = [&](const Support& s) -> int32_t {
-        if (s.all) return -1;
-        int32_t o = (int32_t)simap.size();
-        simap.insert(simap.end(), s.idx.begin(), s.idx.end());
-        return o;
-    };
+    // intermediate form: per colour step, per super-node, both pivots with
+    // their frozen out-edges (forward) and in-edges (backward)
     int64_t solve_bytes = 0;
+    auto local = [](const Support& s) { return s.all ? std::vector<int32_t>() : s.idx; };
     auto piv = [&](const PivotPlan& pp) {
-        DSPiv D{};
+        SwPivIR D;
         const int32_t v = pp.node;
+        D.node = v;
         D.m = pp.e_self >= 0 ? h->size[v] : 0;
-        D.off = (int32_t)h->var_off[v];
-        D.Sinv = pp.e_self >= 0 ? h->eptr[pp.e_self] : nullptr;
+        D.off = h->var_off[v];
+        D.inv = pp.e_self >= 0 ? h->eptr[pp.e_self] : nullptr;
         solve_bytes += 2ll * D.m * D.m * 8;
-        D.out0 = (int32_t)edges.size();
-        for (size_t i = 0; i < pp.out_edges.size(); ++i) {
-            const int32_t e = pp.out_edges[i];
-            const PEdge& E = P.edges[e];
-            DSEdge s{};
-            s.E = h->eptr[e];
-            s.nr = dim_of(E.rows, h->size[E.dst]);
-            s.nc = dim_of(E.cols, h->size[E.src]);
-            if ((int64_t)s.nr * s.nc == 0) continue;
-            s.rbase = (int32_t)h->var_off[E.dst];
-            s.rmap = abs_list(E.rows, E.dst);
-            s.cbase = 0;
-            s.cmap = loc_list(E.cols);
-            solve_bytes += (int64_t)s.nr * s.nc * 8;
-            edges.push_back(s);
+        for (int pass = 0; pass < 2; ++pass) {
+            const auto& list = pass == 0 ? pp.out_edges : pp.in_edges;
+            for (int32_t e : list) {
+                const PEdge& E = P.edges[e];
+                SwEdgeIR s;
+                s.E = h->eptr[e];
+                s.nr = dim_of(E.rows, h->size[E.dst]);
+                s.nc = dim_of(E.cols, h->size[E.src]);
+                if ((int64_t)s.nr * s.nc == 0) continue;
+                s.other = pass == 0 ? E.dst : E.src;
+                s.other_off = h->var_off[s.other];
+                s.rows = local(E.rows);
+                s.cols = local(E.cols);
+                solve_bytes += (int64_t)s.nr * s.nc * 8;
+                (pass == 0 ? D.out : D.in).push_back(std::move(s));
+            }
         }
-        D.nout = (int32_t)edges.size() - D.out0;
-        D.in0 = (int32_t)edges.size();
-        for (size_t i = 0; i < pp.in_edges.size(); ++i) {
-            const int32_t e = pp.in_edges[i];
-            const PEdge& E = P.edges[e];
-            DSEdge s{};
-            s.E = h->eptr[e];
-            s.nr = dim_of(E.rows, h->size[E.dst]);
-            s.nc = dim_of(E.cols, h->size[E.src]);
-            if ((int64_t)s.nr * s.nc == 0) continue;
-            s.rbase = 0;
-            s.rmap = loc_list(E.rows);
-            s.cbase = (int32_t)h->var_off[E.src];
-            s.cmap = abs_list(E.cols, E.src);
-            solve_bytes += (int64_t)s.nr * s.nc * 8;
-            edges.push_back(s);
-        }
-        D.nin = (int32_t)edges.size() - D.in0;
         return D;
     };
+    std::vector<std::vector<SwNodeIR>> ir;
     h->ssteps.clear();
     for (const ColourStep& cs : P.steps) {
         SolveStep ss;
-        ss.node0 = (int32_t)nodes.size();
+        ir.emplace_back();
         for (const NodeStep& ns : cs.nodes) {
-            DSNode d;
+            SwNodeIR d;
             d.s = piv(ns.ps);
             d.b = piv(ns.pb);
-            for (const DSPiv* pv : {&d.s, &d.b}) {
+            for (const SwPivIR* pv : {&d.s, &d.b}) {
                 const int64_t pivb = (int64_t)pv->m * pv->m * 8;
                 int64_t ob = 0, ib = 0;
-                for (int32_t q = 0; q < pv->nout; ++q) ob += (int64_t)edges[pv->out0 + q].nr * edges[pv->out0 + q].nc * 8;
-                for (int32_t q = 0; q < pv->nin; ++q) ib += (int64_t)edges[pv->in0 + q].nr * edges[pv->in0 + q].nc * 8;
+                for (auto& e : pv->out) ob += (int64_t)e.nr * e.nc * 8;
+                for (auto& e : pv->in) ib += (int64_t)e.nr * e.nc * 8;
                 ss.bytes_fwd += pivb + ob;
                 ss.bytes_bwd += pivb + ib;
             }
-            ss.max_m = std::max(ss.max_m, std::max(d.s.m, d.b.m));
-            nodes.push_back(d);
+            ir.back().push_back(std::move(d));
         }
-        ss.nnode = (int32_t)nodes.size() - ss.node0;
         h->ssteps.push_back(ss);
     }
-    h->d_snodes.ensure(std::max<size_t>(nodes.size(), 1) * sizeof(DSNode));
-    h->d_sedges.ensure(std::max<size_t>(edges.size(), 1) * sizeof(DSEdge));
-    h->d_simap.ensure(std::max<size_t>(simap.size(), 1) * sizeof(int32_t));
-    if (!nodes.empty()) HIPCHK(hipMemcpy(h->d_snodes.p, nodes.data(), nodes.size() * sizeof(DSNode), hipMemcpyHostToDevice));
-    if (!edges.empty()) HIPCHK(hipMemcpy(h->d_sedges.p, edges.data(), edges.size() * sizeof(DSEdge), hipMemcpyHostToDevice));
-    if (!simap.empty()) HIPCHK(hipMemcpy(h->d_simap.p, simap.data(), simap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    SwProgram prog;
+    std::string err;
+    if (!build_sweep_program(ir, prog, err)) fail(LRX_EDEVICE, err);
+    for (size_t i = 0; i < h->ssteps.size(); ++i) {
+        h->ssteps[i].node0 = prog.step0[i];
+        h->ssteps[i].nnode = prog.step0[i + 1] - prog.step0[i];
+    }
+    const size_t nn = prog.fwd.size();
+    h->d_swnodes.ensure(std::max<size_t>(2 * nn, 1) * sizeof(SwNode));
+    h->d_swprog.ensure(std::max<size_t>(prog.words.size(), 1) * sizeof(int32_t));
+    if (nn) {
+        std::vector<SwNode> both(prog.fwd);
+        both.insert(both.end(), prog.bwd.begin(), prog.bwd.end());
+        HIPCHK(hipMemcpy(h->d_swnodes.p, both.data(), both.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+    }
+    if (!prog.words.empty())
+        HIPCHK(hipMemcpy(h->d_swprog.p, prog.words.data(), prog.words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    h->sw_nnode = (int32_t)nn;
+    h->sw_stages = prog.total_stages;
+    h->sw_words = (int64_t)prog.words.size();
     h->stats.solve_bytes = solve_bytes;
 }
 
 // x_ext (n_ext x nrhs interleaved) -> in place sweeps
 void sweeps(lrx_handle h, double* xe, int nrhs) {
     const hipStream_t st = h->stream;
-    const DSNode* nd = h->d_snodes.as<DSNode>();
-    const DSEdge* ed = h->d_sedges.as<DSEdge>();
-    const int32_t* im = h->d_simap.as<int32_t>();
-    for (const SolveStep& s : h->ssteps) {
-        LaunchTimer tm(LRX_K_SOLVE_FWD, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nrhs);
-        HIPCHK(launch_solve_fwd(nd + s.node0, s.nnode, ed, im, xe, nrhs, s.max_m, st));
-    }
-    for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it) {
-        LaunchTimer tm(LRX_K_SOLVE_BWD, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nrhs);
-        HIPCHK(launch_solve_bwd(nd + it->node0, it->nnode, ed, im, xe, nrhs, it->max_m, st));
+    const SwNode* fwd = h->d_swnodes.as<SwNode>();
+    const SwNode* bwd = fwd + h->sw_nnode;
+    const int32_t* prog = h->d_swprog.as<int32_t>();
+    for (int k0 = 0; k0 < nrhs;) {
+        const int rem = nrhs - k0;
+        const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+        for (const SolveStep& s : h->ssteps) {
+            LaunchTimer tm(LRX_K_SOLVE_FWD, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nk);
+            HIPCHK(launch_sweep(fwd + s.node0, s.nnode, prog, xe, nrhs, k0, nk, st));
+        }
+        for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it) {
+            LaunchTimer tm(LRX_K_SOLVE_BWD, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nk);
+            HIPCHK(launch_sweep(bwd + it->node0, it->nnode, prog, xe, nrhs, k0, nk, st));
+        }
+        k0 += nk;
     }
 }
 
