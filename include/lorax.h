@@ -104,6 +104,8 @@ typedef struct {
     int64_t factor_flops;          /* algorithmic flops of the factorization */
     double t_plan_ms;              /* host symbolic planning */
     double t_factor_ms;            /* whole lrx_factor call */
+    double t_sync_ms;              /* host time blocked on the stream inside lrx_factor */
+    double t_solve_prog_ms;        /* host compilation of the solve sweeps */
 } lrx_stats_t;
 
 /* Symbolic counts, computed on the host without any device call. */

@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <set>
 #include <string>
 #include <vector>
@@ -226,6 +228,7 @@ struct lrx_handle_s {
     std::vector<double> tails;          // per compression: |R11|, ||R22||_F for k = 0..r
     std::vector<int64_t> tail_off;
     double max_tail_ratio = 0.0;
+    double t_sync_ms = 0.0, t_solve_prog_ms = 0.0;
 };
 
 namespace {
@@ -259,6 +262,12 @@ void ensure_gfx950(int dev) {
 void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
     Plan& P = h->plan;
     const hipStream_t st = h->stream;
+#define SYNC(s_)                                                   \
+    do {                                                           \
+        const double ts_ = now_ms();                               \
+        HIPCHK(hipStreamSynchronize(s_));                          \
+        h->t_sync_ms += now_ms() - ts_;                            \
+    } while (0)
     const int32_t n = P.n;
     h->size.assign(P.nodes.size(), -1);
     h->eptr.assign(P.edges.size(), nullptr);
@@ -402,7 +411,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             }
             HIPCHK(launch_scatter(base, d_idx.as<int64_t>(), src, A->nnz, st));
         }
-        HIPCHK(hipStreamSynchronize(st));   // d_idx/d_val are released at scope end
+        SYNC(st);   // d_idx/d_val are released at scope end
     }
 
     // ---------------- level loop
@@ -440,13 +449,13 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             if (!mt.empty()) {
                 std::vector<char> buf;
                 size_t o = append_bytes(buf, mt);
-                HIPCHK(hipStreamSynchronize(st));
+                SYNC(st);
                 stage_c.ensure(buf.size());
                 std::memcpy(stage_c.p, buf.data(), buf.size());
                 d_desc_c.ensure(buf.size());
                 HIPCHK(hipMemcpyAsync(d_desc_c.p, stage_c.p, buf.size(), hipMemcpyHostToDevice, st));
                 HIPCHK(launch_merge((const DMerge*)(d_desc_c.as<char>() + o), (int)mt.size(), st));
-                HIPCHK(hipStreamSynchronize(st));
+                SYNC(st);
             }
         }
         for (int32_t si = L.step0; si < L.step0 + L.nsteps; ++si) {
@@ -524,8 +533,14 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 w_need += (((size_t)rmax * sum_nc_b) + 31) & ~(size_t)31;
             }
             const size_t ws_total = ws_need + w_need;
-            HIPCHK(hipStreamSynchronize(st));      // previous kernels done: buffers reusable
-            if (ws_total * 8 > ws.bytes) ws.ensure(ws_total * 8 + (ws_total * 8) / 2);
+            // The workspace is only touched by kernels on this stream, so the
+            // compress below may be queued behind the previous node kernel; the
+            // host staging buffers were released by the previous rank read-back.
+            // Growing the workspace frees it, which needs the stream idle.
+            if (ws_total * 8 > ws.bytes) {
+                SYNC(st);
+                ws.ensure(ws_total * 8 + (ws_total * 8) / 2);
+            }
             double* wsp = ws.as<double>();
             d_ranks.ensure(std::max(nn, 1) * sizeof(int32_t));
             for (int ni = 0; ni < nn; ++ni) {
@@ -562,7 +577,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             double* tails_h = (double*)((char*)pin_ranks.p + (((size_t)nn * 4 + 63) & ~(size_t)63));
             if (tails_total)
                 HIPCHK(hipMemcpyAsync(tails_h, wsp + wsT[0], tails_total * 8, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            SYNC(st);
             const int32_t* rk = (const int32_t*)pin_ranks.p;
             for (int ni = 0; ni < nn; ++ni) {
                 const NodeStep& ns = cs.nodes[ni];
@@ -701,7 +716,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             }
         }
     }
-    HIPCHK(hipStreamSynchronize(st));
+    SYNC(st);
     {
         std::vector<int32_t> info(std::max(info_slots, 1));
         HIPCHK(hipMemcpy(info.data(), d_info.p, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -712,7 +727,10 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
 }
 
 // ------------------------------------------------------------------ solve program
+#undef SYNC
+
 void build_solve_program(lrx_handle h) {
+    const double t_begin = now_ms();
     Plan& P = h->plan;
     const int32_t n = P.n;
     h->var_off.assign(P.nodes.size(), -1);
@@ -739,79 +757,114 @@ void build_solve_program(lrx_handle h) {
         }
     h->n_ext = off;
 
-    // intermediate form: per colour step, per super-node, both pivots with
-    // their frozen out-edges (forward) and in-edges (backward)
-    int64_t solve_bytes = 0;
-    auto local = [](const Support& s) { return s.all ? std::vector<int32_t>() : s.idx; };
-    auto piv = [&](const PivotPlan& pp) {
-        SwPivIR D;
-        const int32_t v = pp.node;
-        D.node = v;
-        D.m = pp.e_self >= 0 ? h->size[v] : 0;
-        D.off = h->var_off[v];
-        D.inv = pp.e_self >= 0 ? h->eptr[pp.e_self] : nullptr;
-        solve_bytes += 2ll * D.m * D.m * 8;
-        for (int pass = 0; pass < 2; ++pass) {
-            const auto& list = pass == 0 ? pp.out_edges : pp.in_edges;
-            for (int32_t e : list) {
-                const PEdge& E = P.edges[e];
-                SwEdgeIR s;
-                s.E = h->eptr[e];
-                s.nr = dim_of(E.rows, h->size[E.dst]);
-                s.nc = dim_of(E.cols, h->size[E.src]);
-                if ((int64_t)s.nr * s.nc == 0) continue;
-                s.other = pass == 0 ? E.dst : E.src;
-                s.other_off = h->var_off[s.other];
-                s.rows = local(E.rows);
-                s.cols = local(E.cols);
-                solve_bytes += (int64_t)s.nr * s.nc * 8;
-                (pass == 0 ? D.out : D.in).push_back(std::move(s));
-            }
-        }
-        return D;
+    // per super-node (in colour-step order): the intermediate form of both
+    // pivots with their frozen out-edges (forward) and in-edges (backward), then
+    // its two programs; nodes are independent, so host threads share them
+    struct NodeRef { int32_t step, node; };
+    std::vector<NodeRef> refs;
+    h->ssteps.assign(P.steps.size(), SolveStep{});
+    for (size_t si = 0; si < P.steps.size(); ++si) {
+        h->ssteps[si].node0 = (int32_t)refs.size();
+        for (size_t ni = 0; ni < P.steps[si].nodes.size(); ++ni) refs.push_back({(int32_t)si, (int32_t)ni});
+        h->ssteps[si].nnode = (int32_t)refs.size() - h->ssteps[si].node0;
+    }
+    const size_t nn = refs.size();
+    struct NodeOut {
+        std::vector<int32_t> words;
+        SwNode f{}, b{};
+        int64_t bytes_fwd = 0, bytes_bwd = 0, solve_bytes = 0;
+        std::string err;
     };
-    std::vector<std::vector<SwNodeIR>> ir;
-    h->ssteps.clear();
-    for (const ColourStep& cs : P.steps) {
-        SolveStep ss;
-        ir.emplace_back();
-        for (const NodeStep& ns : cs.nodes) {
-            SwNodeIR d;
-            d.s = piv(ns.ps);
-            d.b = piv(ns.pb);
-            for (const SwPivIR* pv : {&d.s, &d.b}) {
-                const int64_t pivb = (int64_t)pv->m * pv->m * 8;
-                int64_t ob = 0, ib = 0;
-                for (auto& e : pv->out) ob += (int64_t)e.nr * e.nc * 8;
-                for (auto& e : pv->in) ib += (int64_t)e.nr * e.nc * 8;
-                ss.bytes_fwd += pivb + ob;
-                ss.bytes_bwd += pivb + ib;
+    std::vector<NodeOut> outs(nn);
+    auto local = [](const Support& s) { return s.all ? std::vector<int32_t>() : s.idx; };
+    auto work = [&](size_t i) {
+        NodeOut& o = outs[i];
+        const NodeStep& ns = P.steps[refs[i].step].nodes[refs[i].node];
+        auto piv = [&](const PivotPlan& pp) {
+            SwPivIR D;
+            const int32_t v = pp.node;
+            D.node = v;
+            D.m = pp.e_self >= 0 ? h->size[v] : 0;
+            D.off = h->var_off[v];
+            D.inv = pp.e_self >= 0 ? h->eptr[pp.e_self] : nullptr;
+            o.solve_bytes += 2ll * D.m * D.m * 8;
+            for (int pass = 0; pass < 2; ++pass) {
+                const auto& list = pass == 0 ? pp.out_edges : pp.in_edges;
+                for (int32_t e : list) {
+                    const PEdge& E = P.edges[e];
+                    SwEdgeIR s;
+                    s.E = h->eptr[e];
+                    s.nr = dim_of(E.rows, h->size[E.dst]);
+                    s.nc = dim_of(E.cols, h->size[E.src]);
+                    if ((int64_t)s.nr * s.nc == 0) continue;
+                    s.other = pass == 0 ? E.dst : E.src;
+                    s.other_off = h->var_off[s.other];
+                    s.rows = local(E.rows);
+                    s.cols = local(E.cols);
+                    o.solve_bytes += (int64_t)s.nr * s.nc * 8;
+                    (pass == 0 ? D.out : D.in).push_back(std::move(s));
+                }
             }
-            ir.back().push_back(std::move(d));
+            return D;
+        };
+        SwNodeIR d;
+        d.s = piv(ns.ps);
+        d.b = piv(ns.pb);
+        for (const SwPivIR* pv : {&d.s, &d.b}) {
+            const int64_t pivb = (int64_t)pv->m * pv->m * 8;
+            int64_t ob = 0, ib = 0;
+            for (auto& e : pv->out) ob += (int64_t)e.nr * e.nc * 8;
+            for (auto& e : pv->in) ib += (int64_t)e.nr * e.nc * 8;
+            o.bytes_fwd += pivb + ob;
+            o.bytes_bwd += pivb + ib;
         }
-        h->ssteps.push_back(ss);
+        if (!build_node_programs(d, o.words, o.f, o.b, o.err) && o.err.empty()) o.err = "solve sweep";
+    };
+    {
+        const size_t nth = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+        std::atomic<size_t> next{0};
+        auto loop = [&]() {
+            for (size_t i; (i = next.fetch_add(1)) < nn;) {
+                try {
+                    work(i);
+                } catch (const std::exception& e) {
+                    outs[i].err = std::string("solve sweep: ") + e.what();
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (size_t t = 1; t < nth && t < nn; ++t) pool.emplace_back(loop);
+        loop();
+        for (auto& t : pool) t.join();
     }
-    SwProgram prog;
-    std::string err;
-    if (!build_sweep_program(ir, prog, err)) fail(LRX_EDEVICE, err);
-    for (size_t i = 0; i < h->ssteps.size(); ++i) {
-        h->ssteps[i].node0 = prog.step0[i];
-        h->ssteps[i].nnode = prog.step0[i + 1] - prog.step0[i];
+    int64_t solve_bytes = 0;
+    std::vector<int32_t> words;
+    std::vector<SwNode> both(2 * nn);
+    for (size_t i = 0; i < nn; ++i) {
+        NodeOut& o = outs[i];
+        if (!o.err.empty()) fail(LRX_EDEVICE, o.err);
+        if (words.size() & 1) words.push_back(0);
+        const int64_t base = (int64_t)words.size();
+        words.insert(words.end(), o.words.begin(), o.words.end());
+        both[i] = o.f;
+        both[nn + i] = o.b;
+        both[i].desc += base;
+        both[nn + i].desc += base;
+        solve_bytes += o.solve_bytes;
+        SolveStep& ss = h->ssteps[refs[i].step];
+        ss.bytes_fwd += o.bytes_fwd;
+        ss.bytes_bwd += o.bytes_bwd;
+        h->sw_stages += o.f.nstage + o.b.nstage;
     }
-    const size_t nn = prog.fwd.size();
     h->d_swnodes.ensure(std::max<size_t>(2 * nn, 1) * sizeof(SwNode));
-    h->d_swprog.ensure(std::max<size_t>(prog.words.size(), 1) * sizeof(int32_t));
-    if (nn) {
-        std::vector<SwNode> both(prog.fwd);
-        both.insert(both.end(), prog.bwd.begin(), prog.bwd.end());
-        HIPCHK(hipMemcpy(h->d_swnodes.p, both.data(), both.size() * sizeof(SwNode), hipMemcpyHostToDevice));
-    }
-    if (!prog.words.empty())
-        HIPCHK(hipMemcpy(h->d_swprog.p, prog.words.data(), prog.words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    h->d_swprog.ensure(std::max<size_t>(words.size(), 1) * sizeof(int32_t));
+    if (nn) HIPCHK(hipMemcpy(h->d_swnodes.p, both.data(), both.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+    if (!words.empty())
+        HIPCHK(hipMemcpy(h->d_swprog.p, words.data(), words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    h->sw_words = (int64_t)words.size();
     h->sw_nnode = (int32_t)nn;
-    h->sw_stages = prog.total_stages;
-    h->sw_words = (int64_t)prog.words.size();
     h->stats.solve_bytes = solve_bytes;
+    h->t_solve_prog_ms = now_ms() - t_begin;
 }
 
 // x_ext (n_ext x nrhs interleaved) -> in place sweeps
@@ -1184,6 +1237,8 @@ static lrx_status factor_impl(const lrx_csr* A, const double* val_dev, const lrx
         S.factor_bytes = h->arena.total * 8;
         S.t_plan_ms = t1 - t0;
         S.t_factor_ms = t2 - t0;
+        S.t_sync_ms = h->t_sync_ms;
+        S.t_solve_prog_ms = h->t_solve_prog_ms;
         {
             std::lock_guard<std::mutex> lk(g_reg_mu);
             g_live.insert(h);

@@ -11,10 +11,12 @@ namespace lrx {
 void Support::unite(const Support& o) {
     if (all) return;
     if (o.all) { all = true; idx.clear(); return; }
-    std::vector<int32_t> u;
+    if (std::includes(idx.begin(), idx.end(), o.idx.begin(), o.idx.end())) return;   // no change
+    thread_local std::vector<int32_t> u;
+    u.clear();
     u.reserve(idx.size() + o.idx.size());
     std::set_union(idx.begin(), idx.end(), o.idx.begin(), o.idx.end(), std::back_inserter(u));
-    idx.swap(u);
+    idx.assign(u.begin(), u.end());
 }
 
 std::vector<int32_t> positions(const Support& sub, const Support& sup, int32_t full) {
@@ -124,10 +126,10 @@ struct Builder {
                     Support r = P.edges[e_vq].rows, c = P.edges[e_kv].cols;
                     e_kq = add_edge(k, q, std::move(r), std::move(c), EO_FILL);
                     cs.new_edges.push_back(e_kq);
-                } else {
-                    Support r = P.edges[e_vq].rows, c = P.edges[e_kv].cols;
-                    P.edges[e_kq].rows.unite(r);
-                    P.edges[e_kq].cols.unite(c);
+                } else {                       // no edge is added here: references stay valid
+                    PEdge& T = P.edges[e_kq];
+                    T.rows.unite(P.edges[e_vq].rows);
+                    T.cols.unite(P.edges[e_kv].cols);
                 }
                 pp.pair_in.push_back((int32_t)ki);
                 pp.pair_out.push_back((int32_t)qi);
@@ -241,9 +243,17 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
                 ents.push_back({ss, sd, lr, tc - P.nodes[ss].dof0});
             }
         }
-        std::sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) {
-            return a.src != b.src ? a.src < b.src : a.dst < b.dst;
-        });
+        {   // group by (src, dst): two stable counting passes (dst, then src)
+            std::vector<Ent> tmp(ents.size());
+            std::vector<int64_t> cnt((size_t)nsl + 1);
+            for (int pass = 0; pass < 2; ++pass) {
+                std::fill(cnt.begin(), cnt.end(), 0);
+                for (const Ent& x : ents) ++cnt[(pass == 0 ? x.dst : x.src) + 1];
+                for (int32_t b = 0; b < nsl; ++b) cnt[b + 1] += cnt[b];
+                for (const Ent& x : ents) tmp[cnt[pass == 0 ? x.dst : x.src]++] = x;
+                ents.swap(tmp);
+            }
+        }
         size_t i0 = 0;
         while (i0 < ents.size()) {
             size_t i1 = i0;

@@ -623,6 +623,11 @@ bool build_bwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std:
 
 }  // namespace
 
+bool build_node_programs(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& fwd, SwNode& bwd,
+                         std::string& err) {
+    return build_fwd(N, words, fwd, err) && build_bwd(N, words, bwd, err);
+}
+
 bool build_sweep_program(const std::vector<std::vector<SwNodeIR>>& steps, SwProgram& out,
                          std::string& err) {
     out = SwProgram{};

@@ -46,4 +46,9 @@ struct SwProgram {
 bool build_sweep_program(const std::vector<std::vector<SwNodeIR>>& steps, SwProgram& out,
                          std::string& err);
 
+// Compiles the forward and backward programs of one super-node, appending their
+// descriptor blocks to words (descriptors relative to the start of words).
+bool build_node_programs(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& fwd, SwNode& bwd,
+                         std::string& err);
+
 }  // namespace lrx

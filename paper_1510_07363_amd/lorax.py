@@ -55,7 +55,8 @@ class Stats(C.Structure):
                 ("extended_size", C.c_int64), ("max_compression_error", C.c_double),
                 ("factor_bytes", C.c_int64),
                 ("solve_bytes", C.c_int64), ("factor_flops", C.c_int64),
-                ("t_plan_ms", C.c_double), ("t_factor_ms", C.c_double)]
+                ("t_plan_ms", C.c_double), ("t_factor_ms", C.c_double),
+                ("t_sync_ms", C.c_double), ("t_solve_prog_ms", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -267,7 +268,8 @@ class Factor:
                     max_compression_error=float(s.max_compression_error),
                     factor_bytes=int(s.factor_bytes),
                     solve_bytes=int(s.solve_bytes), factor_flops=int(s.factor_flops),
-                    t_plan_ms=float(s.t_plan_ms), t_factor_ms=float(s.t_factor_ms))
+                    t_plan_ms=float(s.t_plan_ms), t_factor_ms=float(s.t_factor_ms),
+                    t_sync_ms=float(s.t_sync_ms), t_solve_prog_ms=float(s.t_solve_prog_ms))
 
     def ranks(self):
         n = self.stats()["n_compressions"]
