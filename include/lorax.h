@@ -192,10 +192,11 @@ lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order,
  * adds two event records to its stream. */
 typedef enum {
     LRX_K_COMPRESS = 0,       /* stacked-block assembly + truncated SVD / RRQR (Sec. 4.3) */
-    LRX_K_FACTOR_NODE = 1,    /* projection, rewiring, Eliminate(s), Eliminate(b) (Sec. 4.4) */
+    LRX_K_FACTOR_NODE = 1,    /* projection, rewiring and pivot inverses of the nodes (Sec. 4.3, 4.4) */
     LRX_K_SOLVE_FWD = 2,      /* SolveL sweep of one colour step (Algorithm 3) */
     LRX_K_SOLVE_BWD = 3,      /* SolveU sweep of one colour step (Algorithm 4) */
     LRX_K_SPMV = 4,           /* A times the preconditioned vectors (GMRES) */
+    LRX_K_SCHUR = 5,          /* Schur-complement products of Eliminate(s), Eliminate(b) (Sec. 2.2) */
     LRX_K_CLASSES = 8
 } lrx_kernel_class;
 

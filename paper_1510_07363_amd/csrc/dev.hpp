@@ -55,36 +55,36 @@ struct DProj {
                          // columns (trans 1): later fill may widen dst's support
 };
 
-struct DIn {             // in-edge Mat(k -> v); its rows are vars of v
-    DBlk blk;
-    int32_t rmap, pad_;  // rows -> pivot-local index (map or identity)
-    double* W;           // workspace m x blk.nc: Mat(v->v)^{-1} Mat(k->v)
-};
-
-struct DOut {            // out-edge Mat(v -> q); its columns are vars of v
-    DBlk blk;
-    int32_t cmap, pad_;  // columns -> pivot-local index
-};
-
-struct DPair {           // Mat(k->q)[rpos, cpos] -= Mat(v->q) W_k
-    DBlk tgt;
-    int32_t in_i, out_i;
-    int32_t rpos, cpos;  // row positions (len out.nr) and column positions (len in.nc) in tgt
-};
-
-struct DPivot {
-    DBlk piv;            // Mat(v->v), inverted in place
-    int32_t in0, nin, out0, nout, pair0, npair;
-    int32_t info_slot, pad_;
-};
-
-struct DNode {
+// One launch per colour step prepares every super-node (projection and
+// rewiring, then the inverse of its pivot); a second kind of launch covers the
+// pivot of the black node only (do_proj == 0).
+struct DPrep {
     int32_t r, c, nproj, proj0;
     int32_t M, svd;      // svd: R_k / Q_k = B V computed from the kept B (column-major, ld M)
     const double* B;     // SVD: stacked block (column-major); RRQR: transformed block (row-major)
     const double* V;     // c x r column-major
     DBlk sb, bs, bP, Pb; // Mat(s->b) = V^T, Mat(b->s) = V, Mat(b->P) = Mat(P->b) = -I_r
-    DPivot ps, pb;
+    DBlk piv;            // pivot block Mat(v->v), inverted in place (nr == 0: none)
+    int32_t info_slot, do_proj;
+};
+
+// ---- Block elimination as batched gather/scatter products (Sec. 2.2) --------
+//   C[crow(i), ccol(j)] (-)= sum_t A[i + acol(t) lda] B[brow(t) + j ldb]
+// i < M, j < N, t < K; every map is an imap offset or -1 (identity).  For the
+// pivot v with inverse S: W_k = S[:, rows of Mat(k->v)] Mat(k->v) (sub = 0),
+// then Mat(k->q)[rpos, cpos] -= Mat(v->q) W_k[cols of Mat(v->q), :] (sub = 1).
+struct DGemm {
+    const double* A;
+    const double* B;
+    double* C;
+    int32_t M, N, K;
+    int32_t lda, ldb, ldc;
+    int32_t amap, bmap, crmap, ccmap;
+    int32_t sub, pad_;
+};
+
+struct DTile {           // one 32 x 32 block of C of product g
+    int32_t g, i0, j0, pad_;
 };
 
 // ---- MergeRedNodes: copy a red block into its super-node block --------------

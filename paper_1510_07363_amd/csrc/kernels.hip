@@ -6,6 +6,8 @@
 // same memory and no atomics are needed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <climits>
 #include <cmath>
 
@@ -739,8 +741,8 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
 }
 
 // ------------------------------------------------------------------ elimination
-constexpr int NTN = 512;                     // threads of the node-factorization kernel
-constexpr int NWN = NTN / WAVE;
+constexpr int NTP = 1024;                    // threads of the pivot-preparation kernel
+constexpr int NWP = NTP / WAVE;
 
 // In-place inverse of the m x m column-major block by Gauss-Jordan elimination
 // with partial (row) pivoting inside the block (large blocks, global memory);
@@ -766,19 +768,19 @@ __device__ bool gj_inverse_global(double* A, int m, double* scol, int* sperm, do
         const int p = sperm[k];
         if (!(s_d[0] > 0.0)) return false;
         if (p != k)
-            for (int j = tid; j < m; j += NTN) {
+            for (int j = tid; j < m; j += NTP) {
                 double t = A[k + (int64_t)j * m];
                 A[k + (int64_t)j * m] = A[p + (int64_t)j * m];
                 A[p + (int64_t)j * m] = t;
             }
         __syncthreads();
         const double d = 1.0 / A[k + (int64_t)k * m];
-        for (int i = tid; i < m; i += NTN) scol[i] = A[i + (int64_t)k * m];
+        for (int i = tid; i < m; i += NTP) scol[i] = A[i + (int64_t)k * m];
         __syncthreads();
-        for (int j = tid; j < m; j += NTN)
+        for (int j = tid; j < m; j += NTP)
             A[k + (int64_t)j * m] = (j == k) ? d : A[k + (int64_t)j * m] * d;
         __syncthreads();
-        for (int e = tid; e < m * m; e += NTN) {
+        for (int e = tid; e < m * m; e += NTP) {
             const int i = e % m, j = e / m;
             if (i == k) continue;
             const double f = scol[i];
@@ -787,7 +789,7 @@ __device__ bool gj_inverse_global(double* A, int m, double* scol, int* sperm, do
         }
         __syncthreads();
     }
-    for (int i = tid; i < m; i += NTN)
+    for (int i = tid; i < m; i += NTP)
         for (int k = m - 1; k >= 0; --k) {
             const int p = sperm[k];
             if (p != k) {
@@ -800,200 +802,126 @@ __device__ bool gj_inverse_global(double* A, int m, double* scol, int* sperm, do
     return true;
 }
 
-// Register-resident Gauss-Jordan inverse with partial pivoting for m <= MB:
-// thread t owns row t % MB, columns [(t / MB) * CPT, + CPT); the matrix is
-// padded with the identity beyond m.  Pivot row and column go through LDS.
-// `lds` needs 3 * MB doubles + 2 * MB ints + NWN (double, int) slots.
+// Register-resident Gauss-Jordan inverse with partial pivoting for m <= MB.
+// Thread t owns row i = t % MB and the CPT columns [h CPT, (h+1) CPT), h = t / MB;
+// the matrix is padded with the identity beyond m.  Pivoting is implicit: step
+// k takes the unused physical row p_k with the largest |A[p_k, k]| (lowest
+// index on ties) as pivot row, without moving rows, so the storage ends as
+// (P A)^{-1} by physical rows, and A^{-1}[k, p_l] = stored[p_k, l] on output.
+// The pivot search of step k+1 runs inside the update of step k, so a step
+// costs two barriers; every register index is a compile-time constant.
+// `lds` needs 2 MB doubles + MB ints + 4 NWP (double, int) slots.
 template <int MB>
 __device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
-    constexpr int TPR = NTN / MB;         // threads per row
+    constexpr int TPR = NTP / MB;         // threads per row
     constexpr int CPT = MB / TPR;         // columns per thread
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int i = tid % MB, h = tid / MB, c0 = h * CPT;
-    double* prow = lds;                   // MB
-    double* pcol = lds + MB;              // MB
-    double* rbuf = lds + 2 * MB;          // MB (row exchange)
-    int* perm = (int*)(lds + 3 * MB);     // MB
-    int* dest = perm + MB;                // MB
-    double* rv = (double*)(dest + MB);    // NWN reduction values
-    int* ri = (int*)(rv + NWN);           // NWN reduction indices
+    double* prow = lds;                   // MB: pivot row
+    double* pcol = lds + MB;              // MB: pivot column (multipliers)
+    int* pivrow = (int*)(lds + 2 * MB);   // MB: physical pivot row of each step
+    double* rv = (double*)(pivrow + MB);  // 2 x NWP partial maxima (double-buffered)
+    int* ri = (int*)(rv + 2 * NWP);       // 2 x NWP their rows
     double a[CPT];
 #pragma unroll
     for (int jj = 0; jj < CPT; ++jj) {
         const int col = c0 + jj;
         a[jj] = (i < m && col < m) ? A[i + (int64_t)col * m] : (i == col ? 1.0 : 0.0);
     }
-    for (int k = 0; k < m; ++k) {
-        const int kh = k / CPT, kj = k % CPT;
-        double v = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < CPT; ++jj) v = (jj == kj) ? a[jj] : v;
-        // ---- pivot: largest |A[i, k]|, i in [k, m), lowest index on ties
-        double best = -1.0;
-        int bi = INT_MAX;
-        if (h == kh && i >= k && i < m) { best = fabs(v); bi = i; }
+    bool used = i >= m;                   // padding rows never pivot
+    int mystep = -1;
+    // value of this thread's row in the next pivot column (owners only)
+    double ck = (h == 0 && !used) ? a[0] : 0.0;
+    auto publish_max = [&](double cand, int buf) {
+        double best = cand;
+        int bi = cand >= 0.0 ? i : INT_MAX;
         for (int o = WAVE / 2; o > 0; o >>= 1) {
-            const double ob = __shfl_down(best, o);
-            const int oi = __shfl_down(bi, o);
+            const double ob = __shfl_xor(best, o);
+            const int oi = __shfl_xor(bi, o);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
-        if (tid % WAVE == 0) { rv[tid / WAVE] = best; ri[tid / WAVE] = bi; }
-        __syncthreads();
-        best = rv[0]; bi = ri[0];
-        for (int w = 1; w < NWN; ++w)
-            if (rv[w] > best || (rv[w] == best && ri[w] < bi)) { best = rv[w]; bi = ri[w]; }
-        if (!(best > 0.0)) return false;          // uniform
-        const int p = bi;
-        if (tid == 0) perm[k] = p;
-        // ---- swap rows k and p
-        if (p != k) {
-            if (i == p) {
-#pragma unroll
-                for (int jj = 0; jj < CPT; ++jj) rbuf[c0 + jj] = a[jj];
-            }
-            if (i == k) {
-#pragma unroll
-                for (int jj = 0; jj < CPT; ++jj) prow[c0 + jj] = a[jj];
-            }
-            __syncthreads();
-            if (i == k) {
-#pragma unroll
-                for (int jj = 0; jj < CPT; ++jj) a[jj] = rbuf[c0 + jj];
-            }
-            if (i == p) {
-#pragma unroll
-                for (int jj = 0; jj < CPT; ++jj) a[jj] = prow[c0 + jj];
-            }
-            __syncthreads();
+        if (lane == 0) { rv[buf * NWP + wv] = best; ri[buf * NWP + wv] = bi; }
+    };
+    publish_max((h == 0 && !used) ? fabs(ck) : -1.0, 0);
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        const int buf = k & 1;
+        double best = rv[buf * NWP];
+        int p = ri[buf * NWP];
+        for (int w = 1; w < NWP; ++w) {
+            const double v = rv[buf * NWP + w];
+            const int q = ri[buf * NWP + w];
+            if (v > best || (v == best && q < p)) { best = v; p = q; }
         }
-        // ---- publish the pivot row and column
-        if (i == k) {
+        if (!(best > 0.0)) return false;          // uniform: exactly singular
+        const int kh = k / CPT;
+        if (i == p) {
 #pragma unroll
             for (int jj = 0; jj < CPT; ++jj) prow[c0 + jj] = a[jj];
+            used = true;
+            mystep = k;
         }
-        if (h == kh) {
-            double w = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < CPT; ++jj) w = (jj == kj) ? a[jj] : w;
-            pcol[i] = w;
-        }
+        if (h == kh) pcol[i] = ck;
+        if (tid == 0) pivrow[k] = p;
         __syncthreads();
         const double d = 1.0 / prow[k];
-        if (i == k) {
-#pragma unroll
-            for (int jj = 0; jj < CPT; ++jj) a[jj] = (c0 + jj == k) ? d : a[jj] * d;
-        } else {
-            const double f = pcol[i];
+        const int kn = k + 1, knh = kn / CPT;
+        double cnext = 0.0;
+        if (i == p) {
 #pragma unroll
             for (int jj = 0; jj < CPT; ++jj) {
                 const int col = c0 + jj;
-                a[jj] = (col == k) ? -f * d : a[jj] - f * (prow[col] * d);
+                a[jj] = (col == k) ? d : a[jj] * d;
+                cnext = (col == kn) ? a[jj] : cnext;
+            }
+        } else {
+            const double f = pcol[i] * d;
+            if (h == kh || h == knh) {            // holds column k or k + 1
+#pragma unroll
+                for (int jj = 0; jj < CPT; ++jj) {
+                    const int col = c0 + jj;
+                    const double v = a[jj] - f * prow[col];
+                    a[jj] = (col == k) ? -f : v;
+                    cnext = (col == kn) ? a[jj] : cnext;
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < CPT; ++jj) a[jj] -= f * prow[c0 + jj];
             }
         }
+        ck = cnext;
+        if (kn < m) publish_max((h == knh && !used) ? fabs(ck) : -1.0, buf ^ 1);
         __syncthreads();
     }
-    // undo the row interchanges as column interchanges: destination of every column
-    if (tid < m) {
-        int j = tid;
-        for (int k = 0; k < m; ++k) {
-            const int p = perm[k];
-            j = (j == k) ? p : (j == p ? k : j);
-        }
-        dest[j] = tid;
-    }
-    __syncthreads();
-    if (i < m) {
+    // A^{-1}[k, p_l] = stored[p_k, l]: this thread holds stored[i, c0..] with i = p_mystep
+    if (mystep >= 0) {
 #pragma unroll
         for (int jj = 0; jj < CPT; ++jj) {
             const int col = c0 + jj;
-            if (col < m) A[i + (int64_t)dest[col] * m] = a[jj];
+            if (col < m) A[mystep + (int64_t)pivrow[col] * m] = a[jj];
         }
     }
     __syncthreads();
     return true;
 }
 
-// Block Gauss elimination of one pivot (Sec. 2.2): invert Mat(v->v); then for
-// every in-edge k, W_k = Mat(v->v)^{-1} Mat(k->v) is formed in LDS (in column
-// chunks) and applied to every out-edge q: Mat(k->q) -= Mat(v->q) W_k.  The
-// inverse stays in LDS when it fits.  Pairs are stored q-major (q * nin + k).
-__device__ void eliminate(const DPivot& P, const DIn* __restrict__ ins,
-                          const DOut* __restrict__ outs, const DPair* __restrict__ pairs,
-                          const int32_t* __restrict__ imap, int32_t* __restrict__ info,
-                          double* sm, int cap) {
-    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    const int m = P.piv.nr;
-    if (m == 0) return;
-    bool ok;
-    if (m <= 32) ok = gj_inverse_reg<32>(P.piv.p, m, sm);
-    else if (m <= 64) ok = gj_inverse_reg<64>(P.piv.p, m, sm);
-    else if (m <= 128) ok = gj_inverse_reg<128>(P.piv.p, m, sm);
-    else ok = gj_inverse_global(P.piv.p, m, sm, (int*)(sm + m), sm + 2 * m);
-    if (!ok) {
-        if (tid == 0) info[P.info_slot] = 1;
-        return;
-    }
-    if (P.nin == 0 || P.nout == 0) return;
-    // LDS: S^{-1} (m^2) when it leaves room for a W chunk of >= 8 columns
-    const bool sl = (int64_t)m * m + 8ll * m <= cap;
-    const double* S = P.piv.p;
-    double* Wl = sm;
-    if (sl) {
-        for (int e = tid; e < m * m; e += NTN) sm[e] = P.piv.p[e];
-        S = sm;
-        Wl = sm + (size_t)m * m;
-    }
-    const int wch = (int)((cap - (sl ? (int64_t)m * m : 0)) / m);
-    __syncthreads();
-    for (int i = 0; i < P.nin; ++i) {
-        const DIn I = ins[P.in0 + i];
-        const int nr = I.blk.nr, nc = I.blk.nc;
-        for (int b0 = 0; b0 < nc; b0 += wch) {
-            const int wc = min(wch, nc - b0);
-            for (int e = tid; e < m * wc; e += NTN) {
-                const int a = e % m, b = e / m;
-                const double* col = I.blk.p + (int64_t)(b0 + b) * nr;
-                double s = 0.0;
-#pragma unroll 4
-                for (int t = 0; t < nr; ++t) s += S[a + (int64_t)imap_at(imap, I.rmap, t) * m] * col[t];
-                Wl[a + b * m] = s;
-            }
-            __syncthreads();
-            for (int q = wv; q < P.nout; q += NWN) {
-                const DOut O = outs[P.out0 + q];
-                const DPair Q = pairs[P.pair0 + q * P.nin + i];
-                const int onr = O.blk.nr, K = O.blk.nc;
-                for (int e = lane; e < onr * wc; e += WAVE) {
-                    const int a = e % onr, b = e / onr;
-                    const double* wb = Wl + b * m;
-                    double s = 0.0;
-#pragma unroll 4
-                    for (int t = 0; t < K; ++t) s += O.blk.p[a + (int64_t)t * onr] * wb[imap_at(imap, O.cmap, t)];
-                    const int ra = imap_at(imap, Q.rpos, a), cb = imap_at(imap, Q.cpos, b0 + b);
-                    Q.tgt.p[ra + (int64_t)cb * Q.tgt.nr] -= s;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-__global__ __launch_bounds__(NTN) void k_factor_node(const DNode* __restrict__ tasks,
-                                                     const DProj* __restrict__ projs,
-                                                     const DIn* __restrict__ ins,
-                                                     const DOut* __restrict__ outs,
-                                                     const DPair* __restrict__ pairs,
-                                                     const int32_t* __restrict__ imap,
-                                                     int32_t* __restrict__ info, int cap) {
-    const DNode T = tasks[blockIdx.x];
+// Per super-node preparation (Sec. 4.3, Sec. 4.4): [R; Q] = B V into the
+// blocks Mat(P -> p_k) and Mat(p_k -> P), the rewiring blocks V, V^T, -I, and
+// the inverse of the pivot block.  With do_proj == 0 only the pivot is
+// inverted (black nodes, after the Schur updates of their super-node).
+__global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tasks,
+                                                   const DProj* __restrict__ projs,
+                                                   const int32_t* __restrict__ imap,
+                                                   int32_t* __restrict__ info) {
+    const DPrep T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
     extern __shared__ double sm[];
     const int r = T.r, c = T.c;
-    if (r > 0) {
+    if (T.do_proj && r > 0) {
         for (int q = 0; q < T.nproj; ++q) {
             const DProj Pj = projs[T.proj0 + q];
             const int nrow = Pj.nrows;
-            for (int e = tid; e < nrow * r; e += NTN) {
+            for (int e = tid; e < nrow * r; e += NTP) {
                 int a, t;
                 if (!Pj.trans) { a = e % nrow; t = e / nrow; }
                 else           { t = e % r;    a = e / r; }
@@ -1001,9 +929,16 @@ __global__ __launch_bounds__(NTN) void k_factor_node(const DNode* __restrict__ t
                 if (T.svd) {                      // (B V)[row0 + a, t]
                     const double* brow = T.B + (Pj.row0 + a);
                     const double* vcol = T.V + (int64_t)t * c;
-                    v = 0.0;
-#pragma unroll 4
-                    for (int j = 0; j < c; ++j) v += brow[(int64_t)j * T.M] * vcol[j];
+                    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+                    int j = 0;
+                    for (; j + 4 <= c; j += 4) {
+                        v0 += brow[(int64_t)j * T.M] * vcol[j];
+                        v1 += brow[(int64_t)(j + 1) * T.M] * vcol[j + 1];
+                        v2 += brow[(int64_t)(j + 2) * T.M] * vcol[j + 2];
+                        v3 += brow[(int64_t)(j + 3) * T.M] * vcol[j + 3];
+                    }
+                    for (; j < c; ++j) v0 += brow[(int64_t)j * T.M] * vcol[j];
+                    v = (v0 + v1) + (v2 + v3);
                 } else {                          // transformed row-pivoted block
                     v = T.B[(int64_t)(Pj.row0 + a) * c + t];
                 }
@@ -1011,21 +946,108 @@ __global__ __launch_bounds__(NTN) void k_factor_node(const DNode* __restrict__ t
                 else           Pj.dst.p[t + (int64_t)imap_at(imap, Pj.map, a) * r] = v;           // Q_k^T
             }
         }
-        for (int e = tid; e < c * r; e += NTN) {
+        for (int e = tid; e < c * r; e += NTP) {
             T.bs.p[e] = T.V[e];                          // V      (c x r)
             const int t = e % r, a = e / r;
             T.sb.p[e] = T.V[a + (int64_t)t * c];         // V^T    (r x c)
         }
-        for (int e = tid; e < r * r; e += NTN) {
+        for (int e = tid; e < r * r; e += NTP) {
             const double v = (e % r == e / r) ? -1.0 : 0.0;
             T.bP.p[e] = v;
             T.Pb.p[e] = v;
         }
     }
+    const int m = T.piv.nr;
+    if (m == 0) return;
     __syncthreads();
-    eliminate(T.ps, ins, outs, pairs, imap, info, sm, cap);
-    __syncthreads();
-    eliminate(T.pb, ins, outs, pairs, imap, info, sm, cap);
+    bool ok;
+    if (m <= 32) ok = gj_inverse_reg<32>(T.piv.p, m, sm);
+    else if (m <= 64) ok = gj_inverse_reg<64>(T.piv.p, m, sm);
+    else if (m <= 128) ok = gj_inverse_reg<128>(T.piv.p, m, sm);
+    else ok = gj_inverse_global(T.piv.p, m, sm, (int*)(sm + m), sm + 2 * m);
+    if (!ok && tid == 0) info[T.info_slot] = 1;
+}
+
+// Tiled product with gathers and scatters (DGemm): one work-group per 32 x 32
+// tile of C; the A panel (32 x K), the B panel (K x 32) and, for sub, the C tile
+// are copied to LDS in one pass (every load in flight), then each thread
+// accumulates a 2 x 2 block.  K is taken in chunks of gk <= GK.
+constexpr int GT = 256;                      // threads per tile
+constexpr int GK = 256;                      // K chunk held in LDS
+constexpr int GLA = 33;                      // LDS leading dimension of A and C tiles
+
+__global__ __launch_bounds__(GT) void k_gemm_tiles(const DGemm* __restrict__ gs,
+                                                   const DTile* __restrict__ tiles,
+                                                   const int32_t* __restrict__ imap, int gk) {
+    extern __shared__ double sm[];
+    const DTile tl = tiles[blockIdx.x];
+    const DGemm G = gs[tl.g];
+    const int tid = threadIdx.x;
+    const int mt = min(32, G.M - tl.i0), nt = min(32, G.N - tl.j0);
+    double* As = sm;                         // 32 x gk, ld GLA
+    double* Cs = As + GLA * gk;              // 32 x 32, ld GLA
+    double* Bs = Cs + GLA * 32;              // gk x 32, ld kb1 (odd)
+    const int tx = tid % 16, ty = tid / 16;
+    double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
+    for (int k0 = 0; k0 < G.K; k0 += gk) {
+        const int kc = min(gk, G.K - k0);
+        const int kb1 = kc | 1;
+        // A panel: lane a = tid % 32 over rows, 8 column slots
+        {
+            const int a = tid % 32;
+            if (a < mt)
+                for (int t = tid / 32; t < kc; t += GT / 32) {
+                    const int col = imap_at(imap, G.amap, k0 + t);
+                    As[a + t * GLA] = G.A[(int64_t)(tl.i0 + a) + (int64_t)col * G.lda];
+                }
+        }
+        // B panel: lane over K, 4 column slots
+        {
+            const int tt = tid % 64;
+            for (int b = tid / 64; b < nt; b += GT / 64)
+                for (int t = tt; t < kc; t += 64) {
+                    const int row = imap_at(imap, G.bmap, k0 + t);
+                    Bs[t + b * kb1] = G.B[(int64_t)row + (int64_t)(tl.j0 + b) * G.ldb];
+                }
+        }
+        if (k0 == 0 && G.sub) {
+            const int a = tid % 32;
+            if (a < mt) {
+                const int row = imap_at(imap, G.crmap, tl.i0 + a);
+                for (int b = tid / 32; b < nt; b += GT / 32) {
+                    const int col = imap_at(imap, G.ccmap, tl.j0 + b);
+                    Cs[a + b * GLA] = G.C[(int64_t)row + (int64_t)col * G.ldc];
+                }
+            }
+        }
+        __syncthreads();
+        const bool r0 = ty < mt, r1 = ty + 16 < mt, c0 = tx < nt, c1 = tx + 16 < nt;
+        if ((r0 || r1) && (c0 || c1)) {
+            const double* ap = As + ty;
+            const double* bp0 = Bs + tx * kb1;
+            const double* bp1 = Bs + (tx + 16) * kb1;
+#pragma unroll 4
+            for (int t = 0; t < kc; ++t) {
+                const double x0 = ap[t * GLA], x1 = ap[t * GLA + 16];
+                const double y0 = bp0[t], y1 = bp1[t];
+                acc00 = fma(x0, y0, acc00);
+                acc01 = fma(x0, y1, acc01);
+                acc10 = fma(x1, y0, acc10);
+                acc11 = fma(x1, y1, acc11);
+            }
+        }
+        __syncthreads();
+    }
+    auto put = [&](int a, int b, double v) {
+        if (a >= mt || b >= nt) return;
+        const int row = imap_at(imap, G.crmap, tl.i0 + a);
+        const int col = imap_at(imap, G.ccmap, tl.j0 + b);
+        G.C[(int64_t)row + (int64_t)col * G.ldc] = G.sub ? Cs[a + b * GLA] - v : v;
+    };
+    put(ty, tx, acc00);
+    put(ty, tx + 16, acc01);
+    put(ty + 16, tx, acc10);
+    put(ty + 16, tx + 16, acc11);
 }
 
 // ------------------------------------------------------------------ solve sweeps
@@ -1397,20 +1419,39 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
     return hipGetLastError();
 }
 
-hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DIn* ins,
-                              const DOut* outs, const DPair* pairs, const int32_t* imap,
-                              int32_t* info, int max_m, hipStream_t st) {
+hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,
+                            int32_t* info, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void*)k_factor_node, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
-        attr_set = true;
+    // LDS: the Gauss-Jordan exchange buffers (4 KiB), or the global variant's
+    // scratch (2 m + 1 doubles)
+    const size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
+    if (need > (size_t)kLdsBudget) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_node_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
     }
-    // the whole budget: Gauss-Jordan scratch, then S^{-1} and W chunks
-    const int cap = kLdsBudget / (int)sizeof(double);
-    (void)max_m;
-    hipLaunchKernelGGL(k_factor_node, dim3(n), dim3(NTN), (size_t)kLdsBudget, st, t, proj, ins, outs, pairs,
-                       imap, info, cap);
+    const size_t lds = need;
+    hipLaunchKernelGGL(k_node_prep, dim3(n), dim3(NTP), lds, st, t, proj, imap, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int kmax, const int32_t* imap,
+                             hipStream_t st) {
+    if (ntile == 0) return hipSuccess;
+    static bool attr = false;
+    if (!attr) {
+        constexpr size_t most = (size_t)(GLA * GK + GLA * 32 + (GK + 1) * 32) * sizeof(double);
+        hipError_t e = hipFuncSetAttribute((const void*)k_gemm_tiles, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)most);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int gk = kmax < 1 ? 1 : (kmax > GK ? GK : kmax);
+    const size_t lds = (size_t)(GLA * gk + GLA * 32 + (gk + 1) * 32) * sizeof(double);
+    hipLaunchKernelGGL(k_gemm_tiles, dim3(ntile), dim3(GT), lds, st, g, tiles, imap, gk);
     return hipGetLastError();
 }
 

@@ -26,9 +26,14 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
                            int max_c, hipStream_t st);
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                                int max_c, int max_M, hipStream_t st);
-hipError_t launch_factor_node(const DNode* t, int n, const DProj* proj, const DIn* ins,
-                              const DOut* outs, const DPair* pairs, const int32_t* imap,
-                              int32_t* info, int max_m, hipStream_t st);
+// Projection, rewiring and pivot inverse per task (DPrep); info[slot] = 1 for an
+// exactly singular pivot.
+hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,
+                            int32_t* info, hipStream_t st);
+// ntile 32 x 32 tiles of the products g (DGemm, DTile); kmax = largest K.
+hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int kmax, const int32_t* imap,
+                             hipStream_t st);
+
 // One sweep launch (forward or backward program) over n super-nodes of a
 // colour step, right-hand sides [k0, k0 + nk) of x (ldx per row), nk in {1,2,4,8}.
 hipError_t launch_sweep(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,

@@ -604,61 +604,52 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             }
             // ---- allocate the blocks created in this step
             alloc_group(cs.new_edges);
-            // ---- node descriptors
-            const int64_t flops_before_nodes = flops;
-            std::vector<DNode> nt(nn);
+            // ---- node descriptors: preparation of every super-node (projection,
+            //      rewiring, inverse of S), Schur products of s, inverse of the
+            //      black pivot B = -V^T S^{-1} V, Schur products of b
+            std::vector<DPrep> prep_s(nn), prep_b(nn);
             std::vector<DProj> projs;
-            std::vector<DIn> ins;
-            std::vector<DOut> outs;
-            std::vector<DPair> pairs;
+            std::vector<DGemm> g1s, g2s, g1b, g2b;
             size_t wcur = ws_need;
-            int max_m = 1;
-            auto build_piv = [&](const PivotPlan& pp, const PivMaps& pm, DPivot& D) {
+            int max_ms = 1, max_mb = 1;
+            int64_t pf_s = 0, pf_b = 0, gf_s = 0, gf_b = 0;
+            auto schur = [&](const PivotPlan& pp, const PivMaps& pm, std::vector<DGemm>& g1,
+                             std::vector<DGemm>& g2, int64_t& gfl) {
                 const int32_t m = h->size[pp.node];
-                D.piv = blk(pp.e_self);
-                D.in0 = (int32_t)ins.size();
-                D.out0 = (int32_t)outs.size();
-                D.pair0 = (int32_t)pairs.size();
-                D.info_slot = info_slots++;
-                max_m = std::max(max_m, m);
+                if (m == 0 || pp.e_self < 0) return;
+                const double* Sinv = h->eptr[pp.e_self];
+                std::vector<double*> W(pp.in_edges.size(), nullptr);
+                std::vector<DBlk> ib(pp.in_edges.size());
                 for (size_t i = 0; i < pp.in_edges.size(); ++i) {
-                    DIn I{};
-                    I.blk = blk(pp.in_edges[i]);
-                    I.rmap = pm.in_rmap[i];
-                    I.W = wsp + wcur;
-                    wcur += (((size_t)m * I.blk.nc) + 31) & ~(size_t)31;
-                    ins.push_back(I);
-                    flops += 2ll * m * I.blk.nr * I.blk.nc;
-                }
-                for (size_t i = 0; i < pp.out_edges.size(); ++i) {
-                    DOut O{};
-                    O.blk = blk(pp.out_edges[i]);
-                    O.cmap = pm.out_cmap[i];
-                    outs.push_back(O);
+                    ib[i] = blk(pp.in_edges[i]);
+                    W[i] = wsp + wcur;
+                    wcur += (((size_t)m * ib[i].nc) + 31) & ~(size_t)31;
+                    if ((int64_t)ib[i].nr * ib[i].nc == 0) continue;
+                    DGemm G{};
+                    G.A = Sinv; G.lda = m; G.amap = pm.in_rmap[i];
+                    G.B = ib[i].p; G.ldb = ib[i].nr; G.bmap = -1;
+                    G.C = W[i]; G.ldc = m; G.crmap = -1; G.ccmap = -1;
+                    G.M = m; G.N = ib[i].nc; G.K = ib[i].nr; G.sub = 0;
+                    g1.push_back(G);
+                    gfl += 2ll * m * ib[i].nr * ib[i].nc;
                 }
                 for (size_t q = 0; q < pp.pair_edge.size(); ++q) {
-                    DPair Q{};
-                    Q.tgt = blk(pp.pair_edge[q]);
-                    Q.in_i = pp.pair_in[q];
-                    Q.out_i = pp.pair_out[q];
-                    Q.rpos = pm.pair_rpos[q];
-                    Q.cpos = pm.pair_cpos[q];
-                    const DOut& O = outs[D.out0 + Q.out_i];
-                    const DIn& I = ins[D.in0 + Q.in_i];
-                    flops += 2ll * O.blk.nr * O.blk.nc * I.blk.nc;
-                    pairs.push_back(Q);
+                    const int32_t qi = pp.pair_out[q], ki = pp.pair_in[q];
+                    const DBlk O = blk(pp.out_edges[qi]);
+                    const DBlk T = blk(pp.pair_edge[q]);
+                    if ((int64_t)O.nr * O.nc * ib[ki].nc == 0) continue;
+                    DGemm G{};
+                    G.A = O.p; G.lda = O.nr; G.amap = -1;
+                    G.B = W[ki]; G.ldb = m; G.bmap = pm.out_cmap[qi];
+                    G.C = T.p; G.ldc = T.nr; G.crmap = pm.pair_rpos[q]; G.ccmap = pm.pair_cpos[q];
+                    G.M = O.nr; G.N = ib[ki].nc; G.K = O.nc; G.sub = 1;
+                    g2.push_back(G);
+                    gfl += 2ll * O.nr * O.nc * ib[ki].nc;
                 }
-                D.nin = (int32_t)pp.in_edges.size();
-                D.nout = (int32_t)pp.out_edges.size();
-                D.npair = (int32_t)pp.pair_edge.size();
-                // the kernel addresses pair (q, k) at q * nin + k
-                if (D.npair != 0 && D.npair != D.nin * D.nout)
-                    fail(LRX_EDEVICE, "internal: Schur pairs are not the full product of in- and out-edges");
-                flops += 2ll * m * m * m;
             };
             for (int ni = 0; ni < nn; ++ni) {
                 const NodeStep& ns = cs.nodes[ni];
-                DNode& T = nt[ni];
+                DPrep& T = prep_s[ni];
                 const int32_t r = rk[ni];
                 T.r = r;
                 T.c = ct[ni].c;
@@ -666,6 +657,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 T.svd = use_svd ? 1 : 0;
                 T.B = ct[ni].B;
                 T.V = ct[ni].V;
+                T.do_proj = 1;
                 T.proj0 = (int32_t)projs.size();
                 for (size_t k = 0; k < ns.cands.size(); ++k) {
                     const CandRef& cr = ns.cands[k];
@@ -693,26 +685,67 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 T.bs = blk(ns.e_bs);
                 T.bP = blk(ns.e_bP);
                 T.Pb = blk(ns.e_Pb);
-                build_piv(ns.ps, maps[si][ni].ps, T.ps);
-                build_piv(ns.pb, maps[si][ni].pb, T.pb);
+                T.piv = blk(ns.ps.e_self);
+                T.info_slot = info_slots++;
+                max_ms = std::max(max_ms, (int)T.piv.nr);
+                pf_s += 2ll * T.piv.nr * T.piv.nr * T.piv.nr + 2ll * T.M * T.c * r;
+                DPrep& U = prep_b[ni];
+                U.piv = blk(ns.pb.e_self);
+                U.info_slot = info_slots++;
+                U.do_proj = 0;
+                max_mb = std::max(max_mb, (int)U.piv.nr);
+                pf_b += 2ll * U.piv.nr * U.piv.nr * U.piv.nr;
+                schur(ns.ps, maps[si][ni].ps, g1s, g2s, gf_s);
+                schur(ns.pb, maps[si][ni].pb, g1b, g2b, gf_b);
             }
+            flops += pf_s + pf_b + gf_s + gf_b;
             if (wcur * 8 > ws.bytes) fail(LRX_EDEVICE, "internal: workspace estimate too small");
+            auto tiles_of = [](const std::vector<DGemm>& gs, int& kmax) {
+                std::vector<DTile> t;
+                kmax = 1;
+                for (size_t g = 0; g < gs.size(); ++g) {
+                    kmax = std::max(kmax, (int)gs[g].K);
+                    for (int32_t i0 = 0; i0 < gs[g].M; i0 += 32)
+                        for (int32_t j0 = 0; j0 < gs[g].N; j0 += 32) t.push_back(DTile{(int32_t)g, i0, j0, 0});
+                }
+                return t;
+            };
+            int k1s, k2s, k1b, k2b;
+            const std::vector<DTile> t1s = tiles_of(g1s, k1s), t2s = tiles_of(g2s, k2s);
+            const std::vector<DTile> t1b = tiles_of(g1b, k1b), t2b = tiles_of(g2b, k2b);
             {
                 std::vector<char> buf;
-                size_t o1 = append_bytes(buf, nt);
-                size_t o2 = append_bytes(buf, projs);
-                size_t o3 = append_bytes(buf, ins);
-                size_t o4 = append_bytes(buf, outs);
-                size_t o5 = append_bytes(buf, pairs);
+                const size_t o_ps = append_bytes(buf, prep_s), o_pj = append_bytes(buf, projs);
+                const size_t o_pb = append_bytes(buf, prep_b);
+                const size_t o_g1s = append_bytes(buf, g1s), o_t1s = append_bytes(buf, t1s);
+                const size_t o_g2s = append_bytes(buf, g2s), o_t2s = append_bytes(buf, t2s);
+                const size_t o_g1b = append_bytes(buf, g1b), o_t1b = append_bytes(buf, t1b);
+                const size_t o_g2b = append_bytes(buf, g2b), o_t2b = append_bytes(buf, t2b);
                 stage_n.ensure(buf.size());
                 std::memcpy(stage_n.p, buf.data(), buf.size());
                 d_desc_n.ensure(buf.size());
                 HIPCHK(hipMemcpyAsync(d_desc_n.p, stage_n.p, buf.size(), hipMemcpyHostToDevice, st));
                 char* b = d_desc_n.as<char>();
-                LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)(flops - flops_before_nodes));
-                HIPCHK(launch_factor_node((const DNode*)(b + o1), nn, (const DProj*)(b + o2),
-                                          (const DIn*)(b + o3), (const DOut*)(b + o4),
-                                          (const DPair*)(b + o5), d_imap, d_info.as<int32_t>(), max_m, st));
+                int32_t* inf = d_info.as<int32_t>();
+                auto gemm = [&](size_t og, size_t ot, const std::vector<DTile>& t, int kmax, int64_t fl) {
+                    if (t.empty()) return;
+                    LaunchTimer tm(LRX_K_SCHUR, st, 0.0, (double)fl);
+                    HIPCHK(launch_gemm_tiles((const DGemm*)(b + og), (const DTile*)(b + ot), (int)t.size(), kmax,
+                                             d_imap, st));
+                };
+                {
+                    LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)pf_s);
+                    HIPCHK(launch_node_prep((const DPrep*)(b + o_ps), nn, max_ms, (const DProj*)(b + o_pj), d_imap,
+                                            inf, st));
+                }
+                gemm(o_g1s, o_t1s, t1s, k1s, 0);
+                gemm(o_g2s, o_t2s, t2s, k2s, gf_s);
+                {
+                    LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)pf_b);
+                    HIPCHK(launch_node_prep((const DPrep*)(b + o_pb), nn, max_mb, nullptr, d_imap, inf, st));
+                }
+                gemm(o_g1b, o_t1b, t1b, k1b, 0);
+                gemm(o_g2b, o_t2b, t2b, k2b, gf_b);
             }
         }
     }

@@ -68,7 +68,8 @@ class Timing(C.Structure):
     _fields_ = [("k", KernelTime * 8)]
 
 
-KERNEL_CLASSES = {0: "compress", 1: "factor_node", 2: "solve_fwd", 3: "solve_bwd", 4: "spmv"}
+KERNEL_CLASSES = {0: "compress", 1: "factor_node", 2: "solve_fwd", 3: "solve_bwd", 4: "spmv",
+                  5: "schur"}
 
 
 class PlanInfo(C.Structure):
