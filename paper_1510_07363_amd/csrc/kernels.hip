@@ -445,6 +445,34 @@ __device__ __forceinline__ double row16_sum(double v) {
     return v;
 }
 
+// Largest v over a wavefront (lowest i on ties); every lane receives (v, i).
+// DPP within rows of 16 lanes, then the four row results through readlane.
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+    const double ov = dpp_mov<CTRL>(v);
+    const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+    argmax_step<0xB1>(v, i);
+    argmax_step<0x4E>(v, i);
+    argmax_step<0x141>(v, i);
+    argmax_step<0x140>(v, i);
+    double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                __builtin_amdgcn_readlane(__double2loint(v), 0));
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const double o = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * r),
+                                          __builtin_amdgcn_readlane(__double2loint(v), 16 * r));
+        const int oi = __builtin_amdgcn_readlane(i, 16 * r);
+        if (o > b || (o == b && oi < bi)) { b = o; bi = oi; }
+    }
+    v = b;
+    i = bi;
+}
+
 // In-place Householder QR, optionally with column pivoting (largest remaining
 // column norm, lowest index on ties), of the nr x c matrix A in LDS (column-
 // major, leading dimension ld, c <= 64).  On exit R is the upper triangle;
@@ -832,29 +860,29 @@ __device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
     int mystep = -1;
     // value of this thread's row in the next pivot column (owners only)
     double ck = (h == 0 && !used) ? a[0] : 0.0;
+    // column k is held by the wavefronts [kh MB / WAVE, kh MB / WAVE + WPG)
+    constexpr int WPG = MB >= WAVE ? MB / WAVE : 1;
     auto publish_max = [&](double cand, int buf) {
         double best = cand;
         int bi = cand >= 0.0 ? i : INT_MAX;
-        for (int o = WAVE / 2; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o);
-            const int oi = __shfl_xor(bi, o);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
+        wave_argmax(best, bi);
         if (lane == 0) { rv[buf * NWP + wv] = best; ri[buf * NWP + wv] = bi; }
     };
     publish_max((h == 0 && !used) ? fabs(ck) : -1.0, 0);
     __syncthreads();
     for (int k = 0; k < m; ++k) {
         const int buf = k & 1;
-        double best = rv[buf * NWP];
-        int p = ri[buf * NWP];
-        for (int w = 1; w < NWP; ++w) {
-            const double v = rv[buf * NWP + w];
-            const int q = ri[buf * NWP + w];
+        const int kh = k / CPT;
+        const int w0 = (kh * MB) / WAVE;
+        double best = rv[buf * NWP + w0];
+        int p = ri[buf * NWP + w0];
+#pragma unroll
+        for (int w = 1; w < WPG; ++w) {
+            const double v = rv[buf * NWP + w0 + w];
+            const int q = ri[buf * NWP + w0 + w];
             if (v > best || (v == best && q < p)) { best = v; p = q; }
         }
         if (!(best > 0.0)) return false;          // uniform: exactly singular
-        const int kh = k / CPT;
         if (i == p) {
 #pragma unroll
             for (int jj = 0; jj < CPT; ++jj) prow[c0 + jj] = a[jj];
@@ -918,33 +946,39 @@ __global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tas
     extern __shared__ double sm[];
     const int r = T.r, c = T.c;
     if (T.do_proj && r > 0) {
-        for (int q = 0; q < T.nproj; ++q) {
-            const DProj Pj = projs[T.proj0 + q];
-            const int nrow = Pj.nrows;
-            for (int e = tid; e < nrow * r; e += NTP) {
-                int a, t;
-                if (!Pj.trans) { a = e % nrow; t = e / nrow; }
-                else           { t = e % r;    a = e / r; }
-                double v;
-                if (T.svd) {                      // (B V)[row0 + a, t]
-                    const double* brow = T.B + (Pj.row0 + a);
-                    const double* vcol = T.V + (int64_t)t * c;
-                    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-                    int j = 0;
-                    for (; j + 4 <= c; j += 4) {
-                        v0 += brow[(int64_t)j * T.M] * vcol[j];
-                        v1 += brow[(int64_t)(j + 1) * T.M] * vcol[j + 1];
-                        v2 += brow[(int64_t)(j + 2) * T.M] * vcol[j + 2];
-                        v3 += brow[(int64_t)(j + 3) * T.M] * vcol[j + 3];
-                    }
-                    for (; j < c; ++j) v0 += brow[(int64_t)j * T.M] * vcol[j];
-                    v = (v0 + v1) + (v2 + v3);
-                } else {                          // transformed row-pivoted block
-                    v = T.B[(int64_t)(Pj.row0 + a) * c + t];
-                }
-                if (!Pj.trans) Pj.dst.p[imap_at(imap, Pj.map, a) + (int64_t)t * Pj.dst.nr] = v;   // R_k
-                else           Pj.dst.p[t + (int64_t)imap_at(imap, Pj.map, a) * r] = v;           // Q_k^T
+        // all pieces as one element range, so every thread has work
+        int total = 0;
+        for (int q = 0; q < T.nproj; ++q) total += projs[T.proj0 + q].nrows * r;
+        int q = 0, qstart = 0;
+        for (int e = tid; e < total; e += NTP) {
+            while (e >= qstart + projs[T.proj0 + q].nrows * r) {
+                qstart += projs[T.proj0 + q].nrows * r;
+                ++q;
             }
+            const DProj Pj = projs[T.proj0 + q];
+            const int nrow = Pj.nrows, le = e - qstart;
+            int a, t;
+            if (!Pj.trans) { a = le % nrow; t = le / nrow; }
+            else           { t = le % r;    a = le / r; }
+            double v;
+            if (T.svd) {                      // (B V)[row0 + a, t]
+                const double* brow = T.B + (Pj.row0 + a);
+                const double* vcol = T.V + (int64_t)t * c;
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+                int j = 0;
+                for (; j + 4 <= c; j += 4) {
+                    v0 += brow[(int64_t)j * T.M] * vcol[j];
+                    v1 += brow[(int64_t)(j + 1) * T.M] * vcol[j + 1];
+                    v2 += brow[(int64_t)(j + 2) * T.M] * vcol[j + 2];
+                    v3 += brow[(int64_t)(j + 3) * T.M] * vcol[j + 3];
+                }
+                for (; j < c; ++j) v0 += brow[(int64_t)j * T.M] * vcol[j];
+                v = (v0 + v1) + (v2 + v3);
+            } else {                          // transformed row-pivoted block
+                v = T.B[(int64_t)(Pj.row0 + a) * c + t];
+            }
+            if (!Pj.trans) Pj.dst.p[imap_at(imap, Pj.map, a) + (int64_t)t * Pj.dst.nr] = v;   // R_k
+            else           Pj.dst.p[t + (int64_t)imap_at(imap, Pj.map, a) * r] = v;           // Q_k^T
         }
         for (int e = tid; e < c * r; e += NTP) {
             T.bs.p[e] = T.V[e];                          // V      (c x r)
