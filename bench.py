@@ -5,14 +5,18 @@ Workload (default): 2-D variable-coefficient diffusion on a 256 x 256 grid
 (n = 65,536, 5-point, kappa = exp(g) with g a seeded Gaussian field of unit
 variance and correlation length 8 cells), RCB cluster tree with leaf clusters
 of 64 (depth 10), epsilon = 1e-4, 8 seeded right-hand sides uniform in [-1, 1],
-right-preconditioned GMRES(30) to a true relative residual of 1e-10, FP64.
+right-preconditioned GMRES(30) to a true relative residual of 1e-10.
 
 One step = lrx_factor_dev (symbolic plan on the host + numeric factorization
 from values resident in HBM) + lrx_gmres_dev on the 8 right-hand sides
 resident in HBM.  value = right-hand sides solved per second over the timed
-steps.  The line also carries the roofline entry of the dominant kernel class
-(event-timed inside the timed region) and the CPU-oracle baseline measured on a
-bounded sample of the same recipe.
+steps, in the precision given by --precision (default mixed: FP32 compression
+arithmetic and FP32 stored factor for the solve, FP64 pivots, Schur updates
+and GMRES); the other precision is measured the same way and reported in
+detail, with the distance between the two solutions.  The line also carries
+the roofline entry of the dominant kernel class (event-timed inside the timed
+region) and the CPU-oracle baseline measured on a bounded sample of the same
+recipe.
 """
 import argparse
 import json
@@ -37,6 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="varcoef2d_256")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"],
+                    help="precision of the reported value; the other one is measured too and "
+                         "reported in detail")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-side", type=int, default=128,
                     help="grid side of the oracle's bounded sample (same recipe)")
@@ -76,6 +83,77 @@ def cpu_baseline(workload, side):
                        f"to n={full.n}")}
 
 
+def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
+    """Warm-up, one untimed probe step (finds the dominant kernel class), then
+    exactly args.steps timed steps bracketed by stream synchronisation."""
+    nrhs = p.rhs.shape[1]
+    state = {}
+
+    def step():
+        F = lorax.Factor(p.row_ptr, p.col_idx, None, p.perm, p.leaf_ptr, p.depth, p.epsilon,
+                         stream=sptr, val_dev=val_d.data_ptr(), precision=precision)
+        its, rr, st = F.gmres_dev(b_d.data_ptr(), x_d.data_ptr(), nrhs, tol=TOL,
+                                  restart=RESTART, maxit=500)
+        if st != lorax.LRX_OK or float(np.max(rr)) > TOL:
+            raise RuntimeError(f"GMRES did not reach {TOL}: status {st}, relres {rr}")
+        state["its"], state["rr"], state["stats"] = its, rr, F.stats()
+        F.free()
+
+    for _ in range(args.warmup):
+        step()
+    lorax.timing_enable(None)
+    lorax.timing_read(reset=True)
+    step()
+    probe = lorax.timing_read(reset=True)
+    dom = max(probe, key=lambda k: probe[k]["total_ms"])
+    lorax.timing_enable([dom])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = lorax.timing_read(reset=True)
+    lorax.timing_enable([])
+    # independent check of the last solution
+    A = p.scipy()
+    X = x_d.cpu().numpy().T
+    res = np.linalg.norm(A @ X - p.rhs, axis=0) / np.linalg.norm(p.rhs, axis=0)
+    if float(res.max()) > TOL:
+        raise RuntimeError(f"true residual {res.max():.3e} above {TOL}")
+    T = t1 - t0
+    d = timing[dom]
+    avg_ms = d["total_ms"] / max(d["launches"], 1)
+    if dom in ("solve_fwd", "solve_bwd", "spmv"):
+        per_launch = d["bytes"] / max(d["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        per_launch = d["flops"] / max(d["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = d["launches"]
+    st = state["stats"]
+    return {
+        "ms_per_step": 1e3 * T / args.steps,
+        "value": nrhs * args.steps / T,
+        "roofline": roof,
+        "X": X,
+        "detail": {"gmres_iters": [int(i) for i in state["its"]],
+                   "true_relres_max": float(res.max()),
+                   "t_factor_ms": st["t_factor_ms"], "t_plan_ms": st["t_plan_ms"],
+                   "t_factor_sync_ms": st["t_sync_ms"], "t_solve_prog_ms": st["t_solve_prog_ms"],
+                   "factor_bytes": st["factor_bytes"], "solve_bytes": st["solve_bytes"],
+                   "mean_rank": st["mean_rank"], "max_rank": st["max_rank"],
+                   "kernel_ms_per_step_probe": {k: round(v["total_ms"], 3) for k, v in probe.items()},
+                   "kernel_launches_per_step_probe": {k: v["launches"] for k, v in probe.items()}},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -94,89 +172,35 @@ def main():
     x_d = torch.zeros_like(b_d)
     torch.cuda.synchronize()
 
-    state = {}
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    runs = {}
+    for prec in (other, args.precision):          # the reported precision is timed last
+        runs[prec] = measure(args, p, lorax, torch, prec, sptr, val_d, b_d, x_d)
+    main_run, other_run = runs[args.precision], runs[other]
+    # error of the reported solutions against the other precision's (both at 1e-10 residual)
+    diff = np.linalg.norm(main_run["X"] - other_run["X"], axis=0) / np.linalg.norm(other_run["X"], axis=0)
 
-    def step():
-        F = lorax.Factor(p.row_ptr, p.col_idx, None, p.perm, p.leaf_ptr, p.depth, p.epsilon,
-                         stream=sptr, val_dev=val_d.data_ptr())
-        its, rr, st = F.gmres_dev(b_d.data_ptr(), x_d.data_ptr(), nrhs, tol=TOL,
-                                  restart=RESTART, maxit=500)
-        if st != lorax.LRX_OK or float(np.max(rr)) > TOL:
-            raise RuntimeError(f"GMRES did not reach {TOL}: status {st}, relres {rr}")
-        state["its"], state["rr"], state["stats"] = its, rr, F.stats()
-        F.free()
-
-    for _ in range(args.warmup):
-        step()
-    # find the dominant kernel class on an untimed step, then time only that one
-    lorax.timing_enable(None)
-    lorax.timing_read(reset=True)
-    step()
-    probe = lorax.timing_read(reset=True)
-    dom = max(probe, key=lambda k: probe[k]["total_ms"])
-    lorax.timing_enable([dom])
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timing = lorax.timing_read(reset=True)
-    lorax.timing_enable([])
-
-    # independent check of the last solution
-    A = p.scipy()
-    X = x_d.cpu().numpy().T
-    res = np.linalg.norm(A @ X - p.rhs, axis=0) / np.linalg.norm(p.rhs, axis=0)
-    if float(res.max()) > TOL:
-        raise RuntimeError(f"true residual {res.max():.3e} above {TOL}")
-
-    T = t1 - t0
-    ms_per_step = 1e3 * T / args.steps
-    value = nrhs * args.steps / T
-    d = timing[dom]
-    avg_ms = d["total_ms"] / max(d["launches"], 1)
-    if dom in ("solve_fwd", "solve_bwd", "spmv"):
-        per_launch = d["bytes"] / max(d["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    else:
-        per_launch = d["flops"] / max(d["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = avg_ms
-    roof["launches"] = d["launches"]
-
-    st = state["stats"]
     line = {
         "metric": "factor+GMRES solves/s at 1e-10 resid",
-        "value": value,
+        "value": main_run["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": p.n, "nnz": p.nnz, "depth": p.depth,
                    "leaf": 64, "epsilon": p.epsilon, "nrhs": nrhs, "gmres": f"FGMRES({RESTART})",
-                   "tol": TOL, "precision": "fp64", "compress": "svd"},
-        "roofline": roof,
-        "detail": {"gmres_iters": [int(i) for i in state["its"]],
-                   "true_relres_max": float(res.max()),
-                   "t_factor_ms": st["t_factor_ms"], "t_plan_ms": st["t_plan_ms"],
-                   "t_factor_sync_ms": st["t_sync_ms"], "t_solve_prog_ms": st["t_solve_prog_ms"],
-                   "factor_bytes": st["factor_bytes"], "solve_bytes": st["solve_bytes"],
-                   "mean_rank": st["mean_rank"], "max_rank": st["max_rank"],
-                   "kernel_ms_per_step_probe": {k: round(v["total_ms"], 3) for k, v in probe.items()},
-                   "kernel_launches_per_step_probe": {k: v["launches"] for k, v in probe.items()}},
+                   "tol": TOL, "precision": args.precision, "compress": "svd"},
+        "roofline": main_run["roofline"],
+        "detail": dict(main_run["detail"], **{
+            other: {"value": other_run["value"], "ms_per_step": other_run["ms_per_step"],
+                    "roofline": other_run["roofline"], **other_run["detail"]},
+            f"rel_diff_vs_{other}_solution_max": float(diff.max())}),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_side)

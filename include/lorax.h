@@ -46,7 +46,13 @@ typedef enum {
     LRX_EBUSY = 6       /* reserved */
 } lrx_status;
 
-typedef enum { LRX_FP64 = 0 } lrx_precision;
+/* LRX_FP64: every step in FP64.
+ * LRX_MIXED: the compression's reduced QRs and Jacobi SVD run in FP32 when
+ * epsilon >= 1e-5 (FP64 below), and the solve reads FP32 copies of the stored
+ * off-diagonal blocks (the FP64 factor is released after factorization); pivot
+ * inverses (computed and stored), Schur updates, vectors, accumulation in the
+ * solve and GMRES stay FP64, so GMRES refines the result to its FP64 tolerance. */
+typedef enum { LRX_FP64 = 0, LRX_MIXED = 1 } lrx_precision;
 typedef enum { LRX_COLORED = 0, LRX_NATURAL = 1 } lrx_order;
 typedef enum { LRX_SVD = 0, LRX_RRQR = 1 } lrx_compress;
 
@@ -142,6 +148,16 @@ lrx_status lrx_solve(lrx_handle h, int32_t nrhs, const double* b, int64_t ldb,
 /* Same on device memory, enqueued on the handle's stream, no host sync.
  * b and x are n x nrhs with leading dimension n, column-major, may not alias. */
 lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev);
+
+/* Batched form of lrx_solve_dev: k distinct handles on the same device, nrhs
+ * right-hand sides each; b_dev[i], x_dev[i] are n_i x nrhs
+ * column-major in HBM.  Every (level, colour) step of the sweeps is one launch
+ * over the nodes of all k factorizations (their steps are independent), on the
+ * stream of hs[0]; FP64 and mixed-precision handles may share a batch.
+ * Synchronous: returns when every x_dev[i] is written.  Each result equals the
+ * one lrx_solve_dev gives for that handle alone. */
+lrx_status lrx_solve_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                               double* const* x_dev);
 
 /* GMRES(restart) with the solve as right preconditioner, x_0 = 0, for nrhs
  * right-hand sides (host, column-major, leading dimension n).  A must be the

@@ -111,8 +111,9 @@ constexpr int kSwData = 17408;         // doubles of LDS for buffers and staged 
 constexpr int kSwKS = 8;               // row stride of vector buffers in LDS (max RHS per launch)
 
 struct SwNode {
-    int64_t desc;        // word offset of stage 0's descriptor block
-    int32_t words0;      // its size in words
+    const int32_t* desc; // stage 0's descriptor block (device)
+    double* x;           // extended vector of this node's system (nullptr: the launch's)
+    int32_t words0;      // size of stage 0's block in words
     int32_t nstage;
 };
 
@@ -130,15 +131,15 @@ struct SwGroup {         // 4 words: comps [comp0, comp0 + ncomp), rows summed
     int32_t lglanes;     // log2 of the lanes that share one row's dot products
 };
 
-// Matrix run set: nrun runs of len doubles, run t at src + t * ld, stored in LDS
-// at lds + t * dld.  Vector run set (src == nullptr): nrun rows of x, row t is
-// x row (map < 0 ? ld + t : map[t]), the launch's right-hand sides, stored at
-// lds + t * kSwKS.
+// Matrix run set: nrun runs of len elements, run t at src + t * ld (elements of
+// es bytes: FP64, or FP32 for the off-diagonal blocks in mixed precision),
+// stored in LDS as doubles at lds + t * dld.  Vector run set (src == nullptr): nrun rows of x, row t is x row (map < 0
+// ? ld + t : map[t]), the launch's right-hand sides, stored at lds + t * kSwKS.
 struct SwRun {           // 10 words
-    const double* src;
+    const void* src;
     int32_t ld, len, nrun, map, lds, dld;
     float rlen;          // 1 / len (index split without integer division)
-    int32_t pad_;
+    int32_t es;          // bytes per element of src: 8 (FP64) or 4 (FP32)
 };
 
 // One row computation: for each row a < nr of the block at LDS `mat`
@@ -152,6 +153,13 @@ struct SwComp {          // 12 words
     int32_t init, init_map;
     int32_t out, out_map;
     int32_t gbase, gmap;
+};
+
+// FP64 -> FP32 copy of one stored block (mixed precision)
+struct DConv {
+    const double* src;
+    float* dst;
+    int64_t n;
 };
 
 }  // namespace lrx

@@ -436,8 +436,14 @@ __device__ __forceinline__ double dpp_mov(double v) {
     return __hiloint2double(hi, lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Sum over the 16 lanes of a DPP row; every lane receives the same value.
-__device__ __forceinline__ double row16_sum(double v) {
+template <class T>
+__device__ __forceinline__ T row16_sum(T v) {
     v += dpp_mov<0xB1>(v);     // quad_perm [1,0,3,2]
     v += dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]
     v += dpp_mov<0x141>(v);    // row_half_mirror
@@ -478,9 +484,9 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 // major, leading dimension ld, c <= 64).  On exit R is the upper triangle;
 // reflector j is H_j = I - tau_j v v^T with v = (v0_j, A[j+1.., j]) acting on
 // rows j..nr-1; perm[j] is the original column now at position j (pivot only).
-// P: SEGC x WAVE doubles, NV: SEGC doubles of LDS scratch.
-__device__ void qr64(double* A, int nr, int c, int ld, bool pivot, int* perm, double* hv0,
-                     double* htau, double* P, double* NV) {
+// P: SEGC x WAVE, NV: SEGC elements of LDS scratch.  T: arithmetic type.
+template <class T>
+__device__ void qr64(T* A, int nr, int c, int ld, bool pivot, int* perm, T* hv0, T* htau, T* P, T* NV) {
     const int tid = threadIdx.x, k = tid % WAVE, s = tid / WAVE;
     const int kmax = min(nr, c);
     if (pivot) {
@@ -491,24 +497,24 @@ __device__ void qr64(double* A, int nr, int c, int ld, bool pivot, int* perm, do
         // first row > j of this segment (rows i = s mod SEGC)
         const int i0 = j + 1 + ((s - (j + 1)) % SEGC + SEGC) % SEGC;
         if (pivot) {
-            double q = 0.0;
+            T q = 0.0;
             if (k >= j && k < c) {
                 for (int i = j + ((s - j) % SEGC + SEGC) % SEGC; i < nr; i += SEGC) {   // rows >= j
-                    const double x = A[i + k * ld];
+                    const T x = A[i + k * ld];
                     q += x * x;
                 }
             }
             P[s * WAVE + k] = q;
             __syncthreads();
-            double nk = -1.0;
+            T nk = -1.0;
             if (k >= j && k < c) {
                 nk = 0.0;
                 for (int t = 0; t < SEGC; ++t) nk += P[t * WAVE + k];
             }
             int bi = k;
-            double bv = nk;
+            T bv = nk;
             for (int o = WAVE / 2; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o);
+                const T ov = __shfl_xor(bv, o);
                 const int oi = __shfl_xor(bi, o);
                 if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
             }
@@ -516,7 +522,7 @@ __device__ void qr64(double* A, int nr, int c, int ld, bool pivot, int* perm, do
             if (bi != j) {
                 if (k == j)
                     for (int i = s; i < nr; i += SEGC) {
-                        const double a = A[i + j * ld];
+                        const T a = A[i + j * ld];
                         A[i + j * ld] = A[i + bi * ld];
                         A[i + bi * ld] = a;
                     }
@@ -529,30 +535,33 @@ __device__ void qr64(double* A, int nr, int c, int ld, bool pivot, int* perm, do
             }
         }
         // phase 1: partial products of column j with the columns to its right
-        const double ajj = A[j + j * ld];
-        const double ajk = k < c ? A[j + k * ld] : 0.0;
-        double p1 = 0.0, nv = 0.0;
+        const T ajj = A[j + j * ld];
+        const T ajk = k < c ? A[j + k * ld] : 0.0;
+        T p1 = 0.0, nv = 0.0;
         for (int i = i0; i < nr; i += SEGC) {
-            const double vi = A[i + j * ld];
+            const T vi = A[i + j * ld];
             nv += vi * vi;
             if (k > j && k < c) p1 += vi * A[i + k * ld];
         }
         P[s * WAVE + k] = p1;
         if (k == 0) NV[s] = nv;
         __syncthreads();
-        // phase 2: reflector and update
-        double nvt = 0.0;
+        // phase 2: reflector and update.  A column whose squared norm below the
+        // diagonal is at the bottom of T's range (denormal in FP32) is taken as
+        // zero: 1 / (s2 + |ajj| xn) would overflow.  Callers scale A to max |A| < 1.
+        const T tiny_sq = sizeof(T) == 4 ? (T)1e-30 : (T)1e-280;
+        T nvt = 0.0;
         for (int t = 0; t < SEGC; ++t) nvt += NV[t];
-        double tau = 0.0, v0 = 0.0, alpha = ajj;
-        if (nvt > 0.0) {
-            const double s2 = ajj * ajj + nvt;
-            const double xn = sqrt(s2);
+        T tau = 0.0, v0 = 0.0, alpha = ajj;
+        if (nvt > tiny_sq) {
+            const T s2 = ajj * ajj + nvt;
+            const T xn = sqrt(s2);
             alpha = -copysign(xn, ajj);
             v0 = ajj - alpha;
             tau = 1.0 / (s2 + fabs(ajj) * xn);
         }
         if (tau != 0.0 && k > j && k < c) {
-            double w = v0 * ajk;
+            T w = v0 * ajk;
             for (int t = 0; t < SEGC; ++t) w += P[t * WAVE + k];
             w *= tau;
             if (s == 0) A[j + k * ld] = ajk - w * v0;
@@ -567,45 +576,62 @@ __device__ void qr64(double* A, int nr, int c, int ld, bool pivot, int* perm, do
     }
 }
 
+// T = float: the reduced QRs and Jacobi in FP32 (mixed precision); B, the
+// projection B V and all outputs stay FP64.
+template <class F>
 __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
-                                                        const int32_t* __restrict__ imap, int cap) {
+                                                        const int32_t* __restrict__ imap, int cap_d) {
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
-    extern __shared__ double sm[];
+    extern __shared__ double sm_d[];
+    F* sm = reinterpret_cast<F*>(sm_d);
+    const int cap = cap_d * (int)(sizeof(double) / sizeof(F));
     __shared__ int s_perm[WAVE];
     __shared__ int s_rot;
     if (M == 0 || c == 0) {
         if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; }
         return;
     }
-    double* P = sm;                          // SEGC x WAVE
-    double* NV = P + SEGC * WAVE;            // SEGC
-    double* hv0 = NV + SEGC;                 // WAVE
-    double* htau = hv0 + WAVE;               // WAVE
-    double* sv = htau + WAVE;                // WAVE
-    double* region = sv + WAVE;
+    F* P = sm;                               // SEGC x WAVE
+    F* NV = P + SEGC * WAVE;                 // SEGC
+    F* hv0 = NV + SEGC;                      // WAVE
+    F* htau = hv0 + WAVE;                    // WAVE
+    F* sv = htau + WAVE;                     // WAVE
+    F* region = sv + WAVE;
     const int reg = cap - (SEGC * WAVE + SEGC + 3 * WAVE);
     const int ldc = c | 1;
-    double* X = region + reg - c * ldc;      // c x c, kept to the end
+    F* X = region + reg - c * ldc;           // c x c, kept to the end
     // ---- assemble B (column-major, ld M) in global memory; it stays for the projection
     double* __restrict__ B = T.B;
     for (int64_t e = tid; e < (int64_t)M * c; e += NTC) B[e] = 0.0;
     __syncthreads();
+    double amax = 0.0;
     for (int q = 0; q < T.npieces; ++q) {
         const DPiece pc = pieces[T.piece0 + q];
         const int nr = pc.blk.nr, nc = pc.blk.nc;
         for (int e = tid; e < nr * nc; e += NTC) {
             const int a = e % nr, b = e / nr;
             const double v = pc.blk.p[e];
+            amax = fmax(amax, fabs(v));
             if (!pc.trans) B[(pc.row0 + a) + (int64_t)imap_at(imap, pc.map, b) * M] = v;
             else           B[(pc.row0 + b) + (int64_t)imap_at(imap, pc.map, a) * M] = v;
         }
     }
+    // the factorization works on B / 2^e with max |B / 2^e| in [0.5, 1), so squared
+    // column norms and their products stay inside the range of F; singular values
+    // are scaled back exactly, V does not change
+    __shared__ double s_amax[SEGC];
+    for (int o = WAVE / 2; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    if (tid % WAVE == 0) s_amax[tid / WAVE] = amax;
     __syncthreads();
+    amax = 0.0;
+    for (int t = 0; t < SEGC; ++t) amax = fmax(amax, s_amax[t]);
+    const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
+    const double inv_scale = ldexp(1.0, -bexp), scale = ldexp(1.0, bexp);
     // ---- 1. QR of B through LDS chunks: [R (c rows); next rows of B]
     {
-        double* A = region;
+        F* A = region;
         const int rows_cap = (reg - c * ldc) / c - 1;
         const int ldA = rows_cap | 1;
         int r0 = 0, nrA = 0;
@@ -621,7 +647,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
             }
             for (int e = tid; e < nnew * c; e += NTC) {
                 const int k = e / nnew, i = e - k * nnew;
-                A[top + i + k * ldA] = B[(r0 + i) + (int64_t)k * M];
+                A[top + i + k * ldA] = (F)(B[(r0 + i) + (int64_t)k * M] * inv_scale);
             }
             nrA = top + nnew;
             __syncthreads();
@@ -639,8 +665,8 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     // ---- 2. R0 P = Q1 R1
     qr64(X, c, c, ldc, true, s_perm, hv0, htau, P, NV);
     // ---- 3. R1^T = Q2 R2 (A2 after W in the region); L = R2^T into X
-    double* W = region;
-    double* A2 = region + c * ldc;
+    F* W = region;
+    F* A2 = region + c * ldc;
     for (int e = tid; e < c * c; e += NTC) {
         const int i = e % c, k = e / c;
         A2[i + k * ldc] = (k <= i) ? X[k + i * ldc] : 0.0;
@@ -657,18 +683,18 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     {
         const int k = tid % WAVE, sg = tid / WAVE;
         for (int j = c - 1; j >= 0; --j) {
-            const double tau = htau[j];
-            if (tau == 0.0) continue;                // uniform: H_j = I
+            const F tau = htau[j];
+            if (tau == (F)0) continue;               // uniform: H_j = I
             const int i0 = j + 1 + ((sg - (j + 1)) % SEGC + SEGC) % SEGC;
-            const double v0 = hv0[j];
-            double p1 = 0.0;
-            const double wjk = k < c ? W[j + k * ldc] : 0.0;
+            const F v0 = hv0[j];
+            F p1 = 0;
+            const F wjk = k < c ? W[j + k * ldc] : (F)0;
             if (k < c)
                 for (int i = i0; i < c; i += SEGC) p1 += A2[i + j * ldc] * W[i + k * ldc];
             P[sg * WAVE + k] = p1;
             __syncthreads();
             if (k < c) {
-                double w = v0 * wjk;
+                F w = v0 * wjk;
                 for (int t = 0; t < SEGC; ++t) w += P[t * WAVE + k];
                 w *= tau;
                 if (sg == 0) W[j + k * ldc] = wjk - w * v0;
@@ -681,19 +707,22 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     {
         const int n2 = c + (c & 1), npair = n2 / 2;
         const int g = tid / 16, gl = tid % 16;
-        const double tol = 4.0e-16 * (double)c;
+        // rotation threshold ~3.6 c u and rounding-level columns (u: unit roundoff of F)
+        const F u = sizeof(F) == 8 ? (F)1.1102230246251565e-16 : (F)5.9604645e-8;
+        const F tol = (F)3.6 * u * (F)c;
         double f = 0.0;
         for (int e = tid; e < c * c; e += NTC) {
             const int i = e % c, k = e / c;
-            const double x = X[i + k * ldc];
+            const double x = (double)X[i + k * ldc];
             f += x * x;
         }
         f = wave_sum(f);
-        if (tid % WAVE == 0) P[tid / WAVE] = f;
+        __shared__ double s_fro[SEGC];
+        if (tid % WAVE == 0) s_fro[tid / WAVE] = f;
         __syncthreads();
         double fro = 0.0;
-        for (int t = 0; t < SEGC; ++t) fro += P[t];
-        const double tiny2 = 1e-30 * fro;
+        for (int t = 0; t < SEGC; ++t) fro += s_fro[t];
+        const F tiny2 = (F)(81.0 * (double)u * (double)u * fro);
         constexpr int EPL = WAVE / 16;             // elements per lane (c <= 64)
         for (int sweep = 0; sweep < 40; ++sweep) {
             if (tid == 0) s_rot = 0;
@@ -704,13 +733,13 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
                     const int b = g == 0 ? n2 - 1 : (t - g + n2 - 1) % (n2 - 1);
                     const int p = a < b ? a : b, q = a < b ? b : a;
                     const bool act = q < c;
-                    double xp[EPL], xq[EPL];
-                    double al = 0.0, be = 0.0, ga = 0.0;
+                    F xp[EPL], xq[EPL];
+                    F al = 0, be = 0, ga = 0;
 #pragma unroll
                     for (int u = 0; u < EPL; ++u) {
                         const int r = gl + 16 * u;
-                        xp[u] = (act && r < c) ? X[r + p * ldc] : 0.0;
-                        xq[u] = (act && r < c) ? X[r + q * ldc] : 0.0;
+                        xp[u] = (act && r < c) ? X[r + p * ldc] : (F)0;
+                        xq[u] = (act && r < c) ? X[r + q * ldc] : (F)0;
                         al += xp[u] * xp[u];
                         be += xq[u] * xq[u];
                         ga += xp[u] * xq[u];
@@ -718,17 +747,17 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
                     al = row16_sum(al);
                     be = row16_sum(be);
                     ga = row16_sum(ga);
-                    if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al * be) && al > tiny2 && be > tiny2) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                    if (act && ga != (F)0 && fabs(ga) > tol * sqrt(al * be) && al > tiny2 && be > tiny2) {
+                        const F zeta = (be - al) / ((F)2 * ga);
+                        const F tt = copysign((F)1, zeta) / (fabs(zeta) + sqrt((F)1 + zeta * zeta));
+                        const F cs = (F)1 / sqrt((F)1 + tt * tt), sn = cs * tt;
 #pragma unroll
                         for (int u = 0; u < EPL; ++u) {
                             const int r = gl + 16 * u;
                             if (r < c) {
                                 X[r + p * ldc] = cs * xp[u] - sn * xq[u];
                                 X[r + q * ldc] = sn * xp[u] + cs * xq[u];
-                                const double wp = W[r + p * ldc], wq = W[r + q * ldc];
+                                const F wp = W[r + p * ldc], wq = W[r + q * ldc];
                                 W[r + p * ldc] = cs * wp - sn * wq;
                                 W[r + q * ldc] = sn * wp + cs * wq;
                             }
@@ -744,23 +773,25 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
         }
     }
     // ---- singular values, order, rank, V = P W
+    __shared__ double s_sv[WAVE];
     for (int k = tid / WAVE; k < c; k += SEGC) {
         double s2 = 0.0;
-        for (int r = tid % WAVE; r < c; r += WAVE) { const double x = X[r + k * ldc]; s2 += x * x; }
+        for (int r = tid % WAVE; r < c; r += WAVE) { const double x = (double)X[r + k * ldc]; s2 += x * x; }
         s2 = wave_sum(s2);
-        if (tid % WAVE == 0) sv[k] = sqrt(s2);
+        if (tid % WAVE == 0) s_sv[k] = sqrt(s2) * scale;
     }
     __syncthreads();
-    for (int k = tid; k < c; k += NTC) T.tails[1 + desc_pos(sv, c, k)] = sv[k];
+    (void)sv;
+    for (int k = tid; k < c; k += NTC) T.tails[1 + desc_pos(s_sv, c, k)] = s_sv[k];
     double smax = 0.0;
-    for (int k = 0; k < c; ++k) smax = fmax(smax, sv[k]);
+    for (int k = 0; k < c; ++k) smax = fmax(smax, s_sv[k]);
     int r = 0;
     if (smax > 0.0)
-        for (int k = 0; k < c; ++k) r += (sv[k] >= T.eps * smax) ? 1 : 0;
+        for (int k = 0; k < c; ++k) r += (s_sv[k] >= T.eps * smax) ? 1 : 0;
     for (int e = tid; e < c * c; e += NTC) {
         const int a = e % c, k = e / c;
-        const int pos = desc_pos(sv, c, k);
-        if (pos < r) T.V[s_perm[a] + (size_t)pos * c] = W[a + k * ldc];
+        const int pos = desc_pos(s_sv, c, k);
+        if (pos < r) T.V[s_perm[a] + (size_t)pos * c] = (double)W[a + k * ldc];
     }
     if (tid == 0) {
         T.tails[0] = smax;
@@ -1099,12 +1130,14 @@ __device__ __forceinline__ void sw_copy(const SwRun* runs, int nrun, const int32
     if (nrun == 0 || threadIdx.x >= elems) return;
     int ri = 0, rstart = 0;
     // current run
-    const double* src = nullptr;
+    const void* src = nullptr;
+    bool f32 = false;
     int len = 0, ld = 0, dld = 0, lds = 0, map = -1, cnt = 0, q = 0, r = 0;
     int t = 0, a = 0;                         // position of element g inside the run
     auto load_run = [&](int g) {
         const SwRun& R = runs[ri];
         src = R.src;
+        f32 = R.es == 4;
         map = R.map;
         lds = R.lds;
         if (src) { len = R.len; ld = R.ld; dld = R.dld; }
@@ -1140,7 +1173,8 @@ __device__ __forceinline__ void sw_copy(const SwRun* runs, int nrun, const int32
                     load_run(g);
                 }
                 if (src) {
-                    v[u] = src[(int64_t)t * ld + a];
+                    const int64_t o = (int64_t)t * ld + a;
+                    v[u] = f32 ? (double)static_cast<const float*>(src)[o] : static_cast<const double*>(src)[o];
                 } else {
                     const int row = map < 0 ? ld + t : D[map + t];
                     v[u] = x[(int64_t)row * ldx + a];
@@ -1217,9 +1251,10 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
 
 // One work-group per super-node of a colour step; x is the extended vector
 // (row-interleaved, ldx right-hand sides), this launch treats [k0, k0 + NK).
+// Each run states the storage type of its block (FP64, or FP32 for off-diagonal
+// blocks in mixed precision); LDS, vectors and accumulation stay FP64.
 template <int NK>
 __global__ __launch_bounds__(kSwThreads) void k_sweep(const SwNode* __restrict__ nodes,
-                                                      const int32_t* __restrict__ prog,
                                                       double* __restrict__ x, int ldx, int k0) {
     extern __shared__ double smem[];
     int32_t* Dbuf = reinterpret_cast<int32_t*>(smem);
@@ -1227,9 +1262,10 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const SwNode* __restrict__
     const int tid = threadIdx.x;
     const SwNode nd = nodes[blockIdx.x];
     if (nd.nstage == 0) return;
-    const int32_t* src = prog + nd.desc;
+    const int32_t* src = nd.desc;
     for (int w = tid; w < nd.words0; w += kSwThreads) Dbuf[w] = src[w];
     src += nd.words0;
+    if (nd.x) x = nd.x;
     x += k0;
     __syncthreads();
     for (int s = 0; s < nd.nstage; ++s) {
@@ -1417,19 +1453,26 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 }
 
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, int max_M, hipStream_t st) {
+                               int max_c, int max_M, bool fp32, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (max_c <= 64) {
         static bool attr64 = false;
         if (!attr64) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_compress_svd64,
+            hipError_t e = hipFuncSetAttribute((const void*)k_compress_svd64<double>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void*)k_compress_svd64<float>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
             if (e != hipSuccess) return e;
             attr64 = true;
         }
-        const int cap = (kLdsBudget - 2048) / (int)sizeof(double);   // static LDS of the kernel aside
-        hipLaunchKernelGGL(k_compress_svd64, dim3(n), dim3(NTC), (size_t)cap * sizeof(double), st, t, pieces,
-                           imap, cap);
+        const int cap = (kLdsBudget - 4096) / (int)sizeof(double);   // static LDS of the kernel aside
+        if (fp32)
+            hipLaunchKernelGGL(k_compress_svd64<float>, dim3(n), dim3(NTC), (size_t)cap * sizeof(double), st, t,
+                               pieces, imap, cap);
+        else
+            hipLaunchKernelGGL(k_compress_svd64<double>, dim3(n), dim3(NTC), (size_t)cap * sizeof(double), st, t,
+                               pieces, imap, cap);
         return hipGetLastError();
     }
     // LDS plan: R and V (2 c^2) plus a chunk of ch rows of B (ch c), within the
@@ -1490,7 +1533,7 @@ hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int 
 }
 
 template <int NK>
-hipError_t launch_sweep_nk(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,
+hipError_t launch_sweep_nk(const SwNode* nodes, int n, double* x, int ldx, int k0,
                            hipStream_t st) {
     constexpr size_t lds = (size_t)kSwDescWords * 2 * sizeof(int32_t) + (size_t)kSwData * sizeof(double);
     static bool attr = false;
@@ -1500,20 +1543,31 @@ hipError_t launch_sweep_nk(const SwNode* nodes, int n, const int32_t* prog, doub
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_sweep<NK>, dim3(n), dim3(kSwThreads), lds, st, nodes, prog, x, ldx, k0);
+    hipLaunchKernelGGL(k_sweep<NK>, dim3(n), dim3(kSwThreads), lds, st, nodes, x, ldx, k0);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,
-                        int nk, hipStream_t st) {
+hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, hipStream_t st) {
     if (n == 0) return hipSuccess;
     switch (nk) {
-        case 8: return launch_sweep_nk<8>(nodes, n, prog, x, ldx, k0, st);
-        case 4: return launch_sweep_nk<4>(nodes, n, prog, x, ldx, k0, st);
-        case 2: return launch_sweep_nk<2>(nodes, n, prog, x, ldx, k0, st);
-        case 1: return launch_sweep_nk<1>(nodes, n, prog, x, ldx, k0, st);
+        case 8: return launch_sweep_nk<8>(nodes, n, x, ldx, k0, st);
+        case 4: return launch_sweep_nk<4>(nodes, n, x, ldx, k0, st);
+        case 2: return launch_sweep_nk<2>(nodes, n, x, ldx, k0, st);
+        case 1: return launch_sweep_nk<1>(nodes, n, x, ldx, k0, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// dst[e] = (float) src[e] for every segment (one work-group per segment)
+__global__ void k_to_f32(const DConv* __restrict__ segs) {
+    const DConv S = segs[blockIdx.x];
+    for (int64_t e = threadIdx.x; e < S.n; e += blockDim.x) S.dst[e] = (float)S.src[e];
+}
+
+hipError_t launch_to_f32(const DConv* segs, int n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3(n), dim3(256), 0, st, segs);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather_perm(const double* b, int64_t ldb, const int32_t* perm, int n, int nrhs,

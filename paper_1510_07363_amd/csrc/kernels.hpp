@@ -24,8 +24,9 @@ hipError_t launch_count_nonfinite(const double* v, int64_t n, int64_t* cnt, hipS
 // lds_bytes: dynamic LDS per work-group
 hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                            int max_c, hipStream_t st);
+// fp32: reduced QRs and Jacobi in FP32 when every task has c <= 64 (mixed precision)
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, int max_M, hipStream_t st);
+                               int max_c, int max_M, bool fp32, hipStream_t st);
 // Projection, rewiring and pivot inverse per task (DPrep); info[slot] = 1 for an
 // exactly singular pivot.
 hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,
@@ -36,8 +37,12 @@ hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int 
 
 // One sweep launch (forward or backward program) over n super-nodes of a
 // colour step, right-hand sides [k0, k0 + nk) of x (ldx per row), nk in {1,2,4,8}.
-hipError_t launch_sweep(const SwNode* nodes, int n, const int32_t* prog, double* x, int ldx, int k0,
-                        int nk, hipStream_t st);
+// Nodes with x == nullptr use x; each node's program is its own device pointer
+// and each run states its blocks' storage type, so nodes of several
+// factorizations (FP64 or mixed precision) can share one launch.
+hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, hipStream_t st);
+// FP64 -> FP32 copies of stored blocks (DConv), one work-group per block.
+hipError_t launch_to_f32(const DConv* segs, int n, hipStream_t st);
 
 // ---- vectors: layout v[i * nrhs + k] ("row-interleaved") -------------------
 // xt[t*nrhs + k] = b[perm[t] + k*ldb]   (t < n)      and zero xt[n*nrhs .. ntot*nrhs)

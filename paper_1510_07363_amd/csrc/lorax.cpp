@@ -93,7 +93,13 @@ struct Arena {
     size_t used = 0;                                  // in the last chunk
     int64_t total = 0;                                // doubles handed out
     int64_t budget_bytes = 0;
-    ~Arena() { for (auto& c : chunks) (void)hipFree(c.first); }
+    ~Arena() { release(); }
+    void release() {
+        for (auto& c : chunks) (void)hipFree(c.first);
+        chunks.clear();
+        used = 0;
+        total = 0;
+    }
     double* alloc(size_t n) {
         n = (n + 31) & ~(size_t)31;                   // 256-byte aligned blocks
         if (chunks.empty() || used + n > chunks.back().second) {
@@ -136,6 +142,7 @@ struct NodeMaps {
 
 struct SolveStep {
     int32_t node0 = 0, nnode = 0;
+    int32_t height = 0, colour = 0;         // level above the leaves, colour inside the level
     int64_t bytes_fwd = 0, bytes_bwd = 0;   // algorithmic bytes of one launch (one right-hand side)
 };
 
@@ -212,6 +219,8 @@ struct lrx_handle_s {
     DevBuf d_imap;                 // factor maps
     // solve program (staged node programs of both sweeps)
     DevBuf d_swnodes, d_swprog;
+    std::vector<SwNode> sw_host;   // host copy of d_swnodes (forward nodes, then backward)
+    DevBuf batch_nodes;            // node lists of batched solves led by this handle
     int32_t sw_nnode = 0;
     int64_t sw_stages = 0, sw_words = 0;
     std::vector<SolveStep> ssteps;
@@ -229,6 +238,9 @@ struct lrx_handle_s {
     std::vector<int64_t> tail_off;
     double max_tail_ratio = 0.0;
     double t_sync_ms = 0.0, t_solve_prog_ms = 0.0;
+    int32_t precision = LRX_FP64;
+    bool solve_fp32 = false;       // the solve reads FP32 copies of the stored blocks
+    Arena arena32;                 // those copies (mixed precision)
 };
 
 namespace {
@@ -428,6 +440,9 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
         HIPCHK(hipMemsetAsync(d_info.p, 0, std::max(npiv, 1) * sizeof(int32_t), st));
     }
     int64_t flops = 0;
+    // mixed precision: the reduced QRs and Jacobi of the compression in FP32
+    // when FP32 resolves the cut-off (sigma_k / sigma_0 >= epsilon >= 1e-5)
+    const bool fp32_compress = h->precision == LRX_MIXED && h->epsilon >= 1e-5;
     for (size_t li = 0; li < P.levels.size(); ++li) {
         const LevelPlan& L = P.levels[li];
         if (L.level < P.depth) {
@@ -567,7 +582,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 if (use_svd)
                     HIPCHK(launch_compress_svd((const DCompress*)(d_desc_c.as<char>() + o1), nn,
                                                (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c,
-                                               max_M, st));
+                                               max_M, fp32_compress, st));
                 else
                     HIPCHK(launch_compress((const DCompress*)(d_desc_c.as<char>() + o1), nn,
                                            (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c, st));
@@ -790,6 +805,48 @@ void build_solve_program(lrx_handle h) {
         }
     h->n_ext = off;
 
+    // mixed precision: the solve reads FP32 copies of every block it uses (pivot
+    // inverses and frozen edges); the FP64 factor is released afterwards
+    const bool f32 = h->precision == LRX_MIXED;
+    const int32_t es = f32 ? 4 : 8;
+    std::vector<const void*> sptr(P.edges.size(), nullptr);
+    if (f32) {
+        std::vector<char> usedf(P.edges.size(), 0), pivf(P.edges.size(), 0);
+        for (const ColourStep& cs : P.steps)
+            for (const NodeStep& ns : cs.nodes)
+                for (const PivotPlan* pp : {&ns.ps, &ns.pb}) {
+                    if (pp->e_self >= 0) pivf[pp->e_self] = 1;
+                    for (int32_t e : pp->out_edges) usedf[e] = 1;
+                    for (int32_t e : pp->in_edges) usedf[e] = 1;
+                }
+        std::vector<DConv> segs;
+        for (size_t e = 0; e < P.edges.size(); ++e) {
+            if ((!usedf[e] && !pivf[e]) || !h->eptr[e]) continue;
+            const PEdge& E = P.edges[e];
+            const int64_t cnt = (int64_t)dim_of(E.rows, h->size[E.dst]) * dim_of(E.cols, h->size[E.src]);
+            if (cnt <= 0) continue;
+            if (pivf[e]) {                 // pivot inverses stay FP64
+                double* d = h->arena32.alloc((size_t)cnt);
+                HIPCHK(hipMemcpyAsync(d, h->eptr[e], (size_t)cnt * 8, hipMemcpyDeviceToDevice, h->stream));
+                sptr[e] = d;
+                continue;
+            }
+            float* d = (float*)h->arena32.alloc((size_t)(cnt + 1) / 2);
+            segs.push_back(DConv{h->eptr[e], d, cnt});
+            sptr[e] = d;
+        }
+        DevBuf dsegs;
+        dsegs.ensure(std::max<size_t>(segs.size(), 1) * sizeof(DConv));
+        if (!segs.empty()) {
+            HIPCHK(hipMemcpy(dsegs.p, segs.data(), segs.size() * sizeof(DConv), hipMemcpyHostToDevice));
+            HIPCHK(launch_to_f32(dsegs.as<DConv>(), (int)segs.size(), h->stream));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->solve_fp32 = true;
+    } else {
+        for (size_t e = 0; e < P.edges.size(); ++e) sptr[e] = h->eptr[e];
+    }
+
     // per super-node (in colour-step order): the intermediate form of both
     // pivots with their frozen out-edges (forward) and in-edges (backward), then
     // its two programs; nodes are independent, so host threads share them
@@ -804,7 +861,7 @@ void build_solve_program(lrx_handle h) {
     const size_t nn = refs.size();
     struct NodeOut {
         std::vector<int32_t> words;
-        SwNode f{}, b{};
+        SwNodeRel f{}, b{};
         int64_t bytes_fwd = 0, bytes_bwd = 0, solve_bytes = 0;
         std::string err;
     };
@@ -819,14 +876,14 @@ void build_solve_program(lrx_handle h) {
             D.node = v;
             D.m = pp.e_self >= 0 ? h->size[v] : 0;
             D.off = h->var_off[v];
-            D.inv = pp.e_self >= 0 ? h->eptr[pp.e_self] : nullptr;
+            D.inv = pp.e_self >= 0 ? sptr[pp.e_self] : nullptr;
             o.solve_bytes += 2ll * D.m * D.m * 8;
             for (int pass = 0; pass < 2; ++pass) {
                 const auto& list = pass == 0 ? pp.out_edges : pp.in_edges;
                 for (int32_t e : list) {
                     const PEdge& E = P.edges[e];
                     SwEdgeIR s;
-                    s.E = h->eptr[e];
+                    s.E = sptr[e];
                     s.nr = dim_of(E.rows, h->size[E.dst]);
                     s.nc = dim_of(E.cols, h->size[E.src]);
                     if ((int64_t)s.nr * s.nc == 0) continue;
@@ -834,20 +891,22 @@ void build_solve_program(lrx_handle h) {
                     s.other_off = h->var_off[s.other];
                     s.rows = local(E.rows);
                     s.cols = local(E.cols);
-                    o.solve_bytes += (int64_t)s.nr * s.nc * 8;
+                    o.solve_bytes += (int64_t)s.nr * s.nc * es;
                     (pass == 0 ? D.out : D.in).push_back(std::move(s));
                 }
             }
             return D;
         };
         SwNodeIR d;
+        d.es = es;
+        d.es_piv = 8;
         d.s = piv(ns.ps);
         d.b = piv(ns.pb);
         for (const SwPivIR* pv : {&d.s, &d.b}) {
             const int64_t pivb = (int64_t)pv->m * pv->m * 8;
             int64_t ob = 0, ib = 0;
-            for (auto& e : pv->out) ob += (int64_t)e.nr * e.nc * 8;
-            for (auto& e : pv->in) ib += (int64_t)e.nr * e.nc * 8;
+            for (auto& e : pv->out) ob += (int64_t)e.nr * e.nc * es;
+            for (auto& e : pv->in) ib += (int64_t)e.nr * e.nc * es;
             o.bytes_fwd += pivb + ob;
             o.bytes_bwd += pivb + ib;
         }
@@ -872,7 +931,7 @@ void build_solve_program(lrx_handle h) {
     }
     int64_t solve_bytes = 0;
     std::vector<int32_t> words;
-    std::vector<SwNode> both(2 * nn);
+    std::vector<SwNodeRel> both(2 * nn);
     for (size_t i = 0; i < nn; ++i) {
         NodeOut& o = outs[i];
         if (!o.err.empty()) fail(LRX_EDEVICE, o.err);
@@ -891,12 +950,26 @@ void build_solve_program(lrx_handle h) {
     }
     h->d_swnodes.ensure(std::max<size_t>(2 * nn, 1) * sizeof(SwNode));
     h->d_swprog.ensure(std::max<size_t>(words.size(), 1) * sizeof(int32_t));
-    if (nn) HIPCHK(hipMemcpy(h->d_swnodes.p, both.data(), both.size() * sizeof(SwNode), hipMemcpyHostToDevice));
     if (!words.empty())
         HIPCHK(hipMemcpy(h->d_swprog.p, words.data(), words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    h->sw_host.resize(2 * nn);
+    for (size_t i = 0; i < 2 * nn; ++i)
+        h->sw_host[i] = SwNode{h->d_swprog.as<int32_t>() + both[i].desc, nullptr, both[i].words0, both[i].nstage};
+    if (nn)
+        HIPCHK(hipMemcpy(h->d_swnodes.p, h->sw_host.data(), h->sw_host.size() * sizeof(SwNode),
+                         hipMemcpyHostToDevice));
+    for (size_t si = 0; si < P.steps.size(); ++si) {
+        h->ssteps[si].height = P.depth - P.steps[si].level;
+        h->ssteps[si].colour = P.steps[si].colour;
+    }
     h->sw_words = (int64_t)words.size();
     h->sw_nnode = (int32_t)nn;
     h->stats.solve_bytes = solve_bytes;
+    if (h->solve_fp32) {               // the FP64 blocks are no longer read
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->arena.release();
+        std::fill(h->eptr.begin(), h->eptr.end(), nullptr);
+    }
     h->t_solve_prog_ms = now_ms() - t_begin;
 }
 
@@ -905,17 +978,16 @@ void sweeps(lrx_handle h, double* xe, int nrhs) {
     const hipStream_t st = h->stream;
     const SwNode* fwd = h->d_swnodes.as<SwNode>();
     const SwNode* bwd = fwd + h->sw_nnode;
-    const int32_t* prog = h->d_swprog.as<int32_t>();
     for (int k0 = 0; k0 < nrhs;) {
         const int rem = nrhs - k0;
         const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
         for (const SolveStep& s : h->ssteps) {
             LaunchTimer tm(LRX_K_SOLVE_FWD, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nk);
-            HIPCHK(launch_sweep(fwd + s.node0, s.nnode, prog, xe, nrhs, k0, nk, st));
+            HIPCHK(launch_sweep(fwd + s.node0, s.nnode, xe, nrhs, k0, nk, st));
         }
         for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it) {
             LaunchTimer tm(LRX_K_SOLVE_BWD, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nk);
-            HIPCHK(launch_sweep(bwd + it->node0, it->nnode, prog, xe, nrhs, k0, nk, st));
+            HIPCHK(launch_sweep(bwd + it->node0, it->nnode, xe, nrhs, k0, nk, st));
         }
         k0 += nk;
     }
@@ -941,6 +1013,71 @@ void solve_dev(lrx_handle h, int nrhs, const double* b, double* x) {
     HIPCHK(launch_gather_perm(b, n, h->d_perm.as<int32_t>(), n, nrhs, xe, h->n_ext, st));
     sweeps(h, xe, nrhs);
     HIPCHK(launch_scatter_perm(xe, h->d_perm.as<int32_t>(), n, nrhs, x, n, st));
+}
+
+// Algorithms 2-4 for k factorizations at once: one sweep launch per (height,
+// colour) step covers the nodes of every factorization that has that step (the
+// factorizations share nothing, so their steps commute).  Synchronous.
+void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const* b, double* const* x) {
+    const lrx_handle h0 = hs[0];
+    const hipStream_t st = h0->stream;
+    std::vector<std::pair<int32_t, int32_t>> keys;
+    for (int i = 0; i < k; ++i)
+        for (const SolveStep& s : hs[i]->ssteps) keys.push_back({s.height, s.colour});
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    // extended vectors, then per step the nodes of every factorization
+    std::vector<double*> xe(k);
+    for (int i = 0; i < k; ++i) {
+        const lrx_handle h = hs[i];
+        h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
+        xe[i] = h->x_ext.as<double>();
+    }
+    std::vector<SwNode> nf, nb;
+    std::vector<int32_t> k0f, k0b;
+    for (const auto& key : keys) {
+        k0f.push_back((int32_t)nf.size());
+        for (int i = 0; i < k; ++i) {
+            const lrx_handle h = hs[i];
+            for (const SolveStep& s : h->ssteps) {
+                if (s.height != key.first || s.colour != key.second) continue;
+                for (int32_t j = 0; j < s.nnode; ++j) {
+                    SwNode a = h->sw_host[s.node0 + j];
+                    SwNode c = h->sw_host[h->sw_nnode + s.node0 + j];
+                    a.x = c.x = xe[i];
+                    nf.push_back(a);
+                    nb.push_back(c);
+                }
+            }
+        }
+    }
+    k0f.push_back((int32_t)nf.size());
+    h0->batch_nodes.ensure(std::max<size_t>(2 * nf.size(), 1) * sizeof(SwNode));
+    SwNode* dn = h0->batch_nodes.as<SwNode>();
+    if (!nf.empty()) {
+        HIPCHK(hipMemcpy(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+    }
+    for (int i = 0; i < k; ++i) {
+        const lrx_handle h = hs[i];
+        const int32_t n = h->plan.n;
+        HIPCHK(launch_gather_perm(b[i], n, h->d_perm.as<int32_t>(), n, nrhs, xe[i], h->n_ext, st));
+    }
+    for (int c0 = 0; c0 < nrhs;) {
+        const int rem = nrhs - c0;
+        const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+        for (size_t q = 0; q + 1 < k0f.size(); ++q)
+            HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
+        for (size_t q = k0f.size() - 1; q-- > 0;)
+            HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
+        c0 += nk;
+    }
+    for (int i = 0; i < k; ++i) {
+        const lrx_handle h = hs[i];
+        const int32_t n = h->plan.n;
+        HIPCHK(launch_scatter_perm(xe[i], h->d_perm.as<int32_t>(), n, nrhs, x[i], n, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -1170,7 +1307,8 @@ static lrx_status factor_impl(const lrx_csr* A, const double* val_dev, const lrx
             check_csr(A);
         }
         if (!(o->epsilon >= 0.0 && o->epsilon < 1.0)) fail(LRX_EINVAL, "epsilon must be in [0, 1)");
-        if (o->precision != LRX_FP64) fail(LRX_EINVAL, "only LRX_FP64 is implemented");
+        if (o->precision != LRX_FP64 && o->precision != LRX_MIXED)
+            fail(LRX_EINVAL, "precision must be LRX_FP64 or LRX_MIXED");
         if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
         if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
         h = new lrx_handle_s();
@@ -1183,6 +1321,7 @@ static lrx_status factor_impl(const lrx_csr* A, const double* val_dev, const lrx
         h->stream = (hipStream_t)o->stream;
         h->epsilon = o->epsilon;
         h->compress = o->compress;
+        h->precision = o->precision;
         h->arena.budget_bytes = o->hbm_budget_bytes;
         // A in tree order for the GMRES products
         const int32_t n = A->n;
@@ -1267,7 +1406,7 @@ static lrx_status factor_impl(const lrx_csr* A, const double* val_dev, const lrx
         S.mean_rank = h->ranks.empty() ? 0.0 : rs / h->ranks.size();
         S.extended_size = h->n_ext;
         S.max_compression_error = h->max_tail_ratio;
-        S.factor_bytes = h->arena.total * 8;
+        S.factor_bytes = (h->solve_fp32 ? h->arena32.total : h->arena.total) * 8;
         S.t_plan_ms = t1 - t0;
         S.t_factor_ms = t2 - t0;
         S.t_sync_ms = h->t_sync_ms;
@@ -1322,6 +1461,22 @@ lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double
         if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
         if (!b_dev || !x_dev || b_dev == x_dev) fail(LRX_EINVAL, "bad b/x pointers");
         solve_dev(h, nrhs, b_dev, x_dev);
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_solve_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                               double* const* x_dev) {
+    return guarded([&]() -> lrx_status {
+        if (k < 1 || !hs || !b_dev || !x_dev) fail(LRX_EINVAL, "bad batch arguments");
+        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+        for (int i = 0; i < k; ++i) {
+            check_handle(hs[i]);
+            if (!b_dev[i] || !x_dev[i] || b_dev[i] == x_dev[i]) fail(LRX_EINVAL, "bad b/x pointers");
+            for (int j = 0; j < i; ++j)
+                if (hs[j] == hs[i]) fail(LRX_EINVAL, "a handle appears twice in the batch");
+        }
+        solve_batch_dev(k, hs, nrhs, b_dev, x_dev);
         return LRX_OK;
     });
 }

@@ -38,8 +38,8 @@ struct Off {
 };
 
 struct URun {
-    const double* src = nullptr;     // nullptr: rows of x
-    int32_t ld = 0, len = 0, nrun = 0, dld = 0;
+    const void* src = nullptr;       // nullptr: rows of x
+    int32_t ld = 0, len = 0, nrun = 0, dld = 0, es = 8;
     int map = -1;                    // unit map id
     Off dst;
 };
@@ -137,6 +137,7 @@ struct NodePacker {
             w.lds = resolve(r.dst);
             w.dld = r.dld;
             w.rlen = r.len > 0 ? 1.0f / (float)r.len : 0.0f;
+            w.es = r.es;
             s.runs.push_back(w);
             if (r.src) s.elems_mat += r.len * r.nrun;
         }
@@ -176,8 +177,8 @@ struct NodePacker {
 
     // Serialises the stages into words; returns the node descriptor.  Sets
     // ok = false if a block exceeds the descriptor budget.
-    SwNode emit(std::vector<int32_t>& words, bool& ok) const {
-        SwNode nd{};
+    SwNodeRel emit(std::vector<int32_t>& words, bool& ok) const {
+        SwNodeRel nd{};
         nd.nstage = (int32_t)stages.size();
         std::vector<std::vector<int32_t>> blocks;
         for (const StageB& s : stages) {
@@ -245,9 +246,13 @@ struct NodePacker {
 };
 
 // ------------------------------------------------------------------ units
+inline const void* at(const void* base, int64_t elems, int32_t es) {
+    return (const char*)base + elems * es;
+}
+
 // Rows [r0, r0 + rc) of a pivot inverse: out = inv[rows, :] * in.
 void pivot_units(const SwPivIR& P, int32_t in_abs, int32_t out_abs, bool to_x, int seq, int32_t cap,
-                 std::vector<Unit>& units) {
+                 int32_t es, std::vector<Unit>& units) {
     const int32_t m = P.m;
     int32_t rc = m;
     while (rc > 1 && (int64_t)odd(rc) * m > cap) rc = (rc + 1) / 2;
@@ -255,7 +260,8 @@ void pivot_units(const SwPivIR& P, int32_t in_abs, int32_t out_abs, bool to_x, i
         const int32_t n = std::min(rc, m - r0);
         Unit u;
         URun r;
-        r.src = P.inv + r0;
+        r.src = at(P.inv, r0, es);
+        r.es = es;
         r.ld = m; r.len = n; r.nrun = m; r.dld = odd(n);
         r.dst = Off::rel_(0);
         u.runs.push_back(r);
@@ -275,14 +281,15 @@ void pivot_units(const SwPivIR& P, int32_t in_abs, int32_t out_abs, bool to_x, i
 // An edge whose input and output both live in reserved buffers:
 // buf[rows] = buf[rows] - E * in[cols].
 void local_edge_units(const SwEdgeIR& E, int32_t in_abs, int32_t buf_abs, int seq, int32_t cap,
-                      std::vector<Unit>& units) {
+                      int32_t es, std::vector<Unit>& units) {
     int32_t rc = E.nr;
     while (rc > 1 && (int64_t)odd(rc) * E.nc > cap) rc = (rc + 1) / 2;
     for (int32_t a0 = 0; a0 < E.nr; a0 += rc) {
         const int32_t n = std::min(rc, E.nr - a0);
         Unit u;
         URun r;
-        r.src = E.E + a0;
+        r.src = at(E.E, a0, es);
+        r.es = es;
         r.ld = E.nr; r.len = n; r.nrun = E.nc; r.dld = odd(n);
         r.dst = Off::rel_(0);
         u.runs.push_back(r);
@@ -309,7 +316,7 @@ void local_edge_units(const SwEdgeIR& E, int32_t in_abs, int32_t buf_abs, int se
 
 // Forward: the later node q receives Mat(s->q) F_s and Mat(b->q) F_b.
 void target_units(const SwEdgeIR* Es, const SwEdgeIR* Eb, int32_t fs_abs, int32_t fb_abs,
-                  int32_t cap, std::vector<Unit>& units) {
+                  int32_t cap, int32_t es, std::vector<Unit>& units) {
     std::vector<int32_t> U;
     std::vector<int32_t> abs_s, abs_b;
     if (Es) {
@@ -367,7 +374,8 @@ void target_units(const SwEdgeIR* Es, const SwEdgeIR* Eb, int32_t fs_abs, int32_
             const int32_t n = rg.second - rg.first;
             if (n <= 0) return;
             URun r;
-            r.src = E->E + rg.first;
+            r.src = at(E->E, rg.first, es);
+            r.es = es;
             r.ld = E->nr; r.len = n; r.nrun = E->nc; r.dld = odd(n);
             r.dst = Off::rel_(fill);
             u.runs.push_back(r);
@@ -423,7 +431,7 @@ struct SrcEdge {
     int seq;
 };
 
-void source_units(const std::vector<SrcEdge>& es, int32_t cap, std::vector<Unit>& units) {
+void source_units(const std::vector<SrcEdge>& es, int32_t cap, int32_t esz, std::vector<Unit>& units) {
     // columns of all edges of this source, as absolute rows of x
     std::vector<int32_t> U;
     std::vector<std::vector<int32_t>> absc(es.size());
@@ -448,7 +456,8 @@ void source_units(const std::vector<SrcEdge>& es, int32_t cap, std::vector<Unit>
             const SwEdgeIR& E = *se.E;
             const int32_t a0 = pr.second.first, n = pr.second.second - a0;
             URun r;
-            r.src = E.E + a0;
+            r.src = at(E.E, a0, esz);
+            r.es = esz;
             r.ld = E.nr; r.len = n; r.nrun = E.nc; r.dld = odd(n);
             r.dst = Off::rel_(fill);
             u.runs.push_back(r);
@@ -492,7 +501,7 @@ void source_units(const std::vector<SrcEdge>& es, int32_t cap, std::vector<Unit>
 
 bool edge_nonempty(const SwEdgeIR& e) { return e.E && e.nr > 0 && e.nc > 0; }
 
-bool build_fwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std::string& err) {
+bool build_fwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNodeRel& out, std::string& err) {
     const SwPivIR& S = N.s;
     const SwPivIR& B = N.b;
     const int32_t ms = S.m, r = B.m;
@@ -516,13 +525,13 @@ bool build_fwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std:
         }
         units.push_back(std::move(u));
     }
-    pivot_units(S, oRs, oFs, false, 0, pk.cap_area, units);
+    pivot_units(S, oRs, oFs, false, 0, pk.cap_area, N.es_piv, units);
     const SwEdgeIR* sb = nullptr;
     for (const SwEdgeIR& e : S.out)
         if (e.other == B.node && edge_nonempty(e)) sb = &e;
     if (r > 0) {
-        if (sb) local_edge_units(*sb, oFs, oRb, 1, pk.cap_area, units);
-        pivot_units(B, oRb, oFb, false, 2, pk.cap_area, units);
+        if (sb) local_edge_units(*sb, oFs, oRb, 1, pk.cap_area, N.es, units);
+        pivot_units(B, oRb, oFb, false, 2, pk.cap_area, N.es_piv, units);
         Unit u;                                     // x[b] = R_b
         UComp st;
         st.seq = 2; st.nr = r; st.nc = 0; st.ld = 1;
@@ -542,7 +551,7 @@ bool build_fwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std:
         const SwEdgeIR* eb = nullptr;
         for (const SwEdgeIR& e : S.out) if (e.other == q && edge_nonempty(e)) es = &e;
         if (r > 0) for (const SwEdgeIR& e : B.out) if (e.other == q && edge_nonempty(e)) eb = &e;
-        target_units(es, eb, oFs, oFb, pk.cap_area, units);
+        target_units(es, eb, oFs, oFb, pk.cap_area, N.es, units);
     }
     for (const Unit& u : units)
         if (!pk.add(u, err)) return false;
@@ -551,7 +560,7 @@ bool build_fwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std:
     return ok;
 }
 
-bool build_bwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std::string& err) {
+bool build_bwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNodeRel& out, std::string& err) {
     const SwPivIR& S = N.s;
     const SwPivIR& B = N.b;
     const int32_t ms = S.m, r = B.m;
@@ -608,12 +617,12 @@ bool build_bwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std:
             }
         pend.push_back(std::move(p));
     }
-    for (auto& p : pend) source_units(p.es, pk.cap_area, units);
+    for (auto& p : pend) source_units(p.es, pk.cap_area, N.es, units);
     if (r > 0) {
-        pivot_units(B, oYb, oXb, true, nround, pk.cap_area, units);
-        if (bs) local_edge_units(*bs, oXb, oYs, nround + 1, pk.cap_area, units);
+        pivot_units(B, oYb, oXb, true, nround, pk.cap_area, N.es_piv, units);
+        if (bs) local_edge_units(*bs, oXb, oYs, nround + 1, pk.cap_area, N.es, units);
     }
-    pivot_units(S, oYs, -1, true, nround + 2, pk.cap_area, units);
+    pivot_units(S, oYs, -1, true, nround + 2, pk.cap_area, N.es_piv, units);
     for (const Unit& u : units)
         if (!pk.add(u, err)) return false;
     out = pk.emit(words, ok);
@@ -623,7 +632,7 @@ bool build_bwd(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& out, std:
 
 }  // namespace
 
-bool build_node_programs(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& fwd, SwNode& bwd,
+bool build_node_programs(const SwNodeIR& N, std::vector<int32_t>& words, SwNodeRel& fwd, SwNodeRel& bwd,
                          std::string& err) {
     return build_fwd(N, words, fwd, err) && build_bwd(N, words, bwd, err);
 }
@@ -634,7 +643,7 @@ bool build_sweep_program(const std::vector<std::vector<SwNodeIR>>& steps, SwProg
     for (const auto& st : steps) {
         out.step0.push_back((int32_t)out.fwd.size());
         for (const SwNodeIR& N : st) {
-            SwNode f{}, b{};
+            SwNodeRel f{}, b{};
             if (!build_fwd(N, out.words, f, err)) return false;
             if (!build_bwd(N, out.words, b, err)) return false;
             out.fwd.push_back(f);

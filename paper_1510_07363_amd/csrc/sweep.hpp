@@ -13,9 +13,9 @@ namespace lrx {
 
 // A stored block Mat(u -> v): column-major nr x nc, rows are variables of v and
 // columns variables of u, given as local indices of those nodes (an empty list
-// is the identity 0..n-1).
+// is the identity 0..n-1).  Blocks hold elements of es bytes (8: FP64, 4: FP32).
 struct SwEdgeIR {
-    const double* E = nullptr;
+    const void* E = nullptr;
     int32_t nr = 0, nc = 0;
     int32_t other = -1;              // target node (out-edge) or source node (in-edge)
     int64_t other_off = 0;           // first variable of that node in the extended vector
@@ -23,7 +23,7 @@ struct SwEdgeIR {
 };
 
 struct SwPivIR {
-    const double* inv = nullptr;     // explicit inverse of the pivot block, m x m column-major
+    const void* inv = nullptr;       // explicit inverse of the pivot block, m x m column-major
     int32_t m = 0;
     int64_t off = 0;                 // first variable of the node
     int32_t node = -1;
@@ -32,11 +32,19 @@ struct SwPivIR {
 
 struct SwNodeIR {
     SwPivIR s, b;                    // super-node pivot, then its black node
+    int32_t es = 8;                  // bytes per element of the edge blocks
+    int32_t es_piv = 8;              // bytes per element of the pivot inverses
+};
+
+// A node program before upload: its first block as a word offset.
+struct SwNodeRel {
+    int64_t desc = 0;
+    int32_t words0 = 0, nstage = 0;
 };
 
 struct SwProgram {
     std::vector<int32_t> words;      // all descriptor blocks
-    std::vector<SwNode> fwd, bwd;    // one per super-node, grouped by colour step
+    std::vector<SwNodeRel> fwd, bwd; // one per super-node, grouped by colour step
     std::vector<int32_t> step0;      // first node of each colour step (same in fwd and bwd)
     int64_t max_stages = 0, total_stages = 0;
 };
@@ -48,7 +56,7 @@ bool build_sweep_program(const std::vector<std::vector<SwNodeIR>>& steps, SwProg
 
 // Compiles the forward and backward programs of one super-node, appending their
 // descriptor blocks to words (descriptors relative to the start of words).
-bool build_node_programs(const SwNodeIR& N, std::vector<int32_t>& words, SwNode& fwd, SwNode& bwd,
+bool build_node_programs(const SwNodeIR& N, std::vector<int32_t>& words, SwNodeRel& fwd, SwNodeRel& bwd,
                          std::string& err);
 
 }  // namespace lrx

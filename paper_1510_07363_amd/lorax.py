@@ -18,11 +18,12 @@ LIB_PATH = os.path.join(_HERE, "liblorax.so")
 LRX_OK, LRX_EINVAL, LRX_ENOMEM, LRX_ESINGULAR, LRX_ENOCONV, LRX_EDEVICE, LRX_EBUSY = range(7)
 STATUS_NAMES = {0: "LRX_OK", 1: "LRX_EINVAL", 2: "LRX_ENOMEM", 3: "LRX_ESINGULAR",
                 4: "LRX_ENOCONV", 5: "LRX_EDEVICE", 6: "LRX_EBUSY"}
-LRX_FP64 = 0
+LRX_FP64, LRX_MIXED = 0, 1
 LRX_COLORED, LRX_NATURAL = 0, 1
 ORDERS = {"colored": LRX_COLORED, "natural": LRX_NATURAL}
 LRX_SVD, LRX_RRQR = 0, 1
 COMPRESS = {"svd": LRX_SVD, "rrqr": LRX_RRQR}
+PRECISION = {"fp64": LRX_FP64, "mixed": LRX_MIXED}
 
 
 class LoraxError(RuntimeError):
@@ -80,7 +81,8 @@ class PlanInfo(C.Structure):
 
 
 # every symbol declared in include/lorax.h
-EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev", "lrx_gmres", "lrx_gmres_dev",
+EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
+           "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev",
            "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
            "lrx_last_error", "lrx_version")
 
@@ -99,6 +101,8 @@ def _load():
         "lrx_timing_read": (C.c_int, [P(Timing), C.c_int32]),
         "lrx_solve": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int64, f64p, C.c_int64]),
         "lrx_solve_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+        "lrx_solve_batch_dev": (C.c_int, [C.c_int32, P(C.c_void_p), C.c_int32, P(C.c_void_p),
+                                          P(C.c_void_p)]),
         "lrx_gmres": (C.c_int, [P(Csr), C.c_void_p, C.c_int32, f64p, f64p, C.c_double,
                                 C.c_int32, C.c_int32, i32p, f64p]),
         "lrx_gmres_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
@@ -194,13 +198,15 @@ class Factor:
 
     def __init__(self, row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon,
                  order="colored", compress="svd", stream=None, hbm_budget_bytes=0,
-                 val_dev=None):
-        """val: host values, or None with val_dev = device address of the values."""
+                 val_dev=None, precision="fp64"):
+        """val: host values, or None with val_dev = device address of the values.
+        precision: "fp64" or "mixed" (FP32 compression arithmetic and FP32 stored
+        factor for the solve; FP64 pivots, Schur updates and GMRES)."""
         if val is None:
             val = np.zeros(0)
         self._A = _CsrArgs(row_ptr, col_idx, val)
         T = _TreeArgs(perm, leaf_ptr, depth)
-        o = Opts(float(epsilon), LRX_FP64, COMPRESS[compress], ORDERS[order],
+        o = Opts(float(epsilon), PRECISION[precision], COMPRESS[compress], ORDERS[order],
                  int(hbm_budget_bytes), C.c_void_p(stream) if stream else None)
         h = C.c_void_p()
         if val_dev is not None:
@@ -299,3 +305,14 @@ class Factor:
             self.free()
         except Exception:
             pass
+
+
+def solve_batch_dev(factors, nrhs, b_ptrs, x_ptrs):
+    """lrx_solve_batch_dev: one solve per factor, all sweeps of one (level, colour)
+    step in one launch; b_ptrs[i], x_ptrs[i] are device addresses (n_i x nrhs,
+    column-major).  Synchronous."""
+    k = len(factors)
+    hs = (C.c_void_p * k)(*[f._h for f in factors])
+    bs = (C.c_void_p * k)(*[C.c_void_p(int(b)) for b in b_ptrs])
+    xs = (C.c_void_p * k)(*[C.c_void_p(int(x)) for x in x_ptrs])
+    _check(_lib.lrx_solve_batch_dev(int(k), hs, int(nrhs), bs, xs))
