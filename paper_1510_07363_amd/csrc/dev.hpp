@@ -155,11 +155,13 @@ struct SwComp {          // 12 words
     int32_t gbase, gmap;
 };
 
-// FP64 -> FP32 copy of one stored block (mixed precision)
+// Copy of one stored block for the solve (mixed precision): to FP32 (f64 == 0)
+// or as FP64 (f64 == 1, pivot inverses)
 struct DConv {
     const double* src;
-    float* dst;
+    void* dst;
     int64_t n;
+    int32_t f64, pad_;
 };
 
 }  // namespace lrx

@@ -1558,10 +1558,13 @@ hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, 
     }
 }
 
-// dst[e] = (float) src[e] for every segment (one work-group per segment)
+// dst[e] = src[e] (as FP32 or FP64) for every segment (one work-group per segment)
 __global__ void k_to_f32(const DConv* __restrict__ segs) {
     const DConv S = segs[blockIdx.x];
-    for (int64_t e = threadIdx.x; e < S.n; e += blockDim.x) S.dst[e] = (float)S.src[e];
+    if (S.f64)
+        for (int64_t e = threadIdx.x; e < S.n; e += blockDim.x) static_cast<double*>(S.dst)[e] = S.src[e];
+    else
+        for (int64_t e = threadIdx.x; e < S.n; e += blockDim.x) static_cast<float*>(S.dst)[e] = (float)S.src[e];
 }
 
 hipError_t launch_to_f32(const DConv* segs, int n, hipStream_t st) {

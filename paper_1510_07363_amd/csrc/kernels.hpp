@@ -41,7 +41,7 @@ hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int 
 // and each run states its blocks' storage type, so nodes of several
 // factorizations (FP64 or mixed precision) can share one launch.
 hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, hipStream_t st);
-// FP64 -> FP32 copies of stored blocks (DConv), one work-group per block.
+// Copies of stored blocks (DConv: to FP32, or FP64 as is), one work-group per block.
 hipError_t launch_to_f32(const DConv* segs, int n, hipStream_t st);
 
 // ---- vectors: layout v[i * nrhs + k] ("row-interleaved") -------------------

@@ -827,12 +827,12 @@ void build_solve_program(lrx_handle h) {
             if (cnt <= 0) continue;
             if (pivf[e]) {                 // pivot inverses stay FP64
                 double* d = h->arena32.alloc((size_t)cnt);
-                HIPCHK(hipMemcpyAsync(d, h->eptr[e], (size_t)cnt * 8, hipMemcpyDeviceToDevice, h->stream));
+                segs.push_back(DConv{h->eptr[e], d, cnt, 1, 0});
                 sptr[e] = d;
                 continue;
             }
             float* d = (float*)h->arena32.alloc((size_t)(cnt + 1) / 2);
-            segs.push_back(DConv{h->eptr[e], d, cnt});
+            segs.push_back(DConv{h->eptr[e], d, cnt, 0, 0});
             sptr[e] = d;
         }
         DevBuf dsegs;
@@ -841,7 +841,7 @@ void build_solve_program(lrx_handle h) {
             HIPCHK(hipMemcpy(dsegs.p, segs.data(), segs.size() * sizeof(DConv), hipMemcpyHostToDevice));
             HIPCHK(launch_to_f32(dsegs.as<DConv>(), (int)segs.size(), h->stream));
         }
-        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));      // dsegs is released at scope end
         h->solve_fp32 = true;
     } else {
         for (size_t e = 0; e < P.edges.size(); ++e) sptr[e] = h->eptr[e];
