@@ -139,6 +139,21 @@ lrx_status lrx_factor(const lrx_csr* A, const lrx_tree* T, const lrx_opts* o, lr
 lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tree* T,
                           const lrx_opts* o, lrx_handle* out);
 
+/* Batched form of lrx_factor (Algorithm 1 for k independent systems at once).
+ * A[i], T[i] (arrays of k structs, host memory, copied) describe system i; all
+ * share the options o (epsilon, precision, rule, order, per-handle HBM budget
+ * and stream).  The symbolic plans run on host threads; the numeric level loops
+ * of all systems advance in lock-step over (height above the leaves, colour):
+ * each kernel of a step is one launch over the nodes of every system with a
+ * step there (super-nodes of one colour are independent, Sec. 3.3, and distinct
+ * systems share nothing).  On success out[i] is the handle of system i and
+ * equals the handle lrx_factor gives for that system alone (the solve results
+ * are bitwise the same).  The batch succeeds or fails as a whole: on any error
+ * no handle is created and every out[i] is set to NULL; the message of
+ * lrx_last_error names the system.  1 <= k <= 65536. */
+lrx_status lrx_factor_batch(int32_t k, const lrx_csr* A, const lrx_tree* T, const lrx_opts* o,
+                            lrx_handle* out);
+
 /* Algorithms 2-4 for nrhs right-hand sides, host memory, column-major:
  * b[k*ldb + i] is entry i of right-hand side k (ldb >= n); x likewise (ldx >= n).
  * Synchronous. */

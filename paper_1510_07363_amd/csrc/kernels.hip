@@ -211,11 +211,20 @@ template <int JG>   // lanes per Jacobi pair
 __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict__ tasks,
                                                      const DPiece* __restrict__ pieces,
                                                      const int32_t* __restrict__ imap,
-                                                     int ch) {
-    // ch > 0: R, V and a chunk of ch rows of B live in LDS (2 c^2 + ch c doubles);
-    // ch == 0: everything in the task's workspace.
+                                                     int cap) {
+    // With cap doubles of dynamic LDS, R, V and a chunk of ch rows of B live in
+    // LDS (2 c^2 + ch c doubles), ch taken from the task's own sizes so that its
+    // arithmetic does not depend on the other tasks of the launch; below 16 rows
+    // (ch == 0) everything stays in the task's workspace.
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
+    int ch = 0;
+    if (c > 0) {
+        int64_t t = ((int64_t)cap - 2ll * c * c) / c;
+        t = t > M ? M : t;
+        t = t > 1024 ? 1024 : t;
+        ch = t < 16 ? 0 : (int)t;
+    }
     const int lane = tid % WAVE, wv = tid / WAVE;
     constexpr int NW = NT / WAVE;
     __shared__ double s_s[NT / WAVE + 1];
@@ -1483,16 +1492,12 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
         (void)hipFuncSetAttribute((const void*)k_compress_svd<16>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
         attr_set = true;
     }
-    const int64_t cap = kLdsBudget / (int64_t)sizeof(double);
-    int64_t ch = (cap - 2ll * max_c * max_c) / (max_c > 0 ? max_c : 1);
-    if (ch > max_M) ch = max_M;
-    if (ch > 1024) ch = 1024;
-    if (ch < 16) ch = 0;
-    const size_t lds = ch > 0 ? (size_t)(2ll * max_c * max_c + ch * max_c) * sizeof(double) : 0;
+    const int cap = kLdsBudget / (int)sizeof(double);
+    const size_t lds = (size_t)cap * sizeof(double);
     if (max_c <= 64)
-        hipLaunchKernelGGL(k_compress_svd<8>, dim3(n), dim3(NT), lds, st, t, pieces, imap, (int)ch);
+        hipLaunchKernelGGL(k_compress_svd<8>, dim3(n), dim3(NT), lds, st, t, pieces, imap, cap);
     else
-        hipLaunchKernelGGL(k_compress_svd<16>, dim3(n), dim3(NT), lds, st, t, pieces, imap, (int)ch);
+        hipLaunchKernelGGL(k_compress_svd<16>, dim3(n), dim3(NT), lds, st, t, pieces, imap, cap);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <set>
@@ -216,7 +217,6 @@ struct lrx_handle_s {
     std::vector<int64_t> var_off;  // per node
     int64_t n_ext = 0;
     Arena arena;
-    DevBuf d_imap;                 // factor maps
     // solve program (staged node programs of both sweeps)
     DevBuf d_swnodes, d_swprog;
     std::vector<SwNode> sw_host;   // host copy of d_swnodes (forward nodes, then backward)
@@ -271,45 +271,91 @@ void ensure_gfx950(int dev) {
 }
 
 // ------------------------------------------------------------------ factor driver
-void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
-    Plan& P = h->plan;
-    const hipStream_t st = h->stream;
-#define SYNC(s_)                                                   \
-    do {                                                           \
-        const double ts_ = now_ms();                               \
-        HIPCHK(hipStreamSynchronize(s_));                          \
-        h->t_sync_ms += now_ms() - ts_;                            \
-    } while (0)
-    const int32_t n = P.n;
-    h->size.assign(P.nodes.size(), -1);
-    h->eptr.assign(P.edges.size(), nullptr);
-    for (size_t v = 0; v < P.nodes.size(); ++v)
-        if (P.nodes[v].leaf) h->size[v] = P.nodes[v].static_size;
+// State of one factorization in the level loop.  The driver below advances one
+// or several factorizations in lock-step over (height above the leaves,
+// colour): super-nodes of one colour are independent (Sec. 3.3) and distinct
+// systems share nothing, so every participating factorization's tasks of a step
+// go into one launch per kernel.  Each task's arithmetic depends on its own
+// operands only, so a factorization in a batch equals the same factorization
+// alone.
+struct NodeBatch {
+    std::vector<DPrep> prep_s, prep_b;
+    std::vector<DProj> projs;
+    std::vector<DGemm> g1s, g2s, g1b, g2b;
+    int max_ms = 1, max_mb = 1;
+    int64_t pf_s = 0, pf_b = 0, gf_s = 0, gf_b = 0;
+};
 
-    auto nr_of = [&](int32_t e) { const PEdge& E = P.edges[e]; return dim_of(E.rows, h->size[E.dst]); };
-    auto nc_of = [&](int32_t e) { const PEdge& E = P.edges[e]; return dim_of(E.cols, h->size[E.src]); };
-    auto blk = [&](int32_t e) {
+struct FactorRun {
+    lrx_handle h;
+    Plan& P;
+    std::vector<int32_t> imap;             // static index maps of this factorization
+    int32_t imap_base = 0;                 // its offset in the batch table
+    std::vector<std::vector<NodeMaps>> maps;
+    std::vector<int32_t> level_at_height;  // plan level index per height (-1: none)
+    int32_t info_base = 0, info_count = 0, info_next = 0;
+    bool fp32_compress = false;
+    int64_t flops = 0;
+    DevBuf d_idx, d_val;                   // temporaries of the initial scatter
+    // current colour step
+    int32_t si = -1;
+    std::vector<DCompress> ct;
+    std::vector<DPiece> pieces;
+    std::vector<std::vector<int32_t>> a_row0, b_row0;
+    std::vector<size_t> wsB, wsV, wsH, tail_at;
+    size_t ws_need = 0, w_need = 0, tails_total = 0;
+    int64_t task0 = 0, tails0 = 0;         // first task / tail value in the batch arrays
+
+    explicit FactorRun(lrx_handle h_) : h(h_), P(h_->plan) {}
+
+    int32_t mo(int32_t m) const { return m >= 0 ? m + imap_base : m; }
+    int32_t nr_of(int32_t e) const { const PEdge& E = P.edges[e]; return dim_of(E.rows, h->size[E.dst]); }
+    int32_t nc_of(int32_t e) const { const PEdge& E = P.edges[e]; return dim_of(E.cols, h->size[E.src]); }
+    DBlk blk(int32_t e) const {
         DBlk b;
         if (e < 0) { b.p = nullptr; b.nr = 0; b.nc = 0; return b; }   // empty pivot
         b.p = h->eptr[e]; b.nr = nr_of(e); b.nc = nc_of(e);
         return b;
-    };
+    }
     // one contiguous, zeroed region for a group of new blocks (one memset)
-    auto alloc_group = [&](const std::vector<int32_t>& es) {
+    void alloc_group(const std::vector<int32_t>& es, hipStream_t st) {
+        if (es.empty()) return;
         std::vector<size_t> off(es.size());
         size_t tot = 0;
         for (size_t q = 0; q < es.size(); ++q) {
             off[q] = tot;
             tot += (((size_t)nr_of(es[q]) * nc_of(es[q])) + 31) & ~(size_t)31;
         }
-        if (es.empty()) return;
         double* base = h->arena.alloc(std::max<size_t>(tot, 1));
         for (size_t q = 0; q < es.size(); ++q) h->eptr[es[q]] = base + off[q];
         HIPCHK(hipMemsetAsync(base, 0, std::max<size_t>(tot, 1) * 8, st));
-    };
+    }
+
+    void setup(const lrx_csr* A, const double* val_dev, hipStream_t st);
+    void merge_tasks(const LevelPlan& L, hipStream_t st, std::vector<DMerge>& mt);
+    size_t compress_tasks();
+    void bind_compress(double* wsp, int32_t* ranks_dev, double* tails_dev, int32_t piece_base);
+    void take_ranks(const int32_t* rk, const double* tails_h, hipStream_t st);
+    void node_tasks(const int32_t* rk, NodeBatch& nb);
+};
+
+void FactorRun::setup(const lrx_csr* A, const double* val_dev, hipStream_t st) {
+    const int32_t n = P.n;
+    h->size.assign(P.nodes.size(), -1);
+    h->eptr.assign(P.edges.size(), nullptr);
+    for (size_t v = 0; v < P.nodes.size(); ++v)
+        if (P.nodes[v].leaf) h->size[v] = P.nodes[v].static_size;
+    // mixed precision: the reduced QRs and Jacobi of the compression in FP32
+    // when FP32 resolves the cut-off (sigma_k / sigma_0 >= epsilon >= 1e-5)
+    fp32_compress = h->precision == LRX_MIXED && h->epsilon >= 1e-5;
+    for (size_t li = 0; li < P.levels.size(); ++li) {
+        const int32_t hgt = P.depth - P.levels[li].level;
+        if (hgt < 0) fail(LRX_EDEVICE, "internal: level above the depth");
+        if ((size_t)hgt >= level_at_height.size()) level_at_height.resize(hgt + 1, -1);
+        level_at_height[hgt] = (int32_t)li;
+    }
 
     // ---------------- static index maps (depend on supports only)
-    std::vector<int32_t> imap;
     auto put_map = [&](const std::vector<int32_t>& v) -> int32_t {
         int32_t off = (int32_t)imap.size();
         imap.insert(imap.end(), v.begin(), v.end());
@@ -323,7 +369,7 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
         if (sub.all) fail(LRX_EDEVICE, "internal: full support with a compact target");
         return put_map(v);
     };
-    std::vector<std::vector<NodeMaps>> maps(P.steps.size());
+    maps.assign(P.steps.size(), {});
     auto piv_maps = [&](const PivotPlan& pp, PivMaps& pm) {
         for (int32_t e : pp.in_edges) {
             const Support& r = P.edges[e].rows;
@@ -344,12 +390,13 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             pm.pair_cpos.push_back(put_pos(I.cols, T.cols));
         }
     };
-    for (size_t si = 0; si < P.steps.size(); ++si) {
-        const ColourStep& cs = P.steps[si];
-        maps[si].resize(cs.nodes.size());
+    for (size_t s = 0; s < P.steps.size(); ++s) {
+        const ColourStep& cs = P.steps[s];
+        maps[s].resize(cs.nodes.size());
+        info_count += 2 * (int32_t)cs.nodes.size();
         for (size_t ni = 0; ni < cs.nodes.size(); ++ni) {
             const NodeStep& ns = cs.nodes[ni];
-            NodeMaps& nm = maps[si][ni];
+            NodeMaps& nm = maps[s][ni];
             for (const CandRef& cr : ns.cands) {
                 if (cr.e_sp >= 0) {
                     nm.a_map.push_back(put_pos(P.edges[cr.e_sp].cols, ns.gamma));
@@ -364,357 +411,447 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
             piv_maps(ns.pb, nm.pb);
         }
     }
-    h->d_imap.ensure(std::max<size_t>(imap.size(), 1) * sizeof(int32_t));
-    if (!imap.empty())
-        HIPCHK(hipMemcpyAsync(h->d_imap.p, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    const int32_t* d_imap = h->d_imap.as<int32_t>();
 
     // ---------------- initial blocks: A gathered into the leaf super-node blocks
-    {
-        int64_t tot = 0;
-        std::vector<int64_t> eoff(P.init_edges.size());
-        for (size_t q = 0; q < P.init_edges.size(); ++q) {
-            int32_t e = P.init_edges[q];
-            eoff[q] = tot;
-            tot += (((int64_t)nr_of(e) * nc_of(e)) + 31) & ~(int64_t)31;
-        }
-        double* base = h->arena.alloc((size_t)std::max<int64_t>(tot, 1));
-        std::vector<int32_t> slot(P.edges.size(), -1);
-        for (size_t q = 0; q < P.init_edges.size(); ++q) {
-            h->eptr[P.init_edges[q]] = base + eoff[q];
-            slot[P.init_edges[q]] = (int32_t)q;
-        }
-        HIPCHK(hipMemsetAsync(base, 0, (size_t)std::max<int64_t>(tot, 1) * 8, st));
-        // destination of every entry of A
-        std::vector<int32_t> leaf_of(n);
-        const int64_t nleaf = (int64_t)1 << P.depth;
-        for (int64_t c = 0; c < nleaf; ++c)
-            for (int32_t t = P.leaf_ptr[c]; t < P.leaf_ptr[c + 1]; ++t) leaf_of[t] = (int32_t)c;
-        // edge lookup per (src, dst) super pair
-        std::vector<std::vector<std::pair<int32_t, int32_t>>> out_init(P.nodes.size());
-        for (int32_t e : P.init_edges) out_init[P.edges[e].src].push_back({P.edges[e].dst, e});
-        std::vector<int64_t> idx((size_t)A->nnz);
-        for (int32_t r = 0; r < n; ++r) {
-            const int32_t tr = P.pos[r];
-            const int32_t sd = leaf_of[tr] >> 1;
-            const int32_t lr = tr - P.nodes[sd].dof0;
-            for (int64_t q = A->row_ptr[r]; q < A->row_ptr[r + 1]; ++q) {
-                const int32_t tc = P.pos[A->col_idx[q]];
-                const int32_t ss = leaf_of[tc] >> 1;
-                const int32_t lc = tc - P.nodes[ss].dof0;
-                int32_t e = -1;
-                for (auto& pr : out_init[ss]) if (pr.first == sd) { e = pr.second; break; }
-                if (e < 0) fail(LRX_EDEVICE, "internal: missing initial edge");
-                const PEdge& E = P.edges[e];
-                int32_t pr_ = E.rows.all ? lr : (int32_t)(std::lower_bound(E.rows.idx.begin(), E.rows.idx.end(), lr) - E.rows.idx.begin());
-                int32_t pc_ = E.cols.all ? lc : (int32_t)(std::lower_bound(E.cols.idx.begin(), E.cols.idx.end(), lc) - E.cols.idx.begin());
-                idx[q] = eoff[slot[e]] + pr_ + (int64_t)pc_ * nr_of(e);
-            }
-        }
-        DevBuf d_idx, d_val;
-        d_idx.ensure(std::max<size_t>(idx.size(), 1) * 8);
-        if (A->nnz > 0) {
-            HIPCHK(hipMemcpyAsync(d_idx.p, idx.data(), idx.size() * 8, hipMemcpyHostToDevice, st));
-            const double* src = val_dev;
-            if (!src) {
-                d_val.ensure(std::max<size_t>(idx.size(), 1) * 8);
-                HIPCHK(hipMemcpyAsync(d_val.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice, st));
-                src = d_val.as<double>();
-            }
-            HIPCHK(launch_scatter(base, d_idx.as<int64_t>(), src, A->nnz, st));
-        }
-        SYNC(st);   // d_idx/d_val are released at scope end
+    int64_t tot = 0;
+    std::vector<int64_t> eoff(P.init_edges.size());
+    for (size_t q = 0; q < P.init_edges.size(); ++q) {
+        int32_t e = P.init_edges[q];
+        eoff[q] = tot;
+        tot += (((int64_t)nr_of(e) * nc_of(e)) + 31) & ~(int64_t)31;
     }
+    double* base = h->arena.alloc((size_t)std::max<int64_t>(tot, 1));
+    std::vector<int32_t> slot(P.edges.size(), -1);
+    for (size_t q = 0; q < P.init_edges.size(); ++q) {
+        h->eptr[P.init_edges[q]] = base + eoff[q];
+        slot[P.init_edges[q]] = (int32_t)q;
+    }
+    HIPCHK(hipMemsetAsync(base, 0, (size_t)std::max<int64_t>(tot, 1) * 8, st));
+    // destination of every entry of A
+    std::vector<int32_t> leaf_of(n);
+    const int64_t nleaf = (int64_t)1 << P.depth;
+    for (int64_t c = 0; c < nleaf; ++c)
+        for (int32_t t = P.leaf_ptr[c]; t < P.leaf_ptr[c + 1]; ++t) leaf_of[t] = (int32_t)c;
+    // edge lookup per (src, dst) super pair
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> out_init(P.nodes.size());
+    for (int32_t e : P.init_edges) out_init[P.edges[e].src].push_back({P.edges[e].dst, e});
+    std::vector<int64_t> idx((size_t)A->nnz);
+    for (int32_t r = 0; r < n; ++r) {
+        const int32_t tr = P.pos[r];
+        const int32_t sd = leaf_of[tr] >> 1;
+        const int32_t lr = tr - P.nodes[sd].dof0;
+        for (int64_t q = A->row_ptr[r]; q < A->row_ptr[r + 1]; ++q) {
+            const int32_t tc = P.pos[A->col_idx[q]];
+            const int32_t ss = leaf_of[tc] >> 1;
+            const int32_t lc = tc - P.nodes[ss].dof0;
+            int32_t e = -1;
+            for (auto& pr : out_init[ss]) if (pr.first == sd) { e = pr.second; break; }
+            if (e < 0) fail(LRX_EDEVICE, "internal: missing initial edge");
+            const PEdge& E = P.edges[e];
+            int32_t pr_ = E.rows.all ? lr : (int32_t)(std::lower_bound(E.rows.idx.begin(), E.rows.idx.end(), lr) - E.rows.idx.begin());
+            int32_t pc_ = E.cols.all ? lc : (int32_t)(std::lower_bound(E.cols.idx.begin(), E.cols.idx.end(), lc) - E.cols.idx.begin());
+            idx[q] = eoff[slot[e]] + pr_ + (int64_t)pc_ * nr_of(e);
+        }
+    }
+    if (A->nnz > 0) {
+        // the driver synchronizes before these temporaries are released
+        d_idx.ensure(idx.size() * 8);
+        HIPCHK(hipMemcpy(d_idx.p, idx.data(), idx.size() * 8, hipMemcpyHostToDevice));
+        const double* src = val_dev;
+        if (!src) {
+            d_val.ensure((size_t)A->nnz * 8);
+            HIPCHK(hipMemcpy(d_val.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice));
+            src = d_val.as<double>();
+        }
+        HIPCHK(launch_scatter(base, d_idx.as<int64_t>(), src, A->nnz, st));
+    }
+}
 
-    // ---------------- level loop
-    PinBuf stage_c, stage_n;              // descriptor staging (compress side, node side)
-    DevBuf d_desc_c, d_desc_n;
-    PinBuf pin_ranks;
-    DevBuf d_ranks, d_info;
-    DevBuf& ws = h->ws_b;
-    int32_t info_slots = 0;
-    {
-        int32_t npiv = 0;
-        for (auto& cs : P.steps) npiv += 2 * (int32_t)cs.nodes.size();
-        d_info.ensure(std::max(npiv, 1) * sizeof(int32_t));
-        HIPCHK(hipMemsetAsync(d_info.p, 0, std::max(npiv, 1) * sizeof(int32_t), st));
+void FactorRun::merge_tasks(const LevelPlan& L, hipStream_t st, std::vector<DMerge>& mt) {
+    for (int32_t s : L.supers) {
+        const PNode& nd = P.nodes[s];
+        h->size[s] = h->size[nd.comp0] + h->size[nd.comp1];
     }
-    int64_t flops = 0;
-    // mixed precision: the reduced QRs and Jacobi of the compression in FP32
-    // when FP32 resolves the cut-off (sigma_k / sigma_0 >= epsilon >= 1e-5)
-    const bool fp32_compress = h->precision == LRX_MIXED && h->epsilon >= 1e-5;
-    for (size_t li = 0; li < P.levels.size(); ++li) {
-        const LevelPlan& L = P.levels[li];
-        if (L.level < P.depth) {
-            for (int32_t s : L.supers) {
-                const PNode& nd = P.nodes[s];
-                h->size[s] = h->size[nd.comp0] + h->size[nd.comp1];
-            }
-            alloc_group(L.merge_edges);
-            std::vector<DMerge> mt;
-            for (const MergePiece& mp : L.merges) {
-                DMerge d;
-                d.src = blk(mp.src_edge);
-                d.dst = blk(mp.dst_edge);
-                const PEdge& D = P.edges[mp.dst_edge];
-                d.r0 = mp.row_hi ? h->size[P.nodes[D.dst].comp0] : 0;
-                d.c0 = mp.col_hi ? h->size[P.nodes[D.src].comp0] : 0;
-                if (d.src.nr * d.src.nc > 0) mt.push_back(d);
-            }
-            if (!mt.empty()) {
-                std::vector<char> buf;
-                size_t o = append_bytes(buf, mt);
-                SYNC(st);
-                stage_c.ensure(buf.size());
-                std::memcpy(stage_c.p, buf.data(), buf.size());
-                d_desc_c.ensure(buf.size());
-                HIPCHK(hipMemcpyAsync(d_desc_c.p, stage_c.p, buf.size(), hipMemcpyHostToDevice, st));
-                HIPCHK(launch_merge((const DMerge*)(d_desc_c.as<char>() + o), (int)mt.size(), st));
-                SYNC(st);
+    alloc_group(L.merge_edges, st);
+    for (const MergePiece& mp : L.merges) {
+        DMerge d;
+        d.src = blk(mp.src_edge);
+        d.dst = blk(mp.dst_edge);
+        const PEdge& D = P.edges[mp.dst_edge];
+        d.r0 = mp.row_hi ? h->size[P.nodes[D.dst].comp0] : 0;
+        d.c0 = mp.col_hi ? h->size[P.nodes[D.src].comp0] : 0;
+        if (d.src.nr * d.src.nc > 0) mt.push_back(d);
+    }
+}
+
+// Compress descriptors of the current step (Algorithm 1, stacked B of eqn.
+// cutOff1); returns the workspace this step needs, in doubles.
+size_t FactorRun::compress_tasks() {
+    const ColourStep& cs = P.steps[si];
+    const int nn = (int)cs.nodes.size();
+    const bool svd = h->compress == LRX_SVD;
+    ct.assign(nn, DCompress{});
+    pieces.clear();
+    a_row0.assign(nn, {});
+    b_row0.assign(nn, {});
+    wsB.assign(nn, 0); wsV.assign(nn, 0); wsH.assign(nn, 0); tail_at.assign(nn, 0);
+    ws_need = 0;
+    tails_total = 0;
+    for (int ni = 0; ni < nn; ++ni) {
+        const NodeStep& ns = cs.nodes[ni];
+        const NodeMaps& nm = maps[si][ni];
+        const int32_t ms = h->size[ns.s];
+        DCompress& T = ct[ni];
+        T.piece0 = (int32_t)pieces.size();
+        int32_t row = 0;
+        for (size_t k = 0; k < ns.cands.size(); ++k) {
+            const CandRef& cr = ns.cands[k];
+            a_row0[ni].push_back(row);
+            if (cr.e_sp >= 0) {
+                DPiece pc{};
+                pc.blk = blk(cr.e_sp); pc.trans = 0; pc.row0 = row; pc.map = mo(nm.a_map[k]);
+                row += pc.blk.nr;
+                if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
             }
         }
-        for (int32_t si = L.step0; si < L.step0 + L.nsteps; ++si) {
-            const ColourStep& cs = P.steps[si];
-            const int nn = (int)cs.nodes.size();
-            // ---- compress descriptors
-            std::vector<DCompress> ct(nn);
-            std::vector<DPiece> pieces;
-            std::vector<std::vector<int32_t>> a_row0(nn), b_row0(nn);
-            size_t ws_need = 0;
-            std::vector<size_t> wsB(nn), wsV(nn), wsH(nn), wsT(nn);
-            int max_c = 1, max_M = 1;
-            for (int ni = 0; ni < nn; ++ni) {
-                const NodeStep& ns = cs.nodes[ni];
-                const NodeMaps& nm = maps[si][ni];
-                const int32_t ms = h->size[ns.s];
-                DCompress& T = ct[ni];
-                T.piece0 = (int32_t)pieces.size();
-                int32_t row = 0;
-                for (size_t k = 0; k < ns.cands.size(); ++k) {
-                    const CandRef& cr = ns.cands[k];
-                    a_row0[ni].push_back(row);
-                    if (cr.e_sp >= 0) {
-                        DPiece pc{};
-                        pc.blk = blk(cr.e_sp); pc.trans = 0; pc.row0 = row; pc.map = nm.a_map[k];
-                        row += pc.blk.nr;
-                        if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
-                    }
-                }
-                for (size_t k = 0; k < ns.cands.size(); ++k) {
-                    const CandRef& cr = ns.cands[k];
-                    b_row0[ni].push_back(row);
-                    if (cr.e_ps >= 0) {
-                        DPiece pc{};
-                        pc.blk = blk(cr.e_ps); pc.trans = 1; pc.row0 = row; pc.map = nm.b_map[k];
-                        row += pc.blk.nc;
-                        if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
-                    }
-                }
-                T.npieces = (int32_t)pieces.size() - T.piece0;
-                T.M = row;
-                T.c = ns.gamma.count(ms);
-                T.eps = h->epsilon;
-                max_c = std::max(max_c, T.c);
-                max_M = std::max(max_M, T.M);
-                const bool svd = h->compress == LRX_SVD;
-                wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
-                wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
-                wsH[ni] = ws_need; ws_need += ((size_t)T.c * T.c + T.c + 31) & ~(size_t)31;
+        for (size_t k = 0; k < ns.cands.size(); ++k) {
+            const CandRef& cr = ns.cands[k];
+            b_row0[ni].push_back(row);
+            if (cr.e_ps >= 0) {
+                DPiece pc{};
+                pc.blk = blk(cr.e_ps); pc.trans = 1; pc.row0 = row; pc.map = mo(nm.b_map[k]);
+                row += pc.blk.nc;
+                if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
             }
-            size_t tails_total = 0;
-            for (int ni = 0; ni < nn; ++ni) { wsT[ni] = ws_need + tails_total; tails_total += (size_t)ct[ni].c + 2; }
-            const bool use_svd = h->compress == LRX_SVD;
-            ws_need += (tails_total + 31) & ~(size_t)31;
-            // node-side W workspace is sized after the ranks are known; reserve now
-            // for the worst case r <= c.
-            size_t w_need = 0;
-            for (int ni = 0; ni < nn; ++ni) {
-                const NodeStep& ns = cs.nodes[ni];
-                const int32_t ms = h->size[ns.s];
-                const int32_t rmax = std::min(ct[ni].c, ct[ni].M);
-                size_t sum_nc = 0;
-                for (int32_t e : ns.ps.in_edges) {
-                    const PEdge& E = P.edges[e];
-                    int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
-                    sum_nc += (size_t)dim_of(E.cols, srcsz);
-                }
-                w_need += (((size_t)ms * sum_nc) + 31) & ~(size_t)31;
-                size_t sum_nc_b = 0;
-                for (int32_t e : ns.pb.in_edges) {
-                    const PEdge& E = P.edges[e];
-                    int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
-                    sum_nc_b += (size_t)dim_of(E.cols, srcsz);
-                }
-                w_need += (((size_t)rmax * sum_nc_b) + 31) & ~(size_t)31;
+        }
+        T.npieces = (int32_t)pieces.size() - T.piece0;
+        T.M = row;
+        T.c = ns.gamma.count(ms);
+        T.eps = h->epsilon;
+        wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
+        wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
+        wsH[ni] = ws_need; ws_need += ((size_t)T.c * T.c + T.c + 31) & ~(size_t)31;
+        tail_at[ni] = tails_total;
+        tails_total += (size_t)T.c + 2;
+    }
+    // node-side W workspace, sized for the worst case r <= c before the ranks are known
+    w_need = 0;
+    for (int ni = 0; ni < nn; ++ni) {
+        const NodeStep& ns = cs.nodes[ni];
+        const int32_t ms = h->size[ns.s];
+        const int32_t rmax = std::min(ct[ni].c, ct[ni].M);
+        size_t sum_nc = 0;
+        for (int32_t e : ns.ps.in_edges) {
+            const PEdge& E = P.edges[e];
+            int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
+            sum_nc += (size_t)dim_of(E.cols, srcsz);
+        }
+        w_need += (((size_t)ms * sum_nc) + 31) & ~(size_t)31;
+        size_t sum_nc_b = 0;
+        for (int32_t e : ns.pb.in_edges) {
+            const PEdge& E = P.edges[e];
+            int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
+            sum_nc_b += (size_t)dim_of(E.cols, srcsz);
+        }
+        w_need += (((size_t)rmax * sum_nc_b) + 31) & ~(size_t)31;
+    }
+    return ws_need + w_need;
+}
+
+void FactorRun::bind_compress(double* wsp, int32_t* ranks_dev, double* tails_dev, int32_t piece_base) {
+    const bool svd = h->compress == LRX_SVD;
+    for (size_t ni = 0; ni < ct.size(); ++ni) {
+        DCompress& T = ct[ni];
+        T.piece0 += piece_base;
+        T.B = wsp + wsB[ni];
+        T.Bw = svd ? wsp + wsB[ni] + (size_t)T.M * T.c : nullptr;
+        T.V = wsp + wsV[ni];
+        T.hv = wsp + wsH[ni];
+        T.tails = tails_dev + tail_at[ni];
+        T.rank_out = ranks_dev + ni;
+    }
+}
+
+void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t st) {
+    const ColourStep& cs = P.steps[si];
+    const bool svd = h->compress == LRX_SVD;
+    for (size_t ni = 0; ni < cs.nodes.size(); ++ni) {
+        const NodeStep& ns = cs.nodes[ni];
+        const DCompress& T = ct[ni];
+        h->size[ns.b] = rk[ni];
+        h->size[ns.P] = rk[ni];
+        h->ranks.push_back(rk[ni]);
+        const double* tl = tails_h + tail_at[ni];
+        const bool emptyB = T.M == 0 || T.c == 0;
+        const int len = emptyB ? 1 : (svd ? T.c + 1 : rk[ni] + 2);
+        h->tail_off.push_back((int64_t)h->tails.size());
+        h->tails.insert(h->tails.end(), tl, tl + len);
+        double ratio = 0.0;
+        if (!emptyB && tl[0] > 0) {
+            if (svd) ratio = rk[ni] < T.c ? tl[1 + rk[ni]] / tl[0] : 0.0;
+            else ratio = tl[1 + rk[ni]] / tl[0];
+        }
+        h->max_tail_ratio = std::max(h->max_tail_ratio, ratio);
+        h->rank_level.push_back(cs.level);
+        h->rank_j.push_back(ns.j);
+        // flops of the stacked QR (and the Jacobi SVD), or of the pivoted QR
+        flops += svd ? 4ll * T.M * T.c * T.c : 4ll * T.M * T.c * rk[ni];
+    }
+    // the blocks created in this step
+    alloc_group(cs.new_edges, st);
+}
+
+// Preparation of every super-node (projection, rewiring, inverse of S), Schur
+// products of s, inverse of the black pivot B = -V^T S^{-1} V, Schur products
+// of b (Sec. 3.2, eqns. for Eliminate(s) and Eliminate(b)).
+void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
+    const ColourStep& cs = P.steps[si];
+    const int nn = (int)cs.nodes.size();
+    DevBuf& ws = h->ws_b;
+    double* wsp = ws.as<double>();
+    size_t wcur = ws_need;
+    const int64_t gf_s0 = nb.gf_s, gf_b0 = nb.gf_b, pf_s0 = nb.pf_s, pf_b0 = nb.pf_b;
+    auto schur = [&](const PivotPlan& pp, const PivMaps& pm, std::vector<DGemm>& g1, std::vector<DGemm>& g2,
+                     int64_t& gfl) {
+        const int32_t m = h->size[pp.node];
+        if (m == 0 || pp.e_self < 0) return;
+        const double* Sinv = h->eptr[pp.e_self];
+        std::vector<double*> W(pp.in_edges.size(), nullptr);
+        std::vector<DBlk> ib(pp.in_edges.size());
+        for (size_t i = 0; i < pp.in_edges.size(); ++i) {
+            ib[i] = blk(pp.in_edges[i]);
+            W[i] = wsp + wcur;
+            wcur += (((size_t)m * ib[i].nc) + 31) & ~(size_t)31;
+            if ((int64_t)ib[i].nr * ib[i].nc == 0) continue;
+            DGemm G{};
+            G.A = Sinv; G.lda = m; G.amap = mo(pm.in_rmap[i]);
+            G.B = ib[i].p; G.ldb = ib[i].nr; G.bmap = -1;
+            G.C = W[i]; G.ldc = m; G.crmap = -1; G.ccmap = -1;
+            G.M = m; G.N = ib[i].nc; G.K = ib[i].nr; G.sub = 0;
+            g1.push_back(G);
+            gfl += 2ll * m * ib[i].nr * ib[i].nc;
+        }
+        for (size_t q = 0; q < pp.pair_edge.size(); ++q) {
+            const int32_t qi = pp.pair_out[q], ki = pp.pair_in[q];
+            const DBlk O = blk(pp.out_edges[qi]);
+            const DBlk T = blk(pp.pair_edge[q]);
+            if ((int64_t)O.nr * O.nc * ib[ki].nc == 0) continue;
+            DGemm G{};
+            G.A = O.p; G.lda = O.nr; G.amap = -1;
+            G.B = W[ki]; G.ldb = m; G.bmap = mo(pm.out_cmap[qi]);
+            G.C = T.p; G.ldc = T.nr; G.crmap = mo(pm.pair_rpos[q]); G.ccmap = mo(pm.pair_cpos[q]);
+            G.M = O.nr; G.N = ib[ki].nc; G.K = O.nc; G.sub = 1;
+            g2.push_back(G);
+            gfl += 2ll * O.nr * O.nc * ib[ki].nc;
+        }
+    };
+    for (int ni = 0; ni < nn; ++ni) {
+        const NodeStep& ns = cs.nodes[ni];
+        DPrep T{};
+        const int32_t r = rk[ni];
+        T.r = r;
+        T.c = ct[ni].c;
+        T.M = ct[ni].M;
+        T.svd = h->compress == LRX_SVD ? 1 : 0;
+        T.B = ct[ni].B;
+        T.V = ct[ni].V;
+        T.do_proj = 1;
+        T.proj0 = (int32_t)nb.projs.size();
+        for (size_t k = 0; k < ns.cands.size(); ++k) {
+            const CandRef& cr = ns.cands[k];
+            if (cr.e_sp >= 0) {
+                DProj pj{};
+                pj.dst = blk(cr.e_Pp);
+                pj.row0 = a_row0[ni][k];
+                pj.nrows = nr_of(cr.e_sp);
+                pj.trans = 0;
+                pj.map = mo(maps[si][ni].ra_map[k]);
+                if (pj.nrows > 0 && r > 0) nb.projs.push_back(pj);
             }
-            const size_t ws_total = ws_need + w_need;
-            // The workspace is only touched by kernels on this stream, so the
-            // compress below may be queued behind the previous node kernel; the
-            // host staging buffers were released by the previous rank read-back.
-            // Growing the workspace frees it, which needs the stream idle.
-            if (ws_total * 8 > ws.bytes) {
-                SYNC(st);
-                ws.ensure(ws_total * 8 + (ws_total * 8) / 2);
+            if (cr.e_ps >= 0) {
+                DProj pj{};
+                pj.dst = blk(cr.e_pP);
+                pj.row0 = b_row0[ni][k];
+                pj.nrows = nc_of(cr.e_ps);
+                pj.trans = 1;
+                pj.map = mo(maps[si][ni].qb_map[k]);
+                if (pj.nrows > 0 && r > 0) nb.projs.push_back(pj);
             }
-            double* wsp = ws.as<double>();
-            d_ranks.ensure(std::max(nn, 1) * sizeof(int32_t));
-            for (int ni = 0; ni < nn; ++ni) {
-                ct[ni].B = wsp + wsB[ni];
-                ct[ni].Bw = use_svd ? wsp + wsB[ni] + (size_t)ct[ni].M * ct[ni].c : nullptr;
-                ct[ni].V = wsp + wsV[ni];
-                ct[ni].hv = wsp + wsH[ni];
-                ct[ni].tails = wsp + wsT[ni];
-                ct[ni].rank_out = d_ranks.as<int32_t>() + ni;
+        }
+        T.nproj = (int32_t)nb.projs.size() - T.proj0;
+        T.sb = blk(ns.e_sb);
+        T.bs = blk(ns.e_bs);
+        T.bP = blk(ns.e_bP);
+        T.Pb = blk(ns.e_Pb);
+        T.piv = blk(ns.ps.e_self);
+        T.info_slot = info_base + info_next++;
+        nb.max_ms = std::max(nb.max_ms, (int)T.piv.nr);
+        nb.pf_s += 2ll * T.piv.nr * T.piv.nr * T.piv.nr + 2ll * T.M * T.c * r;
+        nb.prep_s.push_back(T);
+        DPrep U{};
+        U.piv = blk(ns.pb.e_self);
+        U.info_slot = info_base + info_next++;
+        U.do_proj = 0;
+        nb.max_mb = std::max(nb.max_mb, (int)U.piv.nr);
+        nb.pf_b += 2ll * U.piv.nr * U.piv.nr * U.piv.nr;
+        nb.prep_b.push_back(U);
+        schur(ns.ps, maps[si][ni].ps, nb.g1s, nb.g2s, nb.gf_s);
+        schur(ns.pb, maps[si][ni].pb, nb.g1b, nb.g2b, nb.gf_b);
+    }
+    flops += (nb.pf_s - pf_s0) + (nb.pf_b - pf_b0) + (nb.gf_s - gf_s0) + (nb.gf_b - gf_b0);
+    if (wcur * 8 > ws.bytes) fail(LRX_EDEVICE, "internal: workspace estimate too small");
+}
+
+// The level loop over one or several factorizations sharing the stream st.
+// Throws on failure; the caller frees the handles.
+void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::vector<const lrx_csr*>& A,
+                const std::vector<const double*>& val_dev) {
+    double t_sync = 0.0;
+    int64_t epoch = 0;                   // number of stream synchronizations so far
+    auto sync = [&]() {
+        const double ts = now_ms();
+        HIPCHK(hipStreamSynchronize(st));
+        t_sync += now_ms() - ts;
+        ++epoch;
+    };
+    std::vector<int32_t> imap;
+    int32_t info_total = 0;
+    size_t max_h = 0;
+    for (size_t i = 0; i < runs.size(); ++i) {
+        FactorRun& r = *runs[i];
+        r.setup(A[i], val_dev[i], st);
+        if ((int64_t)imap.size() + (int64_t)r.imap.size() > INT32_MAX) fail(LRX_ENOMEM, "index tables exceed 2^31 entries");
+        r.imap_base = (int32_t)imap.size();
+        imap.insert(imap.end(), r.imap.begin(), r.imap.end());
+        std::vector<int32_t>().swap(r.imap);
+        r.info_base = info_total;
+        info_total += r.info_count;
+        max_h = std::max(max_h, r.level_at_height.size());
+    }
+    DevBuf d_imap, d_info;
+    d_imap.ensure(std::max<size_t>(imap.size(), 1) * sizeof(int32_t));
+    if (!imap.empty())
+        HIPCHK(hipMemcpyAsync(d_imap.p, imap.data(), imap.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const int32_t* dmap = d_imap.as<int32_t>();
+    d_info.ensure(std::max(info_total, 1) * sizeof(int32_t));
+    HIPCHK(hipMemsetAsync(d_info.p, 0, std::max(info_total, 1) * sizeof(int32_t), st));
+    sync();
+    for (FactorRun* r : runs) { r->d_idx.release(); r->d_val.release(); }
+
+    PinBuf stage_m, stage_c, stage_n, pin_rt;   // descriptor staging, rank read-back
+    DevBuf d_desc_m, d_desc_c, d_desc_n, d_rt;
+    int64_t m_epoch = -1;                       // epoch of the last merge upload
+    for (size_t hgt = 0; hgt < max_h; ++hgt) {
+        std::vector<FactorRun*> lv;
+        std::vector<DMerge> mt;
+        int32_t ncol = 0;
+        for (FactorRun* r : runs) {
+            if (hgt >= r->level_at_height.size() || r->level_at_height[hgt] < 0) continue;
+            const LevelPlan& L = r->P.levels[r->level_at_height[hgt]];
+            if (L.level < r->P.depth) r->merge_tasks(L, st, mt);
+            lv.push_back(r);
+            ncol = std::max(ncol, L.nsteps);
+        }
+        if (!mt.empty()) {
+            // the previous merge upload may still read stage_m, its kernel d_desc_m
+            if (m_epoch == epoch) sync();
+            std::vector<char> buf;
+            const size_t o = append_bytes(buf, mt);
+            stage_m.ensure(buf.size());
+            std::memcpy(stage_m.p, buf.data(), buf.size());
+            d_desc_m.ensure(buf.size());
+            HIPCHK(hipMemcpyAsync(d_desc_m.p, stage_m.p, buf.size(), hipMemcpyHostToDevice, st));
+            HIPCHK(launch_merge((const DMerge*)(d_desc_m.as<char>() + o), (int)mt.size(), st));
+            m_epoch = epoch;
+        }
+        for (int32_t c = 0; c < ncol; ++c) {
+            std::vector<FactorRun*> part;
+            for (FactorRun* r : lv) {
+                const LevelPlan& L = r->P.levels[r->level_at_height[hgt]];
+                if (c >= L.nsteps) continue;
+                r->si = L.step0 + c;
+                part.push_back(r);
+            }
+            // ---- compress: descriptors, workspace, one launch per kernel variant
+            bool grow = false;
+            std::vector<size_t> wst(part.size());
+            for (size_t i = 0; i < part.size(); ++i) {
+                wst[i] = part[i]->compress_tasks();
+                grow |= wst[i] * 8 > part[i]->h->ws_b.bytes;
+            }
+            // the workspace is only touched by kernels on this stream; growing it
+            // frees it, which needs the stream idle
+            if (grow) {
+                sync();
+                for (size_t i = 0; i < part.size(); ++i)
+                    if (wst[i] * 8 > part[i]->h->ws_b.bytes) part[i]->h->ws_b.ensure(wst[i] * 8 + (wst[i] * 8) / 2);
+            }
+            int64_t ntask = 0, ntail = 0;
+            for (FactorRun* r : part) {
+                r->task0 = ntask;
+                r->tails0 = ntail;
+                ntask += (int64_t)r->ct.size();
+                ntail += (int64_t)r->tails_total;
+            }
+            const size_t tails_off = ((size_t)ntask * 4 + 255) & ~(size_t)255;
+            const size_t rt_bytes = tails_off + (size_t)ntail * 8;
+            d_rt.ensure(rt_bytes);    // its last reader, the previous read-back, has completed
+            std::vector<DCompress> all;
+            std::vector<DPiece> allp;
+            std::vector<int32_t> fp32_of;
+            all.reserve(ntask);
+            for (FactorRun* r : part) {
+                r->bind_compress(r->h->ws_b.as<double>(), d_rt.as<int32_t>() + r->task0,
+                                 (double*)(d_rt.as<char>() + tails_off) + r->tails0, (int32_t)allp.size());
+                all.insert(all.end(), r->ct.begin(), r->ct.end());
+                allp.insert(allp.end(), r->pieces.begin(), r->pieces.end());
+                for (size_t q = 0; q < r->ct.size(); ++q)
+                    fp32_of.push_back((r->h->compress == LRX_SVD ? 0 : 4) | (r->fp32_compress ? 1 : 0));
+            }
+            // variants: SVD with c <= 64 (FP64 / FP32 arithmetic), SVD with c > 64,
+            // pivoted QR; each task takes its own variant whatever the others are
+            struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0; size_t off = 0; };
+            std::vector<Group> groups;
+            for (size_t q = 0; q < all.size(); ++q) {
+                const int key = fp32_of[q] == 4 || fp32_of[q] == 5 ? 4 : (all[q].c <= 64 ? fp32_of[q] : 2);
+                size_t g = 0;
+                while (g < groups.size() && groups[g].key != key) ++g;
+                if (g == groups.size()) { groups.push_back(Group{}); groups[g].key = key; }
+                Group& G = groups[g];
+                G.t.push_back(all[q]);
+                G.max_c = std::max(G.max_c, (int)all[q].c);
+                G.max_M = std::max(G.max_M, (int)all[q].M);
+                const double M = all[q].M, cc = all[q].c;
+                G.fl += key == 4 ? 4.0 * M * cc * cc : 4.0 * M * cc * cc + 8.0 * 6.0 * cc * cc * cc;
             }
             {
                 std::vector<char> buf;
-                size_t o1 = append_bytes(buf, ct);
-                size_t o2 = append_bytes(buf, pieces);
+                for (Group& G : groups) G.off = append_bytes(buf, G.t);
+                const size_t op = append_bytes(buf, allp);
                 stage_c.ensure(buf.size());
                 std::memcpy(stage_c.p, buf.data(), buf.size());
                 d_desc_c.ensure(buf.size());
                 HIPCHK(hipMemcpyAsync(d_desc_c.p, stage_c.p, buf.size(), hipMemcpyHostToDevice, st));
-                double cfl = 0;
-                for (int ni = 0; ni < nn; ++ni)
-                    cfl += use_svd ? 4.0 * ct[ni].M * ct[ni].c * ct[ni].c + 8.0 * 6.0 * ct[ni].c * ct[ni].c * ct[ni].c
-                                   : 4.0 * ct[ni].M * ct[ni].c * ct[ni].c;
-                LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, cfl);
-                if (use_svd)
-                    HIPCHK(launch_compress_svd((const DCompress*)(d_desc_c.as<char>() + o1), nn,
-                                               (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c,
-                                               max_M, fp32_compress, st));
-                else
-                    HIPCHK(launch_compress((const DCompress*)(d_desc_c.as<char>() + o1), nn,
-                                           (const DPiece*)(d_desc_c.as<char>() + o2), d_imap, max_c, st));
+                const DPiece* dp = (const DPiece*)(d_desc_c.as<char>() + op);
+                for (Group& G : groups) {
+                    const DCompress* dt = (const DCompress*)(d_desc_c.as<char>() + G.off);
+                    LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, G.fl);
+                    if (G.key == 4)
+                        HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, st));
+                    else
+                        HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
+                                                   (G.key & 1) != 0, st));
+                }
             }
-            pin_ranks.ensure(std::max(nn, 1) * sizeof(int32_t) + tails_total * 8 + 64);
-            HIPCHK(hipMemcpyAsync(pin_ranks.p, d_ranks.p, nn * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            double* tails_h = (double*)((char*)pin_ranks.p + (((size_t)nn * 4 + 63) & ~(size_t)63));
-            if (tails_total)
-                HIPCHK(hipMemcpyAsync(tails_h, wsp + wsT[0], tails_total * 8, hipMemcpyDeviceToHost, st));
-            SYNC(st);
-            const int32_t* rk = (const int32_t*)pin_ranks.p;
-            for (int ni = 0; ni < nn; ++ni) {
-                const NodeStep& ns = cs.nodes[ni];
-                h->size[ns.b] = rk[ni];
-                h->size[ns.P] = rk[ni];
-                h->ranks.push_back(rk[ni]);
-                {
-                    const double* tl = tails_h + (wsT[ni] - wsT[0]);
-                    const bool emptyB = ct[ni].M == 0 || ct[ni].c == 0;
-                    const int len = emptyB ? 1 : (use_svd ? ct[ni].c + 1 : rk[ni] + 2);
-                    h->tail_off.push_back((int64_t)h->tails.size());
-                    h->tails.insert(h->tails.end(), tl, tl + len);
-                    double ratio = 0.0;
-                    if (!emptyB && tl[0] > 0) {
-                        if (use_svd) ratio = rk[ni] < ct[ni].c ? tl[1 + rk[ni]] / tl[0] : 0.0;
-                        else ratio = tl[1 + rk[ni]] / tl[0];
-                    }
-                    h->max_tail_ratio = std::max(h->max_tail_ratio, ratio);
-                }
-                h->rank_level.push_back(cs.level);
-                h->rank_j.push_back(ns.j);
-                // flops of the pivoted QR: ~4 M c r
-                flops += use_svd ? 4ll * ct[ni].M * ct[ni].c * ct[ni].c : 4ll * ct[ni].M * ct[ni].c * rk[ni];
-            }
-            // ---- allocate the blocks created in this step
-            alloc_group(cs.new_edges);
-            // ---- node descriptors: preparation of every super-node (projection,
-            //      rewiring, inverse of S), Schur products of s, inverse of the
-            //      black pivot B = -V^T S^{-1} V, Schur products of b
-            std::vector<DPrep> prep_s(nn), prep_b(nn);
-            std::vector<DProj> projs;
-            std::vector<DGemm> g1s, g2s, g1b, g2b;
-            size_t wcur = ws_need;
-            int max_ms = 1, max_mb = 1;
-            int64_t pf_s = 0, pf_b = 0, gf_s = 0, gf_b = 0;
-            auto schur = [&](const PivotPlan& pp, const PivMaps& pm, std::vector<DGemm>& g1,
-                             std::vector<DGemm>& g2, int64_t& gfl) {
-                const int32_t m = h->size[pp.node];
-                if (m == 0 || pp.e_self < 0) return;
-                const double* Sinv = h->eptr[pp.e_self];
-                std::vector<double*> W(pp.in_edges.size(), nullptr);
-                std::vector<DBlk> ib(pp.in_edges.size());
-                for (size_t i = 0; i < pp.in_edges.size(); ++i) {
-                    ib[i] = blk(pp.in_edges[i]);
-                    W[i] = wsp + wcur;
-                    wcur += (((size_t)m * ib[i].nc) + 31) & ~(size_t)31;
-                    if ((int64_t)ib[i].nr * ib[i].nc == 0) continue;
-                    DGemm G{};
-                    G.A = Sinv; G.lda = m; G.amap = pm.in_rmap[i];
-                    G.B = ib[i].p; G.ldb = ib[i].nr; G.bmap = -1;
-                    G.C = W[i]; G.ldc = m; G.crmap = -1; G.ccmap = -1;
-                    G.M = m; G.N = ib[i].nc; G.K = ib[i].nr; G.sub = 0;
-                    g1.push_back(G);
-                    gfl += 2ll * m * ib[i].nr * ib[i].nc;
-                }
-                for (size_t q = 0; q < pp.pair_edge.size(); ++q) {
-                    const int32_t qi = pp.pair_out[q], ki = pp.pair_in[q];
-                    const DBlk O = blk(pp.out_edges[qi]);
-                    const DBlk T = blk(pp.pair_edge[q]);
-                    if ((int64_t)O.nr * O.nc * ib[ki].nc == 0) continue;
-                    DGemm G{};
-                    G.A = O.p; G.lda = O.nr; G.amap = -1;
-                    G.B = W[ki]; G.ldb = m; G.bmap = pm.out_cmap[qi];
-                    G.C = T.p; G.ldc = T.nr; G.crmap = pm.pair_rpos[q]; G.ccmap = pm.pair_cpos[q];
-                    G.M = O.nr; G.N = ib[ki].nc; G.K = O.nc; G.sub = 1;
-                    g2.push_back(G);
-                    gfl += 2ll * O.nr * O.nc * ib[ki].nc;
-                }
-            };
-            for (int ni = 0; ni < nn; ++ni) {
-                const NodeStep& ns = cs.nodes[ni];
-                DPrep& T = prep_s[ni];
-                const int32_t r = rk[ni];
-                T.r = r;
-                T.c = ct[ni].c;
-                T.M = ct[ni].M;
-                T.svd = use_svd ? 1 : 0;
-                T.B = ct[ni].B;
-                T.V = ct[ni].V;
-                T.do_proj = 1;
-                T.proj0 = (int32_t)projs.size();
-                for (size_t k = 0; k < ns.cands.size(); ++k) {
-                    const CandRef& cr = ns.cands[k];
-                    if (cr.e_sp >= 0) {
-                        DProj pj{};
-                        pj.dst = blk(cr.e_Pp);
-                        pj.row0 = a_row0[ni][k];
-                        pj.nrows = nr_of(cr.e_sp);
-                        pj.trans = 0;
-                        pj.map = maps[si][ni].ra_map[k];
-                        if (pj.nrows > 0 && r > 0) projs.push_back(pj);
-                    }
-                    if (cr.e_ps >= 0) {
-                        DProj pj{};
-                        pj.dst = blk(cr.e_pP);
-                        pj.row0 = b_row0[ni][k];
-                        pj.nrows = nc_of(cr.e_ps);
-                        pj.trans = 1;
-                        pj.map = maps[si][ni].qb_map[k];
-                        if (pj.nrows > 0 && r > 0) projs.push_back(pj);
-                    }
-                }
-                T.nproj = (int32_t)projs.size() - T.proj0;
-                T.sb = blk(ns.e_sb);
-                T.bs = blk(ns.e_bs);
-                T.bP = blk(ns.e_bP);
-                T.Pb = blk(ns.e_Pb);
-                T.piv = blk(ns.ps.e_self);
-                T.info_slot = info_slots++;
-                max_ms = std::max(max_ms, (int)T.piv.nr);
-                pf_s += 2ll * T.piv.nr * T.piv.nr * T.piv.nr + 2ll * T.M * T.c * r;
-                DPrep& U = prep_b[ni];
-                U.piv = blk(ns.pb.e_self);
-                U.info_slot = info_slots++;
-                U.do_proj = 0;
-                max_mb = std::max(max_mb, (int)U.piv.nr);
-                pf_b += 2ll * U.piv.nr * U.piv.nr * U.piv.nr;
-                schur(ns.ps, maps[si][ni].ps, g1s, g2s, gf_s);
-                schur(ns.pb, maps[si][ni].pb, g1b, g2b, gf_b);
-            }
-            flops += pf_s + pf_b + gf_s + gf_b;
-            if (wcur * 8 > ws.bytes) fail(LRX_EDEVICE, "internal: workspace estimate too small");
+            pin_rt.ensure(rt_bytes);
+            if (rt_bytes) HIPCHK(hipMemcpyAsync(pin_rt.p, d_rt.p, rt_bytes, hipMemcpyDeviceToHost, st));
+            sync();
+            const int32_t* rk = (const int32_t*)pin_rt.p;
+            const double* tails_h = (const double*)((const char*)pin_rt.p + tails_off);
+            for (FactorRun* r : part) r->take_ranks(rk + r->task0, tails_h + r->tails0, st);
+            // ---- node tasks of every participating factorization
+            NodeBatch nb;
+            for (FactorRun* r : part) r->node_tasks(rk + r->task0, nb);
             auto tiles_of = [](const std::vector<DGemm>& gs, int& kmax) {
                 std::vector<DTile> t;
                 kmax = 1;
@@ -726,56 +863,59 @@ void run_factor(lrx_handle h, const lrx_csr* A, const double* val_dev) {
                 return t;
             };
             int k1s, k2s, k1b, k2b;
-            const std::vector<DTile> t1s = tiles_of(g1s, k1s), t2s = tiles_of(g2s, k2s);
-            const std::vector<DTile> t1b = tiles_of(g1b, k1b), t2b = tiles_of(g2b, k2b);
+            const std::vector<DTile> t1s = tiles_of(nb.g1s, k1s), t2s = tiles_of(nb.g2s, k2s);
+            const std::vector<DTile> t1b = tiles_of(nb.g1b, k1b), t2b = tiles_of(nb.g2b, k2b);
+            std::vector<char> buf;
+            const size_t o_ps = append_bytes(buf, nb.prep_s), o_pj = append_bytes(buf, nb.projs);
+            const size_t o_pb = append_bytes(buf, nb.prep_b);
+            const size_t o_g1s = append_bytes(buf, nb.g1s), o_t1s = append_bytes(buf, t1s);
+            const size_t o_g2s = append_bytes(buf, nb.g2s), o_t2s = append_bytes(buf, t2s);
+            const size_t o_g1b = append_bytes(buf, nb.g1b), o_t1b = append_bytes(buf, t1b);
+            const size_t o_g2b = append_bytes(buf, nb.g2b), o_t2b = append_bytes(buf, t2b);
+            // the previous step's node kernels completed before the read-back above
+            stage_n.ensure(buf.size());
+            std::memcpy(stage_n.p, buf.data(), buf.size());
+            d_desc_n.ensure(buf.size());
+            HIPCHK(hipMemcpyAsync(d_desc_n.p, stage_n.p, buf.size(), hipMemcpyHostToDevice, st));
+            char* b = d_desc_n.as<char>();
+            int32_t* inf = d_info.as<int32_t>();
+            const int np = (int)nb.prep_s.size();
+            auto gemm = [&](size_t og, size_t ot, const std::vector<DTile>& t, int kmax, int64_t fl) {
+                if (t.empty()) return;
+                LaunchTimer tm(LRX_K_SCHUR, st, 0.0, (double)fl);
+                HIPCHK(launch_gemm_tiles((const DGemm*)(b + og), (const DTile*)(b + ot), (int)t.size(), kmax, dmap,
+                                         st));
+            };
             {
-                std::vector<char> buf;
-                const size_t o_ps = append_bytes(buf, prep_s), o_pj = append_bytes(buf, projs);
-                const size_t o_pb = append_bytes(buf, prep_b);
-                const size_t o_g1s = append_bytes(buf, g1s), o_t1s = append_bytes(buf, t1s);
-                const size_t o_g2s = append_bytes(buf, g2s), o_t2s = append_bytes(buf, t2s);
-                const size_t o_g1b = append_bytes(buf, g1b), o_t1b = append_bytes(buf, t1b);
-                const size_t o_g2b = append_bytes(buf, g2b), o_t2b = append_bytes(buf, t2b);
-                stage_n.ensure(buf.size());
-                std::memcpy(stage_n.p, buf.data(), buf.size());
-                d_desc_n.ensure(buf.size());
-                HIPCHK(hipMemcpyAsync(d_desc_n.p, stage_n.p, buf.size(), hipMemcpyHostToDevice, st));
-                char* b = d_desc_n.as<char>();
-                int32_t* inf = d_info.as<int32_t>();
-                auto gemm = [&](size_t og, size_t ot, const std::vector<DTile>& t, int kmax, int64_t fl) {
-                    if (t.empty()) return;
-                    LaunchTimer tm(LRX_K_SCHUR, st, 0.0, (double)fl);
-                    HIPCHK(launch_gemm_tiles((const DGemm*)(b + og), (const DTile*)(b + ot), (int)t.size(), kmax,
-                                             d_imap, st));
-                };
-                {
-                    LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)pf_s);
-                    HIPCHK(launch_node_prep((const DPrep*)(b + o_ps), nn, max_ms, (const DProj*)(b + o_pj), d_imap,
-                                            inf, st));
-                }
-                gemm(o_g1s, o_t1s, t1s, k1s, 0);
-                gemm(o_g2s, o_t2s, t2s, k2s, gf_s);
-                {
-                    LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)pf_b);
-                    HIPCHK(launch_node_prep((const DPrep*)(b + o_pb), nn, max_mb, nullptr, d_imap, inf, st));
-                }
-                gemm(o_g1b, o_t1b, t1b, k1b, 0);
-                gemm(o_g2b, o_t2b, t2b, k2b, gf_b);
+                LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_s);
+                HIPCHK(launch_node_prep((const DPrep*)(b + o_ps), np, nb.max_ms, (const DProj*)(b + o_pj), dmap,
+                                        inf, st));
             }
+            gemm(o_g1s, o_t1s, t1s, k1s, 0);
+            gemm(o_g2s, o_t2s, t2s, k2s, nb.gf_s);
+            {
+                LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_b);
+                HIPCHK(launch_node_prep((const DPrep*)(b + o_pb), np, nb.max_mb, nullptr, dmap, inf, st));
+            }
+            gemm(o_g1b, o_t1b, t1b, k1b, 0);
+            gemm(o_g2b, o_t2b, t2b, k2b, nb.gf_b);
         }
     }
-    SYNC(st);
-    {
-        std::vector<int32_t> info(std::max(info_slots, 1));
-        HIPCHK(hipMemcpy(info.data(), d_info.p, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-        for (int32_t v : info)
-            if (v) fail(LRX_ESINGULAR, "exactly singular pivot block");
+    sync();
+    std::vector<int32_t> info(std::max(info_total, 1));
+    HIPCHK(hipMemcpy(info.data(), d_info.p, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < runs.size(); ++i) {
+        FactorRun& r = *runs[i];
+        for (int32_t q = 0; q < r.info_count; ++q)
+            if (info[r.info_base + q])
+                fail(LRX_ESINGULAR, runs.size() > 1 ? "exactly singular pivot block in system " + std::to_string(i)
+                                                    : std::string("exactly singular pivot block"));
+        r.h->stats.factor_flops = r.flops;
+        r.h->t_sync_ms += t_sync;
     }
-    h->stats.factor_flops = flops;
 }
 
 // ------------------------------------------------------------------ solve program
-#undef SYNC
 
 void build_solve_program(lrx_handle h) {
     const double t_begin = now_ms();
@@ -1259,6 +1399,189 @@ template <class F> lrx_status guarded(F&& f) {
 }  // namespace
 
 // ====================================================================== C ABI
+namespace {
+
+void check_factor_args(const lrx_csr* A, const double* val_dev, const lrx_tree* T, const lrx_opts* o) {
+    if (!T || !o) fail(LRX_EINVAL, "null tree or options");
+    if (val_dev) {
+        if (!A || A->n < 1 || A->nnz < 0 || !A->row_ptr || !A->col_idx) fail(LRX_EINVAL, "bad CSR pattern");
+    } else {
+        check_csr(A);
+    }
+    if (!(o->epsilon >= 0.0 && o->epsilon < 1.0)) fail(LRX_EINVAL, "epsilon must be in [0, 1)");
+    if (o->precision != LRX_FP64 && o->precision != LRX_MIXED)
+        fail(LRX_EINVAL, "precision must be LRX_FP64 or LRX_MIXED");
+    if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
+    if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
+}
+
+// Options, device, and A in tree order (for the GMRES products) of a handle
+// whose plan is built.
+void init_handle(lrx_handle h, const lrx_csr* A, const double* val_dev, const lrx_opts* o) {
+    HIPCHK(hipGetDevice(&h->device));
+    ensure_gfx950(h->device);
+    h->stream = (hipStream_t)o->stream;
+    h->epsilon = o->epsilon;
+    h->compress = o->compress;
+    h->precision = o->precision;
+    h->arena.budget_bytes = o->hbm_budget_bytes;
+    const int32_t n = A->n;
+    const Plan& P = h->plan;
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> ci((size_t)A->nnz);
+    std::vector<int64_t> src_of((size_t)A->nnz);
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t r = P.perm[t];
+        rp[t + 1] = rp[t] + (A->row_ptr[r + 1] - A->row_ptr[r]);
+    }
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t r = P.perm[t];
+        int64_t q = rp[t];
+        for (int64_t e = A->row_ptr[r]; e < A->row_ptr[r + 1]; ++e, ++q) {
+            ci[q] = P.pos[A->col_idx[e]];
+            src_of[q] = e;
+        }
+    }
+    h->nnz = A->nnz;
+    h->d_rp.ensure(rp.size() * 8);
+    h->d_ci.ensure(std::max<size_t>(ci.size(), 1) * 4);
+    h->d_val.ensure(std::max<size_t>(ci.size(), 1) * 8);
+    h->d_perm.ensure((size_t)n * 4);
+    const hipStream_t s0 = h->stream;
+    HIPCHK(hipMemcpyAsync(h->d_rp.p, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, s0));
+    HIPCHK(hipMemcpyAsync(h->d_perm.p, P.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
+    if (A->nnz) {
+        HIPCHK(hipMemcpyAsync(h->d_ci.p, ci.data(), ci.size() * 4, hipMemcpyHostToDevice, s0));
+        DevBuf d_src, d_vh;
+        d_src.ensure(src_of.size() * 8);
+        HIPCHK(hipMemcpyAsync(d_src.p, src_of.data(), src_of.size() * 8, hipMemcpyHostToDevice, s0));
+        const double* vsrc = val_dev;
+        if (!vsrc) {
+            d_vh.ensure((size_t)A->nnz * 8);
+            HIPCHK(hipMemcpyAsync(d_vh.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice, s0));
+            vsrc = d_vh.as<double>();
+        } else {
+            DevBuf d_cnt;
+            d_cnt.ensure(8);
+            HIPCHK(launch_count_nonfinite(vsrc, A->nnz, d_cnt.as<int64_t>(), s0));
+            int64_t bad = 0;
+            HIPCHK(hipMemcpyAsync(&bad, d_cnt.p, 8, hipMemcpyDeviceToHost, s0));
+            HIPCHK(hipStreamSynchronize(s0));
+            if (bad) fail(LRX_EINVAL, "non-finite value in A");
+        }
+        HIPCHK(launch_gather_idx(h->d_val.as<double>(), vsrc, d_src.as<int64_t>(), A->nnz, s0));
+        HIPCHK(hipStreamSynchronize(s0));     // d_src, d_vh go out of scope
+    } else {
+        HIPCHK(hipStreamSynchronize(s0));     // rp and the host vectors go out of scope
+    }
+}
+
+void finish_stats(lrx_handle h, double t_plan_ms, double t_factor_ms) {
+    const Plan& P = h->plan;
+    lrx_stats_t& S = h->stats;
+    S.depth = P.depth;
+    S.n_compressions = (int32_t)h->ranks.size();
+    S.n_colour_steps = (int32_t)P.steps.size();
+    double rs = 0;
+    int32_t rmax = 0;
+    std::vector<double> lsum(33, 0), lcnt(33, 0);
+    for (size_t i = 0; i < h->ranks.size(); ++i) {
+        rs += h->ranks[i];
+        rmax = std::max(rmax, h->ranks[i]);
+        int lv = h->rank_level[i];
+        if (lv < 32) {
+            S.rank_max_by_level[lv] = std::max(S.rank_max_by_level[lv], h->ranks[i]);
+            lsum[lv] += h->ranks[i];
+            lcnt[lv] += 1;
+        }
+    }
+    for (auto& L : P.levels)
+        if (L.level < 32) {
+            double ms = 0;
+            for (int32_t s : L.supers) ms += h->size[s];
+            S.mean_node_size_by_level[L.level] = L.supers.empty() ? 0 : ms / L.supers.size();
+        }
+    for (int lv = 0; lv < 32; ++lv) S.rank_mean_by_level[lv] = lcnt[lv] ? lsum[lv] / lcnt[lv] : 0.0;
+    S.max_rank = rmax;
+    S.mean_rank = h->ranks.empty() ? 0.0 : rs / h->ranks.size();
+    S.extended_size = h->n_ext;
+    S.max_compression_error = h->max_tail_ratio;
+    S.factor_bytes = (h->solve_fp32 ? h->arena32.total : h->arena.total) * 8;
+    S.t_plan_ms = t_plan_ms;
+    S.t_factor_ms = t_factor_ms;
+    S.t_sync_ms = h->t_sync_ms;
+    S.t_solve_prog_ms = h->t_solve_prog_ms;
+}
+
+// Factorization of k systems (k = 1: lrx_factor); see lrx_factor_batch.
+void factor_many(int32_t k, const lrx_csr* A, const double* const* val_dev, const lrx_tree* T, const lrx_opts* o,
+                 lrx_handle* out) {
+    const double t0 = now_ms();
+    std::vector<std::unique_ptr<lrx_handle_s>> hs(k);
+    for (int32_t i = 0; i < k; ++i) {
+        try {
+            check_factor_args(&A[i], val_dev[i], &T[i], o);
+        } catch (Fail& f) {
+            if (k > 1) f.msg = "system " + std::to_string(i) + ": " + f.msg;
+            throw;
+        }
+        hs[i].reset(new lrx_handle_s());
+    }
+    // symbolic plans on host threads
+    std::vector<std::string> errs(k);
+    std::vector<double> t_plan(k, 0.0);
+    {
+        std::atomic<int32_t> next{0};
+        auto work = [&]() {
+            for (int32_t i; (i = next.fetch_add(1)) < k;) {
+                const double ta = now_ms();
+                try {
+                    errs[i] = build_plan(A[i].n, A[i].nnz, A[i].row_ptr, A[i].col_idx, T[i].depth, T[i].perm,
+                                         T[i].leaf_ptr, o->order, hs[i]->plan);
+                } catch (const std::exception& e) {
+                    errs[i] = std::string("planner: ") + e.what();
+                }
+                t_plan[i] = now_ms() - ta;
+            }
+        };
+        const int nt = (int)std::min<int64_t>(k, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+        if (nt <= 1) {
+            work();
+        } else {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nt; ++t) th.emplace_back(work);
+            for (auto& t : th) t.join();
+        }
+    }
+    for (int32_t i = 0; i < k; ++i)
+        if (!errs[i].empty()) fail(LRX_EINVAL, k > 1 ? "system " + std::to_string(i) + ": " + errs[i] : errs[i]);
+    const double t1 = now_ms();
+    std::vector<std::unique_ptr<FactorRun>> runs;
+    std::vector<FactorRun*> rp;
+    std::vector<const lrx_csr*> ap;
+    std::vector<const double*> vp;
+    for (int32_t i = 0; i < k; ++i) {
+        init_handle(hs[i].get(), &A[i], val_dev[i], o);
+        runs.emplace_back(new FactorRun(hs[i].get()));
+        rp.push_back(runs.back().get());
+        ap.push_back(&A[i]);
+        vp.push_back(val_dev[i]);
+    }
+    run_factor(rp, (hipStream_t)o->stream, ap, vp);
+    runs.clear();
+    for (int32_t i = 0; i < k; ++i) build_solve_program(hs[i].get());
+    HIPCHK(hipStreamSynchronize((hipStream_t)o->stream));
+    const double t2 = now_ms();
+    for (int32_t i = 0; i < k; ++i) finish_stats(hs[i].get(), k > 1 ? t_plan[i] : t1 - t0, t2 - t0);
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    for (int32_t i = 0; i < k; ++i) {
+        out[i] = hs[i].release();
+        g_live.insert(out[i]);
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lrx_last_error(void) { return g_err.c_str(); }
@@ -1294,148 +1617,40 @@ lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order, 
     });
 }
 
-static lrx_status factor_impl(const lrx_csr* A, const double* val_dev, const lrx_tree* T,
-                              const lrx_opts* o, lrx_handle* out) {
-    lrx_handle h = nullptr;
-    lrx_status st = guarded([&]() -> lrx_status {
-        const double t0 = now_ms();
+lrx_status lrx_factor(const lrx_csr* A, const lrx_tree* T, const lrx_opts* o, lrx_handle* out) {
+    return guarded([&]() -> lrx_status {
         if (!out) fail(LRX_EINVAL, "out is NULL");
-        if (!T || !o) fail(LRX_EINVAL, "null tree or options");
-        if (val_dev) {
-            if (!A || A->n < 1 || A->nnz < 0 || !A->row_ptr || !A->col_idx) fail(LRX_EINVAL, "bad CSR pattern");
-        } else {
-            check_csr(A);
-        }
-        if (!(o->epsilon >= 0.0 && o->epsilon < 1.0)) fail(LRX_EINVAL, "epsilon must be in [0, 1)");
-        if (o->precision != LRX_FP64 && o->precision != LRX_MIXED)
-            fail(LRX_EINVAL, "precision must be LRX_FP64 or LRX_MIXED");
-        if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
-        if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
-        h = new lrx_handle_s();
-        std::string err = build_plan(A->n, A->nnz, A->row_ptr, A->col_idx, T->depth, T->perm,
-                                     T->leaf_ptr, o->order, h->plan);
-        if (!err.empty()) fail(LRX_EINVAL, err);
-        const double t1 = now_ms();
-        HIPCHK(hipGetDevice(&h->device));
-        ensure_gfx950(h->device);
-        h->stream = (hipStream_t)o->stream;
-        h->epsilon = o->epsilon;
-        h->compress = o->compress;
-        h->precision = o->precision;
-        h->arena.budget_bytes = o->hbm_budget_bytes;
-        // A in tree order for the GMRES products
-        const int32_t n = A->n;
-        const Plan& P = h->plan;
-        std::vector<int64_t> rp(n + 1, 0);
-        std::vector<int32_t> ci((size_t)A->nnz);
-        std::vector<int64_t> src_of((size_t)A->nnz);
-        for (int32_t t = 0; t < n; ++t) {
-            const int32_t r = P.perm[t];
-            rp[t + 1] = rp[t] + (A->row_ptr[r + 1] - A->row_ptr[r]);
-        }
-        for (int32_t t = 0; t < n; ++t) {
-            const int32_t r = P.perm[t];
-            int64_t q = rp[t];
-            for (int64_t e = A->row_ptr[r]; e < A->row_ptr[r + 1]; ++e, ++q) {
-                ci[q] = P.pos[A->col_idx[e]];
-                src_of[q] = e;
-            }
-        }
-        h->nnz = A->nnz;
-        h->d_rp.ensure(rp.size() * 8);
-        h->d_ci.ensure(std::max<size_t>(ci.size(), 1) * 4);
-        h->d_val.ensure(std::max<size_t>(ci.size(), 1) * 8);
-        h->d_perm.ensure((size_t)n * 4);
-        const hipStream_t s0 = h->stream;
-        HIPCHK(hipMemcpyAsync(h->d_rp.p, rp.data(), rp.size() * 8, hipMemcpyHostToDevice, s0));
-        HIPCHK(hipMemcpyAsync(h->d_perm.p, P.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s0));
-        if (A->nnz) {
-            HIPCHK(hipMemcpyAsync(h->d_ci.p, ci.data(), ci.size() * 4, hipMemcpyHostToDevice, s0));
-            DevBuf d_src, d_vh;
-            d_src.ensure(src_of.size() * 8);
-            HIPCHK(hipMemcpyAsync(d_src.p, src_of.data(), src_of.size() * 8, hipMemcpyHostToDevice, s0));
-            const double* vsrc = val_dev;
-            if (!vsrc) {
-                d_vh.ensure((size_t)A->nnz * 8);
-                HIPCHK(hipMemcpyAsync(d_vh.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice, s0));
-                vsrc = d_vh.as<double>();
-            } else {
-                DevBuf d_cnt;
-                d_cnt.ensure(8);
-                HIPCHK(launch_count_nonfinite(vsrc, A->nnz, d_cnt.as<int64_t>(), s0));
-                int64_t bad = 0;
-                HIPCHK(hipMemcpyAsync(&bad, d_cnt.p, 8, hipMemcpyDeviceToHost, s0));
-                HIPCHK(hipStreamSynchronize(s0));
-                if (bad) fail(LRX_EINVAL, "non-finite value in A");
-            }
-            HIPCHK(launch_gather_idx(h->d_val.as<double>(), vsrc, d_src.as<int64_t>(), A->nnz, s0));
-            HIPCHK(hipStreamSynchronize(s0));     // d_src, d_vh go out of scope
-        }
-
-        run_factor(h, A, val_dev);
-        build_solve_program(h);
-        HIPCHK(hipStreamSynchronize(h->stream));
-        const double t2 = now_ms();
-
-        // statistics
-        lrx_stats_t& S = h->stats;
-        S.depth = P.depth;
-        S.n_compressions = (int32_t)h->ranks.size();
-        S.n_colour_steps = (int32_t)P.steps.size();
-        double rs = 0;
-        int32_t rmax = 0;
-        std::vector<double> lsum(33, 0), lcnt(33, 0), msum(33, 0);
-        for (size_t i = 0; i < h->ranks.size(); ++i) {
-            rs += h->ranks[i];
-            rmax = std::max(rmax, h->ranks[i]);
-            int lv = h->rank_level[i];
-            if (lv < 32) {
-                S.rank_max_by_level[lv] = std::max(S.rank_max_by_level[lv], h->ranks[i]);
-                lsum[lv] += h->ranks[i];
-                lcnt[lv] += 1;
-            }
-        }
-        for (auto& L : P.levels)
-            if (L.level < 32) {
-                double ms = 0;
-                for (int32_t s : L.supers) ms += h->size[s];
-                S.mean_node_size_by_level[L.level] = L.supers.empty() ? 0 : ms / L.supers.size();
-            }
-        for (int lv = 0; lv < 32; ++lv) S.rank_mean_by_level[lv] = lcnt[lv] ? lsum[lv] / lcnt[lv] : 0.0;
-        S.max_rank = rmax;
-        S.mean_rank = h->ranks.empty() ? 0.0 : rs / h->ranks.size();
-        S.extended_size = h->n_ext;
-        S.max_compression_error = h->max_tail_ratio;
-        S.factor_bytes = (h->solve_fp32 ? h->arena32.total : h->arena.total) * 8;
-        S.t_plan_ms = t1 - t0;
-        S.t_factor_ms = t2 - t0;
-        S.t_sync_ms = h->t_sync_ms;
-        S.t_solve_prog_ms = h->t_solve_prog_ms;
-        {
-            std::lock_guard<std::mutex> lk(g_reg_mu);
-            g_live.insert(h);
-        }
-        *out = h;
+        *out = nullptr;
+        if (!A || !T) fail(LRX_EINVAL, "null matrix or tree");
+        const double* none = nullptr;
+        factor_many(1, A, &none, T, o, out);
         return LRX_OK;
     });
-    if (st != LRX_OK && h) {
-        std::lock_guard<std::mutex> lk(g_reg_mu);
-        if (!g_live.count(h)) delete h;
-    }
-    return st;
-}
-
-lrx_status lrx_factor(const lrx_csr* A, const lrx_tree* T, const lrx_opts* o, lrx_handle* out) {
-    return factor_impl(A, nullptr, T, o, out);
 }
 
 lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tree* T,
                           const lrx_opts* o, lrx_handle* out) {
-    if (!val_dev) {
-        g_err = "val_dev is NULL";
-        return LRX_EINVAL;
-    }
-    return factor_impl(A, val_dev, T, o, out);
+    return guarded([&]() -> lrx_status {
+        if (!out) fail(LRX_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!val_dev) fail(LRX_EINVAL, "val_dev is NULL");
+        if (!A || !T) fail(LRX_EINVAL, "null matrix or tree");
+        factor_many(1, A, &val_dev, T, o, out);
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_factor_batch(int32_t k, const lrx_csr* A, const lrx_tree* T, const lrx_opts* o,
+                            lrx_handle* out) {
+    return guarded([&]() -> lrx_status {
+        if (!out) fail(LRX_EINVAL, "out is NULL");
+        if (k < 1 || k > 65536) fail(LRX_EINVAL, "k must be in [1, 65536]");
+        for (int32_t i = 0; i < k; ++i) out[i] = nullptr;
+        if (!A || !T) fail(LRX_EINVAL, "null matrix or tree array");
+        std::vector<const double*> none(k, nullptr);
+        factor_many(k, A, none.data(), T, o, out);
+        return LRX_OK;
+    });
 }
 
 void lrx_timing_enable(int32_t class_mask) {

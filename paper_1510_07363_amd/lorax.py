@@ -81,7 +81,7 @@ class PlanInfo(C.Structure):
 
 
 # every symbol declared in include/lorax.h
-EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
+EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_factor_batch", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
            "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev",
            "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
            "lrx_last_error", "lrx_version")
@@ -97,6 +97,7 @@ def _load():
     sig = {
         "lrx_factor": (C.c_int, [P(Csr), P(Tree), P(Opts), P(C.c_void_p)]),
         "lrx_factor_dev": (C.c_int, [P(Csr), C.c_void_p, P(Tree), P(Opts), P(C.c_void_p)]),
+        "lrx_factor_batch": (C.c_int, [C.c_int32, P(Csr), P(Tree), P(Opts), P(C.c_void_p)]),
         "lrx_timing_enable": (None, [C.c_int32]),
         "lrx_timing_read": (C.c_int, [P(Timing), C.c_int32]),
         "lrx_solve": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int64, f64p, C.c_int64]),
@@ -193,6 +194,24 @@ def plan_inspect(row_ptr, col_idx, perm, leaf_ptr, depth, order="colored"):
                 n_edges_created=int(info.n_edges_created))
 
 
+def factor_batch(systems, epsilon, order="colored", compress="svd", stream=None, hbm_budget_bytes=0,
+                 precision="fp64"):
+    """Factorizes several systems in one lrx_factor_batch call.
+    systems: sequence of (row_ptr, col_idx, val, perm, leaf_ptr, depth).
+    Returns one Factor per system (each equal to factoring it alone)."""
+    systems = list(systems)
+    k = len(systems)
+    As = [_CsrArgs(rp, ci, v) for rp, ci, v, _, _, _ in systems]
+    Ts = [_TreeArgs(pm, lp, d) for _, _, _, pm, lp, d in systems]
+    A_arr = (Csr * k)(*[a.s for a in As])
+    T_arr = (Tree * k)(*[t.s for t in Ts])
+    o = Opts(float(epsilon), PRECISION[precision], COMPRESS[compress], ORDERS[order],
+             int(hbm_budget_bytes), C.c_void_p(stream) if stream else None)
+    hs = (C.c_void_p * k)()
+    _check(_lib.lrx_factor_batch(k, A_arr, T_arr, C.byref(o), hs))
+    return [Factor._adopt(C.c_void_p(hs[i]), As[i]) for i in range(k)]
+
+
 class Factor:
     """A factorization resident in HBM (wraps lrx_handle)."""
 
@@ -216,6 +235,12 @@ class Factor:
             _check(_lib.lrx_factor(C.byref(self._A.s), C.byref(T.s), C.byref(o), C.byref(h)))
         self._h = h
         self.n = len(self._A.rp) - 1
+
+    @classmethod
+    def _adopt(cls, h, A):
+        F = cls.__new__(cls)
+        F._A, F._h, F.n = A, h, len(A.rp) - 1
+        return F
 
     # ------------------------------------------------------------ host arrays
     def solve(self, b):

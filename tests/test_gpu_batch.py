@@ -78,3 +78,79 @@ def test_batch_rejects_repeated_handle(env):
     with pytest.raises(lx.LoraxError) as e:
         lx.solve_batch_dev([Fa, Fa], 1, [b.data_ptr()] * 2, [x.data_ptr(), y.data_ptr()])
     assert e.value.status == lx.LRX_EINVAL
+
+
+def _batch_inputs(systems):
+    out = []
+    for kind, nx, leaf, seed in systems:
+        csr, n, perm, lp, depth, rng = _system(kind, nx, leaf, seed)
+        out.append((csr, n, perm, lp, depth, rng))
+    return out
+
+
+# sizes and kinds vary so the systems have different depths, colour counts and
+# ranks; the 3D system with 128-point leaves has compressions with c > 64
+FSYSTEMS = [("diff2d", 40, 32, 11), ("diff3d", 12, 32, 12), ("convdiff2d", 64, 64, 13),
+            ("diff2d", 24, 16, 14), ("diff3d", 16, 128, 15)]
+
+
+@pytest.mark.parametrize("precision,compress", [("fp64", "svd"), ("mixed", "svd"), ("fp64", "rrqr")])
+def test_factor_batch_equals_single_factors(env, precision, compress):
+    """Each factorization of a batch equals the same system factored alone: the
+    same ranks, truncation tails and storage, and bit-identical solves."""
+    lx, torch = env
+    ins = _batch_inputs(FSYSTEMS)
+    eps = 1e-4
+    batch = lx.factor_batch([(*csr, perm, lp, depth) for csr, n, perm, lp, depth, _ in ins], eps,
+                            compress=compress, precision=precision)
+    assert len(batch) == len(ins)
+    nrhs = 3
+    for i, ((csr, n, perm, lp, depth, rng), Fb) in enumerate(zip(ins, batch)):
+        Fs = lx.Factor(*csr, perm, lp, depth, eps, compress=compress, precision=precision)
+        rs, rb = Fs.ranks(), Fb.ranks()
+        for a, b in zip(rs, rb):
+            assert np.array_equal(a, b), i
+        Ss, Sb = Fs.stats(), Fb.stats()
+        for key in ("factor_bytes", "solve_bytes", "extended_size", "n_compressions", "factor_flops"):
+            assert Ss[key] == Sb[key], (i, key, Ss[key], Sb[key])
+        assert Ss["max_compression_error"] == Sb["max_compression_error"]
+        b = torch.from_numpy(rng.uniform(-1, 1, (nrhs, n))).to("cuda:0")
+        xs, xb = torch.zeros_like(b), torch.zeros_like(b)
+        Fs.solve_dev(b.data_ptr(), xs.data_ptr(), nrhs)
+        Fb.solve_dev(b.data_ptr(), xb.data_ptr(), nrhs)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, xb), (i, float((xs - xb).abs().max()))
+        # and the batched factor is a working preconditioner of its own system
+        x, its, rr = Fb.gmres(rng.uniform(-1, 1, n), tol=1e-10)
+        assert rr[0] <= 1e-10
+
+
+def test_factor_batch_single_system_and_errors(env):
+    lx, torch = env
+    (csr, n, perm, lp, depth, rng), = _batch_inputs([("diff2d", 24, 16, 21)])
+    Fb, = lx.factor_batch([(*csr, perm, lp, depth)], 1e-6)
+    Fs = lx.Factor(*csr, perm, lp, depth, 1e-6)
+    b = rng.uniform(-1, 1, n)
+    assert np.array_equal(Fb.solve(b), Fs.solve(b))
+    # a bad tree in one system fails the whole batch and names that system
+    bad_lp = lp.copy()
+    bad_lp[-1] += 1
+    with pytest.raises(lx.LoraxError) as e:
+        lx.factor_batch([(*csr, perm, lp, depth), (*csr, perm, bad_lp, depth)], 1e-6)
+    assert e.value.status == lx.LRX_EINVAL and "system 1" in str(e.value)
+    # an exactly singular pivot in one system: LRX_ESINGULAR for the batch
+    import scipy.sparse as sp
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n)).tolil()
+    for r in perm[lp[0]:lp[1]]:
+        A[r, :] = 0.0
+        A[:, r] = 0.0
+    A = A.tocsr()
+    A.sort_indices()
+    A.eliminate_zeros()
+    sing = (A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, perm, lp, depth)
+    with pytest.raises(lx.LoraxError) as e:
+        lx.factor_batch([(*csr, perm, lp, depth), sing], 1e-6)
+    assert e.value.status == lx.LRX_ESINGULAR and "system 1" in str(e.value)
+    # the library still works after the failed batches
+    F2, = lx.factor_batch([(*csr, perm, lp, depth)], 1e-6)
+    assert np.array_equal(F2.solve(b), Fs.solve(b))
