@@ -83,22 +83,31 @@ def cpu_baseline(workload, side):
                        f"to n={full.n}")}
 
 
-def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
+def roofline(timing, dom):
+    """Roofline entry of kernel class dom from its event-timed launches: HBM
+    bound for the sweeps and the SpMV (algorithmic bytes per launch), ALU bound
+    otherwise (algorithmic FP64 flops per launch)."""
+    d = timing[dom]
+    avg_ms = d["total_ms"] / max(d["launches"], 1)
+    if dom in ("solve_fwd", "solve_bwd", "spmv"):
+        per_launch = d["bytes"] / max(d["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        per_launch = d["flops"] / max(d["launches"], 1)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = d["launches"]
+    return roof
+
+
+def timed_steps(args, lorax, torch, step):
     """Warm-up, one untimed probe step (finds the dominant kernel class), then
     exactly args.steps timed steps bracketed by stream synchronisation."""
-    nrhs = p.rhs.shape[1]
-    state = {}
-
-    def step():
-        F = lorax.Factor(p.row_ptr, p.col_idx, None, p.perm, p.leaf_ptr, p.depth, p.epsilon,
-                         stream=sptr, val_dev=val_d.data_ptr(), precision=precision)
-        its, rr, st = F.gmres_dev(b_d.data_ptr(), x_d.data_ptr(), nrhs, tol=TOL,
-                                  restart=RESTART, maxit=500)
-        if st != lorax.LRX_OK or float(np.max(rr)) > TOL:
-            raise RuntimeError(f"GMRES did not reach {TOL}: status {st}, relres {rr}")
-        state["its"], state["rr"], state["stats"] = its, rr, F.stats()
-        F.free()
-
     for _ in range(args.warmup):
         step()
     lorax.timing_enable(None)
@@ -115,28 +124,123 @@ def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
     t1 = time.perf_counter()
     timing = lorax.timing_read(reset=True)
     lorax.timing_enable([])
+    return t1 - t0, probe, roofline(timing, dom)
+
+
+def measure_batch(args, probs, lorax, torch, precision, sptr):
+    """Batched form: one step = lrx_factor_batch of every system (values resident
+    in HBM) + lrx_gmres_batch_dev of all their right-hand sides."""
+    nrhs = probs[0].rhs.shape[1]
+    eps = probs[0].epsilon
+    systems = [(p.row_ptr, p.col_idx, None, p.perm, p.leaf_ptr, p.depth) for p in probs]
+    vals = [torch.from_numpy(p.val).to("cuda:0") for p in probs]
+    bs = [torch.from_numpy(np.ascontiguousarray(p.rhs.T)).to("cuda:0") for p in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+    vptr = [v.data_ptr() for v in vals]
+    bptr = [b.data_ptr() for b in bs]
+    xptr = [x.data_ptr() for x in xs]
+    torch.cuda.synchronize()
+    state = {}
+
+    def step():
+        Fs = lorax.factor_batch(systems, eps, stream=sptr, precision=precision, val_dev=vptr)
+        its, rr, st = lorax.gmres_batch_dev(Fs, nrhs, bptr, xptr, tol=TOL, restart=RESTART, maxit=500)
+        if st != lorax.LRX_OK or float(np.max(rr)) > TOL:
+            raise RuntimeError(f"batched GMRES did not reach {TOL}: status {st}, max relres {np.max(rr)}")
+        state["its"], state["stats"] = its, [F.stats() for F in Fs]
+        for F in Fs:
+            F.free()
+
+    T, probe, roof = timed_steps(args, lorax, torch, step)
+    res = 0.0
+    for p, x in zip(probs, xs):
+        X = x.cpu().numpy().T
+        r = np.linalg.norm(p.scipy() @ X - p.rhs, axis=0) / np.linalg.norm(p.rhs, axis=0)
+        res = max(res, float(r.max()))
+    if res > TOL:
+        raise RuntimeError(f"true residual {res:.3e} above {TOL}")
+    sts = state["stats"]
+    its = state["its"]
+    return {
+        "ms_per_step": 1e3 * T / args.steps,
+        "value": len(probs) * nrhs * args.steps / T,
+        "roofline": roof,
+        "detail": {"gmres_iters_min": int(its.min()), "gmres_iters_max": int(its.max()),
+                   "gmres_iters_mean": float(its.mean()), "true_relres_max": res,
+                   "t_factor_batch_ms": sts[0]["t_factor_ms"],
+                   "t_plan_ms_sum": float(sum(s["t_plan_ms"] for s in sts)),
+                   "t_factor_sync_ms": sts[0]["t_sync_ms"],
+                   "factor_bytes": int(sum(s["factor_bytes"] for s in sts)),
+                   "solve_bytes": int(sum(s["solve_bytes"] for s in sts)),
+                   "max_rank": int(max(s["max_rank"] for s in sts)),
+                   "kernel_ms_per_step_probe": {k: round(v["total_ms"], 3) for k, v in probe.items()},
+                   "kernel_launches_per_step_probe": {k: v["launches"] for k, v in probe.items()}},
+    }
+
+
+def cpu_baseline_batch(probs, budget_s=20.0):
+    """Oracle on the smallest systems of the batch (at least one 2-D and one 3-D,
+    then more while the running time stays within budget_s); the rate is scaled
+    to the whole batch by the unknown count (the cost is linear in n)."""
+    import oracle
+    order = sorted(range(len(probs)), key=lambda i: probs[i].n)
+    picks, seen_dim = [], set()
+    for i in order:
+        d = probs[i].coords.shape[1]
+        if d not in seen_dim:
+            picks.append(i)
+            seen_dim.add(d)
+    t_all, n_done, solves, done = 0.0, 0, 0, []
+    queue = picks + [i for i in order if i not in picks]
+    for i in queue:
+        if done and t_all >= budget_s:
+            break
+        p = probs[i]
+        A = p.scipy()
+        t0 = time.perf_counter()
+        F = oracle.factor(p.row_ptr, p.col_idx, p.val, p.perm, p.leaf_ptr, p.depth, p.epsilon, check=False)
+        for k in range(p.rhs.shape[1]):
+            oracle.fgmres(A, lambda v: oracle.solve(F, v), p.rhs[:, k], tol=TOL, restart=RESTART, maxit=500)
+        t_all += time.perf_counter() - t0
+        n_done += p.n
+        solves += p.rhs.shape[1]
+        done.append(i)
+    n_total = sum(p.n for p in probs)
+    scale = n_total / n_done
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count()
+    total_solves = len(probs) * probs[0].rhs.shape[1]
+    return {"value": total_solves / (t_all * scale), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{len(done)} smallest systems of the batch (n = {[probs[i].n for i in done]}), "
+                       f"factor + FGMRES(30) of {solves} RHS in {t_all:.1f}s; time scaled by the "
+                       f"unknown ratio {scale:.0f} to the {len(probs)} systems (n = {n_total})")}
+
+
+def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
+    """Warm-up, one untimed probe step (finds the dominant kernel class), then
+    exactly args.steps timed steps bracketed by stream synchronisation."""
+    nrhs = p.rhs.shape[1]
+    state = {}
+
+    def step():
+        F = lorax.Factor(p.row_ptr, p.col_idx, None, p.perm, p.leaf_ptr, p.depth, p.epsilon,
+                         stream=sptr, val_dev=val_d.data_ptr(), precision=precision)
+        its, rr, st = F.gmres_dev(b_d.data_ptr(), x_d.data_ptr(), nrhs, tol=TOL,
+                                  restart=RESTART, maxit=500)
+        if st != lorax.LRX_OK or float(np.max(rr)) > TOL:
+            raise RuntimeError(f"GMRES did not reach {TOL}: status {st}, relres {rr}")
+        state["its"], state["rr"], state["stats"] = its, rr, F.stats()
+        F.free()
+
+    T, probe, roof = timed_steps(args, lorax, torch, step)
     # independent check of the last solution
     A = p.scipy()
     X = x_d.cpu().numpy().T
     res = np.linalg.norm(A @ X - p.rhs, axis=0) / np.linalg.norm(p.rhs, axis=0)
     if float(res.max()) > TOL:
         raise RuntimeError(f"true residual {res.max():.3e} above {TOL}")
-    T = t1 - t0
-    d = timing[dom]
-    avg_ms = d["total_ms"] / max(d["launches"], 1)
-    if dom in ("solve_fwd", "solve_bwd", "spmv"):
-        per_launch = d["bytes"] / max(d["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    else:
-        per_launch = d["flops"] / max(d["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = avg_ms
-    roof["launches"] = d["launches"]
     st = state["stats"]
     return {
         "ms_per_step": 1e3 * T / args.steps,
@@ -163,6 +267,8 @@ def main():
     from paper_1510_07363_amd import lorax, workloads
 
     torch.cuda.set_device(0)
+    if args.workload == "batch256":
+        return main_batch(args, torch, lorax, workloads)
     p = workloads.make_config(args.workload)
     nrhs = p.rhs.shape[1]
     stream = torch.cuda.current_stream()
@@ -204,6 +310,43 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_side)
+    print(json.dumps(line), flush=True)
+
+
+def main_batch(args, torch, lorax, workloads):
+    probs = workloads.make_batch()
+    sptr = torch.cuda.current_stream().cuda_stream
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    runs = {}
+    for prec in (other, args.precision):
+        runs[prec] = measure_batch(args, probs, lorax, torch, prec, sptr)
+    main_run, other_run = runs[args.precision], runs[other]
+    nrhs = probs[0].rhs.shape[1]
+    line = {
+        "metric": "factor+GMRES solves/s at 1e-10 resid",
+        "value": main_run["value"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "batch256", "systems": len(probs), "n_total": int(sum(p.n for p in probs)),
+                   "n_min": int(min(p.n for p in probs)), "n_max": int(max(p.n for p in probs)),
+                   "depth_min": int(min(p.depth for p in probs)), "depth_max": int(max(p.depth for p in probs)),
+                   "leaf": 64, "epsilon": probs[0].epsilon, "nrhs": nrhs, "gmres": f"FGMRES({RESTART})",
+                   "tol": TOL, "precision": args.precision, "compress": "svd"},
+        "roofline": main_run["roofline"],
+        "detail": dict(main_run["detail"], **{
+            other: {"value": other_run["value"], "ms_per_step": other_run["ms_per_step"],
+                    "roofline": other_run["roofline"], **other_run["detail"]}}),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(probs)
     print(json.dumps(line), flush=True)
 
 

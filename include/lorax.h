@@ -140,8 +140,10 @@ lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tre
                           const lrx_opts* o, lrx_handle* out);
 
 /* Batched form of lrx_factor (Algorithm 1 for k independent systems at once).
- * A[i], T[i] (arrays of k structs, host memory, copied) describe system i; all
- * share the options o (epsilon, precision, rule, order, per-handle HBM budget
+ * A[i], T[i] (arrays of k structs, host memory, copied) describe system i;
+ * val_dev is NULL (values in A[i].val on the host) or an array of k device
+ * pointers, val_dev[i] holding the nnz_i values of system i in HBM as in
+ * lrx_factor_dev (A[i].val is then ignored).  All systems share the options o (epsilon, precision, rule, order, per-handle HBM budget
  * and stream).  The symbolic plans run on host threads; the numeric level loops
  * of all systems advance in lock-step over (height above the leaves, colour):
  * each kernel of a step is one launch over the nodes of every system with a
@@ -151,8 +153,8 @@ lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tre
  * are bitwise the same).  The batch succeeds or fails as a whole: on any error
  * no handle is created and every out[i] is set to NULL; the message of
  * lrx_last_error names the system.  1 <= k <= 65536. */
-lrx_status lrx_factor_batch(int32_t k, const lrx_csr* A, const lrx_tree* T, const lrx_opts* o,
-                            lrx_handle* out);
+lrx_status lrx_factor_batch(int32_t k, const lrx_csr* A, const double* const* val_dev, const lrx_tree* T,
+                            const lrx_opts* o, lrx_handle* out);
 
 /* Algorithms 2-4 for nrhs right-hand sides, host memory, column-major:
  * b[k*ldb + i] is entry i of right-hand side k (ldb >= n); x likewise (ldx >= n).
@@ -191,6 +193,23 @@ lrx_status lrx_gmres(const lrx_csr* A, lrx_handle h, int32_t nrhs, const double*
 lrx_status lrx_gmres_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev,
                          double tol, int32_t restart, int32_t maxit,
                          int32_t* iters, double* relres);
+
+/* Batched form of lrx_gmres_dev: k distinct handles on one device, nrhs
+ * right-hand sides each, b_dev[i] and x_dev[i] n_i x nrhs column-major in HBM.
+ * The k FGMRES iterations (Sec. 4.2) run in lock-step on the stream of hs[0]:
+ * each vector operation is one launch over the rows of every system still
+ * iterating, the preconditioner one sweep launch per (level, colour) step over
+ * the nodes of all of them, and the Hessenberg columns of all systems cross to
+ * the host in one copy per Arnoldi step.  Every right-hand side of every system
+ * stops on its own true relative residual (tol); a system whose right-hand
+ * sides have all stopped leaves the launches.  iters and relres (may be NULL)
+ * receive k * nrhs entries, system-major: entry i * nrhs + j is right-hand side
+ * j of system i.  Synchronous.  Returns LRX_ENOCONV if any right-hand side
+ * reached maxit (all outputs are still written).  1 <= k <= 65535; a handle may
+ * appear once; concurrent calls that share a handle race. */
+lrx_status lrx_gmres_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                               double* const* x_dev, double tol, int32_t restart, int32_t maxit,
+                               int32_t* iters, double* relres);
 
 /* Releases every resource of the handle.  NULL is accepted.  A handle that was
  * already freed gives LRX_EINVAL. */

@@ -113,6 +113,7 @@ constexpr int kSwKS = 8;               // row stride of vector buffers in LDS (m
 struct SwNode {
     const int32_t* desc; // stage 0's descriptor block (device)
     double* x;           // extended vector of this node's system (nullptr: the launch's)
+    const int32_t* live; // nullptr, or a flag of the node's system: 0 = skip the node
     int32_t words0;      // size of stage 0's block in words
     int32_t nstage;
 };
@@ -162,6 +163,33 @@ struct DConv {
     void* dst;
     int64_t n;
     int32_t f64, pad_;
+};
+
+// ---- Batched FGMRES vectors (preconditioned by the solve, Sec. 4.2) ---------
+// Vectors of a system are n x nrhs, row-interleaved (v[i*nrhs + k]), in tree
+// order.  One work-group per chunk of rows of one system (DKryChunk); systems
+// whose act flag is 0 are skipped.
+struct DKry {
+    int32_t n, chunk0;          // rows; first chunk of the system in the chunk table
+    int32_t nchunk, pad_;
+    int64_t nv, n_ext;          // n * nrhs; rows of the extended vector
+    const int64_t* rp;          // A in tree order (CSR)
+    const int32_t* ci;
+    const double* av;
+    const int32_t* perm;        // tree position -> original index
+    double* V;                  // basis V_0..V_m, each nv
+    double* Z;                  // preconditioned vectors Z_0..Z_{m-1}
+    double* w;
+    double* r;
+    double* b;                  // right-hand sides in tree order
+    double* x;                  // iterate in tree order
+    double* xe;                 // extended vector of the solve (n_ext x nrhs)
+    double* sm;                 // scalars, see kry_sm_* offsets
+    const double* bin;          // caller's b and x: n x nrhs column-major
+    double* xout;
+};
+struct DKryChunk {
+    int32_t sys, row0;
 };
 
 }  // namespace lrx

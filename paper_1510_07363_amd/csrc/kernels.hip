@@ -1270,7 +1270,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const SwNode* __restrict__
     double* dat = smem + kSwDescWords;           // after two descriptor buffers
     const int tid = threadIdx.x;
     const SwNode nd = nodes[blockIdx.x];
-    if (nd.nstage == 0) return;
+    if (nd.nstage == 0 || (nd.live && *nd.live == 0)) return;
     const int32_t* src = nd.desc;
     for (int w = tid; w < nd.words0; w += kSwThreads) Dbuf[w] = src[w];
     src += nd.words0;
@@ -1325,81 +1325,154 @@ __global__ void k_scatter_perm(const double* __restrict__ xt, const int32_t* __r
     x[perm[t] + (int64_t)k * ldx] = xt[e];
 }
 
-template <bool RES>
-__global__ void k_spmv(int n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                       const double* __restrict__ v, const double* __restrict__ x,
-                       const double* __restrict__ b, double* __restrict__ y, int nrhs) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * nrhs) return;
-    const int64_t i = e / nrhs;
-    const int k = (int)(e % nrhs);
-    double s = 0.0;
-    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s += v[q] * x[(int64_t)ci[q] * nrhs + k];
-    y[e] = RES ? b[e] - s : s;
+// ------------------------------------------------------------------ batched FGMRES vectors
+// One work-group per chunk (DKryChunk) of rc rows of one system; chunks of
+// systems whose act flag is 0 return at once.  Per system the arithmetic is
+// fixed by its own chunks, so a system's iteration does not depend on the
+// others in the batch.
+struct KryRows {
+    int64_t r0, r1;
+};
+__device__ inline KryRows kry_rows_of(const DKryChunk& C, int n, int rc) {
+    KryRows r;
+    r.r0 = C.row0;
+    r.r1 = min((int64_t)n, (int64_t)C.row0 + rc);
+    return r;
 }
 
-// partial[(j*nrhs + k) * gridDim.x + block]; nrhs <= 256
-__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t ldv, int J,
-                                              const double* __restrict__ w, int n, int nrhs,
-                                              double* __restrict__ partial, int sq) {
+// mode 0: b = bin[perm] (tree order), x = 0; mode 1: xout[perm] = x
+__global__ __launch_bounds__(256) void k_kry_perm(const DKry* __restrict__ sys, const DKryChunk* __restrict__ ch,
+                                                  const int32_t* __restrict__ act, int nrhs, int rc, int mode) {
+    const DKryChunk C = ch[blockIdx.x];
+    if (!act[C.sys]) return;
+    const DKry& S = sys[C.sys];
+    const KryRows R = kry_rows_of(C, S.n, rc);
+    const int64_t cnt = (R.r1 - R.r0) * nrhs;
+    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+        const int64_t i = R.r0 + e / nrhs;
+        const int k = (int)(e % nrhs);
+        const int64_t o = (int64_t)S.perm[i] + (int64_t)k * S.n;
+        if (mode == 0) {
+            S.b[i * nrhs + k] = S.bin[o];
+            S.x[i * nrhs + k] = 0.0;
+        } else {
+            S.xout[o] = S.x[i * nrhs + k];
+        }
+    }
+}
+
+// RES: r = b - A x;  otherwise w = A Z_j
+template <bool RES>
+__global__ __launch_bounds__(256) void k_kry_spmv(const DKry* __restrict__ sys, const DKryChunk* __restrict__ ch,
+                                                  const int32_t* __restrict__ act, int nrhs, int rc, int j) {
+    const DKryChunk C = ch[blockIdx.x];
+    if (!act[C.sys]) return;
+    const DKry& S = sys[C.sys];
+    const KryRows R = kry_rows_of(C, S.n, rc);
+    const double* __restrict__ x = RES ? S.x : S.Z + (int64_t)j * S.nv;
+    double* __restrict__ y = RES ? S.r : S.w;
+    const int64_t* __restrict__ rp = S.rp;
+    const int32_t* __restrict__ ci = S.ci;
+    const double* __restrict__ av = S.av;
+    const int64_t cnt = (R.r1 - R.r0) * nrhs;
+    for (int64_t e = threadIdx.x; e < cnt; e += 256) {
+        const int64_t i = R.r0 + e / nrhs;
+        const int k = (int)(e % nrhs);
+        double s = 0.0;
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s += av[q] * x[(int64_t)ci[q] * nrhs + k];
+        y[i * nrhs + k] = RES ? S.b[i * nrhs + k] - s : s;
+    }
+}
+
+// Partial sums of one chunk: part[(chunk * J + j) * nrhs + k] = sum_i a_j[i,k] c[i,k]
+// with (mode 0) a_j = V_j, c = w, j < J; (mode 1) a = c = w; (mode 2) a = c = r.
+// nrhs <= 256.
+__global__ __launch_bounds__(256) void k_kry_dot(const DKry* __restrict__ sys, const DKryChunk* __restrict__ ch,
+                                                 const int32_t* __restrict__ act, int nrhs, int rc, int J, int mode,
+                                                 double* __restrict__ part) {
     __shared__ double red[256];
+    const DKryChunk C = ch[blockIdx.x];
+    if (!act[C.sys]) return;                  // uniform over the work-group
+    const DKry& S = sys[C.sys];
+    const KryRows R = kry_rows_of(C, S.n, rc);
     const int tid = threadIdx.x;
-    const int rpb = 256 / nrhs;                   // rows per block and pass
-    const int T = rpb * nrhs;
+    const int rpb = 256 / nrhs, T = rpb * nrhs;
     const int k = tid % nrhs, r0 = tid / nrhs;
+    const double* __restrict__ c = mode == 2 ? S.r : S.w;
     for (int j = 0; j < J; ++j) {
-        const double* Vj = sq ? w : V + (int64_t)j * ldv;
+        const double* __restrict__ a = mode == 0 ? S.V + (int64_t)j * S.nv : c;
         double s = 0.0;
         if (tid < T)
-            for (int64_t i = (int64_t)blockIdx.x * rpb + r0; i < n; i += (int64_t)gridDim.x * rpb)
-                s += Vj[i * nrhs + k] * w[i * nrhs + k];
+            for (int64_t i = R.r0 + r0; i < R.r1; i += rpb) s += a[i * nrhs + k] * c[i * nrhs + k];
         red[tid] = s;
         __syncthreads();
         if (tid < nrhs) {
             double t = 0.0;
             for (int q = 0; q < rpb; ++q) t += red[q * nrhs + tid];
-            partial[((int64_t)j * nrhs + tid) * gridDim.x + blockIdx.x] = t;
+            part[((int64_t)blockIdx.x * J + j) * nrhs + tid] = t;
         }
         __syncthreads();
     }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int cnt,
-                                  double* __restrict__ out) {
+// sm[out_off + q] = sum over the system's chunks of part[(chunk * J) * nrhs + q], q < J nrhs
+__global__ void k_kry_reduce(const DKry* __restrict__ sys, const int32_t* __restrict__ act, int cnt,
+                             const double* __restrict__ part, int out_off) {
+    const int s = blockIdx.y;
+    if (!act[s]) return;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cnt) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)q * nblk + b];
-    out[q] = s;
+    const DKry& S = sys[s];
+    double t = 0.0;
+    for (int c = S.chunk0; c < S.chunk0 + S.nchunk; ++c) t += part[(int64_t)c * cnt + q];
+    S.sm[out_off + q] = t;
 }
 
-__global__ void k_mupdate(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
-                          double* __restrict__ w, int n, int nrhs) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * nrhs) return;
-    const int k = (int)(e % nrhs);
-    double s = w[e];
-    for (int j = 0; j < J; ++j) s -= V[(int64_t)j * ldv + e] * h[j * nrhs + k];
-    w[e] = s;
-}
-
-__global__ void k_normalize(const double* __restrict__ src, const double* __restrict__ nrm2,
-                            double* __restrict__ dst, int n, int nrhs) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * nrhs) return;
-    const int k = (int)(e % nrhs);
-    const double q = nrm2[k];
-    dst[e] = q > 0.0 ? src[e] / sqrt(q) : 0.0;
-}
-
-__global__ void k_xupdate(const double* __restrict__ Z, int64_t ldz, int J, const double* __restrict__ y,
-                          double* __restrict__ x, int n, int nrhs) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n * nrhs) return;
-    const int k = (int)(e % nrhs);
-    double s = x[e];
-    for (int j = 0; j < J; ++j) s += Z[(int64_t)j * ldz + e] * y[j * nrhs + k];
-    x[e] = s;
+// op 0: w -= sum_{j<J} V_j h_j (h at sm[off]);  op 1: x += sum_{j<Js} Z_j y_j (y at
+// sm[off], Js = sm[off2]);  op 2: V_j = src / sqrt(n2) (src: r if J == 0 else w,
+// n2 at sm[off]);  op 3: xe = [V_j; 0];  op 4: Z_j = xe[0:n]
+__global__ __launch_bounds__(256) void k_kry_axpy(const DKry* __restrict__ sys, const DKryChunk* __restrict__ ch,
+                                                  const int32_t* __restrict__ act, int nrhs, int rc, int op, int J,
+                                                  int j, int off, int off2) {
+    const DKryChunk C = ch[blockIdx.x];
+    if (!act[C.sys]) return;
+    const DKry& S = sys[C.sys];
+    const KryRows R = kry_rows_of(C, S.n, rc);
+    const int64_t e0 = R.r0 * nrhs, e1 = R.r1 * nrhs;
+    const double* __restrict__ sm = S.sm;
+    if (op == 0) {
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+            const int k = (int)(e % nrhs);
+            double s = S.w[e];
+            for (int q = 0; q < J; ++q) s -= S.V[(int64_t)q * S.nv + e] * sm[off + q * nrhs + k];
+            S.w[e] = s;
+        }
+    } else if (op == 1) {
+        const int Js = (int)sm[off2];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+            const int k = (int)(e % nrhs);
+            double s = S.x[e];
+            for (int q = 0; q < Js; ++q) s += S.Z[(int64_t)q * S.nv + e] * sm[off + q * nrhs + k];
+            S.x[e] = s;
+        }
+    } else if (op == 2) {
+        const double* __restrict__ src = J == 0 ? S.r : S.w;
+        double* __restrict__ dst = S.V + (int64_t)j * S.nv;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+            const double q = sm[off + (int)(e % nrhs)];
+            dst[e] = q > 0.0 ? src[e] / sqrt(q) : 0.0;
+        }
+    } else if (op == 3) {
+        const double* __restrict__ src = S.V + (int64_t)j * S.nv;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) S.xe[e] = src[e];
+        // the extension rows n..n_ext are shared out over the system's chunks
+        const int64_t q = blockIdx.x - S.chunk0;
+        for (int64_t e = S.nv + q * 256 + threadIdx.x; e < S.n_ext * nrhs; e += (int64_t)S.nchunk * 256)
+            S.xe[e] = 0.0;
+    } else {
+        double* __restrict__ dst = S.Z + (int64_t)j * S.nv;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) dst[e] = S.xe[e];
+    }
 }
 
 __global__ void k_gather_idx(double* __restrict__ dst, const double* __restrict__ src,
@@ -1593,58 +1666,38 @@ hipError_t launch_scatter_perm(const double* xt, const int32_t* perm, int n, int
     return hipGetLastError();
 }
 
-hipError_t launch_spmv(int n, const int64_t* rp, const int32_t* ci, const double* v, const double* x,
-                       double* y, int nrhs, hipStream_t st) {
-    int64_t work = (int64_t)n * nrhs;
-    hipLaunchKernelGGL(k_spmv<false>, dim3(nblocks(work, 256)), dim3(256), 0, st, n, rp, ci, v, x,
-                       (const double*)nullptr, y, nrhs);
+hipError_t kry_perm(const KryLaunch& L, int mode) {
+    if (L.nchunk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kry_perm, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, mode);
     return hipGetLastError();
 }
 
-hipError_t launch_residual(int n, const int64_t* rp, const int32_t* ci, const double* v,
-                           const double* x, const double* b, double* y, int nrhs, hipStream_t st) {
-    int64_t work = (int64_t)n * nrhs;
-    hipLaunchKernelGGL(k_spmv<true>, dim3(nblocks(work, 256)), dim3(256), 0, st, n, rp, ci, v, x, b, y, nrhs);
+hipError_t kry_spmv(const KryLaunch& L, bool residual, int j) {
+    if (L.nchunk == 0) return hipSuccess;
+    if (residual)
+        hipLaunchKernelGGL(k_kry_spmv<true>, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, j);
+    else
+        hipLaunchKernelGGL(k_kry_spmv<false>, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, j);
     return hipGetLastError();
 }
 
-hipError_t launch_mdot(const double* V, int64_t ldv, int J, const double* w, int n, int nrhs,
-                       double* partial, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(256), 0, st, V, ldv, J, w, n, nrhs, partial, 0);
+hipError_t kry_dots(const KryLaunch& L, int mode, int J, double* part, int out_off) {
+    if (L.nchunk == 0 || J == 0) return hipSuccess;
+    if (L.nrhs < 1 || L.nrhs > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kry_dot, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, J, mode,
+                       part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int cnt = J * nrhs;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(cnt, 64)), dim3(64), 0, st, partial, kDotBlocks, cnt, out);
+    const int cnt = J * L.nrhs;
+    hipLaunchKernelGGL(k_kry_reduce, dim3(nblocks(cnt, 64), L.nsys), dim3(64), 0, L.st, L.sys, L.act, cnt,
+                       (const double*)part, out_off);
     return hipGetLastError();
 }
 
-hipError_t launch_mupdate(const double* V, int64_t ldv, int J, const double* h, double* w, int n,
-                          int nrhs, hipStream_t st) {
-    int64_t work = (int64_t)n * nrhs;
-    hipLaunchKernelGGL(k_mupdate, dim3(nblocks(work, 256)), dim3(256), 0, st, V, ldv, J, h, w, n, nrhs);
-    return hipGetLastError();
-}
-
-hipError_t launch_sqnorm(const double* w, int n, int nrhs, double* partial, double* out,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(256), 0, st, w, (int64_t)0, 1, w, n, nrhs, partial, 1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nblocks(nrhs, 64)), dim3(64), 0, st, partial, kDotBlocks, nrhs, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_normalize(const double* src, const double* nrm2, double* dst, int n, int nrhs,
-                            hipStream_t st) {
-    int64_t work = (int64_t)n * nrhs;
-    hipLaunchKernelGGL(k_normalize, dim3(nblocks(work, 256)), dim3(256), 0, st, src, nrm2, dst, n, nrhs);
-    return hipGetLastError();
-}
-
-hipError_t launch_xupdate(const double* Z, int64_t ldz, int J, const double* y, double* x, int n,
-                          int nrhs, hipStream_t st) {
-    int64_t work = (int64_t)n * nrhs;
-    hipLaunchKernelGGL(k_xupdate, dim3(nblocks(work, 256)), dim3(256), 0, st, Z, ldz, J, y, x, n, nrhs);
+hipError_t kry_axpy(const KryLaunch& L, int op, int J, int j, int off, int off2) {
+    if (L.nchunk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kry_axpy, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, op, J, j,
+                       off, off2);
     return hipGetLastError();
 }
 

@@ -51,28 +51,26 @@ hipError_t launch_gather_perm(const double* b, int64_t ldb, const int32_t* perm,
 // x[perm[t] + k*ldx] = xt[t*nrhs + k]
 hipError_t launch_scatter_perm(const double* xt, const int32_t* perm, int n, int nrhs, double* x,
                                int64_t ldx, hipStream_t st);
-// y = A x  (CSR, interleaved vectors)
-hipError_t launch_spmv(int n, const int64_t* rp, const int32_t* ci, const double* v, const double* x,
-                       double* y, int nrhs, hipStream_t st);
-// y = b - A x
-hipError_t launch_residual(int n, const int64_t* rp, const int32_t* ci, const double* v,
-                           const double* x, const double* b, double* y, int nrhs, hipStream_t st);
-// out[j*nrhs + k] = sum_i V_j[i,k] w[i,k], j < J (V_j = V + j*ldv); partial needs
-// J*nrhs*kDotBlocks doubles
-constexpr int kDotBlocks = 240;
-hipError_t launch_mdot(const double* V, int64_t ldv, int J, const double* w, int n, int nrhs,
-                       double* partial, double* out, hipStream_t st);
-// w[i,k] -= sum_j V_j[i,k] h[j*nrhs + k]
-hipError_t launch_mupdate(const double* V, int64_t ldv, int J, const double* h, double* w, int n,
-                          int nrhs, hipStream_t st);
-// out[k] = sum_i w[i,k]^2
-hipError_t launch_sqnorm(const double* w, int n, int nrhs, double* partial, double* out,
-                         hipStream_t st);
-// dst[i,k] = src[i,k] * (nrm2[k] > 0 ? 1/sqrt(nrm2[k]) : 0);  also beta[k] = sqrt(nrm2[k])
-hipError_t launch_normalize(const double* src, const double* nrm2, double* dst, int n, int nrhs,
-                            hipStream_t st);
-// x[i,k] += sum_j Z_j[i,k] y[j*nrhs + k]
-hipError_t launch_xupdate(const double* Z, int64_t ldz, int J, const double* y, double* x, int n,
-                          int nrhs, hipStream_t st);
+// ---- batched FGMRES vector operations (DKry systems, DKryChunk chunks) ------
+// Rows per chunk for nrhs right-hand sides (about 2048 elements per work-group).
+inline int kry_rows(int nrhs) { return nrhs >= 2048 ? 1 : 2048 / nrhs; }
+struct KryLaunch {
+    const DKry* sys;
+    const DKryChunk* ch;
+    const int32_t* act;     // per system: 0 = skip
+    int nchunk, nsys, nrhs, rc;
+    hipStream_t st;
+};
+// mode 0: b = bin in tree order, x = 0;  mode 1: xout = x in the original order
+hipError_t kry_perm(const KryLaunch& L, int mode);
+// residual: r = b - A x;  otherwise w = A Z_j
+hipError_t kry_spmv(const KryLaunch& L, bool residual, int j);
+// sm[out_off + j*nrhs + k] = (mode 0) <V_j, w>_k for j < J, (1) ||w||_k^2, (2) ||r||_k^2;
+// part holds nchunk * J * nrhs doubles
+hipError_t kry_dots(const KryLaunch& L, int mode, int J, double* part, int out_off);
+// op 0: w -= sum_{j<J} V_j h_j (h at sm[off]);  op 1: x += sum_{j<Js} Z_j y_j (y at
+// sm[off], Js = sm[off2]);  op 2: V_j = (J == 0 ? r : w) / sqrt(sm[off + k]);
+// op 3: xe = [V_j; 0];  op 4: Z_j = xe[0:n]
+hipError_t kry_axpy(const KryLaunch& L, int op, int J, int j, int off, int off2);
 
 }  // namespace lrx

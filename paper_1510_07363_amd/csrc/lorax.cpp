@@ -229,8 +229,9 @@ struct lrx_handle_s {
     int64_t nnz = 0;
     // scratch
     DevBuf x_ext, ws_b, ws_x;
-    DevBuf g_basis, g_z, g_w, g_r, g_b, g_x, g_small, g_partial;
-    PinBuf pin_small;
+    DevBuf g_basis, g_z, g_w, g_r, g_b, g_x;
+    DevBuf kry_tab, kry_small, kry_part;   // batched GMRES led by this handle
+    PinBuf kry_pin;
     // stats
     lrx_stats_t stats{};
     std::vector<int32_t> ranks, rank_level, rank_j;
@@ -1094,7 +1095,8 @@ void build_solve_program(lrx_handle h) {
         HIPCHK(hipMemcpy(h->d_swprog.p, words.data(), words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     h->sw_host.resize(2 * nn);
     for (size_t i = 0; i < 2 * nn; ++i)
-        h->sw_host[i] = SwNode{h->d_swprog.as<int32_t>() + both[i].desc, nullptr, both[i].words0, both[i].nstage};
+        h->sw_host[i] = SwNode{h->d_swprog.as<int32_t>() + both[i].desc, nullptr, nullptr, both[i].words0,
+                              both[i].nstage};
     if (nn)
         HIPCHK(hipMemcpy(h->d_swnodes.p, h->sw_host.data(), h->sw_host.size() * sizeof(SwNode),
                          hipMemcpyHostToDevice));
@@ -1131,18 +1133,6 @@ void sweeps(lrx_handle h, double* xe, int nrhs) {
         }
         k0 += nk;
     }
-}
-
-// z (tree order, interleaved n x nrhs) = M^{-1} v
-void precond(lrx_handle h, const double* v, double* z, int nrhs) {
-    const hipStream_t st = h->stream;
-    const int64_t n = h->plan.n;
-    h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
-    double* xe = h->x_ext.as<double>();
-    HIPCHK(hipMemcpyAsync(xe, v, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
-    if (h->n_ext > n) HIPCHK(hipMemsetAsync(xe + n * nrhs, 0, (size_t)(h->n_ext - n) * nrhs * 8, st));
-    sweeps(h, xe, nrhs);
-    HIPCHK(hipMemcpyAsync(z, xe, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
 }
 
 void solve_dev(lrx_handle h, int nrhs, const double* b, double* x) {
@@ -1221,163 +1211,306 @@ void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const*
 }
 
 // ------------------------------------------------------------------ GMRES
-lrx_status gmres_dev(lrx_handle h, int nrhs, const double* b, double* x, double tol, int restart,
-                     int maxit, int32_t* iters_out, double* relres_out) {
-    const hipStream_t st = h->stream;
-    const int32_t n = h->plan.n;
-    const int64_t nv = (int64_t)n * nrhs;
+// FGMRES(restart) with the solve as right preconditioner (Sec. 4.2), x_0 = 0,
+// for k factorizations at once, nrhs right-hand sides each.  Every vector
+// operation is one launch over the row chunks of all systems still iterating
+// (DKry/DKryChunk tables); the preconditioner is one sweep launch per
+// (height, colour) step over the nodes of all of them; the Hessenberg columns of
+// all systems cross to the host with one copy per Arnoldi step.  Each right-hand
+// side stops on its own true relative residual; a system whose right-hand sides
+// have all stopped drops out of the launches (its act flag).  k = 1 is the
+// single-system solver.
+lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* const* b, double* const* x,
+                       double tol, int restart, int maxit, int32_t* iters_out, double* relres_out) {
+    const lrx_handle h0 = hs[0];
+    const hipStream_t st = h0->stream;
     const int m = restart;
-    h->g_basis.ensure((size_t)(m + 1) * nv * 8);
-    h->g_z.ensure((size_t)m * nv * 8);
-    h->g_w.ensure((size_t)nv * 8);
-    h->g_r.ensure((size_t)nv * 8);
-    h->g_b.ensure((size_t)nv * 8);
-    h->g_x.ensure((size_t)nv * 8);
-    const size_t small = (size_t)(3 * (m + 1) * nrhs + 4 * nrhs + 64);
-    h->g_small.ensure(small * 8);
-    h->g_partial.ensure((size_t)(m + 1) * nrhs * kDotBlocks * 8);
-    h->pin_small.ensure(small * 8);
-    double* V = h->g_basis.as<double>();
-    double* Z = h->g_z.as<double>();
-    double* w = h->g_w.as<double>();
-    double* r = h->g_r.as<double>();
-    double* bt = h->g_b.as<double>();
-    double* xt = h->g_x.as<double>();
-    double* d_h1 = h->g_small.as<double>();
-    double* d_h2 = d_h1 + (m + 1) * nrhs;
-    double* d_y = d_h2 + (m + 1) * nrhs;
-    double* d_n2 = d_y + (m + 1) * nrhs;
-    double* part = h->g_partial.as<double>();
-    double* hs = (double*)h->pin_small.p;
-    const int32_t* rp_perm = h->d_perm.as<int32_t>();
-    const int64_t* rp = h->d_rp.as<int64_t>();
-    const int32_t* ci = h->d_ci.as<int32_t>();
-    const double* av = h->d_val.as<double>();
-
-    HIPCHK(launch_gather_perm(b, n, rp_perm, n, nrhs, bt, n, st));
-    HIPCHK(hipMemsetAsync(xt, 0, (size_t)nv * 8, st));
-    HIPCHK(launch_sqnorm(bt, n, nrhs, part, d_n2, st));
-    HIPCHK(hipMemcpyAsync(hs, d_n2, nrhs * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    std::vector<double> bnorm(nrhs), relres(nrhs, 0.0);
-    std::vector<int32_t> its(nrhs, 0);
-    std::vector<char> active(nrhs), conv(nrhs, 0);
-    for (int k = 0; k < nrhs; ++k) {
-        bnorm[k] = std::sqrt(hs[k]);
-        active[k] = bnorm[k] > 0.0;
-        if (!active[k]) conv[k] = 1;
+    const int rc = kry_rows(nrhs);
+    // scalars of one system: h1 | h2 | n2 | y | J
+    const int o_h1 = 0, o_h2 = (m + 1) * nrhs, o_n2 = 2 * (m + 1) * nrhs, o_y = o_n2 + nrhs;
+    const int o_J = o_y + (m + 1) * nrhs;
+    const int smsz = (o_J + 1 + 3) & ~3;
+    std::vector<DKry> sys(K);
+    std::vector<DKryChunk> chunks;
+    double nnz_bytes = 0.0, spmv_flops = 0.0;
+    h0->kry_small.ensure((size_t)K * smsz * 8);
+    for (int s = 0; s < K; ++s) {
+        const lrx_handle h = hs[s];
+        const int32_t n = h->plan.n;
+        const int64_t nv = (int64_t)n * nrhs;
+        h->g_basis.ensure((size_t)(m + 1) * nv * 8);
+        h->g_z.ensure((size_t)m * nv * 8);
+        h->g_w.ensure((size_t)nv * 8);
+        h->g_r.ensure((size_t)nv * 8);
+        h->g_b.ensure((size_t)nv * 8);
+        h->g_x.ensure((size_t)nv * 8);
+        h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
+        DKry& S = sys[s];
+        S.n = n;
+        S.nv = nv;
+        S.n_ext = h->n_ext;
+        S.rp = h->d_rp.as<int64_t>();
+        S.ci = h->d_ci.as<int32_t>();
+        S.av = h->d_val.as<double>();
+        S.perm = h->d_perm.as<int32_t>();
+        S.V = h->g_basis.as<double>();
+        S.Z = h->g_z.as<double>();
+        S.w = h->g_w.as<double>();
+        S.r = h->g_r.as<double>();
+        S.b = h->g_b.as<double>();
+        S.x = h->g_x.as<double>();
+        S.xe = h->x_ext.as<double>();
+        S.sm = h0->kry_small.as<double>() + (size_t)s * smsz;
+        S.bin = b[s];
+        S.xout = x[s];
+        S.chunk0 = (int32_t)chunks.size();
+        for (int32_t r0 = 0; r0 < n; r0 += rc) chunks.push_back(DKryChunk{s, r0});
+        S.nchunk = (int32_t)chunks.size() - S.chunk0;
+        nnz_bytes += (double)h->nnz * 12 + (double)(n + 1) * 8 + 2.0 * nv * 8;
+        spmv_flops += 2.0 * (double)h->nnz * nrhs;
     }
-    std::vector<double> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
-        g((size_t)nrhs * (m + 1));
-    std::vector<int> kk(nrhs);
-    std::vector<char> done(nrhs);
-    while (true) {
-        HIPCHK(launch_residual(n, rp, ci, av, xt, bt, r, nrhs, st));
-        HIPCHK(launch_sqnorm(r, n, nrhs, part, d_n2, st));
-        HIPCHK(hipMemcpyAsync(hs, d_n2, nrhs * 8, hipMemcpyDeviceToHost, st));
+    if (chunks.size() > (size_t)INT32_MAX) fail(LRX_EINVAL, "too many rows in the batch");
+    h0->kry_part.ensure(std::max<size_t>(chunks.size(), 1) * (size_t)(m + 1) * nrhs * 8);
+    double* part = h0->kry_part.as<double>();
+    // device tables: systems | chunks | act
+    const size_t o_ch = ((size_t)K * sizeof(DKry) + 255) & ~(size_t)255;
+    const size_t o_act = (o_ch + chunks.size() * sizeof(DKryChunk) + 255) & ~(size_t)255;
+    h0->kry_tab.ensure(o_act + (size_t)K * 4);
+    HIPCHK(hipMemcpy(h0->kry_tab.p, sys.data(), (size_t)K * sizeof(DKry), hipMemcpyHostToDevice));
+    if (!chunks.empty())
+        HIPCHK(hipMemcpy(h0->kry_tab.as<char>() + o_ch, chunks.data(), chunks.size() * sizeof(DKryChunk),
+                         hipMemcpyHostToDevice));
+    int32_t* act_dev = (int32_t*)(h0->kry_tab.as<char>() + o_act);
+    // pinned mirror: scalars of every system, then act
+    const size_t pin_act = (size_t)K * smsz * 8;
+    h0->kry_pin.ensure(pin_act + (size_t)K * 4);
+    double* hsm = (double*)h0->kry_pin.p;
+    int32_t* act = (int32_t*)((char*)h0->kry_pin.p + pin_act);
+    const KryLaunch L{(const DKry*)h0->kry_tab.p, (const DKryChunk*)(h0->kry_tab.as<char>() + o_ch), act_dev,
+                      (int)chunks.size(), K, nrhs, rc, st};
+    auto put_act = [&]() {
+        HIPCHK(hipMemcpyAsync(act_dev, act, (size_t)K * 4, hipMemcpyHostToDevice, st));
+    };
+    auto get_small = [&]() {
+        HIPCHK(hipMemcpyAsync(hsm, h0->kry_small.p, (size_t)K * smsz * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+    };
+    auto put_small = [&]() {
+        HIPCHK(hipMemcpyAsync(h0->kry_small.p, hsm, (size_t)K * smsz * 8, hipMemcpyHostToDevice, st));
+    };
+    // preconditioner: node lists of both sweeps over all systems, each node
+    // skipped when its system's act flag is 0
+    std::vector<std::pair<int32_t, int32_t>> keys;
+    for (int s = 0; s < K; ++s)
+        for (const SolveStep& q : hs[s]->ssteps) keys.push_back({q.height, q.colour});
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    std::vector<SwNode> nf, nb;
+    std::vector<int32_t> k0f;
+    std::vector<double> step_bytes_f, step_bytes_b;
+    for (const auto& key : keys) {
+        k0f.push_back((int32_t)nf.size());
+        double bf = 0, bb = 0;
+        for (int s = 0; s < K; ++s) {
+            const lrx_handle h = hs[s];
+            for (const SolveStep& q : h->ssteps) {
+                if (q.height != key.first || q.colour != key.second) continue;
+                bf += (double)q.bytes_fwd;
+                bb += (double)q.bytes_bwd;
+                for (int32_t j = 0; j < q.nnode; ++j) {
+                    SwNode a = h->sw_host[q.node0 + j];
+                    SwNode c = h->sw_host[h->sw_nnode + q.node0 + j];
+                    a.x = c.x = sys[s].xe;
+                    a.live = c.live = act_dev + s;
+                    nf.push_back(a);
+                    nb.push_back(c);
+                }
+            }
+        }
+        step_bytes_f.push_back(bf);
+        step_bytes_b.push_back(bb);
+    }
+    k0f.push_back((int32_t)nf.size());
+    h0->batch_nodes.ensure(std::max<size_t>(2 * nf.size(), 1) * sizeof(SwNode));
+    SwNode* dn = h0->batch_nodes.as<SwNode>();
+    if (!nf.empty()) {
+        HIPCHK(hipMemcpy(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+    }
+    auto precondition = [&]() {
+        for (int c0 = 0; c0 < nrhs;) {
+            const int rem = nrhs - c0;
+            const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+            for (size_t q = 0; q + 1 < k0f.size(); ++q) {
+                LaunchTimer tm(LRX_K_SOLVE_FWD, st, step_bytes_f[q], step_bytes_f[q] / 4.0 * nk);
+                HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
+            }
+            for (size_t q = k0f.size() - 1; q-- > 0;) {
+                LaunchTimer tm(LRX_K_SOLVE_BWD, st, step_bytes_b[q], step_bytes_b[q] / 4.0 * nk);
+                HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
+            }
+            c0 += nk;
+        }
+    };
+
+    // host state per (system, right-hand side)
+    const size_t KR = (size_t)K * nrhs;
+    std::vector<double> bnorm(KR, 0.0), relres(KR, 0.0);
+    std::vector<int32_t> its(KR, 0), kk(KR, 0);
+    std::vector<char> active(KR, 0), conv(KR, 0), done(KR, 1);
+    std::vector<double> H(KR * (m + 1) * m), cs(KR * m), sn(KR * m), g(KR * (m + 1));
+    std::vector<char> in_cycle(K, 1);
+    for (int s = 0; s < K; ++s) act[s] = 1;
+    put_act();
+    HIPCHK(kry_perm(L, 0));                   // b in tree order, x = 0
+    bool first = true;
+    while (true) {
+        HIPCHK(kry_spmv(L, true, 0));          // r = b - A x
+        HIPCHK(kry_dots(L, 2, 1, part, o_n2));
+        get_small();
         bool any = false;
-        for (int k = 0; k < nrhs; ++k) {
-            if (bnorm[k] == 0.0) continue;
-            relres[k] = std::sqrt(hs[k]) / bnorm[k];
-            if (!active[k]) continue;
-            if (relres[k] <= tol) { active[k] = 0; conv[k] = 1; }
-            else if (its[k] >= maxit) active[k] = 0;
-            if (active[k]) any = true;
+        for (int s = 0; s < K; ++s) {
+            in_cycle[s] = 0;
+            if (!act[s]) continue;
+            const double* n2 = hsm + (size_t)s * smsz + o_n2;
+            for (int k = 0; k < nrhs; ++k) {
+                const size_t q = (size_t)s * nrhs + k;
+                if (first) {
+                    bnorm[q] = std::sqrt(n2[k]);
+                    active[q] = bnorm[q] > 0.0;
+                    conv[q] = !active[q];
+                }
+                if (bnorm[q] == 0.0) continue;
+                relres[q] = std::sqrt(n2[k]) / bnorm[q];
+                if (!active[q]) continue;
+                if (relres[q] <= tol) { active[q] = 0; conv[q] = 1; }
+                else if (its[q] >= maxit) active[q] = 0;
+                if (active[q]) in_cycle[s] = 1;
+            }
+            any |= in_cycle[s] != 0;
         }
+        first = false;
         if (!any) break;
+        // systems with an active right-hand side take part in this cycle;
         // V_0 = r / ||r|| for active right-hand sides, 0 otherwise
-        for (int k = 0; k < nrhs; ++k) hs[k] = active[k] ? hs[k] : 0.0;
-        HIPCHK(hipMemcpyAsync(d_n2, hs, nrhs * 8, hipMemcpyHostToDevice, st));
-        HIPCHK(launch_normalize(r, d_n2, V, n, nrhs, st));
-        for (int k = 0; k < nrhs; ++k) {
-            std::fill(g.begin() + (size_t)k * (m + 1), g.begin() + (size_t)(k + 1) * (m + 1), 0.0);
-            g[(size_t)k * (m + 1)] = active[k] ? std::sqrt(hs[k]) : 0.0;
-            kk[k] = 0;
-            done[k] = !active[k];
+        for (int s = 0; s < K; ++s) {
+            act[s] = in_cycle[s];
+            if (!act[s]) continue;
+            double* n2 = hsm + (size_t)s * smsz + o_n2;
+            for (int k = 0; k < nrhs; ++k) {
+                const size_t q = (size_t)s * nrhs + k;
+                if (!active[q]) n2[k] = 0.0;
+                double* gq = g.data() + q * (m + 1);
+                std::fill(gq, gq + m + 1, 0.0);
+                gq[0] = active[q] ? std::sqrt(n2[k]) : 0.0;
+                kk[q] = 0;
+                done[q] = !active[q];
+            }
         }
+        put_act();
+        put_small();
+        HIPCHK(kry_axpy(L, 2, 0, 0, o_n2, 0));
         for (int j = 0; j < m; ++j) {
-            double* Vj = V + (int64_t)j * nv;
-            double* Zj = Z + (int64_t)j * nv;
-            precond(h, Vj, Zj, nrhs);
+            HIPCHK(kry_axpy(L, 3, 0, j, 0, 0));          // xe = [V_j; 0]
+            precondition();
+            HIPCHK(kry_axpy(L, 4, 0, j, 0, 0));          // Z_j = M^{-1} V_j
             {
-                LaunchTimer tm(LRX_K_SPMV, st, (double)h->nnz * 12 + (double)(n + 1) * 8 + 2.0 * nv * 8,
-                               2.0 * (double)h->nnz * nrhs);
-                HIPCHK(launch_spmv(n, rp, ci, av, Zj, w, nrhs, st));
+                LaunchTimer tm(LRX_K_SPMV, st, nnz_bytes, spmv_flops);
+                HIPCHK(kry_spmv(L, false, j));           // w = A Z_j
             }
             // classical Gram-Schmidt, twice
-            HIPCHK(launch_mdot(V, nv, j + 1, w, n, nrhs, part, d_h1, st));
-            HIPCHK(launch_mupdate(V, nv, j + 1, d_h1, w, n, nrhs, st));
-            HIPCHK(launch_mdot(V, nv, j + 1, w, n, nrhs, part, d_h2, st));
-            HIPCHK(launch_mupdate(V, nv, j + 1, d_h2, w, n, nrhs, st));
-            HIPCHK(launch_sqnorm(w, n, nrhs, part, d_n2, st));
-            HIPCHK(launch_normalize(w, d_n2, V + (int64_t)(j + 1) * nv, n, nrhs, st));
-            HIPCHK(hipMemcpyAsync(hs, d_h1, (size_t)(2 * (m + 1) * nrhs) * 8, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(hs + 2 * (m + 1) * nrhs, d_n2, nrhs * 8, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            const double* h1 = hs;
-            const double* h2 = hs + (m + 1) * nrhs;
-            const double* n2 = hs + 2 * (m + 1) * nrhs;
-            bool all_done = true;
-            for (int k = 0; k < nrhs; ++k) {
-                if (done[k]) continue;
-                double* Hk = H.data() + (size_t)k * (m + 1) * m;   // Hk[i*m + j]
-                double* gk = g.data() + (size_t)k * (m + 1);
-                double* ck = cs.data() + (size_t)k * m;
-                double* sk = sn.data() + (size_t)k * m;
-                for (int i = 0; i <= j; ++i) Hk[i * m + j] = h1[i * nrhs + k] + h2[i * nrhs + k];
-                Hk[(j + 1) * m + j] = std::sqrt(std::max(n2[k], 0.0));
-                for (int i = 0; i < j; ++i) {
-                    const double t = ck[i] * Hk[i * m + j] + sk[i] * Hk[(i + 1) * m + j];
-                    Hk[(i + 1) * m + j] = -sk[i] * Hk[i * m + j] + ck[i] * Hk[(i + 1) * m + j];
-                    Hk[i * m + j] = t;
+            HIPCHK(kry_dots(L, 0, j + 1, part, o_h1));
+            HIPCHK(kry_axpy(L, 0, j + 1, 0, o_h1, 0));
+            HIPCHK(kry_dots(L, 0, j + 1, part, o_h2));
+            HIPCHK(kry_axpy(L, 0, j + 1, 0, o_h2, 0));
+            HIPCHK(kry_dots(L, 1, 1, part, o_n2));
+            HIPCHK(kry_axpy(L, 2, 1, j + 1, o_n2, 0));   // V_{j+1} = w / ||w||
+            get_small();
+            bool all_done = true, act_changed = false;
+            for (int s = 0; s < K; ++s) {
+                if (!act[s]) continue;
+                const double* sm = hsm + (size_t)s * smsz;
+                const double* h1 = sm + o_h1;
+                const double* h2 = sm + o_h2;
+                const double* n2 = sm + o_n2;
+                bool sys_done = true;
+                for (int k = 0; k < nrhs; ++k) {
+                    const size_t q = (size_t)s * nrhs + k;
+                    if (done[q]) continue;
+                    double* Hk = H.data() + q * (m + 1) * m;   // Hk[i*m + j]
+                    double* gk = g.data() + q * (m + 1);
+                    double* ck = cs.data() + q * m;
+                    double* sk = sn.data() + q * m;
+                    for (int i = 0; i <= j; ++i) Hk[i * m + j] = h1[i * nrhs + k] + h2[i * nrhs + k];
+                    Hk[(j + 1) * m + j] = std::sqrt(std::max(n2[k], 0.0));
+                    for (int i = 0; i < j; ++i) {
+                        const double t = ck[i] * Hk[i * m + j] + sk[i] * Hk[(i + 1) * m + j];
+                        Hk[(i + 1) * m + j] = -sk[i] * Hk[i * m + j] + ck[i] * Hk[(i + 1) * m + j];
+                        Hk[i * m + j] = t;
+                    }
+                    const double a = Hk[j * m + j], bb = Hk[(j + 1) * m + j];
+                    const double den = std::hypot(a, bb);
+                    ck[j] = den != 0.0 ? a / den : 1.0;
+                    sk[j] = den != 0.0 ? bb / den : 0.0;
+                    Hk[j * m + j] = den;
+                    Hk[(j + 1) * m + j] = 0.0;
+                    gk[j + 1] = -sk[j] * gk[j];
+                    gk[j] = ck[j] * gk[j];
+                    its[q] += 1;
+                    kk[q] = j + 1;
+                    if (std::fabs(gk[j + 1]) <= tol * bnorm[q] || its[q] >= maxit || den == 0.0) done[q] = 1;
+                    else sys_done = false;
                 }
-                const double a = Hk[j * m + j], bb = Hk[(j + 1) * m + j];
-                const double den = std::hypot(a, bb);
-                ck[j] = den != 0.0 ? a / den : 1.0;
-                sk[j] = den != 0.0 ? bb / den : 0.0;
-                Hk[j * m + j] = den;
-                Hk[(j + 1) * m + j] = 0.0;
-                gk[j + 1] = -sk[j] * gk[j];
-                gk[j] = ck[j] * gk[j];
-                its[k] += 1;
-                kk[k] = j + 1;
-                if (std::fabs(gk[j + 1]) <= tol * bnorm[k] || its[k] >= maxit || den == 0.0) done[k] = 1;
+                if (sys_done) { act[s] = 0; act_changed = true; }
                 else all_done = false;
             }
             if (all_done) break;
+            if (act_changed) put_act();
         }
-        // y_k from the triangular systems, then x += Z y
-        int J = 0;
-        std::vector<double> y((size_t)(m + 1) * nrhs, 0.0);
-        for (int k = 0; k < nrhs; ++k) {
-            if (!active[k] || kk[k] == 0) continue;
-            const double* Hk = H.data() + (size_t)k * (m + 1) * m;
-            const double* gk = g.data() + (size_t)k * (m + 1);
-            std::vector<double> yk(kk[k]);
-            for (int i = kk[k] - 1; i >= 0; --i) {
-                double s = gk[i];
-                for (int q = i + 1; q < kk[k]; ++q) s -= Hk[i * m + q] * yk[q];
-                yk[i] = Hk[i * m + i] != 0.0 ? s / Hk[i * m + i] : 0.0;
+        // y from the triangular systems, then x += Z y for the systems of this cycle
+        for (int s = 0; s < K; ++s) {
+            act[s] = in_cycle[s];
+            if (!act[s]) continue;
+            double* sm = hsm + (size_t)s * smsz;
+            double* y = sm + o_y;
+            std::fill(y, y + (size_t)(m + 1) * nrhs, 0.0);
+            int J = 0;
+            for (int k = 0; k < nrhs; ++k) {
+                const size_t q = (size_t)s * nrhs + k;
+                if (!active[q] || kk[q] == 0) continue;
+                const double* Hk = H.data() + q * (m + 1) * m;
+                const double* gk = g.data() + q * (m + 1);
+                std::vector<double> yk(kk[q]);
+                for (int i = kk[q] - 1; i >= 0; --i) {
+                    double t = gk[i];
+                    for (int c = i + 1; c < kk[q]; ++c) t -= Hk[i * m + c] * yk[c];
+                    yk[i] = Hk[i * m + i] != 0.0 ? t / Hk[i * m + i] : 0.0;
+                }
+                for (int i = 0; i < kk[q]; ++i) y[(size_t)i * nrhs + k] = yk[i];
+                J = std::max(J, kk[q]);
             }
-            for (int i = 0; i < kk[k]; ++i) y[(size_t)i * nrhs + k] = yk[i];
-            J = std::max(J, kk[k]);
+            sm[o_J] = (double)J;
         }
-        if (J > 0) {
-            std::memcpy(hs, y.data(), (size_t)J * nrhs * 8);
-            HIPCHK(hipMemcpyAsync(d_y, hs, (size_t)J * nrhs * 8, hipMemcpyHostToDevice, st));
-            HIPCHK(launch_xupdate(Z, nv, J, d_y, xt, n, nrhs, st));
-        }
+        put_act();
+        put_small();
+        HIPCHK(kry_axpy(L, 1, 0, 0, o_y, o_J));
     }
-    HIPCHK(launch_scatter_perm(xt, rp_perm, n, nrhs, x, n, st));
+    for (int s = 0; s < K; ++s) act[s] = 1;
+    put_act();
+    HIPCHK(kry_perm(L, 1));                   // x in the original order
     HIPCHK(hipStreamSynchronize(st));
     bool all_conv = true;
-    for (int k = 0; k < nrhs; ++k) {
-        if (iters_out) iters_out[k] = its[k];
-        if (relres_out) relres_out[k] = relres[k];
-        if (!conv[k]) all_conv = false;
+    for (size_t q = 0; q < KR; ++q) {
+        if (iters_out) iters_out[q] = its[q];
+        if (relres_out) relres_out[q] = relres[q];
+        if (!conv[q]) all_conv = false;
     }
     return all_conv ? LRX_OK : LRX_ENOCONV;
+}
+
+lrx_status gmres_dev(lrx_handle h, int nrhs, const double* b, double* x, double tol, int restart, int maxit,
+                     int32_t* iters_out, double* relres_out) {
+    return gmres_batch(1, &h, nrhs, &b, &x, tol, restart, maxit, iters_out, relres_out);
 }
 
 template <class F> lrx_status guarded(F&& f) {
@@ -1580,6 +1713,20 @@ void factor_many(int32_t k, const lrx_csr* A, const double* const* val_dev, cons
     }
 }
 
+// Arguments of the batched entry points: k distinct live handles on one device.
+void check_batch(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                 double* const* x_dev) {
+    if (k < 1 || k > 65535 || !hs || !b_dev || !x_dev) fail(LRX_EINVAL, "bad batch arguments");
+    if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+    std::set<lrx_handle> seen;
+    for (int i = 0; i < k; ++i) {
+        check_handle(hs[i]);
+        if (!b_dev[i] || !x_dev[i] || b_dev[i] == x_dev[i]) fail(LRX_EINVAL, "bad b/x pointers");
+        if (!seen.insert(hs[i]).second) fail(LRX_EINVAL, "a handle appears twice in the batch");
+        if (hs[i]->device != hs[0]->device) fail(LRX_EINVAL, "handles of a batch must share one device");
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1640,15 +1787,20 @@ lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tre
     });
 }
 
-lrx_status lrx_factor_batch(int32_t k, const lrx_csr* A, const lrx_tree* T, const lrx_opts* o,
-                            lrx_handle* out) {
+lrx_status lrx_factor_batch(int32_t k, const lrx_csr* A, const double* const* val_dev, const lrx_tree* T,
+                            const lrx_opts* o, lrx_handle* out) {
     return guarded([&]() -> lrx_status {
         if (!out) fail(LRX_EINVAL, "out is NULL");
         if (k < 1 || k > 65536) fail(LRX_EINVAL, "k must be in [1, 65536]");
         for (int32_t i = 0; i < k; ++i) out[i] = nullptr;
         if (!A || !T) fail(LRX_EINVAL, "null matrix or tree array");
-        std::vector<const double*> none(k, nullptr);
-        factor_many(k, A, none.data(), T, o, out);
+        std::vector<const double*> vd(k, nullptr);
+        if (val_dev)
+            for (int32_t i = 0; i < k; ++i) {
+                if (!val_dev[i]) fail(LRX_EINVAL, "system " + std::to_string(i) + ": val_dev is NULL");
+                vd[i] = val_dev[i];
+            }
+        factor_many(k, A, vd.data(), T, o, out);
         return LRX_OK;
     });
 }
@@ -1683,16 +1835,21 @@ lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double
 lrx_status lrx_solve_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
                                double* const* x_dev) {
     return guarded([&]() -> lrx_status {
-        if (k < 1 || !hs || !b_dev || !x_dev) fail(LRX_EINVAL, "bad batch arguments");
-        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
-        for (int i = 0; i < k; ++i) {
-            check_handle(hs[i]);
-            if (!b_dev[i] || !x_dev[i] || b_dev[i] == x_dev[i]) fail(LRX_EINVAL, "bad b/x pointers");
-            for (int j = 0; j < i; ++j)
-                if (hs[j] == hs[i]) fail(LRX_EINVAL, "a handle appears twice in the batch");
-        }
+        check_batch(k, hs, nrhs, b_dev, x_dev);
         solve_batch_dev(k, hs, nrhs, b_dev, x_dev);
         return LRX_OK;
+    });
+}
+
+lrx_status lrx_gmres_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                               double* const* x_dev, double tol, int32_t restart, int32_t maxit, int32_t* iters,
+                               double* relres) {
+    return guarded([&]() -> lrx_status {
+        check_batch(k, hs, nrhs, b_dev, x_dev);
+        if (!(tol > 0.0) || restart < 1 || restart > 200 || maxit < 0) fail(LRX_EINVAL, "bad tol/restart/maxit");
+        const lrx_status s = gmres_batch(k, hs, nrhs, b_dev, x_dev, tol, restart, maxit, iters, relres);
+        if (s == LRX_ENOCONV) g_err = "GMRES reached maxit before tol";
+        return s;
     });
 }
 

@@ -82,7 +82,7 @@ class PlanInfo(C.Structure):
 
 # every symbol declared in include/lorax.h
 EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_factor_batch", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
-           "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev",
+           "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev", "lrx_gmres_batch_dev",
            "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
            "lrx_last_error", "lrx_version")
 
@@ -97,7 +97,7 @@ def _load():
     sig = {
         "lrx_factor": (C.c_int, [P(Csr), P(Tree), P(Opts), P(C.c_void_p)]),
         "lrx_factor_dev": (C.c_int, [P(Csr), C.c_void_p, P(Tree), P(Opts), P(C.c_void_p)]),
-        "lrx_factor_batch": (C.c_int, [C.c_int32, P(Csr), P(Tree), P(Opts), P(C.c_void_p)]),
+        "lrx_factor_batch": (C.c_int, [C.c_int32, P(Csr), P(C.c_void_p), P(Tree), P(Opts), P(C.c_void_p)]),
         "lrx_timing_enable": (None, [C.c_int32]),
         "lrx_timing_read": (C.c_int, [P(Timing), C.c_int32]),
         "lrx_solve": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int64, f64p, C.c_int64]),
@@ -108,6 +108,8 @@ def _load():
                                 C.c_int32, C.c_int32, i32p, f64p]),
         "lrx_gmres_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
                                     C.c_int32, C.c_int32, i32p, f64p]),
+        "lrx_gmres_batch_dev": (C.c_int, [C.c_int32, P(C.c_void_p), C.c_int32, P(C.c_void_p),
+                                          P(C.c_void_p), C.c_double, C.c_int32, C.c_int32, i32p, f64p]),
         "lrx_free": (C.c_int, [C.c_void_p]),
         "lrx_stats": (C.c_int, [C.c_void_p, P(Stats)]),
         "lrx_ranks": (C.c_int, [C.c_void_p, i32p, i32p, i32p]),
@@ -195,20 +197,22 @@ def plan_inspect(row_ptr, col_idx, perm, leaf_ptr, depth, order="colored"):
 
 
 def factor_batch(systems, epsilon, order="colored", compress="svd", stream=None, hbm_budget_bytes=0,
-                 precision="fp64"):
+                 precision="fp64", val_dev=None):
     """Factorizes several systems in one lrx_factor_batch call.
-    systems: sequence of (row_ptr, col_idx, val, perm, leaf_ptr, depth).
+    systems: sequence of (row_ptr, col_idx, val, perm, leaf_ptr, depth); with
+    val_dev (a sequence of device addresses of each system's values) val may be None.
     Returns one Factor per system (each equal to factoring it alone)."""
     systems = list(systems)
     k = len(systems)
-    As = [_CsrArgs(rp, ci, v) for rp, ci, v, _, _, _ in systems]
+    As = [_CsrArgs(rp, ci, v if v is not None else np.zeros(0)) for rp, ci, v, _, _, _ in systems]
     Ts = [_TreeArgs(pm, lp, d) for _, _, _, pm, lp, d in systems]
     A_arr = (Csr * k)(*[a.s for a in As])
     T_arr = (Tree * k)(*[t.s for t in Ts])
     o = Opts(float(epsilon), PRECISION[precision], COMPRESS[compress], ORDERS[order],
              int(hbm_budget_bytes), C.c_void_p(stream) if stream else None)
     hs = (C.c_void_p * k)()
-    _check(_lib.lrx_factor_batch(k, A_arr, T_arr, C.byref(o), hs))
+    vd = None if val_dev is None else (C.c_void_p * k)(*[int(v) for v in val_dev])
+    _check(_lib.lrx_factor_batch(k, A_arr, vd, T_arr, C.byref(o), hs))
     return [Factor._adopt(C.c_void_p(hs[i]), As[i]) for i in range(k)]
 
 
@@ -341,3 +345,20 @@ def solve_batch_dev(factors, nrhs, b_ptrs, x_ptrs):
     bs = (C.c_void_p * k)(*[C.c_void_p(int(b)) for b in b_ptrs])
     xs = (C.c_void_p * k)(*[C.c_void_p(int(x)) for x in x_ptrs])
     _check(_lib.lrx_solve_batch_dev(int(k), hs, int(nrhs), bs, xs))
+
+
+def gmres_batch_dev(factors, nrhs, b_ptrs, x_ptrs, tol=1e-10, restart=30, maxit=500):
+    """lrx_gmres_batch_dev: FGMRES of every factor's system in lock-step.
+    b_ptrs[i], x_ptrs[i]: device addresses of n_i x nrhs column-major FP64 arrays.
+    Returns (iters, relres, status), each array of shape (k, nrhs)."""
+    k = len(factors)
+    hs = (C.c_void_p * k)(*[f._h.value for f in factors])
+    bp = (C.c_void_p * k)(*[int(p) for p in b_ptrs])
+    xp = (C.c_void_p * k)(*[int(p) for p in x_ptrs])
+    its = np.zeros((k, nrhs), dtype=np.int32)
+    rr = np.zeros((k, nrhs), dtype=np.float64)
+    st = _lib.lrx_gmres_batch_dev(k, hs, int(nrhs), bp, xp, float(tol), int(restart), int(maxit),
+                                  _ptr(its, C.c_int32), _ptr(rr, C.c_double))
+    if st not in (LRX_OK, LRX_ENOCONV):
+        _check(st)
+    return its, rr, st

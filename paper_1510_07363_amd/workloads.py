@@ -24,7 +24,7 @@ import scipy.sparse as sp
 __all__ = [
     "Problem", "poisson2d", "diffusion2d", "diffusion3d", "convdiff2d", "convdiff3d",
     "gaussian_field_2d", "rcb_tree", "tree_depth", "uniform_rhs", "grid_coords",
-    "make_config", "CONFIGS",
+    "make_config", "CONFIGS", "make_batch",
 ]
 
 
@@ -291,3 +291,36 @@ def make_config(which, seed=None, size=None):
 
 
 CONFIGS = ("poisson2d_32", "varcoef2d_256", "convdiff3d_64")
+
+
+def make_batch(count=256, seed=4, n_min=4096, n_max=110592, leaf=64, eps=1e-4, nrhs=4):
+    """Batch of independent systems (the batched-factorization workload).
+
+    System i is 2-D (i even) or 3-D (i odd) variable-coefficient diffusion; its
+    target size is log-uniform in [n_min, n_max] (mean about 32K, so 256 systems
+    hold about 8-9 million unknowns), rounded to a square s x s (s >= 64) or a
+    cube s^3 (16 <= s <= 48).  2-D coefficients: kappa = exp(g), g the Gaussian
+    field of correlation length 8; 3-D: kappa = exp(N(0,1)) per cell.  Leaf
+    clusters of at most `leaf` points, epsilon 1e-4, nrhs uniform right-hand
+    sides.  Returns a list of Problem."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+        r = np.random.default_rng([seed, i])
+        if i % 2 == 0:
+            s = int(min(max(round(math.sqrt(target)), 64), int(math.sqrt(n_max))))
+            kappa = np.exp(gaussian_field_2d((s, s), r, 8.0))
+            csr = diffusion2d(kappa, (s, s))
+            co = grid_coords((s, s))
+            grid = (s, s)
+        else:
+            s = int(min(max(round(target ** (1.0 / 3.0)), 16), 48))
+            kappa = np.exp(r.standard_normal(s ** 3))
+            csr = diffusion3d(kappa, (s, s, s))
+            co = grid_coords((s, s, s))
+            grid = (s, s, s)
+        out.append(_finish(f"batch{count}[{i}]", csr, co, leaf, eps, nrhs, r,
+                           {"grid": grid, "seed": seed, "index": i}))
+    return out
+

@@ -9,6 +9,7 @@ is rejected.
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from paper_1510_07363_amd import workloads as w
 
@@ -139,7 +140,7 @@ def test_factor_batch_single_system_and_errors(env):
         lx.factor_batch([(*csr, perm, lp, depth), (*csr, perm, bad_lp, depth)], 1e-6)
     assert e.value.status == lx.LRX_EINVAL and "system 1" in str(e.value)
     # an exactly singular pivot in one system: LRX_ESINGULAR for the batch
-    import scipy.sparse as sp
+
     A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n)).tolil()
     for r in perm[lp[0]:lp[1]]:
         A[r, :] = 0.0
@@ -154,3 +155,55 @@ def test_factor_batch_single_system_and_errors(env):
     # the library still works after the failed batches
     F2, = lx.factor_batch([(*csr, perm, lp, depth)], 1e-6)
     assert np.array_equal(F2.solve(b), Fs.solve(b))
+
+
+def test_gmres_batch_equals_single_gmres(env):
+    """FGMRES of several systems in lock-step (lrx_gmres_batch_dev): each system's
+    iterates are computed by the same launches over its own rows as when it runs
+    alone, so x, iteration counts and residuals are bit-identical to
+    lrx_gmres_dev; systems of different sizes converge at different steps and
+    drop out; a zero right-hand side stops at once with x = 0."""
+    lx, torch = env
+    nrhs = 3
+    ins = _batch_inputs(FSYSTEMS)
+    facs = lx.factor_batch([(*csr, perm, lp, depth) for csr, n, perm, lp, depth, _ in ins], 1e-3,
+                           precision="mixed")
+    bs, xs = [], []
+    for i, (csr, n, perm, lp, depth, rng) in enumerate(ins):
+        b = rng.uniform(-1, 1, (nrhs, n))
+        if i == 1:
+            b[2] = 0.0
+        bs.append(torch.from_numpy(b).to("cuda:0"))
+        xs.append(torch.zeros_like(bs[-1]))
+    its, rr, st = lx.gmres_batch_dev(facs, nrhs, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
+                                     tol=1e-10)
+    assert st == lx.LRX_OK
+    for i, ((csr, n, perm, lp, depth, rng), F) in enumerate(zip(ins, facs)):
+        x1 = torch.zeros_like(bs[i])
+        its1, rr1, st1 = F.gmres_dev(bs[i].data_ptr(), x1.data_ptr(), nrhs, tol=1e-10)
+        assert st1 == lx.LRX_OK
+        assert np.array_equal(its[i], its1) and np.array_equal(rr[i], rr1), (i, its[i], its1)
+        assert torch.equal(xs[i], x1), (i, float((xs[i] - x1).abs().max()))
+        A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n))
+        X = xs[i].cpu().numpy()
+        B = bs[i].cpu().numpy()
+        for k in range(nrhs):
+            nb = np.linalg.norm(B[k])
+            if nb == 0:
+                assert its[i][k] == 0 and not X[k].any()
+                continue
+            assert np.linalg.norm(A @ X[k] - B[k]) / nb <= 1e-10
+
+
+def test_gmres_batch_nonconvergence_and_errors(env):
+    lx, torch = env
+    ins = _batch_inputs([("diff2d", 24, 16, 31), ("diff2d", 32, 16, 32)])
+    facs = [lx.Factor(*csr, perm, lp, depth, 0.5) for csr, n, perm, lp, depth, _ in ins]
+    bs = [torch.from_numpy(rng.uniform(-1, 1, (1, n))).to("cuda:0") for csr, n, perm, lp, depth, rng in ins]
+    xs = [torch.zeros_like(b) for b in bs]
+    its, rr, st = lx.gmres_batch_dev(facs, 1, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
+                                     tol=1e-14, restart=2, maxit=3)
+    assert st == lx.LRX_ENOCONV and (its == 3).all() and (rr > 1e-14).all()
+    with pytest.raises(lx.LoraxError) as e:
+        lx.gmres_batch_dev([facs[0], facs[0]], 1, [bs[0].data_ptr()] * 2, [xs[0].data_ptr(), xs[1].data_ptr()])
+    assert e.value.status == lx.LRX_EINVAL
