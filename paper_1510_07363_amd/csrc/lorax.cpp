@@ -104,7 +104,10 @@ struct Arena {
     double* alloc(size_t n) {
         n = (n + 31) & ~(size_t)31;                   // 256-byte aligned blocks
         if (chunks.empty() || used + n > chunks.back().second) {
-            size_t cap = std::max(n, (size_t)(32u << 20));   // 256 MiB chunks
+            // chunks grow with the storage so far (4 MiB .. 256 MiB), so a small
+            // factorization holds little more than it uses
+            const size_t grow = std::min(std::max((size_t)total, (size_t)1 << 19), (size_t)32 << 20);
+            size_t cap = std::max(n, grow);
             double* p = nullptr;
             HIPCHK(hipMalloc(&p, cap * sizeof(double)));
             chunks.push_back({p, cap});
@@ -228,7 +231,7 @@ struct lrx_handle_s {
     DevBuf d_rp, d_ci, d_val;      // A in tree order
     int64_t nnz = 0;
     // scratch
-    DevBuf x_ext, ws_b, ws_x;
+    DevBuf x_ext, ws_b, ws_w;      // solve vector; factor workspaces (released after the factorization)
     DevBuf g_basis, g_z, g_w, g_r, g_b, g_x;
     DevBuf kry_tab, kry_small, kry_part;   // batched GMRES led by this handle
     PinBuf kry_pin;
@@ -304,7 +307,7 @@ struct FactorRun {
     std::vector<DPiece> pieces;
     std::vector<std::vector<int32_t>> a_row0, b_row0;
     std::vector<size_t> wsB, wsV, wsH, tail_at;
-    size_t ws_need = 0, w_need = 0, tails_total = 0;
+    size_t ws_need = 0, tails_total = 0;
     int64_t task0 = 0, tails0 = 0;         // first task / tail value in the batch arrays
 
     explicit FactorRun(lrx_handle h_) : h(h_), P(h_->plan) {}
@@ -535,28 +538,7 @@ size_t FactorRun::compress_tasks() {
         tail_at[ni] = tails_total;
         tails_total += (size_t)T.c + 2;
     }
-    // node-side W workspace, sized for the worst case r <= c before the ranks are known
-    w_need = 0;
-    for (int ni = 0; ni < nn; ++ni) {
-        const NodeStep& ns = cs.nodes[ni];
-        const int32_t ms = h->size[ns.s];
-        const int32_t rmax = std::min(ct[ni].c, ct[ni].M);
-        size_t sum_nc = 0;
-        for (int32_t e : ns.ps.in_edges) {
-            const PEdge& E = P.edges[e];
-            int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
-            sum_nc += (size_t)dim_of(E.cols, srcsz);
-        }
-        w_need += (((size_t)ms * sum_nc) + 31) & ~(size_t)31;
-        size_t sum_nc_b = 0;
-        for (int32_t e : ns.pb.in_edges) {
-            const PEdge& E = P.edges[e];
-            int32_t srcsz = h->size[E.src] >= 0 ? h->size[E.src] : rmax;
-            sum_nc_b += (size_t)dim_of(E.cols, srcsz);
-        }
-        w_need += (((size_t)rmax * sum_nc_b) + 31) & ~(size_t)31;
-    }
-    return ws_need + w_need;
+    return ws_need;
 }
 
 void FactorRun::bind_compress(double* wsp, int32_t* ranks_dev, double* tails_dev, int32_t piece_base) {
@@ -608,9 +590,23 @@ void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t
 void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
     const ColourStep& cs = P.steps[si];
     const int nn = (int)cs.nodes.size();
-    DevBuf& ws = h->ws_b;
+    // W_k = S^{-1}[:, rows of Mat(k->v)] Mat(k->v) for every pivot of the step, in
+    // a buffer of its own sized now that the ranks are known (the stream is idle
+    // after the rank read-back, so growing it is safe)
+    size_t wtot = 0;
+    auto w_of = [&](const PivotPlan& pp) {
+        const int32_t m = h->size[pp.node];
+        if (m == 0 || pp.e_self < 0) return;
+        for (int32_t e : pp.in_edges) wtot += (((size_t)m * nc_of(e)) + 31) & ~(size_t)31;
+    };
+    for (int ni = 0; ni < nn; ++ni) {
+        w_of(cs.nodes[ni].ps);
+        w_of(cs.nodes[ni].pb);
+    }
+    DevBuf& ws = h->ws_w;
+    if (wtot * 8 > ws.bytes) ws.ensure(wtot * 8 + (wtot * 8) / 2);
     double* wsp = ws.as<double>();
-    size_t wcur = ws_need;
+    size_t wcur = 0;
     const int64_t gf_s0 = nb.gf_s, gf_b0 = nb.gf_b, pf_s0 = nb.pf_s, pf_b0 = nb.pf_b;
     auto schur = [&](const PivotPlan& pp, const PivMaps& pm, std::vector<DGemm>& g1, std::vector<DGemm>& g2,
                      int64_t& gfl) {
@@ -700,7 +696,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
         schur(ns.pb, maps[si][ni].pb, nb.g1b, nb.g2b, nb.gf_b);
     }
     flops += (nb.pf_s - pf_s0) + (nb.pf_b - pf_b0) + (nb.gf_s - gf_s0) + (nb.gf_b - gf_b0);
-    if (wcur * 8 > ws.bytes) fail(LRX_EDEVICE, "internal: workspace estimate too small");
+    if (wcur != wtot) fail(LRX_EDEVICE, "internal: Schur workspace size mismatch");
 }
 
 // The level loop over one or several factorizations sharing the stream st.
@@ -913,6 +909,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                                                     : std::string("exactly singular pivot block"));
         r.h->stats.factor_flops = r.flops;
         r.h->t_sync_ms += t_sync;
+        r.h->ws_b.release();
+        r.h->ws_w.release();
     }
 }
 

@@ -1,0 +1,212 @@
+"""Serving loop (paper_1510_07363_amd.serve): scheduling, admission by HBM
+budget, eviction and re-factor on demand, continuous batching of solves, and
+"same result alone and in the mix".
+
+The CPU tests run the scheduler over a backend built on the oracle (factor and
+FGMRES in FP64 on the host, one right-hand side at a time), so batching cannot
+change a result and alone/mix equality is exact.  The GPU test runs the same
+scenarios on the library and bounds the alone/mix difference by the
+conditioning (both answers reach the residual tolerance).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_1510_07363_amd import workloads as w
+from paper_1510_07363_amd.serve import OutOfBudget, Server, SystemSpec
+
+
+def _spec(key, kind, nx, leaf, eps, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "diff2d":
+        csr = w.diffusion2d(np.exp(w.gaussian_field_2d((nx, nx), rng, 4.0)), (nx, nx))
+        co = w.grid_coords((nx, nx))
+    elif kind == "diff3d":
+        csr = w.diffusion3d(np.exp(rng.standard_normal(nx ** 3)), (nx, nx, nx))
+        co = w.grid_coords((nx, nx, nx))
+    else:
+        csr, co = w.convdiff2d(nx), w.grid_coords((nx, nx))
+    n = len(csr[0]) - 1
+    depth = w.tree_depth(n, leaf)
+    perm, lp = w.rcb_tree(co, depth)
+    return SystemSpec(key, *csr, perm, lp, depth, eps)
+
+
+class OracleBackend:
+    """Backend on the oracle: factor storage is charged at 800 bytes per unknown."""
+    PER_UNKNOWN = 800
+
+    def __init__(self):
+        self.factored, self.freed, self.batches = [], [], []
+
+    def factor(self, spec, room):
+        if spec.n * self.PER_UNKNOWN > room:
+            raise OutOfBudget(f"{spec.key} needs {spec.n * self.PER_UNKNOWN} > {room}")
+        F = oracle.factor(spec.row_ptr, spec.col_idx, spec.val, spec.perm, spec.leaf_ptr, spec.depth,
+                          spec.epsilon, check=False)
+        A = sp.csr_matrix((spec.val, spec.col_idx, spec.row_ptr), shape=(spec.n, spec.n))
+        self.factored.append(spec.key)
+        return {"key": spec.key, "F": F, "A": A, "n": spec.n}
+
+    def resident_bytes(self, h):
+        return h["n"] * self.PER_UNKNOWN
+
+    def free(self, h):
+        self.freed.append(h["key"])
+
+    def solve_batch(self, items, nrhs, tol, restart, maxit):
+        self.batches.append(([h["key"] for h, _ in items], nrhs))
+        out = []
+        for h, B in items:
+            X = np.zeros_like(B)
+            its = np.zeros(nrhs, dtype=np.int32)
+            rr = np.zeros(nrhs)
+            for k in range(nrhs):
+                o = oracle.fgmres(h["A"], lambda v: oracle.solve(h["F"], v), B[:, k], tol=tol,
+                                  restart=restart, maxit=maxit)
+                X[:, k], its[k], rr[k] = o["x"], o["iters"], o["relres"]
+            out.append((X, its, rr))
+        return out
+
+
+SPECS = [("a", "diff2d", 16, 16, 1e-3, 1), ("b", "diff2d", 20, 16, 1e-3, 2), ("c", "convdiff", 16, 8, 1e-2, 3)]
+
+
+def _server(budget_unknowns, **kw):
+    be = OracleBackend()
+    srv = Server(be, budget_unknowns * OracleBackend.PER_UNKNOWN, tol=1e-10, **kw)
+    specs = {}
+    for key, kind, nx, leaf, eps, seed in SPECS:
+        s = _spec(key, kind, nx, leaf, eps, seed)
+        srv.register(s)
+        specs[key] = s
+    return srv, be, specs
+
+
+def test_continuous_batching_and_alone_equals_mix():
+    rng = np.random.default_rng(0)
+    srv, be, specs = _server(10_000)
+    reqs = [("a", rng.uniform(-1, 1, specs["a"].n)), ("b", rng.uniform(-1, 1, (specs["b"].n, 3))),
+            ("a", rng.uniform(-1, 1, (specs["a"].n, 2))), ("c", rng.uniform(-1, 1, specs["c"].n))]
+    futs = [srv.submit(k, b) for k, b in reqs]
+    srv.run_until_idle()
+    # one round: factors admitted, then every request in one batch over three systems,
+    # "a" carrying both of its requests (1 + 2 columns), all padded to width 4
+    assert sorted(be.factored) == ["a", "b", "c"]
+    assert len(be.batches) == 1 and sorted(be.batches[0][0]) == ["a", "b", "c"] and be.batches[0][1] == 4
+    for (key, b), f in zip(reqs, futs):
+        x, its, rr = f.result()
+        assert x.shape == b.shape and (rr <= 1e-10).all()
+        # the same request served alone gives the same answer
+        srv2, _, _ = _server(10_000)
+        f2 = srv2.submit(key, b)
+        srv2.run_until_idle()
+        x2, its2, rr2 = f2.result()
+        assert np.array_equal(x, x2) and np.array_equal(its, its2)
+        A = sp.csr_matrix((specs[key].val, specs[key].col_idx, specs[key].row_ptr), shape=(specs[key].n,) * 2)
+        B = b.reshape(specs[key].n, -1)
+        X = x.reshape(specs[key].n, -1)
+        assert (np.linalg.norm(A @ X - B, axis=0) / np.linalg.norm(B, axis=0) <= 1e-10).all()
+    st = srv.latency_stats()
+    assert st["count"] == 4 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_admission_by_budget_evicts_idle_and_refactors_on_demand():
+    rng = np.random.default_rng(1)
+    # room for "b" (400 unknowns) or "a" + "c" (256 + 256), not all three
+    srv, be, specs = _server(600)
+    fa = srv.submit("a", rng.uniform(-1, 1, specs["a"].n))
+    srv.run_until_idle()
+    assert list(srv.resident) == ["a"]
+    fb = srv.submit("b", rng.uniform(-1, 1, specs["b"].n))
+    srv.run_until_idle()                                   # "a" is idle: evicted for "b"
+    assert list(srv.resident) == ["b"] and be.freed == ["a"] and srv.n_evicted == 1
+    assert srv.resident_bytes() <= srv.budget
+    fa2 = srv.submit("a", rng.uniform(-1, 1, specs["a"].n))
+    srv.run_until_idle()                                   # re-factored on demand
+    assert be.factored == ["a", "b", "a"]
+    for f in (fa, fb, fa2):
+        assert (f.result()[2] <= 1e-10).all()
+
+
+def test_admission_waits_for_busy_factor_then_serves():
+    rng = np.random.default_rng(2)
+    srv, be, specs = _server(600)
+    srv.submit("b", rng.uniform(-1, 1, specs["b"].n))
+    srv.step()                                             # "b" resident and served
+    fb = srv.submit("b", rng.uniform(-1, 1, specs["b"].n))
+    fa = srv.submit("a", rng.uniform(-1, 1, specs["a"].n))
+    srv.step()       # "a" does not fit while "b" has a pending solve: "b" is served first
+    assert fb.done() and not fa.done() and "a" not in srv.resident
+    srv.run_until_idle()
+    assert fa.done() and (fa.result()[2] <= 1e-10).all()
+
+
+def test_request_too_large_fails_its_future_only():
+    rng = np.random.default_rng(3)
+    srv, be, specs = _server(300)                          # "b" (400 unknowns) never fits
+    fb = srv.submit("b", rng.uniform(-1, 1, specs["b"].n))
+    fa = srv.submit("a", rng.uniform(-1, 1, specs["a"].n))
+    srv.run_until_idle()
+    with pytest.raises(MemoryError):
+        fb.result()
+    assert (fa.result()[2] <= 1e-10).all()
+
+
+def test_batch_limits_split_rounds():
+    rng = np.random.default_rng(4)
+    srv, be, specs = _server(10_000, max_batch_systems=2, max_width=4)
+    futs = [srv.submit(k, rng.uniform(-1, 1, (specs[k].n, 3))) for k in ("a", "b", "c", "a")]
+    srv.run_until_idle()
+    assert all(len(keys) <= 2 for keys, _ in be.batches) and all(wd <= 4 for _, wd in be.batches)
+    assert len(be.batches) >= 2
+    for f in futs:
+        assert (f.result()[2] <= 1e-10).all()
+
+
+def test_submit_validation():
+    srv, be, specs = _server(10_000)
+    with pytest.raises(KeyError):
+        srv.submit("zz", np.zeros(3))
+    with pytest.raises(ValueError):
+        srv.submit("a", np.zeros(specs["a"].n + 1))
+
+
+@pytest.mark.gpu
+def test_serve_on_gpu_alone_vs_mix():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1510_07363_amd.serve import LoraxBackend
+    rng = np.random.default_rng(5)
+    specs = [_spec("p", "diff2d", 48, 16, 1e-5, 11), _spec("q", "diff3d", 12, 32, 1e-3, 12),
+             _spec("r", "convdiff", 40, 16, 1e-3, 13)]
+    srv = Server(LoraxBackend(precision="mixed"), 8 << 30, tol=1e-10)
+    for s in specs:
+        srv.register(s)
+    reqs = [(s.key, rng.uniform(-1, 1, (s.n, k))) for s, k in zip(specs, (1, 5, 2))]
+    reqs.append(("p", rng.uniform(-1, 1, (specs[0].n, 3))))
+    futs = [srv.submit(k, b) for k, b in reqs]
+    srv.run_until_idle()
+    assert srv.batches == [3] and srv.n_factored == 3
+    bykey = {s.key: s for s in specs}
+    for (key, b), f in zip(reqs, futs):
+        x, its, rr = f.result()
+        s = bykey[key]
+        A = sp.csr_matrix((s.val, s.col_idx, s.row_ptr), shape=(s.n, s.n))
+        r_mix = np.linalg.norm(A @ x - b, axis=0) / np.linalg.norm(b, axis=0)
+        assert (r_mix <= 1e-10).all() and (rr <= 1e-10).all()
+        # alone: the same request through the same server (factor resident)
+        f1 = srv.submit(key, b)
+        srv.run_until_idle()
+        x1 = f1.result()[0]
+        r1 = np.linalg.norm(A @ x1 - b, axis=0) / np.linalg.norm(b, axis=0)
+        smin = np.linalg.svd(A.toarray(), compute_uv=False)[-1]
+        bound = (r_mix + r1) * np.linalg.norm(b, axis=0) / smin
+        assert (np.linalg.norm(x - x1, axis=0) <= 1.01 * bound + 1e-14).all()
+    st = srv.latency_stats()
+    assert st["count"] == 8
+    srv.close()
+    assert srv.resident_bytes() == 0
