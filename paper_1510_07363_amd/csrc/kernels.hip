@@ -808,6 +808,433 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     }
 }
 
+// ---------------------------------------------------------------- large stacked blocks
+// Compress for c > 64 columns (FP64, 1024 threads, matrices in the task's
+// workspace): the pipeline of k_compress_svd64 with global-memory QRs.
+//   1. B / 2^e = Q0 R0 (Householder on a copy of B; the reflector in LDS).
+//   2. R0 P = Q1 R1 (column pivoting, norms recomputed each step).  With a
+//      truncation level t = trunc_rel * epsilon > 0 the factorization stops at the first k whose
+//      trailing block has ||R1[k:, k:]||_F <= t |R1[0, 0]| (<= t sigma_0); the
+//      dropped rows move each sigma_i^2 by at most that squared norm, so at
+//      t = epsilon / 100 the singular values near the cut move by about
+//      1/20000 of it (used in mixed precision).  t = 0 keeps every row
+//      that is not exactly zero.
+//   3. R1[:k, :]^T = Q2 R2, L = R2^T (k x k, lower triangular and graded).
+//   4. one-sided Jacobi on the columns of L with W = Q2 accumulating the
+//      rotations: B P = Q0 Q1 L Q2^T, so V = P Q2 J and sigma = column norms.
+// Singular values beyond k (t > 0) are reported as the bound of the dropped
+// part.  Workspace: Bw (M x c) for step 1; hv holds X (c x c: R0, R1, then L),
+// A2 (c x c), W (c x c) and c scratch doubles.  LDS: reflector (M doubles),
+// column norms, perm and the singular values.
+constexpr int NTL = 1024;
+constexpr int NWL = NTL / WAVE;
+
+__device__ double blk_sum_l(double v, double* s_red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (threadIdx.x % WAVE == 0) s_red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < NWL; ++k) t += s_red[k];
+    return t;
+}
+
+// Householder QR step on column j of the nr x ncol matrix A (column-major, ld):
+// rows j..nr-1 reduced, columns j+1..ncol-1 updated; the reflector v (v[0] =
+// v0, v[i - j] = A[i, j] for i > j) is left in A below the diagonal and in
+// s_v (LDS copy, length nr - j).  Returns tau (0: H = I).  Every thread calls it.
+__device__ double hh_step(double* A, int64_t ld, int nr, int ncol, int j, double* s_v, double* s_red,
+                          double* v0_out) {
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < nr; i += NTL) {
+        const double x = A[i + j * ld];
+        s_v[i - j] = x;
+        part += x * x;
+    }
+    const double nvt = blk_sum_l(part, s_red);        // barrier inside: s_v visible
+    const double ajj = A[j + j * ld];
+    double tau = 0.0, v0 = 0.0, alpha = ajj;
+    if (nvt > 1e-280) {
+        const double s2 = ajj * ajj + nvt;
+        const double xn = sqrt(s2);
+        alpha = -copysign(xn, ajj);
+        v0 = ajj - alpha;
+        tau = 1.0 / (s2 + fabs(ajj) * xn);
+    }
+    if (tau != 0.0) {
+        // each lane keeps its elements of the column in registers (8 per pass)
+        constexpr int E = 8;
+        for (int k = j + 1 + wv; k < ncol; k += NWL) {
+            double* col = A + k * ld;
+            const double cj = col[j];
+            double w = 0.0;
+            if (nr - (j + 1) <= WAVE * E) {
+                double x[E];
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int i = j + 1 + lane + WAVE * u;
+                    x[u] = i < nr ? col[i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int i = j + 1 + lane + WAVE * u;
+                    if (i < nr) w += s_v[i - j] * x[u];
+                }
+                w = (wave_sum(w) + v0 * cj) * tau;
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int i = j + 1 + lane + WAVE * u;
+                    if (i < nr) col[i] = x[u] - w * s_v[i - j];
+                }
+            } else {                                  // longer columns: two passes
+                for (int i0 = j + 1; i0 < nr; i0 += WAVE * E) {
+                    double x[E];
+#pragma unroll
+                    for (int u = 0; u < E; ++u) {
+                        const int i = i0 + lane + WAVE * u;
+                        x[u] = i < nr ? col[i] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < E; ++u) {
+                        const int i = i0 + lane + WAVE * u;
+                        if (i < nr) w += s_v[i - j] * x[u];
+                    }
+                }
+                w = (wave_sum(w) + v0 * cj) * tau;
+                for (int i0 = j + 1; i0 < nr; i0 += WAVE * E) {
+                    double x[E];
+#pragma unroll
+                    for (int u = 0; u < E; ++u) {
+                        const int i = i0 + lane + WAVE * u;
+                        x[u] = i < nr ? col[i] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < E; ++u) {
+                        const int i = i0 + lane + WAVE * u;
+                        if (i < nr) col[i] = x[u] - w * s_v[i - j];
+                    }
+                }
+            }
+            if (lane == 0) col[j] = cj - w * v0;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) A[j + j * ld] = alpha;
+    *v0_out = v0;
+    return tau;
+}
+
+// One Jacobi rotation of columns p, q of L (length kk) and of W (length c) by a
+// group of GL lanes (GL = 16, 32 or 64, aligned inside a wavefront); each lane
+// holds E elements of each L column in registers, so all loads of a pass are in
+// flight together.  Columns longer than GL * E take two passes.
+template <int GL>
+__device__ __forceinline__ double grp_sum(double v) {
+    v = row16_sum(v);
+    if (GL >= 32) v += __shfl_xor(v, 16);
+    if (GL >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
+template <int GL, int E>
+__device__ bool jac_pair(double* __restrict__ cp, double* __restrict__ cq, double* __restrict__ wp,
+                         double* __restrict__ wq, int kk, int c, int gl, double tol, double tiny2) {
+    constexpr int SPAN = GL * E;
+    double xp[E], xq[E];
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int r0 = 0; r0 < kk; r0 += SPAN) {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int r = r0 + gl + GL * u;
+            xp[u] = r < kk ? cp[r] : 0.0;
+            xq[u] = r < kk ? cq[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            al += xp[u] * xp[u];
+            be += xq[u] * xq[u];
+            ga += xp[u] * xq[u];
+        }
+    }
+    al = grp_sum<GL>(al);
+    be = grp_sum<GL>(be);
+    ga = grp_sum<GL>(ga);
+    if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be)) || al <= tiny2 || be <= tiny2) return false;
+    const double zeta = (be - al) / (2.0 * ga);
+    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+    for (int r0 = 0; r0 < kk; r0 += SPAN) {
+        if (kk > SPAN) {                         // reload the chunk (uniform)
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int r = r0 + gl + GL * u;
+                xp[u] = r < kk ? cp[r] : 0.0;
+                xq[u] = r < kk ? cq[r] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int r = r0 + gl + GL * u;
+            if (r < kk) {
+                cp[r] = cs * xp[u] - sn * xq[u];
+                cq[r] = sn * xp[u] + cs * xq[u];
+            }
+        }
+    }
+    constexpr int EW = E > 8 ? 8 : E;            // W in passes of GL * 8 rows
+    for (int r0 = 0; r0 < c; r0 += GL * EW) {
+        double yp[EW], yq[EW];
+#pragma unroll
+        for (int u = 0; u < EW; ++u) {
+            const int r = r0 + gl + GL * u;
+            yp[u] = r < c ? wp[r] : 0.0;
+            yq[u] = r < c ? wq[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < EW; ++u) {
+            const int r = r0 + gl + GL * u;
+            if (r < c) {
+                wp[r] = cs * yp[u] - sn * yq[u];
+                wq[r] = sn * yp[u] + cs * yq[u];
+            }
+        }
+    }
+    return true;
+}
+
+// A sweep round of the parallel ordering: pair i of round t joins columns
+// (t + i) mod (n2 - 1) and (t - i) mod (n2 - 1), pair 0 taking column n2 - 1.
+template <int GL, int E>
+__device__ void jac_round(double* X, double* W, int64_t ldc, int kk, int c, int n2, int t, double tol,
+                          double tiny2, int* s_rot) {
+    const int g = threadIdx.x / GL, gl = threadIdx.x % GL;
+    for (int pi = g; pi < n2 / 2; pi += NTL / GL) {
+        const int a = (t + pi) % (n2 - 1);
+        const int b = pi == 0 ? n2 - 1 : (t - pi + n2 - 1) % (n2 - 1);
+        const int pp = a < b ? a : b, qq = a < b ? b : a;
+        if (qq >= kk) continue;                  // uniform over the group
+        if (jac_pair<GL, E>(X + pp * ldc, X + qq * ldc, W + pp * ldc, W + qq * ldc, kk, c, gl, tol, tiny2) &&
+            gl == 0)
+            *s_rot = 1;
+    }
+}
+
+__global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
+                                                        const DPiece* __restrict__ pieces,
+                                                        const int32_t* __restrict__ imap, double trunc_rel) {
+    const DCompress T = tasks[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x;
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    const double trunc = trunc_rel * T.eps;
+    extern __shared__ double sl[];
+    __shared__ double s_red[NWL];
+    __shared__ int s_piv;
+    __shared__ int s_rot;
+    if (M == 0 || c == 0) {
+        if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; }
+        return;
+    }
+    // LDS: reflector (max(M, c) + 1), norms (c), sv (c), hv0 (c), htau (c), perm (c), pos (c)
+    const int vlen = (M > c ? M : c) + 1;
+    double* s_v = sl;
+    double* s_nrm = s_v + vlen;
+    double* s_sv = s_nrm + c;
+    double* s_hv0 = s_sv + c;
+    double* s_tau = s_hv0 + c;
+    int* s_perm = reinterpret_cast<int*>(s_tau + c);
+    int* s_pos = s_perm + c;
+    // ---- assemble B (column-major, ld M; kept for the projection), max |B|
+    double* __restrict__ B = T.B;
+    for (int64_t e = tid; e < (int64_t)M * c; e += NTL) B[e] = 0.0;
+    __syncthreads();
+    double amax = 0.0;
+    for (int q = 0; q < T.npieces; ++q) {
+        const DPiece pc = pieces[T.piece0 + q];
+        const int nr = pc.blk.nr, nc = pc.blk.nc;
+        for (int e = tid; e < nr * nc; e += NTL) {
+            const int a = e % nr, b = e / nr;
+            const double v = pc.blk.p[e];
+            amax = fmax(amax, fabs(v));
+            if (!pc.trans) B[(pc.row0 + a) + (int64_t)imap_at(imap, pc.map, b) * M] = v;
+            else           B[(pc.row0 + b) + (int64_t)imap_at(imap, pc.map, a) * M] = v;
+        }
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    __syncthreads();
+    if (lane == 0) s_red[wv] = amax;
+    __syncthreads();
+    amax = 0.0;
+    for (int t = 0; t < NWL; ++t) amax = fmax(amax, s_red[t]);
+    const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
+    const double inv_scale = ldexp(1.0, -bexp), scale = ldexp(1.0, bexp);
+    double* X = T.hv;                                   // c x c, ld c
+    double* A2 = X + (size_t)c * c;                     // c x c
+    double* W = A2 + (size_t)c * c;                     // c x c
+    const int64_t ldc = c;
+    // ---- 1. tall QR of B / 2^e on the copy Bw
+    double* Bw = T.Bw;
+    for (int64_t e = tid; e < (int64_t)M * c; e += NTL) Bw[e] = B[e] * inv_scale;
+    __syncthreads();
+    const int kq = M < c ? M : c;
+    for (int j = 0; j < kq; ++j) {
+        double v0;
+        hh_step(Bw, M, M, c, j, s_v, s_red, &v0);
+        __syncthreads();
+    }
+    for (int e = tid; e < c * c; e += NTL) {
+        const int i = e % c, k = e / c;
+        X[e] = (i <= k && i < kq) ? Bw[i + (int64_t)k * M] : 0.0;
+    }
+    for (int k = tid; k < c; k += NTL) s_perm[k] = k;
+    __syncthreads();
+    // ---- 2. QRCP of R0 (rows < kq are the only nonzero ones), truncated
+    int kk = 0;
+    double rest2 = 0.0, r00 = 0.0;
+    for (int j = 0; j < kq; ++j) {
+        // squared norms of columns j..c-1 over rows j..kq-1
+        for (int k = j + wv; k < c; k += NWL) {
+            double q = 0.0;
+            for (int i = j + lane; i < kq; i += WAVE) { const double x = X[i + k * ldc]; q += x * x; }
+            q = wave_sum(q);
+            if (lane == 0) s_nrm[k] = q;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double best = -1.0, tot = 0.0;
+            int bi = INT_MAX;
+            for (int k = j + lane; k < c; k += WAVE) {
+                const double q = s_nrm[k];
+                tot += q;
+                if (q > best) { best = q; bi = k; }
+            }
+            tot = wave_sum(tot);
+            wave_argmax(best, bi);
+            if (lane == 0) { s_piv = bi; s_red[0] = tot; s_red[1] = best; }
+        }
+        __syncthreads();
+        const int p = s_piv;
+        const double tot = s_red[0], best = s_red[1];
+        if (j == 0) r00 = sqrt(best);
+        // stop: nothing left, or the trailing block is below the truncation level
+        if (!(best > 0.0) || tot <= trunc * trunc * r00 * r00) { rest2 = tot; break; }
+        __syncthreads();
+        if (p != j) {
+            for (int i = tid; i < c; i += NTL) {
+                const double a = X[i + j * ldc];
+                X[i + j * ldc] = X[i + p * ldc];
+                X[i + p * ldc] = a;
+            }
+            if (tid == 0) { const int t = s_perm[j]; s_perm[j] = s_perm[p]; s_perm[p] = t; }
+            __syncthreads();
+        }
+        double v0;
+        hh_step(X, ldc, kq, c, j, s_v, s_red, &v0);
+        kk = j + 1;
+        __syncthreads();
+    }
+    // ---- 3. A2 = R1[:kk, :]^T (c x kk, lower trapezoidal), QR -> R2, L = R2^T
+    for (int e = tid; e < c * kk; e += NTL) {
+        const int i = e % c, k = e / c;
+        A2[i + k * ldc] = (i >= k) ? X[k + i * ldc] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < kk; ++j) {
+        double v0;
+        const double tau = hh_step(A2, ldc, c, kk, j, s_v, s_red, &v0);
+        if (tid == 0) { s_hv0[j] = v0; s_tau[j] = tau; }
+        __syncthreads();
+    }
+    for (int e = tid; e < kk * kk; e += NTL) {
+        const int i = e % kk, k = e / kk;
+        X[i + k * ldc] = (k <= i) ? A2[k + i * ldc] : 0.0;   // L (kk x kk, ld c)
+    }
+    for (int e = tid; e < c * kk; e += NTL) {
+        const int i = e % c, k = e / c;
+        W[i + k * ldc] = (i == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // W = Q2[:, :kk] = H_0 ... H_{kk-1} E, applied right to left; H_j changes
+    // rows j.. of columns j.. only
+    for (int j = kk - 1; j >= 0; --j) {
+        const double tau = s_tau[j];
+        if (tau == 0.0) continue;                        // uniform
+        const double v0 = s_hv0[j];
+        for (int i = j + 1 + tid; i < c; i += NTL) s_v[i - j] = A2[i + j * ldc];
+        __syncthreads();
+        for (int k = j + wv; k < kk; k += NWL) {
+            double* col = W + k * ldc;
+            double w = 0.0;
+            for (int i = j + 1 + lane; i < c; i += WAVE) w += s_v[i - j] * col[i];
+            w = (wave_sum(w) + v0 * col[j]) * tau;
+            for (int i = j + 1 + lane; i < c; i += WAVE) col[i] -= w * s_v[i - j];
+            if (lane == 0) col[j] -= w * v0;
+        }
+        __syncthreads();
+    }
+    // ---- 4. one-sided Jacobi on the kk columns of L; W follows.  Pairs run in
+    // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes
+    if (kk > 1) {
+        const int n2 = kk + (kk & 1);
+        const double u = 1.1102230246251565e-16;
+        const double tol = 3.6 * u * (double)kk;
+        double f = 0.0;
+        for (int e = tid; e < kk * kk; e += NTL) {
+            const double x = X[(e % kk) + (e / kk) * ldc];
+            f += x * x;
+        }
+        const double fro = blk_sum_l(f, s_red);
+        const double tiny2 = 81.0 * u * u * fro;
+        for (int sweep = 0; sweep < 40; ++sweep) {
+            if (tid == 0) s_rot = 0;
+            __syncthreads();
+            for (int t = 0; t < n2 - 1; ++t) {
+                if (kk <= 128) jac_round<16, 8>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
+                else if (kk <= 256) jac_round<16, 16>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
+                else if (kk <= 512) jac_round<32, 16>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
+                else jac_round<64, 16>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
+                __syncthreads();
+            }
+            const int rot = s_rot;
+            __syncthreads();
+            if (!rot) break;
+        }
+    }
+    // ---- singular values, order, rank, V = P W
+    for (int k = wv; k < kk; k += NWL) {
+        double s2 = 0.0;
+        for (int r = lane; r < kk; r += WAVE) { const double x = X[r + k * ldc]; s2 += x * x; }
+        s2 = wave_sum(s2);
+        if (lane == 0) s_sv[k] = sqrt(s2) * scale;
+    }
+    __syncthreads();
+    for (int k = tid; k < kk; k += NTL) s_pos[k] = desc_pos(s_sv, kk, k);
+    __syncthreads();
+    double smax = 0.0;
+    for (int k = 0; k < kk; ++k) smax = fmax(smax, s_sv[k]);
+    const double bound = sqrt(fmax(rest2, 0.0)) * scale;
+    for (int k = tid; k < kk; k += NTL) T.tails[1 + s_pos[k]] = s_sv[k];
+    for (int k = kk + tid; k < c; k += NTL) T.tails[1 + k] = bound;
+    int r = 0;
+    if (smax > 0.0)
+        for (int k = 0; k < kk; ++k) r += (s_sv[k] >= T.eps * smax) ? 1 : 0;
+    for (int e = tid; e < c * kk; e += NTL) {
+        const int a = e % c, k = e / c;
+        const int pos = s_pos[k];
+        if (pos < r) T.V[s_perm[a] + (size_t)pos * c] = W[a + k * ldc];
+    }
+    if (tid == 0) {
+        T.tails[0] = smax;
+        *T.rank_out = r;
+    }
+}
+
+// LDS of k_compress_large in bytes, or 0 when the task does not fit
+inline size_t compress_large_lds(int M, int c) {
+    const size_t vlen = (size_t)(M > c ? M : c) + 1;
+    return (vlen + 4 * (size_t)c) * sizeof(double) + 2 * (size_t)c * sizeof(int);
+}
+
 // ------------------------------------------------------------------ elimination
 constexpr int NTP = 1024;                    // threads of the pivot-preparation kernel
 constexpr int NWP = NTP / WAVE;
@@ -1571,6 +1998,22 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
         hipLaunchKernelGGL(k_compress_svd<8>, dim3(n), dim3(NT), lds, st, t, pieces, imap, cap);
     else
         hipLaunchKernelGGL(k_compress_svd<16>, dim3(n), dim3(NT), lds, st, t, pieces, imap, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
+                                 int max_M, double trunc_rel, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t lds = compress_large_lds(max_M, max_c);
+    if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_compress_large, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_compress_large, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel);
     return hipGetLastError();
 }
 

@@ -27,6 +27,16 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 // fp32: reduced QRs and Jacobi in FP32 when every task has c <= 64 (mixed precision)
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                                int max_c, int max_M, bool fp32, hipStream_t st);
+// Truncated SVD of stacked blocks with c > 64 columns (FP64, matrices in the
+// workspace: hv needs 3 c^2 + c doubles, Bw M c).  Trailing QRCP rows below
+// trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
+// zeros).  Fits when compress_large_fits(M, c).
+hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
+                                 int max_M, double trunc_rel, hipStream_t st);
+inline bool compress_large_fits(int M, int c) {
+    const size_t vlen = (size_t)(M > c ? M : c) + 1;
+    return (vlen + 4 * (size_t)c) * sizeof(double) + 2 * (size_t)c * sizeof(int) <= 152 * 1024;
+}
 // Projection, rewiring and pivot inverse per task (DPrep); info[slot] = 1 for an
 // exactly singular pivot.
 hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,

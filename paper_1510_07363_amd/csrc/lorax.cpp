@@ -534,7 +534,8 @@ size_t FactorRun::compress_tasks() {
         T.eps = h->epsilon;
         wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
         wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
-        wsH[ni] = ws_need; ws_need += ((size_t)T.c * T.c + T.c + 31) & ~(size_t)31;
+        // hv: c^2 + c, or 3 c^2 + c for the large-block SVD (c > 64)
+        wsH[ni] = ws_need; ws_need += ((size_t)T.c * T.c * (svd && T.c > 64 ? 3 : 1) + T.c + 31) & ~(size_t)31;
         tail_at[ni] = tails_total;
         tails_total += (size_t)T.c + 2;
     }
@@ -805,12 +806,18 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 for (size_t q = 0; q < r->ct.size(); ++q)
                     fp32_of.push_back((r->h->compress == LRX_SVD ? 0 : 4) | (r->fp32_compress ? 1 : 0));
             }
-            // variants: SVD with c <= 64 (FP64 / FP32 arithmetic), SVD with c > 64,
-            // pivoted QR; each task takes its own variant whatever the others are
+            // variants: SVD with c <= 64 (FP64 / FP32 arithmetic: keys 0 / 1), SVD
+            // with c > 64 (key 8: FP64 rows kept, 9: rows below epsilon / 100
+            // dropped in mixed precision; key 2 when its LDS does not fit), pivoted
+            // QR (key 4); each task takes its own variant whatever the others are
             struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0; size_t off = 0; };
             std::vector<Group> groups;
             for (size_t q = 0; q < all.size(); ++q) {
-                const int key = fp32_of[q] == 4 || fp32_of[q] == 5 ? 4 : (all[q].c <= 64 ? fp32_of[q] : 2);
+                int key;
+                if (fp32_of[q] >= 4) key = 4;
+                else if (all[q].c <= 64) key = fp32_of[q];
+                else if (compress_large_fits(all[q].M, all[q].c)) key = 8 | (fp32_of[q] & 1);
+                else key = 2;
                 size_t g = 0;
                 while (g < groups.size() && groups[g].key != key) ++g;
                 if (g == groups.size()) { groups.push_back(Group{}); groups[g].key = key; }
@@ -835,6 +842,9 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                     LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, G.fl);
                     if (G.key == 4)
                         HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, st));
+                    else if (G.key >= 8)
+                        HIPCHK(launch_compress_large(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
+                                                     (G.key & 1) ? 0.01 : 0.0, st));
                     else
                         HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
                                                    (G.key & 1) != 0, st));
