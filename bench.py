@@ -31,6 +31,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+# HBM bytes per launch of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE over every dispatch of that kernel in this bench (each counter scaled by
+# what it reads for a plain device copy of known size: FETCH_SIZE x 2.00, WRITE_SIZE
+# x 1.00); kept per (workload, precision, kernel class) and reported as the
+# roofline's traffic.
+TRAFFIC_BYTES = {
+    ("varcoef2d_256", "mixed", "compress"): 2.195e6,
+    ("varcoef2d_256", "fp64", "compress"): 2.204e6,
+}
 TOL = 1e-10
 RESTART = 30
 
@@ -49,6 +59,9 @@ def parse():
                     help="systems per lrx_factor_batch call in the batch256 workload")
     ap.add_argument("--cpu-sample-side", type=int, default=128,
                     help="grid side of the oracle's bounded sample (same recipe)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only copy this many bytes device to device and exit (a plain copy of known "
+                         "size, the reference for the HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -85,10 +98,12 @@ def cpu_baseline(workload, side):
                        f"to n={full.n}")}
 
 
-def roofline(timing, dom):
+def roofline(timing, dom, precision="fp64"):
     """Roofline entry of kernel class dom from its event-timed launches: HBM
     bound for the sweeps and the SpMV (algorithmic bytes per launch), ALU bound
-    otherwise (algorithmic FP64 flops per launch)."""
+    otherwise (algorithmic flops per launch, against the FP32 vector peak for the
+    compression in mixed precision, whose reduced QRs and Jacobi run in FP32,
+    else the FP64 peak)."""
     d = timing[dom]
     avg_ms = d["total_ms"] / max(d["launches"], 1)
     if dom in ("solve_fwd", "solve_bwd", "spmv"):
@@ -99,15 +114,16 @@ def roofline(timing, dom):
     else:
         per_launch = d["flops"] / max(d["launches"], 1)
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+        peak = FP32_PEAK_TFLOPS if (dom == "compress" and precision == "mixed") else FP64_PEAK_TFLOPS
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = d["launches"]
     return roof
 
 
-def timed_steps(args, lorax, torch, step):
+def timed_steps(args, lorax, torch, step, precision="fp64"):
     """Warm-up, one untimed probe step (finds the dominant kernel class), then
     exactly args.steps timed steps bracketed by stream synchronisation."""
     for _ in range(args.warmup):
@@ -126,7 +142,7 @@ def timed_steps(args, lorax, torch, step):
     t1 = time.perf_counter()
     timing = lorax.timing_read(reset=True)
     lorax.timing_enable([])
-    return t1 - t0, probe, roofline(timing, dom)
+    return t1 - t0, probe, roofline(timing, dom, precision)
 
 
 def measure_batch(args, probs, lorax, torch, precision, sptr):
@@ -164,7 +180,7 @@ def measure_batch(args, probs, lorax, torch, precision, sptr):
                 F.free()
         state["its"], state["stats"] = np.concatenate(its_all), stats_all
 
-    T, probe, roof = timed_steps(args, lorax, torch, step)
+    T, probe, roof = timed_steps(args, lorax, torch, step, precision)
     res = 0.0
     for p, x in zip(probs, xs):
         X = x.cpu().numpy().T
@@ -248,7 +264,8 @@ def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
         state["its"], state["rr"], state["stats"] = its, rr, F.stats()
         F.free()
 
-    T, probe, roof = timed_steps(args, lorax, torch, step)
+    T, probe, roof = timed_steps(args, lorax, torch, step, precision)
+    roof["traffic"] = TRAFFIC_BYTES.get((args.workload, precision, roof["kernel"]))
     # independent check of the last solution
     A = p.scipy()
     X = x_d.cpu().numpy().T
@@ -278,6 +295,14 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes}), flush=True)
+        return
     from paper_1510_07363_amd import lorax, workloads
 
     torch.cuda.set_device(0)
