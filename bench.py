@@ -59,6 +59,11 @@ def parse():
                     help="systems per lrx_factor_batch call in the batch256 workload")
     ap.add_argument("--cpu-sample-side", type=int, default=128,
                     help="grid side of the oracle's bounded sample (same recipe)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving stream replayed (the recipe has 2,000)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrivals per second")
+    ap.add_argument("--serve-n-max", type=int, default=65536,
+                    help="largest system of a factor request (the recipe has 262,144)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only copy this many bytes device to device and exit (a plain copy of known "
                          "size, the reference for the HBM traffic counters)")
@@ -126,11 +131,19 @@ def roofline(timing, dom, precision="fp64"):
 def timed_steps(args, lorax, torch, step, precision="fp64"):
     """Warm-up, one untimed probe step (finds the dominant kernel class), then
     exactly args.steps timed steps bracketed by stream synchronisation."""
-    for _ in range(args.warmup):
+    t_start = time.perf_counter()
+
+    def progress(what):
+        print(f"[bench] {what} done at {time.perf_counter() - t_start:.1f} s ({precision})", file=sys.stderr,
+              flush=True)
+
+    for i in range(args.warmup):
         step()
+        progress(f"warm-up step {i + 1}")
     lorax.timing_enable(None)
     lorax.timing_read(reset=True)
     step()
+    progress("probe step")
     probe = lorax.timing_read(reset=True)
     dom = max(probe, key=lambda k: probe[k]["total_ms"])
     lorax.timing_enable([dom])
@@ -140,6 +153,7 @@ def timed_steps(args, lorax, torch, step, precision="fp64"):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress(f"{args.steps} timed steps")
     timing = lorax.timing_read(reset=True)
     lorax.timing_enable([])
     return t1 - t0, probe, roofline(timing, dom, precision)
@@ -341,7 +355,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": p.n, "nnz": p.nnz, "depth": p.depth,
-                   "leaf": 64, "epsilon": p.epsilon, "nrhs": nrhs, "gmres": f"FGMRES({RESTART})",
+                   "leaf": p.meta["leaf"], "epsilon": p.epsilon, "nrhs": nrhs, "gmres": f"FGMRES({RESTART})",
                    "tol": TOL, "precision": args.precision, "compress": "svd"},
         "roofline": main_run["roofline"],
         "detail": dict(main_run["detail"], **{
@@ -354,67 +368,73 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def serve_schedule(seed=6, n_req=300, rate=40.0):
-    """Seeded arrival schedule of the serving workload: Poisson arrivals at
-    `rate` requests/s; each request picks one of the systems (weights 1/(i+1))
-    and 1-32 right-hand sides (powers of two, uniform)."""
-    rng = np.random.default_rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate, n_req))
-    return [(float(t[i]), int(rng.choice(len(SERVE_SYSTEMS), p=SERVE_P)),
-             int(2 ** rng.integers(0, 6))) for i in range(n_req)]
-
-
-# serving workload: 2-D variable-coefficient diffusion of 16K-262K unknowns,
-# leaf 64, epsilon 1e-3 or 1e-5
-SERVE_SYSTEMS = [(128, 1e-3), (192, 1e-5), (256, 1e-3), (362, 1e-3), (512, 1e-3), (256, 1e-5)]
-SERVE_P = np.array([1.0 / (i + 1) for i in range(len(SERVE_SYSTEMS))])
-SERVE_P = SERVE_P / SERVE_P.sum()
-
-
 def main_serve(args, torch, lorax, workloads):
+    """Wall-clock replay of the serving request stream (make_serve_stream):
+    factor requests run on a worker thread and stream of their own while solve
+    rounds run on the main thread's stream."""
     from paper_1510_07363_amd.serve import LoraxBackend, Server, SystemSpec
-    specs = []
-    for i, (nx, eps) in enumerate(SERVE_SYSTEMS):
-        rng = np.random.default_rng(100 + i)
-        csr = workloads.diffusion2d(np.exp(workloads.gaussian_field_2d((nx, nx), rng, 8.0)), (nx, nx))
-        depth = workloads.tree_depth(nx * nx, 64)
-        perm, lp = workloads.rcb_tree(workloads.grid_coords((nx, nx)), depth)
-        specs.append(SystemSpec(f"diff2d_{nx}_{eps:g}", *csr, perm, lp, depth, eps))
-    sched = serve_schedule()
-    rhs_rng = np.random.default_rng(7)
-    bs = [rhs_rng.uniform(-1, 1, (specs[k].n, m)) for _, k, m in sched]
-    srv = Server(LoraxBackend(precision=args.precision), 64 << 30, tol=TOL, restart=RESTART)
-    for s in specs:
-        srv.register(s)
-    # warm-up: every system factored once and solved once (untimed)
-    for s in specs:
-        srv.submit(s.key, np.ones(s.n))
+    reqs = workloads.make_serve_stream(count=args.serve_requests, rate=args.serve_rate,
+                                       n_max=args.serve_n_max)
+    specs, bs = {}, []
+    for r in reqs:
+        if r["kind"] == "factor":
+            specs[r["key"]] = SystemSpec(r["key"], *workloads.build_serve_system(r))
+    for r in reqs:
+        if r["kind"] == "solve":
+            rng = np.random.default_rng(r["rhs_seed"])
+            bs.append(rng.uniform(-1, 1, (specs[r["key"]].n, r["nrhs"])))
+        else:
+            bs.append(None)
+    print(f"[serve] {len(reqs)} requests, {len(specs)} systems built", file=sys.stderr, flush=True)
+    srv = Server(LoraxBackend(precision=args.precision), 200 << 30, tol=TOL, restart=RESTART,
+                 factor_backend=LoraxBackend(precision=args.precision), max_factor_batch=8)
+    for sp in specs.values():
+        srv.register(sp)
+    # warm-up (untimed): module load and first launches on a small system
+    wkey = min(specs, key=lambda k: specs[k].n)
+    srv.submit(wkey, np.ones(specs[wkey].n))
     srv.run_until_idle()
-    srv.latencies.clear()
+    srv.evict(wkey)
+    for k in srv.latencies:
+        srv.latencies[k].clear()
     srv.batches.clear()
-    # wall-clock replay of the arrival schedule
+    srv.start()
     futs = []
     t0 = time.perf_counter()
-    i = 0
-    while i < len(sched) or srv.pending:
+    t_print = t0
+    i, last = 0, 0
+    while i < len(reqs) or not srv.idle():
         now = time.perf_counter() - t0
-        while i < len(sched) and sched[i][0] <= now:
-            futs.append(srv.submit(specs[sched[i][1]].key, bs[i], arrival=t0 + sched[i][0]))
+        while i < len(reqs) and reqs[i]["t"] <= now:
+            r = reqs[i]
+            if r["kind"] == "factor":
+                futs.append(("factor", r, srv.submit_factor(r["key"], arrival=t0 + r["t"])))
+            else:
+                futs.append(("solve", r, srv.submit(r["key"], bs[i], arrival=t0 + r["t"])))
             i += 1
-        if srv.pending:
-            srv.step()
-        elif i < len(sched):
-            time.sleep(max(0.0, min(0.002, sched[i][0] - now)))
+        if srv.step() == 0:
+            time.sleep(0.0005)
+        ndone = sum(f.done() for _, _, f in futs)
+        tnow = time.perf_counter()
+        if ndone > last and (tnow - t_print > 5.0 or ndone == len(reqs)):
+            last, t_print = ndone, tnow
+            print(f"[serve] {ndone}/{len(reqs)} requests done at {tnow - t0:.1f} s "
+                  f"({srv.n_factored} factored)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    worst = 0.0
-    for (_, k, m), b, f in zip(sched, bs, futs):
-        x, its, rr = f.result()
-        worst = max(worst, float(np.max(rr)))
-    if worst > TOL:
-        raise RuntimeError(f"served relres {worst:.3e} above {TOL}")
-    lat = srv.latency_stats()
-    n_rhs = sum(m for _, _, m in sched)
+    srv.stop()
+    worst, n_rhs, failed = 0.0, 0, 0
+    for kind, r, f in futs:
+        if f.exception() is not None:
+            failed += 1
+            continue
+        if kind == "solve":
+            x, its, rr = f.result()
+            worst = max(worst, float(np.max(rr)))
+            n_rhs += r["nrhs"]
+    if worst > TOL or failed:
+        raise RuntimeError(f"served relres {worst:.3e}, {failed} failed requests")
+    lat_all = np.array(srv.latencies["solve"] + srv.latencies["factor"])
     line = {
         "metric": "served solves/s at 1e-10 resid",
         "value": n_rhs / T,
@@ -428,12 +448,16 @@ def main_serve(args, torch, lorax, workloads):
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "serve", "systems": [s.key for s in specs], "requests": len(sched),
-                   "rate_req_s": 40.0, "rhs_total": n_rhs, "gmres": f"FGMRES({RESTART})", "tol": TOL,
-                   "precision": args.precision},
-        "detail": {"latency": lat, "requests_per_s": len(sched) / T,
-                   "batches": len(srv.batches), "mean_systems_per_batch": float(np.mean(srv.batches)),
-                   "resident_bytes": srv.resident_bytes(), "factored": srv.n_factored},
+        "config": {"workload": "serve", "requests": len(reqs), "rate_req_s": args.serve_rate,
+                   "n_range": [16384, args.serve_n_max], "factor_requests": len(specs), "rhs_total": n_rhs,
+                   "hbm_budget_gib": 200, "gmres": f"FGMRES({RESTART})", "tol": TOL, "precision": args.precision},
+        "detail": {"latency_solve": srv.latency_stats("solve"), "latency_factor": srv.latency_stats("factor"),
+                   "latency_all_p50_ms": float(np.percentile(lat_all, 50) * 1e3),
+                   "latency_all_p99_ms": float(np.percentile(lat_all, 99) * 1e3),
+                   "requests_per_s": len(reqs) / T, "solve_rounds": len(srv.batches),
+                   "mean_systems_per_round": float(np.mean(srv.batches)) if srv.batches else 0.0,
+                   "factored": srv.n_factored, "evicted": srv.n_evicted,
+                   "resident_bytes_end": srv.resident_bytes()},
     }
     srv.close()
     print(json.dumps(line), flush=True)

@@ -211,6 +211,12 @@ lrx_status lrx_gmres_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, co
                                double* const* x_dev, double tol, int32_t restart, int32_t maxit,
                                int32_t* iters, double* relres);
 
+/* Moves the handle to another HIP stream (NULL: the null stream): solves and
+ * GMRES calls on it are enqueued there from now on, so a server can factor on
+ * one stream while it solves on another.  The caller orders the switch with any
+ * work still running on the old stream.  Errors: LRX_EINVAL (bad handle). */
+lrx_status lrx_set_stream(lrx_handle h, void* stream);
+
 /* Releases every resource of the handle.  NULL is accepted.  A handle that was
  * already freed gives LRX_EINVAL. */
 lrx_status lrx_free(lrx_handle h);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include <climits>
 #include <cmath>
@@ -1965,7 +1966,7 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
                                int max_c, int max_M, bool fp32, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (max_c <= 64) {
-        static bool attr64 = false;
+        static std::atomic<bool> attr64{false};
         if (!attr64) {
             hipError_t e = hipFuncSetAttribute((const void*)k_compress_svd64<double>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
@@ -1986,7 +1987,7 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
     }
     // LDS plan: R and V (2 c^2) plus a chunk of ch rows of B (ch c), within the
     // dynamic LDS budget; below 16 rows per chunk the workspace path is used.
-    static bool attr_set = false;
+    static std::atomic<bool> attr_set{false};
     if (!attr_set) {
         (void)hipFuncSetAttribute((const void*)k_compress_svd<8>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
         (void)hipFuncSetAttribute((const void*)k_compress_svd<16>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
@@ -2006,7 +2007,7 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
     if (n == 0) return hipSuccess;
     const size_t lds = compress_large_lds(max_M, max_c);
     if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_compress_large, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kLdsBudget);
@@ -2024,7 +2025,7 @@ hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj,
     // scratch (2 m + 1 doubles)
     const size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
     if (need > (size_t)kLdsBudget) return hipErrorInvalidValue;
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_node_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kLdsBudget);
@@ -2039,7 +2040,7 @@ hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj,
 hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int kmax, const int32_t* imap,
                              hipStream_t st) {
     if (ntile == 0) return hipSuccess;
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         constexpr size_t most = (size_t)(GLA * GK + GLA * 32 + (GK + 1) * 32) * sizeof(double);
         hipError_t e = hipFuncSetAttribute((const void*)k_gemm_tiles, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2057,7 +2058,7 @@ template <int NK>
 hipError_t launch_sweep_nk(const SwNode* nodes, int n, double* x, int ldx, int k0,
                            hipStream_t st) {
     constexpr size_t lds = (size_t)kSwDescWords * 2 * sizeof(int32_t) + (size_t)kSwData * sizeof(double);
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_sweep<NK>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

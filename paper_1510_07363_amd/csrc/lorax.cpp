@@ -1917,6 +1917,14 @@ lrx_status lrx_gmres(const lrx_csr* A, lrx_handle h, int32_t nrhs, const double*
     });
 }
 
+lrx_status lrx_set_stream(lrx_handle h, void* stream) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        h->stream = (hipStream_t)stream;
+        return LRX_OK;
+    });
+}
+
 lrx_status lrx_free(lrx_handle h) {
     return guarded([&]() -> lrx_status {
         if (!h) return LRX_OK;

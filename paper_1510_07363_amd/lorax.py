@@ -82,7 +82,7 @@ class PlanInfo(C.Structure):
 
 # every symbol declared in include/lorax.h
 EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_factor_batch", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
-           "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev", "lrx_gmres_batch_dev",
+           "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev", "lrx_gmres_batch_dev", "lrx_set_stream",
            "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
            "lrx_last_error", "lrx_version")
 
@@ -110,6 +110,7 @@ def _load():
                                     C.c_int32, C.c_int32, i32p, f64p]),
         "lrx_gmres_batch_dev": (C.c_int, [C.c_int32, P(C.c_void_p), C.c_int32, P(C.c_void_p),
                                           P(C.c_void_p), C.c_double, C.c_int32, C.c_int32, i32p, f64p]),
+        "lrx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
         "lrx_free": (C.c_int, [C.c_void_p]),
         "lrx_stats": (C.c_int, [C.c_void_p, P(Stats)]),
         "lrx_ranks": (C.c_int, [C.c_void_p, i32p, i32p, i32p]),
@@ -323,6 +324,10 @@ class Factor:
         _check(_lib.lrx_compression_tails(self._h, int(idx), _ptr(out, C.c_double), n.value,
                                           C.byref(n)))
         return out[:n.value]
+
+    def set_stream(self, stream):
+        """Later solves and GMRES calls run on this HIP stream (an int address, or None)."""
+        _check(_lib.lrx_set_stream(self._h, C.c_void_p(stream) if stream else None))
 
     def free(self):
         if self._h is not None and self._h.value:

@@ -1,45 +1,51 @@
 """Serving loop over resident factorizations (factor once, solve many times).
 
 A Server keeps factorizations resident in HBM under a byte budget and answers
-solve requests with FGMRES preconditioned by the factorization (the use the
-paper makes of one factorization for many right-hand sides, Sec. 6.2).  Work is
-scheduled in rounds (`step`):
+factor and solve requests; solves use FGMRES preconditioned by the
+factorization (the use the paper makes of one factorization for many
+right-hand sides, Sec. 6.2).
 
-* admission: a solve request whose system is not resident queues a factor job;
-  a factor job runs when the resident factors plus its own storage fit the
-  budget.  The budget is enforced by the library itself (the factor's
-  hbm_budget_bytes is the room left, so an oversized factor fails with
-  LRX_ENOMEM instead of overcommitting); on that failure idle resident factors
-  are evicted, least recently used first, and the job is retried, or it waits
-  while solves on resident factors are still pending, or its requests fail
-  when nothing more can be freed.
-* continuous batching: all ready solve requests, over every resident system,
-  go into one lrx_gmres_batch_dev call per round (several requests on one
+* admission: a factor request, or a solve request whose system is not
+  resident, queues a factor job.  A factor job runs when the resident factors
+  plus its own storage fit the budget.  The budget is enforced by the library
+  itself (the factor's hbm_budget_bytes is the room left, so an oversized
+  factor fails with LRX_ENOMEM instead of overcommitting); on that failure idle
+  resident factors are evicted, least recently used first, and the job is
+  retried, or it waits while solves on resident factors are in flight, or its
+  requests fail when nothing more can be freed.
+* continuous batching: each round puts all ready solve requests, over every
+  resident system, into one lrx_gmres_batch_dev call (several requests on one
   system are concatenated as extra right-hand sides; every system's block is
   padded with zero columns to the batch's width, rounded up to a power of two).
-  A request's result does not depend on which other systems share its batch;
-  the width of the batch changes only the summation order of its dot products.
-* completion: each request's future receives (x, iterations, relative
-  residuals); its latency (completion - arrival) is recorded.
+  Requests that arrive during a round join the next one.  A request's result
+  does not depend on which other systems share its batch; the width of the
+  batch changes only the summation order of its dot products.
+* overlap: with `start()`, factor jobs run on a worker thread with their own
+  backend (its own stream), so factorizations and solve rounds proceed on the
+  device at the same time; without it, `step()` runs factor jobs inline.
+* completion: each request's future receives its result, (x, iterations,
+  relative residuals) for solves and the factor's byte count for factors; its
+  latency (completion - arrival) is recorded by kind.
 
 The arithmetic runs in the library (the backend); this module only schedules,
-marshals arrays and measures.  PyTorch provides device memory and the stream.
+marshals arrays and measures.  PyTorch provides device memory and streams.
 """
 from __future__ import annotations
 
 import collections
 import concurrent.futures as cf
+import threading
 import time
 from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["SystemSpec", "SolveRequest", "Server", "LoraxBackend"]
+__all__ = ["SystemSpec", "Server", "LoraxBackend", "OutOfBudget"]
 
 
 @dataclass
 class SystemSpec:
-    """A linear system the server may be asked to solve: CSR matrix and cluster tree."""
+    """A linear system the server may be asked to factor and solve: CSR matrix and cluster tree."""
     key: str
     row_ptr: np.ndarray
     col_idx: np.ndarray
@@ -55,10 +61,11 @@ class SystemSpec:
 
 
 @dataclass
-class SolveRequest:
+class _Request:
+    kind: str                           # "solve" or "factor"
     key: str
-    b: np.ndarray                       # (n,) or (n, k)
-    arrival: float = field(default_factory=time.perf_counter)
+    b: np.ndarray | None
+    arrival: float
     future: cf.Future = field(default_factory=cf.Future)
 
 
@@ -68,23 +75,39 @@ class OutOfBudget(Exception):
 
 class LoraxBackend:
     """The library on the current GPU: lrx_factor for factor jobs and
-    lrx_gmres_batch_dev for each batch of solves, on one stream."""
+    lrx_gmres_batch_dev for each batch of solves, on one stream (None: a new
+    stream of default priority)."""
 
     def __init__(self, precision="mixed", stream=None):
         import torch
         from . import lorax
         self.torch, self.lx = torch, lorax
         self.precision = precision
-        self.stream = stream
-        self.device = "cuda:%d" % torch.cuda.current_device()
+        self.device_index = torch.cuda.current_device()
+        self.device = "cuda:%d" % self.device_index
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
 
     def factor(self, spec: SystemSpec, room_bytes: int):
-        lx = self.lx
-        sptr = self.stream.cuda_stream if self.stream is not None else None
+        lx, torch = self.lx, self.torch
+        torch.cuda.set_device(self.device_index)          # worker threads start on device 0
         try:
             return lx.Factor(spec.row_ptr, spec.col_idx, spec.val, spec.perm, spec.leaf_ptr, spec.depth,
-                             spec.epsilon, stream=sptr, hbm_budget_bytes=max(int(room_bytes), 1),
-                             precision=self.precision)
+                             spec.epsilon, stream=self.stream.cuda_stream,
+                             hbm_budget_bytes=max(int(room_bytes), 1), precision=self.precision)
+        except lx.LoraxError as e:
+            if e.status == lx.LRX_ENOMEM:
+                raise OutOfBudget(str(e)) from None
+            raise
+
+    def factor_batch(self, specs, room_bytes: int):
+        """Several systems of one epsilon in one lrx_factor_batch call; each
+        handle's storage is capped at room_bytes (LRX_ENOMEM: OutOfBudget)."""
+        lx, torch = self.lx, self.torch
+        torch.cuda.set_device(self.device_index)
+        try:
+            return lx.factor_batch([(sp.row_ptr, sp.col_idx, sp.val, sp.perm, sp.leaf_ptr, sp.depth)
+                                    for sp in specs], specs[0].epsilon, stream=self.stream.cuda_stream,
+                                   hbm_budget_bytes=max(int(room_bytes), 1), precision=self.precision)
         except lx.LoraxError as e:
             if e.status == lx.LRX_ENOMEM:
                 raise OutOfBudget(str(e)) from None
@@ -93,6 +116,10 @@ class LoraxBackend:
     def resident_bytes(self, handle) -> int:
         return int(handle.stats()["factor_bytes"])
 
+    def adopt(self, handle) -> None:
+        """A handle factored elsewhere is solved on this backend's stream."""
+        handle.set_stream(self.stream.cuda_stream)
+
     def free(self, handle) -> None:
         handle.free()
 
@@ -100,11 +127,17 @@ class LoraxBackend:
         """items: list of (handle, B) with B of shape (n, nrhs); returns a list of
         (X, iters, relres) in the same order."""
         torch, lx = self.torch, self.lx
-        bs = [torch.from_numpy(np.ascontiguousarray(B.T)).to(self.device) for _, B in items]
-        xs = [torch.zeros_like(b) for b in bs]
-        its, rr, st = lx.gmres_batch_dev([h for h, _ in items], nrhs, [b.data_ptr() for b in bs],
-                                         [x.data_ptr() for x in xs], tol=tol, restart=restart, maxit=maxit)
-        return [(x.cpu().numpy().T, its[i], rr[i]) for i, x in enumerate(xs)]
+        torch.cuda.set_device(self.device_index)
+        with torch.cuda.stream(self.stream):
+            bs = [torch.from_numpy(np.ascontiguousarray(B.T)).to(self.device) for _, B in items]
+            xs = [torch.zeros_like(b) for b in bs]
+            self.stream.synchronize()
+            # the library runs the batch on the stream of the first handle; the
+            # inputs above are complete before it starts
+            its, rr, st = lx.gmres_batch_dev([h for h, _ in items], nrhs, [b.data_ptr() for b in bs],
+                                             [x.data_ptr() for x in xs], tol=tol, restart=restart, maxit=maxit)
+            out = [(x.cpu().numpy().T, its[i], rr[i]) for i, x in enumerate(xs)]
+        return out
 
 
 class _Resident:
@@ -116,40 +149,144 @@ class _Resident:
 
 class Server:
     def __init__(self, backend, hbm_budget_bytes, tol=1e-10, restart=30, maxit=500, max_batch_systems=256,
-                 max_width=256):
+                 max_width=256, factor_backend=None, max_factor_batch=1):
         if hbm_budget_bytes <= 0:
             raise ValueError("hbm_budget_bytes must be positive")
         self.backend = backend
+        self.factor_backend = factor_backend if factor_backend is not None else backend
         self.budget = int(hbm_budget_bytes)
         self.tol, self.restart, self.maxit = tol, restart, maxit
         self.max_batch_systems = max_batch_systems
         self.max_width = max_width
+        self.max_factor_batch = max_factor_batch
         self.specs: dict[str, SystemSpec] = {}
         self.resident: "collections.OrderedDict[str, _Resident]" = collections.OrderedDict()
-        self.pending: "collections.deque[SolveRequest]" = collections.deque()
-        self.latencies: list[float] = []
+        self.pending: "collections.deque[_Request]" = collections.deque()     # solves
+        self.factor_waiters: dict[str, list] = {}                            # factor requests by key
+        self.jobs: "collections.deque[str]" = collections.deque()            # factor jobs to run
+        self.factoring: set[str] = set()                                     # factor jobs running
+        self.busy: set[str] = set()                                          # systems in a solve round
+        self.latencies: dict[str, list] = {"solve": [], "factor": []}
         self.n_solved = 0
         self.n_factored = 0
         self.n_evicted = 0
-        self.batches: list[int] = []              # systems per solve batch
+        self.batches: list[int] = []              # systems per solve round
+        self._lock = threading.Lock()
+        self._wake = threading.Condition(self._lock)
+        self._worker = None
+        self._stop = False
 
     # ------------------------------------------------------------ interface
     def register(self, spec: SystemSpec) -> None:
-        self.specs[spec.key] = spec
+        with self._lock:
+            self.specs[spec.key] = spec
 
     def submit(self, key: str, b, arrival: float | None = None) -> cf.Future:
-        if key not in self.specs:
-            raise KeyError(f"unknown system {key!r}")
+        """Solve request: future of (x, iterations, relative residuals)."""
         b = np.asarray(b, dtype=np.float64)
-        n = self.specs[key].n
-        if b.shape[0] != n or b.ndim not in (1, 2):
-            raise ValueError(f"b must have {n} rows")
-        req = SolveRequest(key, b) if arrival is None else SolveRequest(key, b, arrival)
-        self.pending.append(req)
+        with self._lock:
+            if key not in self.specs:
+                raise KeyError(f"unknown system {key!r}")
+            n = self.specs[key].n
+            if b.shape[0] != n or b.ndim not in (1, 2):
+                raise ValueError(f"b must have {n} rows")
+            req = _Request("solve", key, b, time.perf_counter() if arrival is None else arrival)
+            self.pending.append(req)
+            self._need(key)
+            self._wake.notify_all()
+        return req.future
+
+    def submit_factor(self, key: str, arrival: float | None = None) -> cf.Future:
+        """Factor request: future of the resident factor's byte count."""
+        with self._lock:
+            if key not in self.specs:
+                raise KeyError(f"unknown system {key!r}")
+            req = _Request("factor", key, None, time.perf_counter() if arrival is None else arrival)
+            if key in self.resident:
+                self._complete_factor(req, self.resident[key].bytes)
+            else:
+                self.factor_waiters.setdefault(key, []).append(req)
+                self._need(key)
+                self._wake.notify_all()
         return req.future
 
     def evict(self, key: str) -> bool:
         """Frees the factorization of key (it is factored again on demand)."""
+        with self._lock:
+            return self._evict(key)
+
+    def resident_bytes(self) -> int:
+        with self._lock:
+            return self._resident_bytes()
+
+    def start(self) -> None:
+        """Runs factor jobs on a worker thread (overlapping the solve rounds)."""
+        if self._worker is None:
+            self._stop = False
+            self._worker = threading.Thread(target=self._factor_loop, daemon=True)
+            self._worker.start()
+
+    def stop(self) -> None:
+        if self._worker is not None:
+            with self._lock:
+                self._stop = True
+                self._wake.notify_all()
+            self._worker.join()
+            self._worker = None
+
+    def step(self) -> int:
+        """One scheduling round: factor jobs (inline unless the worker runs), then
+        one batch of ready solves.  Returns the number of requests completed."""
+        done = 0
+        if self._worker is None:
+            with self._lock:
+                njobs = len(self.jobs)
+            for _ in range(njobs):                      # a job that must wait goes back to the queue
+                with self._lock:
+                    if not self.jobs:
+                        break
+                    key = self.jobs.popleft()
+                    self.factoring.add(key)
+                done += self._run_factor_job(key, inline=True)
+        return done + self._solve_ready()
+
+    def idle(self) -> bool:
+        with self._lock:
+            return not self.pending and not self.jobs and not self.factoring and not self.factor_waiters
+
+    def run_until_idle(self, max_rounds=10_000_000) -> None:
+        for _ in range(max_rounds):
+            if self.idle():
+                return
+            if self.step() == 0 and self._worker is not None:
+                with self._lock:
+                    if not self._ready_keys():
+                        self._wake.wait(timeout=0.005)
+        raise RuntimeError("server did not drain")
+
+    def latency_stats(self, kind="solve") -> dict:
+        with self._lock:
+            lat = np.array(self.latencies[kind])
+        if lat.size == 0:
+            return {"count": 0}
+        return {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
+
+    def close(self) -> None:
+        self.stop()
+        with self._lock:
+            for key in list(self.resident):
+                self._evict(key)
+
+    # ------------------------------------------------------------ internals (lock held)
+    def _resident_bytes(self) -> int:
+        return sum(r.bytes for r in self.resident.values())
+
+    def _need(self, key) -> None:
+        if key not in self.resident and key not in self.factoring and key not in self.jobs:
+            self.jobs.append(key)
+
+    def _evict(self, key) -> bool:
         r = self.resident.pop(key, None)
         if r is None:
             return False
@@ -157,64 +294,9 @@ class Server:
         self.n_evicted += 1
         return True
 
-    def resident_bytes(self) -> int:
-        return sum(r.bytes for r in self.resident.values())
-
-    def step(self) -> int:
-        """One scheduling round; returns the number of requests completed."""
-        if not self.pending:
-            return 0
-        self._admit()
-        return self._solve_ready()
-
-    def run_until_idle(self, max_rounds=1_000_000) -> None:
-        for _ in range(max_rounds):
-            if not self.pending:
-                return
-            self.step()
-        raise RuntimeError("server did not drain")
-
-    def latency_stats(self) -> dict:
-        if not self.latencies:
-            return {"count": 0}
-        lat = np.array(self.latencies)
-        return {"count": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
-
-    def close(self) -> None:
-        for key in list(self.resident):
-            self.evict(key)
-
-    # ------------------------------------------------------------ internals
-    def _admit(self) -> None:
-        needed = []
-        for req in self.pending:
-            if req.key not in self.resident and req.key not in needed:
-                needed.append(req.key)
-        busy = {req.key for req in self.pending if req.key in self.resident}
-        for key in needed:
-            spec = self.specs[key]
-            while True:
-                room = self.budget - self.resident_bytes()
-                try:
-                    h = self.backend.factor(spec, room) if room > 0 else None
-                    if h is None:
-                        raise OutOfBudget("no room left")
-                except OutOfBudget:
-                    idle = [k for k in self.resident if k not in busy]
-                    if idle:
-                        self.evict(idle[0])                 # least recently used first
-                        continue
-                    if busy:
-                        break                               # wait for solves in flight to finish
-                    self._fail_key(key, MemoryError(f"system {key} does not fit in the HBM budget"))
-                    break
-                except Exception as e:                      # a library error: fail its requests
-                    self._fail_key(key, e)
-                    break
-                self.resident[key] = _Resident(h, self.backend.resident_bytes(h), time.perf_counter())
-                self.n_factored += 1
-                break
+    def _complete_factor(self, req, nbytes) -> None:
+        self.latencies["factor"].append(time.perf_counter() - req.arrival)
+        req.future.set_result(nbytes)
 
     def _fail_key(self, key, exc) -> None:
         keep = collections.deque()
@@ -224,35 +306,149 @@ class Server:
             else:
                 keep.append(req)
         self.pending = keep
+        for req in self.factor_waiters.pop(key, []):
+            req.future.set_exception(exc)
 
+    def _ready_keys(self):
+        return [r.key for r in self.pending if r.key in self.resident and r.key not in self.busy]
+
+    # ------------------------------------------------------------ factor jobs
+    def _factor_loop(self) -> None:
+        while True:
+            with self._lock:
+                while not self.jobs and not self._stop:
+                    self._wake.wait()
+                if self._stop:
+                    return
+                key = self.jobs.popleft()
+                # queued jobs of the same epsilon join one batched factorization
+                group = [key]
+                if self.max_factor_batch > 1 and hasattr(self.factor_backend, "factor_batch"):
+                    eps = self.specs[key].epsilon
+                    for k in list(self.jobs):
+                        if len(group) >= self.max_factor_batch:
+                            break
+                        if self.specs[k].epsilon == eps:
+                            self.jobs.remove(k)
+                            group.append(k)
+                self.factoring |= set(group)
+            if len(group) == 1 or not self._run_factor_batch(group):
+                for k in group:
+                    self._run_factor_job(k, inline=False)
+
+    def _run_factor_batch(self, group) -> bool:
+        """One lrx_factor_batch over group; False (nothing admitted) when it does
+        not fit, the jobs then run one by one."""
+        with self._lock:
+            room = self.budget - self._resident_bytes()
+            specs = [self.specs[k] for k in group]
+        if room <= 0:
+            return False
+        try:
+            hs = self.factor_backend.factor_batch(specs, room)
+        except OutOfBudget:
+            return False
+        for h in hs:
+            if self.factor_backend is not self.backend and hasattr(self.backend, "adopt"):
+                self.backend.adopt(h)
+        with self._lock:
+            for k, h in zip(group, hs):
+                nbytes = self.factor_backend.resident_bytes(h)
+                self.resident[k] = _Resident(h, nbytes, time.perf_counter())
+                self.n_factored += 1
+                for req in self.factor_waiters.pop(k, []):
+                    self._complete_factor(req, nbytes)
+            # each handle was capped at the room left; the batch as a whole may
+            # exceed it: idle systems outside the batch are evicted to compensate
+            wanted = {r.key for r in self.pending} | self.busy | set(group)
+            while self._resident_bytes() > self.budget:
+                idle = [k for k in self.resident if k not in wanted]
+                if not idle:
+                    break
+                self._evict(idle[0])
+            self.factoring -= set(group)
+            self._wake.notify_all()
+        return True
+
+    def _run_factor_job(self, key, inline) -> int:
+        """Factors key under the budget (evicting idle systems as needed).
+        Returns the number of factor requests completed."""
+        spec = self.specs[key]
+        while True:
+            with self._lock:
+                room = self.budget - self._resident_bytes()
+            try:
+                if room <= 0:
+                    raise OutOfBudget("no room left")
+                h = self.factor_backend.factor(spec, room)
+            except OutOfBudget:
+                with self._lock:
+                    # systems with pending or running solves are kept
+                    wanted = {r.key for r in self.pending} | self.busy
+                    idle = [k for k in self.resident if k not in wanted]
+                    if idle:
+                        self._evict(idle[0])                # least recently used first
+                        continue
+                    if wanted & set(self.resident):
+                        if inline:                          # let this round's solves run first
+                            self.jobs.appendleft(key)
+                            self.factoring.discard(key)
+                            return 0
+                        self._wake.wait(timeout=0.005)
+                        continue
+                    self._fail_key(key, MemoryError(f"system {key} does not fit in the HBM budget"))
+                    self.factoring.discard(key)
+                    return 0
+            except Exception as e:                          # a library error: fail its requests
+                with self._lock:
+                    self._fail_key(key, e)
+                    self.factoring.discard(key)
+                return 0
+            if self.factor_backend is not self.backend and hasattr(self.backend, "adopt"):
+                self.backend.adopt(h)                       # its solves run on the solve stream
+            with self._lock:
+                nbytes = self.factor_backend.resident_bytes(h)
+                self.resident[key] = _Resident(h, nbytes, time.perf_counter())
+                self.n_factored += 1
+                waiters = self.factor_waiters.pop(key, [])
+                for req in waiters:
+                    self._complete_factor(req, nbytes)
+                self.factoring.discard(key)
+                self._wake.notify_all()
+                return len(waiters)
+
+    # ------------------------------------------------------------ solve rounds
     def _solve_ready(self) -> int:
-        # requests of resident systems, grouped by system, up to the batch limits
-        groups: "collections.OrderedDict[str, list[SolveRequest]]" = collections.OrderedDict()
-        width: dict[str, int] = {}
-        rest = collections.deque()
-        for req in self.pending:
-            k = 1 if req.b.ndim == 1 else req.b.shape[1]
-            if req.key not in self.resident:
-                rest.append(req)
-                continue
-            if req.key not in groups and len(groups) >= self.max_batch_systems:
-                rest.append(req)
-                continue
-            if width.get(req.key, 0) + k > self.max_width:
-                rest.append(req)
-                continue
-            groups.setdefault(req.key, []).append(req)
-            width[req.key] = width.get(req.key, 0) + k
-        self.pending = rest
-        if not groups:
-            return 0
+        with self._lock:
+            groups: "collections.OrderedDict[str, list[_Request]]" = collections.OrderedDict()
+            width: dict[str, int] = {}
+            rest = collections.deque()
+            for req in self.pending:
+                k = 1 if req.b.ndim == 1 else req.b.shape[1]
+                if req.key not in self.resident or req.key in self.busy:
+                    rest.append(req)
+                    continue
+                if req.key not in groups and len(groups) >= self.max_batch_systems:
+                    rest.append(req)
+                    continue
+                if width.get(req.key, 0) + k > self.max_width:
+                    rest.append(req)
+                    continue
+                groups.setdefault(req.key, []).append(req)
+                width[req.key] = width.get(req.key, 0) + k
+            self.pending = rest
+            if not groups:
+                return 0
+            self.busy |= set(groups)
+            handles = {key: self.resident[key].handle for key in groups}
+            ns = {key: self.specs[key].n for key in groups}
         w = max(width.values())
         nrhs = 1
         while nrhs < w:
             nrhs *= 2
         items, spans = [], []
         for key, reqs in groups.items():
-            n = self.specs[key].n
+            n = ns[key]
             B = np.zeros((n, nrhs))
             c0, sp = 0, []
             for req in reqs:
@@ -260,27 +456,34 @@ class Server:
                 B[:, c0:c0 + k] = req.b.reshape(n, k)
                 sp.append((req, c0, k))
                 c0 += k
-            items.append((self.resident[key].handle, B))
+            items.append((handles[key], B))
             spans.append(sp)
         try:
             out = self.backend.solve_batch(items, nrhs, self.tol, self.restart, self.maxit)
         except Exception as e:
-            for sp in spans:
-                for req, _, _ in sp:
-                    req.future.set_exception(e)
+            with self._lock:
+                self.busy -= set(groups)
+                for sp in spans:
+                    for req, _, _ in sp:
+                        req.future.set_exception(e)
+                self._wake.notify_all()
             return 0
         now = time.perf_counter()
         done = 0
-        for key, sp, (X, its, rr) in zip(groups, spans, out):
-            self.resident[key].last_use = now
-            self.resident.move_to_end(key)
-            for req, c0, k in sp:
-                x = X[:, c0:c0 + k]
-                res = (x[:, 0] if req.b.ndim == 1 else x.copy(), np.asarray(its[c0:c0 + k]),
-                       np.asarray(rr[c0:c0 + k]))
-                self.latencies.append(now - req.arrival)
-                req.future.set_result(res)
-                done += 1
-        self.n_solved += done
-        self.batches.append(len(groups))
+        with self._lock:
+            self.busy -= set(groups)
+            for key, sp, (X, its, rr) in zip(groups, spans, out):
+                if key in self.resident:
+                    self.resident[key].last_use = now
+                    self.resident.move_to_end(key)
+                for req, c0, k in sp:
+                    x = X[:, c0:c0 + k]
+                    res = (x[:, 0] if req.b.ndim == 1 else x.copy(), np.asarray(its[c0:c0 + k]),
+                           np.asarray(rr[c0:c0 + k]))
+                    self.latencies["solve"].append(now - req.arrival)
+                    req.future.set_result(res)
+                    done += 1
+            self.n_solved += done
+            self.batches.append(len(groups))
+            self._wake.notify_all()
         return done

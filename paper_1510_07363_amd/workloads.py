@@ -24,7 +24,7 @@ import scipy.sparse as sp
 __all__ = [
     "Problem", "poisson2d", "diffusion2d", "diffusion3d", "convdiff2d", "convdiff3d",
     "gaussian_field_2d", "rcb_tree", "tree_depth", "uniform_rhs", "grid_coords",
-    "make_config", "CONFIGS", "make_batch",
+    "make_config", "CONFIGS", "make_batch", "make_serve_stream", "build_serve_system",
 ]
 
 
@@ -251,6 +251,7 @@ def _finish(name, csr, coords, leaf, eps, nrhs, rng, meta):
     depth = tree_depth(n, leaf)
     perm, leaf_ptr = rcb_tree(coords, depth)
     b = uniform_rhs(n, nrhs, rng)
+    meta = dict(meta, leaf=leaf)
     return Problem(name, n, row_ptr, col_idx, val, coords, perm, leaf_ptr, depth, eps, b, meta)
 
 
@@ -293,34 +294,81 @@ def make_config(which, seed=None, size=None):
 CONFIGS = ("poisson2d_32", "varcoef2d_256", "convdiff3d_64")
 
 
-def make_batch(count=256, seed=4, n_min=4096, n_max=110592, leaf=64, eps=1e-4, nrhs=4):
+def make_batch(count=256, seed=4, leaf=64, eps=1e-4, nrhs=4):
     """Batch of independent systems (the batched-factorization workload).
 
-    System i is 2-D (i even) or 3-D (i odd) variable-coefficient diffusion; its
-    target size is log-uniform in [n_min, n_max] (mean about 32K, so 256 systems
-    hold about 8-9 million unknowns), rounded to a square s x s (s >= 64) or a
-    cube s^3 (16 <= s <= 48).  2-D coefficients: kappa = exp(g), g the Gaussian
-    field of correlation length 8; 3-D: kappa = exp(N(0,1)) per cell.  Leaf
-    clusters of at most `leaf` points, epsilon 1e-4, nrhs uniform right-hand
-    sides.  Returns a list of Problem."""
-    rng = np.random.default_rng(seed)
+    System i draws from its own child stream (seed, i): 2-D or 3-D with
+    probability 1/2, grid side uniform in {64..256} (2-D) or {16..48} (3-D),
+    diffusion with kappa = exp(N(0,1)) i.i.d. per cell (harmonic face means),
+    leaf clusters of at most `leaf` points, epsilon 1e-4, nrhs uniform
+    right-hand sides; about 9.0e6 unknowns in all for 256 systems.  Returns a
+    list of Problem."""
     out = []
     for i in range(count):
-        target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
         r = np.random.default_rng([seed, i])
-        if i % 2 == 0:
-            s = int(min(max(round(math.sqrt(target)), 64), int(math.sqrt(n_max))))
-            kappa = np.exp(gaussian_field_2d((s, s), r, 8.0))
-            csr = diffusion2d(kappa, (s, s))
-            co = grid_coords((s, s))
-            grid = (s, s)
+        if r.random() < 0.5:
+            s_ = int(r.integers(64, 257))
+            csr = diffusion2d(np.exp(r.standard_normal(s_ * s_)), (s_, s_))
+            co, grid = grid_coords((s_, s_)), (s_, s_)
         else:
-            s = int(min(max(round(target ** (1.0 / 3.0)), 16), 48))
-            kappa = np.exp(r.standard_normal(s ** 3))
-            csr = diffusion3d(kappa, (s, s, s))
-            co = grid_coords((s, s, s))
-            grid = (s, s, s)
+            s_ = int(r.integers(16, 49))
+            csr = diffusion3d(np.exp(r.standard_normal(s_ ** 3)), (s_, s_, s_))
+            co, grid = grid_coords((s_, s_, s_)), (s_, s_, s_)
         out.append(_finish(f"batch{count}[{i}]", csr, co, leaf, eps, nrhs, r,
                            {"grid": grid, "seed": seed, "index": i}))
     return out
 
+
+def make_serve_stream(count=2000, rate=200.0, seed=5, n_min=16384, n_max=262144):
+    """Request stream of the serving workload (seeded).
+
+    Poisson arrivals at `rate` per second.  20% factor requests (the first one
+    always): type uniform over {2-D diffusion, 3-D diffusion, 2-D
+    convection-diffusion w = (1, 0.5) 10, 3-D convection-diffusion
+    w = (1, 0.5, 0.25) 10}, n uniform in [n_min, n_max] (grid side round(sqrt n)
+    or round(cbrt n)), diffusion coefficients exp(N(0,1)) i.i.d., epsilon 1e-3 or
+    1e-5, leaf 64 (2-D) or 128 (3-D).  80% solve requests: 1-32 right-hand sides
+    uniform in [-1, 1] against a handle chosen uniformly among the factor
+    requests issued so far.  Returns a list of dicts with keys t (arrival, s),
+    kind ("factor" or "solve"), key, and for factors the matrix recipe
+    (kind2, side, epsilon, leaf, seed) or for solves nrhs and rhs_seed; the
+    matrices are built on demand by `build_serve_system`."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    reqs, factors = [], []
+    types = ("diff2d", "diff3d", "convdiff2d", "convdiff3d")
+    for i in range(count):
+        if i == 0 or rng.random() < 0.2:
+            typ = types[int(rng.integers(0, 4))]
+            n = int(rng.integers(n_min, n_max + 1))
+            side = int(round(n ** 0.5)) if typ.endswith("2d") else int(round(n ** (1.0 / 3.0)))
+            eps = 1e-3 if rng.random() < 0.5 else 1e-5
+            key = f"f{len(factors)}_{typ}_{side}_{eps:g}"
+            factors.append(key)
+            reqs.append({"t": float(t[i]), "kind": "factor", "key": key, "type": typ, "side": side,
+                         "epsilon": eps, "leaf": 64 if typ.endswith("2d") else 128,
+                         "seed": int(rng.integers(0, 2 ** 31))})
+        else:
+            reqs.append({"t": float(t[i]), "kind": "solve", "key": factors[int(rng.integers(0, len(factors)))],
+                         "nrhs": int(rng.integers(1, 33)), "rhs_seed": int(rng.integers(0, 2 ** 31))})
+    return reqs
+
+
+def build_serve_system(req):
+    """CSR matrix, cluster tree and epsilon of a factor request of
+    make_serve_stream: returns (row_ptr, col_idx, val, perm, leaf_ptr, depth, eps)."""
+    r = np.random.default_rng(req["seed"])
+    s_ = req["side"]
+    typ = req["type"]
+    if typ == "diff2d":
+        csr, co = diffusion2d(np.exp(r.standard_normal(s_ * s_)), (s_, s_)), grid_coords((s_, s_))
+    elif typ == "diff3d":
+        csr, co = diffusion3d(np.exp(r.standard_normal(s_ ** 3)), (s_, s_, s_)), grid_coords((s_, s_, s_))
+    elif typ == "convdiff2d":
+        csr, co = convdiff2d(s_), grid_coords((s_, s_))
+    else:
+        csr, co = convdiff3d(s_), grid_coords((s_, s_, s_))
+    n = len(csr[0]) - 1
+    depth = tree_depth(n, req["leaf"])
+    perm, lp = rcb_tree(co, depth)
+    return (*csr, perm, lp, depth, req["epsilon"])

@@ -38,7 +38,7 @@ class OracleBackend:
     PER_UNKNOWN = 800
 
     def __init__(self):
-        self.factored, self.freed, self.batches = [], [], []
+        self.factored, self.freed, self.batches, self.factor_batches = [], [], [], []
 
     def factor(self, spec, room):
         if spec.n * self.PER_UNKNOWN > room:
@@ -48,6 +48,10 @@ class OracleBackend:
         A = sp.csr_matrix((spec.val, spec.col_idx, spec.row_ptr), shape=(spec.n, spec.n))
         self.factored.append(spec.key)
         return {"key": spec.key, "F": F, "A": A, "n": spec.n}
+
+    def factor_batch(self, specs, room):
+        self.factor_batches.append([sp.key for sp in specs])
+        return [self.factor(sp, room) for sp in specs]
 
     def resident_bytes(self, h):
         return h["n"] * self.PER_UNKNOWN
@@ -165,6 +169,43 @@ def test_batch_limits_split_rounds():
         assert (f.result()[2] <= 1e-10).all()
 
 
+def test_factor_requests_and_worker_thread():
+    """Factor requests complete with the factor's bytes; with the factor worker
+    running (start), the same requests give the same answers as inline."""
+    rng = np.random.default_rng(6)
+    srv, be, specs = _server(10_000)
+    srv.start()
+    ff = [srv.submit_factor(k) for k in ("a", "b")]
+    reqs = [(k, rng.uniform(-1, 1, (specs[k].n, 2))) for k in ("a", "b", "c", "a")]
+    futs = [srv.submit(k, b) for k, b in reqs]
+    srv.run_until_idle()
+    srv.stop()
+    assert [f.result() for f in ff] == [specs["a"].n * OracleBackend.PER_UNKNOWN,
+                                       specs["b"].n * OracleBackend.PER_UNKNOWN]
+    assert srv.latency_stats("factor")["count"] == 2
+    srv2, _, _ = _server(10_000)
+    f2 = [srv2.submit(k, b) for k, b in reqs]
+    srv2.run_until_idle()
+    for f, g in zip(futs, f2):
+        assert np.array_equal(f.result()[0], g.result()[0])
+    # a factor request for a resident system completes at once
+    f3 = srv.submit_factor("a")
+    assert f3.done() and f3.result() == specs["a"].n * OracleBackend.PER_UNKNOWN
+
+
+def test_queued_factor_jobs_are_batched_by_epsilon():
+    rng = np.random.default_rng(8)
+    srv, be, specs = _server(10_000, max_factor_batch=4)
+    # queue all jobs before the worker starts: "a" and "b" share epsilon 1e-3, "c" has 1e-2
+    futs = [srv.submit(k, rng.uniform(-1, 1, specs[k].n)) for k in ("a", "c", "b")]
+    srv.start()
+    srv.run_until_idle()
+    srv.stop()
+    assert be.factor_batches == [["a", "b"]] and sorted(be.factored) == ["a", "b", "c"]
+    for f in futs:
+        assert (f.result()[2] <= 1e-10).all()
+
+
 def test_submit_validation():
     srv, be, specs = _server(10_000)
     with pytest.raises(KeyError):
@@ -210,3 +251,37 @@ def test_serve_on_gpu_alone_vs_mix():
     assert st["count"] == 8
     srv.close()
     assert srv.resident_bytes() == 0
+
+
+@pytest.mark.gpu
+def test_serve_on_gpu_concurrent_factoring():
+    """Factor jobs on a worker thread and stream of their own while solve rounds
+    run on another stream; every answer reaches the tolerance."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1510_07363_amd.serve import LoraxBackend
+    rng = np.random.default_rng(7)
+    specs = [_spec("p", "diff2d", 64, 16, 1e-3, 21), _spec("q", "diff3d", 14, 32, 1e-3, 22),
+             _spec("r", "convdiff", 48, 16, 1e-3, 23), _spec("s", "diff2d", 40, 16, 1e-5, 24)]
+    srv = Server(LoraxBackend(precision="mixed"), 8 << 30, tol=1e-10,
+                 factor_backend=LoraxBackend(precision="mixed"))
+    for s_ in specs:
+        srv.register(s_)
+    srv.start()
+    ff = [srv.submit_factor(s_.key) for s_ in specs]
+    reqs = [(s_.key, rng.uniform(-1, 1, (s_.n, k))) for s_, k in zip(specs * 2, (1, 4, 2, 3, 5, 1, 2, 8))]
+    futs = [srv.submit(k, b) for k, b in reqs]
+    srv.run_until_idle()
+    srv.stop()
+    assert all(f.result() > 0 for f in ff)
+    bykey = {s_.key: s_ for s_ in specs}
+    for (key, b), f in zip(reqs, futs):
+        x, its, rr = f.result()
+        s_ = bykey[key]
+        A = sp.csr_matrix((s_.val, s_.col_idx, s_.row_ptr), shape=(s_.n, s_.n))
+        assert (np.linalg.norm(A @ x - b, axis=0) / np.linalg.norm(b, axis=0) <= 1e-10).all()
+    assert srv.latency_stats("solve")["count"] == len(reqs)
+    srv.close()
+
