@@ -80,7 +80,8 @@ struct DGemm {
     int32_t M, N, K;
     int32_t lda, ldb, ldc;
     int32_t amap, bmap, crmap, ccmap;
-    int32_t sub, pad_;
+    int32_t sub;
+    int32_t tr;          // 1: element (i, j) of the product goes to C[ccol(j) + crow(i) ldc]
 };
 
 struct DTile {           // one 32 x 32 block of C of product g

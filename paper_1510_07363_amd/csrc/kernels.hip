@@ -1298,6 +1298,140 @@ __device__ bool gj_inverse_global(double* A, int m, double* scol, int* sperm, do
     return true;
 }
 
+// Blocked Gauss-Jordan inverse with partial pivoting (128 < m <= 1024): panels
+// of GJB columns are reduced in LDS (pivot search over the panel column, row
+// swap inside the panel, the Gauss-Jordan step on the panel columns only);
+// then the panel's row swaps are applied to the other columns and they receive
+// the panel's combined transformation as one rank-GJB update.  Correctness:
+// each step is the elementary matrix E_k (identity but for column k) after the
+// swap P_k; a swap by a later step of the panel only permutes rows of the
+// earlier E columns, so the panel's product is M = I + (M[:, J] - I[:, J]) with
+// M[:, J] the panel columns as stored, and every other column c becomes
+// M (swapped c).  Each element of A is read and written once per panel instead
+// of once per column.  LDS: gj_blocked_lds(m) bytes.
+constexpr int GJB = 16;                      // panel width
+constexpr int GJB_CW = 64;                   // columns of the trailing update staged at once
+constexpr int GJB_MAX = 1024;                // rows: one per thread in the update
+
+__device__ bool gj_inverse_blocked(double* A, int m, double* sm) {
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    double* Pn = sm;                                         // m x GJB panel, ld m
+    double* Tc = Pn + (size_t)GJB * m;                       // GJB x GJB_CW
+    double* s_bv = Tc + GJB * GJB_CW;                        // NWP
+    int* s_bi = reinterpret_cast<int*>(s_bv + NWP);          // NWP
+    int* s_perm = s_bi + NWP;                                // m
+    for (int j0 = 0; j0 < m; j0 += GJB) {
+        const int nb = min(GJB, m - j0);
+        for (int e = tid; e < m * nb; e += NTP) {
+            const int i = e % m, t = e / m;
+            Pn[i + t * m] = A[i + (int64_t)(j0 + t) * m];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < nb; ++kk) {
+            const int k = j0 + kk;
+            double best = -1.0;
+            int bi = INT_MAX;
+            for (int i = k + tid; i < m; i += NTP) {
+                const double v = fabs(Pn[i + kk * m]);
+                if (v > best) { best = v; bi = i; }
+            }
+            wave_argmax(best, bi);
+            if (lane == 0) { s_bv[wv] = best; s_bi[wv] = bi; }
+            __syncthreads();
+            best = s_bv[0];
+            bi = s_bi[0];
+            for (int w = 1; w < NWP; ++w)
+                if (s_bv[w] > best || (s_bv[w] == best && s_bi[w] < bi)) { best = s_bv[w]; bi = s_bi[w]; }
+            if (!(best > 0.0)) return false;                     // uniform
+            const int p = bi;
+            if (p != k && tid < nb) {
+                const double a = Pn[k + tid * m];
+                Pn[k + tid * m] = Pn[p + tid * m];
+                Pn[p + tid * m] = a;
+            }
+            if (tid == 0) s_perm[k] = p;
+            __syncthreads();
+            // the step on the panel columns: row k scaled by d = 1 / pivot, the
+            // other rows minus their column-k entry times the new row k
+            const double d = 1.0 / Pn[k + kk * m];
+            double rowk[GJB];
+#pragma unroll
+            for (int t = 0; t < GJB; ++t) rowk[t] = t < nb ? (t == kk ? d : Pn[k + t * m] * d) : 0.0;
+            __syncthreads();                                     // row k read by every thread
+            for (int i = tid; i < m; i += NTP) {
+                if (i == k) {
+                    for (int t = 0; t < nb; ++t) Pn[k + t * m] = rowk[t];
+                } else {
+                    const double f = Pn[i + kk * m];
+                    for (int t = 0; t < nb; ++t)
+                        Pn[i + t * m] = (t == kk) ? -f * d : Pn[i + t * m] - f * rowk[t];
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < m * nb; e += NTP) {
+            const int i = e % m, t = e / m;
+            A[i + (int64_t)(j0 + t) * m] = Pn[i + t * m];
+        }
+        // the panel's swaps on the other columns, in order (one thread per column)
+        for (int c = tid; c < m; c += NTP) {
+            if (c >= j0 && c < j0 + nb) continue;
+            double* col = A + (int64_t)c * m;
+            for (int kk = 0; kk < nb; ++kk) {
+                const int k = j0 + kk, p = s_perm[k];
+                if (p != k) {
+                    const double a = col[k];
+                    col[k] = col[p];
+                    col[p] = a;
+                }
+            }
+        }
+        __syncthreads();
+        // A[:, c] = M A[:, c] = A[:, c] + (M[:, J] - I[:, J]) A[J, c] for c outside J;
+        // thread i keeps row i of M[:, J] - I[:, J] in registers
+        double mh[GJB];
+        const int i = tid;
+#pragma unroll
+        for (int t = 0; t < GJB; ++t)
+            mh[t] = (i < m && t < nb) ? Pn[i + t * m] - (i == j0 + t ? 1.0 : 0.0) : 0.0;
+        for (int c0 = 0; c0 < m; c0 += GJB_CW) {
+            for (int e = tid; e < GJB * GJB_CW; e += NTP) {
+                const int t = e % GJB, cc = e / GJB, c = c0 + cc;
+                Tc[t + cc * GJB] = (t < nb && c < m && (c < j0 || c >= j0 + nb)) ? A[(j0 + t) + (int64_t)c * m] : 0.0;
+            }
+            __syncthreads();
+            if (i < m) {
+                const int cend = min(GJB_CW, m - c0);
+                for (int cc = 0; cc < cend; ++cc) {
+                    const int c = c0 + cc;
+                    if (c >= j0 && c < j0 + nb) continue;
+                    double acc = A[i + (int64_t)c * m];
+#pragma unroll
+                    for (int t = 0; t < GJB; ++t) acc += mh[t] * Tc[t + cc * GJB];
+                    A[i + (int64_t)c * m] = acc;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // the stored matrix is the inverse of A with rows permuted: undo by columns
+    for (int i = tid; i < m; i += NTP)
+        for (int k = m - 1; k >= 0; --k) {
+            const int p = s_perm[k];
+            if (p != k) {
+                const double t = A[i + (int64_t)k * m];
+                A[i + (int64_t)k * m] = A[i + (int64_t)p * m];
+                A[i + (int64_t)p * m] = t;
+            }
+        }
+    __syncthreads();
+    return true;
+}
+
+__host__ __device__ inline size_t gj_blocked_lds(int m) {
+    return ((size_t)GJB * m + GJB * GJB_CW + NWP) * sizeof(double) + (size_t)(NWP + m) * sizeof(int);
+}
+
 // Register-resident Gauss-Jordan inverse with partial pivoting for m <= MB.
 // Thread t owns row i = t % MB and the CPT columns [h CPT, (h+1) CPT), h = t / MB;
 // the matrix is padded with the identity beyond m.  Pivoting is implicit: step
@@ -1466,6 +1600,7 @@ __global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tas
     if (m <= 32) ok = gj_inverse_reg<32>(T.piv.p, m, sm);
     else if (m <= 64) ok = gj_inverse_reg<64>(T.piv.p, m, sm);
     else if (m <= 128) ok = gj_inverse_reg<128>(T.piv.p, m, sm);
+    else if (m <= GJB_MAX && gj_blocked_lds(m) <= (size_t)kLdsBudget) ok = gj_inverse_blocked(T.piv.p, m, sm);
     else ok = gj_inverse_global(T.piv.p, m, sm, (int*)(sm + m), sm + 2 * m);
     if (!ok && tid == 0) info[T.info_slot] = 1;
 }
@@ -1518,7 +1653,7 @@ __global__ __launch_bounds__(GT) void k_gemm_tiles(const DGemm* __restrict__ gs,
                 const int row = imap_at(imap, G.crmap, tl.i0 + a);
                 for (int b = tid / 32; b < nt; b += GT / 32) {
                     const int col = imap_at(imap, G.ccmap, tl.j0 + b);
-                    Cs[a + b * GLA] = G.C[(int64_t)row + (int64_t)col * G.ldc];
+                    Cs[a + b * GLA] = G.C[G.tr ? (int64_t)col + (int64_t)row * G.ldc : (int64_t)row + (int64_t)col * G.ldc];
                 }
             }
         }
@@ -1544,7 +1679,8 @@ __global__ __launch_bounds__(GT) void k_gemm_tiles(const DGemm* __restrict__ gs,
         if (a >= mt || b >= nt) return;
         const int row = imap_at(imap, G.crmap, tl.i0 + a);
         const int col = imap_at(imap, G.ccmap, tl.j0 + b);
-        G.C[(int64_t)row + (int64_t)col * G.ldc] = G.sub ? Cs[a + b * GLA] - v : v;
+        G.C[G.tr ? (int64_t)col + (int64_t)row * G.ldc : (int64_t)row + (int64_t)col * G.ldc] =
+            G.sub ? Cs[a + b * GLA] - v : v;
     };
     put(ty, tx, acc00);
     put(ty, tx + 16, acc01);
@@ -2023,7 +2159,9 @@ hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj,
     if (n == 0) return hipSuccess;
     // LDS: the Gauss-Jordan exchange buffers (4 KiB), or the global variant's
     // scratch (2 m + 1 doubles)
-    const size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
+    size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
+    if (max_m > 128 && max_m <= GJB_MAX && gj_blocked_lds(max_m) <= (size_t)kLdsBudget)
+        need = std::max(need, gj_blocked_lds(max_m));
     if (need > (size_t)kLdsBudget) return hipErrorInvalidValue;
     static std::atomic<bool> attr{false};
     if (!attr) {

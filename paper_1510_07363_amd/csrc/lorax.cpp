@@ -284,10 +284,11 @@ void ensure_gfx950(int dev) {
 // alone.
 struct NodeBatch {
     std::vector<DPrep> prep_s, prep_b;
-    std::vector<DProj> projs;
+    std::vector<DProj> projs;                 // RRQR: copies of rows of the transformed block
+    std::vector<DGemm> gp;                    // SVD: the pieces of B V as products
     std::vector<DGemm> g1s, g2s, g1b, g2b;
     int max_ms = 1, max_mb = 1;
-    int64_t pf_s = 0, pf_b = 0, gf_s = 0, gf_b = 0;
+    int64_t pf_s = 0, pf_b = 0, gf_p = 0, gf_s = 0, gf_b = 0;
 };
 
 struct FactorRun {
@@ -608,7 +609,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
     if (wtot * 8 > ws.bytes) ws.ensure(wtot * 8 + (wtot * 8) / 2);
     double* wsp = ws.as<double>();
     size_t wcur = 0;
-    const int64_t gf_s0 = nb.gf_s, gf_b0 = nb.gf_b, pf_s0 = nb.pf_s, pf_b0 = nb.pf_b;
+    const int64_t gf_s0 = nb.gf_s, gf_b0 = nb.gf_b, pf_s0 = nb.pf_s, pf_b0 = nb.pf_b, gf_p0 = nb.gf_p;
     auto schur = [&](const PivotPlan& pp, const PivMaps& pm, std::vector<DGemm>& g1, std::vector<DGemm>& g2,
                      int64_t& gfl) {
         const int32_t m = h->size[pp.node];
@@ -655,6 +656,21 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
         T.V = ct[ni].V;
         T.do_proj = 1;
         T.proj0 = (int32_t)nb.projs.size();
+        const bool svd = h->compress == LRX_SVD;
+        // SVD: piece k of B V = B[rows of k, :] V (nrows x r) into R_k (trans 0) or,
+        // transposed, into Q_k^T (trans 1), as tiled products; RRQR: row copies
+        auto piece = [&](const DProj& pj) {
+            if (pj.nrows <= 0 || r <= 0) return;
+            if (!svd) { nb.projs.push_back(pj); return; }
+            DGemm G{};
+            G.A = ct[ni].B + pj.row0; G.lda = ct[ni].M; G.amap = -1;
+            G.B = ct[ni].V; G.ldb = ct[ni].c; G.bmap = -1;
+            G.C = pj.dst.p; G.ldc = pj.trans ? r : pj.dst.nr;
+            G.crmap = pj.map; G.ccmap = -1; G.tr = pj.trans;
+            G.M = pj.nrows; G.N = r; G.K = ct[ni].c; G.sub = 0;
+            nb.gp.push_back(G);
+            nb.gf_p += 2ll * pj.nrows * ct[ni].c * r;
+        };
         for (size_t k = 0; k < ns.cands.size(); ++k) {
             const CandRef& cr = ns.cands[k];
             if (cr.e_sp >= 0) {
@@ -664,7 +680,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
                 pj.nrows = nr_of(cr.e_sp);
                 pj.trans = 0;
                 pj.map = mo(maps[si][ni].ra_map[k]);
-                if (pj.nrows > 0 && r > 0) nb.projs.push_back(pj);
+                piece(pj);
             }
             if (cr.e_ps >= 0) {
                 DProj pj{};
@@ -673,7 +689,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
                 pj.nrows = nc_of(cr.e_ps);
                 pj.trans = 1;
                 pj.map = mo(maps[si][ni].qb_map[k]);
-                if (pj.nrows > 0 && r > 0) nb.projs.push_back(pj);
+                piece(pj);
             }
         }
         T.nproj = (int32_t)nb.projs.size() - T.proj0;
@@ -684,7 +700,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
         T.piv = blk(ns.ps.e_self);
         T.info_slot = info_base + info_next++;
         nb.max_ms = std::max(nb.max_ms, (int)T.piv.nr);
-        nb.pf_s += 2ll * T.piv.nr * T.piv.nr * T.piv.nr + 2ll * T.M * T.c * r;
+        nb.pf_s += 2ll * T.piv.nr * T.piv.nr * T.piv.nr + (svd ? 0ll : 2ll * T.M * T.c * r);
         nb.prep_s.push_back(T);
         DPrep U{};
         U.piv = blk(ns.pb.e_self);
@@ -696,7 +712,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
         schur(ns.ps, maps[si][ni].ps, nb.g1s, nb.g2s, nb.gf_s);
         schur(ns.pb, maps[si][ni].pb, nb.g1b, nb.g2b, nb.gf_b);
     }
-    flops += (nb.pf_s - pf_s0) + (nb.pf_b - pf_b0) + (nb.gf_s - gf_s0) + (nb.gf_b - gf_b0);
+    flops += (nb.pf_s - pf_s0) + (nb.pf_b - pf_b0) + (nb.gf_s - gf_s0) + (nb.gf_b - gf_b0) + (nb.gf_p - gf_p0);
     if (wcur != wtot) fail(LRX_EDEVICE, "internal: Schur workspace size mismatch");
 }
 
@@ -869,12 +885,14 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 }
                 return t;
             };
-            int k1s, k2s, k1b, k2b;
+            int kps, k1s, k2s, k1b, k2b;
+            const std::vector<DTile> tps = tiles_of(nb.gp, kps);
             const std::vector<DTile> t1s = tiles_of(nb.g1s, k1s), t2s = tiles_of(nb.g2s, k2s);
             const std::vector<DTile> t1b = tiles_of(nb.g1b, k1b), t2b = tiles_of(nb.g2b, k2b);
             std::vector<char> buf;
             const size_t o_ps = append_bytes(buf, nb.prep_s), o_pj = append_bytes(buf, nb.projs);
             const size_t o_pb = append_bytes(buf, nb.prep_b);
+            const size_t o_gp = append_bytes(buf, nb.gp), o_tp = append_bytes(buf, tps);
             const size_t o_g1s = append_bytes(buf, nb.g1s), o_t1s = append_bytes(buf, t1s);
             const size_t o_g2s = append_bytes(buf, nb.g2s), o_t2s = append_bytes(buf, t2s);
             const size_t o_g1b = append_bytes(buf, nb.g1b), o_t1b = append_bytes(buf, t1b);
@@ -893,6 +911,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 HIPCHK(launch_gemm_tiles((const DGemm*)(b + og), (const DTile*)(b + ot), (int)t.size(), kmax, dmap,
                                          st));
             };
+            if (!tps.empty()) {                    // projection B V of every super-node (SVD)
+                LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.gf_p);
+                HIPCHK(launch_gemm_tiles((const DGemm*)(b + o_gp), (const DTile*)(b + o_tp), (int)tps.size(), kps,
+                                         dmap, st));
+            }
             {
                 LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_s);
                 HIPCHK(launch_node_prep((const DPrep*)(b + o_ps), np, nb.max_ms, (const DProj*)(b + o_pj), dmap,
