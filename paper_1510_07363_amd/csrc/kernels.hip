@@ -1021,9 +1021,19 @@ __device__ void jac_round(double* X, double* W, int64_t ldc, int kk, int c, int 
     }
 }
 
+// State kept in hv after X, A2, W between the three launches of the split form:
+// the pivot order (c values) and a header.
+enum { LH_KK = 0, LH_SCALE, LH_REST2, LH_TOL, LH_TINY2, LH_ROT, LH_DONE, LH_N };
+constexpr int KK_BLK = 8;                    // columns per block of the multi-work-group Jacobi
+constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold in LDS (16 x 1150 doubles)
+
+// mode 0: the whole pipeline in this work-group; mode 1: steps 1-3 and the
+// Jacobi only when L is too tall for the block rounds (state left in hv);
+// mode 2: singular values, rank and V from the state after the block rounds.
 __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
-                                                        const int32_t* __restrict__ imap, double trunc_rel) {
+                                                        const int32_t* __restrict__ imap, double trunc_rel,
+                                                        int mode) {
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
     const int lane = tid % WAVE, wv = tid / WAVE;
@@ -1033,9 +1043,11 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     __shared__ int s_piv;
     __shared__ int s_rot;
     if (M == 0 || c == 0) {
-        if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; }
+        if (tid == 0 && mode != 2) { *T.rank_out = 0; T.tails[0] = 0.0; }
         return;
     }
+    double* hst = T.hv + 3 * (size_t)c * c;                 // pivot order (c), then the header
+    double* hdr = hst + c;
     // LDS: reflector (max(M, c) + 1), norms (c), sv (c), hv0 (c), htau (c), perm (c), pos (c)
     const int vlen = (M > c ? M : c) + 1;
     double* s_v = sl;
@@ -1045,6 +1057,19 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     double* s_tau = s_hv0 + c;
     int* s_perm = reinterpret_cast<int*>(s_tau + c);
     int* s_pos = s_perm + c;
+    double* X = T.hv;                                   // c x c, ld c
+    double* A2 = X + (size_t)c * c;                     // c x c
+    double* W = A2 + (size_t)c * c;                     // c x c
+    const int64_t ldc = c;
+    int kk = 0;
+    double rest2 = 0.0, scale = 1.0;
+    if (mode == 2) {
+        kk = (int)hdr[LH_KK];
+        scale = hdr[LH_SCALE];
+        rest2 = hdr[LH_REST2];
+        for (int k = tid; k < c; k += NTL) s_perm[k] = (int)hst[k];
+        __syncthreads();
+    } else {
     // ---- assemble B (column-major, ld M; kept for the projection), max |B|
     double* __restrict__ B = T.B;
     for (int64_t e = tid; e < (int64_t)M * c; e += NTL) B[e] = 0.0;
@@ -1068,11 +1093,8 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     amax = 0.0;
     for (int t = 0; t < NWL; ++t) amax = fmax(amax, s_red[t]);
     const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
-    const double inv_scale = ldexp(1.0, -bexp), scale = ldexp(1.0, bexp);
-    double* X = T.hv;                                   // c x c, ld c
-    double* A2 = X + (size_t)c * c;                     // c x c
-    double* W = A2 + (size_t)c * c;                     // c x c
-    const int64_t ldc = c;
+    const double inv_scale = ldexp(1.0, -bexp);
+    scale = ldexp(1.0, bexp);
     // ---- 1. tall QR of B / 2^e on the copy Bw
     double* Bw = T.Bw;
     for (int64_t e = tid; e < (int64_t)M * c; e += NTL) Bw[e] = B[e] * inv_scale;
@@ -1090,8 +1112,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     for (int k = tid; k < c; k += NTL) s_perm[k] = k;
     __syncthreads();
     // ---- 2. QRCP of R0 (rows < kq are the only nonzero ones), truncated
-    int kk = 0;
-    double rest2 = 0.0, r00 = 0.0;
+    double r00 = 0.0;
     for (int j = 0; j < kq; ++j) {
         // squared norms of columns j..c-1 over rows j..kq-1
         for (int k = j + wv; k < c; k += NWL) {
@@ -1174,18 +1195,32 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         __syncthreads();
     }
     // ---- 4. one-sided Jacobi on the kk columns of L; W follows.  Pairs run in
-    // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes
-    if (kk > 1) {
-        const int n2 = kk + (kk & 1);
-        const double u = 1.1102230246251565e-16;
-        const double tol = 3.6 * u * (double)kk;
-        double f = 0.0;
-        for (int e = tid; e < kk * kk; e += NTL) {
-            const double x = X[(e % kk) + (e / kk) * ldc];
-            f += x * x;
+    // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes.
+    // In mode 1 it runs here only when L is too tall for the block rounds.
+    const double u = 1.1102230246251565e-16;
+    const double tol = 3.6 * u * (double)kk;
+    double f = 0.0;
+    for (int e = tid; e < kk * kk; e += NTL) {
+        const double x = X[(e % kk) + (e / kk) * ldc];
+        f += x * x;
+    }
+    const double fro = blk_sum_l(f, s_red);
+    const double tiny2 = 81.0 * u * u * fro;
+    const bool inline_jacobi = mode == 0 || kk > KK_LDS_MAX;
+    if (mode == 1) {
+        for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
+        if (tid == 0) {
+            hdr[LH_KK] = kk;
+            hdr[LH_SCALE] = scale;
+            hdr[LH_REST2] = rest2;
+            hdr[LH_TOL] = tol;
+            hdr[LH_TINY2] = tiny2;
+            hdr[LH_ROT] = 0.0;
+            hdr[LH_DONE] = (inline_jacobi || kk <= 1) ? 1.0 : 0.0;
         }
-        const double fro = blk_sum_l(f, s_red);
-        const double tiny2 = 81.0 * u * u * fro;
+    }
+    if (kk > 1 && inline_jacobi) {
+        const int n2 = kk + (kk & 1);
         for (int sweep = 0; sweep < 40; ++sweep) {
             if (tid == 0) s_rot = 0;
             __syncthreads();
@@ -1201,6 +1236,8 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
             if (!rot) break;
         }
     }
+    if (mode == 1) return;
+    }                                                   // mode != 2
     // ---- singular values, order, rank, V = P W
     for (int k = wv; k < kk; k += NWL) {
         double s2 = 0.0;
@@ -1228,6 +1265,120 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         T.tails[0] = smax;
         *T.rank_out = r;
     }
+}
+
+// One round of the block one-sided Jacobi over the columns of L (split form):
+// the kk columns form blocks of KK_BLK; round t pairs the blocks by the same
+// parallel ordering as single columns, and one work-group per block pair (all
+// tasks of the launch, blockIdx.y = task) copies its (up to) 16 columns of L
+// to LDS, runs one sweep of rotations over all pairs among them (a wavefront
+// per pair, Q accumulating the rotations), writes the columns back and
+// updates the same 16 columns of W by W Q.  Every rotation obeys the rotation
+// test of the single-column form, so the result is that of one-sided Jacobi with
+// another pair order.
+__global__ __launch_bounds__(NTL) void k_large_round(const DCompress* __restrict__ tasks, int t) {
+    const DCompress T = tasks[blockIdx.y];
+    const int c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    if (T.M == 0 || c == 0) return;
+    const double* hdr = T.hv + 3 * (size_t)c * c + c;
+    if (hdr[LH_DONE] != 0.0) return;
+    const int kk = (int)hdr[LH_KK];
+    const int nbk = (kk + KK_BLK - 1) / KK_BLK, nb2 = nbk + (nbk & 1);
+    const int pi = blockIdx.x;
+    if (t >= nb2 - 1 || pi >= nb2 / 2) return;
+    const int a = (t + pi) % (nb2 - 1);
+    const int b = pi == 0 ? nb2 - 1 : (t - pi + nb2 - 1) % (nb2 - 1);
+    if (a >= nbk || b >= nbk) return;                           // the dummy block
+    const double tol = hdr[LH_TOL], tiny2 = hdr[LH_TINY2];
+    double* X = T.hv;
+    double* W = T.hv + 2 * (size_t)c * c;
+    const int64_t ldc = c;
+    extern __shared__ double sx[];                              // 16 columns of L, ld kk
+    __shared__ double sq[16 * 16];
+    __shared__ int s_col[16];
+    __shared__ int s_rot;
+    const int na = min(KK_BLK, kk - a * KK_BLK), nbb = min(KK_BLK, kk - b * KK_BLK);
+    const int ncol = na + nbb;
+    if (tid < 16) s_col[tid] = tid < na ? a * KK_BLK + tid : (tid < ncol ? b * KK_BLK + (tid - na) : -1);
+    if (tid < 256) sq[tid] = (tid % 16 == tid / 16) ? 1.0 : 0.0;
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int e = tid; e < ncol * kk; e += NTL) {
+        const int sl_ = e / kk, r = e - sl_ * kk;
+        sx[e] = X[r + s_col[sl_] * ldc];
+    }
+    __syncthreads();
+    // one sweep over the 16 slots: 15 rounds of 8 disjoint pairs, a wavefront each
+    for (int t2 = 0; t2 < 15; ++t2) {
+        if (wv < 8) {
+            const int i = wv;
+            const int p0 = (t2 + i) % 15, q0 = i == 0 ? 15 : (t2 - i + 15) % 15;
+            const int p = p0 < q0 ? p0 : q0, q = p0 < q0 ? q0 : p0;
+            if (q < ncol) {
+                double* xp = sx + (size_t)p * kk;
+                double* xq = sx + (size_t)q * kk;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int r = lane; r < kk; r += WAVE) {
+                    const double x = xp[r], y = xq[r];
+                    al += x * x; be += y * y; ga += x * y;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be) && al > tiny2 && be > tiny2) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                    for (int r = lane; r < kk; r += WAVE) {
+                        const double x = xp[r], y = xq[r];
+                        xp[r] = cs * x - sn * y;
+                        xq[r] = sn * x + cs * y;
+                    }
+                    if (lane < 16) {
+                        const double x = sq[p * 16 + lane], y = sq[q * 16 + lane];
+                        sq[p * 16 + lane] = cs * x - sn * y;
+                        sq[q * 16 + lane] = sn * x + cs * y;
+                    }
+                    if (lane == 0) s_rot = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!s_rot) return;                                         // uniform: nothing moved
+    for (int e = tid; e < ncol * kk; e += NTL) {
+        const int sl_ = e / kk, r = e - sl_ * kk;
+        X[r + s_col[sl_] * ldc] = sx[e];
+    }
+    // W[:, cols] = W[:, cols] Q, one row per thread
+    for (int r = tid; r < c; r += NTL) {
+        double w[16];
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) w[s2] = s2 < ncol ? W[r + s_col[s2] * ldc] : 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) {
+            if (s2 >= ncol) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int s1 = 0; s1 < 16; ++s1) acc += w[s1] * sq[s2 * 16 + s1];
+            W[r + s_col[s2] * ldc] = acc;
+        }
+    }
+    if (tid == 0) const_cast<double*>(hdr)[LH_ROT] = 1.0;
+}
+
+// End of a sweep of the block rounds: out[task] = 1 if the task rotated during
+// the sweep (it goes on), else the task is marked done.
+__global__ void k_large_flags(const DCompress* __restrict__ tasks, int n, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DCompress T = tasks[i];
+    if (T.M == 0 || T.c == 0) { out[i] = 0; return; }
+    double* hdr = T.hv + 3 * (size_t)T.c * T.c + T.c;
+    const int go = hdr[LH_DONE] == 0.0 && hdr[LH_ROT] != 0.0;
+    hdr[LH_ROT] = 0.0;
+    if (!go) hdr[LH_DONE] = 1.0;
+    out[i] = go;
 }
 
 // LDS of k_compress_large in bytes, or 0 when the task does not fit
@@ -2139,7 +2290,7 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
 }
 
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
-                                 int max_M, double trunc_rel, hipStream_t st) {
+                                 int max_M, double trunc_rel, int mode, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const size_t lds = compress_large_lds(max_M, max_c);
     if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
@@ -2147,10 +2298,34 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_compress_large, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kLdsBudget);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_large_round, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBudget);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_compress_large, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel);
+    hipLaunchKernelGGL(k_compress_large, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int kkmax = max_c < KK_LDS_MAX ? max_c : KK_LDS_MAX;
+    const int nbk = (kkmax + KK_BLK - 1) / KK_BLK, nb2 = nbk + (nbk & 1);
+    const size_t lds = (size_t)2 * KK_BLK * kkmax * sizeof(double);
+    hipLaunchKernelGGL(k_large_round, dim3(nb2 / 2, n), dim3(NTL), lds, st, t, round);
+    return hipGetLastError();
+}
+
+int large_rounds(int max_c) {
+    const int kkmax = max_c < KK_LDS_MAX ? max_c : KK_LDS_MAX;
+    const int nbk = (kkmax + KK_BLK - 1) / KK_BLK, nb2 = nbk + (nbk & 1);
+    return nb2 - 1;
+}
+
+hipError_t launch_large_flags(const DCompress* t, int n, int32_t* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_large_flags, dim3(nblocks(n, 64)), dim3(64), 0, st, t, n, out);
     return hipGetLastError();
 }
 

@@ -28,11 +28,18 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                                int max_c, int max_M, bool fp32, hipStream_t st);
 // Truncated SVD of stacked blocks with c > 64 columns (FP64, matrices in the
-// workspace: hv needs 3 c^2 + c doubles, Bw M c).  Trailing QRCP rows below
+// workspace: hv needs 3 c^2 + c + 8 doubles, Bw M c).  Trailing QRCP rows below
 // trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
 // zeros).  Fits when compress_large_fits(M, c).
+// mode 0: the whole pipeline per work-group; mode 1: QRs and state (Jacobi only
+// for L taller than the block rounds hold), then launch_large_round for
+// rounds 0..large_rounds(max_c)-1 per sweep and launch_large_flags (out[i] = 1:
+// task i goes on) until no task goes on; mode 2: singular values, rank and V.
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
-                                 int max_M, double trunc_rel, hipStream_t st);
+                                 int max_M, double trunc_rel, int mode, hipStream_t st);
+hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st);
+int large_rounds(int max_c);
+hipError_t launch_large_flags(const DCompress* t, int n, int32_t* out, hipStream_t st);
 inline bool compress_large_fits(int M, int c) {
     const size_t vlen = (size_t)(M > c ? M : c) + 1;
     return (vlen + 4 * (size_t)c) * sizeof(double) + 2 * (size_t)c * sizeof(int) <= 152 * 1024;

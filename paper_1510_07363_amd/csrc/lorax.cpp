@@ -535,8 +535,9 @@ size_t FactorRun::compress_tasks() {
         T.eps = h->epsilon;
         wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
         wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
-        // hv: c^2 + c, or 3 c^2 + c for the large-block SVD (c > 64)
-        wsH[ni] = ws_need; ws_need += ((size_t)T.c * T.c * (svd && T.c > 64 ? 3 : 1) + T.c + 31) & ~(size_t)31;
+        // hv: c^2 + c, or 3 c^2 + c + 8 for the large-block SVD (c > 64)
+        wsH[ni] = ws_need;
+        ws_need += ((size_t)T.c * T.c * (svd && T.c > 64 ? 3 : 1) + T.c + 8 + 31) & ~(size_t)31;
         tail_at[ni] = tails_total;
         tails_total += (size_t)T.c + 2;
     }
@@ -752,8 +753,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
     sync();
     for (FactorRun* r : runs) { r->d_idx.release(); r->d_val.release(); }
 
-    PinBuf stage_m, stage_c, stage_n, pin_rt;   // descriptor staging, rank read-back
-    DevBuf d_desc_m, d_desc_c, d_desc_n, d_rt;
+    PinBuf stage_m, stage_c, stage_n, pin_rt, pin_flags;   // descriptor staging, rank read-back
+    DevBuf d_desc_m, d_desc_c, d_desc_n, d_rt, d_flags;
     int64_t m_epoch = -1;                       // epoch of the last merge upload
     for (size_t hgt = 0; hgt < max_h; ++hgt) {
         std::vector<FactorRun*> lv;
@@ -823,16 +824,19 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                     fp32_of.push_back((r->h->compress == LRX_SVD ? 0 : 4) | (r->fp32_compress ? 1 : 0));
             }
             // variants: SVD with c <= 64 (FP64 / FP32 arithmetic: keys 0 / 1), SVD
-            // with c > 64 (key 8: FP64 rows kept, 9: rows below epsilon / 100
-            // dropped in mixed precision; key 2 when its LDS does not fit), pivoted
-            // QR (key 4); each task takes its own variant whatever the others are
+            // with c > 64 (keys 8 / 10: FP64 rows kept, 9 / 11: rows below
+            // epsilon / 100 dropped in mixed precision; 10 / 11 for c > 192 run the
+            // Jacobi in multi-work-group block rounds; key 2 when the LDS of the
+            // large kernel does not fit), pivoted QR (key 4); each task takes its own
+            // variant whatever the others are
             struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0; size_t off = 0; };
             std::vector<Group> groups;
             for (size_t q = 0; q < all.size(); ++q) {
                 int key;
                 if (fp32_of[q] >= 4) key = 4;
                 else if (all[q].c <= 64) key = fp32_of[q];
-                else if (compress_large_fits(all[q].M, all[q].c)) key = 8 | (fp32_of[q] & 1);
+                else if (compress_large_fits(all[q].M, all[q].c))
+                    key = (all[q].c > 192 ? 10 : 8) | (fp32_of[q] & 1);   // 10, 11: Jacobi in block rounds
                 else key = 2;
                 size_t g = 0;
                 while (g < groups.size() && groups[g].key != key) ++g;
@@ -858,9 +862,32 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                     LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, G.fl);
                     if (G.key == 4)
                         HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, st));
-                    else if (G.key >= 8)
+                    else if (G.key == 8 || G.key == 9) {
                         HIPCHK(launch_compress_large(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
-                                                     (G.key & 1) ? 0.01 : 0.0, st));
+                                                     (G.key & 1) ? 0.01 : 0.0, 0, st));
+                    } else if (G.key >= 10) {
+                        // QRs, then sweeps of block-Jacobi rounds over all tasks until
+                        // none rotates, then the singular values and V
+                        const int nt = (int)G.t.size();
+                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 1, st));
+                        d_flags.ensure((size_t)nt * sizeof(int32_t));
+                        pin_flags.ensure((size_t)nt * sizeof(int32_t));
+                        const int rounds = large_rounds(G.max_c);
+                        for (int sweep = 0; sweep < 40; ++sweep) {
+                            for (int t = 0; t < rounds; ++t)
+                                HIPCHK(launch_large_round(dt, nt, G.max_c, t, st));
+                            HIPCHK(launch_large_flags(dt, nt, d_flags.as<int32_t>(), st));
+                            HIPCHK(hipMemcpyAsync(pin_flags.p, d_flags.p, (size_t)nt * sizeof(int32_t),
+                                                  hipMemcpyDeviceToHost, st));
+                            sync();
+                            const int32_t* fl = (const int32_t*)pin_flags.p;
+                            bool go = false;
+                            for (int q = 0; q < nt; ++q) go |= fl[q] != 0;
+                            if (!go) break;
+                        }
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 2, st));
+                    }
                     else
                         HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
                                                    (G.key & 1) != 0, st));
