@@ -105,12 +105,11 @@ struct Builder {
         for (auto& e : out[v].v) if (e.first != v) { pp.out_nodes.push_back(e.first); pp.out_edges.push_back(e.second); }
         // deterministic order: by node id
         auto sort_pair = [](std::vector<int32_t>& a, std::vector<int32_t>& b) {
-            std::vector<int32_t> ix(a.size());
-            std::iota(ix.begin(), ix.end(), 0);
-            std::sort(ix.begin(), ix.end(), [&](int32_t x, int32_t y) { return a[x] < a[y]; });
-            std::vector<int32_t> a2, b2;
-            for (int32_t i : ix) { a2.push_back(a[i]); b2.push_back(b[i]); }
-            a.swap(a2); b.swap(b2);
+            thread_local std::vector<std::pair<int32_t, int32_t>> ab;
+            ab.clear();
+            for (size_t i = 0; i < a.size(); ++i) ab.push_back({a[i], b[i]});
+            std::sort(ab.begin(), ab.end());          // node ids are distinct
+            for (size_t i = 0; i < ab.size(); ++i) { a[i] = ab[i].first; b[i] = ab[i].second; }
         };
         sort_pair(pp.in_nodes, pp.in_edges);
         sort_pair(pp.out_nodes, pp.out_edges);
@@ -185,6 +184,12 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
         if (leaf_ptr[c + 1] <= leaf_ptr[c]) return "leaf clusters must be non-empty";
 
     Builder B(P);
+    // room for the edges and nodes the method creates (about 40 edges and 8
+    // nodes per leaf cluster on the workloads here), so the tables are not moved
+    P.edges.reserve((size_t)nleaf * 40);
+    P.nodes.reserve((size_t)nleaf * 8);
+    B.out.reserve((size_t)nleaf * 8);
+    B.in.reserve((size_t)nleaf * 8);
     const int32_t l = depth;
     // leaf cluster of each tree position
     std::vector<int32_t> leaf_of(n);
