@@ -1029,7 +1029,9 @@ constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold 
 
 // mode 0: the whole pipeline in this work-group; mode 1: steps 1-3 and the
 // Jacobi only when L is too tall for the block rounds (state left in hv);
-// mode 2: singular values, rank and V from the state after the block rounds.
+// mode 4: assembly and the scaled copy Bw only; mode 5: mode 1 after the tall
+// QR of Bw was done by the panel and update launches; mode 2: singular values,
+// rank and V from the state after the block rounds.
 __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
                                                         const int32_t* __restrict__ imap, double trunc_rel,
@@ -1070,6 +1072,10 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         for (int k = tid; k < c; k += NTL) s_perm[k] = (int)hst[k];
         __syncthreads();
     } else {
+    double* Bw = T.Bw;
+    if (mode == 5) {
+        scale = hdr[LH_SCALE];
+    } else {
     // ---- assemble B (column-major, ld M; kept for the projection), max |B|
     double* __restrict__ B = T.B;
     for (int64_t e = tid; e < (int64_t)M * c; e += NTL) B[e] = 0.0;
@@ -1095,16 +1101,21 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
     const double inv_scale = ldexp(1.0, -bexp);
     scale = ldexp(1.0, bexp);
-    // ---- 1. tall QR of B / 2^e on the copy Bw
-    double* Bw = T.Bw;
+    // ---- 1. tall QR of B / 2^e on the copy Bw (mode 4: the copy only; the QR
+    // then runs as panel and update launches over many work-groups)
     for (int64_t e = tid; e < (int64_t)M * c; e += NTL) Bw[e] = B[e] * inv_scale;
     __syncthreads();
-    const int kq = M < c ? M : c;
-    for (int j = 0; j < kq; ++j) {
+    if (mode == 4) {
+        if (tid == 0) hdr[LH_SCALE] = scale;
+        return;
+    }
+    for (int j = 0; j < (M < c ? M : c); ++j) {
         double v0;
         hh_step(Bw, M, M, c, j, s_v, s_red, &v0);
         __syncthreads();
     }
+    }                                                   // mode != 5
+    const int kq = M < c ? M : c;
     for (int e = tid; e < c * c; e += NTL) {
         const int i = e % c, k = e / c;
         X[e] = (i <= k && i < kq) ? Bw[i + (int64_t)k * M] : 0.0;
@@ -1207,7 +1218,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     const double fro = blk_sum_l(f, s_red);
     const double tiny2 = 81.0 * u * u * fro;
     const bool inline_jacobi = mode == 0 || kk > KK_LDS_MAX;
-    if (mode == 1) {
+    if (mode == 1 || mode == 5) {
         for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
         if (tid == 0) {
             hdr[LH_KK] = kk;
@@ -1236,7 +1247,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
             if (!rot) break;
         }
     }
-    if (mode == 1) return;
+    if (mode == 1 || mode == 5) return;
     }                                                   // mode != 2
     // ---- singular values, order, rank, V = P W
     for (int k = wv; k < kk; k += NWL) {
@@ -1264,6 +1275,121 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     if (tid == 0) {
         T.tails[0] = smax;
         *T.rank_out = r;
+    }
+}
+
+// Blocked tall QR of Bw (M x c, ld M) over many work-groups, for the large
+// stacked blocks: panel j0 (QB columns) is reduced by one work-group per task,
+// which also forms T of the compact WY form H_j0 ... H_j0+nb-1 = I - V T V^T
+// (V unit-free: column a is v0_a at row j0 + a and Bw below it); the columns to
+// the right then receive C <- C - V T^T V^T C from work-groups of QB columns,
+// reading each element of C twice and writing it once per panel instead of
+// once per column.  tau, v0 and T of the panel live in the task's hv scratch
+// (the A2 area, unused until the LQ step).
+constexpr int QB = 16;
+
+__global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ tasks, int j0) {
+    const DCompress T = tasks[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int kq = M < c ? M : c;
+    if (M == 0 || c == 0 || j0 >= kq) return;
+    const int nb = min(QB, kq - j0);
+    extern __shared__ double s_vp[];
+    __shared__ double s_red[NWL];
+    __shared__ double s_S[QB * QB];
+    double* Bw = T.Bw;
+    double* scr = T.hv + (size_t)c * c;                      // tau (QB), v0 (QB), T (QB x QB)
+    for (int j = j0; j < j0 + nb; ++j) {
+        double v0;
+        const double tau = hh_step(Bw, M, M, j0 + nb, j, s_vp, s_red, &v0);
+        if (tid == 0) { scr[j - j0] = tau; scr[QB + (j - j0)] = v0; }
+        __syncthreads();
+    }
+    // S = V^T V (a <= b), a wavefront per pair
+    for (int pr = wv; pr < nb * nb; pr += NWL) {
+        const int a = pr % nb, b = pr / nb;
+        if (a > b) continue;                                  // uniform over the wavefront
+        const double* va = Bw + (int64_t)(j0 + a) * M;
+        const double* vb = Bw + (int64_t)(j0 + b) * M;
+        double d = 0.0;
+        for (int r = j0 + b + 1 + lane; r < M; r += WAVE) d += va[r] * vb[r];
+        d = wave_sum(d);
+        if (lane == 0) {
+            const double vab = (a == b) ? scr[QB + a] : va[j0 + b];     // V[j0+b, a]
+            s_S[a + b * QB] = d + vab * scr[QB + b];
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double* Tm = scr + 2 * QB;                            // Tm[a + b QB] = T[a][b]
+        for (int e = 0; e < QB * QB; ++e) Tm[e] = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const double tb = scr[b];
+            Tm[b + b * QB] = tb;
+            for (int a = 0; a < b; ++a) {                     // T[0:b, b] = -tau_b T[0:b, 0:b] S[0:b, b]
+                double z = 0.0;
+                for (int k = a; k < b; ++k) z += Tm[a + k * QB] * s_S[k + b * QB];
+                Tm[a + b * QB] = -tb * z;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__ tasks, int j0) {
+    const DCompress T = tasks[blockIdx.y];
+    const int M = T.M, c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int kq = M < c ? M : c;
+    if (M == 0 || c == 0 || j0 >= kq) return;
+    const int nb = min(QB, kq - j0);
+    const int c0 = j0 + nb + blockIdx.x * QB;
+    if (c0 >= c) return;
+    const int ncc = min(QB, c - c0);
+    __shared__ double s_W[QB * QB], s_W2[QB * QB];
+    const double* Bw = T.Bw;
+    const double* scr = T.hv + (size_t)c * c;
+    const double* v0 = scr + QB;
+    const double* Tm = scr + 2 * QB;
+    double* col = T.Bw + (int64_t)(c0 + wv) * M;              // a wavefront per column
+    auto vat = [&](int r, int a) -> double {                   // V[r, a]
+        const int d = j0 + a;
+        return r < d ? 0.0 : (r == d ? v0[a] : Bw[r + (int64_t)d * M]);
+    };
+    if (wv < ncc) {
+        double acc[QB];
+#pragma unroll
+        for (int a = 0; a < QB; ++a) acc[a] = 0.0;
+        for (int r = j0 + lane; r < M; r += WAVE) {
+            const double x = col[r];
+#pragma unroll
+            for (int a = 0; a < QB; ++a)
+                if (a < nb) acc[a] += vat(r, a) * x;
+        }
+#pragma unroll
+        for (int a = 0; a < QB; ++a) {
+            const double t = wave_sum(acc[a]);
+            if (lane == 0) s_W[a + wv * QB] = t;
+        }
+    }
+    __syncthreads();
+    if (tid < QB * QB) {                                       // W2 = T^T W
+        const int a = tid % QB, cc = tid / QB;
+        double z = 0.0;
+        if (a < nb && cc < ncc)
+            for (int b = 0; b <= a; ++b) z += Tm[b + a * QB] * s_W[b + cc * QB];
+        s_W2[a + cc * QB] = z;
+    }
+    __syncthreads();
+    if (wv < ncc) {
+        double w2[QB];
+#pragma unroll
+        for (int a = 0; a < QB; ++a) w2[a] = s_W2[a + wv * QB];
+        for (int r = j0 + lane; r < M; r += WAVE) {
+            double x = col[r];
+#pragma unroll
+            for (int a = 0; a < QB; ++a)
+                if (a < nb) x -= vat(r, a) * w2[a];
+            col[r] = x;
+        }
     }
 }
 
@@ -2306,6 +2432,33 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
     }
     hipLaunchKernelGGL(k_compress_large, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel, mode);
     return hipGetLastError();
+}
+
+hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t lds = (size_t)(max_M + 1) * sizeof(double);
+    if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
+    static std::atomic<bool> attr{false};
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_qr_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int kqmax = max_c < max_M ? max_c : max_M;
+    for (int j0 = 0; j0 < kqmax; j0 += QB) {
+        hipLaunchKernelGGL(k_qr_panel, dim3(n), dim3(NTL), lds, st, t, j0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // columns right of the panel (a task's panel may be narrower than QB)
+        const int nchunk = (max_c - j0 + QB - 1) / QB;
+        if (nchunk > 0) {
+            hipLaunchKernelGGL(k_qr_update, dim3(nchunk, n), dim3(NTL), 0, st, t, j0);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st) {

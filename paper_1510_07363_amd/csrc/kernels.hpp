@@ -32,12 +32,16 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
 // trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
 // zeros).  Fits when compress_large_fits(M, c).
 // mode 0: the whole pipeline per work-group; mode 1: QRs and state (Jacobi only
-// for L taller than the block rounds hold), then launch_large_round for
+// for L taller than the block rounds hold; modes 4 + launch_qr_blocked + 5 do
+// the same with the tall QR over many work-groups), then launch_large_round for
 // rounds 0..large_rounds(max_c)-1 per sweep and launch_large_flags (out[i] = 1:
 // task i goes on) until no task goes on; mode 2: singular values, rank and V.
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
                                  int max_M, double trunc_rel, int mode, hipStream_t st);
 hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st);
+// Tall QR of every task's Bw in panels of 16 columns over many work-groups
+// (between launch_compress_large modes 4 and 5).
+hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, hipStream_t st);
 int large_rounds(int max_c);
 hipError_t launch_large_flags(const DCompress* t, int n, int32_t* out, hipStream_t st);
 inline bool compress_large_fits(int M, int c) {

@@ -870,7 +870,9 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                         // none rotates, then the singular values and V
                         const int nt = (int)G.t.size();
                         const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 1, st));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, st));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, st));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, st));
                         d_flags.ensure((size_t)nt * sizeof(int32_t));
                         pin_flags.ensure((size_t)nt * sizeof(int32_t));
                         const int rounds = large_rounds(G.max_c);
