@@ -1021,17 +1021,18 @@ __device__ void jac_round(double* X, double* W, int64_t ldc, int kk, int c, int 
     }
 }
 
-// State kept in hv after X, A2, W between the three launches of the split form:
-// the pivot order (c values) and a header.
+// State kept in hv after X, A2, W and the panel scratch (c^2 each) between the
+// launches of the split form: the pivot order (c values) and a header.
 enum { LH_KK = 0, LH_SCALE, LH_REST2, LH_TOL, LH_TINY2, LH_ROT, LH_DONE, LH_N };
 constexpr int KK_BLK = 8;                    // columns per block of the multi-work-group Jacobi
 constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold in LDS (16 x 1150 doubles)
 
 // mode 0: the whole pipeline in this work-group; mode 1: steps 1-3 and the
 // Jacobi only when L is too tall for the block rounds (state left in hv);
-// mode 4: assembly and the scaled copy Bw only; mode 5: mode 1 after the tall
-// QR of Bw was done by the panel and update launches; mode 2: singular values,
-// rank and V from the state after the block rounds.
+// mode 4: assembly and the scaled copy Bw only; mode 5: after the tall QR of Bw
+// by the panel and update launches, the pivoted QR and A2 (the LQ and Q2 follow
+// as launches); mode 6: from A2 factored and W = Q2 formed, L and the state for
+// the block rounds; mode 2: singular values, rank and V after the block rounds.
 __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
                                                         const int32_t* __restrict__ imap, double trunc_rel,
@@ -1048,7 +1049,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         if (tid == 0 && mode != 2) { *T.rank_out = 0; T.tails[0] = 0.0; }
         return;
     }
-    double* hst = T.hv + 3 * (size_t)c * c;                 // pivot order (c), then the header
+    double* hst = T.hv + 4 * (size_t)c * c;                 // pivot order (c), then the header
     double* hdr = hst + c;
     // LDS: reflector (max(M, c) + 1), norms (c), sv (c), hv0 (c), htau (c), perm (c), pos (c)
     const int vlen = (M > c ? M : c) + 1;
@@ -1073,6 +1074,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         __syncthreads();
     } else {
     double* Bw = T.Bw;
+    if (mode != 6) {
     if (mode == 5) {
         scale = hdr[LH_SCALE];
     } else {
@@ -1171,6 +1173,28 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         const int i = e % c, k = e / c;
         A2[i + k * ldc] = (i >= k) ? X[k + i * ldc] : 0.0;
     }
+    if (mode == 5) {
+        // the LQ and Q2 then run as panel and update launches (W = E now)
+        for (int e = tid; e < c * kk; e += NTL) {
+            const int i = e % c, k = e / c;
+            W[i + k * ldc] = (i == k) ? 1.0 : 0.0;
+        }
+        for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
+        if (tid == 0) {
+            hdr[LH_KK] = kk;
+            hdr[LH_SCALE] = scale;
+            hdr[LH_REST2] = rest2;
+            hdr[LH_DONE] = 0.0;
+        }
+        return;
+    }
+    }                                                   // mode != 6
+    if (mode == 6) {
+        kk = (int)hdr[LH_KK];
+        scale = hdr[LH_SCALE];
+        rest2 = hdr[LH_REST2];
+        for (int k = tid; k < c; k += NTL) s_perm[k] = (int)hst[k];
+    } else {
     __syncthreads();
     for (int j = 0; j < kk; ++j) {
         double v0;
@@ -1178,18 +1202,20 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         if (tid == 0) { s_hv0[j] = v0; s_tau[j] = tau; }
         __syncthreads();
     }
+    }
     for (int e = tid; e < kk * kk; e += NTL) {
         const int i = e % kk, k = e / kk;
         X[i + k * ldc] = (k <= i) ? A2[k + i * ldc] : 0.0;   // L (kk x kk, ld c)
     }
+    if (mode != 6)
     for (int e = tid; e < c * kk; e += NTL) {
         const int i = e % c, k = e / c;
         W[i + k * ldc] = (i == k) ? 1.0 : 0.0;
     }
     __syncthreads();
     // W = Q2[:, :kk] = H_0 ... H_{kk-1} E, applied right to left; H_j changes
-    // rows j.. of columns j.. only
-    for (int j = kk - 1; j >= 0; --j) {
+    // rows j.. of columns j.. only (mode 6: done by the update launches)
+    for (int j = (mode == 6 ? -1 : kk - 1); j >= 0; --j) {
         const double tau = s_tau[j];
         if (tau == 0.0) continue;                        // uniform
         const double v0 = s_hv0[j];
@@ -1218,7 +1244,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     const double fro = blk_sum_l(f, s_red);
     const double tiny2 = 81.0 * u * u * fro;
     const bool inline_jacobi = mode == 0 || kk > KK_LDS_MAX;
-    if (mode == 1 || mode == 5) {
+    if (mode == 1 || mode == 6) {
         for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
         if (tid == 0) {
             hdr[LH_KK] = kk;
@@ -1247,7 +1273,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
             if (!rot) break;
         }
     }
-    if (mode == 1 || mode == 5) return;
+    if (mode == 1 || mode == 6) return;
     }                                                   // mode != 2
     // ---- singular values, order, rank, V = P W
     for (int k = wv; k < kk; k += NWL) {
@@ -1278,30 +1304,61 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     }
 }
 
-// Blocked tall QR of Bw (M x c, ld M) over many work-groups, for the large
-// stacked blocks: panel j0 (QB columns) is reduced by one work-group per task,
-// which also forms T of the compact WY form H_j0 ... H_j0+nb-1 = I - V T V^T
-// (V unit-free: column a is v0_a at row j0 + a and Bw below it); the columns to
-// the right then receive C <- C - V T^T V^T C from work-groups of QB columns,
-// reading each element of C twice and writing it once per panel instead of
-// once per column.  tau, v0 and T of the panel live in the task's hv scratch
-// (the A2 area, unused until the LQ step).
+// Blocked Householder QR over many work-groups, for the large stacked blocks.
+// A panel of QB columns is reduced by one work-group per task, which also forms
+// T of the compact WY form H_j0 ... H_j0+nb-1 = I - V T V^T (column a of V is
+// v0_a at row j0 + a and the matrix below it); the other columns then receive
+// the panel's transformation from work-groups of QB columns, reading each
+// element twice and writing it once per panel instead of once per column.
+//   which 0: tall QR of Bw (M x c, ld M), C <- C - V T^T V^T C to the right;
+//   which 1: QR of A2 (c x kk, ld c), the LQ step, likewise;
+//   which 2: W <- H_j0 ... H_j0+nb-1 W = W - V T V^T W with the panels of the
+//            LQ, applied last panel first: W = Q2 E from W = E.
+// tau, v0 and T of panel p stay in the task's scratch area (hv + 3 c^2).
 constexpr int QB = 16;
+constexpr int QB_SCR = 2 * QB + QB * QB;     // scratch doubles per panel
 
-__global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ tasks, int j0) {
+struct QrView {
+    double* A;                               // the matrix being factored (V lives in it)
+    int64_t ld;
+    int nr, ncol, kq;                        // rows, columns, reflectors
+    double* C;                               // the matrix updated (which 2: W)
+    int ccol;                                // its columns
+    double* scr;                             // panel scratch base
+};
+
+__device__ inline bool qr_view(const DCompress& T, int which, QrView& v) {
+    const int M = T.M, c = T.c;
+    if (M == 0 || c == 0) return false;
+    v.scr = T.hv + 3 * (size_t)c * c;
+    if (which == 0) {
+        v.A = T.Bw; v.ld = M; v.nr = M; v.ncol = c; v.kq = M < c ? M : c;
+        v.C = T.Bw; v.ccol = c;
+    } else {
+        const double* hdr = T.hv + 4 * (size_t)c * c + c;
+        if (hdr[LH_DONE] != 0.0) return false;
+        const int kk = (int)hdr[LH_KK];
+        v.A = T.hv + (size_t)c * c; v.ld = c; v.nr = c; v.ncol = kk; v.kq = kk;
+        v.C = which == 2 ? T.hv + 2 * (size_t)c * c : v.A; v.ccol = kk;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ tasks, int j0, int which) {
     const DCompress T = tasks[blockIdx.x];
-    const int M = T.M, c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    const int kq = M < c ? M : c;
-    if (M == 0 || c == 0 || j0 >= kq) return;
-    const int nb = min(QB, kq - j0);
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    QrView Q;
+    if (!qr_view(T, which, Q) || j0 >= Q.kq) return;
+    const int nb = min(QB, Q.kq - j0);
     extern __shared__ double s_vp[];
     __shared__ double s_red[NWL];
     __shared__ double s_S[QB * QB];
-    double* Bw = T.Bw;
-    double* scr = T.hv + (size_t)c * c;                      // tau (QB), v0 (QB), T (QB x QB)
+    double* A = Q.A;
+    const int64_t ld = Q.ld;
+    double* scr = Q.scr + (size_t)(j0 / QB) * QB_SCR;        // tau (QB), v0 (QB), T (QB x QB)
     for (int j = j0; j < j0 + nb; ++j) {
         double v0;
-        const double tau = hh_step(Bw, M, M, j0 + nb, j, s_vp, s_red, &v0);
+        const double tau = hh_step(A, ld, Q.nr, j0 + nb, j, s_vp, s_red, &v0);
         if (tid == 0) { scr[j - j0] = tau; scr[QB + (j - j0)] = v0; }
         __syncthreads();
     }
@@ -1309,10 +1366,10 @@ __global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ 
     for (int pr = wv; pr < nb * nb; pr += NWL) {
         const int a = pr % nb, b = pr / nb;
         if (a > b) continue;                                  // uniform over the wavefront
-        const double* va = Bw + (int64_t)(j0 + a) * M;
-        const double* vb = Bw + (int64_t)(j0 + b) * M;
+        const double* va = A + (int64_t)(j0 + a) * ld;
+        const double* vb = A + (int64_t)(j0 + b) * ld;
         double d = 0.0;
-        for (int r = j0 + b + 1 + lane; r < M; r += WAVE) d += va[r] * vb[r];
+        for (int r = j0 + b + 1 + lane; r < Q.nr; r += WAVE) d += va[r] * vb[r];
         d = wave_sum(d);
         if (lane == 0) {
             const double vab = (a == b) ? scr[QB + a] : va[j0 + b];     // V[j0+b, a]
@@ -1335,30 +1392,33 @@ __global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__ tasks, int j0) {
+__global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__ tasks, int j0, int which) {
     const DCompress T = tasks[blockIdx.y];
-    const int M = T.M, c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    const int kq = M < c ? M : c;
-    if (M == 0 || c == 0 || j0 >= kq) return;
-    const int nb = min(QB, kq - j0);
-    const int c0 = j0 + nb + blockIdx.x * QB;
-    if (c0 >= c) return;
-    const int ncc = min(QB, c - c0);
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    QrView Q;
+    if (!qr_view(T, which, Q) || j0 >= Q.kq) return;
+    const int nb = min(QB, Q.kq - j0);
+    const int cfirst = which == 2 ? j0 : j0 + nb;             // columns the panel changes
+    const int c0 = cfirst + blockIdx.x * QB;
+    if (c0 >= Q.ccol) return;
+    const int ncc = min(QB, Q.ccol - c0);
     __shared__ double s_W[QB * QB], s_W2[QB * QB];
-    const double* Bw = T.Bw;
-    const double* scr = T.hv + (size_t)c * c;
+    const double* A = Q.A;
+    const int64_t ld = Q.ld;
+    const int nr = Q.nr;
+    const double* scr = Q.scr + (size_t)(j0 / QB) * QB_SCR;
     const double* v0 = scr + QB;
     const double* Tm = scr + 2 * QB;
-    double* col = T.Bw + (int64_t)(c0 + wv) * M;              // a wavefront per column
+    double* col = Q.C + (int64_t)(c0 + wv) * ld;              // a wavefront per column
     auto vat = [&](int r, int a) -> double {                   // V[r, a]
         const int d = j0 + a;
-        return r < d ? 0.0 : (r == d ? v0[a] : Bw[r + (int64_t)d * M]);
+        return r < d ? 0.0 : (r == d ? v0[a] : A[r + (int64_t)d * ld]);
     };
     if (wv < ncc) {
         double acc[QB];
 #pragma unroll
         for (int a = 0; a < QB; ++a) acc[a] = 0.0;
-        for (int r = j0 + lane; r < M; r += WAVE) {
+        for (int r = j0 + lane; r < nr; r += WAVE) {
             const double x = col[r];
 #pragma unroll
             for (int a = 0; a < QB; ++a)
@@ -1371,11 +1431,15 @@ __global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__
         }
     }
     __syncthreads();
-    if (tid < QB * QB) {                                       // W2 = T^T W
+    if (tid < QB * QB) {                                       // W2 = T^T W (which 0, 1) or T W (which 2)
         const int a = tid % QB, cc = tid / QB;
         double z = 0.0;
-        if (a < nb && cc < ncc)
-            for (int b = 0; b <= a; ++b) z += Tm[b + a * QB] * s_W[b + cc * QB];
+        if (a < nb && cc < ncc) {
+            if (which == 2)
+                for (int b = a; b < nb; ++b) z += Tm[a + b * QB] * s_W[b + cc * QB];
+            else
+                for (int b = 0; b <= a; ++b) z += Tm[b + a * QB] * s_W[b + cc * QB];
+        }
         s_W2[a + cc * QB] = z;
     }
     __syncthreads();
@@ -1383,7 +1447,7 @@ __global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__
         double w2[QB];
 #pragma unroll
         for (int a = 0; a < QB; ++a) w2[a] = s_W2[a + wv * QB];
-        for (int r = j0 + lane; r < M; r += WAVE) {
+        for (int r = j0 + lane; r < nr; r += WAVE) {
             double x = col[r];
 #pragma unroll
             for (int a = 0; a < QB; ++a)
@@ -1406,7 +1470,7 @@ __global__ __launch_bounds__(NTL) void k_large_round(const DCompress* __restrict
     const DCompress T = tasks[blockIdx.y];
     const int c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     if (T.M == 0 || c == 0) return;
-    const double* hdr = T.hv + 3 * (size_t)c * c + c;
+    const double* hdr = T.hv + 4 * (size_t)c * c + c;
     if (hdr[LH_DONE] != 0.0) return;
     const int kk = (int)hdr[LH_KK];
     const int nbk = (kk + KK_BLK - 1) / KK_BLK, nb2 = nbk + (nbk & 1);
@@ -1500,7 +1564,7 @@ __global__ void k_large_flags(const DCompress* __restrict__ tasks, int n, int32_
     if (i >= n) return;
     const DCompress T = tasks[i];
     if (T.M == 0 || T.c == 0) { out[i] = 0; return; }
-    double* hdr = T.hv + 3 * (size_t)T.c * T.c + T.c;
+    double* hdr = T.hv + 4 * (size_t)T.c * T.c + T.c;
     const int go = hdr[LH_DONE] == 0.0 && hdr[LH_ROT] != 0.0;
     hdr[LH_ROT] = 0.0;
     if (!go) hdr[LH_DONE] = 1.0;
@@ -2434,9 +2498,10 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
     return hipGetLastError();
 }
 
-hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, hipStream_t st) {
+hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, int which, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const size_t lds = (size_t)(max_M + 1) * sizeof(double);
+    const int nrmax = which == 0 ? max_M : max_c;             // rows of the matrix factored
+    const size_t lds = (size_t)(nrmax + 1) * sizeof(double);
     if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
     static std::atomic<bool> attr{false};
     if (!attr) {
@@ -2445,16 +2510,20 @@ hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, hi
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const int kqmax = max_c < max_M ? max_c : max_M;
-    for (int j0 = 0; j0 < kqmax; j0 += QB) {
-        hipLaunchKernelGGL(k_qr_panel, dim3(n), dim3(NTL), lds, st, t, j0);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        // columns right of the panel (a task's panel may be narrower than QB)
+    const int kqmax = which == 0 ? (max_c < max_M ? max_c : max_M) : max_c;
+    const int npanel = (kqmax + QB - 1) / QB;
+    for (int p = 0; p < npanel; ++p) {
+        const int j0 = (which == 2 ? npanel - 1 - p : p) * QB;   // Q2: last panel first
+        if (which != 2) {
+            hipLaunchKernelGGL(k_qr_panel, dim3(n), dim3(NTL), lds, st, t, j0, which);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        // columns the panel changes (a task's panel may be narrower than QB)
         const int nchunk = (max_c - j0 + QB - 1) / QB;
         if (nchunk > 0) {
-            hipLaunchKernelGGL(k_qr_update, dim3(nchunk, n), dim3(NTL), 0, st, t, j0);
-            e = hipGetLastError();
+            hipLaunchKernelGGL(k_qr_update, dim3(nchunk, n), dim3(NTL), 0, st, t, j0, which);
+            hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
     }

@@ -28,7 +28,7 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                                int max_c, int max_M, bool fp32, hipStream_t st);
 // Truncated SVD of stacked blocks with c > 64 columns (FP64, matrices in the
-// workspace: hv needs 3 c^2 + c + 8 doubles, Bw M c).  Trailing QRCP rows below
+// workspace: hv needs 4 c^2 + c + 8 doubles, Bw M c).  Trailing QRCP rows below
 // trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
 // zeros).  Fits when compress_large_fits(M, c).
 // mode 0: the whole pipeline per work-group; mode 1: QRs and state (Jacobi only
@@ -39,9 +39,11 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
                                  int max_M, double trunc_rel, int mode, hipStream_t st);
 hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st);
-// Tall QR of every task's Bw in panels of 16 columns over many work-groups
-// (between launch_compress_large modes 4 and 5).
-hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, hipStream_t st);
+// Blocked Householder QR in panels of 16 columns over many work-groups:
+// which 0: tall QR of every task's Bw (between launch_compress_large modes 4
+// and 5); which 1: QR of A2 (the LQ step) and which 2: W = Q2 E (between modes 5
+// and 6).
+hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, int which, hipStream_t st);
 int large_rounds(int max_c);
 hipError_t launch_large_flags(const DCompress* t, int n, int32_t* out, hipStream_t st);
 inline bool compress_large_fits(int M, int c) {

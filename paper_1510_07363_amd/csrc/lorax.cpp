@@ -535,9 +535,9 @@ size_t FactorRun::compress_tasks() {
         T.eps = h->epsilon;
         wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
         wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
-        // hv: c^2 + c, or 3 c^2 + c + 8 for the large-block SVD (c > 64)
+        // hv: c^2 + c, or 4 c^2 + c + 8 for the large-block SVD (c > 64)
         wsH[ni] = ws_need;
-        ws_need += ((size_t)T.c * T.c * (svd && T.c > 64 ? 3 : 1) + T.c + 8 + 31) & ~(size_t)31;
+        ws_need += ((size_t)T.c * T.c * (svd && T.c > 64 ? 4 : 1) + T.c + 8 + 31) & ~(size_t)31;
         tail_at[ni] = tails_total;
         tails_total += (size_t)T.c + 2;
     }
@@ -871,8 +871,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                         const int nt = (int)G.t.size();
                         const double trunc = (G.key & 1) ? 0.01 : 0.0;
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, st));
-                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, st));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, st));
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, st));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 1, st));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 2, st));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 6, st));
                         d_flags.ensure((size_t)nt * sizeof(int32_t));
                         pin_flags.ensure((size_t)nt * sizeof(int32_t));
                         const int rounds = large_rounds(G.max_c);
