@@ -136,7 +136,8 @@ struct SwGroup {         // 4 words: comps [comp0, comp0 + ncomp), rows summed
 // Matrix run set: nrun runs of len elements, run t at src + t * ld (elements of
 // es bytes: FP64, or FP32 for the off-diagonal blocks in mixed precision),
 // stored in LDS as doubles at lds + t * dld.  Vector run set (src == nullptr): nrun rows of x, row t is x row (map < 0
-// ? ld + t : map[t]), the launch's right-hand sides, stored at lds + t * kSwKS.
+// ? ld + t : map[t]), the launch's right-hand sides, stored in the LDS row that
+// starts at lds + t * kSwKS (elements of a row in a bank-spreading order).
 struct SwRun {           // 10 words
     const void* src;
     int32_t ld, len, nrun, map, lds, dld;

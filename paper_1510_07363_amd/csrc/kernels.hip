@@ -1032,7 +1032,8 @@ constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold 
 // mode 4: assembly and the scaled copy Bw only; mode 5: after the tall QR of Bw
 // by the panel and update launches, the pivoted QR and A2 (the LQ and Q2 follow
 // as launches); mode 6: from A2 factored and W = Q2 formed, L and the state for
-// the block rounds; mode 2: singular values, rank and V after the block rounds.
+// the block rounds; mode 2: singular values, rank and V after the block rounds;
+// mode 7: mode 0 from the tall QR of Bw done by the panel and update launches.
 __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
                                                         const int32_t* __restrict__ imap, double trunc_rel,
@@ -1075,7 +1076,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     } else {
     double* Bw = T.Bw;
     if (mode != 6) {
-    if (mode == 5) {
+    if (mode == 5 || mode == 7) {
         scale = hdr[LH_SCALE];
     } else {
     // ---- assemble B (column-major, ld M; kept for the projection), max |B|
@@ -1243,7 +1244,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     }
     const double fro = blk_sum_l(f, s_red);
     const double tiny2 = 81.0 * u * u * fro;
-    const bool inline_jacobi = mode == 0 || kk > KK_LDS_MAX;
+    const bool inline_jacobi = mode == 0 || mode == 7 || kk > KK_LDS_MAX;
     if (mode == 1 || mode == 6) {
         for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
         if (tid == 0) {
@@ -2037,6 +2038,13 @@ __global__ __launch_bounds__(GT) void k_gemm_tiles(const DGemm* __restrict__ gs,
 // A thread's elements are kSwThreads apart, so the position inside the current
 // run advances by a fixed quotient and remainder; the fields of the current
 // run stay in registers.
+// Vector rows in LDS (kSwKS doubles each, right-hand side k of the row that
+// starts at LDS double ra) keep element k at ra + (k ^ ((ra >> 4) & 7)): rows
+// 8 doubles apart then put one element of 16 consecutive rows in 16 different
+// bank pairs, so lanes that read one element of different rows do not conflict.
+static_assert(kSwKS == 8, "vector row swizzle assumes rows of 8 doubles");
+__device__ __forceinline__ int sw_slot(int ra, int k) { return ra + (k ^ ((ra >> 4) & 7)); }
+
 template <int NK>
 __device__ __forceinline__ void sw_copy(const SwRun* runs, int nrun, const int32_t* D, int elems,
                                         const double* x, int ldx, double* dat) {
@@ -2093,7 +2101,7 @@ __device__ __forceinline__ void sw_copy(const SwRun* runs, int nrun, const int32
                     const int row = map < 0 ? ld + t : D[map + t];
                     v[u] = x[(int64_t)row * ldx + a];
                 }
-                dst[u] = lds + t * dld + a;
+                dst[u] = src ? lds + t * dld + a : sw_slot(lds + t * kSwKS, a);
                 g += kSwThreads;
                 a += r;
                 t += q;
@@ -2130,9 +2138,10 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
         for (int t = sub; t < c.nc; t += L) {
             const double mv = mp[t * c.ld];
             const int row = c.in_map < 0 ? t : D[c.in_map + t];
-            const double* iv = dat + c.in + row * kSwKS;
+            const int ra = c.in + row * kSwKS, key = (ra >> 4) & 7;
+            const double* iv = dat + ra;
 #pragma unroll
-            for (int k = 0; k < NK; ++k) acc[k] = fma(mv, iv[k], acc[k]);
+            for (int k = 0; k < NK; ++k) acc[k] = fma(mv, iv[k ^ key], acc[k]);
         }
         for (int o = L >> 1; o > 0; o >>= 1) {
 #pragma unroll
@@ -2141,17 +2150,19 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
         if (sub == 0) {
             double y[NK];
             if (c.init >= 0) {
-                const double* ip = dat + c.init + (c.init_map < 0 ? a : D[c.init_map + a]) * kSwKS;
+                const int ra = c.init + (c.init_map < 0 ? a : D[c.init_map + a]) * kSwKS, key = (ra >> 4) & 7;
+                const double* ip = dat + ra;
 #pragma unroll
-                for (int k = 0; k < NK; ++k) y[k] = ip[k] - acc[k];
+                for (int k = 0; k < NK; ++k) y[k] = ip[k ^ key] - acc[k];
             } else {
 #pragma unroll
                 for (int k = 0; k < NK; ++k) y[k] = acc[k];
             }
             if (c.out >= 0) {
-                double* op = dat + c.out + (c.out_map < 0 ? a : D[c.out_map + a]) * kSwKS;
+                const int ra = c.out + (c.out_map < 0 ? a : D[c.out_map + a]) * kSwKS, key = (ra >> 4) & 7;
+                double* op = dat + ra;
 #pragma unroll
-                for (int k = 0; k < NK; ++k) op[k] = y[k];
+                for (int k = 0; k < NK; ++k) op[k ^ key] = y[k];
             }
             if (c.gmap >= 0 || c.gbase >= 0) {
                 const int row = c.gmap >= 0 ? D[c.gmap + a] : c.gbase + a;

@@ -150,6 +150,41 @@ struct SolveStep {
     int64_t bytes_fwd = 0, bytes_bwd = 0;   // algorithmic bytes of one launch (one right-hand side)
 };
 
+// Two library streams (with a fork and two join events) per host thread and
+// device, on which independent compress variants of one colour step run beside
+// the caller's stream.  Null if they cannot be made (then all runs on one stream).
+struct AuxStreams {
+    bool made = false;
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+};
+thread_local std::vector<AuxStreams> t_aux;
+
+AuxStreams* aux_streams() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    if ((int)t_aux.size() <= dev) t_aux.resize(dev + 1);
+    AuxStreams& a = t_aux[dev];
+    if (!a.made) {
+        for (int k = 0; k < 2; ++k) {
+            if (!a.s[k] && hipStreamCreateWithFlags(&a.s[k], hipStreamNonBlocking) != hipSuccess) {
+                a.s[k] = nullptr;
+                return nullptr;
+            }
+            if (!a.join[k] && hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming) != hipSuccess) {
+                a.join[k] = nullptr;
+                return nullptr;
+            }
+        }
+        if (!a.fork && hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) != hipSuccess) {
+            a.fork = nullptr;
+            return nullptr;
+        }
+        a.made = true;
+    }
+    return &a;
+}
+
 // Optional event timing of every launch, by kernel class (lrx_timing_*).
 struct TimedLaunch {
     int cls;
@@ -824,20 +859,23 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                     fp32_of.push_back((r->h->compress == LRX_SVD ? 0 : 4) | (r->fp32_compress ? 1 : 0));
             }
             // variants: SVD with c <= 64 (FP64 / FP32 arithmetic: keys 0 / 1), SVD
-            // with c > 64 (keys 8 / 10: FP64 rows kept, 9 / 11: rows below
-            // epsilon / 100 dropped in mixed precision; 10 / 11 for c > 192 run the
-            // Jacobi in multi-work-group block rounds; key 2 when the LDS of the
-            // large kernel does not fit), pivoted QR (key 4); each task takes its own
-            // variant whatever the others are
+            // with c > 64 (even keys: FP64 rows kept, odd: rows below epsilon / 100
+            // dropped in mixed precision; 8 / 9: one work-group per task; 12 / 13
+            // for tall blocks, M c >= 3e5: the tall QR in multi-work-group panels,
+            // the rest in one work-group; 10 / 11 for c > 192 or M c >= 1e6: QRs in
+            // panels and the Jacobi in multi-work-group block rounds; key 2 when the
+            // LDS of the large kernel does not fit), pivoted QR (key 4); each task
+            // takes its own variant whatever the others are
             struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0; size_t off = 0; };
             std::vector<Group> groups;
             for (size_t q = 0; q < all.size(); ++q) {
                 int key;
                 if (fp32_of[q] >= 4) key = 4;
                 else if (all[q].c <= 64) key = fp32_of[q];
-                else if (compress_large_fits(all[q].M, all[q].c))
-                    key = (all[q].c > 192 ? 10 : 8) | (fp32_of[q] & 1);   // 10, 11: Jacobi in block rounds
-                else key = 2;
+                else if (compress_large_fits(all[q].M, all[q].c)) {
+                    const int64_t mc = (int64_t)all[q].M * all[q].c;
+                    key = (all[q].c > 192 || mc >= 1000000 ? 10 : mc >= 300000 ? 12 : 8) | (fp32_of[q] & 1);
+                } else key = 2;
                 size_t g = 0;
                 while (g < groups.size() && groups[g].key != key) ++g;
                 if (g == groups.size()) { groups.push_back(Group{}); groups[g].key = key; }
@@ -857,46 +895,85 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 d_desc_c.ensure(buf.size());
                 HIPCHK(hipMemcpyAsync(d_desc_c.p, stage_c.p, buf.size(), hipMemcpyHostToDevice, st));
                 const DPiece* dp = (const DPiece*)(d_desc_c.as<char>() + op);
-                for (Group& G : groups) {
+                // independent variants run side by side: the split variant (its
+                // sweeps are driven from the host) on the caller's stream, the
+                // others on library streams forked from it and joined back after
+                auto run_group = [&](Group& G, hipStream_t gs) {
                     const DCompress* dt = (const DCompress*)(d_desc_c.as<char>() + G.off);
-                    LaunchTimer tm(LRX_K_COMPRESS, st, 0.0, G.fl);
+                    LaunchTimer tm(LRX_K_COMPRESS, gs, 0.0, G.fl);
                     if (G.key == 4)
-                        HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, st));
+                        HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, gs));
                     else if (G.key == 8 || G.key == 9) {
                         HIPCHK(launch_compress_large(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
-                                                     (G.key & 1) ? 0.01 : 0.0, 0, st));
-                    } else if (G.key >= 10) {
+                                                     (G.key & 1) ? 0.01 : 0.0, 0, gs));
+                    } else if (G.key == 12 || G.key == 13) {
+                        const int nt = (int)G.t.size();
+                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 7, gs));
+                    } else if (G.key == 10 || G.key == 11) {
                         // QRs, then sweeps of block-Jacobi rounds over all tasks until
                         // none rotates, then the singular values and V
                         const int nt = (int)G.t.size();
                         const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, st));
-                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, st));
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, st));
-                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 1, st));
-                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 2, st));
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 6, st));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, gs));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 1, gs));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 2, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 6, gs));
                         d_flags.ensure((size_t)nt * sizeof(int32_t));
                         pin_flags.ensure((size_t)nt * sizeof(int32_t));
                         const int rounds = large_rounds(G.max_c);
                         for (int sweep = 0; sweep < 40; ++sweep) {
                             for (int t = 0; t < rounds; ++t)
-                                HIPCHK(launch_large_round(dt, nt, G.max_c, t, st));
-                            HIPCHK(launch_large_flags(dt, nt, d_flags.as<int32_t>(), st));
+                                HIPCHK(launch_large_round(dt, nt, G.max_c, t, gs));
+                            HIPCHK(launch_large_flags(dt, nt, d_flags.as<int32_t>(), gs));
                             HIPCHK(hipMemcpyAsync(pin_flags.p, d_flags.p, (size_t)nt * sizeof(int32_t),
-                                                  hipMemcpyDeviceToHost, st));
+                                                  hipMemcpyDeviceToHost, gs));
                             sync();
                             const int32_t* fl = (const int32_t*)pin_flags.p;
                             bool go = false;
                             for (int q = 0; q < nt; ++q) go |= fl[q] != 0;
                             if (!go) break;
                         }
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 2, st));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 2, gs));
                     }
                     else
                         HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
-                                                   (G.key & 1) != 0, st));
+                                                   (G.key & 1) != 0, gs));
+                };
+                std::vector<hipStream_t> gsv(groups.size(), st);
+                AuxStreams* ax = groups.size() > 1 ? aux_streams() : nullptr;
+                bool used[2] = {false, false};
+                if (ax) {
+                    bool split = false;
+                    for (const Group& G : groups) split |= G.key == 10 || G.key == 11;
+                    bool keep = !split;                  // without a split variant one stays on st
+                    int j = 0;
+                    for (size_t g = 0; g < groups.size(); ++g) {
+                        if (groups[g].key == 10 || groups[g].key == 11) continue;
+                        if (keep) { keep = false; continue; }
+                        gsv[g] = ax->s[j & 1];
+                        used[j & 1] = true;
+                        ++j;
+                    }
+                    if (used[0] || used[1]) {
+                        HIPCHK(hipEventRecord(ax->fork, st));
+                        for (int k = 0; k < 2; ++k)
+                            if (used[k]) HIPCHK(hipStreamWaitEvent(ax->s[k], ax->fork, 0));
+                    }
                 }
+                for (size_t g = 0; g < groups.size(); ++g)
+                    if (gsv[g] != st) run_group(groups[g], gsv[g]);
+                for (size_t g = 0; g < groups.size(); ++g)
+                    if (gsv[g] == st) run_group(groups[g], st);
+                for (int k = 0; k < 2; ++k)
+                    if (used[k]) {
+                        HIPCHK(hipEventRecord(ax->join[k], ax->s[k]));
+                        HIPCHK(hipStreamWaitEvent(st, ax->join[k], 0));
+                    }
             }
             pin_rt.ensure(rt_bytes);
             if (rt_bytes) HIPCHK(hipMemcpyAsync(pin_rt.p, d_rt.p, rt_bytes, hipMemcpyDeviceToHost, st));
