@@ -1,0 +1,127 @@
+"""Compression of large stacked blocks (more than 64 columns) on the GPU.
+
+These blocks take other kernels than the small ones: one work-group per block
+up to 192 columns, the tall QR in 16-column panels over many work-groups for
+tall blocks (M c >= 3e5), and for c > 192 (or M c >= 1e6) the tall QR, LQ and
+Q2 in panels plus the one-sided Jacobi in block rounds over many work-groups.
+The variants of one colour step run side by side on forked streams.  The bar,
+as for the small blocks: the singular values of every stacked block (the
+truncation tails the library reports) match the FP64 oracle's SVD of its own
+stacked block (Sec. 4.3, the cut-off sigma_k >= epsilon sigma_0) to rounding
+accumulated over the levels, the truncation rule holds, GMRES reaches the true
+residual, and a batch reproduces the single factorizations bit for bit.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_1510_07363_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1510_07363_amd import lorax
+    return lorax, torch
+
+
+def _problem(kind, nx, leaf, seed=0):
+    rng = np.random.default_rng(seed)
+    if kind == "varcoef2d":
+        csr = w.diffusion2d(np.exp(w.gaussian_field_2d((nx, nx), rng, 8.0)), (nx, nx))
+        co = w.grid_coords((nx, nx))
+    elif kind == "convdiff3d":
+        csr, co = w.convdiff3d(nx), w.grid_coords((nx, nx, nx))
+    else:
+        raise KeyError(kind)
+    n = len(csr[0]) - 1
+    depth = w.tree_depth(n, leaf)
+    perm, lp = w.rcb_tree(co, depth)
+    return csr, n, perm, lp, depth, rng
+
+
+def _check_sigmas(F, Fo, eps, want):
+    """Tails of F against the oracle's singular values; returns the number of
+    compared compressions whose stacked block satisfies want(rows, cols)."""
+    top = max(c.sigma[0] for c in Fo.compressions if len(c.sigma))
+    hit = 0
+    for i, c in enumerate(Fo.compressions):
+        if len(c.sigma) == 0 or c.sigma[0] < 1e-8 * top:
+            continue
+        t = F.tails(i)
+        k = min(len(t) - 1, len(c.sigma))
+        assert np.max(np.abs(t[1:1 + k] - c.sigma[:k])) <= 1e-11 * top, (i, c.rows, c.m)
+        hit += int(want(c.rows, c.m))
+    for i, r in enumerate(F.ranks()[0]):
+        t = F.tails(i)
+        if t[0] > 0 and 1 + r < len(t):             # a full-rank block has no tail
+            assert t[1 + r] <= eps * t[0] * (1 + 1e-12)
+    assert F.stats()["max_compression_error"] < eps
+    return hit
+
+
+def test_wide_blocks_sigma_match_oracle(env):
+    """Leaf super-nodes of 256 unknowns: c = 256 > 192 takes the split path
+    (panel QRs and block-Jacobi rounds)."""
+    lx, torch = env
+    csr, n, perm, lp, depth, rng = _problem("varcoef2d", 64, 128)
+    eps = 1e-4
+    F = lx.Factor(*csr, perm, lp, depth, eps)
+    Fo = oracle.factor(*csr, perm, lp, depth, eps, check=False)
+    wide = _check_sigmas(F, Fo, eps, lambda M, c: c > 192)
+    print(f"compressions with c > 192 compared: {wide}")
+    assert wide >= 8
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n))
+    b = rng.uniform(-1, 1, (n, 2))
+    for prec in ("fp64", "mixed"):
+        Fp = F if prec == "fp64" else lx.Factor(*csr, perm, lp, depth, eps, precision="mixed")
+        x, its, rr = Fp.gmres(b, tol=1e-10, restart=30, maxit=200)
+        for k in range(b.shape[1]):
+            res = np.linalg.norm(A @ x[:, k] - b[:, k]) / np.linalg.norm(b[:, k])
+            print(f"{prec} rhs {k}: its {int(its[k])}, true residual {res:.2e}")
+            assert res <= 1e-10 and rr[k] <= 1e-10
+
+
+def test_tall_block_sigma_match_oracle(env):
+    """A 24^3 convection-diffusion grid: its top compressions stack more than
+    2,000 rows on up to 186 columns, so one takes the panel tall QR followed by
+    the one-work-group pipeline (M c >= 3e5), next to one-work-group blocks and
+    small blocks of the same colour steps on the forked streams."""
+    lx, torch = env
+    csr, n, perm, lp, depth, rng = _problem("convdiff3d", 24, 64)
+    eps = 1e-3
+    F = lx.Factor(*csr, perm, lp, depth, eps)
+    Fo = oracle.factor(*csr, perm, lp, depth, eps, check=False)
+    tall = _check_sigmas(F, Fo, eps, lambda M, c: 64 < c <= 192 and 300000 <= M * c < 1000000)
+    medium = _check_sigmas(F, Fo, eps, lambda M, c: 64 < c <= 192 and M * c < 300000)
+    print(f"tall blocks compared: {tall}, one-work-group blocks: {medium}")
+    assert tall >= 1 and medium >= 20
+
+
+def test_wide_blocks_batch_equals_single(env):
+    """A batch with wide-block and small-block systems reproduces each system
+    factored alone: ranks, tails and solves bit for bit."""
+    lx, torch = env
+    ins = [_problem("varcoef2d", 64, 128, 5), _problem("varcoef2d", 32, 16, 6), _problem("convdiff3d", 12, 64, 7)]
+    eps = 1e-4
+    for precision in ("fp64", "mixed"):
+        batch = lx.factor_batch([(*csr, perm, lp, depth) for csr, n, perm, lp, depth, _ in ins], eps,
+                                precision=precision)
+        for i, ((csr, n, perm, lp, depth, rng), Fb) in enumerate(zip(ins, batch)):
+            Fs = lx.Factor(*csr, perm, lp, depth, eps, precision=precision)
+            for a, b in zip(Fs.ranks(), Fb.ranks()):
+                assert np.array_equal(a, b), (precision, i)
+            for q in range(len(Fs.ranks()[0])):
+                assert np.array_equal(Fs.tails(q), Fb.tails(q)), (precision, i, q)
+            b = torch.from_numpy(rng.uniform(-1, 1, (2, n))).to("cuda:0")
+            xs, xb = torch.zeros_like(b), torch.zeros_like(b)
+            Fs.solve_dev(b.data_ptr(), xs.data_ptr(), 2)
+            Fb.solve_dev(b.data_ptr(), xb.data_ptr(), 2)
+            torch.cuda.synchronize()
+            assert torch.equal(xs, xb), (precision, i)
