@@ -234,47 +234,58 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
         L0.supers.push_back(id);
     }
     {
-        // (src super, dst super, local row in dst, local col in src)
-        struct Ent { int32_t src, dst, lr, lc; };
-        std::vector<Ent> ents;
-        ents.reserve((size_t)nnz);
-        for (int32_t r = 0; r < n; ++r) {
-            int32_t tr = P.pos[r];
-            int32_t sd = leaf_of[tr] >> 1;
-            int32_t lr = tr - P.nodes[sd].dof0;
-            for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-                int32_t tc = P.pos[col_idx[e]];
-                int32_t ss = leaf_of[tc] >> 1;
-                ents.push_back({ss, sd, lr, tc - P.nodes[ss].dof0});
+        // blocks of A between leaf super-nodes: for every destination super-node
+        // (its rows are consecutive tree positions) the entries of its rows are
+        // bucketed by source super-node; rows come out sorted and unique, columns
+        // are sorted and deduplicated per block; edges are then created in
+        // (source, destination) order
+        struct Grp { int32_t src, dst; std::vector<int32_t> rows, cols; };
+        std::vector<Grp> grps;
+        grps.reserve((size_t)nsl * 12);
+        std::vector<int32_t> slot(nsl, -1);               // group of a source for the current destination
+        std::vector<int32_t> touched;
+        for (int32_t sd = 0; sd < nsl; ++sd) {
+            const PNode& dn = P.nodes[L0.supers[sd]];
+            touched.clear();
+            for (int32_t lr = 0; lr < dn.static_size; ++lr) {
+                const int32_t r = perm[dn.dof0 + lr];
+                for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+                    const int32_t tc = P.pos[col_idx[e]];
+                    const int32_t ss = leaf_of[tc] >> 1;
+                    int32_t g = slot[ss];
+                    if (g < 0) {
+                        g = slot[ss] = (int32_t)grps.size();
+                        grps.push_back(Grp{ss, sd, {}, {}});
+                        touched.push_back(ss);
+                    }
+                    if (ss == sd) continue;                    // the pivot block is full
+                    Grp& G = grps[g];
+                    if (G.rows.empty() || G.rows.back() != lr) G.rows.push_back(lr);
+                    G.cols.push_back(tc - P.nodes[L0.supers[ss]].dof0);
+                }
+            }
+            for (int32_t ss : touched) {
+                Grp& G = grps[slot[ss]];
+                std::sort(G.cols.begin(), G.cols.end());
+                G.cols.erase(std::unique(G.cols.begin(), G.cols.end()), G.cols.end());
+                slot[ss] = -1;
             }
         }
-        {   // group by (src, dst): two stable counting passes (dst, then src)
-            std::vector<Ent> tmp(ents.size());
-            std::vector<int64_t> cnt((size_t)nsl + 1);
-            for (int pass = 0; pass < 2; ++pass) {
-                std::fill(cnt.begin(), cnt.end(), 0);
-                for (const Ent& x : ents) ++cnt[(pass == 0 ? x.dst : x.src) + 1];
-                for (int32_t b = 0; b < nsl; ++b) cnt[b + 1] += cnt[b];
-                for (const Ent& x : ents) tmp[cnt[pass == 0 ? x.dst : x.src]++] = x;
-                ents.swap(tmp);
-            }
-        }
-        size_t i0 = 0;
-        while (i0 < ents.size()) {
-            size_t i1 = i0;
-            while (i1 < ents.size() && ents[i1].src == ents[i0].src && ents[i1].dst == ents[i0].dst) ++i1;
+        std::vector<int32_t> order_g(grps.size());
+        for (size_t g = 0; g < grps.size(); ++g) order_g[g] = (int32_t)g;
+        std::sort(order_g.begin(), order_g.end(), [&](int32_t x, int32_t y) {
+            return grps[x].src != grps[y].src ? grps[x].src < grps[y].src : grps[x].dst < grps[y].dst;
+        });
+        for (int32_t g : order_g) {
+            Grp& G = grps[g];
             Support rows, cols;
-            if (ents[i0].src != ents[i0].dst) {
+            if (G.src != G.dst) {
                 rows.all = false; cols.all = false;
-                for (size_t k = i0; k < i1; ++k) { rows.idx.push_back(ents[k].lr); cols.idx.push_back(ents[k].lc); }
-                std::sort(rows.idx.begin(), rows.idx.end());
-                rows.idx.erase(std::unique(rows.idx.begin(), rows.idx.end()), rows.idx.end());
-                std::sort(cols.idx.begin(), cols.idx.end());
-                cols.idx.erase(std::unique(cols.idx.begin(), cols.idx.end()), cols.idx.end());
+                rows.idx = std::move(G.rows);
+                cols.idx = std::move(G.cols);
             }
-            int32_t e = B.add_edge(ents[i0].src, ents[i0].dst, rows, cols, EO_INIT);
+            int32_t e = B.add_edge(L0.supers[G.src], L0.supers[G.dst], std::move(rows), std::move(cols), EO_INIT);
             P.init_edges.push_back(e);
-            i0 = i1;
         }
         // every super-node carries a pivot block even if A has no diagonal there
         for (int32_t j = 0; j < nsl; ++j) {
