@@ -198,12 +198,19 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
 
     // ---- cluster adjacency at every level (Def. "adjacent clusters"), pattern of A and A^T
     {
+        // distinct pairs of leaf clusters joined by an entry of A, found cluster
+        // by cluster (rows of a cluster are consecutive tree positions)
         std::vector<std::pair<int32_t, int32_t>> lp;
-        for (int32_t r = 0; r < n; ++r) {
-            int32_t a = leaf_of[P.pos[r]];
-            for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-                int32_t b = leaf_of[P.pos[col_idx[e]]];
-                if (a != b) lp.push_back({std::min(a, b), std::max(a, b)});
+        std::vector<int32_t> seen((size_t)nleaf, -1);
+        for (int32_t a = 0; a < (int32_t)nleaf; ++a) {
+            for (int32_t t = leaf_ptr[a]; t < leaf_ptr[a + 1]; ++t) {
+                const int32_t r = perm[t];
+                for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+                    const int32_t b = leaf_of[P.pos[col_idx[e]]];
+                    if (b == a || seen[b] == a) continue;
+                    seen[b] = a;
+                    lp.push_back({std::min(a, b), std::max(a, b)});
+                }
             }
         }
         std::sort(lp.begin(), lp.end());
