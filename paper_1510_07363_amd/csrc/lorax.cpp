@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -49,24 +50,142 @@ double now_ms() {
 }
 
 // --------------------------------------------------------------- device memory
+// Device and pinned host blocks the library releases are kept for reuse: one
+// factorization with its solve takes and releases a few dozen blocks, and
+// hipMalloc / hipFree of large blocks cost tens of microseconds each.  A
+// released block enters the cache only after a device-wide synchronization (as
+// hipFree synchronizes), so no queued kernel or copy still uses it when it is
+// handed out again.  Sizes are rounded up (64 KiB steps to 1 MiB, then eighths
+// of an octave) so that blocks fit again; at most kCacheBytes per device and
+// kPinCacheBytes of pinned host memory are kept, and a device's cache is
+// emptied when hipMalloc reports out of memory.
+constexpr size_t kCacheBytes = (size_t)8 << 30;
+constexpr size_t kPinCacheBytes = (size_t)1 << 30;
+std::mutex g_cache_mu;
+std::map<std::pair<int, size_t>, std::vector<void*>> g_dev_cache;   // (device, bytes) -> blocks
+std::map<int, size_t> g_dev_cached;
+std::map<size_t, std::vector<void*>> g_pin_cache;
+size_t g_pin_cached = 0;
+
+size_t block_class(size_t b) {
+    const size_t step = (size_t)1 << 16;
+    if (b <= ((size_t)1 << 20)) return std::max(step, (b + step - 1) & ~(step - 1));
+    const int k = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t q = (size_t)1 << (k - 3);
+    return (b + q - 1) / q * q;
+}
+
+void cache_flush_device(int dev) {
+    std::vector<void*> ps;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto it = g_dev_cache.begin(); it != g_dev_cache.end();) {
+            if (it->first.first != dev) { ++it; continue; }
+            ps.insert(ps.end(), it->second.begin(), it->second.end());
+            it = g_dev_cache.erase(it);
+        }
+        g_dev_cached[dev] = 0;
+    }
+    for (void* q : ps) (void)hipFree(q);
+}
+
+void* dev_alloc(size_t b, size_t& got, int& dev) {
+    HIPCHK(hipGetDevice(&dev));
+    const size_t c = block_class(b);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_dev_cache.find({dev, c});
+        if (it != g_dev_cache.end() && !it->second.empty()) {
+            void* q = it->second.back();
+            it->second.pop_back();
+            g_dev_cached[dev] -= c;
+            got = c;
+            return q;
+        }
+    }
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, c);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        cache_flush_device(dev);
+        e = hipMalloc(&q, c);
+    }
+    if (e != hipSuccess)
+        fail(e == hipErrorOutOfMemory ? LRX_ENOMEM : LRX_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    got = c;
+    return q;
+}
+
+void dev_release(void* q, size_t c, int dev) {
+    if (!q) return;
+    int cur = dev;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    bool keep = false;
+    if (hipDeviceSynchronize() == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (g_dev_cached[dev] + c <= kCacheBytes) {
+            g_dev_cache[{dev, c}].push_back(q);
+            g_dev_cached[dev] += c;
+            keep = true;
+        }
+    }
+    if (!keep) (void)hipFree(q);
+    if (cur != dev) (void)hipSetDevice(cur);
+}
+
+void* pin_alloc(size_t b, size_t& got) {
+    const size_t c = block_class(b);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_pin_cache.find(c);
+        if (it != g_pin_cache.end() && !it->second.empty()) {
+            void* q = it->second.back();
+            it->second.pop_back();
+            g_pin_cached -= c;
+            got = c;
+            return q;
+        }
+    }
+    void* q = nullptr;
+    HIPCHK(hipHostMalloc(&q, c, hipHostMallocDefault));
+    got = c;
+    return q;
+}
+
+void pin_release(void* q, size_t c) {          // copies from or to it may be queued on the current device
+    if (!q) return;
+    bool keep = false;
+    if (hipDeviceSynchronize() == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (g_pin_cached + c <= kPinCacheBytes) {
+            g_pin_cache[c].push_back(q);
+            g_pin_cached += c;
+            keep = true;
+        }
+    }
+    if (!keep) (void)hipHostFree(q);
+}
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    int dev = 0;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_release(p, bytes, dev);
         p = nullptr;
         bytes = 0;
     }
     void ensure(size_t b) {          // grows; contents are not preserved
         if (b <= bytes) return;
         release();
-        size_t nb = std::max(b, (size_t)4096);
-        HIPCHK(hipMalloc(&p, nb));
-        bytes = nb;
+        size_t got = 0;
+        p = dev_alloc(std::max(b, (size_t)4096), got, dev);
+        bytes = got;
     }
     template <class T> T* as() const { return (T*)p; }
 };
@@ -77,14 +196,15 @@ struct PinBuf {
     PinBuf() = default;
     PinBuf(const PinBuf&) = delete;
     PinBuf& operator=(const PinBuf&) = delete;
-    ~PinBuf() { if (p) (void)hipHostFree(p); }
+    ~PinBuf() { pin_release(p, bytes); }
     void ensure(size_t b) {          // caller guarantees no copy from it is in flight
         if (b <= bytes) return;
-        if (p) (void)hipHostFree(p);
+        pin_release(p, bytes);
         p = nullptr;
-        size_t nb = std::max(b * 2, (size_t)1 << 16);
-        HIPCHK(hipHostMalloc(&p, nb, hipHostMallocDefault));
-        bytes = nb;
+        bytes = 0;
+        size_t got = 0;
+        p = pin_alloc(std::max(b * 2, (size_t)1 << 16), got);
+        bytes = got;
     }
 };
 
@@ -94,9 +214,10 @@ struct Arena {
     size_t used = 0;                                  // in the last chunk
     int64_t total = 0;                                // doubles handed out
     int64_t budget_bytes = 0;
+    int dev = 0;
     ~Arena() { release(); }
     void release() {
-        for (auto& c : chunks) (void)hipFree(c.first);
+        for (auto& c : chunks) dev_release(c.first, c.second * sizeof(double), dev);
         chunks.clear();
         used = 0;
         total = 0;
@@ -108,9 +229,9 @@ struct Arena {
             // factorization holds little more than it uses
             const size_t grow = std::min(std::max((size_t)total, (size_t)1 << 19), (size_t)32 << 20);
             size_t cap = std::max(n, grow);
-            double* p = nullptr;
-            HIPCHK(hipMalloc(&p, cap * sizeof(double)));
-            chunks.push_back({p, cap});
+            size_t got = 0;
+            double* p = (double*)dev_alloc(cap * sizeof(double), got, dev);
+            chunks.push_back({p, got / sizeof(double)});
             used = 0;
         }
         double* p = chunks.back().first + used;
@@ -119,11 +240,6 @@ struct Arena {
         if (budget_bytes > 0 && total * 8 > budget_bytes)
             fail(LRX_ENOMEM, "factor storage exceeds hbm_budget_bytes");
         return p;
-    }
-    int64_t reserved_bytes() const {
-        int64_t b = 0;
-        for (auto& c : chunks) b += (int64_t)c.second * 8;
-        return b;
     }
 };
 
