@@ -116,13 +116,25 @@ void* dev_alloc(size_t b, size_t& got, int& dev) {
     return q;
 }
 
+// Inside an IdleScope this thread has synchronized the device once and
+// releases only blocks that no queued work uses, so releases skip their own
+// synchronization.
+thread_local int t_idle = 0;
+struct IdleScope {
+    bool ok;
+    IdleScope() : ok(hipDeviceSynchronize() == hipSuccess) { if (ok) ++t_idle; }
+    ~IdleScope() { if (ok) --t_idle; }
+    IdleScope(const IdleScope&) = delete;
+    IdleScope& operator=(const IdleScope&) = delete;
+};
+
 void dev_release(void* q, size_t c, int dev) {
     if (!q) return;
     int cur = dev;
     (void)hipGetDevice(&cur);
     if (cur != dev) (void)hipSetDevice(dev);
     bool keep = false;
-    if (hipDeviceSynchronize() == hipSuccess) {
+    if ((t_idle > 0 && cur == dev) || hipDeviceSynchronize() == hipSuccess) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (g_dev_cached[dev] + c <= kCacheBytes) {
             g_dev_cache[{dev, c}].push_back(q);
@@ -156,7 +168,7 @@ void* pin_alloc(size_t b, size_t& got) {
 void pin_release(void* q, size_t c) {          // copies from or to it may be queued on the current device
     if (!q) return;
     bool keep = false;
-    if (hipDeviceSynchronize() == hipSuccess) {
+    if (t_idle > 0 || hipDeviceSynchronize() == hipSuccess) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (g_pin_cached + c <= kPinCacheBytes) {
             g_pin_cache[c].push_back(q);
@@ -196,12 +208,15 @@ struct PinBuf {
     PinBuf() = default;
     PinBuf(const PinBuf&) = delete;
     PinBuf& operator=(const PinBuf&) = delete;
-    ~PinBuf() { pin_release(p, bytes); }
-    void ensure(size_t b) {          // caller guarantees no copy from it is in flight
-        if (b <= bytes) return;
+    ~PinBuf() { release(); }
+    void release() {
         pin_release(p, bytes);
         p = nullptr;
         bytes = 0;
+    }
+    void ensure(size_t b) {          // caller guarantees no copy from it is in flight
+        if (b <= bytes) return;
+        release();
         size_t got = 0;
         p = pin_alloc(std::max(b * 2, (size_t)1 << 16), got);
         bytes = got;
@@ -1167,9 +1182,14 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                                                     : std::string("exactly singular pivot block"));
         r.h->stats.factor_flops = r.flops;
         r.h->t_sync_ms += t_sync;
-        r.h->ws_b.release();
-        r.h->ws_w.release();
     }
+    IdleScope idle;
+    for (FactorRun* r : runs) {
+        r->h->ws_b.release();
+        r->h->ws_w.release();
+    }
+    for (DevBuf* d : {&d_imap, &d_info, &d_desc_m, &d_desc_c, &d_desc_n, &d_rt, &d_flags}) d->release();
+    for (PinBuf* q : {&stage_m, &stage_c, &stage_n, &pin_rt, &pin_flags}) q->release();
 }
 
 // ------------------------------------------------------------------ solve program
@@ -1365,6 +1385,7 @@ void build_solve_program(lrx_handle h) {
     h->stats.solve_bytes = solve_bytes;
     if (h->solve_fp32) {               // the FP64 blocks are no longer read
         HIPCHK(hipStreamSynchronize(h->stream));
+        IdleScope idle;
         h->arena.release();
         std::fill(h->eptr.begin(), h->eptr.end(), nullptr);
     }
@@ -2182,6 +2203,7 @@ lrx_status lrx_free(lrx_handle h) {
             g_live.erase(h);
         }
         (void)hipStreamSynchronize(h->stream);
+        IdleScope idle;
         delete h;
         return LRX_OK;
     });
