@@ -2143,9 +2143,23 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
 #pragma unroll
             for (int k = 0; k < NK; ++k) acc[k] = fma(mv, iv[k ^ key], acc[k]);
         }
-        for (int o = L >> 1; o > 0; o >>= 1) {
+        // sum over the L adjacent lanes of the row (inside one 16-lane DPP row):
+        // quad swaps, then the half-row and row mirrors; every lane gets the sum
+        if (lg >= 1) {
 #pragma unroll
-            for (int k = 0; k < NK; ++k) acc[k] += __shfl_xor(acc[k], o);
+            for (int k = 0; k < NK; ++k) acc[k] += dpp_mov<0xB1>(acc[k]);
+        }
+        if (lg >= 2) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) acc[k] += dpp_mov<0x4E>(acc[k]);
+        }
+        if (lg >= 3) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) acc[k] += dpp_mov<0x141>(acc[k]);
+        }
+        if (lg >= 4) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) acc[k] += dpp_mov<0x140>(acc[k]);
         }
         if (sub == 0) {
             double y[NK];
