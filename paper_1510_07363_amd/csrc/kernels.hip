@@ -177,16 +177,46 @@ __global__ __launch_bounds__(NT) void k_compress(const DCompress* __restrict__ t
 // singular values sorted in descending order, rank = #{sigma_k >= eps sigma_0}.
 // R and V live in LDS when `lds_mat` is set (2 c^2 doubles), otherwise in the
 // task's workspace.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a DPP row; every lane receives the same value.
+template <class T>
+__device__ __forceinline__ T row16_sum(T v) {
+    v += dpp_mov<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);    // row_half_mirror
+    v += dpp_mov<0x140>(v);    // row_mirror
+    return v;
+}
+
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
+    if constexpr (G == 16) return row16_sum(v);
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
     return v;
 }
 
+// Sum over the wavefront (all 64 lanes active); every lane receives the sum.
+// DPP sums inside the four 16-lane rows, then the rows' sums through readlane.
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v = row16_sum(v);
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        t += __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * r),
+                              __builtin_amdgcn_readlane(__double2loint(v), 16 * r));
+    return t;
 }
 
 // position of value k in a descending order of sv[0..c) (ties: lower index first)
@@ -438,28 +468,6 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
 // pair, reduced with DPP row permutations.
 constexpr int NTC = 1024;
 constexpr int SEGC = NTC / WAVE;           // row segments in the QRs
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over the 16 lanes of a DPP row; every lane receives the same value.
-template <class T>
-__device__ __forceinline__ T row16_sum(T v) {
-    v += dpp_mov<0xB1>(v);     // quad_perm [1,0,3,2]
-    v += dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]
-    v += dpp_mov<0x141>(v);    // row_half_mirror
-    v += dpp_mov<0x140>(v);    // row_mirror
-    return v;
-}
 
 // Largest v over a wavefront (lowest i on ties); every lane receives (v, i).
 // DPP within rows of 16 lanes, then the four row results through readlane.
