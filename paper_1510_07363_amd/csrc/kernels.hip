@@ -471,25 +471,32 @@ constexpr int SEGC = NTC / WAVE;           // row segments in the QRs
 
 // Largest v over a wavefront (lowest i on ties); every lane receives (v, i).
 // DPP within rows of 16 lanes, then the four row results through readlane.
-template <int CTRL>
-__device__ __forceinline__ void argmax_step(double& v, int& i) {
-    const double ov = dpp_mov<CTRL>(v);
+__device__ __forceinline__ double lane_read(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+template <int CTRL, class T>
+__device__ __forceinline__ void argmax_step(T& v, int& i) {
+    const T ov = dpp_mov<CTRL>(v);
     const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
     if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
 }
 
-__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+template <class T>
+__device__ __forceinline__ void wave_argmax(T& v, int& i) {
     argmax_step<0xB1>(v, i);
     argmax_step<0x4E>(v, i);
     argmax_step<0x141>(v, i);
     argmax_step<0x140>(v, i);
-    double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
-                                __builtin_amdgcn_readlane(__double2loint(v), 0));
+    T b = lane_read(v, 0);
     int bi = __builtin_amdgcn_readlane(i, 0);
 #pragma unroll
     for (int r = 1; r < 4; ++r) {
-        const double o = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * r),
-                                          __builtin_amdgcn_readlane(__double2loint(v), 16 * r));
+        const T o = lane_read(v, 16 * r);
         const int oi = __builtin_amdgcn_readlane(i, 16 * r);
         if (o > b || (o == b && oi < bi)) { b = o; bi = oi; }
     }
@@ -531,11 +538,7 @@ __device__ void qr64(T* A, int nr, int c, int ld, bool pivot, int* perm, T* hv0,
             }
             int bi = k;
             T bv = nk;
-            for (int o = WAVE / 2; o > 0; o >>= 1) {
-                const T ov = __shfl_xor(bv, o);
-                const int oi = __shfl_xor(bi, o);
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-            }
+            wave_argmax(bv, bi);
             __syncthreads();
             if (bi != j) {
                 if (k == j)
