@@ -38,8 +38,8 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 # x 1.00); kept per (workload, precision, kernel class) and reported as the
 # roofline's traffic.
 TRAFFIC_BYTES = {
-    ("varcoef2d_256", "mixed", "compress"): 2.195e6,
-    ("varcoef2d_256", "fp64", "compress"): 2.204e6,
+    ("varcoef2d_256", "mixed", "compress"): 2.197e6,
+    ("varcoef2d_256", "fp64", "compress"): 2.207e6,
 }
 TOL = 1e-10
 RESTART = 30
