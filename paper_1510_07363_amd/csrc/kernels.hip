@@ -2357,16 +2357,17 @@ __global__ __launch_bounds__(256) void k_kry_dot(const DKry* __restrict__ sys, c
 }
 
 // sm[out_off + q] = sum over the system's chunks of part[(chunk * J) * nrhs + q], q < J nrhs
-__global__ void k_kry_reduce(const DKry* __restrict__ sys, const int32_t* __restrict__ act, int cnt,
-                             const double* __restrict__ part, int out_off) {
-    const int s = blockIdx.y;
-    if (!act[s]) return;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= cnt) return;
+// One wavefront per value q of one system: lanes take the chunks in turn, then
+// a wavefront sum; the order depends on the system's own chunks only.
+__global__ __launch_bounds__(WAVE) void k_kry_reduce(const DKry* __restrict__ sys, const int32_t* __restrict__ act,
+                                                     int cnt, const double* __restrict__ part, int out_off) {
+    const int s = blockIdx.y, q = blockIdx.x;
+    if (!act[s] || q >= cnt) return;                  // uniform over the wavefront
     const DKry& S = sys[s];
     double t = 0.0;
-    for (int c = S.chunk0; c < S.chunk0 + S.nchunk; ++c) t += part[(int64_t)c * cnt + q];
-    S.sm[out_off + q] = t;
+    for (int c = S.chunk0 + (int)threadIdx.x; c < S.chunk0 + S.nchunk; c += WAVE) t += part[(int64_t)c * cnt + q];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) S.sm[out_off + q] = t;
 }
 
 // op 0: w -= sum_{j<J} V_j h_j (h at sm[off]);  op 1: x += sum_{j<Js} Z_j y_j (y at
@@ -2704,7 +2705,7 @@ hipError_t kry_dots(const KryLaunch& L, int mode, int J, double* part, int out_o
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int cnt = J * L.nrhs;
-    hipLaunchKernelGGL(k_kry_reduce, dim3(nblocks(cnt, 64), L.nsys), dim3(64), 0, L.st, L.sys, L.act, cnt,
+    hipLaunchKernelGGL(k_kry_reduce, dim3(cnt, L.nsys), dim3(WAVE), 0, L.st, L.sys, L.act, cnt,
                        (const double*)part, out_off);
     return hipGetLastError();
 }
