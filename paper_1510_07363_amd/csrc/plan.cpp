@@ -101,6 +101,10 @@ struct Builder {
     void eliminate(int32_t v, PivotPlan& pp, ColourStep& cs) {
         pp.node = v;
         pp.e_self = out[v].find(v);
+        pp.in_nodes.reserve(in[v].v.size());
+        pp.in_edges.reserve(in[v].v.size());
+        pp.out_nodes.reserve(out[v].v.size());
+        pp.out_edges.reserve(out[v].v.size());
         for (auto& e : in[v].v) if (e.first != v) { pp.in_nodes.push_back(e.first); pp.in_edges.push_back(e.second); }
         for (auto& e : out[v].v) if (e.first != v) { pp.out_nodes.push_back(e.first); pp.out_edges.push_back(e.second); }
         // deterministic order: by node id
@@ -113,6 +117,12 @@ struct Builder {
         };
         sort_pair(pp.in_nodes, pp.in_edges);
         sort_pair(pp.out_nodes, pp.out_edges);
+        if (!empty[v]) {
+            const size_t np = pp.in_nodes.size() * pp.out_nodes.size();
+            pp.pair_in.reserve(np);
+            pp.pair_out.reserve(np);
+            pp.pair_edge.reserve(np);
+        }
         // a pivot without variables creates no fill
         for (size_t qi = 0; !empty[v] && qi < pp.out_nodes.size(); ++qi) {
             int32_t q = pp.out_nodes[qi];
@@ -390,6 +400,7 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
         for (int32_t c = 0; c < ncol; ++c) {
             ColourStep cs;
             cs.level = i; cs.colour = c;
+            cs.nodes.reserve((size_t)std::count(colour.begin(), colour.end(), c));
             for (int32_t j = 0; j < ns; ++j) {
                 if (colour[j] != c) continue;
                 NodeStep st;
