@@ -68,6 +68,8 @@ struct Builder {
         P.nodes.push_back(nd);
         out.emplace_back();
         in.emplace_back();
+        out.back().v.reserve(8);
+        in.back().v.reserve(8);
         empty.push_back(0);
         return (int32_t)P.nodes.size() - 1;
     }
@@ -350,14 +352,14 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
             }
             std::sort(red_edges.begin(), red_edges.end());
             for (int32_t e : red_edges) {
-                const PEdge E = P.edges[e];
-                int32_t su = owner[E.src], sv = owner[E.dst];
+                const int32_t esrc = P.edges[e].src, edst = P.edges[e].dst;   // add_edge may move P.edges
+                int32_t su = owner[esrc], sv = owner[edst];
                 int32_t me = B.out[su].find(sv);
                 if (me < 0) {
                     me = B.add_edge(su, sv, Support(), Support(), EO_MERGE);
                     Lv.merge_edges.push_back(me);
                 }
-                Lv.merges.push_back({e, me, (int8_t)half[E.dst], (int8_t)half[E.src]});
+                Lv.merges.push_back({e, me, (int8_t)half[edst], (int8_t)half[esrc]});
             }
             for (int32_t e : red_edges) B.drop_edge(e);
             // pivot blocks for super-nodes with no merged self edge
