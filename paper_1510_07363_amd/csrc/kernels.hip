@@ -944,8 +944,12 @@ __device__ double hh_step(double* A, int64_t ld, int nr, int ncol, int j, double
 template <int GL>
 __device__ __forceinline__ double grp_sum(double v) {
     v = row16_sum(v);
-    if (GL >= 32) v += __shfl_xor(v, 16);
-    if (GL >= 64) v += __shfl_xor(v, 32);
+    if constexpr (GL >= 32) {          // the group's DPP rows combined through readlane
+        const double lo = lane_read(v, 0) + lane_read(v, 16);
+        const double hi = lane_read(v, 32) + lane_read(v, 48);
+        if constexpr (GL >= 64) v = lo + hi;
+        else v = (threadIdx.x % WAVE) < 32 ? lo : hi;
+    }
     return v;
 }
 
