@@ -283,7 +283,8 @@ struct SolveStep {
 
 // Two library streams (with a fork and two join events) per host thread and
 // device, on which independent compress variants of one colour step run beside
-// the caller's stream.  Null if they cannot be made (then all runs on one stream).
+// the caller's stream; they are kept until the process ends.  Null if they
+// cannot be made (then all runs on one stream).
 struct AuxStreams {
     bool made = false;
     hipStream_t s[2] = {nullptr, nullptr};
