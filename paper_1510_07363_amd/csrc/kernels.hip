@@ -609,7 +609,6 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     F* sm = reinterpret_cast<F*>(sm_d);
     const int cap = cap_d * (int)(sizeof(double) / sizeof(F));
     __shared__ int s_perm[WAVE];
-    __shared__ int s_rot;
     if (M == 0 || c == 0) {
         if (tid == 0) { *T.rank_out = 0; T.tails[0] = 0.0; }
         return;
@@ -745,8 +744,13 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
         for (int t = 0; t < SEGC; ++t) fro += s_fro[t];
         const F tiny2 = (F)(81.0 * (double)u * (double)u * fro);
         constexpr int EPL = WAVE / 16;             // elements per lane (c <= 64)
+        // a sweep whose rotations all had |gamma| <= sqrt(tol) sqrt(alpha beta)
+        // ends the iteration: by the quadratic convergence of the sweeps the
+        // next one would only rotate below the tol level, so it is not run
+        const F tol_hi = sqrt(tol);
+        __shared__ int s_big;
         for (int sweep = 0; sweep < 40; ++sweep) {
-            if (tid == 0) s_rot = 0;
+            if (tid == 0) s_big = 0;
             __syncthreads();
             for (int t = 0; t < n2 - 1; ++t) {
                 if (g < npair) {
@@ -783,14 +787,14 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
                                 W[r + q * ldc] = sn * wp + cs * wq;
                             }
                         }
-                        if (gl == 0) s_rot = 1;
+                        if (gl == 0 && fabs(ga) > tol_hi * sqrt(al * be)) s_big = 1;
                     }
                 }
                 __syncthreads();
             }
-            const int rot = s_rot;
+            const int big = s_big;
             __syncthreads();
-            if (!rot) break;
+            if (!big) break;
         }
     }
     // ---- singular values, order, rank, V = P W
