@@ -39,7 +39,7 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
 # roofline's traffic.
 TRAFFIC_BYTES = {
     ("varcoef2d_256", "mixed", "compress"): 2.197e6,
-    ("varcoef2d_256", "fp64", "compress"): 2.207e6,
+    ("varcoef2d_256", "fp64", "compress"): 2.208e6,
 }
 TOL = 1e-10
 RESTART = 30
