@@ -957,9 +957,11 @@ __device__ __forceinline__ double grp_sum(double v) {
     return v;
 }
 
+// Returns 0 (no rotation), 1 (a rotation with |gamma| <= tol_hi sqrt(alpha
+// beta)) or 2 (a larger one).
 template <int GL, int E>
-__device__ bool jac_pair(double* __restrict__ cp, double* __restrict__ cq, double* __restrict__ wp,
-                         double* __restrict__ wq, int kk, int c, int gl, double tol, double tiny2) {
+__device__ int jac_pair(double* __restrict__ cp, double* __restrict__ cq, double* __restrict__ wp,
+                        double* __restrict__ wq, int kk, int c, int gl, double tol, double tol_hi, double tiny2) {
     constexpr int SPAN = GL * E;
     double xp[E], xq[E];
     double al = 0.0, be = 0.0, ga = 0.0;
@@ -980,7 +982,8 @@ __device__ bool jac_pair(double* __restrict__ cp, double* __restrict__ cq, doubl
     al = grp_sum<GL>(al);
     be = grp_sum<GL>(be);
     ga = grp_sum<GL>(ga);
-    if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be)) || al <= tiny2 || be <= tiny2) return false;
+    if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al * be)) || al <= tiny2 || be <= tiny2) return 0;
+    const int kind = fabs(ga) > tol_hi * sqrt(al * be) ? 2 : 1;
     const double zeta = (be - al) / (2.0 * ga);
     const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -1020,29 +1023,31 @@ __device__ bool jac_pair(double* __restrict__ cp, double* __restrict__ cq, doubl
             }
         }
     }
-    return true;
+    return kind;
 }
 
 // A sweep round of the parallel ordering: pair i of round t joins columns
 // (t + i) mod (n2 - 1) and (t - i) mod (n2 - 1), pair 0 taking column n2 - 1.
 template <int GL, int E>
 __device__ void jac_round(double* X, double* W, int64_t ldc, int kk, int c, int n2, int t, double tol,
-                          double tiny2, int* s_rot) {
+                          double tol_hi, double tiny2, int* s_big) {
     const int g = threadIdx.x / GL, gl = threadIdx.x % GL;
     for (int pi = g; pi < n2 / 2; pi += NTL / GL) {
         const int a = (t + pi) % (n2 - 1);
         const int b = pi == 0 ? n2 - 1 : (t - pi + n2 - 1) % (n2 - 1);
         const int pp = a < b ? a : b, qq = a < b ? b : a;
         if (qq >= kk) continue;                  // uniform over the group
-        if (jac_pair<GL, E>(X + pp * ldc, X + qq * ldc, W + pp * ldc, W + qq * ldc, kk, c, gl, tol, tiny2) &&
+        if (jac_pair<GL, E>(X + pp * ldc, X + qq * ldc, W + pp * ldc, W + qq * ldc, kk, c, gl, tol, tol_hi,
+                            tiny2) == 2 &&
             gl == 0)
-            *s_rot = 1;
+            *s_big = 1;
     }
 }
 
 // State kept in hv after X, A2, W and the panel scratch (c^2 each) between the
 // launches of the split form: the pivot order (c values) and a header.
-enum { LH_KK = 0, LH_SCALE, LH_REST2, LH_TOL, LH_TINY2, LH_ROT, LH_DONE, LH_N };
+enum { LH_KK = 0, LH_SCALE, LH_REST2, LH_TOL, LH_TINY2, LH_ROT, LH_DONE, LH_BIG, LH_N };
+static_assert(LH_N <= 8, "the header has 8 doubles");
 constexpr int KK_BLK = 8;                    // columns per block of the multi-work-group Jacobi
 constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold in LDS (16 x 1150 doubles)
 
@@ -1255,7 +1260,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes.
     // In mode 1 it runs here only when L is too tall for the block rounds.
     const double u = 1.1102230246251565e-16;
-    const double tol = 3.6 * u * (double)kk;
+    const double tol = 3.6 * u * (double)kk, tol_hi = sqrt(tol);
     double f = 0.0;
     for (int e = tid; e < kk * kk; e += NTL) {
         const double x = X[(e % kk) + (e / kk) * ldc];
@@ -1273,19 +1278,22 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
             hdr[LH_TOL] = tol;
             hdr[LH_TINY2] = tiny2;
             hdr[LH_ROT] = 0.0;
+            hdr[LH_BIG] = 0.0;
             hdr[LH_DONE] = (inline_jacobi || kk <= 1) ? 1.0 : 0.0;
         }
     }
     if (kk > 1 && inline_jacobi) {
         const int n2 = kk + (kk & 1);
+        // a sweep without a rotation above sqrt(tol) sqrt(alpha beta) ends it
+        // (the next would only rotate below the tol level); s_rot holds that flag
         for (int sweep = 0; sweep < 40; ++sweep) {
             if (tid == 0) s_rot = 0;
             __syncthreads();
             for (int t = 0; t < n2 - 1; ++t) {
-                if (kk <= 128) jac_round<16, 8>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
-                else if (kk <= 256) jac_round<16, 16>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
-                else if (kk <= 512) jac_round<32, 16>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
-                else jac_round<64, 16>(X, W, ldc, kk, c, n2, t, tol, tiny2, &s_rot);
+                if (kk <= 128) jac_round<16, 8>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
+                else if (kk <= 256) jac_round<16, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
+                else if (kk <= 512) jac_round<32, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
+                else jac_round<64, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
                 __syncthreads();
             }
             const int rot = s_rot;
@@ -1499,19 +1507,19 @@ __global__ __launch_bounds__(NTL) void k_large_round(const DCompress* __restrict
     const int a = (t + pi) % (nb2 - 1);
     const int b = pi == 0 ? nb2 - 1 : (t - pi + nb2 - 1) % (nb2 - 1);
     if (a >= nbk || b >= nbk) return;                           // the dummy block
-    const double tol = hdr[LH_TOL], tiny2 = hdr[LH_TINY2];
+    const double tol = hdr[LH_TOL], tiny2 = hdr[LH_TINY2], tol_hi = sqrt(tol);
     double* X = T.hv;
     double* W = T.hv + 2 * (size_t)c * c;
     const int64_t ldc = c;
     extern __shared__ double sx[];                              // 16 columns of L, ld kk
     __shared__ double sq[16 * 16];
     __shared__ int s_col[16];
-    __shared__ int s_rot;
+    __shared__ int s_rot, s_big;
     const int na = min(KK_BLK, kk - a * KK_BLK), nbb = min(KK_BLK, kk - b * KK_BLK);
     const int ncol = na + nbb;
     if (tid < 16) s_col[tid] = tid < na ? a * KK_BLK + tid : (tid < ncol ? b * KK_BLK + (tid - na) : -1);
     if (tid < 256) sq[tid] = (tid % 16 == tid / 16) ? 1.0 : 0.0;
-    if (tid == 0) s_rot = 0;
+    if (tid == 0) { s_rot = 0; s_big = 0; }
     __syncthreads();
     for (int e = tid; e < ncol * kk; e += NTL) {
         const int sl_ = e / kk, r = e - sl_ * kk;
@@ -1549,7 +1557,10 @@ __global__ __launch_bounds__(NTL) void k_large_round(const DCompress* __restrict
                         sq[p * 16 + lane] = cs * x - sn * y;
                         sq[q * 16 + lane] = sn * x + cs * y;
                     }
-                    if (lane == 0) s_rot = 1;
+                    if (lane == 0) {
+                        s_rot = 1;
+                        if (fabs(ga) > tol_hi * sqrt(al * be)) s_big = 1;
+                    }
                 }
             }
         }
@@ -1574,19 +1585,25 @@ __global__ __launch_bounds__(NTL) void k_large_round(const DCompress* __restrict
             W[r + s_col[s2] * ldc] = acc;
         }
     }
-    if (tid == 0) const_cast<double*>(hdr)[LH_ROT] = 1.0;
+    if (tid == 0) {
+        const_cast<double*>(hdr)[LH_ROT] = 1.0;
+        if (s_big) const_cast<double*>(hdr)[LH_BIG] = 1.0;
+    }
 }
 
-// End of a sweep of the block rounds: out[task] = 1 if the task rotated during
-// the sweep (it goes on), else the task is marked done.
+// End of a sweep of the block rounds: out[task] = 1 if the task made a rotation
+// with |gamma| > sqrt(tol) sqrt(alpha beta) during the sweep (it goes on), else
+// the task is marked done: by the quadratic convergence of the sweeps the next
+// one would only rotate below the tol level.
 __global__ void k_large_flags(const DCompress* __restrict__ tasks, int n, int32_t* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const DCompress T = tasks[i];
     if (T.M == 0 || T.c == 0) { out[i] = 0; return; }
     double* hdr = T.hv + 4 * (size_t)T.c * T.c + T.c;
-    const int go = hdr[LH_DONE] == 0.0 && hdr[LH_ROT] != 0.0;
+    const int go = hdr[LH_DONE] == 0.0 && hdr[LH_BIG] != 0.0;
     hdr[LH_ROT] = 0.0;
+    hdr[LH_BIG] = 0.0;
     if (!go) hdr[LH_DONE] = 1.0;
     out[i] = go;
 }
