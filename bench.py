@@ -306,7 +306,7 @@ def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "single-GPU implementation: --gpus must be 1"}))
         sys.exit(2)
     import torch
     if args.copy_bytes:

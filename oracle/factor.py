@@ -24,7 +24,7 @@ Steps (Sec. 4):
                   creating the edge when absent (Sec. 2.2); v's edges are then
                   frozen as factor blocks (Sec. 4.4).
 
-Readings where the paper leaves a choice (each one stated in the design notes):
+Readings where the paper leaves a choice:
   * truncation: keep sigma_k with sigma_k / sigma_0 >= epsilon (eqn. cutOff1),
     sigma_0 the largest singular value of this node's stacked B; sigma_0 = 0 or
     no well-separated neighbour gives rank 0; epsilon = 0 keeps every singular

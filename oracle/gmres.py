@@ -1,7 +1,7 @@
 """Restarted GMRES with the hierarchical solve as preconditioner (Sec. 6.2).
 
 The paper solves the left-preconditioned system (A~ A x = A~ b, eqn.
-GMRES_residual).  This build's reading (stated in the design notes) uses right
+GMRES_residual).  The reading taken here uses right
 preconditioning in its flexible form (FGMRES: the preconditioned vectors z_j
 are kept, x = x_0 + Z y), restart m, x_0 = 0, modified Gram-Schmidt and Givens
 rotations; a cycle ends when the Arnoldi estimate of the residual reaches

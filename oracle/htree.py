@@ -10,7 +10,7 @@ Follows Sec. 3 of the paper:
     clusters in the adjacency graph of the coarser partitioning; well-separated
     means distance > 1 (Def. "distance of nodes", Cor. "well-separated").
 
-The colouring is this build's reading of the freedom of elimination order the
+The colouring is the reading taken here of the freedom of elimination order the
 paper grants (Sec. 1, last paragraphs; Sec. 7): at each level the super-nodes
 are greedily coloured (ascending cluster index, smallest free colour) so that
 two clusters of one colour are at distance >= 3 in the adjacency graph of
