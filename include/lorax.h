@@ -22,6 +22,10 @@
  *     them as soon as the call returns.  Device pointers (the *_dev calls) are
  *     HBM allocations of the caller on the current HIP device.
  *   - A handle owns all device memory it allocates and releases it in lrx_free.
+ *     Released blocks (up to 8 GiB per device, and 1 GiB of pinned host
+ *     memory) stay with the library for reuse by later handles until the
+ *     process ends; a failed allocation returns them to HIP and retries.
+ *     A release waits for all work queued on the device, as hipFree does.
  *     Solves on one handle may run concurrently on different streams only if
  *     each stream has its own handle; calls on one handle are not thread-safe.
  *   - Matrices are CSR, 0-based, int64 row pointers, int32 column indices,
@@ -217,8 +221,9 @@ lrx_status lrx_gmres_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, co
  * work still running on the old stream.  Errors: LRX_EINVAL (bad handle). */
 lrx_status lrx_set_stream(lrx_handle h, void* stream);
 
-/* Releases every resource of the handle.  NULL is accepted.  A handle that was
- * already freed gives LRX_EINVAL. */
+/* Releases every resource of the handle (its device blocks go to the library's
+ * reuse cache after a device-wide synchronization).  NULL is accepted.  A
+ * handle that was already freed gives LRX_EINVAL. */
 lrx_status lrx_free(lrx_handle h);
 
 /* Fills *s with the counters of the factorization. */
