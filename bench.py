@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
-FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (vector and dense matrix)
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 # HBM bytes per launch of the dominant kernel class, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE over every dispatch of that kernel in this bench (each counter scaled by
 # what it reads for a plain device copy of known size: FETCH_SIZE x 2.00, WRITE_SIZE
@@ -55,6 +56,10 @@ def parse():
                     help="precision of the reported value; the other one is measured too and "
                          "reported in detail")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_1510_07363_amd", "tune_mi355x.json"),
+                    help="launch shapes measured by paper_1510_07363_amd.autotune (read before timing)")
+    ap.add_argument("--no-bf16-trial", action="store_true",
+                    help="skip the BF16-projection trial run (LRX_MIXED_BF16)")
     ap.add_argument("--batch-group", type=int, default=32,
                     help="systems per lrx_factor_batch call in the batch256 workload")
     ap.add_argument("--cpu-sample-side", type=int, default=128,
@@ -70,37 +75,66 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(workload, side):
-    """Oracle (plain FP64 NumPy/SciPy) on the same recipe at a smaller grid;
-    the rate is scaled to the full size by the unknown count (the method's cost
-    is linear in n for a fixed leaf size)."""
+def blas_info():
+    """BLAS vendor and thread count of the oracle's NumPy."""
+    vendor = "unknown"
+    try:
+        cfg = np.show_config(mode="dicts")
+        bl = cfg.get("Build Dependencies", {}).get("blas", {})
+        vendor = f"{bl.get('name', '?')} {bl.get('version', '')}".strip()
+    except Exception:
+        pass
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        for d in threadpool_info():
+            if d.get("user_api") == "blas":
+                threads = d.get("num_threads")
+                vendor = f"{d.get('internal_api', vendor)} {d.get('version', '')}".strip()
+                break
+    except Exception:
+        pass
+    return vendor, threads
+
+
+def cpu_baseline(workload, side, repeats=3):
+    """Oracle (plain FP64 NumPy/SciPy) on the same recipe at a smaller grid,
+    median of `repeats` runs; the rate is scaled to the full size by the unknown
+    count (the method's cost is linear in n for a fixed leaf size)."""
     import oracle
     from paper_1510_07363_amd import workloads
     full = workloads.make_config(workload)
     p = workloads.make_config(workload, size=side)
     A = p.scipy()
-    t0 = time.perf_counter()
-    F = oracle.factor(p.row_ptr, p.col_idx, p.val, p.perm, p.leaf_ptr, p.depth, p.epsilon,
-                      check=False)
-    t1 = time.perf_counter()
-    its = []
-    for k in range(p.rhs.shape[1]):
-        out = oracle.fgmres(A, lambda v: oracle.solve(F, v), p.rhs[:, k], tol=TOL,
-                            restart=RESTART, maxit=500)
-        its.append(out["iters"])
-    t2 = time.perf_counter()
+    runs = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        F = oracle.factor(p.row_ptr, p.col_idx, p.val, p.perm, p.leaf_ptr, p.depth, p.epsilon,
+                          check=False)
+        t1 = time.perf_counter()
+        its = []
+        for k in range(p.rhs.shape[1]):
+            out = oracle.fgmres(A, lambda v: oracle.solve(F, v), p.rhs[:, k], tol=TOL,
+                                restart=RESTART, maxit=500)
+            its.append(out["iters"])
+        t2 = time.perf_counter()
+        runs.append((t2 - t0, t1 - t0, t2 - t1, its))
+    runs.sort(key=lambda r: r[0])
+    t_all, t_fac, t_gm, its = runs[len(runs) // 2]
     scale = full.n / p.n
-    t_full = (t2 - t0) * scale
+    t_full = t_all * scale
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         threads = os.cpu_count()
+    vendor, blas_threads = blas_info()
     return {"value": p.rhs.shape[1] / t_full, "unit": "solves/s", "cores": threads,
             "kind": "oracle",
-            "sample": (f"{workload} recipe on a {side}x{side} grid (n={p.n}, depth {p.depth}), "
-                       f"factor {t1 - t0:.1f}s + FGMRES(30) of {p.rhs.shape[1]} RHS "
-                       f"{t2 - t1:.1f}s (iters {its}); rate scaled by n ratio {scale:.1f} "
-                       f"to n={full.n}")}
+            "blas": vendor, "blas_threads": blas_threads,
+            "sample": (f"{workload} recipe on a {side}x{side} grid (n={p.n}, depth {p.depth}), median of "
+                       f"{repeats} runs (totals {[round(r[0], 2) for r in runs]} s): factor {t_fac:.1f}s + "
+                       f"FGMRES(30) of {p.rhs.shape[1]} RHS {t_gm:.1f}s (iters {its}); rate scaled by n ratio "
+                       f"{scale:.1f} to n={full.n}")}
 
 
 def roofline(timing, dom, precision="fp64"):
@@ -119,12 +153,21 @@ def roofline(timing, dom, precision="fp64"):
     else:
         per_launch = d["flops"] / max(d["launches"], 1)
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        peak = FP32_PEAK_TFLOPS if (dom == "compress" and precision == "mixed") else FP64_PEAK_TFLOPS
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        # the compression's arithmetic runs on the vector ALUs (FP32 in mixed
+        # precision); the Schur and projection products on the matrix cores
+        # (FP64 MFMA, or FP32 MFMA in mixed precision: same published peaks)
+        # (the pivot inverses of factor_node stay FP64 in every mode)
+        mixed = precision in ("mixed", "mixed_bf16") and dom in ("compress", "schur", "project")
+        peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+        if dom == "project" and precision == "mixed_bf16":
+            peak = BF16_MFMA_PEAK_TFLOPS
+        bound = "mfma" if dom in ("schur", "project") else "alu"
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = d["launches"]
+    roof["algorithmic_bytes_per_launch"] = d["bytes"] / max(d["launches"], 1)
     return roof
 
 
@@ -268,18 +311,26 @@ def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
     nrhs = p.rhs.shape[1]
     state = {}
 
+    state["t_gmres"] = []
+
     def step():
         F = lorax.Factor(p.row_ptr, p.col_idx, None, p.perm, p.leaf_ptr, p.depth, p.epsilon,
                          stream=sptr, val_dev=val_d.data_ptr(), precision=precision)
+        tg = time.perf_counter()
         its, rr, st = F.gmres_dev(b_d.data_ptr(), x_d.data_ptr(), nrhs, tol=TOL,
                                   restart=RESTART, maxit=500)
+        torch.cuda.current_stream().synchronize()
+        state["t_gmres"].append(time.perf_counter() - tg)
         if st != lorax.LRX_OK or float(np.max(rr)) > TOL:
             raise RuntimeError(f"GMRES did not reach {TOL}: status {st}, relres {rr}")
         state["its"], state["rr"], state["stats"] = its, rr, F.stats()
         F.free()
 
     T, probe, roof = timed_steps(args, lorax, torch, step, precision)
+    t_gmres = state["t_gmres"][-args.steps:]
     roof["traffic"] = TRAFFIC_BYTES.get((args.workload, precision, roof["kernel"]))
+    if roof["traffic"]:
+        roof["traffic_over_algorithmic"] = roof["traffic"] / max(roof["algorithmic_bytes_per_launch"], 1.0)
     # independent check of the last solution
     A = p.scipy()
     X = x_d.cpu().numpy().T
@@ -292,7 +343,9 @@ def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
         "value": nrhs * args.steps / T,
         "roofline": roof,
         "X": X,
-        "detail": {"gmres_iters": [int(i) for i in state["its"]],
+        "detail": {"steady_state_solves_per_s": nrhs * len(t_gmres) / sum(t_gmres),
+                   "t_gmres_ms": 1e3 * float(np.median(t_gmres)),
+                   "gmres_iters": [int(i) for i in state["its"]],
                    "true_relres_max": float(res.max()),
                    "t_factor_ms": st["t_factor_ms"], "t_plan_ms": st["t_plan_ms"],
                    "t_factor_sync_ms": st["t_sync_ms"], "t_solve_prog_ms": st["t_solve_prog_ms"],
@@ -326,17 +379,25 @@ def main():
         return main_serve(args, torch, lorax, workloads)
     p = workloads.make_config(args.workload)
     nrhs = p.rhs.shape[1]
-    stream = torch.cuda.current_stream()
+    # a non-blocking stream of the default priority: the library captures the
+    # GMRES preconditioner into a HIP graph there (never on the null stream)
+    stream = torch.cuda.Stream()
     sptr = stream.cuda_stream
     val_d = torch.from_numpy(p.val).to("cuda:0")
     b_d = torch.from_numpy(np.ascontiguousarray(p.rhs.T)).to("cuda:0")      # column-major n x nrhs
     x_d = torch.zeros_like(b_d)
     torch.cuda.synchronize()
 
+    from paper_1510_07363_amd import autotune
     other = "fp64" if args.precision == "mixed" else "mixed"
-    runs = {}
-    for prec in (other, args.precision):          # the reported precision is timed last
-        runs[prec] = measure(args, p, lorax, torch, prec, sptr, val_d, b_d, x_d)
+    runs, tuned = {}, {}
+    order = [other, args.precision]
+    if not args.no_bf16_trial:
+        order = ["mixed_bf16"] + order
+    for prec in order:                              # the reported precision is timed last
+        tuned[prec] = autotune.load(args.tune_file, "fp64" if prec == "fp64" else "mixed", lorax)
+        with torch.cuda.stream(stream):
+            runs[prec] = measure(args, p, lorax, torch, prec, sptr, val_d, b_d, x_d)
     main_run, other_run = runs[args.precision], runs[other]
     # error of the reported solutions against the other precision's (both at 1e-10 residual)
     diff = np.linalg.norm(main_run["X"] - other_run["X"], axis=0) / np.linalg.norm(other_run["X"], axis=0)
@@ -361,8 +422,18 @@ def main():
         "detail": dict(main_run["detail"], **{
             other: {"value": other_run["value"], "ms_per_step": other_run["ms_per_step"],
                     "roofline": other_run["roofline"], **other_run["detail"]},
-            f"rel_diff_vs_{other}_solution_max": float(diff.max())}),
+            f"rel_diff_vs_{other}_solution_max": float(diff.max()),
+            "tune": tuned.get(args.precision) or lorax.tune_get()}),
     }
+    if "mixed_bf16" in runs:
+        rb = runs["mixed_bf16"]
+        ref = runs["fp64"]["X"]
+        db = np.linalg.norm(rb["X"] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        line["detail"]["mixed_bf16_trial"] = {
+            "value": rb["value"], "ms_per_step": rb["ms_per_step"],
+            "gmres_iters": rb["detail"]["gmres_iters"], "true_relres_max": rb["detail"]["true_relres_max"],
+            "rel_diff_vs_fp64_solution_max": float(db.max()),
+            "note": "projection B V on BF16 operands (FP32 accumulation); compression bound not claimed"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_side)
     print(json.dumps(line), flush=True)
@@ -466,8 +537,12 @@ def main_serve(args, torch, lorax, workloads):
 def main_batch(args, torch, lorax, workloads):
     probs = workloads.make_batch()
     print(f"[batch] {len(probs)} systems generated, n = {sum(p.n for p in probs)}", file=sys.stderr, flush=True)
-    sptr = torch.cuda.current_stream().cuda_stream
-    main_run = measure_batch(args, probs, lorax, torch, args.precision, sptr)
+    from paper_1510_07363_amd import autotune
+    stream = torch.cuda.Stream()                 # non-blocking: GMRES replays its preconditioner as a graph
+    tuned = autotune.load(args.tune_file, "fp64" if args.precision == "fp64" else "mixed", lorax)
+    with torch.cuda.stream(stream):
+        main_run = measure_batch(args, probs, lorax, torch, args.precision, stream.cuda_stream)
+    main_run["detail"]["tune"] = tuned or lorax.tune_get()
     nrhs = probs[0].rhs.shape[1]
     line = {
         "metric": "factor+GMRES solves/s at 1e-10 resid",

@@ -50,13 +50,23 @@ typedef enum {
     LRX_EBUSY = 6       /* reserved */
 } lrx_status;
 
-/* LRX_FP64: every step in FP64.
- * LRX_MIXED: the compression's reduced QRs and Jacobi SVD run in FP32 when
- * epsilon >= 1e-5 (FP64 below), and the solve reads FP32 copies of the stored
- * off-diagonal blocks (the FP64 factor is released after factorization); pivot
- * inverses (computed and stored), Schur updates, vectors, accumulation in the
- * solve and GMRES stay FP64, so GMRES refines the result to its FP64 tolerance. */
-typedef enum { LRX_FP64 = 0, LRX_MIXED = 1 } lrx_precision;
+/* LRX_FP64: every step in FP64 (products on FP64 matrix cores).
+ * LRX_MIXED: when epsilon >= 1e-5 (FP32 resolves the cut-off), the compression's
+ * reduced QRs and Jacobi SVD run in FP32, and the Schur-complement GEMMs and
+ * the projection B V of the compression take FP32 operands with FP32
+ * accumulation on the matrix cores (their results update FP64 blocks); the
+ * solve reads FP32 copies of the stored off-diagonal blocks (the FP64 factor is
+ * released after factorization).  Pivot inverses (computed and stored in
+ * FP64), W_k = S^-1 Mat(k->s), vectors, accumulation in the solve and GMRES stay
+ * FP64, so GMRES refines the result to its FP64 tolerance.  Below 1e-5 the
+ * factorization runs as in LRX_FP64 and only the solve reads FP32 copies.
+ * LRX_MIXED_BF16: the BF16 trial of the compression GEMMs: as LRX_MIXED, with
+ * the projection B V of every compression on BF16 operands (FP32
+ * accumulation).  V stays accurate, but [R; Q] = B V carries BF16 input
+ * rounding (about 2^-9 relative), so ||B - [R; Q] V^T||_2 <= epsilon ||B||_2
+ * no longer holds for epsilon below that level; GMRES still refines the result
+ * to its tolerance, with more iterations. */
+typedef enum { LRX_FP64 = 0, LRX_MIXED = 1, LRX_MIXED_BF16 = 2 } lrx_precision;
 typedef enum { LRX_COLORED = 0, LRX_NATURAL = 1 } lrx_order;
 typedef enum { LRX_SVD = 0, LRX_RRQR = 1 } lrx_compress;
 
@@ -116,6 +126,14 @@ typedef struct {
     double t_factor_ms;            /* whole lrx_factor call */
     double t_sync_ms;              /* host time blocked on the stream inside lrx_factor */
     double t_solve_prog_ms;        /* host compilation of the solve sweeps */
+    /* appended fields */
+    int64_t device_bytes;          /* device memory the handle holds now: factor storage (arena chunk
+                                      capacities), solve programs, resident A, and the solve / GMRES
+                                      workspaces it has grown to (they grow with nrhs and restart) */
+    double flops_compress;         /* factor_flops by operation: stacked QRs + truncated SVD / RRQR */
+    double flops_pivot;            /* pivot inverses of super-nodes and black nodes */
+    double flops_schur;            /* Schur-complement products, W_k = S^-1 Mat(k->v) included */
+    double flops_project;          /* projection [R; Q] = B V */
 } lrx_stats_t;
 
 /* Symbolic counts, computed on the host without any device call. */
@@ -151,7 +169,8 @@ lrx_status lrx_factor_dev(const lrx_csr* A, const double* val_dev, const lrx_tre
  * and stream).  The symbolic plans run on host threads; the numeric level loops
  * of all systems advance in lock-step over (height above the leaves, colour):
  * each kernel of a step is one launch over the nodes of every system with a
- * step there (super-nodes of one colour are independent, Sec. 3.3, and distinct
+ * step there (super-nodes of one colour are independent by Thm. "preservation of sparsity",
+ * Sec. 5, and distinct
  * systems share nothing).  On success out[i] is the handle of system i and
  * equals the handle lrx_factor gives for that system alone (the solve results
  * are bitwise the same).  The batch succeeds or fails as a whole: on any error
@@ -182,7 +201,9 @@ lrx_status lrx_solve_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, co
 
 /* GMRES(restart) with the solve as right preconditioner, x_0 = 0, for nrhs
  * right-hand sides (host, column-major, leading dimension n).  A must be the
- * matrix the handle was factored from (n and nnz are checked).  Stops each
+ * matrix the handle was factored from: its pattern and values are compared
+ * entry for entry with the handle's resident copy (read back from the device),
+ * and any difference gives LRX_EINVAL (the products use that copy).  Stops each
  * right-hand side when its true relative residual ||b - A x|| / ||b|| <= tol.
  * iters[k] and relres[k] (nrhs entries each, may be NULL) receive the
  * iteration count and final true relative residual.  Returns LRX_ENOCONV if any
@@ -200,7 +221,7 @@ lrx_status lrx_gmres_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double
 
 /* Batched form of lrx_gmres_dev: k distinct handles on one device, nrhs
  * right-hand sides each, b_dev[i] and x_dev[i] n_i x nrhs column-major in HBM.
- * The k FGMRES iterations (Sec. 4.2) run in lock-step on the stream of hs[0]:
+ * The k FGMRES iterations (Sec. 6.2) run in lock-step on the stream of hs[0]:
  * each vector operation is one launch over the rows of every system still
  * iterating, the preconditioner one sweep launch per (level, colour) step over
  * the nodes of all of them, and the Hessenberg columns of all systems cross to
@@ -215,6 +236,17 @@ lrx_status lrx_gmres_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, co
                                double* const* x_dev, double tol, int32_t restart, int32_t maxit,
                                int32_t* iters, double* relres);
 
+/* lrx_gmres_batch_dev from an initial guess: on entry x_dev[i] holds x_0 of
+ * every right-hand side of system i (column-major, as on exit).  The relative
+ * residual is still ||b - A x|| / ||b||; a right-hand side with b = 0 returns
+ * x = 0.  A caller can so run a few restart cycles per call (maxit = one cycle)
+ * and continue unconverged right-hand sides in a later call, next to new ones
+ * (the serving loop admits requests at cycle boundaries this way).  Other
+ * arguments, results and errors as lrx_gmres_batch_dev. */
+lrx_status lrx_gmres_batch_dev_x0(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                                  double* const* x_dev, double tol, int32_t restart, int32_t maxit,
+                                  int32_t* iters, double* relres);
+
 /* Moves the handle to another HIP stream (NULL: the null stream): solves and
  * GMRES calls on it are enqueued there from now on, so a server can factor on
  * one stream while it solves on another.  The caller orders the switch with any
@@ -225,6 +257,13 @@ lrx_status lrx_set_stream(lrx_handle h, void* stream);
  * reuse cache after a device-wide synchronization).  NULL is accepted.  A
  * handle that was already freed gives LRX_EINVAL. */
 lrx_status lrx_free(lrx_handle h);
+
+/* Releases the handle's solve and GMRES workspaces (extended vectors, Krylov
+ * basis, batch tables); the next solve or GMRES call grows them again.  The
+ * factorization stays resident.  Waits for the handle's stream.  A server
+ * trims idle handles to keep their device footprint (lrx_stats device_bytes)
+ * at the factor itself.  Errors: LRX_EINVAL (bad handle). */
+lrx_status lrx_trim(lrx_handle h);
 
 /* Fills *s with the counters of the factorization. */
 lrx_status lrx_stats(lrx_handle h, lrx_stats_t* s);
@@ -258,6 +297,7 @@ typedef enum {
     LRX_K_SOLVE_BWD = 3,      /* SolveU sweep of one colour step (Algorithm 4) */
     LRX_K_SPMV = 4,           /* A times the preconditioned vectors (GMRES) */
     LRX_K_SCHUR = 5,          /* Schur-complement products of Eliminate(s), Eliminate(b) (Sec. 2.2) */
+    LRX_K_PROJECT = 6,        /* projection [R; Q] = B V of the compressed blocks (Sec. 4.3) */
     LRX_K_CLASSES = 8
 } lrx_kernel_class;
 
@@ -274,6 +314,31 @@ typedef struct {
 
 void lrx_timing_enable(int32_t class_mask);
 lrx_status lrx_timing_read(lrx_timing_t* t, int32_t reset);
+
+/* Launch shapes of the hot kernels, process-wide.  The library starts with
+ * defaults; a tuner measures the alternatives on the device and a caller sets
+ * the winners once, before factorizations and solves (setting them while calls
+ * run on other threads races).  Results depend on these shapes only through
+ * rounding order (gemm_kc: K blocking of the products; compress_nt_*: row
+ * segments of the compression's QRs).  Errors: LRX_EINVAL for values out of
+ * range. */
+typedef struct {
+    int32_t gemm_kc;          /* K chunk staged in LDS by the MFMA products: 16..256, multiple of 16 */
+    int32_t gemm_f64_valu;    /* 1: FP64 products on the VALU tile kernel instead of the matrix cores */
+    int32_t sweep_nk_max;     /* right-hand sides per solve-sweep launch: 1, 2, 4 or 8 */
+    int32_t compress_nt_small;  /* threads per stacked block of <= 32 columns in Compress: 256, 512, 1024 */
+    int32_t compress_nt_mid;    /* the same for 33..64 columns */
+    int32_t gemm_grid;        /* 0: one work-group per 32 x 32 product tile; n > 0: a persistent grid of at
+                                 most n work-groups walks the tile list (0..65536) */
+    int32_t solve_graph;      /* 1: GMRES captures its preconditioner (the sweep launches of one
+                                 application) into a HIP graph after the first application and
+                                 replays it at every later Arnoldi step (not on the null stream,
+                                 nor while solve sweeps are event-timed); 0: direct launches */
+    int32_t reserved[1];
+} lrx_tune;
+
+lrx_status lrx_tune_get(lrx_tune* t);
+lrx_status lrx_tune_set(const lrx_tune* t);
 
 /* Message of the last error on this thread ("" if none). */
 const char* lrx_last_error(void);

@@ -167,7 +167,7 @@ struct DConv {
     int32_t f64, pad_;
 };
 
-// ---- Batched FGMRES vectors (preconditioned by the solve, Sec. 4.2) ---------
+// ---- Batched FGMRES vectors (preconditioned by the solve, Sec. 6.2) ---------
 // Vectors of a system are n x nrhs, row-interleaved (v[i*nrhs + k]), in tree
 // order.  One work-group per chunk of rows of one system (DKryChunk); systems
 // whose act flag is 0 are skipped.

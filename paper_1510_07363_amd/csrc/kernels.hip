@@ -378,9 +378,11 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
     for (int e = tid; e < c * c; e += NT) fro += Rm[e] * Rm[e];
     fro = block_sum(fro, s_s);
     const double tiny2 = 1e-30 * fro;
+    int sweeps_run = 0;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
+        ++sweeps_run;
         for (int t = 0; t < n2 - 1; ++t) {
             for (int i = g; i < n2 / 2; i += NT / JG) {
                 int a = (t + i) % (n2 - 1);
@@ -449,6 +451,7 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
     }
     if (tid == 0) {
         T.tails[0] = smax;
+        T.tails[c + 1] = (double)sweeps_run;     // Jacobi sweeps (work accounting)
         *T.rank_out = r;
     }
 }
@@ -466,8 +469,8 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
 // = P W keeps orthonormal columns to rounding.  1024 threads: in the QRs lane =
 // column and wavefront = rows i = seg (mod 16); in Jacobi 16 lanes per column
 // pair, reduced with DPP row permutations.
-constexpr int NTC = 1024;
-constexpr int SEGC = NTC / WAVE;           // row segments in the QRs
+// NTC threads per task (256, 512 or 1024, a tuning choice); SEGC = NTC / 64
+// row segments in the QRs.
 
 // Largest v over a wavefront (lowest i on ties); every lane receives (v, i).
 // DPP within rows of 16 lanes, then the four row results through readlane.
@@ -510,8 +513,9 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
 // reflector j is H_j = I - tau_j v v^T with v = (v0_j, A[j+1.., j]) acting on
 // rows j..nr-1; perm[j] is the original column now at position j (pivot only).
 // P: SEGC x WAVE, NV: SEGC elements of LDS scratch.  T: arithmetic type.
-template <class T>
+template <class T, int NTC>
 __device__ void qr64(T* A, int nr, int c, int ld, bool pivot, int* perm, T* hv0, T* htau, T* P, T* NV) {
+    constexpr int SEGC = NTC / WAVE;
     const int tid = threadIdx.x, k = tid % WAVE, s = tid / WAVE;
     const int kmax = min(nr, c);
     if (pivot) {
@@ -599,10 +603,11 @@ __device__ void qr64(T* A, int nr, int c, int ld, bool pivot, int* perm, T* hv0,
 
 // T = float: the reduced QRs and Jacobi in FP32 (mixed precision); B, the
 // projection B V and all outputs stay FP64.
-template <class F>
+template <class F, int NTC>
 __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
                                                         const int32_t* __restrict__ imap, int cap_d) {
+    constexpr int SEGC = NTC / WAVE;
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
     extern __shared__ double sm_d[];
@@ -671,7 +676,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
             }
             nrA = top + nnew;
             __syncthreads();
-            qr64(A, nrA, c, ldA, false, nullptr, hv0, htau, P, NV);
+            qr64<F, NTC>(A, nrA, c, ldA, false, nullptr, hv0, htau, P, NV);
             r0 += nnew;
             first = false;
         }
@@ -683,7 +688,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
         __syncthreads();
     }
     // ---- 2. R0 P = Q1 R1
-    qr64(X, c, c, ldc, true, s_perm, hv0, htau, P, NV);
+    qr64<F, NTC>(X, c, c, ldc, true, s_perm, hv0, htau, P, NV);
     // ---- 3. R1^T = Q2 R2 (A2 after W in the region); L = R2^T into X
     F* W = region;
     F* A2 = region + c * ldc;
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
         A2[i + k * ldc] = (k <= i) ? X[k + i * ldc] : 0.0;
     }
     __syncthreads();
-    qr64(A2, c, c, ldc, false, nullptr, hv0, htau, P, NV);
+    qr64<F, NTC>(A2, c, c, ldc, false, nullptr, hv0, htau, P, NV);
     for (int e = tid; e < c * c; e += NTC) {
         const int i = e % c, k = e / c;
         X[i + k * ldc] = (k <= i) ? A2[k + i * ldc] : 0.0;
@@ -724,6 +729,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
         }
     }
     // ---- 4. one-sided Jacobi on the columns of L; W accumulates the rotations
+    int sweeps_run = 0;
     {
         const int n2 = c + (c & 1), npair = n2 / 2;
         const int g = tid / 16, gl = tid % 16;
@@ -752,10 +758,12 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
         for (int sweep = 0; sweep < 40; ++sweep) {
             if (tid == 0) s_big = 0;
             __syncthreads();
+            ++sweeps_run;
             for (int t = 0; t < n2 - 1; ++t) {
-                if (g < npair) {
-                    const int a = (t + g) % (n2 - 1);
-                    const int b = g == 0 ? n2 - 1 : (t - g + n2 - 1) % (n2 - 1);
+                // NTC / 16 groups of 16 lanes take the npair disjoint pairs of round t
+                for (int gp = g; gp < npair; gp += NTC / 16) {
+                    const int a = (t + gp) % (n2 - 1);
+                    const int b = gp == 0 ? n2 - 1 : (t - gp + n2 - 1) % (n2 - 1);
                     const int p = a < b ? a : b, q = a < b ? b : a;
                     const bool act = q < c;
                     F xp[EPL], xq[EPL];
@@ -820,6 +828,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     }
     if (tid == 0) {
         T.tails[0] = smax;
+        T.tails[c + 1] = (double)sweeps_run;     // Jacobi sweeps (work accounting)
         *T.rank_out = r;
     }
 }
@@ -1269,6 +1278,9 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     const double fro = blk_sum_l(f, s_red);
     const double tiny2 = 81.0 * u * u * fro;
     const bool inline_jacobi = mode == 0 || mode == 7 || kk > KK_LDS_MAX;
+    // Jacobi sweeps of this task (work accounting): counted here when the sweeps
+    // run inline, else one per sweep of the block rounds by k_large_flags
+    if (tid == 0) T.tails[c + 1] = 0.0;
     if (mode == 1 || mode == 6) {
         for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
         if (tid == 0) {
@@ -1286,9 +1298,11 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         const int n2 = kk + (kk & 1);
         // a sweep without a rotation above sqrt(tol) sqrt(alpha beta) ends it
         // (the next would only rotate below the tol level); s_rot holds that flag
+        int sweeps_run = 0;
         for (int sweep = 0; sweep < 40; ++sweep) {
             if (tid == 0) s_rot = 0;
             __syncthreads();
+            ++sweeps_run;
             for (int t = 0; t < n2 - 1; ++t) {
                 if (kk <= 128) jac_round<16, 8>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
                 else if (kk <= 256) jac_round<16, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
@@ -1300,6 +1314,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
             __syncthreads();
             if (!rot) break;
         }
+        if (tid == 0) T.tails[c + 1] = (double)sweeps_run;
     }
     if (mode == 1 || mode == 6) return;
     }                                                   // mode != 2
@@ -1601,6 +1616,7 @@ __global__ void k_large_flags(const DCompress* __restrict__ tasks, int n, int32_
     const DCompress T = tasks[i];
     if (T.M == 0 || T.c == 0) { out[i] = 0; return; }
     double* hdr = T.hv + 4 * (size_t)T.c * T.c + T.c;
+    if (hdr[LH_DONE] == 0.0) T.tails[T.c + 1] += 1.0;     // the task ran this sweep
     const int go = hdr[LH_DONE] == 0.0 && hdr[LH_BIG] != 0.0;
     hdr[LH_ROT] = 0.0;
     hdr[LH_BIG] = 0.0;
@@ -2308,7 +2324,8 @@ __device__ inline KryRows kry_rows_of(const DKryChunk& C, int n, int rc) {
 
 // mode 0: b = bin[perm] (tree order), x = 0; mode 1: xout[perm] = x
 __global__ __launch_bounds__(256) void k_kry_perm(const DKry* __restrict__ sys, const DKryChunk* __restrict__ ch,
-                                                  const int32_t* __restrict__ act, int nrhs, int rc, int mode) {
+                                                  const int32_t* __restrict__ act, int nrhs, int rc, int mode,
+                                                  int off) {
     const DKryChunk C = ch[blockIdx.x];
     if (!act[C.sys]) return;
     const DKry& S = sys[C.sys];
@@ -2321,6 +2338,8 @@ __global__ __launch_bounds__(256) void k_kry_perm(const DKry* __restrict__ sys, 
         if (mode == 0) {
             S.b[i * nrhs + k] = S.bin[o];
             S.x[i * nrhs + k] = 0.0;
+        } else if (mode == 2) {                         // initial guess, 0 where ||b|| = 0
+            S.x[i * nrhs + k] = S.sm[off + k] > 0.0 ? S.xout[o] : 0.0;
         } else {
             S.xout[o] = S.x[i * nrhs + k];
         }
@@ -2502,26 +2521,31 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 }
 
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, int max_M, bool fp32, hipStream_t st) {
+                               int max_c, int max_M, bool fp32, int nt, hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (max_c <= 64) {
         static std::atomic<bool> attr64{false};
         if (!attr64) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_compress_svd64<double>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void*)k_compress_svd64<float>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
-            if (e != hipSuccess) return e;
+            const void* fs[6] = {(const void*)k_compress_svd64<double, 256>, (const void*)k_compress_svd64<double, 512>,
+                                 (const void*)k_compress_svd64<double, 1024>, (const void*)k_compress_svd64<float, 256>,
+                                 (const void*)k_compress_svd64<float, 512>, (const void*)k_compress_svd64<float, 1024>};
+            for (const void* f : fs) {
+                hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+                if (e != hipSuccess) return e;
+            }
             attr64 = true;
         }
         const int cap = (kLdsBudget - 4096) / (int)sizeof(double);   // static LDS of the kernel aside
-        if (fp32)
-            hipLaunchKernelGGL(k_compress_svd64<float>, dim3(n), dim3(NTC), (size_t)cap * sizeof(double), st, t,
-                               pieces, imap, cap);
-        else
-            hipLaunchKernelGGL(k_compress_svd64<double>, dim3(n), dim3(NTC), (size_t)cap * sizeof(double), st, t,
-                               pieces, imap, cap);
+        const size_t lds = (size_t)cap * sizeof(double);
+        if (fp32) {
+            if (nt == 256) hipLaunchKernelGGL((k_compress_svd64<float, 256>), dim3(n), dim3(256), lds, st, t, pieces, imap, cap);
+            else if (nt == 512) hipLaunchKernelGGL((k_compress_svd64<float, 512>), dim3(n), dim3(512), lds, st, t, pieces, imap, cap);
+            else hipLaunchKernelGGL((k_compress_svd64<float, 1024>), dim3(n), dim3(1024), lds, st, t, pieces, imap, cap);
+        } else {
+            if (nt == 256) hipLaunchKernelGGL((k_compress_svd64<double, 256>), dim3(n), dim3(256), lds, st, t, pieces, imap, cap);
+            else if (nt == 512) hipLaunchKernelGGL((k_compress_svd64<double, 512>), dim3(n), dim3(512), lds, st, t, pieces, imap, cap);
+            else hipLaunchKernelGGL((k_compress_svd64<double, 1024>), dim3(n), dim3(1024), lds, st, t, pieces, imap, cap);
+        }
         return hipGetLastError();
     }
     // LDS plan: R and V (2 c^2) plus a chunk of ch rows of B (ch c), within the
@@ -2707,9 +2731,9 @@ hipError_t launch_scatter_perm(const double* xt, const int32_t* perm, int n, int
     return hipGetLastError();
 }
 
-hipError_t kry_perm(const KryLaunch& L, int mode) {
+hipError_t kry_perm(const KryLaunch& L, int mode, int off) {
     if (L.nchunk == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kry_perm, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, mode);
+    hipLaunchKernelGGL(k_kry_perm, dim3(L.nchunk), dim3(256), 0, L.st, L.sys, L.ch, L.act, L.nrhs, L.rc, mode, off);
     return hipGetLastError();
 }
 

@@ -24,9 +24,10 @@ hipError_t launch_count_nonfinite(const double* v, int64_t n, int64_t* cnt, hipS
 // lds_bytes: dynamic LDS per work-group
 hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
                            int max_c, hipStream_t st);
-// fp32: reduced QRs and Jacobi in FP32 when every task has c <= 64 (mixed precision)
+// fp32: reduced QRs and Jacobi in FP32 when every task has c <= 64 (mixed
+// precision); nt: threads per task (256, 512 or 1024) when every task has c <= 64
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, int max_M, bool fp32, hipStream_t st);
+                               int max_c, int max_M, bool fp32, int nt, hipStream_t st);
 // Truncated SVD of stacked blocks with c > 64 columns (FP64, matrices in the
 // workspace: hv needs 4 c^2 + c + 8 doubles, Bw M c).  Trailing QRCP rows below
 // trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
@@ -57,6 +58,13 @@ hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj,
 // ntile 32 x 32 tiles of the products g (DGemm, DTile); kmax = largest K.
 hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int kmax, const int32_t* imap,
                              hipStream_t st);
+// The same products on the matrix cores (gemm.hip): operands staged as FP64,
+// FP32 or BF16 (prec: GP_*), FP64 or FP32 accumulation; K staged in chunks of
+// at most kc_cap (<= 256) columns; grid_cap > 0: a persistent grid of at most
+// grid_cap work-groups walks the tile list (0: one work-group per tile).
+enum { GP_F64 = 0, GP_F32 = 1, GP_BF16 = 2 };
+hipError_t launch_gemm_mfma(const DGemm* g, const DTile* tiles, int ntile, int kmax, const int32_t* imap, int prec,
+                            int kc_cap, int grid_cap, hipStream_t st);
 
 // One sweep launch (forward or backward program) over n super-nodes of a
 // colour step, right-hand sides [k0, k0 + nk) of x (ldx per row), nk in {1,2,4,8}.
@@ -84,8 +92,10 @@ struct KryLaunch {
     int nchunk, nsys, nrhs, rc;
     hipStream_t st;
 };
-// mode 0: b = bin in tree order, x = 0;  mode 1: xout = x in the original order
-hipError_t kry_perm(const KryLaunch& L, int mode);
+// mode 0: b = bin in tree order, x = 0;  mode 1: xout = x in the original order;
+// mode 2: x = xout in tree order (an initial guess), 0 for right-hand side k
+// when sm[off + k] (its ||b||^2) is 0
+hipError_t kry_perm(const KryLaunch& L, int mode, int off = 0);
 // residual: r = b - A x;  otherwise w = A Z_j
 hipError_t kry_spmv(const KryLaunch& L, bool residual, int j);
 // sm[out_off + j*nrhs + k] = (mode 0) <V_j, w>_k for j < J, (1) ||w||_k^2, (2) ||r||_k^2;

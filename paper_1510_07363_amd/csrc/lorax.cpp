@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <thread>
 #include <set>
 #include <string>
@@ -47,6 +48,23 @@ struct Fail {
 double now_ms() {
     using namespace std::chrono;
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Device-wide synchronizations and frees (which synchronize) wait while a
+// thread captures a HIP graph on one of its streams: a synchronization that
+// reached a capturing stream would break the capture.
+std::shared_mutex g_capture_mu;
+bool device_sync() {
+    std::shared_lock<std::shared_mutex> lk(g_capture_mu);
+    return hipDeviceSynchronize() == hipSuccess;
+}
+void free_dev(void* q) {
+    std::shared_lock<std::shared_mutex> lk(g_capture_mu);
+    (void)hipFree(q);
+}
+void free_pin(void* q) {
+    std::shared_lock<std::shared_mutex> lk(g_capture_mu);
+    (void)hipHostFree(q);
 }
 
 // --------------------------------------------------------------- device memory
@@ -86,7 +104,7 @@ void cache_flush_device(int dev) {
         }
         g_dev_cached[dev] = 0;
     }
-    for (void* q : ps) (void)hipFree(q);
+    for (void* q : ps) free_dev(q);
 }
 
 void* dev_alloc(size_t b, size_t& got, int& dev) {
@@ -122,7 +140,7 @@ void* dev_alloc(size_t b, size_t& got, int& dev) {
 thread_local int t_idle = 0;
 struct IdleScope {
     bool ok;
-    IdleScope() : ok(hipDeviceSynchronize() == hipSuccess) { if (ok) ++t_idle; }
+    IdleScope() : ok(device_sync()) { if (ok) ++t_idle; }
     ~IdleScope() { if (ok) --t_idle; }
     IdleScope(const IdleScope&) = delete;
     IdleScope& operator=(const IdleScope&) = delete;
@@ -134,7 +152,7 @@ void dev_release(void* q, size_t c, int dev) {
     (void)hipGetDevice(&cur);
     if (cur != dev) (void)hipSetDevice(dev);
     bool keep = false;
-    if ((t_idle > 0 && cur == dev) || hipDeviceSynchronize() == hipSuccess) {
+    if ((t_idle > 0 && cur == dev) || device_sync()) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (g_dev_cached[dev] + c <= kCacheBytes) {
             g_dev_cache[{dev, c}].push_back(q);
@@ -142,7 +160,7 @@ void dev_release(void* q, size_t c, int dev) {
             keep = true;
         }
     }
-    if (!keep) (void)hipFree(q);
+    if (!keep) free_dev(q);
     if (cur != dev) (void)hipSetDevice(cur);
 }
 
@@ -168,7 +186,7 @@ void* pin_alloc(size_t b, size_t& got) {
 void pin_release(void* q, size_t c) {          // copies from or to it may be queued on the current device
     if (!q) return;
     bool keep = false;
-    if (t_idle > 0 || hipDeviceSynchronize() == hipSuccess) {
+    if (t_idle > 0 || device_sync()) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (g_pin_cached + c <= kPinCacheBytes) {
             g_pin_cache[c].push_back(q);
@@ -176,7 +194,7 @@ void pin_release(void* q, size_t c) {          // copies from or to it may be qu
             keep = true;
         }
     }
-    if (!keep) (void)hipHostFree(q);
+    if (!keep) free_pin(q);
 }
 
 struct DevBuf {
@@ -342,6 +360,7 @@ struct LaunchTimer {
     bool on = false;
     hipStream_t st;
     LaunchTimer(int cls, hipStream_t s, double bytes, double flops) : st(s) {
+        if (cls < 0) return;                     // untimed launch
         std::lock_guard<std::mutex> lk(g_tmu);
         if (!(g_timing & (1u << cls))) return;
         t.cls = cls; t.bytes = bytes; t.flops = flops;
@@ -373,6 +392,20 @@ void resolve_timing() {                  // caller holds g_tmu
     g_pending.clear();
 }
 
+}  // namespace
+
+namespace {
+// Tunable launch shapes (lrx_tune_set; defaults measured on MI355X).
+struct Tune {
+    int32_t gemm_kc = 128;          // K chunk of the MFMA products (multiple of 16, <= 256)
+    int32_t gemm_f64_valu = 0;      // 1: FP64 products on the VALU tile kernel instead of MFMA
+    int32_t sweep_nk_max = 8;       // right-hand sides per sweep launch (1, 2, 4 or 8)
+    int32_t compress_nt_small = 1024;   // threads per stacked block of at most 32 columns
+    int32_t compress_nt_mid = 1024;     // threads per stacked block of 33..64 columns
+    int32_t gemm_grid = 0;          // persistent grid of the MFMA products (0: a work-group per tile)
+    int32_t solve_graph = 1;        // 1: GMRES replays its preconditioner as a captured HIP graph
+};
+Tune g_tune;
 }  // namespace
 
 struct lrx_handle_s {
@@ -441,10 +474,35 @@ void ensure_gfx950(int dev) {
         fail(LRX_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
 }
 
+// ------------------------------------------------------------------ work accounting
+// Algorithmic flops of one compression (counted from the actual sizes, ranks and
+// Jacobi sweeps): Householder QR of the M x c stacked block, 2 M c^2 - 2/3 c^3
+// (or 2 c M^2 - 2/3 M^3 when M < c); for the SVD the QR-preconditioned Jacobi of
+// the c x c triangle: a column-pivoted QR, an LQ and the explicit Q2 (4/3 c^3
+// each), then per sweep c (c - 1) / 2 pairs of 3 dot products and 2 rotations
+// of length c (18 c flops a pair); for RRQR the row-pivoted QR stopped at rank
+// r, 4 M c r.  The projection B V (2 M c r) is counted with its own launches.
+double qr_flops(double M, double c) {
+    return M >= c ? 2.0 * M * c * c - 2.0 / 3.0 * c * c * c : 2.0 * c * M * M - 2.0 / 3.0 * M * M * M;
+}
+double svd_pre_flops(double c) { return 4.0 * c * c * c; }
+double jacobi_flops(double c, double sweeps) { return sweeps * 9.0 * c * c * (c - 1.0); }
+
+// Adds work to a kernel class's timing totals without a launch (work known only
+// after the kernels ran, such as Jacobi sweeps and ranks).
+void timing_add(int cls, double bytes, double flops) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (g_timing & (1u << cls)) {
+        g_acc.k[cls].bytes += bytes;
+        g_acc.k[cls].flops += flops;
+    }
+}
+
 // ------------------------------------------------------------------ factor driver
 // State of one factorization in the level loop.  The driver below advances one
 // or several factorizations in lock-step over (height above the leaves,
-// colour): super-nodes of one colour are independent (Sec. 3.3) and distinct
+// colour): super-nodes of one colour are independent (Thm. "preservation of sparsity",
+// Sec. 5) and distinct
 // systems share nothing, so every participating factorization's tasks of a step
 // go into one launch per kernel.  Each task's arithmetic depends on its own
 // operands only, so a factorization in a batch equals the same factorization
@@ -468,6 +526,9 @@ struct FactorRun {
     int32_t info_base = 0, info_count = 0, info_next = 0;
     bool fp32_compress = false;
     int64_t flops = 0;
+    double fl_compress = 0, fl_pivot = 0, fl_schur = 0, fl_project = 0;   // by operation class
+    double jac_flops = 0.0, jac_sweeps = 0.0;   // Jacobi work of the current step (timing)
+    double v_bytes = 0.0;                       // bytes of V written in the current step (timing)
     DevBuf d_idx, d_val;                   // temporaries of the initial scatter
     // current colour step
     int32_t si = -1;
@@ -519,7 +580,7 @@ void FactorRun::setup(const lrx_csr* A, const double* val_dev, hipStream_t st) {
         if (P.nodes[v].leaf) h->size[v] = P.nodes[v].static_size;
     // mixed precision: the reduced QRs and Jacobi of the compression in FP32
     // when FP32 resolves the cut-off (sigma_k / sigma_0 >= epsilon >= 1e-5)
-    fp32_compress = h->precision == LRX_MIXED && h->epsilon >= 1e-5;
+    fp32_compress = h->precision != LRX_FP64 && h->epsilon >= 1e-5;
     for (size_t li = 0; li < P.levels.size(); ++li) {
         const int32_t hgt = P.depth - P.levels[li].level;
         if (hgt < 0) fail(LRX_EDEVICE, "internal: level above the depth");
@@ -747,8 +808,22 @@ void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t
         h->max_tail_ratio = std::max(h->max_tail_ratio, ratio);
         h->rank_level.push_back(cs.level);
         h->rank_j.push_back(ns.j);
-        // flops of the stacked QR (and the Jacobi SVD), or of the pivoted QR
-        flops += svd ? 4ll * T.M * T.c * T.c : 4ll * T.M * T.c * rk[ni];
+        // flops of the stacked QR and the Jacobi SVD (sweeps reported by the
+        // kernel after the c + 1 singular-value slots), or of the pivoted QR
+        if (!emptyB) {
+            if (svd) {
+                const double sw = tl[T.c + 1];
+                const double jf = jacobi_flops(T.c, sw);
+                flops += (int64_t)(qr_flops(T.M, T.c) + svd_pre_flops(T.c) + jf);
+                fl_compress += qr_flops(T.M, T.c) + svd_pre_flops(T.c) + jf;
+                jac_flops += jf;
+                jac_sweeps += sw;
+                v_bytes += 8.0 * T.c * rk[ni];
+            } else {
+                flops += 4ll * T.M * T.c * rk[ni];
+                fl_compress += 4.0 * T.M * T.c * rk[ni];
+            }
+        }
     }
     // the blocks created in this step
     alloc_group(cs.new_edges, st);
@@ -756,7 +831,7 @@ void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t
 
 // Preparation of every super-node (projection, rewiring, inverse of S), Schur
 // products of s, inverse of the black pivot B = -V^T S^{-1} V, Schur products
-// of b (Sec. 3.2, eqns. for Eliminate(s) and Eliminate(b)).
+// of b (Sec. 4.4 with the block elimination of Sec. 2.2).
 void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
     const ColourStep& cs = P.steps[si];
     const int nn = (int)cs.nodes.size();
@@ -881,7 +956,20 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
         schur(ns.pb, maps[si][ni].pb, nb.g1b, nb.g2b, nb.gf_b);
     }
     flops += (nb.pf_s - pf_s0) + (nb.pf_b - pf_b0) + (nb.gf_s - gf_s0) + (nb.gf_b - gf_b0) + (nb.gf_p - gf_p0);
+    fl_pivot += (double)((nb.pf_s - pf_s0) + (nb.pf_b - pf_b0));
+    fl_schur += (double)((nb.gf_s - gf_s0) + (nb.gf_b - gf_b0));
+    fl_project += (double)(nb.gf_p - gf_p0);
     if (wcur != wtot) fail(LRX_EDEVICE, "internal: Schur workspace size mismatch");
+}
+
+// Products of a factorization step (Schur updates, projection): on the matrix
+// cores (MFMA) with operand precision prec, K staged in chunks of
+// g_tune.gemm_kc columns; FP64 products may instead run as the VALU tile kernel
+// when the tuning table says it is faster for this device.
+hipError_t gemm_products(const DGemm* g, const DTile* t, int ntile, int kmax, const int32_t* imap, int prec,
+                         hipStream_t st) {
+    if (prec == GP_F64 && g_tune.gemm_f64_valu) return launch_gemm_tiles(g, t, ntile, kmax, imap, st);
+    return launch_gemm_mfma(g, t, ntile, kmax, imap, prec, g_tune.gemm_kc, g_tune.gemm_grid, st);
 }
 
 // The level loop over one or several factorizations sharing the stream st.
@@ -998,12 +1086,12 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             // panels and the Jacobi in multi-work-group block rounds; key 2 when the
             // LDS of the large kernel does not fit), pivoted QR (key 4); each task
             // takes its own variant whatever the others are
-            struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0; size_t off = 0; };
+            struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0, by = 0; size_t off = 0; };
             std::vector<Group> groups;
             for (size_t q = 0; q < all.size(); ++q) {
                 int key;
                 if (fp32_of[q] >= 4) key = 4;
-                else if (all[q].c <= 64) key = fp32_of[q];
+                else if (all[q].c <= 64) key = fp32_of[q] | (all[q].c > 32 ? 16 : 0);
                 else if (compress_large_fits(all[q].M, all[q].c)) {
                     const int64_t mc = (int64_t)all[q].M * all[q].c;
                     key = (all[q].c > 192 || mc >= 1000000 ? 10 : mc >= 300000 ? 12 : 8) | (fp32_of[q] & 1);
@@ -1015,8 +1103,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 G.t.push_back(all[q]);
                 G.max_c = std::max(G.max_c, (int)all[q].c);
                 G.max_M = std::max(G.max_M, (int)all[q].M);
+                // known before the launch: the QRs (RRQR: at full rank, an upper
+                // bound); the Jacobi sweeps are added after the read-back
                 const double M = all[q].M, cc = all[q].c;
-                G.fl += key == 4 ? 4.0 * M * cc * cc : 4.0 * M * cc * cc + 8.0 * 6.0 * cc * cc * cc;
+                if (M > 0 && cc > 0) G.fl += key == 4 ? 4.0 * M * cc * cc : qr_flops(M, cc) + svd_pre_flops(cc);
+                G.by += 8.0 * M * cc;        // the stacked pieces, read once (V is added after the read-back)
             }
             {
                 std::vector<char> buf;
@@ -1032,7 +1123,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 // others on library streams forked from it and joined back after
                 auto run_group = [&](Group& G, hipStream_t gs) {
                     const DCompress* dt = (const DCompress*)(d_desc_c.as<char>() + G.off);
-                    LaunchTimer tm(LRX_K_COMPRESS, gs, 0.0, G.fl);
+                    LaunchTimer tm(LRX_K_COMPRESS, gs, G.by, G.fl);
                     if (G.key == 4)
                         HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, gs));
                     else if (G.key == 8 || G.key == 9) {
@@ -1074,7 +1165,9 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                     }
                     else
                         HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
-                                                   (G.key & 1) != 0, gs));
+                                                   (G.key & 1) != 0,
+                                                   G.key >= 16 ? g_tune.compress_nt_mid : g_tune.compress_nt_small,
+                                                   gs));
                 };
                 std::vector<hipStream_t> gsv(groups.size(), st);
                 AuxStreams* ax = groups.size() > 1 ? aux_streams() : nullptr;
@@ -1112,7 +1205,12 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             sync();
             const int32_t* rk = (const int32_t*)pin_rt.p;
             const double* tails_h = (const double*)((const char*)pin_rt.p + tails_off);
-            for (FactorRun* r : part) r->take_ranks(rk + r->task0, tails_h + r->tails0, st);
+            for (FactorRun* r : part) {
+                r->jac_flops = 0.0;
+                r->v_bytes = 0.0;
+                r->take_ranks(rk + r->task0, tails_h + r->tails0, st);
+                timing_add(LRX_K_COMPRESS, r->v_bytes, r->jac_flops);
+            }
             // ---- node tasks of every participating factorization
             NodeBatch nb;
             for (FactorRun* r : part) r->node_tasks(rk + r->task0, nb);
@@ -1146,30 +1244,38 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             char* b = d_desc_n.as<char>();
             int32_t* inf = d_info.as<int32_t>();
             const int np = (int)nb.prep_s.size();
-            auto gemm = [&](size_t og, size_t ot, const std::vector<DTile>& t, int kmax, int64_t fl) {
+            // operand precision of the products on the matrix cores: W_k = S^-1 Mat(k->v)
+            // applies the pivot and stays FP64; in mixed precision (when the
+            // compression runs in FP32) the Schur GEMMs take FP32 operands with FP32
+            // accumulation, and the projection B V FP32 operands, or BF16 ones in the
+            // BF16 trial; the results are subtracted from / written to FP64 blocks
+            const bool f32p = part[0]->fp32_compress;
+            const int p_schur = f32p ? GP_F32 : GP_F64;
+            const int p_proj = !f32p ? GP_F64 : (part[0]->h->precision == LRX_MIXED_BF16 ? GP_BF16 : GP_F32);
+            auto gemm = [&](size_t og, size_t ot, const std::vector<DTile>& t, int kmax, int64_t fl, int prec) {
                 if (t.empty()) return;
                 LaunchTimer tm(LRX_K_SCHUR, st, 0.0, (double)fl);
-                HIPCHK(launch_gemm_tiles((const DGemm*)(b + og), (const DTile*)(b + ot), (int)t.size(), kmax, dmap,
-                                         st));
+                HIPCHK(gemm_products((const DGemm*)(b + og), (const DTile*)(b + ot), (int)t.size(), kmax, dmap, prec,
+                                     st));
             };
             if (!tps.empty()) {                    // projection B V of every super-node (SVD)
-                LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.gf_p);
-                HIPCHK(launch_gemm_tiles((const DGemm*)(b + o_gp), (const DTile*)(b + o_tp), (int)tps.size(), kps,
-                                         dmap, st));
+                LaunchTimer tm(LRX_K_PROJECT, st, 0.0, (double)nb.gf_p);
+                HIPCHK(gemm_products((const DGemm*)(b + o_gp), (const DTile*)(b + o_tp), (int)tps.size(), kps, dmap,
+                                     p_proj, st));
             }
             {
                 LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_s);
                 HIPCHK(launch_node_prep((const DPrep*)(b + o_ps), np, nb.max_ms, (const DProj*)(b + o_pj), dmap,
                                         inf, st));
             }
-            gemm(o_g1s, o_t1s, t1s, k1s, 0);
-            gemm(o_g2s, o_t2s, t2s, k2s, nb.gf_s);
+            gemm(o_g1s, o_t1s, t1s, k1s, 0, GP_F64);
+            gemm(o_g2s, o_t2s, t2s, k2s, nb.gf_s, p_schur);
             {
                 LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_b);
                 HIPCHK(launch_node_prep((const DPrep*)(b + o_pb), np, nb.max_mb, nullptr, dmap, inf, st));
             }
-            gemm(o_g1b, o_t1b, t1b, k1b, 0);
-            gemm(o_g2b, o_t2b, t2b, k2b, nb.gf_b);
+            gemm(o_g1b, o_t1b, t1b, k1b, 0, GP_F64);
+            gemm(o_g2b, o_t2b, t2b, k2b, nb.gf_b, p_schur);
         }
     }
     sync();
@@ -1182,6 +1288,10 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 fail(LRX_ESINGULAR, runs.size() > 1 ? "exactly singular pivot block in system " + std::to_string(i)
                                                     : std::string("exactly singular pivot block"));
         r.h->stats.factor_flops = r.flops;
+        r.h->stats.flops_compress = r.fl_compress;
+        r.h->stats.flops_pivot = r.fl_pivot;
+        r.h->stats.flops_schur = r.fl_schur;
+        r.h->stats.flops_project = r.fl_project;
         r.h->t_sync_ms += t_sync;
     }
     IdleScope idle;
@@ -1225,7 +1335,7 @@ void build_solve_program(lrx_handle h) {
 
     // mixed precision: the solve reads FP32 copies of every block it uses (pivot
     // inverses and frozen edges); the FP64 factor is released afterwards
-    const bool f32 = h->precision == LRX_MIXED;
+    const bool f32 = h->precision != LRX_FP64;
     const int32_t es = f32 ? 4 : 8;
     std::vector<const void*> sptr(P.edges.size(), nullptr);
     if (f32) {
@@ -1393,34 +1503,50 @@ void build_solve_program(lrx_handle h) {
     h->t_solve_prog_ms = now_ms() - t_begin;
 }
 
-// x_ext (n_ext x nrhs interleaved) -> in place sweeps
-void sweeps(lrx_handle h, double* xe, int nrhs) {
+// Right-hand sides per sweep launch for rem remaining: the largest of 8, 4, 2, 1
+// that fits, capped by the tuning table.
+int sweep_nk(int rem) {
+    const int cap = g_tune.sweep_nk_max;
+    for (int nk = 8; nk > 1; nk >>= 1)
+        if (nk <= cap && rem >= nk) return nk;
+    return 1;
+}
+
+// x_ext (n_ext x nrhs interleaved) -> in place sweeps.  timed = false records
+// no events (the allocation-free path creates nothing).
+void sweeps(lrx_handle h, double* xe, int nrhs, bool timed = true) {
     const hipStream_t st = h->stream;
     const SwNode* fwd = h->d_swnodes.as<SwNode>();
     const SwNode* bwd = fwd + h->sw_nnode;
     for (int k0 = 0; k0 < nrhs;) {
         const int rem = nrhs - k0;
-        const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+        const int nk = sweep_nk(rem);
         for (const SolveStep& s : h->ssteps) {
-            LaunchTimer tm(LRX_K_SOLVE_FWD, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nk);
+            LaunchTimer tm(timed ? LRX_K_SOLVE_FWD : -1, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nk);
             HIPCHK(launch_sweep(fwd + s.node0, s.nnode, xe, nrhs, k0, nk, st));
         }
         for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it) {
-            LaunchTimer tm(LRX_K_SOLVE_BWD, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nk);
+            LaunchTimer tm(timed ? LRX_K_SOLVE_BWD : -1, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nk);
             HIPCHK(launch_sweep(bwd + it->node0, it->nnode, xe, nrhs, k0, nk, st));
         }
         k0 += nk;
     }
 }
 
-void solve_dev(lrx_handle h, int nrhs, const double* b, double* x) {
+// Algorithms 2-4 with the extended vector in xe (n_ext x nrhs): SetRHS (b in
+// tree order, auxiliary variables zeroed by the same kernel), SolveL, SolveU,
+// SplitVar (nothing to do: a super-node's variables are its reds'), x.
+void solve_into(lrx_handle h, int nrhs, const double* b, double* x, double* xe, bool timed) {
     const hipStream_t st = h->stream;
     const int32_t n = h->plan.n;
-    h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
-    double* xe = h->x_ext.as<double>();
     HIPCHK(launch_gather_perm(b, n, h->d_perm.as<int32_t>(), n, nrhs, xe, h->n_ext, st));
-    sweeps(h, xe, nrhs);
+    sweeps(h, xe, nrhs, timed);
     HIPCHK(launch_scatter_perm(xe, h->d_perm.as<int32_t>(), n, nrhs, x, n, st));
+}
+
+void solve_dev(lrx_handle h, int nrhs, const double* b, double* x) {
+    h->x_ext.ensure((size_t)h->n_ext * nrhs * 8);
+    solve_into(h, nrhs, b, x, h->x_ext.as<double>(), true);
 }
 
 // Algorithms 2-4 for k factorizations at once: one sweep launch per (height,
@@ -1473,7 +1599,7 @@ void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const*
     }
     for (int c0 = 0; c0 < nrhs;) {
         const int rem = nrhs - c0;
-        const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+        const int nk = sweep_nk(rem);
         for (size_t q = 0; q + 1 < k0f.size(); ++q)
             HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
         for (size_t q = k0f.size() - 1; q-- > 0;)
@@ -1489,7 +1615,31 @@ void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const*
 }
 
 // ------------------------------------------------------------------ GMRES
-// FGMRES(restart) with the solve as right preconditioner (Sec. 4.2), x_0 = 0,
+bool timing_on(int cls) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    return (g_timing & (1u << cls)) != 0;
+}
+
+// A captured preconditioner: ends an unfinished capture and releases the graph
+// once the stream has run every replay.
+struct SolveGraph {
+    hipStream_t st;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool capturing = false;
+    explicit SolveGraph(hipStream_t s) : st(s) {}
+    ~SolveGraph() {
+        if (capturing) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(st, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+        }
+        if (exec || g) (void)hipStreamSynchronize(st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+// FGMRES(restart) with the solve as right preconditioner (Sec. 6.2), x_0 = 0,
 // for k factorizations at once, nrhs right-hand sides each.  Every vector
 // operation is one launch over the row chunks of all systems still iterating
 // (DKry/DKryChunk tables); the preconditioner is one sweep launch per
@@ -1499,7 +1649,8 @@ void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const*
 // have all stopped drops out of the launches (its act flag).  k = 1 is the
 // single-system solver.
 lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* const* b, double* const* x,
-                       double tol, int restart, int maxit, int32_t* iters_out, double* relres_out) {
+                       double tol, int restart, int maxit, int32_t* iters_out, double* relres_out,
+                       bool use_x0 = false) {
     const lrx_handle h0 = hs[0];
     const hipStream_t st = h0->stream;
     const int m = restart;
@@ -1615,20 +1766,49 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
         HIPCHK(hipMemcpy(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
     }
-    auto precondition = [&]() {
+    auto sweep_launches = [&](bool timed) {
         for (int c0 = 0; c0 < nrhs;) {
             const int rem = nrhs - c0;
-            const int nk = rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+            const int nk = sweep_nk(rem);
             for (size_t q = 0; q + 1 < k0f.size(); ++q) {
-                LaunchTimer tm(LRX_K_SOLVE_FWD, st, step_bytes_f[q], step_bytes_f[q] / 4.0 * nk);
+                LaunchTimer tm(timed ? LRX_K_SOLVE_FWD : -1, st, step_bytes_f[q], step_bytes_f[q] / 4.0 * nk);
                 HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
             }
             for (size_t q = k0f.size() - 1; q-- > 0;) {
-                LaunchTimer tm(LRX_K_SOLVE_BWD, st, step_bytes_b[q], step_bytes_b[q] / 4.0 * nk);
+                LaunchTimer tm(timed ? LRX_K_SOLVE_BWD : -1, st, step_bytes_b[q], step_bytes_b[q] / 4.0 * nk);
                 HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
             }
             c0 += nk;
         }
+    };
+    // The preconditioner is the same launch sequence at every Arnoldi step (the
+    // node tables, vectors and act flags it reads stay where they are), so after
+    // one direct application it is captured once into a HIP graph and replayed.
+    // Only on a non-blocking stream (the null stream cannot be captured, and
+    // null-stream work of other threads would synchronize with a blocking one),
+    // and not while its launches are being event-timed.
+    SolveGraph graph(st);
+    unsigned int sflags = 0;
+    const bool use_graph = g_tune.solve_graph && st != nullptr && hipStreamGetFlags(st, &sflags) == hipSuccess &&
+                           (sflags & hipStreamNonBlocking) && !timing_on(LRX_K_SOLVE_FWD) &&
+                           !timing_on(LRX_K_SOLVE_BWD);
+    int applications = 0;
+    auto precondition = [&]() {
+        if (!use_graph || applications++ == 0) {
+            sweep_launches(true);
+            return;
+        }
+        if (!graph.exec) {
+            std::unique_lock<std::shared_mutex> lk(g_capture_mu);
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            graph.capturing = true;
+            sweep_launches(false);
+            graph.capturing = false;
+            HIPCHK(hipStreamEndCapture(st, &graph.g));
+            lk.unlock();
+            HIPCHK(hipGraphInstantiate(&graph.exec, graph.g, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(graph.exec, st));
     };
 
     // host state per (system, right-hand side)
@@ -1642,6 +1822,21 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
     put_act();
     HIPCHK(kry_perm(L, 0));                   // b in tree order, x = 0
     bool first = true;
+    if (use_x0) {
+        // ||b|| from the residual of x = 0, then x = the caller's initial guess
+        HIPCHK(kry_spmv(L, true, 0));
+        HIPCHK(kry_dots(L, 2, 1, part, o_n2));
+        get_small();
+        for (int s = 0; s < K; ++s)
+            for (int k = 0; k < nrhs; ++k) {
+                const size_t q = (size_t)s * nrhs + k;
+                bnorm[q] = std::sqrt(hsm[(size_t)s * smsz + o_n2 + k]);
+                active[q] = bnorm[q] > 0.0;
+                conv[q] = !active[q];
+            }
+        HIPCHK(kry_perm(L, 2, o_n2));
+        first = false;
+    }
     while (true) {
         HIPCHK(kry_spmv(L, true, 0));          // r = b - A x
         HIPCHK(kry_dots(L, 2, 1, part, o_n2));
@@ -1820,8 +2015,8 @@ void check_factor_args(const lrx_csr* A, const double* val_dev, const lrx_tree* 
         check_csr(A);
     }
     if (!(o->epsilon >= 0.0 && o->epsilon < 1.0)) fail(LRX_EINVAL, "epsilon must be in [0, 1)");
-    if (o->precision != LRX_FP64 && o->precision != LRX_MIXED)
-        fail(LRX_EINVAL, "precision must be LRX_FP64 or LRX_MIXED");
+    if (o->precision != LRX_FP64 && o->precision != LRX_MIXED && o->precision != LRX_MIXED_BF16)
+        fail(LRX_EINVAL, "precision must be LRX_FP64, LRX_MIXED or LRX_MIXED_BF16");
     if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
     if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
 }
@@ -1884,6 +2079,35 @@ void init_handle(lrx_handle h, const lrx_csr* A, const double* val_dev, const lr
         HIPCHK(hipStreamSynchronize(s0));     // d_src, d_vh go out of scope
     } else {
         HIPCHK(hipStreamSynchronize(s0));     // rp and the host vectors go out of scope
+    }
+}
+
+// lrx_gmres multiplies by the handle's resident copy of A: the caller's A must
+// be that matrix, pattern and values, entry for entry (compared in tree order
+// with the copy read back from the device).
+void check_same_matrix(lrx_handle h, const lrx_csr* A) {
+    const Plan& P = h->plan;
+    const int32_t n = A->n;
+    std::vector<int64_t> rp((size_t)n + 1);
+    std::vector<int32_t> ci((size_t)std::max<int64_t>(A->nnz, 1));
+    std::vector<double> va((size_t)std::max<int64_t>(A->nnz, 1));
+    HIPCHK(hipMemcpyAsync(rp.data(), h->d_rp.p, rp.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    if (A->nnz) {
+        HIPCHK(hipMemcpyAsync(ci.data(), h->d_ci.p, (size_t)A->nnz * 4, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(va.data(), h->d_val.p, (size_t)A->nnz * 8, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t r = P.perm[t];
+        if (A->row_ptr[r + 1] - A->row_ptr[r] != rp[t + 1] - rp[t])
+            fail(LRX_EINVAL, "A's pattern differs from the matrix the handle was factored from");
+        int64_t q = rp[t];
+        for (int64_t e = A->row_ptr[r]; e < A->row_ptr[r + 1]; ++e, ++q) {
+            if (A->col_idx[e] < 0 || A->col_idx[e] >= n || ci[q] != P.pos[A->col_idx[e]])
+                fail(LRX_EINVAL, "A's pattern differs from the matrix the handle was factored from");
+            if (va[q] != A->val[e])
+                fail(LRX_EINVAL, "A's values differ from the matrix the handle was factored from");
+        }
     }
 }
 
@@ -2088,6 +2312,43 @@ void lrx_timing_enable(int32_t class_mask) {
     g_timing = (uint32_t)class_mask;
 }
 
+lrx_status lrx_tune_get(lrx_tune* t) {
+    return guarded([&]() -> lrx_status {
+        if (!t) fail(LRX_EINVAL, "null tuning table");
+        *t = lrx_tune{};
+        t->gemm_kc = g_tune.gemm_kc;
+        t->gemm_f64_valu = g_tune.gemm_f64_valu;
+        t->sweep_nk_max = g_tune.sweep_nk_max;
+        t->compress_nt_small = g_tune.compress_nt_small;
+        t->compress_nt_mid = g_tune.compress_nt_mid;
+        t->gemm_grid = g_tune.gemm_grid;
+        t->solve_graph = g_tune.solve_graph;
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_tune_set(const lrx_tune* t) {
+    return guarded([&]() -> lrx_status {
+        if (!t) fail(LRX_EINVAL, "null tuning table");
+        if (t->gemm_kc < 16 || t->gemm_kc > 256 || t->gemm_kc % 16) fail(LRX_EINVAL, "gemm_kc must be 16..256, a multiple of 16");
+        if (t->gemm_f64_valu != 0 && t->gemm_f64_valu != 1) fail(LRX_EINVAL, "gemm_f64_valu must be 0 or 1");
+        if (t->sweep_nk_max != 1 && t->sweep_nk_max != 2 && t->sweep_nk_max != 4 && t->sweep_nk_max != 8)
+            fail(LRX_EINVAL, "sweep_nk_max must be 1, 2, 4 or 8");
+        for (int32_t v : {t->compress_nt_small, t->compress_nt_mid})
+            if (v != 256 && v != 512 && v != 1024) fail(LRX_EINVAL, "compress_nt_* must be 256, 512 or 1024");
+        if (t->gemm_grid < 0 || t->gemm_grid > 65536) fail(LRX_EINVAL, "gemm_grid must be 0..65536");
+        if (t->solve_graph != 0 && t->solve_graph != 1) fail(LRX_EINVAL, "solve_graph must be 0 or 1");
+        g_tune.solve_graph = t->solve_graph;
+        g_tune.gemm_kc = t->gemm_kc;
+        g_tune.compress_nt_small = t->compress_nt_small;
+        g_tune.compress_nt_mid = t->compress_nt_mid;
+        g_tune.gemm_grid = t->gemm_grid;
+        g_tune.gemm_f64_valu = t->gemm_f64_valu;
+        g_tune.sweep_nk_max = t->sweep_nk_max;
+        return LRX_OK;
+    });
+}
+
 lrx_status lrx_timing_read(lrx_timing_t* t, int32_t reset) {
     return guarded([&]() -> lrx_status {
         if (!t) fail(LRX_EINVAL, "null timing");
@@ -2131,6 +2392,18 @@ lrx_status lrx_gmres_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, co
     });
 }
 
+lrx_status lrx_gmres_batch_dev_x0(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
+                                  double* const* x_dev, double tol, int32_t restart, int32_t maxit, int32_t* iters,
+                                  double* relres) {
+    return guarded([&]() -> lrx_status {
+        check_batch(k, hs, nrhs, b_dev, x_dev);
+        if (!(tol > 0.0) || restart < 1 || restart > 200 || maxit < 0) fail(LRX_EINVAL, "bad tol/restart/maxit");
+        lrx_status s = gmres_batch(k, hs, nrhs, b_dev, x_dev, tol, restart, maxit, iters, relres, true);
+        if (s == LRX_ENOCONV) g_err = "GMRES reached maxit before tol";
+        return s;
+    });
+}
+
 lrx_status lrx_solve(lrx_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx) {
     return guarded([&]() -> lrx_status {
         check_handle(h);
@@ -2169,6 +2442,8 @@ lrx_status lrx_gmres(const lrx_csr* A, lrx_handle h, int32_t nrhs, const double*
     return guarded([&]() -> lrx_status {
         check_handle(h);
         if (!A || A->n != h->plan.n || A->nnz != h->nnz) fail(LRX_EINVAL, "A does not match the handle");
+        check_csr(A);
+        check_same_matrix(h, A);
         const int32_t n = h->plan.n;
         if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
         if (!b || !x) fail(LRX_EINVAL, "null b/x");
@@ -2210,11 +2485,37 @@ lrx_status lrx_free(lrx_handle h) {
     });
 }
 
+// Device bytes a handle holds now: arena chunks (capacity) and every buffer.
+int64_t handle_device_bytes(lrx_handle h) {
+    int64_t b = 0;
+    for (const Arena* a : {&h->arena, &h->arena32})
+        for (const auto& c : a->chunks) b += (int64_t)(c.second * sizeof(double));
+    for (const DevBuf* d : {&h->d_swnodes, &h->d_swprog, &h->batch_nodes, &h->d_perm, &h->d_rp, &h->d_ci, &h->d_val,
+                            &h->x_ext, &h->ws_b, &h->ws_w, &h->g_basis, &h->g_z, &h->g_w, &h->g_r, &h->g_b, &h->g_x,
+                            &h->kry_tab, &h->kry_small, &h->kry_part})
+        b += (int64_t)d->bytes;
+    return b;
+}
+
+lrx_status lrx_trim(lrx_handle h) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        IdleScope idle;
+        for (DevBuf* d : {&h->x_ext, &h->g_basis, &h->g_z, &h->g_w, &h->g_r, &h->g_b, &h->g_x, &h->kry_tab,
+                          &h->kry_small, &h->kry_part, &h->batch_nodes})
+            d->release();
+        h->kry_pin.release();
+        return LRX_OK;
+    });
+}
+
 lrx_status lrx_stats(lrx_handle h, lrx_stats_t* s) {
     return guarded([&]() -> lrx_status {
         check_handle(h);
         if (!s) fail(LRX_EINVAL, "null stats");
         *s = h->stats;
+        s->device_bytes = handle_device_bytes(h);
         return LRX_OK;
     });
 }

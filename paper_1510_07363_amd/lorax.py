@@ -18,12 +18,12 @@ LIB_PATH = os.path.join(_HERE, "liblorax.so")
 LRX_OK, LRX_EINVAL, LRX_ENOMEM, LRX_ESINGULAR, LRX_ENOCONV, LRX_EDEVICE, LRX_EBUSY = range(7)
 STATUS_NAMES = {0: "LRX_OK", 1: "LRX_EINVAL", 2: "LRX_ENOMEM", 3: "LRX_ESINGULAR",
                 4: "LRX_ENOCONV", 5: "LRX_EDEVICE", 6: "LRX_EBUSY"}
-LRX_FP64, LRX_MIXED = 0, 1
+LRX_FP64, LRX_MIXED, LRX_MIXED_BF16 = 0, 1, 2
 LRX_COLORED, LRX_NATURAL = 0, 1
 ORDERS = {"colored": LRX_COLORED, "natural": LRX_NATURAL}
 LRX_SVD, LRX_RRQR = 0, 1
 COMPRESS = {"svd": LRX_SVD, "rrqr": LRX_RRQR}
-PRECISION = {"fp64": LRX_FP64, "mixed": LRX_MIXED}
+PRECISION = {"fp64": LRX_FP64, "mixed": LRX_MIXED, "mixed_bf16": LRX_MIXED_BF16}
 
 
 class LoraxError(RuntimeError):
@@ -57,7 +57,9 @@ class Stats(C.Structure):
                 ("factor_bytes", C.c_int64),
                 ("solve_bytes", C.c_int64), ("factor_flops", C.c_int64),
                 ("t_plan_ms", C.c_double), ("t_factor_ms", C.c_double),
-                ("t_sync_ms", C.c_double), ("t_solve_prog_ms", C.c_double)]
+                ("t_sync_ms", C.c_double), ("t_solve_prog_ms", C.c_double),
+                ("device_bytes", C.c_int64), ("flops_compress", C.c_double), ("flops_pivot", C.c_double),
+                ("flops_schur", C.c_double), ("flops_project", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -70,7 +72,7 @@ class Timing(C.Structure):
 
 
 KERNEL_CLASSES = {0: "compress", 1: "factor_node", 2: "solve_fwd", 3: "solve_bwd", 4: "spmv",
-                  5: "schur"}
+                  5: "schur", 6: "project"}
 
 
 class PlanInfo(C.Structure):
@@ -80,11 +82,22 @@ class PlanInfo(C.Structure):
                 ("n_edges_created", C.c_int64), ("candidates_by_level", C.c_int64 * 32)]
 
 
+class Tune(C.Structure):
+    _fields_ = [("gemm_kc", C.c_int32), ("gemm_f64_valu", C.c_int32), ("sweep_nk_max", C.c_int32),
+                ("compress_nt_small", C.c_int32), ("compress_nt_mid", C.c_int32), ("gemm_grid", C.c_int32),
+                ("solve_graph", C.c_int32), ("reserved", C.c_int32 * 1)]
+
+
+TUNE_FIELDS = ("gemm_kc", "gemm_f64_valu", "sweep_nk_max", "compress_nt_small", "compress_nt_mid", "gemm_grid",
+               "solve_graph")
+
+
 # every symbol declared in include/lorax.h
 EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_factor_batch", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
            "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev", "lrx_gmres_batch_dev", "lrx_set_stream",
            "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
-           "lrx_last_error", "lrx_version")
+           "lrx_last_error", "lrx_version", "lrx_tune_get", "lrx_tune_set",
+           "lrx_gmres_batch_dev_x0", "lrx_trim")
 
 
 def _load():
@@ -110,7 +123,10 @@ def _load():
                                     C.c_int32, C.c_int32, i32p, f64p]),
         "lrx_gmres_batch_dev": (C.c_int, [C.c_int32, P(C.c_void_p), C.c_int32, P(C.c_void_p),
                                           P(C.c_void_p), C.c_double, C.c_int32, C.c_int32, i32p, f64p]),
+        "lrx_gmres_batch_dev_x0": (C.c_int, [C.c_int32, P(C.c_void_p), C.c_int32, P(C.c_void_p),
+                                             P(C.c_void_p), C.c_double, C.c_int32, C.c_int32, i32p, f64p]),
         "lrx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "lrx_trim": (C.c_int, [C.c_void_p]),
         "lrx_free": (C.c_int, [C.c_void_p]),
         "lrx_stats": (C.c_int, [C.c_void_p, P(Stats)]),
         "lrx_ranks": (C.c_int, [C.c_void_p, i32p, i32p, i32p]),
@@ -118,6 +134,8 @@ def _load():
         "lrx_plan_inspect": (C.c_int, [P(Csr), P(Tree), C.c_int32, P(PlanInfo)]),
         "lrx_last_error": (C.c_char_p, []),
         "lrx_version": (C.c_char_p, []),
+        "lrx_tune_get": (C.c_int, [P(Tune)]),
+        "lrx_tune_set": (C.c_int, [P(Tune)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -158,6 +176,24 @@ class _TreeArgs:
         self.perm = np.ascontiguousarray(perm, dtype=np.int32)
         self.lp = np.ascontiguousarray(leaf_ptr, dtype=np.int32)
         self.s = Tree(int(depth), _ptr(self.perm, C.c_int32), _ptr(self.lp, C.c_int32))
+
+
+def tune_get():
+    """Current launch shapes of the hot kernels (lrx_tune_get) as a dict."""
+    t = Tune()
+    _check(_lib.lrx_tune_get(C.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNE_FIELDS}
+
+
+def tune_set(**fields):
+    """Sets some launch shapes (lrx_tune_set); the others keep their values."""
+    cur = tune_get()
+    for k, v in fields.items():
+        if k not in TUNE_FIELDS:
+            raise KeyError(k)
+        cur[k] = int(v)
+    t = Tune(*[cur[f] for f in TUNE_FIELDS])
+    _check(_lib.lrx_tune_set(C.byref(t)))
 
 
 def timing_enable(classes=None):
@@ -258,8 +294,16 @@ class Factor:
                               _ptr(X, C.c_double), self.n))
         return X[:, 0] if vec else X
 
-    def gmres(self, b, tol=1e-10, restart=30, maxit=500, raise_on_noconv=True):
-        """Right-preconditioned GMRES; returns (x, iters, relres)."""
+    def gmres(self, b, tol=1e-10, restart=30, maxit=500, raise_on_noconv=True, val=None):
+        """Right-preconditioned GMRES; returns (x, iters, relres).  A is the
+        matrix factored (its host values; pass val for a handle factored from
+        device values); the library rejects a matrix that differs from the
+        handle's resident copy."""
+        A = self._A
+        if val is not None:
+            A = _CsrArgs(self._A.rp, self._A.ci, val)
+        if len(A.v) != len(A.ci):
+            raise ValueError("the handle was factored from device values: pass val")
         b = np.asarray(b, dtype=np.float64)
         vec = b.ndim == 1
         B = np.asfortranarray(b.reshape(self.n, -1))
@@ -267,7 +311,7 @@ class Factor:
         X = np.zeros_like(B, order="F")
         its = np.zeros(k, dtype=np.int32)
         rr = np.zeros(k, dtype=np.float64)
-        st = _lib.lrx_gmres(C.byref(self._A.s), self._h, k, _ptr(B, C.c_double),
+        st = _lib.lrx_gmres(C.byref(A.s), self._h, k, _ptr(B, C.c_double),
                             _ptr(X, C.c_double), float(tol), int(restart), int(maxit),
                             _ptr(its, C.c_int32), _ptr(rr, C.c_double))
         if st != LRX_OK and (st != LRX_ENOCONV or raise_on_noconv):
@@ -306,7 +350,10 @@ class Factor:
                     factor_bytes=int(s.factor_bytes),
                     solve_bytes=int(s.solve_bytes), factor_flops=int(s.factor_flops),
                     t_plan_ms=float(s.t_plan_ms), t_factor_ms=float(s.t_factor_ms),
-                    t_sync_ms=float(s.t_sync_ms), t_solve_prog_ms=float(s.t_solve_prog_ms))
+                    t_sync_ms=float(s.t_sync_ms), t_solve_prog_ms=float(s.t_solve_prog_ms),
+                    device_bytes=int(s.device_bytes),
+                    flops_by_op={"compress": float(s.flops_compress), "pivot": float(s.flops_pivot),
+                                 "schur": float(s.flops_schur), "project": float(s.flops_project)})
 
     def ranks(self):
         n = self.stats()["n_compressions"]
@@ -324,6 +371,10 @@ class Factor:
         _check(_lib.lrx_compression_tails(self._h, int(idx), _ptr(out, C.c_double), n.value,
                                           C.byref(n)))
         return out[:n.value]
+
+    def trim(self):
+        """Releases the solve/GMRES workspaces (lrx_trim); the factor stays resident."""
+        _check(_lib.lrx_trim(self._h))
 
     def set_stream(self, stream):
         """Later solves and GMRES calls run on this HIP stream (an int address, or None)."""
@@ -352,9 +403,10 @@ def solve_batch_dev(factors, nrhs, b_ptrs, x_ptrs):
     _check(_lib.lrx_solve_batch_dev(int(k), hs, int(nrhs), bs, xs))
 
 
-def gmres_batch_dev(factors, nrhs, b_ptrs, x_ptrs, tol=1e-10, restart=30, maxit=500):
+def gmres_batch_dev(factors, nrhs, b_ptrs, x_ptrs, tol=1e-10, restart=30, maxit=500, x0=False):
     """lrx_gmres_batch_dev: FGMRES of every factor's system in lock-step.
     b_ptrs[i], x_ptrs[i]: device addresses of n_i x nrhs column-major FP64 arrays.
+    x0: x_ptrs hold the initial guesses (lrx_gmres_batch_dev_x0).
     Returns (iters, relres, status), each array of shape (k, nrhs)."""
     k = len(factors)
     hs = (C.c_void_p * k)(*[f._h.value for f in factors])
@@ -362,8 +414,9 @@ def gmres_batch_dev(factors, nrhs, b_ptrs, x_ptrs, tol=1e-10, restart=30, maxit=
     xp = (C.c_void_p * k)(*[int(p) for p in x_ptrs])
     its = np.zeros((k, nrhs), dtype=np.int32)
     rr = np.zeros((k, nrhs), dtype=np.float64)
-    st = _lib.lrx_gmres_batch_dev(k, hs, int(nrhs), bp, xp, float(tol), int(restart), int(maxit),
-                                  _ptr(its, C.c_int32), _ptr(rr, C.c_double))
+    fn = _lib.lrx_gmres_batch_dev_x0 if x0 else _lib.lrx_gmres_batch_dev
+    st = fn(k, hs, int(nrhs), bp, xp, float(tol), int(restart), int(maxit), _ptr(its, C.c_int32),
+            _ptr(rr, C.c_double))
     if st not in (LRX_OK, LRX_ENOCONV):
         _check(st)
     return its, rr, st

@@ -1,0 +1,76 @@
+"""Helpers shared by the GPU parity tests (no test functions here).
+
+Parity protocol for the FP64 mode (solutions, not stored blocks, are compared,
+because V is unique only up to an orthogonal change of basis, Sec. 4.3):
+  * the rank of every compression equals the oracle's; where one differs, every
+    singular value between the two cuts lies at the threshold within the
+    rounding band max(1e-8, 1e-13 / eps), and the oracle is re-run with the
+    GPU's ranks (rank replay);
+  * ||x_gpu - x_oracle|| / ||x_oracle|| <= 1e-10 for the stand-alone solve.
+"""
+import numpy as np
+
+import oracle
+from paper_1510_07363_amd import workloads as w
+
+TOL = 1e-10
+
+
+def grid(kind, nx, leaf, seed=0):
+    rng = np.random.default_rng(seed)
+    if kind == "poisson2d":
+        csr, co = w.poisson2d(nx), w.grid_coords((nx, nx))
+    elif kind == "varcoef2d":
+        csr = w.diffusion2d(np.exp(w.gaussian_field_2d((nx, nx), rng, 8.0)), (nx, nx))
+        co = w.grid_coords((nx, nx))
+    elif kind == "convdiff3d":
+        csr, co = w.convdiff3d(nx), w.grid_coords((nx, nx, nx))
+    elif kind == "lognormal3d":
+        csr = w.diffusion3d(np.exp(rng.standard_normal(nx ** 3)), (nx, nx, nx))
+        co = w.grid_coords((nx, nx, nx))
+    elif kind == "lognormal2d":
+        csr = w.diffusion2d(np.exp(rng.standard_normal(nx * nx)), (nx, nx))
+        co = w.grid_coords((nx, nx))
+    elif kind == "convdiff2d":
+        csr, co = w.convdiff2d(nx), w.grid_coords((nx, nx))
+    else:
+        raise KeyError(kind)
+    n = len(csr[0]) - 1
+    depth = w.tree_depth(n, leaf)
+    perm, lp = w.rcb_tree(co, depth)
+    return csr, n, perm, lp, depth, rng
+
+
+def relerr(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def replay_ranks(gpu_ranks, Fo, eps, method="svd"):
+    """None if every rank agrees, else the GPU's ranks as {(level, j): rank}
+    after checking that each disagreement is a threshold tie."""
+    gpu = [int(r) for r in gpu_ranks]
+    ora = [c.rank for c in Fo.compressions]
+    assert len(gpu) == len(ora)
+    if gpu == ora:
+        return None
+    assert method == "svd", "RRQR ranks must agree exactly on these inputs"
+    band = max(1e-8, 1e-13 / eps)
+    for rg, c in zip(gpu, Fo.compressions):
+        if rg == c.rank:
+            continue
+        sig = np.asarray(c.sigma) / c.sigma[0]
+        for k in range(min(rg, c.rank), max(rg, c.rank)):
+            assert abs(sig[k] / eps - 1.0) <= band, (c.level, c.j, rg, c.rank, sig[k])
+    return {(c.level, c.j): rg for rg, c in zip(gpu, Fo.compressions)}
+
+
+def oracle_matching(F, csr, perm, lp, depth, eps, Fo=None, order="colored", method="svd"):
+    """The oracle's factorization of the same input, rank-replayed onto the
+    GPU handle F's ranks where they differ by a threshold tie."""
+    if Fo is None:
+        Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False)
+    forced = replay_ranks(F.ranks()[0], Fo, eps, method) if eps > 1e-10 else None
+    if forced is not None:
+        Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False,
+                           forced_ranks=forced)
+    return Fo

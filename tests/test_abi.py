@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "lorax.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lrx_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lrx_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -104,3 +104,25 @@ def test_factor_rejects_nonfinite_and_eps():
     with pytest.raises(lorax.LoraxError) as e:
         lorax.Factor(p.row_ptr, p.col_idx, p.val, p.perm, p.leaf_ptr, p.depth, 1.5)
     assert e.value.status == lorax.LRX_EINVAL
+
+
+def test_tune_table_validation():
+    """lrx_tune_set accepts the documented ranges and rejects the rest (host only)."""
+    from paper_1510_07363_amd import lorax
+    base = lorax.tune_get()
+    assert base["gemm_kc"] % 16 == 0 and base["sweep_nk_max"] in (1, 2, 4, 8)
+    try:
+        lorax.tune_set(gemm_kc=64, sweep_nk_max=4, gemm_f64_valu=1, compress_nt_small=256, compress_nt_mid=512,
+                       gemm_grid=1024, solve_graph=0)
+        assert lorax.tune_get() == {"gemm_kc": 64, "gemm_f64_valu": 1, "sweep_nk_max": 4,
+                                    "compress_nt_small": 256, "compress_nt_mid": 512, "gemm_grid": 1024,
+                                    "solve_graph": 0}
+        for bad in ({"gemm_kc": 24}, {"gemm_kc": 512}, {"sweep_nk_max": 3}, {"gemm_f64_valu": 2},
+                    {"compress_nt_small": 128}, {"compress_nt_mid": 2048}, {"gemm_grid": -1},
+                    {"solve_graph": 2}):
+            with pytest.raises(lorax.LoraxError) as e:
+                lorax.tune_set(**bad)
+            assert e.value.status == lorax.LRX_EINVAL
+        assert lorax.tune_get()["gemm_kc"] == 64          # a rejected call changes nothing
+    finally:
+        lorax.tune_set(**base)

@@ -44,3 +44,12 @@ def test_roofline_alu_and_hbm_entries():
     assert r["peak"] == 157.3 and r["frac"] == pytest.approx(78.6 / 157.3)
     t2 = {"factor_node": dict(t["compress"])}
     assert bench.roofline(t2, "factor_node", "mixed")["peak"] == 78.6
+
+
+def test_roofline_mfma_classes():
+    t = {"schur": {"launches": 2, "total_ms": 2.0, "bytes": 0.0, "flops": 2 * 78.6e9}}
+    r = bench.roofline(t, "schur", "fp64")
+    assert r["bound"] == "mfma" and r["peak"] == 78.6 and r["frac"] == pytest.approx(1.0)
+    assert bench.roofline(t, "schur", "mixed")["peak"] == 157.3
+    t = {"project": dict(t["schur"])}
+    assert bench.roofline(t, "project", "mixed_bf16")["peak"] == 2500.0

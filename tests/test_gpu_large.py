@@ -8,8 +8,12 @@ The variants of one colour step run side by side on forked streams.  The bar,
 as for the small blocks: the singular values of every stacked block (the
 truncation tails the library reports) match the FP64 oracle's SVD of its own
 stacked block (Sec. 4.3, the cut-off sigma_k >= epsilon sigma_0) to rounding
-accumulated over the levels, the truncation rule holds, GMRES reaches the true
-residual, and a batch reproduces the single factorizations bit for bit.
+accumulated over the levels, the truncation rule holds, the FP64 stand-alone
+solve equals the oracle's solve to 1e-10 (rank replay on threshold ties; the
+solve is invariant only under orthogonal changes of basis inside the kept
+subspace, so a wrong V in any variant moves it far beyond that), GMRES
+reaches the true residual, and a batch reproduces the single factorizations
+bit for bit.
 """
 import numpy as np
 import pytest
@@ -17,6 +21,7 @@ import scipy.sparse as sp
 
 import oracle
 from paper_1510_07363_amd import workloads as w
+from parity_util import TOL, oracle_matching, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +84,10 @@ def test_wide_blocks_sigma_match_oracle(env):
     assert wide >= 8
     A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n))
     b = rng.uniform(-1, 1, (n, 2))
+    Fr = oracle_matching(F, csr, perm, lp, depth, eps, Fo=Fo)
+    err = relerr(F.solve(b), np.column_stack([oracle.solve(Fr, b[:, k]) for k in range(2)]))
+    print(f"FP64 solve vs oracle: {err:.2e}")
+    assert err <= TOL
     for prec in ("fp64", "mixed"):
         Fp = F if prec == "fp64" else lx.Factor(*csr, perm, lp, depth, eps, precision="mixed")
         x, its, rr = Fp.gmres(b, tol=1e-10, restart=30, maxit=200)
@@ -102,6 +111,11 @@ def test_tall_block_sigma_match_oracle(env):
     medium = _check_sigmas(F, Fo, eps, lambda M, c: 64 < c <= 192 and M * c < 300000)
     print(f"tall blocks compared: {tall}, one-work-group blocks: {medium}")
     assert tall >= 1 and medium >= 20
+    b = rng.uniform(-1, 1, (n, 2))
+    Fr = oracle_matching(F, csr, perm, lp, depth, eps, Fo=Fo)
+    err = relerr(F.solve(b), np.column_stack([oracle.solve(Fr, b[:, k]) for k in range(2)]))
+    print(f"FP64 solve vs oracle: {err:.2e}")
+    assert err <= TOL
 
 
 def test_wide_blocks_batch_equals_single(env):

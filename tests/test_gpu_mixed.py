@@ -1,8 +1,10 @@
 """Mixed precision (LRX_MIXED) on the GPU, through the C ABI.
 
-In this mode the compression arithmetic runs in FP32 (epsilon >= 1e-5) and the
-solve reads FP32 copies of the stored off-diagonal blocks, while pivot
-inverses, Schur updates, solve accumulation and GMRES stay FP64.  The bar: GMRES reaches the
+In this mode (epsilon >= 1e-5) the compression arithmetic runs in FP32, the
+Schur-complement GEMMs and the projection B V take FP32 operands with FP32
+accumulation on the matrix cores, and the solve reads FP32 copies of the stored
+off-diagonal blocks, while pivot inverses, W_k = S^-1 Mat(k->s), solve
+accumulation and GMRES stay FP64.  The bar: GMRES reaches the
 same FP64 true relative residual (1e-10) as the FP64 path; the distance of the
 result to the FP64 oracle's FGMRES solution is reported and bounded by the
 conditioning, ||x - x_o|| <= ||A^{-1}||_2 (||r|| + ||r_o||); the mixed
@@ -94,9 +96,10 @@ def test_mixed_preconditioner_quality_and_linearity(lx):
     for k in range(B.shape[1]):
         rm = np.linalg.norm(A @ Xm[:, k] - B[:, k]) / np.linalg.norm(B[:, k])
         rd = np.linalg.norm(A @ Xd[:, k] - B[:, k]) / np.linalg.norm(B[:, k])
-        # FP32 Jacobi stops at |gamma| <= c u sqrt(alpha beta) (u = 6e-8), which moves the
-        # kept subspaces by about 1e-5 relative: a perturbation of the epsilon-level
-        # approximation, not of its order
+        # the FP32 arithmetic (Jacobi stopped after a sweep whose rotations all stayed
+        # below sqrt(tol), tol = 3.6 c u, u = 6e-8; FP32 Schur products) moves the kept
+        # subspaces and the updates at the FP32 level: a perturbation of the
+        # epsilon-level approximation, not of its order
         print(f"stand-alone relative residual: mixed {rm:.2e}, fp64 {rd:.2e}")
         assert rm <= 10.0 * rd + 1e-6, (rm, rd)
     y = Fm.solve(2.0 * B[:, 0] - 3.0 * B[:, 1])
@@ -115,3 +118,25 @@ def test_mixed_factor_footprint(lx):
           f"solve bytes {Sm['solve_bytes'] / Sd['solve_bytes']:.3f}")
     assert 0.5 <= Sm["solve_bytes"] / Sd["solve_bytes"] < 0.9
     assert Sm["factor_bytes"] < 0.9 * Sd["factor_bytes"]
+
+
+@pytest.mark.parametrize("kind,nx,leaf,eps", [("varcoef2d", 64, 64, 1e-4), ("convdiff3d", 16, 64, 1e-3)])
+def test_bf16_projection_trial(lx, kind, nx, leaf, eps):
+    """LRX_MIXED_BF16: the projection B V of every compression on BF16 operands.
+    Measured, not assumed: the stand-alone residual of the preconditioner, the
+    GMRES iterations against LRX_MIXED, and the true residual, which GMRES must
+    still bring to 1e-10 (BF16 input rounding, about 4e-3 relative, exceeds
+    epsilon, so the compression bound of the FP32 mode is not claimed)."""
+    csr, A, n, perm, lp, depth, rng = _grid(kind, nx, leaf)
+    b = rng.uniform(-1, 1, (n, 2))
+    Fb = lx.Factor(*csr, perm, lp, depth, eps, precision="mixed_bf16")
+    Fm = lx.Factor(*csr, perm, lp, depth, eps, precision="mixed")
+    rb = np.linalg.norm(A @ Fb.solve(b) - b, axis=0) / np.linalg.norm(b, axis=0)
+    rm = np.linalg.norm(A @ Fm.solve(b) - b, axis=0) / np.linalg.norm(b, axis=0)
+    xb, itb, rrb = Fb.gmres(b, tol=TOL, restart=30, maxit=500)
+    xm, itm, rrm = Fm.gmres(b, tol=TOL, restart=30, maxit=500)
+    res = np.linalg.norm(A @ xb - b, axis=0) / np.linalg.norm(b, axis=0)
+    print(f"{kind}: stand-alone residual bf16 {rb.max():.2e} vs fp32 {rm.max():.2e}; "
+          f"GMRES iterations bf16 {list(itb)} vs fp32 {list(itm)}; true residual {res.max():.2e}")
+    assert (res <= TOL).all() and (rrb <= TOL).all()
+    assert rb.max() < 0.5          # still a preconditioner

@@ -244,3 +244,16 @@ def test_singular_pivot_reported(lx):
     with pytest.raises(lx.LoraxError) as e:
         lx.Factor(A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, perm, lp, depth, 1e-6)
     assert e.value.status == lx.LRX_ESINGULAR
+
+
+def test_gmres_rejects_other_matrix(lx):
+    """lrx_gmres multiplies by the handle's resident A: a caller's matrix with
+    other values (same pattern) is rejected, the matrix itself is accepted."""
+    csr, n, perm, lp, depth, rng = _grid("poisson2d", 16, 8)
+    F = lx.Factor(*csr, perm, lp, depth, 1e-6)
+    b = rng.uniform(-1, 1, n)
+    with pytest.raises(lx.LoraxError) as e:
+        F.gmres(b, val=csr[2] * 1.5)
+    assert e.value.status == lx.LRX_EINVAL
+    x, its, rr = F.gmres(b, val=csr[2].copy())
+    assert rr[0] <= TOL
