@@ -189,6 +189,21 @@ lrx_status lrx_solve(lrx_handle h, int32_t nrhs, const double* b, int64_t ldb,
  * b and x are n x nrhs with leading dimension n, column-major, may not alias. */
 lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): lrx_solve_dev
+ * with the extended vector (n + auxiliary variables, times nrhs doubles) in a
+ * static device array of the library, 32 MiB per device, held until the
+ * process ends, instead of the handle's workspace.  It allocates nothing and
+ * records no timing events.  The array's device address is looked up on the
+ * first call on each device (the handle's device must be current).  Every call
+ * on one device shares that array: calls that overlap on one device (other
+ * streams or threads) race and give wrong results; calls queued on one stream
+ * are ordered and safe.  Results equal lrx_solve_dev's bit for bit.
+ * Errors: LRX_EINVAL when n_ext * nrhs * 8 exceeds 32 MiB (lrx_stats gives
+ * n_ext as extended_size), for bad pointers or nrhs, or when the handle's
+ * device is not current. */
+lrx_status lrx_solve_dev_noalloc(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev);
+
 /* Batched form of lrx_solve_dev: k distinct handles on the same device, nrhs
  * right-hand sides each; b_dev[i], x_dev[i] are n_i x nrhs
  * column-major in HBM.  Every (level, colour) step of the sweeps is one launch

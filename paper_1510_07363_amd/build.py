@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblorax.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "sweep.cpp", "lorax.cpp", "kernels.hip", "gemm.hip"]
+SOURCES = ["plan.cpp", "sweep.cpp", "lorax.cpp", "kernels.hip", "gemm.hip", "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -72,6 +72,12 @@ hipError_t launch_gemm_mfma(const DGemm* g, const DTile* tiles, int ntile, int k
 // and each run states its blocks' storage type, so nodes of several
 // factorizations (FP64 or mixed precision) can share one launch.
 hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, hipStream_t st);
+// Device address of the static scratch array of the allocation-free entry
+// points on device dev (which must be current at the first call per device);
+// kNoallocScratchBytes per device, shared by every such call on that device.
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+hipError_t noalloc_scratch(int dev, void** ptr);
+
 // Copies of stored blocks (DConv: to FP32, or FP64 as is), one work-group per block.
 hipError_t launch_to_f32(const DConv* segs, int n, hipStream_t st);
 

@@ -2371,6 +2371,25 @@ lrx_status lrx_solve_dev(lrx_handle h, int32_t nrhs, const double* b_dev, double
     });
 }
 
+lrx_status lrx_solve_dev_noalloc(lrx_handle h, int32_t nrhs, const double* b_dev, double* x_dev) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (nrhs < 1 || nrhs > 256) fail(LRX_EINVAL, "nrhs must be in [1, 256]");
+        if (!b_dev || !x_dev || b_dev == x_dev) fail(LRX_EINVAL, "bad b/x pointers");
+        const size_t need = (size_t)h->n_ext * nrhs * sizeof(double);
+        if (need > kNoallocScratchBytes)
+            fail(LRX_EINVAL, "n_ext * nrhs * 8 = " + std::to_string(need) + " bytes exceeds the " +
+                                 std::to_string(kNoallocScratchBytes) + "-byte scratch of lrx_solve_dev_noalloc");
+        int cur = -1;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != h->device) fail(LRX_EINVAL, "the handle's device is not the current device");
+        void* p = nullptr;
+        HIPCHK(noalloc_scratch(h->device, &p));
+        solve_into(h, nrhs, b_dev, x_dev, static_cast<double*>(p), false);
+        return LRX_OK;
+    });
+}
+
 lrx_status lrx_solve_batch_dev(int32_t k, const lrx_handle* hs, int32_t nrhs, const double* const* b_dev,
                                double* const* x_dev) {
     return guarded([&]() -> lrx_status {

@@ -97,7 +97,7 @@ EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_factor_batch", "lrx_timing_enabl
            "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev", "lrx_gmres_batch_dev", "lrx_set_stream",
            "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_plan_inspect",
            "lrx_last_error", "lrx_version", "lrx_tune_get", "lrx_tune_set",
-           "lrx_gmres_batch_dev_x0", "lrx_trim")
+           "lrx_solve_dev_noalloc", "lrx_gmres_batch_dev_x0", "lrx_trim")
 
 
 def _load():
@@ -115,6 +115,7 @@ def _load():
         "lrx_timing_read": (C.c_int, [P(Timing), C.c_int32]),
         "lrx_solve": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int64, f64p, C.c_int64]),
         "lrx_solve_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+        "lrx_solve_dev_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
         "lrx_solve_batch_dev": (C.c_int, [C.c_int32, P(C.c_void_p), C.c_int32, P(C.c_void_p),
                                           P(C.c_void_p)]),
         "lrx_gmres": (C.c_int, [P(Csr), C.c_void_p, C.c_int32, f64p, f64p, C.c_double,
@@ -322,6 +323,10 @@ class Factor:
     def solve_dev(self, b_ptr, x_ptr, nrhs):
         """b_ptr, x_ptr: device addresses of n x nrhs column-major FP64 arrays."""
         _check(_lib.lrx_solve_dev(self._h, int(nrhs), C.c_void_p(b_ptr), C.c_void_p(x_ptr)))
+
+    def solve_dev_noalloc(self, b_ptr, x_ptr, nrhs):
+        """solve_dev with the library's static device scratch (no allocation)."""
+        _check(_lib.lrx_solve_dev_noalloc(self._h, int(nrhs), C.c_void_p(b_ptr), C.c_void_p(x_ptr)))
 
     def gmres_dev(self, b_ptr, x_ptr, nrhs, tol=1e-10, restart=30, maxit=500):
         its = np.zeros(nrhs, dtype=np.int32)
