@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="arrivals per second")
     ap.add_argument("--serve-n-max", type=int, default=65536,
                     help="largest system of a factor request (the recipe has 262,144)")
+    ap.add_argument("--serve-cycle", type=int, default=8,
+                    help="Arnoldi steps per serving round (one FGMRES restart cycle; unconverged "
+                         "right-hand sides continue in the next round); 0: rounds solve to convergence")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only copy this many bytes device to device and exit (a plain copy of known "
                          "size, the reference for the HBM traffic counters)")
@@ -458,7 +461,8 @@ def main_serve(args, torch, lorax, workloads):
             bs.append(None)
     print(f"[serve] {len(reqs)} requests, {len(specs)} systems built", file=sys.stderr, flush=True)
     srv = Server(LoraxBackend(precision=args.precision), 200 << 30, tol=TOL, restart=RESTART,
-                 factor_backend=LoraxBackend(precision=args.precision), max_factor_batch=8)
+                 factor_backend=LoraxBackend(precision=args.precision), max_factor_batch=8,
+                 cycle=args.serve_cycle or None)
     for sp in specs.values():
         srv.register(sp)
     # warm-up (untimed): module load and first launches on a small system
@@ -520,12 +524,14 @@ def main_serve(args, torch, lorax, workloads):
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "serve", "requests": len(reqs), "rate_req_s": args.serve_rate,
+                   "cycle": args.serve_cycle,
                    "n_range": [16384, args.serve_n_max], "factor_requests": len(specs), "rhs_total": n_rhs,
                    "hbm_budget_gib": 200, "gmres": f"FGMRES({RESTART})", "tol": TOL, "precision": args.precision},
         "detail": {"latency_solve": srv.latency_stats("solve"), "latency_factor": srv.latency_stats("factor"),
                    "latency_all_p50_ms": float(np.percentile(lat_all, 50) * 1e3),
                    "latency_all_p99_ms": float(np.percentile(lat_all, 99) * 1e3),
-                   "requests_per_s": len(reqs) / T, "solve_rounds": len(srv.batches),
+                   "requests_per_s": len(reqs) / T, "solve_rounds": srv.n_rounds,
+                   "round": f"FGMRES({args.serve_cycle}) cycle" if args.serve_cycle else "solve to convergence",
                    "mean_systems_per_round": float(np.mean(srv.batches)) if srv.batches else 0.0,
                    "factored": srv.n_factored, "evicted": srv.n_evicted,
                    "resident_bytes_end": srv.resident_bytes()},

@@ -108,6 +108,8 @@ class Factorization:
     compressions: list
     order_index: dict         # node -> elimination position (Order(p))
     level_colours: dict       # i -> number of colours used
+    rule: str = "cutoff1"     # truncation rule
+    level_norm: dict = field(default_factory=dict)   # i -> N_i of eqn. curOff6 (rule 'frob')
 
     def ranks_by_level(self):
         out = defaultdict(list)
@@ -173,16 +175,27 @@ def _key(node):
 
 
 def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored",
-           forced_ranks=None, check=True, keep_blocks=False, compress="svd"):
+           forced_ranks=None, check=True, keep_blocks=False, compress="svd", rule="cutoff1"):
     """Algorithm 1.  Inputs are a CSR matrix (0-based) and the cluster tree.
 
     compress:     'svd' (eqn. cutOff1, as in the paper's experiments) or 'rrqr'.
+    rule:         'cutoff1': keep sigma_k >= epsilon sigma_0 of each stacked block
+                  (eqn. cutOff1; RRQR: ||R22||_F <= epsilon |R11|);
+                  'frob': the paper's variant of eqn. curOff6: the smallest k
+                  with ||B - B V_k V_k^T||_F < epsilon N_i, where N_i^2 is the sum
+                  of squared Frobenius norms of all blocks of the current level
+                  and of the levels below, each level's blocks taken when that
+                  level starts (after MergeRedNodes); the leaf level's blocks are
+                  the blocks of A, so N_l = ||A||_F.  RRQR: the first k with
+                  ||R22||_F < epsilon N_i.
 
     forced_ranks: optional {(level, j): rank} to replay ranks decided elsewhere.
     keep_blocks:  keep every stacked B and V in the compression records (tests).
     """
     if not (0.0 <= epsilon < 1.0):
         raise ValueError("epsilon must be in [0, 1)")
+    if rule not in ("cutoff1", "frob"):
+        raise ValueError(rule)
     if int(depth) < 1:
         raise ValueError("depth must be >= 1 (the root cluster is never a leaf)")
     T = ClusterTree(row_ptr, col_idx, perm, leaf_ptr, depth)
@@ -208,6 +221,8 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
     compressions = []
     order_index = {}
     level_colours = {}
+    level_norm = {}           # i -> N_i (rule 'frob')
+    norm2 = 0.0
     counter = 0
 
     def clus(node):
@@ -247,6 +262,9 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
         for (su, sv), M in merged.items():
             G.put(su, sv, M)
         events.append(("merge", i, groups))
+        # N_i^2 = N_{i+1}^2 + squared Frobenius norms of this level's blocks (eqn. curOff6)
+        norm2 += sum(float(np.sum(M * M)) for M in G.mat.values())
+        level_norm[i] = float(np.sqrt(norm2))
 
         js, cols = T.level_order(i, order)
         level_colours[i] = (max(cols) + 1) if cols else 0
@@ -267,7 +285,8 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
             forced = None
             if forced_ranks is not None and (i, j) in forced_ranks:
                 forced = int(forced_ranks[(i, j)])
-            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress)
+            tau = epsilon * level_norm[i] if rule == "frob" else None
+            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress, tau)
             rec.level, rec.j = i, j
             compressions.append(rec)
 
@@ -279,13 +298,14 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
                 events.append(("elim", fr))
 
     return Factorization(n, l, float(epsilon), order, T.perm.copy(), T.leaf_ptr.copy(),
-                         events, dict(G.size), compressions, order_index, level_colours)
+                         events, dict(G.size), compressions, order_index, level_colours, rule, level_norm)
 
 
-def rrqr_rows(B, epsilon, forced_rank=None):
+def rrqr_rows(B, epsilon, forced_rank=None, tau=None):
     """Column-pivoted Householder QR of B^T (pivots are rows of B), truncated at
-    the first k with ||R22||_F <= epsilon |R11|.  Returns (k, V, pivots, tails)
-    with V (m x k) orthonormal, tails[k] = ||R22^(k)||_F."""
+    the first k with ||R22||_F <= epsilon |R11| (or, given tau, the first k with
+    ||R22||_F < tau).  Returns (k, V, pivots, tails) with V (m x k) orthonormal,
+    tails[k] = ||R22^(k)||_F."""
     X = np.array(B, dtype=np.float64).T.copy()          # m x M
     m, M = X.shape
     kmax = min(m, M)
@@ -303,6 +323,9 @@ def rrqr_rows(B, epsilon, forced_rank=None):
             r11 = float(np.sqrt(nrm2[p]))
         if forced_rank is not None:
             if k >= forced_rank:
+                break
+        elif tau is not None:
+            if T < tau:
                 break
         elif T == 0.0 or T <= epsilon * r11:
             break
@@ -328,7 +351,7 @@ def rrqr_rows(B, epsilon, forced_rank=None):
 
 
 def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
-              method="svd"):
+              method="svd", tau=None):
     """Compress(s): replace the well-separated edges of s by low-rank edges through
     its black node b and the parent red node P = P(b) (Sec. 4.3, eqn. lra,
     eqn. anterpol, eqn. interpol and the edge-update list)."""
@@ -349,6 +372,12 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
             sig, Vt = np.zeros(0), np.zeros((0, m))
         if forced_rank is not None:
             r = forced_rank
+        elif tau is not None:
+            # eqn. curOff6: smallest k whose discarded tail has Frobenius norm < tau
+            # (tail_k^2 = sum of sigma_t^2 for t >= k); all of B when none does
+            tail2 = np.concatenate([np.cumsum((sig ** 2)[::-1])[::-1], [0.0]])
+            ok = np.nonzero(np.sqrt(tail2) < tau)[0]
+            r = int(ok[0]) if len(ok) else len(sig)
         elif len(sig) == 0 or sig[0] == 0.0:
             r = 0
         else:
@@ -356,7 +385,7 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
         V = Vt[:r].T.copy()                           # m x r, orthonormal columns
     elif method == "rrqr":
         if B.shape[0] > 0 and m > 0:
-            r, V, _, sig = rrqr_rows(B, epsilon, forced_rank)
+            r, V, _, sig = rrqr_rows(B, epsilon, forced_rank, tau)
             sig = np.asarray(sig)                     # ||R22^(k)||_F for k = 0..r
         else:
             r, V, sig = 0, np.zeros((m, 0)), np.zeros(0)

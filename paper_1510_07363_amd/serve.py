@@ -13,13 +13,26 @@ right-hand sides, Sec. 6.2).
   resident factors are evicted, least recently used first, and the job is
   retried, or it waits while solves on resident factors are in flight, or its
   requests fail when nothing more can be freed.
-* continuous batching: each round puts all ready solve requests, over every
-  resident system, into one lrx_gmres_batch_dev call (several requests on one
-  system are concatenated as extra right-hand sides; every system's block is
-  padded with zero columns to the batch's width, rounded up to a power of two).
-  Requests that arrive during a round join the next one.  A request's result
-  does not depend on which other systems share its batch; the width of the
-  batch changes only the summation order of its dot products.
+* admission counts device footprints: a resident system is charged what its
+  handle holds on the device (factor storage, solve programs, resident A and
+  the solve / GMRES workspaces it has grown to: lrx_stats device_bytes), and a
+  solve round first reserves the Krylov workspace it will grow, trimming the
+  workspaces of idle handles and then evicting idle systems when the budget
+  would be exceeded.  A round that still runs out of device memory evicts the
+  idle systems and is retried once.
+* continuous batching: each round puts the ready solve requests, over every
+  resident system, into batched FGMRES calls (several requests on one system
+  are concatenated as extra right-hand sides).  Systems are grouped by width
+  class (their own column count rounded up to a power of two), one call per
+  class, so a one-column request is never padded to the widest system's
+  width.  With `cycle` set, a round is one FGMRES restart cycle of `cycle`
+  Arnoldi steps: right-hand sides that have not converged carry their iterate
+  into the next round as its initial guess (lrx_gmres_batch_dev_x0), next to
+  requests that arrived meanwhile, so new work is admitted every `cycle` steps
+  instead of after whole solves.  Without `cycle` a round solves to
+  convergence (FGMRES(restart)).  A request's result does not depend on which
+  other systems share its batch; the width of its class changes only the
+  summation order of its dot products.
 * overlap: with `start()`, factor jobs run on a worker thread with their own
   backend (its own stream), so factorizations and solve rounds proceed on the
   device at the same time; without it, `step()` runs factor jobs inline.
@@ -67,6 +80,14 @@ class _Request:
     b: np.ndarray | None
     arrival: float
     future: cf.Future = field(default_factory=cf.Future)
+    # solves, across rounds: iterate, iterations, relative residuals, converged flags (per column)
+    x: np.ndarray | None = None
+    its: np.ndarray | None = None
+    rr: np.ndarray | None = None
+    conv: np.ndarray | None = None
+
+    def cols(self) -> int:
+        return 1 if self.b.ndim == 1 else self.b.shape[1]
 
 
 class OutOfBudget(Exception):
@@ -114,7 +135,12 @@ class LoraxBackend:
             raise
 
     def resident_bytes(self, handle) -> int:
-        return int(handle.stats()["factor_bytes"])
+        """Device bytes the handle holds now (factor, programs, A, workspaces)."""
+        return int(handle.stats()["device_bytes"])
+
+    def trim(self, handle) -> None:
+        """Releases the handle's solve/GMRES workspaces (the factor stays)."""
+        handle.trim()
 
     def adopt(self, handle) -> None:
         """A handle factored elsewhere is solved on this backend's stream."""
@@ -123,19 +149,30 @@ class LoraxBackend:
     def free(self, handle) -> None:
         handle.free()
 
-    def solve_batch(self, items, nrhs, tol, restart, maxit):
-        """items: list of (handle, B) with B of shape (n, nrhs); returns a list of
-        (X, iters, relres) in the same order."""
+    def solve_batch(self, items, nrhs, tol, restart, maxit, x0=False):
+        """items: list of (handle, B, X0) with B of shape (n, nrhs) and X0 the
+        initial guess (same shape) when x0 is set (else ignored); returns a list
+        of (X, iters, relres) in the same order.  Out of device memory raises
+        OutOfBudget."""
         torch, lx = self.torch, self.lx
         torch.cuda.set_device(self.device_index)
         with torch.cuda.stream(self.stream):
-            bs = [torch.from_numpy(np.ascontiguousarray(B.T)).to(self.device) for _, B in items]
-            xs = [torch.zeros_like(b) for b in bs]
+            bs = [torch.from_numpy(np.ascontiguousarray(B.T)).to(self.device) for _, B, _ in items]
+            if x0:
+                xs = [torch.from_numpy(np.ascontiguousarray(X0.T)).to(self.device) for _, _, X0 in items]
+            else:
+                xs = [torch.zeros_like(b) for b in bs]
             self.stream.synchronize()
             # the library runs the batch on the stream of the first handle; the
             # inputs above are complete before it starts
-            its, rr, st = lx.gmres_batch_dev([h for h, _ in items], nrhs, [b.data_ptr() for b in bs],
-                                             [x.data_ptr() for x in xs], tol=tol, restart=restart, maxit=maxit)
+            try:
+                its, rr, st = lx.gmres_batch_dev([h for h, _, _ in items], nrhs, [b.data_ptr() for b in bs],
+                                                 [x.data_ptr() for x in xs], tol=tol, restart=restart,
+                                                 maxit=maxit, x0=x0)
+            except lx.LoraxError as e:
+                if e.status == lx.LRX_ENOMEM:
+                    raise OutOfBudget(str(e)) from None
+                raise
             out = [(x.cpu().numpy().T, its[i], rr[i]) for i, x in enumerate(xs)]
         return out
 
@@ -149,7 +186,7 @@ class _Resident:
 
 class Server:
     def __init__(self, backend, hbm_budget_bytes, tol=1e-10, restart=30, maxit=500, max_batch_systems=256,
-                 max_width=256, factor_backend=None, max_factor_batch=1):
+                 max_width=256, factor_backend=None, max_factor_batch=1, cycle=None):
         if hbm_budget_bytes <= 0:
             raise ValueError("hbm_budget_bytes must be positive")
         self.backend = backend
@@ -159,6 +196,10 @@ class Server:
         self.max_batch_systems = max_batch_systems
         self.max_width = max_width
         self.max_factor_batch = max_factor_batch
+        if cycle is not None and not (1 <= int(cycle) <= restart):
+            raise ValueError("cycle must be in [1, restart]")
+        self.cycle = None if cycle is None else int(cycle)
+        self.n_rounds = 0
         self.specs: dict[str, SystemSpec] = {}
         self.resident: "collections.OrderedDict[str, _Resident]" = collections.OrderedDict()
         self.pending: "collections.deque[_Request]" = collections.deque()     # solves
@@ -418,13 +459,49 @@ class Server:
                 return len(waiters)
 
     # ------------------------------------------------------------ solve rounds
+    def _ws_bytes(self, n, width) -> int:
+        """Device bytes of the GMRES workspace of one system at a width: Krylov
+        basis and preconditioned vectors (2 m + 1 vectors), five more vectors and
+        the extended vector of the solve (at most 2 n rows)."""
+        m = self.restart if self.cycle is None else self.cycle
+        return int((2 * m + 1 + 5 + 2) * n * width * 8)
+
+    def _make_room(self, keep, need) -> None:
+        """Lock held: frees device memory so that the resident footprint plus
+        `need` fits the budget: trims the workspaces of idle handles, then evicts
+        idle systems (least recently used first).  Systems in `keep` stay."""
+        if self._resident_bytes() + need <= self.budget:
+            return
+        trim = getattr(self.backend, "trim", None)
+        if trim is not None:
+            for k, r in self.resident.items():
+                if k in keep or k in self.busy:
+                    continue
+                trim(r.handle)
+                r.bytes = self.backend.resident_bytes(r.handle)
+        wanted = keep | self.busy | {q.key for q in self.pending}
+        while self._resident_bytes() + need > self.budget:
+            idle = [k for k in self.resident if k not in wanted]
+            if not idle:
+                idle = [k for k in self.resident if k not in keep and k not in self.busy]
+            if not idle:
+                return
+            self._evict(idle[0])
+
     def _solve_ready(self) -> int:
         with self._lock:
-            groups: "collections.OrderedDict[str, list[_Request]]" = collections.OrderedDict()
+            groups: "collections.OrderedDict[str, list]" = collections.OrderedDict()
             width: dict[str, int] = {}
             rest = collections.deque()
             for req in self.pending:
-                k = 1 if req.b.ndim == 1 else req.b.shape[1]
+                if req.x is None:                   # first round of this request
+                    k = req.cols()
+                    req.x = np.zeros((req.b.shape[0], k))
+                    req.its = np.zeros(k, dtype=np.int64)
+                    req.rr = np.full(k, np.inf)
+                    req.conv = np.zeros(k, dtype=bool)
+                cols = [c for c in range(req.cols()) if not req.conv[c]]
+                k = len(cols)
                 if req.key not in self.resident or req.key in self.busy:
                     rest.append(req)
                     continue
@@ -434,7 +511,7 @@ class Server:
                 if width.get(req.key, 0) + k > self.max_width:
                     rest.append(req)
                     continue
-                groups.setdefault(req.key, []).append(req)
+                groups.setdefault(req.key, []).append((req, cols))
                 width[req.key] = width.get(req.key, 0) + k
             self.pending = rest
             if not groups:
@@ -442,29 +519,54 @@ class Server:
             self.busy |= set(groups)
             handles = {key: self.resident[key].handle for key in groups}
             ns = {key: self.specs[key].n for key in groups}
-        w = max(width.values())
-        nrhs = 1
-        while nrhs < w:
-            nrhs *= 2
-        items, spans = [], []
-        for key, reqs in groups.items():
-            n = ns[key]
-            B = np.zeros((n, nrhs))
-            c0, sp = 0, []
-            for req in reqs:
-                k = 1 if req.b.ndim == 1 else req.b.shape[1]
-                B[:, c0:c0 + k] = req.b.reshape(n, k)
-                sp.append((req, c0, k))
-                c0 += k
-            items.append((handles[key], B))
-            spans.append(sp)
+            pw = {}
+            for key in groups:
+                w = 1
+                while w < width[key]:
+                    w *= 2
+                pw[key] = w
+            self._make_room(set(groups), sum(self._ws_bytes(ns[k], pw[k]) for k in groups))
+        # one batched call per width class
+        classes: dict[int, list] = {}
+        for key in groups:
+            classes.setdefault(pw[key], []).append(key)
+        x0 = self.cycle is not None
+        restart = self.restart if self.cycle is None else self.cycle
+        maxit = self.maxit if self.cycle is None else self.cycle
+        results = {}
         try:
-            out = self.backend.solve_batch(items, nrhs, self.tol, self.restart, self.maxit)
+            for wcls in sorted(classes):
+                items, spans = [], []
+                for key in classes[wcls]:
+                    n = ns[key]
+                    B = np.zeros((n, wcls))
+                    X0 = np.zeros((n, wcls))
+                    c0 = 0
+                    for req, cols in groups[key]:
+                        bb = req.b.reshape(n, -1)
+                        for c in cols:
+                            B[:, c0] = bb[:, c]
+                            X0[:, c0] = req.x[:, c]
+                            c0 += 1
+                    items.append((handles[key], B, X0))
+                for attempt in (0, 1):
+                    try:
+                        out = self.backend.solve_batch(items, wcls, self.tol, restart, maxit, x0=x0)
+                        break
+                    except OutOfBudget:
+                        if attempt:
+                            raise
+                        with self._lock:            # evict the idle systems and retry once
+                            wanted = set(groups) | self.busy
+                            for k in [k for k in self.resident if k not in wanted]:
+                                self._evict(k)
+                for key, res in zip(classes[wcls], out):
+                    results[key] = res
         except Exception as e:
             with self._lock:
                 self.busy -= set(groups)
-                for sp in spans:
-                    for req, _, _ in sp:
+                for key in groups:
+                    for req, _ in groups[key]:
                         req.future.set_exception(e)
                 self._wake.notify_all()
             return 0
@@ -472,18 +574,34 @@ class Server:
         done = 0
         with self._lock:
             self.busy -= set(groups)
-            for key, sp, (X, its, rr) in zip(groups, spans, out):
+            again = []
+            for key in groups:
+                X, its, rr = results[key]
                 if key in self.resident:
-                    self.resident[key].last_use = now
+                    r = self.resident[key]
+                    r.last_use = now
+                    r.bytes = self.backend.resident_bytes(r.handle)
                     self.resident.move_to_end(key)
-                for req, c0, k in sp:
-                    x = X[:, c0:c0 + k]
-                    res = (x[:, 0] if req.b.ndim == 1 else x.copy(), np.asarray(its[c0:c0 + k]),
-                           np.asarray(rr[c0:c0 + k]))
-                    self.latencies["solve"].append(now - req.arrival)
-                    req.future.set_result(res)
-                    done += 1
+                c0 = 0
+                for req, cols in groups[key]:
+                    for c in cols:
+                        req.x[:, c] = X[:, c0]
+                        req.its[c] += int(its[c0])
+                        req.rr[c] = float(rr[c0])
+                        req.conv[c] = req.rr[c] <= self.tol
+                        c0 += 1
+                    finished = all(req.conv[c] or req.its[c] >= self.maxit for c in range(req.cols()))
+                    if self.cycle is None or finished:
+                        x = req.x[:, 0] if req.b.ndim == 1 else req.x.copy()
+                        req.future.set_result((x, req.its.astype(np.int32), req.rr.copy()))
+                        self.latencies["solve"].append(now - req.arrival)
+                        done += 1
+                    else:
+                        again.append(req)
+            # unfinished requests keep their place ahead of later arrivals
+            self.pending.extendleft(reversed(again))
             self.n_solved += done
             self.batches.append(len(groups))
+            self.n_rounds += 1
             self._wake.notify_all()
         return done

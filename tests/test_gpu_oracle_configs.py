@@ -154,14 +154,16 @@ def test_batched_factor_against_oracle(lx):
             assert abs(int(its_b[i, k]) - o["iters"]) <= 1, (i, k, its_b[i, k], o["iters"])
 
 
-def test_served_answers_against_oracle(lx):
-    """Served solves (continuous batching across resident handles) reach the
-    tolerance, and each equals the oracle-preconditioned FP64 FGMRES answer
-    within the conditioning bound."""
+@pytest.mark.parametrize("cycle", [None, 2])
+def test_served_answers_against_oracle(lx, cycle):
+    """Served solves (continuous batching across resident handles; with cycle,
+    rounds of one FGMRES(2) cycle that continue unconverged right-hand sides
+    from their iterate) reach the tolerance, and each equals the
+    oracle-preconditioned FP64 FGMRES answer within the conditioning bound."""
     from paper_1510_07363_amd.serve import LoraxBackend, Server, SystemSpec
     ins = {"a": (grid("lognormal2d", 48, 16, 11), 1e-5), "b": (grid("lognormal3d", 12, 32, 12), 1e-3)}
     for precision in ("fp64", "mixed"):
-        srv = Server(LoraxBackend(precision=precision), 8 << 30, tol=TOL)
+        srv = Server(LoraxBackend(precision=precision), 8 << 30, tol=TOL, cycle=cycle)
         for key, ((csr, n, perm, lp, depth, rng), eps) in ins.items():
             srv.register(SystemSpec(key, csr[0], csr[1], csr[2], perm, lp, depth, eps))
         rng = np.random.default_rng(99)
@@ -182,4 +184,33 @@ def test_served_answers_against_oracle(lx):
                 bound = (r + ro) * np.linalg.norm(b[:, k]) / smin
                 assert r <= TOL
                 assert np.linalg.norm(x[:, k] - o["x"]) <= 1.01 * bound + 1e-14, (precision, key, k)
+        if cycle:
+            assert srv.n_rounds >= 2
         srv.close()
+
+
+def test_gmres_from_initial_guess(lx):
+    """lrx_gmres_batch_dev_x0: a converged iterate stops at once; a cycle-limited
+    first call (ENOCONV) continued from its iterate reaches the tolerance; a
+    zero right-hand side returns x = 0 whatever the guess."""
+    import torch
+    csr, n, perm, lp, depth, rng = grid("varcoef2d", 48, 16, 21)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n))
+    F = lx.Factor(*csr, perm, lp, depth, 1e-1)
+    B = rng.uniform(-1, 1, (n, 3))
+    B[:, 2] = 0.0
+    b = torch.from_numpy(np.ascontiguousarray(B.T)).to("cuda:0")
+    x = torch.zeros_like(b)
+    its1, rr1, st1 = lx.gmres_batch_dev([F], 3, [b.data_ptr()], [x.data_ptr()], tol=TOL, restart=2, maxit=2)
+    assert st1 == lx.LRX_ENOCONV and rr1[0, 0] > TOL
+    x[2].fill_(7.0)                                   # guess for the zero right-hand side
+    its2, rr2, st2 = lx.gmres_batch_dev([F], 3, [b.data_ptr()], [x.data_ptr()], tol=TOL, restart=2, maxit=200,
+                                        x0=True)
+    assert st2 == lx.LRX_OK
+    X = x.cpu().numpy().T
+    r = np.linalg.norm(A @ X[:, :2] - B[:, :2], axis=0) / np.linalg.norm(B[:, :2], axis=0)
+    assert (r <= TOL).all() and (rr2[0, :2] <= TOL).all()
+    assert np.all(X[:, 2] == 0.0)
+    its3, rr3, st3 = lx.gmres_batch_dev([F], 3, [b.data_ptr()], [x.data_ptr()], tol=TOL, restart=2, maxit=200,
+                                        x0=True)
+    assert st3 == lx.LRX_OK and (its3 == 0).all()

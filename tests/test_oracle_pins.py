@@ -371,3 +371,47 @@ def test_invalid_inputs_rejected():
         oracle.factor(*csr, bad, lp, depth, 0.1)
     with pytest.raises(ValueError):
         oracle.factor(*csr, perm, lp[:-1], depth, 0.1)
+
+
+# --------------------------------------------------------------------------- eqn. curOff6
+@pytest.mark.parametrize("method", ["svd", "rrqr"])
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_frobenius_rule_bound_minimality_and_leaf_norm(method, eps):
+    """The 'frob' rule (the paper's variant, eqn. curOff6): every compression's
+    discarded part has Frobenius norm below eps N_i, recomputed from the stacked
+    block with an independent eigen-solver of its Gram matrix; with SVD the rank
+    is the smallest such; N_i grows towards the root and at the leaf level equals
+    ||A||_F (every entry of A lies in exactly one leaf block)."""
+    csr, n, perm, lp, depth, rng = _grid_problem("lognormal3d", 8, 8, seed=5)
+    F = oracle.factor(*csr, perm, lp, depth, eps, keep_blocks=True, compress=method, rule="frob")
+    A = _dense(csr, n)
+    assert F.level_norm[depth] == pytest.approx(np.linalg.norm(A, "fro"), rel=1e-13)
+    norms = [F.level_norm[i] for i in range(depth, 0, -1)]
+    assert all(b >= a for a, b in zip(norms, norms[1:]))
+    for c in F.compressions:
+        if c.rows == 0 or c.m == 0:
+            continue
+        tau = eps * F.level_norm[c.level]
+        B, V = c.B, c.V
+        E = B - (B @ V) @ V.T
+        # ||E||_F^2 = trace(E^T E), from eigenvalues of the Gram matrix (not an SVD)
+        tail = np.sqrt(max(float(np.sum(sla.eigvalsh(E.T @ E))), 0.0))
+        assert tail < tau * (1 + 1e-9) + 1e-14 * np.linalg.norm(B), (c.level, c.j)
+        if method == "svd" and c.rank > 0:
+            # one column fewer violates the bound: the squared tail gains sigma_{r-1}^2
+            lam = np.sort(sla.eigvalsh(B.T @ B))[::-1]
+            tail_less = np.sqrt(max(float(np.sum(lam[c.rank - 1:])), 0.0))
+            assert tail_less >= tau * (1 - 1e-9), (c.level, c.j)
+
+
+def test_frobenius_rule_exact_at_eps0_and_converges():
+    csr, n, perm, lp, depth, rng = _grid_problem("convdiff3d", 8, 8)
+    A = _dense(csr, n)
+    b = rng.uniform(-1, 1, n)
+    F0 = oracle.factor(*csr, perm, lp, depth, 0.0, rule="frob")
+    assert _relerr(oracle.solve(F0, b), np.linalg.solve(A, b)) <= 1e-12
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6):
+        F = oracle.factor(*csr, perm, lp, depth, eps, rule="frob", check=True)
+        errs.append(_relerr(oracle.solve(F, b), np.linalg.solve(A, b)))
+    assert errs[0] > errs[1] > errs[2]

@@ -36,9 +36,11 @@ def _spec(key, kind, nx, leaf, eps, seed):
 class OracleBackend:
     """Backend on the oracle: factor storage is charged at 800 bytes per unknown."""
     PER_UNKNOWN = 800
+    WS_PER_UNKNOWN = 0            # workspace bytes per unknown and column charged by a round (tests set it)
 
     def __init__(self):
         self.factored, self.freed, self.batches, self.factor_batches = [], [], [], []
+        self.trimmed, self.cycles = [], []
 
     def factor(self, spec, room):
         if spec.n * self.PER_UNKNOWN > room:
@@ -54,22 +56,43 @@ class OracleBackend:
         return [self.factor(sp, room) for sp in specs]
 
     def resident_bytes(self, h):
-        return h["n"] * self.PER_UNKNOWN
+        return h["n"] * self.PER_UNKNOWN + h.get("ws", 0)
+
+    def trim(self, h):
+        self.trimmed.append(h["key"])
+        h["ws"] = 0
 
     def free(self, h):
         self.freed.append(h["key"])
 
-    def solve_batch(self, items, nrhs, tol, restart, maxit):
-        self.batches.append(([h["key"] for h, _ in items], nrhs))
+    def solve_batch(self, items, nrhs, tol, restart, maxit, x0=False):
+        """FGMRES per column; with x0, from the given iterate: the correction d
+        solves A d = b - A x0 to the tolerance relative to ||b||."""
+        self.batches.append(([h["key"] for h, _, _ in items], nrhs))
+        self.cycles.append((restart, maxit, x0))
         out = []
-        for h, B in items:
+        for h, B, X0 in items:
+            h["ws"] = self.WS_PER_UNKNOWN * h["n"] * nrhs      # workspace grown by the round
             X = np.zeros_like(B)
             its = np.zeros(nrhs, dtype=np.int32)
             rr = np.zeros(nrhs)
             for k in range(nrhs):
-                o = oracle.fgmres(h["A"], lambda v: oracle.solve(h["F"], v), B[:, k], tol=tol,
+                b = B[:, k]
+                nb = np.linalg.norm(b)
+                xs = X0[:, k] if x0 else np.zeros_like(b)
+                if nb == 0.0:
+                    X[:, k], its[k], rr[k] = 0.0, 0, 0.0
+                    continue
+                r0 = b - h["A"] @ xs
+                nr0 = np.linalg.norm(r0)
+                if nr0 <= tol * nb:
+                    X[:, k], its[k], rr[k] = xs, 0, nr0 / nb
+                    continue
+                o = oracle.fgmres(h["A"], lambda v: oracle.solve(h["F"], v), r0, tol=tol * nb / nr0,
                                   restart=restart, maxit=maxit)
-                X[:, k], its[k], rr[k] = o["x"], o["iters"], o["relres"]
+                X[:, k] = xs + o["x"]
+                its[k] = o["iters"]
+                rr[k] = np.linalg.norm(b - h["A"] @ X[:, k]) / nb
             out.append((X, its, rr))
         return out
 
@@ -95,10 +118,11 @@ def test_continuous_batching_and_alone_equals_mix():
             ("a", rng.uniform(-1, 1, (specs["a"].n, 2))), ("c", rng.uniform(-1, 1, specs["c"].n))]
     futs = [srv.submit(k, b) for k, b in reqs]
     srv.run_until_idle()
-    # one round: factors admitted, then every request in one batch over three systems,
-    # "a" carrying both of its requests (1 + 2 columns), all padded to width 4
+    # one round: factors admitted, then every request in one call per width class:
+    # "c" (1 column) alone, "a" (its two requests, 1 + 2 columns) and "b" (3) padded to 4
     assert sorted(be.factored) == ["a", "b", "c"]
-    assert len(be.batches) == 1 and sorted(be.batches[0][0]) == ["a", "b", "c"] and be.batches[0][1] == 4
+    assert srv.n_rounds == 1
+    assert sorted((sorted(k), wd) for k, wd in be.batches) == [(["a", "b"], 4), (["c"], 1)]
     for (key, b), f in zip(reqs, futs):
         x, its, rr = f.result()
         assert x.shape == b.shape and (rr <= 1e-10).all()
@@ -285,3 +309,57 @@ def test_serve_on_gpu_concurrent_factoring():
     assert srv.latency_stats("solve")["count"] == len(reqs)
     srv.close()
 
+
+
+def test_cycle_rounds_admit_new_requests_between_cycles():
+    """With cycle = 2, a round is one FGMRES(2) cycle: unconverged right-hand
+    sides carry their iterate into the next round (initial guess), and a
+    request submitted after the first round joins the second, beside them.
+    Every answer reaches the tolerance and equals the same request served
+    alone (the fake backend works column by column, so the mix cannot change
+    the arithmetic)."""
+    rng = np.random.default_rng(11)
+    srv, be, specs = _server(10_000, cycle=2)
+    b1 = rng.uniform(-1, 1, (specs["c"].n, 2))
+    b2 = rng.uniform(-1, 1, specs["b"].n)
+    f1 = srv.submit("c", b1)
+    srv.step()                                  # factor "c", first cycle of f1
+    assert not f1.done() and srv.n_rounds == 1
+    f2 = srv.submit("b", b2)                    # arrives between cycles
+    srv.run_until_idle()
+    assert all(c == (2, 2, True) for c in be.cycles)
+    second = be.batches[1:]
+    assert any("b" in keys for keys, _ in second) and any("c" in keys for keys, _ in second)
+    for key, b, f in (("c", b1, f1), ("b", b2, f2)):
+        x, its, rr = f.result()
+        A = sp.csr_matrix((specs[key].val, specs[key].col_idx, specs[key].row_ptr), shape=(specs[key].n,) * 2)
+        X, B = x.reshape(specs[key].n, -1), b.reshape(specs[key].n, -1)
+        assert (np.linalg.norm(A @ X - B, axis=0) / np.linalg.norm(B, axis=0) <= 1e-10).all() and (rr <= 1e-10).all()
+        assert (its > 2).any()                  # more than one cycle was needed
+        srv2, _, _ = _server(10_000, cycle=2)
+        g = srv2.submit(key, b)
+        srv2.run_until_idle()
+        assert np.array_equal(g.result()[0], x) and np.array_equal(g.result()[1], its)
+
+
+def test_round_workspace_counts_in_admission():
+    """A round reserves its GMRES workspace: idle handles are trimmed first,
+    then idle systems evicted when the footprint would exceed the budget."""
+    rng = np.random.default_rng(12)
+    OracleBackend.WS_PER_UNKNOWN = 100
+    try:
+        srv, be, specs = _server(900)          # 720,000 bytes
+        fa = srv.submit("a", rng.uniform(-1, 1, (specs["a"].n, 1)))
+        srv.run_until_idle()                   # "a": 256 unknowns -> 204,800 bytes + 25,600 of workspace
+        assert srv.resident["a"].bytes == 256 * 800 + 256 * 100
+        fc = srv.submit("c", rng.uniform(-1, 1, (specs["c"].n, 4)))
+        srv.run_until_idle()                   # "c" factored; its 4-column round needs room
+        assert "a" in be.trimmed               # the idle handle gave its workspace back first
+        assert srv.resident_bytes() <= srv.budget
+        fb = srv.submit("b", rng.uniform(-1, 1, (specs["b"].n, 8)))
+        srv.run_until_idle()                   # 400 unknowns + an 8-column workspace: idle systems go
+        assert srv.n_evicted >= 1 and srv.resident_bytes() <= srv.budget
+        for f in (fa, fc, fb):
+            assert (f.result()[2] <= 1e-10).all()
+    finally:
+        OracleBackend.WS_PER_UNKNOWN = 0
