@@ -69,6 +69,16 @@ typedef enum {
 typedef enum { LRX_FP64 = 0, LRX_MIXED = 1, LRX_MIXED_BF16 = 2 } lrx_precision;
 typedef enum { LRX_COLORED = 0, LRX_NATURAL = 1 } lrx_order;
 typedef enum { LRX_SVD = 0, LRX_RRQR = 1 } lrx_compress;
+/* Truncation rule of Compress.  LRX_RULE_CUTOFF1 (eqn. cutOff1): keep sigma_k >=
+ * epsilon sigma_0 of each stacked block (RRQR: stop at ||R22||_F <= epsilon |R11|).
+ * LRX_RULE_FROB, the paper's variant of eqn. curOff6: keep the fewest singular
+ * values whose discarded tail has Frobenius norm < epsilon N_i, where N_i^2 sums
+ * the squared Frobenius norms of all blocks of level i and of every level below,
+ * each level's blocks taken when the level starts (after MergeRedNodes; at the
+ * leaf level they are the entries of A, so N_l = ||A||_F); RRQR: stop at the
+ * first k with ||R22||_F < epsilon N_i.  The threshold is absolute per level, so
+ * blocks that are small against the whole take lower ranks (Sec. 6.2). */
+typedef enum { LRX_RULE_CUTOFF1 = 0, LRX_RULE_FROB = 1 } lrx_rule;
 
 typedef struct lrx_handle_s* lrx_handle;     /* opaque */
 
@@ -103,6 +113,10 @@ typedef struct {
     int32_t order;             /* lrx_order: order of the super-nodes inside a level */
     int64_t hbm_budget_bytes;  /* 0 = no limit; otherwise LRX_ENOMEM when exceeded */
     void* stream;              /* hipStream_t used by the handle, or NULL for the null stream */
+    int32_t rule;              /* lrx_rule (appended field) */
+    int32_t symmetric;         /* 1: A is symmetric (checked entry for entry, LRX_EINVAL otherwise) and
+                                  Compress stacks only A_k = Mat(s->p_k), since B_k = A_k, with
+                                  Q_k = R_k: half the stacked rows (Sec. 4.3, last paragraph) */
 } lrx_opts;
 
 /* Counters of a factorization (sizes in elements/bytes, times in ms). */
@@ -134,6 +148,7 @@ typedef struct {
     double flops_pivot;            /* pivot inverses of super-nodes and black nodes */
     double flops_schur;            /* Schur-complement products, W_k = S^-1 Mat(k->v) included */
     double flops_project;          /* projection [R; Q] = B V */
+    double level_norm_by_level[32];/* LRX_RULE_FROB: N_i of eqn. curOff6 by level (0 otherwise) */
 } lrx_stats_t;
 
 /* Symbolic counts, computed on the host without any device call. */

@@ -175,7 +175,8 @@ def _key(node):
 
 
 def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored",
-           forced_ranks=None, check=True, keep_blocks=False, compress="svd", rule="cutoff1"):
+           forced_ranks=None, check=True, keep_blocks=False, compress="svd", rule="cutoff1",
+           symmetric=False):
     """Algorithm 1.  Inputs are a CSR matrix (0-based) and the cluster tree.
 
     compress:     'svd' (eqn. cutOff1, as in the paper's experiments) or 'rrqr'.
@@ -188,6 +189,10 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
                   level starts (after MergeRedNodes); the leaf level's blocks are
                   the blocks of A, so N_l = ||A||_F.  RRQR: the first k with
                   ||R22||_F < epsilon N_i.
+    symmetric:    the half stack of the symmetric case (Sec. 4.3, last paragraph):
+                  for symmetric A, B_k = A_k, so B stacks only A_k = Mat(s->p_k)
+                  (Mat(p_k->s)^T where the first is absent) and Q_k = R_k.  A must
+                  be symmetric (checked).
 
     forced_ranks: optional {(level, j): rank} to replay ranks decided elsewhere.
     keep_blocks:  keep every stacked B and V in the compression records (tests).
@@ -196,6 +201,11 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
         raise ValueError("epsilon must be in [0, 1)")
     if rule not in ("cutoff1", "frob"):
         raise ValueError(rule)
+    if symmetric:
+        As = sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col_idx), np.asarray(row_ptr)),
+                           shape=(len(row_ptr) - 1,) * 2)
+        if (As != As.T).nnz:
+            raise ValueError("symmetric=True needs a symmetric matrix")
     if int(depth) < 1:
         raise ValueError("depth must be >= 1 (the root cluster is never a leaf)")
     T = ClusterTree(row_ptr, col_idx, perm, leaf_ptr, depth)
@@ -286,7 +296,7 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
             if forced_ranks is not None and (i, j) in forced_ranks:
                 forced = int(forced_ranks[(i, j)])
             tau = epsilon * level_norm[i] if rule == "frob" else None
-            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress, tau)
+            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress, tau, symmetric)
             rec.level, rec.j = i, j
             compressions.append(rec)
 
@@ -351,12 +361,15 @@ def rrqr_rows(B, epsilon, forced_rank=None, tau=None):
 
 
 def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
-              method="svd", tau=None):
+              method="svd", tau=None, symmetric=False):
     """Compress(s): replace the well-separated edges of s by low-rank edges through
     its black node b and the parent red node P = P(b) (Sec. 4.3, eqn. lra,
     eqn. anterpol, eqn. interpol and the edge-update list)."""
     m = G.size[s]
-    if cand:
+    if cand and symmetric:                             # half stack: A_k only (B_k = A_k)
+        B = np.vstack([G.get(s, p) if G.has(s, p) else
+                       (G.get(p, s).T if G.has(p, s) else np.zeros((G.size[p], m))) for p in cand])
+    elif cand:
         parts = []
         for p in cand:                                 # A_k = Mat(s -> p_k)
             parts.append(G.get(s, p) if G.has(s, p) else np.zeros((G.size[p], m)))
@@ -403,10 +416,11 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
     G.size[b] = r
     G.size[P] = r
     t = len(cand)
-    offs = np.cumsum([0] + [G.size[p] for p in cand] * 2)
+    offs = np.cumsum([0] + [G.size[p] for p in cand] * (1 if symmetric else 2))
     for k, p in enumerate(cand):
         G.put(P, p, RQ[offs[k]:offs[k + 1]].copy())             # Mat(P(b) -> p_k) = R_k
-        G.put(p, P, RQ[offs[t + k]:offs[t + k + 1]].T.copy())   # Mat(p_k -> P(b)) = Q_k^T
+        q0 = k if symmetric else t + k                          # Q_k = R_k when symmetric
+        G.put(p, P, RQ[offs[q0]:offs[q0 + 1]].T.copy())         # Mat(p_k -> P(b)) = Q_k^T
     G.put(s, b, V.T.copy())                            # Mat(s -> b) = V^T
     G.put(b, s, V.copy())                              # Mat(b -> s) = V
     G.put(b, P, -np.eye(r))                            # Mat(b -> P(b)) = -I_r

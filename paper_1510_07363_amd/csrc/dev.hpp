@@ -43,6 +43,9 @@ struct DCompress {
     double* tails;      // SVD: sigma_0 then the c singular values in descending order;
                         // RRQR: |R11|, then ||R22||_F before each step and at the stop
     double eps;
+    const double* tau;  // nullptr: cut-off of eqn. cutOff1 (eps relative to sigma_0); else the
+                        // absolute threshold of eqn. curOff6: the smallest k whose discarded
+                        // tail has Frobenius norm < *tau (RRQR: ||R22||_F < *tau)
 };
 
 // ---- Node factorization: projection, rewiring, Eliminate(s), Eliminate(b) ---

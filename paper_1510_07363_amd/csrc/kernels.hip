@@ -122,7 +122,7 @@ __global__ __launch_bounds__(NT) void k_compress(const DCompress* __restrict__ t
         const double tail = sqrt(sum);
         if (k == 0) r11 = sqrt(best);
         if (tid == 0) { T.tails[0] = r11; T.tails[1 + k] = tail; }
-        if (tail == 0.0 || tail <= T.eps * r11) break;
+        if (T.tau ? tail < *T.tau : (tail == 0.0 || tail <= T.eps * r11)) break;
         const int p = bi;
         double* rowp = B + (int64_t)p * c;
         const double xnorm = sqrt(best);
@@ -225,6 +225,23 @@ __device__ __forceinline__ int desc_pos(const double* sv, int c, int k) {
     int pos = 0;
     for (int j = 0; j < c; ++j) pos += (sv[j] > x) || (sv[j] == x && j < k);
     return pos;
+}
+
+// Rank under the Frobenius rule (eqn. curOff6): desc holds kk singular values in
+// descending order, extra2 the squared Frobenius norm of what was dropped before
+// (rows of a truncated pivoted QR, 0 otherwise); the smallest k with
+// sqrt(extra2 + sum_{t >= k} desc[t]^2) < tau, or kk when no k qualifies.  The
+// tail is summed from the smallest value up.
+__device__ int frob_rank(const double* desc, int kk, double extra2, double tau) {
+    double t2 = extra2;
+    if (!(sqrt(t2) < tau)) return kk;
+    int r = kk;
+    for (int k = kk - 1; k >= 0; --k) {
+        t2 += desc[k] * desc[k];
+        if (sqrt(t2) < tau) r = k;
+        else break;
+    }
+    return r;
 }
 
 __device__ double block_sum(double v, double* s_s) {
@@ -435,7 +452,8 @@ __global__ __launch_bounds__(NT) void k_compress_svd(const DCompress* __restrict
     __syncthreads();
     const double smax = T.tails[1];
     int r = 0;
-    if (smax > 0.0)
+    if (T.tau) r = frob_rank(T.tails + 1, c, 0.0, *T.tau);
+    else if (smax > 0.0)
         for (int k = 0; k < c; ++k) r += (T.tails[1 + k] >= T.eps * smax) ? 1 : 0;
     // V (c x r): output column pos(k) is column k of the accumulated rotations
     const double* Vsrc = Vm;
@@ -819,7 +837,10 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     double smax = 0.0;
     for (int k = 0; k < c; ++k) smax = fmax(smax, s_sv[k]);
     int r = 0;
-    if (smax > 0.0)
+    if (T.tau) {
+        __syncthreads();                          // the sorted values above are written
+        r = frob_rank(T.tails + 1, c, 0.0, *T.tau);
+    } else if (smax > 0.0)
         for (int k = 0; k < c; ++k) r += (s_sv[k] >= T.eps * smax) ? 1 : 0;
     for (int e = tid; e < c * c; e += NTC) {
         const int a = e % c, k = e / c;
@@ -1334,7 +1355,10 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     for (int k = tid; k < kk; k += NTL) T.tails[1 + s_pos[k]] = s_sv[k];
     for (int k = kk + tid; k < c; k += NTL) T.tails[1 + k] = bound;
     int r = 0;
-    if (smax > 0.0)
+    if (T.tau) {
+        __syncthreads();                          // the sorted values above are written
+        r = frob_rank(T.tails + 1, kk, bound * bound, *T.tau);
+    } else if (smax > 0.0)
         for (int k = 0; k < kk; ++k) r += (s_sv[k] >= T.eps * smax) ? 1 : 0;
     for (int e = tid; e < c * kk; e += NTL) {
         const int a = e % c, k = e / c;
@@ -2480,6 +2504,55 @@ __global__ void k_count_nonfinite(const double* __restrict__ v, int64_t n, unsig
     if (threadIdx.x == 0 && s) atomicAdd(cnt, (unsigned long long)s);
 }
 
+// Sum of squares for the Frobenius rule: one 256-thread work-group per merge
+// piece (its source block) or per chunk of a value array; partial[g] per group.
+__global__ __launch_bounds__(256) void k_sumsq(const DMerge* __restrict__ pieces, const double* __restrict__ v,
+                                               int64_t n, int64_t chunk, double* __restrict__ partial) {
+    __shared__ double s_w[256 / WAVE];
+    const double* p;
+    int64_t len;
+    if (!v) {
+        const DMerge d = pieces[blockIdx.x];
+        p = d.src.p;
+        len = (int64_t)d.src.nr * d.src.nc;
+    } else {
+        const int64_t e0 = (int64_t)blockIdx.x * chunk;
+        p = v + e0;
+        len = n - e0 < chunk ? n - e0 : chunk;
+    }
+    double a = 0.0;
+    for (int64_t e = threadIdx.x; e < len; e += 256) a += p[e] * p[e];
+    a = wave_sum(a);
+    if (threadIdx.x % WAVE == 0) s_w[threadIdx.x / WAVE] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 256 / WAVE; ++w) t += s_w[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// state[0] += sum of partial[0..n) (fixed order), state[1] = eps sqrt(state[0]),
+// state[2 + level] = sqrt(state[0]).  One work-group.
+__global__ __launch_bounds__(256) void k_norm_accum(const double* __restrict__ partial, int n, double* state,
+                                                    double eps, int level) {
+    __shared__ double s_t[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += partial[i];
+    s_t[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s_t[threadIdx.x] += s_t[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n2 = state[0] + s_t[0];
+        state[0] = n2;
+        state[1] = eps * sqrt(n2);
+        state[2 + level] = sqrt(n2);
+    }
+}
+
 inline unsigned nblocks(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
 
 }  // namespace
@@ -2504,6 +2577,23 @@ hipError_t launch_count_nonfinite(const double* v, int64_t n, int64_t* cnt, hipS
     if (e != hipSuccess || n == 0) return e;
     hipLaunchKernelGGL(k_count_nonfinite, dim3(256), dim3(256), 0, st, v, n, (unsigned long long*)cnt);
     return hipGetLastError();
+}
+
+hipError_t launch_level_norm(const DMerge* pieces, int npieces, const double* v, int64_t nv, double* state,
+                             double* partial, double eps, int level, hipStream_t st) {
+    constexpr int64_t chunk = 65536;
+    const int ng = v ? (int)((nv + chunk - 1) / chunk) : npieces;
+    if (ng > 0) {
+        hipLaunchKernelGGL(k_sumsq, dim3(ng), dim3(256), 0, st, pieces, v, nv, chunk, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_norm_accum, dim3(1), dim3(256), 0, st, partial, ng, state, eps, level);
+    return hipGetLastError();
+}
+
+int level_norm_groups(int npieces, int64_t nv) {
+    return nv > 0 ? (int)((nv + 65535) / 65536) : npieces;
 }
 
 hipError_t launch_merge(const DMerge* t, int n, hipStream_t st) {

@@ -16,6 +16,14 @@ constexpr int kFactorThreads = 256;
 hipError_t launch_scatter(double* dst_base, const int64_t* idx, const double* val, int64_t nnz,
                           hipStream_t st);
 hipError_t launch_merge(const DMerge* t, int n, hipStream_t st);
+// Frobenius rule (eqn. curOff6): adds the squared Frobenius norms of the nv
+// values v (v != nullptr) or of the source blocks of npieces merge pieces
+// (npieces may be 0) to state[0], then state[1] = eps sqrt(state[0]) and
+// state[2 + level] = sqrt(state[0]); partial holds level_norm_groups(npieces,
+// nv) doubles.
+hipError_t launch_level_norm(const DMerge* pieces, int npieces, const double* v, int64_t nv, double* state,
+                             double* partial, double eps, int level, hipStream_t st);
+int level_norm_groups(int npieces, int64_t nv);
 // dst[e] = src[idx[e]]
 hipError_t launch_gather_idx(double* dst, const double* src, const int64_t* idx, int64_t n,
                              hipStream_t st);

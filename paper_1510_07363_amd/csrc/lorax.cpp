@@ -415,6 +415,8 @@ struct lrx_handle_s {
     int device = 0;
     double epsilon = 0;
     int32_t compress = LRX_SVD;
+    int32_t rule = LRX_RULE_CUTOFF1;
+    bool symmetric = false;        // half stack of the symmetric case (Sec. 4.3)
     std::vector<int32_t> size;     // per node
     std::vector<double*> eptr;     // per edge
     std::vector<int64_t> var_off;  // per node
@@ -525,6 +527,9 @@ struct FactorRun {
     std::vector<int32_t> level_at_height;  // plan level index per height (-1: none)
     int32_t info_base = 0, info_count = 0, info_next = 0;
     bool fp32_compress = false;
+    bool frob = false;                     // truncation by eqn. curOff6
+    DevBuf d_norm;                         // curOff6: N^2, tau, N per level (33), partial sums
+    size_t merge0 = 0, merge1 = 0;         // this run's pieces in the height's merge list
     int64_t flops = 0;
     double fl_compress = 0, fl_pivot = 0, fl_schur = 0, fl_project = 0;   // by operation class
     double jac_flops = 0.0, jac_sweeps = 0.0;   // Jacobi work of the current step (timing)
@@ -698,6 +703,19 @@ void FactorRun::setup(const lrx_csr* A, const double* val_dev, hipStream_t st) {
         }
         HIPCHK(launch_scatter(base, d_idx.as<int64_t>(), src, A->nnz, st));
     }
+    // Frobenius rule: the leaf level's blocks hold exactly the entries of A, so
+    // N_l^2 = sum of the squared values
+    frob = h->rule == LRX_RULE_FROB;
+    if (frob) {
+        size_t groups = (size_t)level_norm_groups(0, A->nnz);
+        for (const LevelPlan& L : P.levels) groups = std::max(groups, L.merges.size());
+        d_norm.ensure((35 + std::max<size_t>(groups, 1)) * sizeof(double));
+        HIPCHK(hipMemsetAsync(d_norm.p, 0, 35 * sizeof(double), st));
+        double* state = d_norm.as<double>();
+        const double* src = val_dev ? val_dev : d_val.as<double>();
+        HIPCHK(launch_level_norm(nullptr, 0, A->nnz ? src : nullptr, A->nnz, state, state + 35, h->epsilon,
+                                 P.depth, st));
+    }
 }
 
 void FactorRun::merge_tasks(const LevelPlan& L, hipStream_t st, std::vector<DMerge>& mt) {
@@ -715,6 +733,10 @@ void FactorRun::merge_tasks(const LevelPlan& L, hipStream_t st, std::vector<DMer
         d.c0 = mp.col_hi ? h->size[P.nodes[D.src].comp0] : 0;
         if (d.src.nr * d.src.nc > 0) mt.push_back(d);
     }
+}
+
+bool same_support(const Support& a, const Support& b) {
+    return a.all == b.all && (a.all || a.idx == b.idx);
 }
 
 // Compress descriptors of the current step (Algorithm 1, stacked B of eqn.
@@ -745,11 +767,21 @@ size_t FactorRun::compress_tasks() {
                 pc.blk = blk(cr.e_sp); pc.trans = 0; pc.row0 = row; pc.map = mo(nm.a_map[k]);
                 row += pc.blk.nr;
                 if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
+                // half stack (symmetric A): B_k = A_k, so Q_k = R_k takes the same rows;
+                // that needs p's support in Mat(s->p) rows and Mat(p->s) columns to agree
+                if (h->symmetric && cr.e_ps >= 0 && !same_support(P.edges[cr.e_sp].rows, P.edges[cr.e_ps].cols))
+                    fail(LRX_EINVAL, "symmetric: the block pattern is not symmetric");
+            } else if (h->symmetric && cr.e_ps >= 0) {
+                DPiece pc{};
+                pc.blk = blk(cr.e_ps); pc.trans = 1; pc.row0 = row; pc.map = mo(nm.b_map[k]);
+                row += pc.blk.nc;
+                if (pc.blk.nr * pc.blk.nc > 0) pieces.push_back(pc);
             }
         }
         for (size_t k = 0; k < ns.cands.size(); ++k) {
             const CandRef& cr = ns.cands[k];
-            b_row0[ni].push_back(row);
+            b_row0[ni].push_back(h->symmetric ? a_row0[ni][k] : row);
+            if (h->symmetric) continue;                 // the half stack has no B_k rows
             if (cr.e_ps >= 0) {
                 DPiece pc{};
                 pc.blk = blk(cr.e_ps); pc.trans = 1; pc.row0 = row; pc.map = mo(nm.b_map[k]);
@@ -761,6 +793,7 @@ size_t FactorRun::compress_tasks() {
         T.M = row;
         T.c = ns.gamma.count(ms);
         T.eps = h->epsilon;
+        T.tau = frob ? d_norm.as<double>() + 1 : nullptr;
         wsB[ni] = ws_need; ws_need += ((size_t)T.M * T.c * (svd ? 2 : 1) + 31) & ~(size_t)31;
         wsV[ni] = ws_need; ws_need += ((size_t)T.c * T.c + 31) & ~(size_t)31;
         // hv: c^2 + c, or 4 c^2 + c + 8 for the large-block SVD (c > 64)
@@ -928,7 +961,7 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
             if (cr.e_ps >= 0) {
                 DProj pj{};
                 pj.dst = blk(cr.e_pP);
-                pj.row0 = b_row0[ni][k];
+                pj.row0 = b_row0[ni][k];                 // half stack: the rows of A_k (Q_k = R_k)
                 pj.nrows = nc_of(cr.e_ps);
                 pj.trans = 1;
                 pj.map = mo(maps[si][ni].qb_map[k]);
@@ -1018,7 +1051,9 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
         for (FactorRun* r : runs) {
             if (hgt >= r->level_at_height.size() || r->level_at_height[hgt] < 0) continue;
             const LevelPlan& L = r->P.levels[r->level_at_height[hgt]];
+            r->merge0 = r->merge1 = mt.size();
             if (L.level < r->P.depth) r->merge_tasks(L, st, mt);
+            r->merge1 = mt.size();
             lv.push_back(r);
             ncol = std::max(ncol, L.nsteps);
         }
@@ -1033,6 +1068,16 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             HIPCHK(hipMemcpyAsync(d_desc_m.p, stage_m.p, buf.size(), hipMemcpyHostToDevice, st));
             HIPCHK(launch_merge((const DMerge*)(d_desc_m.as<char>() + o), (int)mt.size(), st));
             m_epoch = epoch;
+        }
+        // Frobenius rule: this level's blocks are the merged red blocks (a level
+        // whose reds are all empty adds nothing, N carries over)
+        for (FactorRun* r : lv) {
+            const LevelPlan& L = r->P.levels[r->level_at_height[hgt]];
+            if (!r->frob || L.level >= r->P.depth) continue;
+            double* state = r->d_norm.as<double>();
+            const DMerge* pieces = r->merge1 > r->merge0 ? d_desc_m.as<DMerge>() + r->merge0 : nullptr;
+            HIPCHK(launch_level_norm(pieces, (int)(r->merge1 - r->merge0), nullptr, 0, state, state + 35,
+                                     r->h->epsilon, L.level, st));
         }
         for (int32_t c = 0; c < ncol; ++c) {
             std::vector<FactorRun*> part;
@@ -1094,7 +1139,10 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 else if (all[q].c <= 64) key = fp32_of[q] | (all[q].c > 32 ? 16 : 0);
                 else if (compress_large_fits(all[q].M, all[q].c)) {
                     const int64_t mc = (int64_t)all[q].M * all[q].c;
-                    key = (all[q].c > 192 || mc >= 1000000 ? 10 : mc >= 300000 ? 12 : 8) | (fp32_of[q] & 1);
+                    // (odd keys drop pivoted-QR rows below epsilon / 100 relative to
+                    // sigma_0: not under the absolute threshold of the Frobenius rule)
+                    key = (all[q].c > 192 || mc >= 1000000 ? 10 : mc >= 300000 ? 12 : 8) |
+                          ((fp32_of[q] & 1) && !all[q].tau ? 1 : 0);
                 } else key = 2;
                 size_t g = 0;
                 while (g < groups.size() && groups[g].key != key) ++g;
@@ -1292,6 +1340,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
         r.h->stats.flops_pivot = r.fl_pivot;
         r.h->stats.flops_schur = r.fl_schur;
         r.h->stats.flops_project = r.fl_project;
+        if (r.frob) {
+            double st_h[35];
+            HIPCHK(hipMemcpy(st_h, r.d_norm.p, sizeof(st_h), hipMemcpyDeviceToHost));
+            for (int lv = 0; lv < 32 && lv <= r.P.depth; ++lv) r.h->stats.level_norm_by_level[lv] = st_h[2 + lv];
+        }
         r.h->t_sync_ms += t_sync;
     }
     IdleScope idle;
@@ -2018,7 +2071,31 @@ void check_factor_args(const lrx_csr* A, const double* val_dev, const lrx_tree* 
     if (o->precision != LRX_FP64 && o->precision != LRX_MIXED && o->precision != LRX_MIXED_BF16)
         fail(LRX_EINVAL, "precision must be LRX_FP64, LRX_MIXED or LRX_MIXED_BF16");
     if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
+    if (o->rule != LRX_RULE_CUTOFF1 && o->rule != LRX_RULE_FROB) fail(LRX_EINVAL, "unknown truncation rule");
+    if (o->symmetric != 0 && o->symmetric != 1) fail(LRX_EINVAL, "symmetric must be 0 or 1");
     if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
+}
+
+// The half stack needs A = A^T entry for entry (values on the host, or copied
+// from the device).
+void check_symmetric(const lrx_csr* A, const double* val_dev) {
+    std::vector<double> vh;
+    const double* v = A->val;
+    if (val_dev) {
+        vh.resize((size_t)A->nnz);
+        if (A->nnz) HIPCHK(hipMemcpy(vh.data(), val_dev, (size_t)A->nnz * 8, hipMemcpyDeviceToHost));
+        v = vh.data();
+    }
+    for (int32_t r = 0; r < A->n; ++r)
+        for (int64_t e = A->row_ptr[r]; e < A->row_ptr[r + 1]; ++e) {
+            const int32_t c = A->col_idx[e];
+            if (c < 0 || c >= A->n) fail(LRX_EINVAL, "column index out of range");
+            const int32_t* b = A->col_idx + A->row_ptr[c];
+            const int32_t* en = A->col_idx + A->row_ptr[c + 1];
+            const int32_t* it = std::lower_bound(b, en, r);
+            if (it == en || *it != r || v[A->row_ptr[c] + (it - b)] != v[e])
+                fail(LRX_EINVAL, "symmetric: A is not symmetric");
+        }
 }
 
 // Options, device, and A in tree order (for the GMRES products) of a handle
@@ -2029,6 +2106,9 @@ void init_handle(lrx_handle h, const lrx_csr* A, const double* val_dev, const lr
     h->stream = (hipStream_t)o->stream;
     h->epsilon = o->epsilon;
     h->compress = o->compress;
+    h->rule = o->rule;
+    h->symmetric = o->symmetric != 0;
+    if (h->symmetric) check_symmetric(A, val_dev);
     h->precision = o->precision;
     h->arena.budget_bytes = o->hbm_budget_bytes;
     const int32_t n = A->n;

@@ -24,6 +24,7 @@ ORDERS = {"colored": LRX_COLORED, "natural": LRX_NATURAL}
 LRX_SVD, LRX_RRQR = 0, 1
 COMPRESS = {"svd": LRX_SVD, "rrqr": LRX_RRQR}
 PRECISION = {"fp64": LRX_FP64, "mixed": LRX_MIXED, "mixed_bf16": LRX_MIXED_BF16}
+RULES = {"cutoff1": 0, "frob": 1}
 
 
 class LoraxError(RuntimeError):
@@ -44,7 +45,8 @@ class Tree(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("epsilon", C.c_double), ("precision", C.c_int32), ("compress", C.c_int32),
-                ("order", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("stream", C.c_void_p)]
+                ("order", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("stream", C.c_void_p),
+                ("rule", C.c_int32), ("symmetric", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -59,7 +61,8 @@ class Stats(C.Structure):
                 ("t_plan_ms", C.c_double), ("t_factor_ms", C.c_double),
                 ("t_sync_ms", C.c_double), ("t_solve_prog_ms", C.c_double),
                 ("device_bytes", C.c_int64), ("flops_compress", C.c_double), ("flops_pivot", C.c_double),
-                ("flops_schur", C.c_double), ("flops_project", C.c_double)]
+                ("flops_schur", C.c_double), ("flops_project", C.c_double),
+                ("level_norm_by_level", C.c_double * 32)]
 
 
 class KernelTime(C.Structure):
@@ -235,7 +238,7 @@ def plan_inspect(row_ptr, col_idx, perm, leaf_ptr, depth, order="colored"):
 
 
 def factor_batch(systems, epsilon, order="colored", compress="svd", stream=None, hbm_budget_bytes=0,
-                 precision="fp64", val_dev=None):
+                 precision="fp64", val_dev=None, rule="cutoff1", symmetric=False):
     """Factorizes several systems in one lrx_factor_batch call.
     systems: sequence of (row_ptr, col_idx, val, perm, leaf_ptr, depth); with
     val_dev (a sequence of device addresses of each system's values) val may be None.
@@ -247,7 +250,7 @@ def factor_batch(systems, epsilon, order="colored", compress="svd", stream=None,
     A_arr = (Csr * k)(*[a.s for a in As])
     T_arr = (Tree * k)(*[t.s for t in Ts])
     o = Opts(float(epsilon), PRECISION[precision], COMPRESS[compress], ORDERS[order],
-             int(hbm_budget_bytes), C.c_void_p(stream) if stream else None)
+             int(hbm_budget_bytes), C.c_void_p(stream) if stream else None, RULES[rule], int(symmetric))
     hs = (C.c_void_p * k)()
     vd = None if val_dev is None else (C.c_void_p * k)(*[int(v) for v in val_dev])
     _check(_lib.lrx_factor_batch(k, A_arr, vd, T_arr, C.byref(o), hs))
@@ -259,7 +262,7 @@ class Factor:
 
     def __init__(self, row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon,
                  order="colored", compress="svd", stream=None, hbm_budget_bytes=0,
-                 val_dev=None, precision="fp64"):
+                 val_dev=None, precision="fp64", rule="cutoff1", symmetric=False):
         """val: host values, or None with val_dev = device address of the values.
         precision: "fp64" or "mixed" (FP32 compression arithmetic and FP32 stored
         factor for the solve; FP64 pivots, Schur updates and GMRES)."""
@@ -268,7 +271,8 @@ class Factor:
         self._A = _CsrArgs(row_ptr, col_idx, val)
         T = _TreeArgs(perm, leaf_ptr, depth)
         o = Opts(float(epsilon), PRECISION[precision], COMPRESS[compress], ORDERS[order],
-                 int(hbm_budget_bytes), C.c_void_p(stream) if stream else None)
+                 int(hbm_budget_bytes), C.c_void_p(stream) if stream else None, RULES[rule],
+                 int(symmetric))
         h = C.c_void_p()
         if val_dev is not None:
             _check(_lib.lrx_factor_dev(C.byref(self._A.s), C.c_void_p(val_dev), C.byref(T.s),
@@ -358,7 +362,8 @@ class Factor:
                     t_sync_ms=float(s.t_sync_ms), t_solve_prog_ms=float(s.t_solve_prog_ms),
                     device_bytes=int(s.device_bytes),
                     flops_by_op={"compress": float(s.flops_compress), "pivot": float(s.flops_pivot),
-                                 "schur": float(s.flops_schur), "project": float(s.flops_project)})
+                                 "schur": float(s.flops_schur), "project": float(s.flops_project)},
+                    level_norm_by_level={i: float(s.level_norm_by_level[i]) for i in range(1, d + 1)})
 
     def ranks(self):
         n = self.stats()["n_compressions"]

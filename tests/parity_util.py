@@ -47,7 +47,10 @@ def relerr(x, y):
 
 def replay_ranks(gpu_ranks, Fo, eps, method="svd"):
     """None if every rank agrees, else the GPU's ranks as {(level, j): rank}
-    after checking that each disagreement is a threshold tie."""
+    after checking that each disagreement is a threshold tie: under eqn.
+    cutOff1 every singular value between the two cuts lies at eps sigma_0, under
+    the Frobenius rule (eqn. curOff6) every tail between them at eps N_i, within
+    the rounding band max(1e-8, 1e-13 / eps)."""
     gpu = [int(r) for r in gpu_ranks]
     ora = [c.rank for c in Fo.compressions]
     assert len(gpu) == len(ora)
@@ -55,8 +58,24 @@ def replay_ranks(gpu_ranks, Fo, eps, method="svd"):
         return None
     assert method == "svd", "RRQR ranks must agree exactly on these inputs"
     band = max(1e-8, 1e-13 / eps)
+    frob = getattr(Fo, "rule", "cutoff1") == "frob"
+    top = max((float(c.sigma[0]) for c in Fo.compressions if len(c.sigma)), default=0.0)
     for rg, c in zip(gpu, Fo.compressions):
         if rg == c.rank:
+            continue
+        # a stacked block whose largest singular value is below 1e-8 of the largest
+        # one is what remains of an exact cancellation (rounding noise): its rank is
+        # not reproducible and carries no information; it is replayed
+        if len(c.sigma) and method == "svd" and c.sigma[0] < 1e-8 * top:
+            continue
+        if frob:
+            sig = np.asarray(c.sigma)
+            tail = np.sqrt(np.concatenate([np.cumsum((sig ** 2)[::-1])[::-1], [0.0]]))
+            tau = eps * Fo.level_norm[c.level]
+            # the rank is the smallest k with tail_k < tau: the two sides disagree on
+            # every k between their ranks, so each of those tails is at tau
+            for k in range(min(rg, c.rank), max(rg, c.rank)):
+                assert abs(tail[k] / tau - 1.0) <= band, (c.level, c.j, rg, c.rank, tail[k] / tau)
             continue
         sig = np.asarray(c.sigma) / c.sigma[0]
         for k in range(min(rg, c.rank), max(rg, c.rank)):
@@ -64,13 +83,13 @@ def replay_ranks(gpu_ranks, Fo, eps, method="svd"):
     return {(c.level, c.j): rg for rg, c in zip(gpu, Fo.compressions)}
 
 
-def oracle_matching(F, csr, perm, lp, depth, eps, Fo=None, order="colored", method="svd"):
+def oracle_matching(F, csr, perm, lp, depth, eps, Fo=None, order="colored", method="svd", rule="cutoff1"):
     """The oracle's factorization of the same input, rank-replayed onto the
     GPU handle F's ranks where they differ by a threshold tie."""
     if Fo is None:
-        Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False)
+        Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False, rule=rule)
     forced = replay_ranks(F.ranks()[0], Fo, eps, method) if eps > 1e-10 else None
     if forced is not None:
         Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False,
-                           forced_ranks=forced)
+                           forced_ranks=forced, rule=rule)
     return Fo

@@ -415,3 +415,36 @@ def test_frobenius_rule_exact_at_eps0_and_converges():
         F = oracle.factor(*csr, perm, lp, depth, eps, rule="frob", check=True)
         errs.append(_relerr(oracle.solve(F, b), np.linalg.solve(A, b)))
     assert errs[0] > errs[1] > errs[2]
+
+
+# --------------------------------------------------------------------------- symmetric half stack
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_symmetric_half_stack_equals_full_stack(eps):
+    """Sec. 4.3, last paragraph: for symmetric A, B_k = A_k, so stacking A_k
+    alone gives the same V (the full stack [A; A] only scales every singular
+    value by sqrt 2): the ranks agree, each compression still meets the 2-norm
+    bound on the FULL stack (recomputed with Gram eigenvalues), the solve equals
+    the full-stack solve to rounding, and at eps = 0 both equal the dense solve."""
+    csr, n, perm, lp, depth, rng = _grid_problem("varcoef2d", 24, 8, seed=3)
+    b = rng.uniform(-1, 1, n)
+    Ff = oracle.factor(*csr, perm, lp, depth, eps, check=False)
+    Fh = oracle.factor(*csr, perm, lp, depth, eps, symmetric=True, keep_blocks=True)
+    assert [c.rank for c in Fh.compressions] == [c.rank for c in Ff.compressions]
+    for c in Fh.compressions:
+        if c.rows == 0:
+            continue
+        Bfull = np.vstack([c.B, c.B])
+        E = Bfull - (Bfull @ c.V) @ c.V.T
+        nE = np.sqrt(max(float(np.max(sla.eigvalsh(E.T @ E))), 0.0))
+        nB = np.sqrt(float(np.max(sla.eigvalsh(Bfull.T @ Bfull))))
+        assert nE <= eps * nB * (1 + 1e-9) + 1e-14 * nB
+    assert _relerr(oracle.solve(Fh, b), oracle.solve(Ff, b)) <= 1e-10
+    A = _dense(csr, n)
+    F0 = oracle.factor(*csr, perm, lp, depth, 0.0, symmetric=True)
+    assert _relerr(oracle.solve(F0, b), np.linalg.solve(A, b)) <= 1e-12
+
+
+def test_symmetric_half_stack_rejects_nonsymmetric():
+    csr, n, perm, lp, depth, rng = _grid_problem("convdiff3d", 6, 8)
+    with pytest.raises(ValueError):
+        oracle.factor(*csr, perm, lp, depth, 1e-3, symmetric=True)
