@@ -39,8 +39,8 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 # x 1.00); kept per (workload, precision, kernel class) and reported as the
 # roofline's traffic.
 TRAFFIC_BYTES = {
-    ("varcoef2d_256", "mixed", "compress"): 2.197e6,
-    ("varcoef2d_256", "fp64", "compress"): 2.208e6,
+    ("varcoef2d_256", "mixed", "compress"): 1.388e6,
+    ("varcoef2d_256", "fp64", "compress"): 1.382e6,
 }
 TOL = 1e-10
 RESTART = 30

@@ -179,7 +179,10 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
            symmetric=False):
     """Algorithm 1.  Inputs are a CSR matrix (0-based) and the cluster tree.
 
-    compress:     'svd' (eqn. cutOff1, as in the paper's experiments) or 'rrqr'.
+    compress:     'svd' (eqn. cutOff1, as in the paper's experiments), 'rrqr', or
+                  'rand' (adaptive randomized range finder, rand_compress, for
+                  stacked blocks of at most RAND_LMAX columns; wider ones take
+                  'svd').
     rule:         'cutoff1': keep sigma_k >= epsilon sigma_0 of each stacked block
                   (eqn. cutOff1; RRQR: ||R22||_F <= epsilon |R11|);
                   'frob': the paper's variant of eqn. curOff6: the smallest k
@@ -296,7 +299,8 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
             if forced_ranks is not None and (i, j) in forced_ranks:
                 forced = int(forced_ranks[(i, j)])
             tau = epsilon * level_norm[i] if rule == "frob" else None
-            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress, tau, symmetric)
+            rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress, tau, symmetric,
+                            task=(i << 24) | j)
             rec.level, rec.j = i, j
             compressions.append(rec)
 
@@ -360,8 +364,91 @@ def rrqr_rows(B, epsilon, forced_rank=None, tau=None):
     return k, V, piv, tails
 
 
+# ------------------------------------------------------------- randomized compression
+# Randomized range finder (Sec. 7 lists randomized SVD among the low-rank methods
+# the algorithm admits), with the draws taken from a counter-based generator so
+# that any implementation reproduces them: SplitMix64 (Steele, Lea and Flood,
+# "Fast splittable pseudorandom number generators", 2014), output of the state
+# equal to the counter.  The sketch is a Rademacher (random sign) matrix: sign of
+# the top bit of the output for counter (task << 34) + (row << 6) + column,
+# task = (level << 24) | j.
+_M64 = (1 << 64) - 1
+RAND_L0, RAND_LMAX = 16, 64
+
+
+def splitmix64(x):
+    """SplitMix64 output for state x (the state is advanced by the golden gamma
+    before mixing, as in the published generator)."""
+    z = (int(x) + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def rademacher(task, rows, cols):
+    """rows x cols matrix of +-1: entry (a, t) is +1 when the top bit of
+    splitmix64((task << 34) + (a << 6) + t) is 0."""
+    out = np.empty((rows, cols))
+    for a in range(rows):
+        for t in range(cols):
+            h = splitmix64(((task << 34) + (a << 6) + t) & _M64)
+            out[a, t] = -1.0 if (h >> 63) else 1.0
+    return out
+
+
+def rand_rank(sig, uncaptured2, eps):
+    """Smallest k with sqrt(uncaptured2 + sum_{t >= k} sig_t^2) <= eps sig_0 (the
+    Frobenius norm of the discarded part, an upper bound of its 2-norm), or None
+    when even k = len(sig) does not qualify."""
+    if len(sig) == 0 or sig[0] == 0.0:
+        return 0 if uncaptured2 == 0.0 else None
+    thr = eps * sig[0]
+    t2 = uncaptured2
+    if not (np.sqrt(t2) <= thr):
+        return None
+    r = len(sig)
+    for k in range(len(sig) - 1, -1, -1):
+        t2 += sig[k] * sig[k]
+        if np.sqrt(t2) <= thr:
+            r = k
+        else:
+            break
+    return r
+
+
+def rand_compress(B, epsilon, task, l0=RAND_L0, lmax=RAND_LMAX):
+    """Adaptive randomized compression of the stacked block B (M x c).
+    With l = min(c, l0) sketch columns: Y = B^T Omega (Omega the Rademacher
+    M x l matrix of the task), Q = the orthonormal factor of Householder QR of Y
+    (c x l), C = B Q, C = U S W^T; the uncaptured energy is ||B||_F^2 - sum S^2
+    (0 when l = c: Q is then a basis of the whole column space).  The rank is
+    rand_rank(S, uncaptured, eps): the fewest directions whose discarded part
+    has Frobenius norm <= eps S_0 <= eps ||B||_2, so ||B - B V V^T||_2 <= eps
+    ||B||_2 holds (a-posteriori check).  Accepted when that rank is below l, or
+    l = c; otherwise l doubles.  Returns (r, V, S, l), or None when l would
+    exceed lmax while c > lmax (the caller then takes the SVD)."""
+    M, c = B.shape
+    l = min(c, l0)
+    nB2 = float(np.sum(B * B))
+    while True:
+        Om = rademacher(task, M, l)
+        Y = B.T @ Om
+        Q, _ = np.linalg.qr(Y)                       # Householder (LAPACK geqrf), reduced
+        C = B @ Q
+        _, S, Wt = np.linalg.svd(C, full_matrices=False)
+        unc = 0.0 if l == c else max(0.0, nB2 - float(np.sum(S * S)))
+        r = rand_rank(S, unc, epsilon)
+        if l == c or (r is not None and r < l):
+            if r is None:
+                r = l
+            return r, Q @ Wt[:r].T, S, l
+        if 2 * l > lmax and c > lmax:
+            return None
+        l = min(c, 2 * l)
+
+
 def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
-              method="svd", tau=None, symmetric=False):
+              method="svd", tau=None, symmetric=False, task=0):
     """Compress(s): replace the well-separated edges of s by low-rank edges through
     its black node b and the parent red node P = P(b) (Sec. 4.3, eqn. lra,
     eqn. anterpol, eqn. interpol and the edge-update list)."""
@@ -378,6 +465,17 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
         B = np.vstack(parts)
     else:
         B = np.zeros((0, m))
+    if method == "rand" and m > RAND_LMAX:
+        method = "svd"                                  # blocks wider than the widest sketch
+    if method == "rand":
+        res = rand_compress(B, epsilon, task) if (B.shape[0] > 0 and m > 0) else (0, np.zeros((m, 0)),
+                                                                                   np.zeros(0), 0)
+        if res is None:
+            method = "svd"
+        else:
+            r, V, sig, _ = res
+            if forced_rank is not None and forced_rank != r:
+                raise ValueError("rank replay is not supported for randomized compression")
     if method == "svd":
         if B.shape[0] > 0 and m > 0:
             _, sig, Vt = np.linalg.svd(B, full_matrices=False)
@@ -396,6 +494,8 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
         else:
             r = int(np.count_nonzero(sig >= epsilon * sig[0]))   # eqn. cutOff1
         V = Vt[:r].T.copy()                           # m x r, orthonormal columns
+    elif method == "rand":
+        pass
     elif method == "rrqr":
         if B.shape[0] > 0 and m > 0:
             r, V, _, sig = rrqr_rows(B, epsilon, forced_rank, tau)

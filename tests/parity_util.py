@@ -83,13 +83,31 @@ def replay_ranks(gpu_ranks, Fo, eps, method="svd"):
     return {(c.level, c.j): rg for rg, c in zip(gpu, Fo.compressions)}
 
 
-def oracle_matching(F, csr, perm, lp, depth, eps, Fo=None, order="colored", method="svd", rule="cutoff1"):
+def oracle_matching(F, csr, perm, lp, depth, eps, Fo=None, order="colored", method="svd", rule="cutoff1",
+                    **kw):
     """The oracle's factorization of the same input, rank-replayed onto the
-    GPU handle F's ranks where they differ by a threshold tie."""
+    GPU handle F's ranks where they differ by a threshold tie.  A tie changes
+    every later block, so the replay goes tie by tie: the first compression
+    whose rank differs must be a tie (replay_ranks on it alone); the oracle is
+    re-run with the GPU's ranks up to and including it, and compared again."""
+    def run(forced):
+        return oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False, rule=rule,
+                             forced_ranks=forced, **kw)
     if Fo is None:
-        Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False, rule=rule)
-    forced = replay_ranks(F.ranks()[0], Fo, eps, method) if eps > 1e-10 else None
-    if forced is not None:
-        Fo = oracle.factor(*csr, perm, lp, depth, eps, order=order, compress=method, check=False,
-                           forced_ranks=forced, rule=rule)
-    return Fo
+        Fo = run(None)
+    if eps <= 1e-10:
+        return Fo
+    gpu = [int(r) for r in F.ranks()[0]]
+    forced = {}
+    for _ in range(64):
+        diff = [q for q, c in enumerate(Fo.compressions) if gpu[q] != c.rank]
+        if not diff:
+            return Fo
+        q = diff[0]
+        # the first disagreement alone must be a threshold tie (or a noise block)
+        only = [c.rank if k != q else gpu[q] for k, c in enumerate(Fo.compressions)]
+        replay_ranks(only, Fo, eps, method)
+        for k, c in enumerate(Fo.compressions[:q + 1]):
+            forced[(c.level, c.j)] = gpu[k]
+        Fo = run(dict(forced))
+    raise AssertionError("rank replay did not converge")

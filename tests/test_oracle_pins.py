@@ -448,3 +448,61 @@ def test_symmetric_half_stack_rejects_nonsymmetric():
     csr, n, perm, lp, depth, rng = _grid_problem("convdiff3d", 6, 8)
     with pytest.raises(ValueError):
         oracle.factor(*csr, perm, lp, depth, 1e-3, symmetric=True)
+
+
+# --------------------------------------------------------------------------- randomized compression
+def test_splitmix64_published_outputs():
+    """The counter-based generator of the sketch: the first outputs of SplitMix64
+    from state 0 are the published 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4,
+    0x06c45d188009454f (state advanced by the golden gamma each step)."""
+    from oracle.factor import splitmix64
+    g = 0x9E3779B97F4A7C15
+    assert [splitmix64((k * g) & ((1 << 64) - 1)) for k in range(3)] == \
+        [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_rand_compress_full_sketch_is_exact_svd():
+    """With the sketch as wide as B (l = c) Q spans everything: the sketched
+    singular values are B's (an independent SVD) and the rank is the smallest
+    k whose tail has Frobenius norm <= eps sigma_0, computed from that SVD."""
+    from oracle.factor import rand_compress
+    rng = np.random.default_rng(7)
+    for M, c, eps in ((40, 12, 1e-3), (30, 30, 1e-6), (50, 9, 0.1)):
+        U, _ = np.linalg.qr(rng.standard_normal((M, c)))
+        W, _ = np.linalg.qr(rng.standard_normal((c, c)))
+        sv = np.logspace(0, -9, c)
+        B = (U * sv) @ W.T
+        r, V, S, l = rand_compress(B, eps, task=123, l0=c)
+        assert l == c
+        ex = np.linalg.svd(B, compute_uv=False)
+        assert np.allclose(S, ex, rtol=1e-10, atol=1e-14)
+        tail = np.sqrt(np.concatenate([np.cumsum((ex ** 2)[::-1])[::-1], [0.0]]))
+        assert r == int(np.nonzero(tail <= eps * ex[0])[0][0])
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_rand_compress_bound_in_factorization(eps):
+    """Every randomized compression meets ||B - B V V^T||_2 <= eps ||B||_2
+    (Gram eigenvalues); V is orthonormal; the sketch grows only as needed."""
+    csr, n, perm, lp, depth, rng = _grid_problem("lognormal3d", 8, 8, seed=9)
+    F = oracle.factor(*csr, perm, lp, depth, eps, compress="rand", keep_blocks=True)
+    for c in F.compressions:
+        if c.rows == 0 or c.m == 0:
+            continue
+        B, V = c.B, c.V
+        assert np.allclose(V.T @ V, np.eye(V.shape[1]), atol=1e-12)
+        E = B - (B @ V) @ V.T
+        nE = np.sqrt(max(float(np.max(sla.eigvalsh(E.T @ E))), 0.0))
+        nB = np.sqrt(float(np.max(sla.eigvalsh(B.T @ B))))
+        assert nE <= eps * nB * (1 + 1e-9) + 1e-13 * nB
+
+
+def test_rand_factorization_exact_at_eps0_and_converges():
+    csr, n, perm, lp, depth, rng = _grid_problem("varcoef2d", 24, 8, seed=4)
+    A = _dense(csr, n)
+    b = rng.uniform(-1, 1, n)
+    F0 = oracle.factor(*csr, perm, lp, depth, 0.0, compress="rand")
+    assert _relerr(oracle.solve(F0, b), np.linalg.solve(A, b)) <= 1e-12
+    errs = [_relerr(oracle.solve(oracle.factor(*csr, perm, lp, depth, e, compress="rand", check=False), b),
+                    np.linalg.solve(A, b)) for e in (1e-2, 1e-4, 1e-6)]
+    assert errs[0] > errs[1] > errs[2]
