@@ -157,9 +157,10 @@ def roofline(timing, dom, precision="fp64"):
         per_launch = d["flops"] / max(d["launches"], 1)
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         # the compression's arithmetic runs on the vector ALUs (FP32 in mixed
-        # precision); the Schur and projection products on the matrix cores
-        # (FP64 MFMA, or FP32 MFMA in mixed precision: same published peaks)
-        # (the pivot inverses of factor_node stay FP64 in every mode)
+        # precision; the Gram-path class compress_gram computes in FP64); the
+        # Schur and projection products on the matrix cores (FP64 MFMA, or FP32
+        # MFMA in mixed precision: same published peaks) (the pivot inverses of
+        # factor_node stay FP64 in every mode)
         mixed = precision in ("mixed", "mixed_bf16") and dom in ("compress", "schur", "project")
         peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
         if dom == "project" and precision == "mixed_bf16":

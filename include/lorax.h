@@ -68,7 +68,7 @@ typedef enum {
  * to its tolerance, with more iterations. */
 typedef enum { LRX_FP64 = 0, LRX_MIXED = 1, LRX_MIXED_BF16 = 2 } lrx_precision;
 typedef enum { LRX_COLORED = 0, LRX_NATURAL = 1 } lrx_order;
-typedef enum { LRX_SVD = 0, LRX_RRQR = 1 } lrx_compress;
+typedef enum { LRX_SVD = 0, LRX_RRQR = 1, LRX_RAND = 2 } lrx_compress;
 /* Truncation rule of Compress.  LRX_RULE_CUTOFF1 (eqn. cutOff1): keep sigma_k >=
  * epsilon sigma_0 of each stacked block (RRQR: stop at ||R22||_F <= epsilon |R11|).
  * LRX_RULE_FROB, the paper's variant of eqn. curOff6: keep the fewest singular
@@ -107,7 +107,19 @@ typedef struct {
                                   LRX_SVD: keep sigma_k >= epsilon * sigma_0 of the stacked block B
                                   (eqn. cutOff1), so ||B - B V V^T||_2 < epsilon ||B||_2.
                                   LRX_RRQR: row-pivoted QR of B stopped at the first k with
-                                  ||R22||_F <= epsilon |R11|, so ||B - B V V^T||_2 <= epsilon ||B||_2. */
+                                  ||R22||_F <= epsilon |R11|, so ||B - B V V^T||_2 <= epsilon ||B||_2.
+                                  LRX_RAND (randomized SVD, one of the low-rank methods Sec. 7
+                                  lists): blocks of at most 64 columns by an adaptive randomized
+                                  range finder on the nonzero rows and columns of B: sketch
+                                  Y = B^T Omega with l = min(16, c_nz) Rademacher columns drawn
+                                  from SplitMix64 of (((level << 24) | j) << 34) + (row << 6) + col
+                                  (row counted among the nonzero rows of B, stacking order),
+                                  Q = Householder QR of Y, C = B Q = U S W^T; rank = fewest k with
+                                  sqrt(||B||_F^2 - sum S^2 + sum_{t>=k} S_t^2) <= epsilon S_0
+                                  (uncaptured energy 0 when l = c_nz), accepted when k < l or
+                                  l = c_nz, else l doubles; V = Q W_k.  Then again
+                                  ||B - B V V^T||_2 <= epsilon ||B||_2.  Wider blocks take the SVD.
+                                  Needs rule LRX_RULE_CUTOFF1. */
     int32_t precision;         /* lrx_precision */
     int32_t compress;          /* lrx_compress: low-rank method of Compress (Sec. 4.3) */
     int32_t order;             /* lrx_order: order of the super-nodes inside a level */
@@ -149,6 +161,8 @@ typedef struct {
     double flops_schur;            /* Schur-complement products, W_k = S^-1 Mat(k->v) included */
     double flops_project;          /* projection [R; Q] = B V */
     double level_norm_by_level[32];/* LRX_RULE_FROB: N_i of eqn. curOff6 by level (0 otherwise) */
+    int64_t sweep_stages;          /* LDS stages of both sweeps' node programs, summed over the nodes */
+    int64_t sweep_launches;        /* launches of one solve application (one per colour step and sweep) */
 } lrx_stats_t;
 
 /* Symbolic counts, computed on the host without any device call. */
@@ -309,6 +323,8 @@ lrx_status lrx_ranks(lrx_handle h, int32_t* ranks, int32_t* levels, int32_t* js)
  *           *len = c + 1.
  * LRX_RRQR: out[0] = |R11| (largest row norm of B), out[1 + k] = ||R22||_F before
  *           pivot step k, k = 0..rank; *len = rank + 2.
+ * LRX_RAND: as LRX_SVD, with the singular values of the sketched block C = B Q
+ *           (l of them, then zeros) for the blocks of at most 64 columns.
  * At most cap values are written. */
 lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t cap, int32_t* len);
 
@@ -328,6 +344,7 @@ typedef enum {
     LRX_K_SPMV = 4,           /* A times the preconditioned vectors (GMRES) */
     LRX_K_SCHUR = 5,          /* Schur-complement products of Eliminate(s), Eliminate(b) (Sec. 2.2) */
     LRX_K_PROJECT = 6,        /* projection [R; Q] = B V of the compressed blocks (Sec. 4.3) */
+    LRX_K_COMPRESS_GRAM = 7,  /* Compress of blocks of <= 64 columns through the FP64 Gram matrix (mixed) */
     LRX_K_CLASSES = 8
 } lrx_kernel_class;
 
@@ -364,7 +381,11 @@ typedef struct {
                                  application) into a HIP graph after the first application and
                                  replays it at every later Arnoldi step (not on the null stream,
                                  nor while solve sweeps are event-timed); 0: direct launches */
-    int32_t reserved[1];
+    int32_t compress_gram;    /* SVD compression of stacked blocks of <= 64 columns at epsilon >= 1e-5
+                                 through the FP64 Gram matrix B^T B and two-sided Jacobi (sigma_k off by
+                                 about c u sigma_0^2 / sigma_k; values below about 1e-7 sigma_0 not
+                                 resolved) instead of QR-preconditioned one-sided Jacobi: 0 never,
+                                 1 in mixed precision (default), 2 in mixed and FP64 precision */
 } lrx_tune;
 
 lrx_status lrx_tune_get(lrx_tune* t);

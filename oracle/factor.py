@@ -180,9 +180,12 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
     """Algorithm 1.  Inputs are a CSR matrix (0-based) and the cluster tree.
 
     compress:     'svd' (eqn. cutOff1, as in the paper's experiments), 'rrqr', or
-                  'rand' (adaptive randomized range finder, rand_compress, for
-                  stacked blocks of at most RAND_LMAX columns; wider ones take
-                  'svd').
+                  'rand' (adaptive randomized range finder, rand_compress, on
+                  the nonzero rows and columns of the stacked block when it has
+                  at most RAND_LMAX nonzero columns; wider ones take 'svd'; every
+                  V of the factorization then has each column's entry of largest
+                  magnitude positive, so that the auxiliary variables, and with
+                  them the sketches of later blocks, are defined uniquely).
     rule:         'cutoff1': keep sigma_k >= epsilon sigma_0 of each stacked block
                   (eqn. cutOff1; RRQR: ||R22||_F <= epsilon |R11|);
                   'frob': the paper's variant of eqn. curOff6: the smallest k
@@ -300,7 +303,7 @@ def factor(row_ptr, col_idx, val, perm, leaf_ptr, depth, epsilon, order="colored
                 forced = int(forced_ranks[(i, j)])
             tau = epsilon * level_norm[i] if rule == "frob" else None
             rec = _compress(G, s, b, P, cand, epsilon, forced, keep_blocks, compress, tau, symmetric,
-                            task=(i << 24) | j)
+                            task=(i << 24) | j, canon_sign=compress == "rand")
             rec.level, rec.j = i, j
             compressions.append(rec)
 
@@ -448,7 +451,7 @@ def rand_compress(B, epsilon, task, l0=RAND_L0, lmax=RAND_LMAX):
 
 
 def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
-              method="svd", tau=None, symmetric=False, task=0):
+              method="svd", tau=None, symmetric=False, task=0, canon_sign=False):
     """Compress(s): replace the well-separated edges of s by low-rank edges through
     its black node b and the parent red node P = P(b) (Sec. 4.3, eqn. lra,
     eqn. anterpol, eqn. interpol and the edge-update list)."""
@@ -465,15 +468,23 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
         B = np.vstack(parts)
     else:
         B = np.zeros((0, m))
-    if method == "rand" and m > RAND_LMAX:
+    # the randomized range finder works on the nonzero part of B: the rows and
+    # columns that are zero (variables of a candidate that s does not touch) take
+    # no part in the draw, so the sketch does not depend on that padding; its row
+    # index is the position among the nonzero rows, in stacking order
+    nzr = np.any(B != 0.0, axis=1) if B.size else np.zeros(B.shape[0], dtype=bool)
+    nzc = np.any(B != 0.0, axis=0) if B.size else np.zeros(m, dtype=bool)
+    if method == "rand" and int(nzc.sum()) > RAND_LMAX:
         method = "svd"                                  # blocks wider than the widest sketch
     if method == "rand":
-        res = rand_compress(B, epsilon, task) if (B.shape[0] > 0 and m > 0) else (0, np.zeros((m, 0)),
-                                                                                   np.zeros(0), 0)
+        Bz = B[nzr][:, nzc]
+        res = rand_compress(Bz, epsilon, task) if Bz.size else (0, np.zeros((Bz.shape[1], 0)), np.zeros(0), 0)
         if res is None:
             method = "svd"
         else:
-            r, V, sig, _ = res
+            r, Vz, sig, _ = res
+            V = np.zeros((m, r))
+            V[nzc] = Vz
             if forced_rank is not None and forced_rank != r:
                 raise ValueError("rank replay is not supported for randomized compression")
     if method == "svd":
@@ -504,6 +515,13 @@ def _compress(G, s, b, P, cand, epsilon, forced_rank=None, keep_blocks=False,
             r, V, sig = 0, np.zeros((m, 0)), np.zeros(0)
     else:
         raise ValueError(method)
+    if canon_sign and V.size:
+        # the auxiliary variables of b and P are the columns of V, each defined up
+        # to its sign; a randomized sketch of a later stacked block sees that sign
+        # (a deterministic SVD does not), so each column is fixed with its entry of
+        # largest magnitude positive (lowest row on exact ties)
+        piv = np.argmax(np.abs(V), axis=0)
+        V = V * np.where(V[piv, np.arange(V.shape[1])] < 0.0, -1.0, 1.0)
     RQ = B @ V                                         # [R_1;..;R_t;Q_1;..;Q_t]
     rec = CompressionRecord(0, 0, B.shape[0], m, r, sig, list(cand),
                             B.copy() if keep_blocks else None,

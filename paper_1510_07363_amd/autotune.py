@@ -40,7 +40,7 @@ CANDIDATES = {
     "sweep_nk_max": [2, 4, 8],
     "gemm_grid": [0, 512, 1024, 2048],
 }
-FACTOR_CLASSES = ("compress", "factor_node", "schur", "project")
+FACTOR_CLASSES = ("compress", "compress_gram", "factor_node", "schur", "project")
 SOLVE_CLASSES = ("solve_fwd", "solve_bwd")
 
 

@@ -33,7 +33,7 @@ struct DPiece {
 //        Jacobi SVD gives sigma and V; rank = #{sigma_k >= eps * sigma_0}.
 //   RRQR: B is assembled row-major and overwritten by the row-pivoted QR.
 struct DCompress {
-    int32_t piece0, npieces;
+    int32_t piece0, npieces;   // npieces < 0 (small-block SVD only): B is already in place
     int32_t M, c;
     double* B;          // SVD: M x c column-major (kept); RRQR: M x c row-major (overwritten)
     double* Bw;         // SVD: working copy of B (M x c column-major)
@@ -46,6 +46,20 @@ struct DCompress {
     const double* tau;  // nullptr: cut-off of eqn. cutOff1 (eps relative to sigma_0); else the
                         // absolute threshold of eqn. curOff6: the smallest k whose discarded
                         // tail has Frobenius norm < *tau (RRQR: ||R22||_F < *tau)
+    const double* nb2;  // randomized compression (the sketched block C = B Q is this task):
+                        // ||B||_F^2 of the original stacked block, for the rank rule of the
+                        // sketch (nullptr otherwise)
+    int32_t rand_full;  // the sketch spans every column of B (nothing uncaptured)
+    int32_t rand_pad_;
+};
+
+// Randomized compression of one stacked block with at most 64 columns: the
+// requested sketch width l and the task key of its counter-based sketch (the
+// sketched block C = B Q, M x l, is compressed by a task of its own at the same
+// index, whose width and full-sketch flag the sketch kernel fills in).
+struct DRand {
+    int32_t l, active;
+    int64_t key;
 };
 
 // ---- Node factorization: projection, rewiring, Eliminate(s), Eliminate(b) ---

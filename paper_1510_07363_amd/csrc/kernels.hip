@@ -244,6 +244,23 @@ __device__ int frob_rank(const double* desc, int kk, double extra2, double tau) 
     return r;
 }
 
+// Rank rule of the randomized compression: the smallest k with
+// sqrt(unc + sum_{t >= k} desc[t]^2) <= eps desc[0], or n + 1 when even k = n
+// does not qualify (desc: n values in descending order).
+__device__ int rand_rank(const double* desc, int n, double unc, double eps) {
+    if (n == 0 || desc[0] == 0.0) return unc == 0.0 ? 0 : n + 1;
+    const double thr = eps * desc[0];
+    double t2 = unc;
+    if (!(sqrt(t2) <= thr)) return n + 1;
+    int r = n;
+    for (int k = n - 1; k >= 0; --k) {
+        t2 += desc[k] * desc[k];
+        if (sqrt(t2) <= thr) r = k;
+        else break;
+    }
+    return r;
+}
+
 __device__ double block_sum(double v, double* s_s) {
     v = wave_sum(v);
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -619,9 +636,127 @@ __device__ void qr64(T* A, int nr, int c, int ld, bool pivot, int* perm, T* hv0,
     }
 }
 
+// R1 (c x c upper triangular, into X as F, ld ldx) and perm (the original column
+// at each position) of B (M x c, column-major in HBM, scaled by inv_scale):
+// FP64 Gram matrix from LDS chunks of 64 rows (2 x 2 register blocks, upper
+// half mirrored), then right-looking Cholesky with diagonal pivoting (largest
+// remaining diagonal, lowest index on ties) in LDS.  work: at least
+// 64 (65) + 64 (65) doubles of LDS.  NTC >= 1024 is not needed: blocks loop.
+template <class F, int NTC>
+__device__ void gram_chol_r1(const double* __restrict__ B, int M, int c, double inv_scale, double* work, F* X,
+                             int ldx, int* perm) {
+    constexpr int RCH = 64;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int ld = c | 1, ldb = c + 1;
+    double* G = work;                        // c x c (ld)
+    double* Bc = work + WAVE * (WAVE + 1);   // RCH x (c + 1), row-major
+    __shared__ double s_d[2];
+    __shared__ int s_p[2];
+    const int nb = (c + 1) / 2, nblk = nb * nb;
+    constexpr int BPT = (32 * 32 + NTC - 1) / NTC;    // 2 x 2 blocks per thread (c <= 64)
+    double acc[BPT][4];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) acc[u][0] = acc[u][1] = acc[u][2] = acc[u][3] = 0.0;
+    for (int a0 = 0; a0 < M; a0 += RCH) {
+        const int nr = min(RCH, M - a0);
+        for (int e = tid; e < nr * c; e += NTC) {
+            const int r = e % nr, k = e / nr;
+            Bc[r * ldb + k] = B[(a0 + r) + (int64_t)k * M] * inv_scale;
+        }
+        if (c & 1)
+            for (int r = tid; r < nr; r += NTC) Bc[r * ldb + c] = 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < BPT; ++u) {
+            const int blk = tid + u * NTC;
+            const int bi = blk / max(nb, 1), bk = blk % max(nb, 1);
+            if (blk < nblk && bi <= bk) {
+                const int i0 = 2 * bi, k0 = 2 * bk;
+                for (int r = 0; r < nr; ++r) {
+                    const double* row = Bc + r * ldb;
+                    const double x0 = row[i0], x1 = row[i0 + 1], y0 = row[k0], y1 = row[k0 + 1];
+                    acc[u][0] = fma(x0, y0, acc[u][0]);
+                    acc[u][1] = fma(x0, y1, acc[u][1]);
+                    acc[u][2] = fma(x1, y0, acc[u][2]);
+                    acc[u][3] = fma(x1, y1, acc[u][3]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int blk = tid + u * NTC;
+        const int bi = blk / max(nb, 1), bk = blk % max(nb, 1);
+        if (blk < nblk && bi <= bk) {
+            const int i0 = 2 * bi, k0 = 2 * bk, i1 = i0 + 1, k1 = k0 + 1;
+            G[i0 + k0 * ld] = acc[u][0]; G[k0 + i0 * ld] = acc[u][0];
+            if (k1 < c) { G[i0 + k1 * ld] = acc[u][1]; G[k1 + i0 * ld] = acc[u][1]; }
+            if (i1 < c) { G[i1 + k0 * ld] = acc[u][2]; G[k0 + i1 * ld] = acc[u][2]; }
+            if (i1 < c && k1 < c) { G[i1 + k1 * ld] = acc[u][3]; G[k1 + i1 * ld] = acc[u][3]; }
+        }
+    }
+    for (int j = tid; j < c; j += NTC) perm[j] = j;
+    __syncthreads();
+    double trace = 0.0;
+    for (int k = 0; k < c; ++k) trace += G[k + k * ld];
+    const double stop = 1.1102230246251565e-16 * (double)c * trace;
+    int kk = c;
+    for (int k = 0; k < c; ++k) {
+        // pivot: largest remaining diagonal (one wavefront; c <= 64)
+        if (tid < WAVE) {
+            double v = lane >= k && lane < c ? G[lane + lane * ld] : -1.0;
+            int i = lane;
+            for (int o = WAVE / 2; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(v, o);
+                const int oi = __shfl_xor(i, o);
+                if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+            }
+            if (lane == 0) { s_d[0] = v; s_p[0] = i; }
+        }
+        __syncthreads();
+        const double dk = s_d[0];
+        const int pk = s_p[0];
+        if (!(dk > stop)) { kk = k; break; }             // uniform: the rest is numerically zero
+        if (pk != k) {                                   // symmetric swap of k and pk
+            for (int j = tid; j < c; j += NTC) {
+                const double a = G[k + j * ld];
+                G[k + j * ld] = G[pk + j * ld];
+                G[pk + j * ld] = a;
+            }
+            __syncthreads();
+            for (int j = tid; j < c; j += NTC) {
+                const double a = G[j + k * ld];
+                G[j + k * ld] = G[j + pk * ld];
+                G[j + pk * ld] = a;
+            }
+            if (tid == 0) { const int t = perm[k]; perm[k] = perm[pk]; perm[pk] = t; }
+            __syncthreads();
+        }
+        // row k of R1: r_kk = sqrt(g_kk), r_kj = g_kj / r_kk (into G's row k)
+        const double rkk = sqrt(G[k + k * ld]);
+        __syncthreads();                                 // everyone has read g_kk
+        for (int j = k + tid; j < c; j += NTC) G[k + j * ld] = j == k ? rkk : G[k + j * ld] / rkk;
+        __syncthreads();
+        // trailing update G[i][j] -= r_ki r_kj, i, j > k
+        const int nt = c - k - 1;
+        for (int e = tid; e < nt * nt; e += NTC) {
+            const int i = k + 1 + e % nt, j = k + 1 + e / nt;
+            G[i + j * ld] -= G[k + i * ld] * G[k + j * ld];
+        }
+        __syncthreads();
+    }
+    // X = R1 (rows >= kk zero)
+    for (int e = tid; e < c * c; e += NTC) {
+        const int i = e % c, j = e / c;
+        X[i + j * ldx] = (i <= j && i < kk) ? (F)G[i + j * ld] : (F)0;
+    }
+    __syncthreads();
+}
+
 // T = float: the reduced QRs and Jacobi in FP32 (mixed precision); B, the
 // projection B V and all outputs stay FP64.
-template <class F, int NTC>
+template <class F, int NTC, bool GRAM>
 __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
                                                         const int32_t* __restrict__ imap, int cap_d) {
@@ -647,9 +782,13 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     F* X = region + reg - c * ldc;           // c x c, kept to the end
     // ---- assemble B (column-major, ld M) in global memory; it stays for the projection
     double* __restrict__ B = T.B;
-    for (int64_t e = tid; e < (int64_t)M * c; e += NTC) B[e] = 0.0;
-    __syncthreads();
     double amax = 0.0;
+    if (T.npieces < 0)                       // B already in place (sketched block)
+        for (int64_t e = tid; e < (int64_t)M * c; e += NTC) amax = fmax(amax, fabs(B[e]));
+    else {
+        for (int64_t e = tid; e < (int64_t)M * c; e += NTC) B[e] = 0.0;
+        __syncthreads();
+    }
     for (int q = 0; q < T.npieces; ++q) {
         const DPiece pc = pieces[T.piece0 + q];
         const int nr = pc.blk.nr, nc = pc.blk.nc;
@@ -672,6 +811,16 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     for (int t = 0; t < SEGC; ++t) amax = fmax(amax, s_amax[t]);
     const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
     const double inv_scale = ldexp(1.0, -bexp), scale = ldexp(1.0, bexp);
+    if constexpr (GRAM) {
+        // ---- 1'-2'. R1 and its column order from the FP64 Gram matrix: G =
+        // (B / 2^e)^T (B / 2^e), then Cholesky with diagonal pivoting, P^T G P =
+        // R1^T R1: in exact arithmetic the R and the column order of the pivoted
+        // QR of steps 1-2 (the largest remaining diagonal is the largest
+        // remaining column norm).  It stops once the largest remaining diagonal
+        // is below c u trace(G) (rows below are zero), so singular values under
+        // about sqrt(c u) sigma_0 are not resolved.
+        gram_chol_r1<F, NTC>(B, M, c, inv_scale, reinterpret_cast<double*>(region), X, ldc, s_perm);
+    } else {
     // ---- 1. QR of B through LDS chunks: [R (c rows); next rows of B]
     {
         F* A = region;
@@ -707,6 +856,7 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     }
     // ---- 2. R0 P = Q1 R1
     qr64<F, NTC>(X, c, c, ldc, true, s_perm, hv0, htau, P, NV);
+    }
     // ---- 3. R1^T = Q2 R2 (A2 after W in the region); L = R2^T into X
     F* W = region;
     F* A2 = region + c * ldc;
@@ -837,7 +987,16 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     double smax = 0.0;
     for (int k = 0; k < c; ++k) smax = fmax(smax, s_sv[k]);
     int r = 0;
-    if (T.tau) {
+    if (T.nb2) {
+        // sketched block of a randomized compression: the fewest directions whose
+        // discarded part (tail of this block plus the energy of B outside the
+        // sketch) has Frobenius norm <= eps sigma_0; c + 1 when none qualifies
+        __syncthreads();                          // the sorted values above are written
+        double cap2 = 0.0;
+        for (int k = 0; k < c; ++k) cap2 += T.tails[1 + k] * T.tails[1 + k];
+        const double unc = T.rand_full ? 0.0 : fmax(0.0, *T.nb2 - cap2);
+        r = rand_rank(T.tails + 1, c, unc, T.eps);
+    } else if (T.tau) {
         __syncthreads();                          // the sorted values above are written
         r = frob_rank(T.tails + 1, c, 0.0, *T.tau);
     } else if (smax > 0.0)
@@ -845,12 +1004,275 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
     for (int e = tid; e < c * c; e += NTC) {
         const int a = e % c, k = e / c;
         const int pos = desc_pos(s_sv, c, k);
-        if (pos < r) T.V[s_perm[a] + (size_t)pos * c] = (double)W[a + k * ldc];
+        if (pos < r) T.V[s_perm[a] + (size_t)pos * c] = (double)W[a + k * ldc];   // (r = c + 1: all)
     }
     if (tid == 0) {
         T.tails[0] = smax;
         T.tails[c + 1] = (double)sweeps_run;     // Jacobi sweeps (work accounting)
         *T.rank_out = r;
+    }
+}
+
+// ---- randomized compression (stacked blocks of at most 64 columns) ------------
+// Adaptive randomized range finder on the nonzero part of the stacked block B
+// (M x c): rows and columns that are zero (structural padding of the stacked
+// pieces) take no part in the draw.
+//   k_rand_sketch: (first pass) assemble B as the SVD kernels do, ||B||_F^2 and
+//     the number c_nz of nonzero columns; the sketch width is
+//     l = min(requested, c_nz) (written into the sketch task).  Y = B^T Omega
+//     (c x l): Omega(a', t) = -1 when the top bit of SplitMix64 of the counter
+//     (key << 34) + (a' << 6) + t is set, a' the position of row a among the
+//     nonzero rows of B (SplitMix64: Steele, Lea and Flood, 2014); Householder
+//     QR of Y, the explicit Q (c x l, kept in hv); C = B Q (M x l) into Bw.
+//   k_compress_svd64<double> on the sketch tasks (C in place, npieces < 0,
+//     with the rank rule of the sketch, rand_rank);
+//   k_rand_finish: accept when the rank is below l or the sketch spans all c_nz
+//     columns, then V = Q V_C (c x r), tails and rank; else flag the task (the
+//     host doubles the requested width and runs the three launches again).
+// bf16: the sketch product takes B rounded to BF16 (the signs are exact in
+// BF16) with FP32 accumulation; C and everything after stay FP64.
+constexpr int NTR = 1024;
+constexpr int SEGR = NTR / WAVE;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float bf16_round(float f) {   // to nearest, ties to even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return f;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// LDS of k_rand_sketch, in doubles: Y and Q (c x l, ld <= 65), P (SEGR x WAVE),
+// NV (SEGR), hv0 and htau (WAVE each), then NTR sign masks and NTR row ids.
+constexpr size_t kRandLds = (size_t)(2 * (WAVE + 1) * WAVE + SEGR * WAVE + SEGR + 2 * WAVE) * sizeof(double) +
+                            (size_t)NTR * (sizeof(uint64_t) + sizeof(int32_t));
+
+__global__ __launch_bounds__(NTR) void k_rand_sketch(const DCompress* __restrict__ tasks,
+                                                     const DRand* __restrict__ rt,
+                                                     DCompress* __restrict__ ctasks,
+                                                     const DPiece* __restrict__ pieces,
+                                                     const int32_t* __restrict__ imap, int first, int bf16) {
+    const DCompress T = tasks[blockIdx.x];
+    const DRand R = rt[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    if (!R.active || M <= 0 || c <= 0 || c > WAVE) return;
+    extern __shared__ double sm[];
+    const int ldy = c | 1;
+    double* Y = sm;                          // c x l
+    double* Qs = Y + (WAVE + 1) * WAVE;      // c x l
+    double* P = Qs + (WAVE + 1) * WAVE;      // SEGR x WAVE
+    double* NV = P + SEGR * WAVE;            // SEGR
+    double* hv0 = NV + SEGR;                 // WAVE
+    double* htau = hv0 + WAVE;               // WAVE
+    uint64_t* masks = reinterpret_cast<uint64_t*>(htau + WAVE);   // NTR
+    int32_t* rowid = reinterpret_cast<int32_t*>(masks + NTR);     // NTR
+    __shared__ double s_red[SEGR];
+    __shared__ int s_cnt[SEGR];
+    double* __restrict__ B = T.B;
+    if (first) {
+        for (int64_t e = tid; e < (int64_t)M * c; e += NTR) B[e] = 0.0;
+        __syncthreads();
+        double f = 0.0;
+        for (int q = 0; q < T.npieces; ++q) {
+            const DPiece pc = pieces[T.piece0 + q];
+            const int nr = pc.blk.nr, nc = pc.blk.nc;
+            for (int e = tid; e < nr * nc; e += NTR) {
+                const int a = e % nr, b = e / nr;
+                const double v = pc.blk.p[e];
+                f += v * v;
+                if (!pc.trans) B[(pc.row0 + a) + (int64_t)imap_at(imap, pc.map, b) * M] = v;
+                else           B[(pc.row0 + b) + (int64_t)imap_at(imap, pc.map, a) * M] = v;
+            }
+        }
+        f = wave_sum(f);
+        if (lane == 0) s_red[w] = f;
+        __syncthreads();                     // B assembled, partial sums written
+        int nzc = 0;                         // nonzero columns, a wave per column
+        for (int k = w; k < c; k += SEGR) {
+            bool nz = false;
+            for (int a = lane; a < M; a += WAVE) nz |= B[a + (int64_t)k * M] != 0.0;
+            nzc += __ballot(nz) != 0ull ? 1 : 0;
+        }
+        if (lane == 0) s_cnt[w] = nzc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            int n = 0;
+            for (int q = 0; q < SEGR; ++q) { t += s_red[q]; n += s_cnt[q]; }
+            T.hv[(size_t)c * c] = t;         // ||B||_F^2
+            T.hv[(size_t)c * c + 1] = (double)n;
+        }
+        __syncthreads();
+    }
+    const int cnz = (int)T.hv[(size_t)c * c + 1];
+    const int l = min(R.l, cnz);
+    if (tid == 0) {
+        ctasks[blockIdx.x].c = l;
+        ctasks[blockIdx.x].rand_full = l == cnz ? 1 : 0;
+    }
+    if (l <= 0) return;                      // B = 0: the sketch task has no columns
+    for (int e = tid; e < ldy * l; e += NTR) Y[e] = 0.0;
+    // ---- Y = B^T Omega over chunks of NTR rows
+    int base = 0;                            // nonzero rows before the chunk
+    for (int a0 = 0; a0 < M; a0 += NTR) {
+        const int na = min(NTR, M - a0);
+        bool nz = false;
+        if (tid < na)
+            for (int k = 0; k < c; ++k) nz |= B[(a0 + tid) + (int64_t)k * M] != 0.0;
+        const uint64_t bm = __ballot(nz);
+        if (lane == 0) s_cnt[w] = __popcll(bm);
+        __syncthreads();
+        int pre = base, tot = 0;
+        for (int q = 0; q < SEGR; ++q) {
+            const int t = s_cnt[q];
+            pre += q < w ? t : 0;
+            tot += t;
+        }
+        rowid[tid] = pre + __popcll(bm & ((1ull << lane) - 1ull));
+        base += tot;
+        __syncthreads();
+        for (int a = w; a < na; a += SEGR) {
+            const uint64_t cnt = ((uint64_t)R.key << 34) + ((uint64_t)rowid[a] << 6) + (uint64_t)lane;
+            const bool neg = lane < l && (splitmix64(cnt) >> 63) != 0;
+            const uint64_t m = __ballot(neg);
+            if (lane == 0) masks[a] = m;
+        }
+        __syncthreads();
+        for (int k = w; k < c; k += SEGR) {
+            if (lane < l) {
+                const double* bc = B + (int64_t)k * M + a0;
+                if (bf16) {
+                    float acc = 0.f;
+                    for (int a = 0; a < na; ++a) {
+                        const float b = bf16_round((float)bc[a]);
+                        acc += ((masks[a] >> lane) & 1ull) ? -b : b;
+                    }
+                    Y[k + lane * ldy] += (double)acc;
+                } else {
+                    double acc = 0.0;
+                    for (int a = 0; a < na; ++a) {
+                        const double b = bc[a];
+                        acc += ((masks[a] >> lane) & 1ull) ? -b : b;
+                    }
+                    Y[k + lane * ldy] += acc;
+                }
+            }
+        }
+        __syncthreads();                     // s_cnt, rowid and masks are reused
+    }
+    // ---- Householder QR of Y (c x l), then Q = H_0 ... H_{l-1} I[:, :l]
+    qr64<double, NTR>(Y, c, l, ldy, false, nullptr, hv0, htau, P, NV);
+    for (int e = tid; e < c * l; e += NTR) {
+        const int i = e % c, t = e / c;
+        Qs[i + t * ldy] = (i == t) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    {
+        const int k = lane, sg = w;
+        for (int j = l - 1; j >= 0; --j) {
+            const double tau = htau[j];
+            if (tau == 0.0) continue;                    // uniform: H_j = I
+            const int i0 = j + 1 + ((sg - (j + 1)) % SEGR + SEGR) % SEGR;
+            const double v0 = hv0[j];
+            double p1 = 0.0;
+            const double qjk = k < l ? Qs[j + k * ldy] : 0.0;
+            if (k < l)
+                for (int i = i0; i < c; i += SEGR) p1 += Y[i + j * ldy] * Qs[i + k * ldy];
+            P[sg * WAVE + k] = p1;
+            __syncthreads();
+            if (k < l) {
+                double wv = v0 * qjk;
+                for (int t = 0; t < SEGR; ++t) wv += P[t * WAVE + k];
+                wv *= tau;
+                if (sg == 0) Qs[j + k * ldy] = qjk - wv * v0;
+                for (int i = i0; i < c; i += SEGR) Qs[i + k * ldy] -= wv * Y[i + j * ldy];
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < c * l; e += NTR) {
+        const int i = e % c, t = e / c;
+        T.hv[i + (size_t)t * c] = Qs[i + t * ldy];
+    }
+    // ---- C = B Q (M x l) into Bw
+    for (int64_t e = tid; e < (int64_t)M * l; e += NTR) {
+        const int a = (int)(e % M), t = (int)(e / M);
+        double acc = 0.0;
+        for (int k = 0; k < c; ++k) acc += B[a + (int64_t)k * M] * Qs[k + t * ldy];
+        T.Bw[e] = acc;
+    }
+}
+
+// flags[i]: bit 0 = the sketch was too narrow (rank not below l, l < c_nz); bits
+// 1..7 the Jacobi sweeps of the sketched block's SVD; bits 8.. the width l.
+__global__ __launch_bounds__(256) void k_rand_finish(const DCompress* __restrict__ tasks,
+                                                     const DRand* __restrict__ rt,
+                                                     const DCompress* __restrict__ ctasks,
+                                                     int32_t* __restrict__ flags) {
+    const DCompress T = tasks[blockIdx.x];
+    const DRand R = rt[blockIdx.x];
+    const int tid = threadIdx.x;
+    if (!R.active || T.M <= 0 || T.c <= 0 || T.c > WAVE) {
+        if (tid == 0) flags[blockIdx.x] = 0;
+        return;
+    }
+    const DCompress C = ctasks[blockIdx.x];
+    const int l = C.c, c = T.c;
+    const int rc = l > 0 ? *C.rank_out : 0;
+    const int sweeps = l > 0 ? (int)C.tails[l + 1] : 0;
+    const bool accept = C.rand_full || rc < l;
+    if (!accept) {
+        if (tid == 0) flags[blockIdx.x] = 1 | (sweeps << 1) | (l << 8);
+        return;
+    }
+    const int r = min(rc, l);
+    for (int e = tid; e < c * r; e += 256) {
+        const int a = e % c, p = e / c;
+        double acc = 0.0;
+        for (int t = 0; t < l; ++t) acc += T.hv[a + (size_t)t * c] * C.V[t + (size_t)p * l];
+        T.V[a + (size_t)p * c] = acc;
+    }
+    for (int k = tid; k < c; k += 256) T.tails[1 + k] = k < l ? C.tails[1 + k] : 0.0;
+    if (tid == 0) {
+        T.tails[0] = l > 0 ? C.tails[0] : 0.0;
+        T.tails[c + 1] = (double)sweeps;
+        *T.rank_out = r;
+        flags[blockIdx.x] = (sweeps << 1) | (l << 8);
+    }
+}
+
+// Sign of the auxiliary variables: every column of V (c x r, r = *rank_out)
+// gets its entry of largest magnitude positive (lowest row on exact ties).  The
+// factorization does not depend on these signs; a randomized sketch of a later
+// stacked block, whose rows include these variables, does.  One wavefront per task.
+__global__ __launch_bounds__(WAVE) void k_v_sign(const DCompress* __restrict__ tasks) {
+    const DCompress T = tasks[blockIdx.x];
+    const int lane = threadIdx.x;
+    if (T.M <= 0 || T.c <= 0) return;
+    const int c = T.c, r = min(*T.rank_out, c);
+    for (int p = 0; p < r; ++p) {
+        double* col = T.V + (size_t)p * c;
+        double bv = -1.0;
+        int bi = c;
+        for (int a = lane; a < c; a += WAVE) {
+            const double v = fabs(col[a]);
+            if (v > bv) { bv = v; bi = a; }             // rows ascending: first of equals kept
+        }
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (bi >= c) continue;
+        const bool neg = col[bi] < 0.0;
+        if (neg)
+            for (int a = lane; a < c; a += WAVE) col[a] = -col[a];
     }
 }
 
@@ -2611,14 +3033,18 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
 }
 
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, int max_M, bool fp32, int nt, hipStream_t st) {
+                               int max_c, int max_M, bool fp32, int nt, hipStream_t st, bool gram) {
     if (n == 0) return hipSuccess;
     if (max_c <= 64) {
         static std::atomic<bool> attr64{false};
         if (!attr64) {
-            const void* fs[6] = {(const void*)k_compress_svd64<double, 256>, (const void*)k_compress_svd64<double, 512>,
-                                 (const void*)k_compress_svd64<double, 1024>, (const void*)k_compress_svd64<float, 256>,
-                                 (const void*)k_compress_svd64<float, 512>, (const void*)k_compress_svd64<float, 1024>};
+            const void* fs[12] = {
+                (const void*)k_compress_svd64<double, 256, false>, (const void*)k_compress_svd64<double, 512, false>,
+                (const void*)k_compress_svd64<double, 1024, false>, (const void*)k_compress_svd64<float, 256, false>,
+                (const void*)k_compress_svd64<float, 512, false>, (const void*)k_compress_svd64<float, 1024, false>,
+                (const void*)k_compress_svd64<double, 256, true>, (const void*)k_compress_svd64<double, 512, true>,
+                (const void*)k_compress_svd64<double, 1024, true>, (const void*)k_compress_svd64<float, 256, true>,
+                (const void*)k_compress_svd64<float, 512, true>, (const void*)k_compress_svd64<float, 1024, true>};
             for (const void* f : fs) {
                 hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
                 if (e != hipSuccess) return e;
@@ -2627,15 +3053,27 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
         }
         const int cap = (kLdsBudget - 4096) / (int)sizeof(double);   // static LDS of the kernel aside
         const size_t lds = (size_t)cap * sizeof(double);
-        if (fp32) {
-            if (nt == 256) hipLaunchKernelGGL((k_compress_svd64<float, 256>), dim3(n), dim3(256), lds, st, t, pieces, imap, cap);
-            else if (nt == 512) hipLaunchKernelGGL((k_compress_svd64<float, 512>), dim3(n), dim3(512), lds, st, t, pieces, imap, cap);
-            else hipLaunchKernelGGL((k_compress_svd64<float, 1024>), dim3(n), dim3(1024), lds, st, t, pieces, imap, cap);
+#define LRX_SVD64(FT, NTV, GR) hipLaunchKernelGGL((k_compress_svd64<FT, NTV, GR>), dim3(n), dim3(NTV), lds, st, t, pieces, imap, cap)
+        if (gram) {
+            if (fp32) {
+                if (nt == 256) LRX_SVD64(float, 256, true);
+                else if (nt == 512) LRX_SVD64(float, 512, true);
+                else LRX_SVD64(float, 1024, true);
+            } else {
+                if (nt == 256) LRX_SVD64(double, 256, true);
+                else if (nt == 512) LRX_SVD64(double, 512, true);
+                else LRX_SVD64(double, 1024, true);
+            }
+        } else if (fp32) {
+            if (nt == 256) LRX_SVD64(float, 256, false);
+            else if (nt == 512) LRX_SVD64(float, 512, false);
+            else LRX_SVD64(float, 1024, false);
         } else {
-            if (nt == 256) hipLaunchKernelGGL((k_compress_svd64<double, 256>), dim3(n), dim3(256), lds, st, t, pieces, imap, cap);
-            else if (nt == 512) hipLaunchKernelGGL((k_compress_svd64<double, 512>), dim3(n), dim3(512), lds, st, t, pieces, imap, cap);
-            else hipLaunchKernelGGL((k_compress_svd64<double, 1024>), dim3(n), dim3(1024), lds, st, t, pieces, imap, cap);
+            if (nt == 256) LRX_SVD64(double, 256, false);
+            else if (nt == 512) LRX_SVD64(double, 512, false);
+            else LRX_SVD64(double, 1024, false);
         }
+#undef LRX_SVD64
         return hipGetLastError();
     }
     // LDS plan: R and V (2 c^2) plus a chunk of ch rows of B (ch c), within the
@@ -2652,6 +3090,33 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
         hipLaunchKernelGGL(k_compress_svd<8>, dim3(n), dim3(NT), lds, st, t, pieces, imap, cap);
     else
         hipLaunchKernelGGL(k_compress_svd<16>, dim3(n), dim3(NT), lds, st, t, pieces, imap, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_rand_sketch(const DCompress* t, const DRand* rt, DCompress* ctasks, int n, const DPiece* pieces,
+                              const int32_t* imap, int first, int bf16, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    static std::atomic<bool> attr{false};
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_rand_sketch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kRandLds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_rand_sketch, dim3(n), dim3(NTR), kRandLds, st, t, rt, ctasks, pieces, imap, first, bf16);
+    return hipGetLastError();
+}
+
+hipError_t launch_v_sign(const DCompress* t, int n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_v_sign, dim3(n), dim3(WAVE), 0, st, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_rand_finish(const DCompress* t, const DRand* rt, const DCompress* ctasks, int n, int32_t* flags,
+                              hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rand_finish, dim3(n), dim3(256), 0, st, t, rt, ctasks, flags);
     return hipGetLastError();
 }
 

@@ -34,8 +34,10 @@ hipError_t launch_compress(const DCompress* t, int n, const DPiece* pieces, cons
                            int max_c, hipStream_t st);
 // fp32: reduced QRs and Jacobi in FP32 when every task has c <= 64 (mixed
 // precision); nt: threads per task (256, 512 or 1024) when every task has c <= 64
+// gram (max_c <= 64): R1 and the column order from the FP64 Gram matrix and a
+// pivoted Cholesky instead of the QR and QRCP of B.
 hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                               int max_c, int max_M, bool fp32, int nt, hipStream_t st);
+                               int max_c, int max_M, bool fp32, int nt, hipStream_t st, bool gram = false);
 // Truncated SVD of stacked blocks with c > 64 columns (FP64, matrices in the
 // workspace: hv needs 4 c^2 + c + 8 doubles, Bw M c).  Trailing QRCP rows below
 // trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
@@ -48,6 +50,18 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
                                  int max_M, double trunc_rel, int mode, hipStream_t st);
 hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st);
+// Randomized compression of stacked blocks with at most 64 columns (see
+// k_rand_sketch): the sketch launch (first = 1 also assembles B, ||B||_F^2 and
+// the nonzero column count; it writes the width l and the full-sketch flag
+// into ctasks), then launch_compress_svd(fp32 = false) on ctasks, then the
+// finish launch (flags[i]: bit 0 = task i needs a wider sketch, bits 1..7 the
+// Jacobi sweeps, bits 8.. the width).
+hipError_t launch_rand_sketch(const DCompress* t, const DRand* rt, DCompress* ctasks, int n, const DPiece* pieces,
+                              const int32_t* imap, int first, int bf16, hipStream_t st);
+// Each column of V of every task gets its entry of largest magnitude positive.
+hipError_t launch_v_sign(const DCompress* t, int n, hipStream_t st);
+hipError_t launch_rand_finish(const DCompress* t, const DRand* rt, const DCompress* ctasks, int n, int32_t* flags,
+                              hipStream_t st);
 // Blocked Householder QR in panels of 16 columns over many work-groups:
 // which 0: tall QR of every task's Bw (between launch_compress_large modes 4
 // and 5); which 1: QR of A2 (the LQ step) and which 2: W = Q2 E (between modes 5

@@ -404,6 +404,7 @@ struct Tune {
     int32_t compress_nt_mid = 1024;     // threads per stacked block of 33..64 columns
     int32_t gemm_grid = 0;          // persistent grid of the MFMA products (0: a work-group per tile)
     int32_t solve_graph = 1;        // 1: GMRES replays its preconditioner as a captured HIP graph
+    int32_t compress_gram = 1;      // 1: mixed-precision small blocks through the FP64 Gram matrix
 };
 Tune g_tune;
 }  // namespace
@@ -534,6 +535,7 @@ struct FactorRun {
     double fl_compress = 0, fl_pivot = 0, fl_schur = 0, fl_project = 0;   // by operation class
     double jac_flops = 0.0, jac_sweeps = 0.0;   // Jacobi work of the current step (timing)
     double v_bytes = 0.0;                       // bytes of V written in the current step (timing)
+    double jac_flops_g = 0.0, v_bytes_g = 0.0;  // the same for the Gram-path tasks (their own class)
     DevBuf d_idx, d_val;                   // temporaries of the initial scatter
     // current colour step
     int32_t si = -1;
@@ -541,10 +543,23 @@ struct FactorRun {
     std::vector<DPiece> pieces;
     std::vector<std::vector<int32_t>> a_row0, b_row0;
     std::vector<size_t> wsB, wsV, wsH, tail_at;
+    std::vector<size_t> wsR;               // randomized compression: sketch task workspace (0: none)
+    std::vector<double*> rand_ws;
+    std::vector<double> rand_fl;           // flops of the randomized compressions of the step
+    std::vector<int> rand_l;               // their accepted sketch widths
+    std::vector<char> gram_task;           // R1 from the Gram matrix (k_compress_svd64 GRAM variant)
     size_t ws_need = 0, tails_total = 0;
     int64_t task0 = 0, tails0 = 0;         // first task / tail value in the batch arrays
 
     explicit FactorRun(lrx_handle h_) : h(h_), P(h_->plan) {}
+
+    // the SVD-shaped descriptor (B column-major and kept, V from an SVD):
+    // the SVD and the randomized range finder
+    bool svd_like() const { return h->compress != LRX_RRQR; }
+    // stacked blocks that take the randomized path (at most 64 columns)
+    bool rand_task(const DCompress& T) const {
+        return h->compress == LRX_RAND && T.M > 0 && T.c > 0 && T.c <= 64;
+    }
 
     int32_t mo(int32_t m) const { return m >= 0 ? m + imap_base : m; }
     int32_t nr_of(int32_t e) const { const PEdge& E = P.edges[e]; return dim_of(E.rows, h->size[E.dst]); }
@@ -744,12 +759,14 @@ bool same_support(const Support& a, const Support& b) {
 size_t FactorRun::compress_tasks() {
     const ColourStep& cs = P.steps[si];
     const int nn = (int)cs.nodes.size();
-    const bool svd = h->compress == LRX_SVD;
+    const bool svd = svd_like();
     ct.assign(nn, DCompress{});
     pieces.clear();
     a_row0.assign(nn, {});
     b_row0.assign(nn, {});
     wsB.assign(nn, 0); wsV.assign(nn, 0); wsH.assign(nn, 0); tail_at.assign(nn, 0);
+    wsR.assign(nn, 0); rand_ws.assign(nn, nullptr); rand_fl.assign(nn, 0.0); rand_l.assign(nn, 0);
+    gram_task.assign(nn, 0);
     ws_need = 0;
     tails_total = 0;
     for (int ni = 0; ni < nn; ++ni) {
@@ -799,6 +816,11 @@ size_t FactorRun::compress_tasks() {
         // hv: c^2 + c, or 4 c^2 + c + 8 for the large-block SVD (c > 64)
         wsH[ni] = ws_need;
         ws_need += ((size_t)T.c * T.c * (svd && T.c > 64 ? 4 : 1) + T.c + 8 + 31) & ~(size_t)31;
+        // randomized: V_C (l x l), tails and rank of the sketched block
+        if (rand_task(T)) {
+            wsR[ni] = ws_need;
+            ws_need += (((size_t)T.c * T.c + 31) & ~(size_t)31) + (((size_t)T.c + 2 + 31) & ~(size_t)31) + 32;
+        }
         tail_at[ni] = tails_total;
         tails_total += (size_t)T.c + 2;
     }
@@ -806,7 +828,7 @@ size_t FactorRun::compress_tasks() {
 }
 
 void FactorRun::bind_compress(double* wsp, int32_t* ranks_dev, double* tails_dev, int32_t piece_base) {
-    const bool svd = h->compress == LRX_SVD;
+    const bool svd = svd_like();
     for (size_t ni = 0; ni < ct.size(); ++ni) {
         DCompress& T = ct[ni];
         T.piece0 += piece_base;
@@ -816,12 +838,13 @@ void FactorRun::bind_compress(double* wsp, int32_t* ranks_dev, double* tails_dev
         T.hv = wsp + wsH[ni];
         T.tails = tails_dev + tail_at[ni];
         T.rank_out = ranks_dev + ni;
+        rand_ws[ni] = wsR[ni] ? wsp + wsR[ni] : nullptr;
     }
 }
 
 void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t st) {
     const ColourStep& cs = P.steps[si];
-    const bool svd = h->compress == LRX_SVD;
+    const bool svd = svd_like();
     for (size_t ni = 0; ni < cs.nodes.size(); ++ni) {
         const NodeStep& ns = cs.nodes[ni];
         const DCompress& T = ct[ni];
@@ -844,7 +867,26 @@ void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t
         // flops of the stacked QR and the Jacobi SVD (sweeps reported by the
         // kernel after the c + 1 singular-value slots), or of the pivoted QR
         if (!emptyB) {
-            if (svd) {
+            if (rand_ws[ni]) {
+                // every sketch width tried (counted by the launches), then V = Q V_C
+                const double fl = rand_fl[ni] + 2.0 * T.c * rand_l[ni] * rk[ni];
+                flops += (int64_t)fl;
+                fl_compress += fl;
+                jac_flops += fl;
+                v_bytes += 8.0 * T.c * rk[ni];
+            } else if (gram_task[ni]) {
+                // the Gram matrix (upper half, M c (c + 1) flops), its pivoted
+                // Cholesky (c^3 / 3), the LQ and Q2 (8/3 c^3), then the Jacobi sweeps
+                const double sw = tl[T.c + 1];
+                const double jf = jacobi_flops(T.c, sw);
+                const double cc = T.c;
+                const double fg = (double)T.M * cc * (cc + 1.0) + cc * cc * cc / 3.0 + svd_pre_flops(cc) * 2.0 / 3.0;
+                flops += (int64_t)(fg + jf);
+                fl_compress += fg + jf;
+                jac_flops_g += jf;
+                jac_sweeps += sw;
+                v_bytes_g += 8.0 * T.c * rk[ni];
+            } else if (svd) {
                 const double sw = tl[T.c + 1];
                 const double jf = jacobi_flops(T.c, sw);
                 flops += (int64_t)(qr_flops(T.M, T.c) + svd_pre_flops(T.c) + jf);
@@ -927,12 +969,12 @@ void FactorRun::node_tasks(const int32_t* rk, NodeBatch& nb) {
         T.r = r;
         T.c = ct[ni].c;
         T.M = ct[ni].M;
-        T.svd = h->compress == LRX_SVD ? 1 : 0;
+        T.svd = svd_like() ? 1 : 0;
         T.B = ct[ni].B;
         T.V = ct[ni].V;
         T.do_proj = 1;
         T.proj0 = (int32_t)nb.projs.size();
-        const bool svd = h->compress == LRX_SVD;
+        const bool svd = svd_like();
         // SVD: piece k of B V = B[rows of k, :] V (nrows x r) into R_k (trans 0) or,
         // transposed, into Q_k^T (trans 1), as tiled products; RRQR: row copies
         auto piece = [&](const DProj& pj) {
@@ -1043,6 +1085,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
 
     PinBuf stage_m, stage_c, stage_n, pin_rt, pin_flags;   // descriptor staging, rank read-back
     DevBuf d_desc_m, d_desc_c, d_desc_n, d_rt, d_flags;
+    PinBuf pin_rand, pin_rflags;               // randomized compression: attempt descriptors, flags
+    DevBuf d_rand, d_rflags;
     int64_t m_epoch = -1;                       // epoch of the last merge upload
     for (size_t hgt = 0; hgt < max_h; ++hgt) {
         std::vector<FactorRun*> lv;
@@ -1114,29 +1158,49 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             std::vector<DCompress> all;
             std::vector<DPiece> allp;
             std::vector<int32_t> fp32_of;
+            std::vector<std::pair<FactorRun*, int>> owner;   // run and node of every task
             all.reserve(ntask);
             for (FactorRun* r : part) {
                 r->bind_compress(r->h->ws_b.as<double>(), d_rt.as<int32_t>() + r->task0,
                                  (double*)(d_rt.as<char>() + tails_off) + r->tails0, (int32_t)allp.size());
                 all.insert(all.end(), r->ct.begin(), r->ct.end());
                 allp.insert(allp.end(), r->pieces.begin(), r->pieces.end());
-                for (size_t q = 0; q < r->ct.size(); ++q)
-                    fp32_of.push_back((r->h->compress == LRX_SVD ? 0 : 4) | (r->fp32_compress ? 1 : 0));
+                for (size_t q = 0; q < r->ct.size(); ++q) {
+                    // bit 2: pivoted QR; bit 3: randomized, bit 1 with it: BF16 sketch
+                    // bit 4: the Gram path may take it (SVD, epsilon >= 1e-5, mixed
+                    // precision with compress_gram >= 1 or FP64 with compress_gram = 2)
+                    int f = r->h->compress == LRX_RRQR ? 4 : r->fp32_compress ? 1 : 0;
+                    const bool gram = r->h->compress == LRX_SVD && r->h->epsilon >= 1e-5 &&
+                                      g_tune.compress_gram >= (r->h->precision == LRX_FP64 ? 2 : 1);
+                    if (gram) f |= 16;
+                    if (r->rand_task(r->ct[q])) f = 8 | (r->h->precision == LRX_MIXED_BF16 ? 2 : 0);
+                    fp32_of.push_back(f);
+                    owner.emplace_back(r, (int)q);
+                }
             }
-            // variants: SVD with c <= 64 (FP64 / FP32 arithmetic: keys 0 / 1), SVD
+            // variants: SVD with c <= 64 (FP64 / FP32 arithmetic: keys 0 / 1; 16 / 17
+            // for 33..64 columns; 24: mixed precision through the FP64 Gram matrix), SVD
             // with c > 64 (even keys: FP64 rows kept, odd: rows below epsilon / 100
             // dropped in mixed precision; 8 / 9: one work-group per task; 12 / 13
             // for tall blocks, M c >= 3e5: the tall QR in multi-work-group panels,
             // the rest in one work-group; 10 / 11 for c > 192 or M c >= 1e6: QRs in
             // panels and the Jacobi in multi-work-group block rounds; key 2 when the
-            // LDS of the large kernel does not fit), pivoted QR (key 4); each task
-            // takes its own variant whatever the others are
-            struct Group { int key; std::vector<DCompress> t; int max_c = 1, max_M = 1; double fl = 0, by = 0; size_t off = 0; };
+            // LDS of the large kernel does not fit), pivoted QR (key 4), randomized
+            // range finder with c <= 64 (20: FP64 sketch, 21: BF16 sketch); each
+            // task takes its own variant whatever the others are
+            struct Group {
+                int key; std::vector<DCompress> t; std::vector<int> q;
+                int max_c = 1, max_M = 1; double fl = 0, by = 0; size_t off = 0;
+            };
             std::vector<Group> groups;
             for (size_t q = 0; q < all.size(); ++q) {
                 int key;
-                if (fp32_of[q] >= 4) key = 4;
-                else if (all[q].c <= 64) key = fp32_of[q] | (all[q].c > 32 ? 16 : 0);
+                if (fp32_of[q] & 8) key = 20 | ((fp32_of[q] & 2) ? 1 : 0);
+                else if (fp32_of[q] & 4) key = 4;
+                else if (all[q].c <= 64 && (fp32_of[q] & 16)) {
+                    key = 24 | (fp32_of[q] & 1);         // FP64 Gram matrix and pivoted Cholesky
+                    owner[q].first->gram_task[owner[q].second] = 1;
+                } else if (all[q].c <= 64) key = (fp32_of[q] & 1) | (all[q].c > 32 ? 16 : 0);
                 else if (compress_large_fits(all[q].M, all[q].c)) {
                     const int64_t mc = (int64_t)all[q].M * all[q].c;
                     // (odd keys drop pivoted-QR rows below epsilon / 100 relative to
@@ -1149,18 +1213,25 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 if (g == groups.size()) { groups.push_back(Group{}); groups[g].key = key; }
                 Group& G = groups[g];
                 G.t.push_back(all[q]);
+                G.q.push_back((int)q);
                 G.max_c = std::max(G.max_c, (int)all[q].c);
                 G.max_M = std::max(G.max_M, (int)all[q].M);
                 // known before the launch: the QRs (RRQR: at full rank, an upper
                 // bound); the Jacobi sweeps are added after the read-back
                 const double M = all[q].M, cc = all[q].c;
-                if (M > 0 && cc > 0) G.fl += key == 4 ? 4.0 * M * cc * cc : qr_flops(M, cc) + svd_pre_flops(cc);
+                if (M > 0 && cc > 0 && key < 20)     // (randomized: counted per sketch width)
+                    G.fl += key == 4 ? 4.0 * M * cc * cc : qr_flops(M, cc) + svd_pre_flops(cc);
+                else if (M > 0 && cc > 0 && (key == 24 || key == 25))
+                    G.fl += M * cc * (cc + 1.0) + cc * cc * cc / 3.0 + svd_pre_flops(cc) * 2.0 / 3.0;
                 G.by += 8.0 * M * cc;        // the stacked pieces, read once (V is added after the read-back)
             }
             {
                 std::vector<char> buf;
                 for (Group& G : groups) G.off = append_bytes(buf, G.t);
                 const size_t op = append_bytes(buf, allp);
+                // randomized mode: every task's V gets a fixed sign per column
+                const bool canon = part[0]->h->compress == LRX_RAND;
+                const size_t oall = canon ? append_bytes(buf, all) : 0;
                 stage_c.ensure(buf.size());
                 std::memcpy(stage_c.p, buf.data(), buf.size());
                 d_desc_c.ensure(buf.size());
@@ -1169,9 +1240,91 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 // independent variants run side by side: the split variant (its
                 // sweeps are driven from the host) on the caller's stream, the
                 // others on library streams forked from it and joined back after
+                // randomized range finder: sketch widths min(16, c_nz), then doubled
+                // for the tasks whose rank was not below the width, until c_nz; each
+                // attempt is a sketch, the SVD of the sketched blocks and a finish
+                // launch, then a read-back of the flags (host-driven, on st)
+                auto run_rand = [&](const std::vector<DCompress>& tk, const std::vector<int>& qs, int bf16,
+                                    hipStream_t gs) {
+                    const int n = (int)tk.size();
+                    std::vector<int> act(n), lreq(n, 16);
+                    for (int i = 0; i < n; ++i) act[i] = i;
+                    bool first = true;
+                    while (!act.empty()) {
+                        const int na = (int)act.size();
+                        std::vector<DCompress> ta(na), ca(na);
+                        std::vector<DRand> ra(na);
+                        int max_l = 1, max_M = 1;
+                        for (int k = 0; k < na; ++k) {
+                            const int i = act[k];
+                            const DCompress& T = tk[i];
+                            FactorRun* r = owner[qs[i]].first;
+                            const int ni = owner[qs[i]].second;
+                            const size_t cc = (size_t)T.c;
+                            ta[k] = T;
+                            ra[k] = DRand{};
+                            ra[k].l = std::min(lreq[i], (int)T.c);
+                            ra[k].active = 1;
+                            ra[k].key = ((int64_t)r->P.steps[r->si].level << 24) | r->P.steps[r->si].nodes[ni].j;
+                            double* w = r->rand_ws[ni];
+                            DCompress C{};
+                            C.piece0 = 0; C.npieces = -1; C.M = T.M; C.c = ra[k].l;
+                            C.B = T.Bw; C.V = w;
+                            C.tails = w + ((cc * cc + 31) & ~(size_t)31);
+                            C.rank_out = (int32_t*)(C.tails + ((cc + 2 + 31) & ~(size_t)31));
+                            C.eps = T.eps; C.nb2 = T.hv + cc * cc;
+                            ca[k] = C;
+                            max_l = std::max(max_l, ra[k].l);
+                            max_M = std::max(max_M, (int)T.M);
+                        }
+                        std::vector<char> buf;
+                        const size_t ot = append_bytes(buf, ta), orr = append_bytes(buf, ra);
+                        const size_t oc = append_bytes(buf, ca);
+                        // the previous attempt's copies and kernels completed at its sync
+                        pin_rand.ensure(buf.size());
+                        std::memcpy(pin_rand.p, buf.data(), buf.size());
+                        d_rand.ensure(buf.size());
+                        d_rflags.ensure((size_t)na * sizeof(int32_t));
+                        pin_rflags.ensure((size_t)na * sizeof(int32_t));
+                        HIPCHK(hipMemcpyAsync(d_rand.p, pin_rand.p, buf.size(), hipMemcpyHostToDevice, gs));
+                        const DCompress* dta = (const DCompress*)(d_rand.as<char>() + ot);
+                        const DRand* dra = (const DRand*)(d_rand.as<char>() + orr);
+                        DCompress* dca = (DCompress*)(d_rand.as<char>() + oc);
+                        HIPCHK(launch_rand_sketch(dta, dra, dca, na, dp, dmap, first ? 1 : 0, bf16, gs));
+                        HIPCHK(launch_compress_svd(dca, na, dp, dmap, max_l, max_M, false,
+                                                   max_l > 32 ? g_tune.compress_nt_mid : g_tune.compress_nt_small,
+                                                   gs));
+                        HIPCHK(launch_rand_finish(dta, dra, dca, na, d_rflags.as<int32_t>(), gs));
+                        HIPCHK(hipMemcpyAsync(pin_rflags.p, d_rflags.p, (size_t)na * sizeof(int32_t),
+                                              hipMemcpyDeviceToHost, gs));
+                        sync();
+                        const int32_t* fl = (const int32_t*)pin_rflags.p;
+                        std::vector<int> next;
+                        for (int k = 0; k < na; ++k) {
+                            const int i = act[k];
+                            FactorRun* r = owner[qs[i]].first;
+                            const int ni = owner[qs[i]].second;
+                            const double M = tk[i].M, c = tk[i].c;
+                            const int l = fl[k] >> 8;
+                            const double sw = (fl[k] >> 1) & 127;
+                            // sketch (M c l additions), QR of Y and its explicit Q, C = B Q,
+                            // QR-preconditioned Jacobi SVD of C
+                            double f = M * c * l + 2.0 * qr_flops(c, l) + 2.0 * M * c * l;
+                            if (l > 0) f += qr_flops(M, l) + svd_pre_flops(l) + jacobi_flops(l, sw);
+                            r->rand_fl[ni] += f;
+                            r->rand_l[ni] = l;
+                            if (fl[k] & 1) {
+                                lreq[i] *= 2;
+                                next.push_back(i);
+                            }
+                        }
+                        act.swap(next);
+                        first = false;
+                    }
+                };
                 auto run_group = [&](Group& G, hipStream_t gs) {
                     const DCompress* dt = (const DCompress*)(d_desc_c.as<char>() + G.off);
-                    LaunchTimer tm(LRX_K_COMPRESS, gs, G.by, G.fl);
+                    LaunchTimer tm(G.key == 24 || G.key == 25 ? LRX_K_COMPRESS_GRAM : LRX_K_COMPRESS, gs, G.by, G.fl);
                     if (G.key == 4)
                         HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, gs));
                     else if (G.key == 8 || G.key == 9) {
@@ -1210,6 +1363,13 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                             if (!go) break;
                         }
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 2, gs));
+                    } else if (G.key == 20 || G.key == 21) {
+                        run_rand(G.t, G.q, G.key & 1, gs);
+                    } else if (G.key == 24 || G.key == 25) {
+                        // Gram path (25: FP32 LQ and Jacobi in mixed precision)
+                        HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M, G.key == 25,
+                                                   G.max_c > 32 ? g_tune.compress_nt_mid : g_tune.compress_nt_small,
+                                                   gs, true));
                     }
                     else
                         HIPCHK(launch_compress_svd(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
@@ -1217,16 +1377,17 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                                                    G.key >= 16 ? g_tune.compress_nt_mid : g_tune.compress_nt_small,
                                                    gs));
                 };
+                auto host_driven = [](int key) { return key == 10 || key == 11 || key == 20 || key == 21; };
                 std::vector<hipStream_t> gsv(groups.size(), st);
                 AuxStreams* ax = groups.size() > 1 ? aux_streams() : nullptr;
                 bool used[2] = {false, false};
                 if (ax) {
                     bool split = false;
-                    for (const Group& G : groups) split |= G.key == 10 || G.key == 11;
-                    bool keep = !split;                  // without a split variant one stays on st
+                    for (const Group& G : groups) split |= host_driven(G.key);
+                    bool keep = !split;                  // without a host-driven variant one stays on st
                     int j = 0;
                     for (size_t g = 0; g < groups.size(); ++g) {
-                        if (groups[g].key == 10 || groups[g].key == 11) continue;
+                        if (host_driven(groups[g].key)) continue;
                         if (keep) { keep = false; continue; }
                         gsv[g] = ax->s[j & 1];
                         used[j & 1] = true;
@@ -1247,6 +1408,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                         HIPCHK(hipEventRecord(ax->join[k], ax->s[k]));
                         HIPCHK(hipStreamWaitEvent(st, ax->join[k], 0));
                     }
+                if (canon)
+                    HIPCHK(launch_v_sign((const DCompress*)(d_desc_c.as<char>() + oall), (int)all.size(), st));
             }
             pin_rt.ensure(rt_bytes);
             if (rt_bytes) HIPCHK(hipMemcpyAsync(pin_rt.p, d_rt.p, rt_bytes, hipMemcpyDeviceToHost, st));
@@ -1256,8 +1419,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             for (FactorRun* r : part) {
                 r->jac_flops = 0.0;
                 r->v_bytes = 0.0;
+                r->jac_flops_g = 0.0;
+                r->v_bytes_g = 0.0;
                 r->take_ranks(rk + r->task0, tails_h + r->tails0, st);
                 timing_add(LRX_K_COMPRESS, r->v_bytes, r->jac_flops);
+                timing_add(LRX_K_COMPRESS_GRAM, r->v_bytes_g, r->jac_flops_g);
             }
             // ---- node tasks of every participating factorization
             NodeBatch nb;
@@ -1513,6 +1679,7 @@ void build_solve_program(lrx_handle h) {
     int64_t solve_bytes = 0;
     std::vector<int32_t> words;
     std::vector<SwNodeRel> both(2 * nn);
+    h->sw_stages = 0;
     for (size_t i = 0; i < nn; ++i) {
         NodeOut& o = outs[i];
         if (!o.err.empty()) fail(LRX_EDEVICE, o.err);
@@ -1547,6 +1714,8 @@ void build_solve_program(lrx_handle h) {
     h->sw_words = (int64_t)words.size();
     h->sw_nnode = (int32_t)nn;
     h->stats.solve_bytes = solve_bytes;
+    h->stats.sweep_stages = h->sw_stages;
+    h->stats.sweep_launches = 2 * (int64_t)h->plan.steps.size();
     if (h->solve_fp32) {               // the FP64 blocks are no longer read
         HIPCHK(hipStreamSynchronize(h->stream));
         IdleScope idle;
@@ -2070,8 +2239,11 @@ void check_factor_args(const lrx_csr* A, const double* val_dev, const lrx_tree* 
     if (!(o->epsilon >= 0.0 && o->epsilon < 1.0)) fail(LRX_EINVAL, "epsilon must be in [0, 1)");
     if (o->precision != LRX_FP64 && o->precision != LRX_MIXED && o->precision != LRX_MIXED_BF16)
         fail(LRX_EINVAL, "precision must be LRX_FP64, LRX_MIXED or LRX_MIXED_BF16");
-    if (o->compress != LRX_SVD && o->compress != LRX_RRQR) fail(LRX_EINVAL, "unknown compress method");
+    if (o->compress != LRX_SVD && o->compress != LRX_RRQR && o->compress != LRX_RAND)
+        fail(LRX_EINVAL, "unknown compress method");
     if (o->rule != LRX_RULE_CUTOFF1 && o->rule != LRX_RULE_FROB) fail(LRX_EINVAL, "unknown truncation rule");
+    if (o->rule == LRX_RULE_FROB && o->compress == LRX_RAND)
+        fail(LRX_EINVAL, "the randomized range finder takes the relative rule only");
     if (o->symmetric != 0 && o->symmetric != 1) fail(LRX_EINVAL, "symmetric must be 0 or 1");
     if (o->hbm_budget_bytes < 0) fail(LRX_EINVAL, "negative hbm budget");
 }
@@ -2403,6 +2575,7 @@ lrx_status lrx_tune_get(lrx_tune* t) {
         t->compress_nt_mid = g_tune.compress_nt_mid;
         t->gemm_grid = g_tune.gemm_grid;
         t->solve_graph = g_tune.solve_graph;
+        t->compress_gram = g_tune.compress_gram;
         return LRX_OK;
     });
 }
@@ -2418,7 +2591,9 @@ lrx_status lrx_tune_set(const lrx_tune* t) {
             if (v != 256 && v != 512 && v != 1024) fail(LRX_EINVAL, "compress_nt_* must be 256, 512 or 1024");
         if (t->gemm_grid < 0 || t->gemm_grid > 65536) fail(LRX_EINVAL, "gemm_grid must be 0..65536");
         if (t->solve_graph != 0 && t->solve_graph != 1) fail(LRX_EINVAL, "solve_graph must be 0 or 1");
+        if (t->compress_gram < 0 || t->compress_gram > 2) fail(LRX_EINVAL, "compress_gram must be 0, 1 or 2");
         g_tune.solve_graph = t->solve_graph;
+        g_tune.compress_gram = t->compress_gram;
         g_tune.gemm_kc = t->gemm_kc;
         g_tune.compress_nt_small = t->compress_nt_small;
         g_tune.compress_nt_mid = t->compress_nt_mid;

@@ -21,8 +21,8 @@ STATUS_NAMES = {0: "LRX_OK", 1: "LRX_EINVAL", 2: "LRX_ENOMEM", 3: "LRX_ESINGULAR
 LRX_FP64, LRX_MIXED, LRX_MIXED_BF16 = 0, 1, 2
 LRX_COLORED, LRX_NATURAL = 0, 1
 ORDERS = {"colored": LRX_COLORED, "natural": LRX_NATURAL}
-LRX_SVD, LRX_RRQR = 0, 1
-COMPRESS = {"svd": LRX_SVD, "rrqr": LRX_RRQR}
+LRX_SVD, LRX_RRQR, LRX_RAND = 0, 1, 2
+COMPRESS = {"svd": LRX_SVD, "rrqr": LRX_RRQR, "rand": LRX_RAND}
 PRECISION = {"fp64": LRX_FP64, "mixed": LRX_MIXED, "mixed_bf16": LRX_MIXED_BF16}
 RULES = {"cutoff1": 0, "frob": 1}
 
@@ -62,7 +62,8 @@ class Stats(C.Structure):
                 ("t_sync_ms", C.c_double), ("t_solve_prog_ms", C.c_double),
                 ("device_bytes", C.c_int64), ("flops_compress", C.c_double), ("flops_pivot", C.c_double),
                 ("flops_schur", C.c_double), ("flops_project", C.c_double),
-                ("level_norm_by_level", C.c_double * 32)]
+                ("level_norm_by_level", C.c_double * 32), ("sweep_stages", C.c_int64),
+                ("sweep_launches", C.c_int64)]
 
 
 class KernelTime(C.Structure):
@@ -75,7 +76,7 @@ class Timing(C.Structure):
 
 
 KERNEL_CLASSES = {0: "compress", 1: "factor_node", 2: "solve_fwd", 3: "solve_bwd", 4: "spmv",
-                  5: "schur", 6: "project"}
+                  5: "schur", 6: "project", 7: "compress_gram"}
 
 
 class PlanInfo(C.Structure):
@@ -88,11 +89,11 @@ class PlanInfo(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("gemm_kc", C.c_int32), ("gemm_f64_valu", C.c_int32), ("sweep_nk_max", C.c_int32),
                 ("compress_nt_small", C.c_int32), ("compress_nt_mid", C.c_int32), ("gemm_grid", C.c_int32),
-                ("solve_graph", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("solve_graph", C.c_int32), ("compress_gram", C.c_int32)]
 
 
 TUNE_FIELDS = ("gemm_kc", "gemm_f64_valu", "sweep_nk_max", "compress_nt_small", "compress_nt_mid", "gemm_grid",
-               "solve_graph")
+               "solve_graph", "compress_gram")
 
 
 # every symbol declared in include/lorax.h
@@ -363,7 +364,8 @@ class Factor:
                     device_bytes=int(s.device_bytes),
                     flops_by_op={"compress": float(s.flops_compress), "pivot": float(s.flops_pivot),
                                  "schur": float(s.flops_schur), "project": float(s.flops_project)},
-                    level_norm_by_level={i: float(s.level_norm_by_level[i]) for i in range(1, d + 1)})
+                    level_norm_by_level={i: float(s.level_norm_by_level[i]) for i in range(1, d + 1)},
+                    sweep_stages=int(s.sweep_stages), sweep_launches=int(s.sweep_launches))
 
     def ranks(self):
         n = self.stats()["n_compressions"]
