@@ -636,6 +636,25 @@ __device__ void qr64(T* A, int nr, int c, int ld, bool pivot, int* perm, T* hv0,
     }
 }
 
+// Rotation (cs, sn) that makes columns with squared norms al, be and product
+// ga orthogonal (one-sided Jacobi): zeta = (be - al) / (2 ga),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), cs = 1 / sqrt(1 + t^2),
+// sn = cs t.  FP64 uses correctly rounded division and square roots; FP32 the
+// hardware reciprocal, square root and reciprocal square root (about 1 ulp,
+// the size of the FP32 rounding of every other step of that path).
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double& cs, double& sn) {
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    cs = 1.0 / sqrt(1.0 + t * t);
+    sn = cs * t;
+}
+__device__ __forceinline__ void jacobi_rotation(float al, float be, float ga, float& cs, float& sn) {
+    const float zeta = (be - al) * __builtin_amdgcn_rcpf(2.0f * ga);
+    const float t = copysignf(1.0f, zeta) * __builtin_amdgcn_rcpf(fabsf(zeta) + __builtin_amdgcn_sqrtf(1.0f + zeta * zeta));
+    cs = __builtin_amdgcn_rsqf(1.0f + t * t);
+    sn = cs * t;
+}
+
 // R1 (c x c upper triangular, into X as F, ld ldx) and perm (the original column
 // at each position) of B (M x c, column-major in HBM, scaled by inv_scale):
 // FP64 Gram matrix from LDS chunks of 64 rows (2 x 2 register blocks, upper
@@ -696,60 +715,57 @@ __device__ void gram_chol_r1(const double* __restrict__ B, int M, int c, double 
             if (i1 < c && k1 < c) { G[i1 + k1 * ld] = acc[u][3]; G[k1 + i1 * ld] = acc[u][3]; }
         }
     }
-    for (int j = tid; j < c; j += NTC) perm[j] = j;
+    __shared__ int s_mark[WAVE];             // 1 once a column is pivoted
+    for (int j = tid; j < WAVE; j += NTC) s_mark[j] = 0;
     __syncthreads();
     double trace = 0.0;
     for (int k = 0; k < c; ++k) trace += G[k + k * ld];
     const double stop = 1.1102230246251565e-16 * (double)c * trace;
+    // G stays in the original order: step k pivots on the largest remaining
+    // diagonal p_k and updates the remaining rows and columns only, so row p_k
+    // keeps the values of step k (R1[k][l] = G[p_k][p_l] / sqrt(G[p_k][p_k]))
     int kk = c;
     for (int k = 0; k < c; ++k) {
-        // pivot: largest remaining diagonal (one wavefront; c <= 64)
         if (tid < WAVE) {
-            double v = lane >= k && lane < c ? G[lane + lane * ld] : -1.0;
+            double v = lane < c && !s_mark[lane] ? G[lane + lane * ld] : -1.0;
             int i = lane;
             for (int o = WAVE / 2; o > 0; o >>= 1) {
                 const double ov = __shfl_xor(v, o);
                 const int oi = __shfl_xor(i, o);
                 if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
             }
-            if (lane == 0) { s_d[0] = v; s_p[0] = i; }
+            if (lane == 0) {
+                s_d[0] = v;
+                s_p[0] = i;
+                if (v > stop) { s_mark[i] = 1; perm[k] = i; }
+            }
         }
         __syncthreads();
         const double dk = s_d[0];
         const int pk = s_p[0];
         if (!(dk > stop)) { kk = k; break; }             // uniform: the rest is numerically zero
-        if (pk != k) {                                   // symmetric swap of k and pk
-            for (int j = tid; j < c; j += NTC) {
-                const double a = G[k + j * ld];
-                G[k + j * ld] = G[pk + j * ld];
-                G[pk + j * ld] = a;
-            }
-            __syncthreads();
-            for (int j = tid; j < c; j += NTC) {
-                const double a = G[j + k * ld];
-                G[j + k * ld] = G[j + pk * ld];
-                G[j + pk * ld] = a;
-            }
-            if (tid == 0) { const int t = perm[k]; perm[k] = perm[pk]; perm[pk] = t; }
-            __syncthreads();
-        }
-        // row k of R1: r_kk = sqrt(g_kk), r_kj = g_kj / r_kk (into G's row k)
-        const double rkk = sqrt(G[k + k * ld]);
-        __syncthreads();                                 // everyone has read g_kk
-        for (int j = k + tid; j < c; j += NTC) G[k + j * ld] = j == k ? rkk : G[k + j * ld] / rkk;
-        __syncthreads();
-        // trailing update G[i][j] -= r_ki r_kj, i, j > k
-        const int nt = c - k - 1;
-        for (int e = tid; e < nt * nt; e += NTC) {
-            const int i = k + 1 + e % nt, j = k + 1 + e / nt;
-            G[i + j * ld] -= G[k + i * ld] * G[k + j * ld];
+        const double inv = 1.0 / dk;
+        for (int e = tid; e < c * c; e += NTC) {
+            const int i = e % c, j = e / c;
+            if (!s_mark[i] && !s_mark[j]) G[i + j * ld] -= G[i + pk * ld] * G[pk + j * ld] * inv;
         }
         __syncthreads();
     }
+    if (tid == 0) {                                      // the unpivoted columns follow in order
+        int q = kk;
+        for (int j = 0; j < c; ++j)
+            if (!s_mark[j]) perm[q++] = j;
+    }
+    __syncthreads();
     // X = R1 (rows >= kk zero)
     for (int e = tid; e < c * c; e += NTC) {
         const int i = e % c, j = e / c;
-        X[i + j * ldx] = (i <= j && i < kk) ? (F)G[i + j * ld] : (F)0;
+        F v = (F)0;
+        if (i <= j && i < kk) {
+            const int pi = perm[i], pj = perm[j];
+            v = (F)(G[pi + pj * ld] / sqrt(G[pi + pi * ld]));
+        }
+        X[i + j * ldx] = v;
     }
     __syncthreads();
 }
@@ -930,17 +946,25 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
             for (int t = 0; t < n2 - 1; ++t) {
                 // NTC / 16 groups of 16 lanes take the npair disjoint pairs of round t
                 for (int gp = g; gp < npair; gp += NTC / 16) {
-                    const int a = (t + gp) % (n2 - 1);
-                    const int b = gp == 0 ? n2 - 1 : (t - gp + n2 - 1) % (n2 - 1);
+                    // round-robin pair of round t (t + gp < 2 (n2 - 1): no division)
+                    int a = t + gp;
+                    if (a >= n2 - 1) a -= n2 - 1;
+                    const int b = gp == 0 ? n2 - 1 : (t >= gp ? t - gp : t - gp + n2 - 1);
                     const int p = a < b ? a : b, q = a < b ? b : a;
                     const bool act = q < c;
-                    F xp[EPL], xq[EPL];
+                    F xp[EPL], xq[EPL], wp[EPL], wq[EPL];
                     F al = 0, be = 0, ga = 0;
 #pragma unroll
                     for (int u = 0; u < EPL; ++u) {
                         const int r = gl + 16 * u;
-                        xp[u] = (act && r < c) ? X[r + p * ldc] : (F)0;
-                        xq[u] = (act && r < c) ? X[r + q * ldc] : (F)0;
+                        const bool in = act && r < c;
+                        xp[u] = in ? X[r + p * ldc] : (F)0;
+                        xq[u] = in ? X[r + q * ldc] : (F)0;
+                        wp[u] = in ? W[r + p * ldc] : (F)0;          // issued with X, used after the rotation
+                        wq[u] = in ? W[r + q * ldc] : (F)0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < EPL; ++u) {
                         al += xp[u] * xp[u];
                         be += xq[u] * xq[u];
                         ga += xp[u] * xq[u];
@@ -948,22 +972,21 @@ __global__ __launch_bounds__(NTC) void k_compress_svd64(const DCompress* __restr
                     al = row16_sum(al);
                     be = row16_sum(be);
                     ga = row16_sum(ga);
-                    if (act && ga != (F)0 && fabs(ga) > tol * sqrt(al * be) && al > tiny2 && be > tiny2) {
-                        const F zeta = (be - al) / ((F)2 * ga);
-                        const F tt = copysign((F)1, zeta) / (fabs(zeta) + sqrt((F)1 + zeta * zeta));
-                        const F cs = (F)1 / sqrt((F)1 + tt * tt), sn = cs * tt;
+                    const F d = sqrt(al * be);
+                    if (act && ga != (F)0 && fabs(ga) > tol * d && al > tiny2 && be > tiny2) {
+                        F cs, sn;
+                        jacobi_rotation(al, be, ga, cs, sn);
 #pragma unroll
                         for (int u = 0; u < EPL; ++u) {
                             const int r = gl + 16 * u;
                             if (r < c) {
                                 X[r + p * ldc] = cs * xp[u] - sn * xq[u];
                                 X[r + q * ldc] = sn * xp[u] + cs * xq[u];
-                                const F wp = W[r + p * ldc], wq = W[r + q * ldc];
-                                W[r + p * ldc] = cs * wp - sn * wq;
-                                W[r + q * ldc] = sn * wp + cs * wq;
+                                W[r + p * ldc] = cs * wp[u] - sn * wq[u];
+                                W[r + q * ldc] = sn * wp[u] + cs * wq[u];
                             }
                         }
-                        if (gl == 0 && fabs(ga) > tol_hi * sqrt(al * be)) s_big = 1;
+                        if (gl == 0 && fabs(ga) > tol_hi * d) s_big = 1;
                     }
                 }
                 __syncthreads();
