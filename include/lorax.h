@@ -163,6 +163,8 @@ typedef struct {
     double level_norm_by_level[32];/* LRX_RULE_FROB: N_i of eqn. curOff6 by level (0 otherwise) */
     int64_t sweep_stages;          /* LDS stages of both sweeps' node programs, summed over the nodes */
     int64_t sweep_launches;        /* launches of one solve application (one per colour step and sweep) */
+    double t_host_compress_ms;     /* host time building and launching the compress steps (no waits) */
+    double t_host_node_ms;         /* host time from each rank read-back to the last node launch */
 } lrx_stats_t;
 
 /* Symbolic counts, computed on the host without any device call. */

@@ -2709,8 +2709,9 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
     }
 }
 
-// One work-group per super-node of a colour step; x is the extended vector
-// (row-interleaved, ldx right-hand sides), this launch treats [k0, k0 + NK).
+// One work-group per super-node of a colour step and slice of NK right-hand
+// sides; x is the extended vector (row-interleaved, ldx right-hand sides), this
+// launch treats [k0, k0 + gridDim.y NK).
 // Each run states the storage type of its block (FP64, or FP32 for off-diagonal
 // blocks in mixed precision); LDS, vectors and accumulation stay FP64.
 template <int NK>
@@ -2726,7 +2727,7 @@ __global__ __launch_bounds__(kSwThreads) void k_sweep(const SwNode* __restrict__
     for (int w = tid; w < nd.words0; w += kSwThreads) Dbuf[w] = src[w];
     src += nd.words0;
     if (nd.x) x = nd.x;
-    x += k0;
+    x += k0 + (int)blockIdx.y * NK;             // slice y of the launch: right-hand sides k0 + y NK ..
     __syncthreads();
     for (int s = 0; s < nd.nstage; ++s) {
         const int32_t* D = Dbuf + (s & 1) * kSwDescWords;
@@ -3254,7 +3255,7 @@ hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int 
 }
 
 template <int NK>
-hipError_t launch_sweep_nk(const SwNode* nodes, int n, double* x, int ldx, int k0,
+hipError_t launch_sweep_nk(const SwNode* nodes, int n, double* x, int ldx, int k0, int ns,
                            hipStream_t st) {
     constexpr size_t lds = (size_t)kSwDescWords * 2 * sizeof(int32_t) + (size_t)kSwData * sizeof(double);
     static std::atomic<bool> attr{false};
@@ -3264,17 +3265,17 @@ hipError_t launch_sweep_nk(const SwNode* nodes, int n, double* x, int ldx, int k
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_sweep<NK>, dim3(n), dim3(kSwThreads), lds, st, nodes, x, ldx, k0);
+    hipLaunchKernelGGL(k_sweep<NK>, dim3(n, ns), dim3(kSwThreads), lds, st, nodes, x, ldx, k0);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, hipStream_t st) {
-    if (n == 0) return hipSuccess;
+hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, int ns, hipStream_t st) {
+    if (n == 0 || ns == 0) return hipSuccess;
     switch (nk) {
-        case 8: return launch_sweep_nk<8>(nodes, n, x, ldx, k0, st);
-        case 4: return launch_sweep_nk<4>(nodes, n, x, ldx, k0, st);
-        case 2: return launch_sweep_nk<2>(nodes, n, x, ldx, k0, st);
-        case 1: return launch_sweep_nk<1>(nodes, n, x, ldx, k0, st);
+        case 8: return launch_sweep_nk<8>(nodes, n, x, ldx, k0, ns, st);
+        case 4: return launch_sweep_nk<4>(nodes, n, x, ldx, k0, ns, st);
+        case 2: return launch_sweep_nk<2>(nodes, n, x, ldx, k0, ns, st);
+        case 1: return launch_sweep_nk<1>(nodes, n, x, ldx, k0, ns, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -89,11 +89,12 @@ hipError_t launch_gemm_mfma(const DGemm* g, const DTile* tiles, int ntile, int k
                             int kc_cap, int grid_cap, hipStream_t st);
 
 // One sweep launch (forward or backward program) over n super-nodes of a
-// colour step, right-hand sides [k0, k0 + nk) of x (ldx per row), nk in {1,2,4,8}.
+// colour step and ns slices of nk right-hand sides, [k0, k0 + ns nk) of x (ldx
+// per row), nk in {1,2,4,8}; a work-group per (node, slice).
 // Nodes with x == nullptr use x; each node's program is its own device pointer
 // and each run states its blocks' storage type, so nodes of several
 // factorizations (FP64 or mixed precision) can share one launch.
-hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, hipStream_t st);
+hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, int ns, hipStream_t st);
 // Device address of the static scratch array of the allocation-free entry
 // points on device dev (which must be current at the first call per device);
 // kNoallocScratchBytes per device, shared by every such call on that device.

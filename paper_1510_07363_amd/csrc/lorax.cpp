@@ -1052,6 +1052,7 @@ hipError_t gemm_products(const DGemm* g, const DTile* t, int ntile, int kmax, co
 void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::vector<const lrx_csr*>& A,
                 const std::vector<const double*>& val_dev) {
     double t_sync = 0.0;
+    double t_h_comp = 0.0, t_h_node = 0.0;   // host work of the compress and node phases
     int64_t epoch = 0;                   // number of stream synchronizations so far
     auto sync = [&]() {
         const double ts = now_ms();
@@ -1132,6 +1133,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 part.push_back(r);
             }
             // ---- compress: descriptors, workspace, one launch per kernel variant
+            const double tc0 = now_ms();
             bool grow = false;
             std::vector<size_t> wst(part.size());
             for (size_t i = 0; i < part.size(); ++i) {
@@ -1411,9 +1413,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 if (canon)
                     HIPCHK(launch_v_sign((const DCompress*)(d_desc_c.as<char>() + oall), (int)all.size(), st));
             }
+            t_h_comp += now_ms() - tc0;
             pin_rt.ensure(rt_bytes);
             if (rt_bytes) HIPCHK(hipMemcpyAsync(pin_rt.p, d_rt.p, rt_bytes, hipMemcpyDeviceToHost, st));
             sync();
+            const double tn0 = now_ms();
             const int32_t* rk = (const int32_t*)pin_rt.p;
             const double* tails_h = (const double*)((const char*)pin_rt.p + tails_off);
             for (FactorRun* r : part) {
@@ -1490,6 +1494,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             }
             gemm(o_g1b, o_t1b, t1b, k1b, 0, GP_F64);
             gemm(o_g2b, o_t2b, t2b, k2b, nb.gf_b, p_schur);
+            t_h_node += now_ms() - tn0;
         }
     }
     sync();
@@ -1512,6 +1517,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             for (int lv = 0; lv < 32 && lv <= r.P.depth; ++lv) r.h->stats.level_norm_by_level[lv] = st_h[2 + lv];
         }
         r.h->t_sync_ms += t_sync;
+        r.h->stats.t_host_compress_ms = t_h_comp;
+        r.h->stats.t_host_node_ms = t_h_node;
     }
     IdleScope idle;
     for (FactorRun* r : runs) {
@@ -1725,13 +1732,33 @@ void build_solve_program(lrx_handle h) {
     h->t_solve_prog_ms = now_ms() - t_begin;
 }
 
-// Right-hand sides per sweep launch for rem remaining: the largest of 8, 4, 2, 1
-// that fits, capped by the tuning table.
+// Right-hand sides per sweep work-group for rem remaining: the largest of 8, 4,
+// 2, 1 that fits, capped by the tuning table.
 int sweep_nk(int rem) {
     const int cap = g_tune.sweep_nk_max;
     for (int nk = 8; nk > 1; nk >>= 1)
         if (nk <= cap && rem >= nk) return nk;
     return 1;
+}
+
+constexpr int kDeviceCUs = 256;
+
+// One colour step of a sweep over all nrhs right-hand sides: the right-hand
+// sides are split into slices that run side by side (a work-group per node and
+// slice), with smaller slices while the node count leaves compute units idle;
+// f(k0, nk, ns) issues one launch of ns slices of nk from k0.  The arithmetic of
+// each right-hand side does not depend on the slicing.
+template <class Fn>
+void sweep_step(int nnode, int nrhs, Fn&& f) {
+    const int target = std::max(1, kDeviceCUs / std::max(nnode, 1));
+    for (int c0 = 0; c0 < nrhs;) {
+        const int rem = nrhs - c0;
+        int nk = sweep_nk(rem);
+        while (nk > 1 && rem / (nk / 2) <= target) nk /= 2;
+        const int ns = rem / nk;
+        f(c0, nk, ns);
+        c0 += nk * ns;
+    }
 }
 
 // x_ext (n_ext x nrhs interleaved) -> in place sweeps.  timed = false records
@@ -1740,19 +1767,16 @@ void sweeps(lrx_handle h, double* xe, int nrhs, bool timed = true) {
     const hipStream_t st = h->stream;
     const SwNode* fwd = h->d_swnodes.as<SwNode>();
     const SwNode* bwd = fwd + h->sw_nnode;
-    for (int k0 = 0; k0 < nrhs;) {
-        const int rem = nrhs - k0;
-        const int nk = sweep_nk(rem);
-        for (const SolveStep& s : h->ssteps) {
-            LaunchTimer tm(timed ? LRX_K_SOLVE_FWD : -1, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nk);
-            HIPCHK(launch_sweep(fwd + s.node0, s.nnode, xe, nrhs, k0, nk, st));
-        }
-        for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it) {
-            LaunchTimer tm(timed ? LRX_K_SOLVE_BWD : -1, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nk);
-            HIPCHK(launch_sweep(bwd + it->node0, it->nnode, xe, nrhs, k0, nk, st));
-        }
-        k0 += nk;
-    }
+    for (const SolveStep& s : h->ssteps)
+        sweep_step(s.nnode, nrhs, [&](int k0, int nk, int ns) {
+            LaunchTimer tm(timed ? LRX_K_SOLVE_FWD : -1, st, (double)s.bytes_fwd, (double)s.bytes_fwd / 4.0 * nk * ns);
+            HIPCHK(launch_sweep(fwd + s.node0, s.nnode, xe, nrhs, k0, nk, ns, st));
+        });
+    for (auto it = h->ssteps.rbegin(); it != h->ssteps.rend(); ++it)
+        sweep_step(it->nnode, nrhs, [&](int k0, int nk, int ns) {
+            LaunchTimer tm(timed ? LRX_K_SOLVE_BWD : -1, st, (double)it->bytes_bwd, (double)it->bytes_bwd / 4.0 * nk * ns);
+            HIPCHK(launch_sweep(bwd + it->node0, it->nnode, xe, nrhs, k0, nk, ns, st));
+        });
 }
 
 // Algorithms 2-4 with the extended vector in xe (n_ext x nrhs): SetRHS (b in
@@ -1819,15 +1843,14 @@ void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const*
         const int32_t n = h->plan.n;
         HIPCHK(launch_gather_perm(b[i], n, h->d_perm.as<int32_t>(), n, nrhs, xe[i], h->n_ext, st));
     }
-    for (int c0 = 0; c0 < nrhs;) {
-        const int rem = nrhs - c0;
-        const int nk = sweep_nk(rem);
-        for (size_t q = 0; q + 1 < k0f.size(); ++q)
-            HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
-        for (size_t q = k0f.size() - 1; q-- > 0;)
-            HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
-        c0 += nk;
-    }
+    for (size_t q = 0; q + 1 < k0f.size(); ++q)
+        sweep_step(k0f[q + 1] - k0f[q], nrhs, [&](int c0, int nk, int ns) {
+            HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, ns, st));
+        });
+    for (size_t q = k0f.size() - 1; q-- > 0;)
+        sweep_step(k0f[q + 1] - k0f[q], nrhs, [&](int c0, int nk, int ns) {
+            HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, ns, st));
+        });
     for (int i = 0; i < k; ++i) {
         const lrx_handle h = hs[i];
         const int32_t n = h->plan.n;
@@ -1989,19 +2012,16 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
         HIPCHK(hipMemcpy(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
     }
     auto sweep_launches = [&](bool timed) {
-        for (int c0 = 0; c0 < nrhs;) {
-            const int rem = nrhs - c0;
-            const int nk = sweep_nk(rem);
-            for (size_t q = 0; q + 1 < k0f.size(); ++q) {
-                LaunchTimer tm(timed ? LRX_K_SOLVE_FWD : -1, st, step_bytes_f[q], step_bytes_f[q] / 4.0 * nk);
-                HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
-            }
-            for (size_t q = k0f.size() - 1; q-- > 0;) {
-                LaunchTimer tm(timed ? LRX_K_SOLVE_BWD : -1, st, step_bytes_b[q], step_bytes_b[q] / 4.0 * nk);
-                HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, st));
-            }
-            c0 += nk;
-        }
+        for (size_t q = 0; q + 1 < k0f.size(); ++q)
+            sweep_step(k0f[q + 1] - k0f[q], nrhs, [&](int c0, int nk, int ns) {
+                LaunchTimer tm(timed ? LRX_K_SOLVE_FWD : -1, st, step_bytes_f[q], step_bytes_f[q] / 4.0 * nk * ns);
+                HIPCHK(launch_sweep(dn + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, ns, st));
+            });
+        for (size_t q = k0f.size() - 1; q-- > 0;)
+            sweep_step(k0f[q + 1] - k0f[q], nrhs, [&](int c0, int nk, int ns) {
+                LaunchTimer tm(timed ? LRX_K_SOLVE_BWD : -1, st, step_bytes_b[q], step_bytes_b[q] / 4.0 * nk * ns);
+                HIPCHK(launch_sweep(dn + nf.size() + k0f[q], k0f[q + 1] - k0f[q], nullptr, nrhs, c0, nk, ns, st));
+            });
     };
     // The preconditioner is the same launch sequence at every Arnoldi step (the
     // node tables, vectors and act flags it reads stay where they are), so after

@@ -63,7 +63,8 @@ class Stats(C.Structure):
                 ("device_bytes", C.c_int64), ("flops_compress", C.c_double), ("flops_pivot", C.c_double),
                 ("flops_schur", C.c_double), ("flops_project", C.c_double),
                 ("level_norm_by_level", C.c_double * 32), ("sweep_stages", C.c_int64),
-                ("sweep_launches", C.c_int64)]
+                ("sweep_launches", C.c_int64), ("t_host_compress_ms", C.c_double),
+                ("t_host_node_ms", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -365,7 +366,8 @@ class Factor:
                     flops_by_op={"compress": float(s.flops_compress), "pivot": float(s.flops_pivot),
                                  "schur": float(s.flops_schur), "project": float(s.flops_project)},
                     level_norm_by_level={i: float(s.level_norm_by_level[i]) for i in range(1, d + 1)},
-                    sweep_stages=int(s.sweep_stages), sweep_launches=int(s.sweep_launches))
+                    sweep_stages=int(s.sweep_stages), sweep_launches=int(s.sweep_launches),
+                    t_host_compress_ms=float(s.t_host_compress_ms), t_host_node_ms=float(s.t_host_node_ms))
 
     def ranks(self):
         n = self.stats()["n_compressions"]
