@@ -353,6 +353,8 @@ def measure(args, p, lorax, torch, precision, sptr, val_d, b_d, x_d):
                    "true_relres_max": float(res.max()),
                    "t_factor_ms": st["t_factor_ms"], "t_plan_ms": st["t_plan_ms"],
                    "t_factor_sync_ms": st["t_sync_ms"], "t_solve_prog_ms": st["t_solve_prog_ms"],
+                   "t_host_compress_ms": st["t_host_compress_ms"], "t_host_node_ms": st["t_host_node_ms"],
+                   "sweep_stages": st["sweep_stages"], "sweep_launches": st["sweep_launches"],
                    "factor_bytes": st["factor_bytes"], "solve_bytes": st["solve_bytes"],
                    "mean_rank": st["mean_rank"], "max_rank": st["max_rank"],
                    "kernel_ms_per_step_probe": {k: round(v["total_ms"], 3) for k, v in probe.items()},

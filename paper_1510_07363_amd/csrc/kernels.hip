@@ -2333,7 +2333,9 @@ __device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
         wave_argmax(best, bi);
         if (lane == 0) { rv[buf * NWP + wv] = best; ri[buf * NWP + wv] = bi; }
     };
-    publish_max((h == 0 && !used) ? fabs(ck) : -1.0, 0);
+    // only the wavefronts that hold the next pivot column publish (for MB >= 64
+    // a wavefront holds one column range; smaller MB mix ranges in a wavefront)
+    if (MB < WAVE || h == 0) publish_max((h == 0 && !used) ? fabs(ck) : -1.0, 0);
     __syncthreads();
     for (int k = 0; k < m; ++k) {
         const int buf = k & 1;
@@ -2383,7 +2385,7 @@ __device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
             }
         }
         ck = cnext;
-        if (kn < m) publish_max((h == knh && !used) ? fabs(ck) : -1.0, buf ^ 1);
+        if (kn < m && (MB < WAVE || h == knh)) publish_max((h == knh && !used) ? fabs(ck) : -1.0, buf ^ 1);
         __syncthreads();
     }
     // A^{-1}[k, p_l] = stored[p_k, l]: this thread holds stored[i, c0..] with i = p_mystep
