@@ -39,8 +39,9 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 # x 1.00); kept per (workload, precision, kernel class) and reported as the
 # roofline's traffic.
 TRAFFIC_BYTES = {
-    ("varcoef2d_256", "mixed", "compress"): 1.388e6,
-    ("varcoef2d_256", "fp64", "compress"): 1.382e6,
+    ("varcoef2d_256", "mixed", "compress"): 1.388e6,          # FP32 QR path (compress_gram = 0)
+    ("varcoef2d_256", "mixed", "compress_gram"): 2.200e6,     # FETCH 707.9 KiB, WRITE 732.4 KiB
+    ("varcoef2d_256", "fp64", "compress"): 1.393e6,           # FETCH 454.8 KiB, WRITE 451.0 KiB
 }
 TOL = 1e-10
 RESTART = 30

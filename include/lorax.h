@@ -374,7 +374,8 @@ lrx_status lrx_timing_read(lrx_timing_t* t, int32_t reset);
 typedef struct {
     int32_t gemm_kc;          /* K chunk staged in LDS by the MFMA products: 16..256, multiple of 16 */
     int32_t gemm_f64_valu;    /* 1: FP64 products on the VALU tile kernel instead of the matrix cores */
-    int32_t sweep_nk_max;     /* right-hand sides per solve-sweep launch: 1, 2, 4 or 8 */
+    int32_t sweep_nk_max;     /* right-hand sides per solve-sweep work-group (at most; the library also
+                                 splits them into slices that run side by side): 1, 2 or 4 */
     int32_t compress_nt_small;  /* threads per stacked block of <= 32 columns in Compress: 256, 512, 1024 */
     int32_t compress_nt_mid;    /* the same for 33..64 columns */
     int32_t gemm_grid;        /* 0: one work-group per 32 x 32 product tile; n > 0: a persistent grid of at

@@ -37,7 +37,7 @@ CANDIDATES = {
     "gemm_f64_valu": [0, 1],
     "compress_nt_small": [256, 512, 1024],
     "compress_nt_mid": [256, 512, 1024],
-    "sweep_nk_max": [2, 4, 8],
+    "sweep_nk_max": [1, 2, 4],
     "gemm_grid": [0, 512, 1024, 2048],
 }
 FACTOR_CLASSES = ("compress", "compress_gram", "factor_node", "schur", "project")

@@ -126,7 +126,7 @@ struct DMerge {
 constexpr int kSwThreads = 1024;       // work-group size of the sweep kernel
 constexpr int kSwDescWords = 2048;     // largest descriptor block (two are resident)
 constexpr int kSwData = 17408;         // doubles of LDS for buffers and staged data
-constexpr int kSwKS = 8;               // row stride of vector buffers in LDS (max RHS per launch)
+constexpr int kSwKS = 4;               // row stride of vector buffers in LDS (max RHS per work-group)
 
 struct SwNode {
     const int32_t* desc; // stage 0's descriptor block (device)

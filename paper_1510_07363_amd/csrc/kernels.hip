@@ -2562,11 +2562,12 @@ __global__ __launch_bounds__(GT) void k_gemm_tiles(const DGemm* __restrict__ gs,
 // run advances by a fixed quotient and remainder; the fields of the current
 // run stay in registers.
 // Vector rows in LDS (kSwKS doubles each, right-hand side k of the row that
-// starts at LDS double ra) keep element k at ra + (k ^ ((ra >> 4) & 7)): rows
-// 8 doubles apart then put one element of 16 consecutive rows in 16 different
-// bank pairs, so lanes that read one element of different rows do not conflict.
-static_assert(kSwKS == 8, "vector row swizzle assumes rows of 8 doubles");
-__device__ __forceinline__ int sw_slot(int ra, int k) { return ra + (k ^ ((ra >> 4) & 7)); }
+// starts at LDS double ra) keep element k at ra + (k ^ ((ra >> 5) & 3)): 8
+// consecutive rows fill the 64 banks once, and the next 8 are shifted by the
+// key, so lanes that read one element of 16 consecutive rows do not conflict.
+static_assert(kSwKS == 4, "vector row swizzle assumes rows of 4 doubles");
+__device__ __forceinline__ int sw_key(int ra) { return (ra >> 5) & 3; }
+__device__ __forceinline__ int sw_slot(int ra, int k) { return ra + (k ^ sw_key(ra)); }
 
 template <int NK>
 __device__ __forceinline__ void sw_copy(const SwRun* runs, int nrun, const int32_t* D, int elems,
@@ -2661,7 +2662,7 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
         for (int t = sub; t < c.nc; t += L) {
             const double mv = mp[t * c.ld];
             const int row = c.in_map < 0 ? t : D[c.in_map + t];
-            const int ra = c.in + row * kSwKS, key = (ra >> 4) & 7;
+            const int ra = c.in + row * kSwKS, key = sw_key(ra);
             const double* iv = dat + ra;
 #pragma unroll
             for (int k = 0; k < NK; ++k) acc[k] = fma(mv, iv[k ^ key], acc[k]);
@@ -2687,7 +2688,7 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
         if (sub == 0) {
             double y[NK];
             if (c.init >= 0) {
-                const int ra = c.init + (c.init_map < 0 ? a : D[c.init_map + a]) * kSwKS, key = (ra >> 4) & 7;
+                const int ra = c.init + (c.init_map < 0 ? a : D[c.init_map + a]) * kSwKS, key = sw_key(ra);
                 const double* ip = dat + ra;
 #pragma unroll
                 for (int k = 0; k < NK; ++k) y[k] = ip[k ^ key] - acc[k];
@@ -2696,7 +2697,7 @@ __device__ __forceinline__ void sw_group(const SwGroup& G, const SwComp* C, cons
                 for (int k = 0; k < NK; ++k) y[k] = acc[k];
             }
             if (c.out >= 0) {
-                const int ra = c.out + (c.out_map < 0 ? a : D[c.out_map + a]) * kSwKS, key = (ra >> 4) & 7;
+                const int ra = c.out + (c.out_map < 0 ? a : D[c.out_map + a]) * kSwKS, key = sw_key(ra);
                 double* op = dat + ra;
 #pragma unroll
                 for (int k = 0; k < NK; ++k) op[k ^ key] = y[k];
@@ -3273,8 +3274,7 @@ hipError_t launch_sweep_nk(const SwNode* nodes, int n, double* x, int ldx, int k
 
 hipError_t launch_sweep(const SwNode* nodes, int n, double* x, int ldx, int k0, int nk, int ns, hipStream_t st) {
     if (n == 0 || ns == 0) return hipSuccess;
-    switch (nk) {
-        case 8: return launch_sweep_nk<8>(nodes, n, x, ldx, k0, ns, st);
+    switch (nk) {                                // nk <= kSwKS
         case 4: return launch_sweep_nk<4>(nodes, n, x, ldx, k0, ns, st);
         case 2: return launch_sweep_nk<2>(nodes, n, x, ldx, k0, ns, st);
         case 1: return launch_sweep_nk<1>(nodes, n, x, ldx, k0, ns, st);

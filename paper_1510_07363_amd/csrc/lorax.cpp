@@ -399,7 +399,7 @@ namespace {
 struct Tune {
     int32_t gemm_kc = 128;          // K chunk of the MFMA products (multiple of 16, <= 256)
     int32_t gemm_f64_valu = 0;      // 1: FP64 products on the VALU tile kernel instead of MFMA
-    int32_t sweep_nk_max = 8;       // right-hand sides per sweep launch (1, 2, 4 or 8)
+    int32_t sweep_nk_max = 4;       // right-hand sides per sweep work-group (1, 2 or 4)
     int32_t compress_nt_small = 1024;   // threads per stacked block of at most 32 columns
     int32_t compress_nt_mid = 1024;     // threads per stacked block of 33..64 columns
     int32_t gemm_grid = 0;          // persistent grid of the MFMA products (0: a work-group per tile)
@@ -1736,7 +1736,7 @@ void build_solve_program(lrx_handle h) {
 // 2, 1 that fits, capped by the tuning table.
 int sweep_nk(int rem) {
     const int cap = g_tune.sweep_nk_max;
-    for (int nk = 8; nk > 1; nk >>= 1)
+    for (int nk = kSwKS; nk > 1; nk >>= 1)
         if (nk <= cap && rem >= nk) return nk;
     return 1;
 }
@@ -2605,8 +2605,8 @@ lrx_status lrx_tune_set(const lrx_tune* t) {
         if (!t) fail(LRX_EINVAL, "null tuning table");
         if (t->gemm_kc < 16 || t->gemm_kc > 256 || t->gemm_kc % 16) fail(LRX_EINVAL, "gemm_kc must be 16..256, a multiple of 16");
         if (t->gemm_f64_valu != 0 && t->gemm_f64_valu != 1) fail(LRX_EINVAL, "gemm_f64_valu must be 0 or 1");
-        if (t->sweep_nk_max != 1 && t->sweep_nk_max != 2 && t->sweep_nk_max != 4 && t->sweep_nk_max != 8)
-            fail(LRX_EINVAL, "sweep_nk_max must be 1, 2, 4 or 8");
+        if (t->sweep_nk_max != 1 && t->sweep_nk_max != 2 && t->sweep_nk_max != 4)
+            fail(LRX_EINVAL, "sweep_nk_max must be 1, 2 or 4");
         for (int32_t v : {t->compress_nt_small, t->compress_nt_mid})
             if (v != 256 && v != 512 && v != 1024) fail(LRX_EINVAL, "compress_nt_* must be 256, 512 or 1024");
         if (t->gemm_grid < 0 || t->gemm_grid > 65536) fail(LRX_EINVAL, "gemm_grid must be 0..65536");
