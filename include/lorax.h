@@ -330,6 +330,14 @@ lrx_status lrx_ranks(lrx_handle h, int32_t* ranks, int32_t* levels, int32_t* js)
  * At most cap values are written. */
 lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t cap, int32_t* len);
 
+/* Shape of the stacked block B of compression idx (same order as lrx_ranks, Sec.
+ * 4.3): *rows = the rows stored (the non-zero rows of the pieces of
+ * well-separated neighbours), *cols = its columns c (the super-node's variables
+ * that couple to them).  The variant that compressed it follows from the
+ * shape: c <= 64, 64 < c <= 192 (tall when rows c >= 3e5), and the split form
+ * beyond (or rows c >= 1e6).  LRX_EINVAL for a bad index or NULL outputs. */
+lrx_status lrx_compression_shape(lrx_handle h, int32_t idx, int32_t* rows, int32_t* cols);
+
 /* Host-only symbolic plan of Algorithm 1 for (A, T, order): no device call. */
 lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order,
                             lrx_plan_info* info);
@@ -346,7 +354,7 @@ typedef enum {
     LRX_K_SPMV = 4,           /* A times the preconditioned vectors (GMRES) */
     LRX_K_SCHUR = 5,          /* Schur-complement products of Eliminate(s), Eliminate(b) (Sec. 2.2) */
     LRX_K_PROJECT = 6,        /* projection [R; Q] = B V of the compressed blocks (Sec. 4.3) */
-    LRX_K_COMPRESS_GRAM = 7,  /* Compress of blocks of <= 64 columns through the FP64 Gram matrix (mixed) */
+    LRX_K_COMPRESS_GRAM = 7,  /* Compress through the FP64 Gram matrix (lrx_tune.compress_gram) */
     LRX_K_CLASSES = 8
 } lrx_kernel_class;
 
@@ -384,11 +392,14 @@ typedef struct {
                                  application) into a HIP graph after the first application and
                                  replays it at every later Arnoldi step (not on the null stream,
                                  nor while solve sweeps are event-timed); 0: direct launches */
-    int32_t compress_gram;    /* SVD compression of stacked blocks of <= 64 columns at epsilon >= 1e-5
-                                 through the FP64 Gram matrix B^T B and two-sided Jacobi (sigma_k off by
-                                 about c u sigma_0^2 / sigma_k; values below about 1e-7 sigma_0 not
-                                 resolved) instead of QR-preconditioned one-sided Jacobi: 0 never,
-                                 1 in mixed precision (default), 2 in mixed and FP64 precision */
+    int32_t compress_gram;    /* SVD compression at epsilon >= 1e-5 under the cut-off of eqn. cutOff1
+                                 with R1 and the column order from the FP64 Gram matrix G = B^T B and a
+                                 Cholesky factorization with diagonal pivoting, instead of the QR of B
+                                 and the QRCP of R (the LQ and the one-sided Jacobi follow as usual):
+                                 sigma_k is off by about c u sigma_0^2 / sigma_k and values below about
+                                 sqrt(c u trace(G)) are not resolved.  Blocks of more than 64 columns
+                                 form G on the matrix cores and factor it in panels.  0 never, 1 in mixed
+                                 precision (default), 2 in mixed and FP64 precision */
 } lrx_tune;
 
 lrx_status lrx_tune_get(lrx_tune* t);

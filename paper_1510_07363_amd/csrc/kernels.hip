@@ -1526,17 +1526,19 @@ static_assert(LH_N <= 8, "the header has 8 doubles");
 constexpr int KK_BLK = 8;                    // columns per block of the multi-work-group Jacobi
 constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold in LDS (16 x 1150 doubles)
 
-// mode 0: the whole pipeline in this work-group; mode 1: steps 1-3 and the
-// Jacobi only when L is too tall for the block rounds (state left in hv);
-// mode 4: assembly and the scaled copy Bw only; mode 5: after the tall QR of Bw
+// mode 0: the whole pipeline in this work-group; mode 4: assembly and the scaled copy Bw only; mode 5: after the tall QR of Bw
 // by the panel and update launches, the pivoted QR and A2 (the LQ and Q2 follow
 // as launches); mode 6: from A2 factored and W = Q2 formed, L and the state for
 // the block rounds; mode 2: singular values, rank and V after the block rounds;
-// mode 7: mode 0 from the tall QR of Bw done by the panel and update launches.
+// mode 7: mode 0 from the tall QR of Bw done by the panel and update launches;
+// mode 8: after the Gram matrix and its pivoted Cholesky (launch_gram_chol), A2
+// and the state, as mode 5 leaves them; mode 9: from there the LQ, Q2, Jacobi
+// and finish in this work-group.
+// (The mode is a template parameter: each stage compiles to its own kernel.)
+template <int mode>
 __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
-                                                        const int32_t* __restrict__ imap, double trunc_rel,
-                                                        int mode) {
+                                                        const int32_t* __restrict__ imap, double trunc_rel) {
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
     const int lane = tid % WAVE, wv = tid / WAVE;
@@ -1566,6 +1568,20 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     const int64_t ldc = c;
     int kk = 0;
     double rest2 = 0.0, scale = 1.0;
+    if (mode == 8) {
+        // A2 = R1[:kk, :]^T in pivot order from the rows of R kept transposed in X
+        // over the original columns (Rt[i + J c] = R(J, i)); W = E
+        kk = (int)hdr[LH_KK];
+        for (int k = tid; k < c; k += NTL) s_perm[k] = (int)hst[k];
+        __syncthreads();
+        for (int e = tid; e < c * kk; e += NTL) {
+            const int q = e % c, J = e / c;
+            A2[q + J * ldc] = q >= J ? X[s_perm[q] + (int64_t)J * ldc] : 0.0;
+            W[q + J * ldc] = q == J ? 1.0 : 0.0;
+        }
+        if (tid == 0) hdr[LH_DONE] = 0.0;
+        return;
+    }
     if (mode == 2) {
         kk = (int)hdr[LH_KK];
         scale = hdr[LH_SCALE];
@@ -1574,7 +1590,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         __syncthreads();
     } else {
     double* Bw = T.Bw;
-    if (mode != 6) {
+    if (mode != 6 && mode != 9) {
     if (mode == 5 || mode == 7) {
         scale = hdr[LH_SCALE];
     } else {
@@ -1688,13 +1704,14 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         }
         return;
     }
-    }                                                   // mode != 6
-    if (mode == 6) {
+    }                                                   // mode != 6, 9
+    if (mode == 6 || mode == 9) {
         kk = (int)hdr[LH_KK];
         scale = hdr[LH_SCALE];
         rest2 = hdr[LH_REST2];
         for (int k = tid; k < c; k += NTL) s_perm[k] = (int)hst[k];
-    } else {
+    }
+    if (mode != 6) {
     __syncthreads();
     for (int j = 0; j < kk; ++j) {
         double v0;
@@ -1733,7 +1750,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     }
     // ---- 4. one-sided Jacobi on the kk columns of L; W follows.  Pairs run in
     // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes.
-    // In mode 1 it runs here only when L is too tall for the block rounds.
+    // In mode 6 it runs here only when L is too tall for the block rounds.
     const double u = 1.1102230246251565e-16;
     const double tol = 3.6 * u * (double)kk, tol_hi = sqrt(tol);
     double f = 0.0;
@@ -1743,11 +1760,11 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     }
     const double fro = blk_sum_l(f, s_red);
     const double tiny2 = 81.0 * u * u * fro;
-    const bool inline_jacobi = mode == 0 || mode == 7 || kk > KK_LDS_MAX;
+    const bool inline_jacobi = mode == 0 || mode == 7 || mode == 9 || kk > KK_LDS_MAX;
     // Jacobi sweeps of this task (work accounting): counted here when the sweeps
     // run inline, else one per sweep of the block rounds by k_large_flags
     if (tid == 0) T.tails[c + 1] = 0.0;
-    if (mode == 1 || mode == 6) {
+    if (mode == 6) {
         for (int k = tid; k < c; k += NTL) hst[k] = (double)s_perm[k];
         if (tid == 0) {
             hdr[LH_KK] = kk;
@@ -1782,7 +1799,7 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         }
         if (tid == 0) T.tails[c + 1] = (double)sweeps_run;
     }
-    if (mode == 1 || mode == 6) return;
+    if (mode == 6) return;
     }                                                   // mode != 2
     // ---- singular values, order, rank, V = P W
     for (int k = wv; k < kk; k += NWL) {
@@ -1839,7 +1856,8 @@ struct QrView {
     double* scr;                             // panel scratch base
 };
 
-__device__ inline bool qr_view(const DCompress& T, int which, QrView& v) {
+template <int which>
+__device__ inline bool qr_view(const DCompress& T, QrView& v) {
     const int M = T.M, c = T.c;
     if (M == 0 || c == 0) return false;
     v.scr = T.hv + 3 * (size_t)c * c;
@@ -1856,11 +1874,12 @@ __device__ inline bool qr_view(const DCompress& T, int which, QrView& v) {
     return true;
 }
 
-__global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ tasks, int j0, int which) {
+template <int which>
+__global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ tasks, int j0) {
     const DCompress T = tasks[blockIdx.x];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     QrView Q;
-    if (!qr_view(T, which, Q) || j0 >= Q.kq) return;
+    if (!qr_view<which>(T, Q) || j0 >= Q.kq) return;
     const int nb = min(QB, Q.kq - j0);
     extern __shared__ double s_vp[];
     __shared__ double s_red[NWL];
@@ -1904,11 +1923,12 @@ __global__ __launch_bounds__(NTL) void k_qr_panel(const DCompress* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__ tasks, int j0, int which) {
+template <int which>
+__global__ __launch_bounds__(NTL) void k_qr_update(const DCompress* __restrict__ tasks, int j0) {
     const DCompress T = tasks[blockIdx.y];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     QrView Q;
-    if (!qr_view(T, which, Q) || j0 >= Q.kq) return;
+    if (!qr_view<which>(T, Q) || j0 >= Q.kq) return;
     const int nb = min(QB, Q.kq - j0);
     const int cfirst = which == 2 ? j0 : j0 + nb;             // columns the panel changes
     const int c0 = cfirst + blockIdx.x * QB;
@@ -2091,6 +2111,214 @@ __global__ void k_large_flags(const DCompress* __restrict__ tasks, int n, int32_
     hdr[LH_BIG] = 0.0;
     if (!go) hdr[LH_DONE] = 1.0;
     out[i] = go;
+}
+
+// ---------------------------------------------------------------- large blocks via the Gram matrix
+// R1 and the column order of a stacked block with c > 64 columns from its FP64
+// Gram matrix, in place of the tall QR of Bw and the QRCP of R0 (the LQ, Q2,
+// Jacobi and finish stages follow as on the QR route):
+//   1. G = Bw^T Bw (c x c, both triangles) in the W area, on the matrix cores:
+//      a work-group per 32 x 32 tile of the upper triangle, K (the rows of Bw)
+//      in LDS chunks of GT_KC.
+//   2. panels of CHB pivots, a work-group per task: the pivot is the largest
+//      remaining diagonal (lowest column on ties); row J of R over the original
+//      columns is R(J, i) = (S(i, p) - sum of R(J', i) R(J', p) over the
+//      panel's earlier rows J') / sqrt(d_p), kept transposed in the X area
+//      (Rt[i + J c]), and the remaining diagonal d drops by R(J, i)^2 at once.
+//      The factorization stops at the first J whose largest remaining diagonal
+//      is at most c u trace(G) (the rest is rounding) or whose remaining
+//      diagonals sum (the squared Frobenius norm of the trailing block of R1)
+//      to at most (trunc_rel epsilon)^2 R1[0,0]^2, the QRCP's truncation.
+//   3. after each panel, S -= Rp^T Rp over the panel's rows Rp (matrix cores);
+//      rows and columns already pivoted change too but are not read again.
+// State at hv + 3 c^2: d (c doubles), then CH_N doubles; the pivot order, kk
+// and the dropped part go where the QR route's mode 5 leaves them.
+constexpr int GT_T = 256;                    // threads per Gram tile work-group
+constexpr int GT_KC = 64;                    // K chunk of a tile in LDS
+constexpr int GT_LDK = GT_KC + 1;
+constexpr int CHB = 16;                      // pivots per Cholesky panel
+enum { CH_J = 0, CH_DONE, CH_R00SQ, CH_STOP, CH_N };
+typedef double gt_f64x4 __attribute__((ext_vector_type(4)));
+
+// t-th tile (ti, tj), ti <= tj, of the upper triangle, column of tiles by column
+__device__ inline void upper_tile(int t, int& ti, int& tj) {
+    int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    while (j * (j + 1) / 2 > t) --j;
+    tj = j;
+    ti = t - j * (j + 1) / 2;
+}
+
+// CHOL false: S = Bw^T Bw; true: S -= Rp^T Rp for the panel of rows J0 .. CH_J
+// of the task's transposed R.  Operand layout of v_mfma_f64_16x16x4f64 (lane l):
+// A[l % 16][k + l / 16], B[k + l / 16][l % 16], D[l / 16 + 4 v][l % 16].
+template <bool CHOL>
+__global__ __launch_bounds__(GT_T) void k_gram_tile(const DCompress* __restrict__ tasks, int J0) {
+    const DCompress T = tasks[blockIdx.y];
+    const int M = T.M, c = T.c;
+    if (M == 0 || c == 0) return;
+    int ti, tj;
+    upper_tile(blockIdx.x, ti, tj);
+    if (tj * 32 >= c) return;
+    double* S = T.hv + 2 * (size_t)c * c;
+    const double* A;
+    int64_t lda;
+    int k0, k1;
+    if (!CHOL) {
+        A = T.Bw; lda = M; k0 = 0; k1 = M;            // A(k, i) = Bw[k + i M]
+    } else {
+        const double* st = T.hv + 3 * (size_t)c * c + c;
+        if (st[CH_DONE] != 0.0) return;               // stopped: S is not read again
+        A = T.hv; lda = c; k0 = J0; k1 = (int)st[CH_J];   // A(k, i) = Rt[i + k c]
+        if (k1 <= k0) return;
+    }
+    __shared__ double As[32 * GT_LDK], Bs[32 * GT_LDK];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int iq = w & 1, jq = w >> 1;
+    const int i0 = ti * 32, j0 = tj * 32;
+    gt_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = k0; kb < k1; kb += GT_KC) {
+        const int kc = min(GT_KC, k1 - kb);
+        const int kp = (kc + 3) & ~3;
+        __syncthreads();                              // the previous chunk is consumed
+        if (!CHOL) {                                  // lanes along K (contiguous)
+            const int t = tid % WAVE;
+            for (int a = tid / WAVE; a < 32; a += GT_T / WAVE) {
+                const bool ok = t < kc;
+                As[a * GT_LDK + t] = ok && i0 + a < c ? A[(kb + t) + (int64_t)(i0 + a) * lda] : 0.0;
+                Bs[a * GT_LDK + t] = ok && j0 + a < c ? A[(kb + t) + (int64_t)(j0 + a) * lda] : 0.0;
+            }
+        } else {                                      // lanes along the columns (contiguous)
+            const int a = tid % 32;
+            for (int t = tid / 32; t < GT_KC; t += GT_T / 32) {
+                const bool ok = t < kc;
+                As[a * GT_LDK + t] = ok && i0 + a < c ? A[(i0 + a) + (int64_t)(kb + t) * lda] : 0.0;
+                Bs[a * GT_LDK + t] = ok && j0 + a < c ? A[(j0 + a) + (int64_t)(kb + t) * lda] : 0.0;
+            }
+        }
+        __syncthreads();
+        const double* ap = As + (iq * 16 + lane % 16) * GT_LDK + lane / 16;
+        const double* bp = Bs + (jq * 16 + lane % 16) * GT_LDK + lane / 16;
+        for (int k = 0; k < kp; k += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], bp[k], acc, 0, 0, 0);
+    }
+    const int j = j0 + jq * 16 + lane % 16;
+    if (j >= c) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = i0 + iq * 16 + lane / 16 + 4 * v;
+        if (i >= c) continue;
+        double* g = S + i + (int64_t)j * c;
+        const double val = CHOL ? *g - acc[v] : acc[v];
+        *g = val;
+        if (ti != tj) S[j + (int64_t)i * c] = val;
+    }
+}
+
+// One panel of the pivoted Cholesky (step 2 above), a work-group per task.
+__global__ __launch_bounds__(NTL) void k_chol_panel(const DCompress* __restrict__ tasks, int J0, double trunc_rel) {
+    const DCompress T = tasks[blockIdx.x];
+    const int M = T.M, c = T.c, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    if (M == 0 || c == 0 || J0 >= c) return;
+    double* Rt = T.hv;                                  // Rt[i + J c] = R(J, i)
+    const double* S = T.hv + 2 * (size_t)c * c;
+    double* d = T.hv + 3 * (size_t)c * c;
+    double* st = d + c;
+    double* hst = T.hv + 4 * (size_t)c * c;             // pivot order (c), then the header
+    double* hdr = hst + c;
+    extern __shared__ double sl[];
+    double* s_d = sl;                                   // remaining diagonal, by original column
+    int* s_perm = reinterpret_cast<int*>(s_d + c);      // position -> original column
+    __shared__ double s_pv[NWL], s_pt[NWL];
+    __shared__ int s_pi[NWL], s_pq[NWL];
+    double stop, r00sq;
+    if (J0 == 0) {
+        double tr = 0.0;
+        for (int i = tid; i < c; i += NTL) {
+            const double g = S[i + (int64_t)i * c];
+            s_d[i] = g;
+            s_perm[i] = i;
+            tr += g;
+        }
+        tr = blk_sum_l(tr, s_pv);                       // barriers inside
+        stop = 1.1102230246251565e-16 * (double)c * tr;
+        r00sq = 0.0;
+    } else {
+        if (st[CH_DONE] != 0.0) return;                 // uniform
+        for (int i = tid; i < c; i += NTL) {
+            s_d[i] = d[i];
+            s_perm[i] = (int)hst[i];
+        }
+        stop = st[CH_STOP];
+        r00sq = st[CH_R00SQ];
+    }
+    __syncthreads();
+    const double trunc = trunc_rel * T.eps;
+    bool done = false;
+    double rest2 = 0.0;
+    int J = J0;
+    for (; J < J0 + CHB && J < c; ++J) {
+        // largest remaining diagonal (lowest original column on ties), and the sum
+        double bv = -1.0, tot = 0.0;
+        int bi = INT_MAX, bq = 0;
+        for (int q = J + tid; q < c; q += NTL) {
+            const int i = s_perm[q];
+            const double v = s_d[i];
+            tot += v;
+            if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; bq = q; }
+        }
+        tot = wave_sum(tot);
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o), oq = __shfl_xor(bq, o);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; bq = oq; }
+        }
+        if (lane == 0) { s_pv[wv] = bv; s_pi[wv] = bi; s_pq[wv] = bq; s_pt[wv] = tot; }
+        __syncthreads();
+        bv = -1.0; bi = INT_MAX; bq = 0; tot = 0.0;
+        for (int k = 0; k < NWL; ++k) {                 // every thread, same order
+            tot += s_pt[k];
+            if (s_pv[k] > bv || (s_pv[k] == bv && s_pi[k] < bi)) { bv = s_pv[k]; bi = s_pi[k]; bq = s_pq[k]; }
+        }
+        if (J == 0) r00sq = bv;
+        if (!(bv > stop) || tot <= trunc * trunc * r00sq) {   // uniform
+            done = true;
+            rest2 = tot;
+            break;
+        }
+        __syncthreads();                                // the partials and s_perm are read
+        if (tid == 0) { s_perm[bq] = s_perm[J]; s_perm[J] = bi; }
+        __syncthreads();
+        const int p = bi;
+        const double rpp = sqrt(bv);
+        for (int q = tid; q < c; q += NTL) {
+            const int i = s_perm[q];
+            double r;
+            if (q < J) r = 0.0;
+            else if (q == J) r = rpp;
+            else {
+                double v = S[i + (int64_t)p * c];
+                for (int k = J0; k < J; ++k) v -= Rt[i + (int64_t)k * c] * Rt[p + (int64_t)k * c];
+                r = v / rpp;
+                s_d[i] -= r * r;
+            }
+            Rt[i + (int64_t)J * c] = r;
+        }
+        __syncthreads();                                // row J and d are complete
+    }
+    for (int i = tid; i < c; i += NTL) {
+        d[i] = s_d[i];
+        hst[i] = (double)s_perm[i];
+    }
+    if (tid == 0) {
+        st[CH_J] = (double)J;
+        if (J0 == 0) { st[CH_STOP] = stop; st[CH_R00SQ] = r00sq; }
+        const bool fin = done || J >= c;
+        st[CH_DONE] = fin ? 1.0 : 0.0;
+        if (fin) {
+            hdr[LH_KK] = (double)J;
+            hdr[LH_REST2] = done ? rest2 : 0.0;
+        }
+    }
 }
 
 // LDS of k_compress_large in bytes, or 0 when the task does not fit
@@ -3147,6 +3375,12 @@ hipError_t launch_rand_finish(const DCompress* t, const DRand* rt, const DCompre
     return hipGetLastError();
 }
 
+template <int mode>
+static void launch_large_mode(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                              double trunc_rel, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_compress_large<mode>, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel);
+}
+
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
                                  int max_M, double trunc_rel, int mode, hipStream_t st) {
     if (n == 0) return hipSuccess;
@@ -3154,27 +3388,64 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
     if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
     static std::atomic<bool> attr{false};
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_compress_large, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kLdsBudget);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_large_round, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBudget);
+        hipError_t e = hipSuccess;
+        for (const void* f : {(const void*)k_compress_large<0>, (const void*)k_compress_large<2>,
+                              (const void*)k_compress_large<4>, (const void*)k_compress_large<5>,
+                              (const void*)k_compress_large<6>, (const void*)k_compress_large<7>,
+                              (const void*)k_compress_large<8>, (const void*)k_compress_large<9>,
+                              (const void*)k_large_round})
+            if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_compress_large, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel, mode);
+    switch (mode) {
+    case 0: launch_large_mode<0>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 2: launch_large_mode<2>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 4: launch_large_mode<4>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 5: launch_large_mode<5>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 6: launch_large_mode<6>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 7: launch_large_mode<7>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 8: launch_large_mode<8>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 9: launch_large_mode<9>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, int which, hipStream_t st) {
+hipError_t launch_gram_chol(const DCompress* t, int n, int max_c, double trunc_rel, hipStream_t st) {
     if (n == 0) return hipSuccess;
+    const size_t lds = (size_t)max_c * (sizeof(double) + sizeof(int));
+    if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
+    static std::atomic<bool> attr{false};
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBudget);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int ntile = (max_c + 31) / 32, npair = ntile * (ntile + 1) / 2;
+    hipLaunchKernelGGL(k_gram_tile<false>, dim3(npair, n), dim3(GT_T), 0, st, t, 0);
+    hipError_t e = hipGetLastError();
+    for (int J0 = 0; J0 < max_c && e == hipSuccess; J0 += CHB) {
+        hipLaunchKernelGGL(k_chol_panel, dim3(n), dim3(NTL), lds, st, t, J0, trunc_rel);
+        e = hipGetLastError();
+        if (e == hipSuccess && J0 + CHB < max_c) {
+            hipLaunchKernelGGL(k_gram_tile<true>, dim3(npair, n), dim3(GT_T), 0, st, t, J0);
+            e = hipGetLastError();
+        }
+    }
+    return e;
+}
+
+template <int which>
+static hipError_t qr_blocked(const DCompress* t, int n, int max_c, int max_M, hipStream_t st) {
     const int nrmax = which == 0 ? max_M : max_c;             // rows of the matrix factored
     const size_t lds = (size_t)(nrmax + 1) * sizeof(double);
     if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
     static std::atomic<bool> attr{false};
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_qr_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kLdsBudget);
+    if (which != 2 && !attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_qr_panel<which == 2 ? 0 : which>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
         if (e != hipSuccess) return e;
         attr = true;
     }
@@ -3182,20 +3453,30 @@ hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, in
     const int npanel = (kqmax + QB - 1) / QB;
     for (int p = 0; p < npanel; ++p) {
         const int j0 = (which == 2 ? npanel - 1 - p : p) * QB;   // Q2: last panel first
-        if (which != 2) {
-            hipLaunchKernelGGL(k_qr_panel, dim3(n), dim3(NTL), lds, st, t, j0, which);
+        if constexpr (which != 2) {
+            hipLaunchKernelGGL(k_qr_panel<which>, dim3(n), dim3(NTL), lds, st, t, j0);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         // columns the panel changes (a task's panel may be narrower than QB)
         const int nchunk = (max_c - j0 + QB - 1) / QB;
         if (nchunk > 0) {
-            hipLaunchKernelGGL(k_qr_update, dim3(nchunk, n), dim3(NTL), 0, st, t, j0, which);
+            hipLaunchKernelGGL(k_qr_update<which>, dim3(nchunk, n), dim3(NTL), 0, st, t, j0);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
     }
     return hipSuccess;
+}
+
+hipError_t launch_qr_blocked(const DCompress* t, int n, int max_c, int max_M, int which, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    switch (which) {
+    case 0: return qr_blocked<0>(t, n, max_c, max_M, st);
+    case 1: return qr_blocked<1>(t, n, max_c, max_M, st);
+    case 2: return qr_blocked<2>(t, n, max_c, max_M, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st) {

@@ -66,6 +66,13 @@ void free_pin(void* q) {
     std::shared_lock<std::shared_mutex> lk(g_capture_mu);
     (void)hipHostFree(q);
 }
+// Synchronous copies run on the null stream, which the runtime refuses while a
+// blocking stream captures (the serving scheduler factors in one thread while
+// another captures its solve graph): they wait for the capture as well.
+hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    std::shared_lock<std::shared_mutex> lk(g_capture_mu);
+    return hipMemcpy(dst, src, bytes, kind);
+}
 
 // --------------------------------------------------------------- device memory
 // Device and pinned host blocks the library releases are kept for reuse: one
@@ -404,7 +411,7 @@ struct Tune {
     int32_t compress_nt_mid = 1024;     // threads per stacked block of 33..64 columns
     int32_t gemm_grid = 0;          // persistent grid of the MFMA products (0: a work-group per tile)
     int32_t solve_graph = 1;        // 1: GMRES replays its preconditioner as a captured HIP graph
-    int32_t compress_gram = 1;      // 1: mixed-precision small blocks through the FP64 Gram matrix
+    int32_t compress_gram = 1;      // 1: mixed-precision compression through the FP64 Gram matrix
 };
 Tune g_tune;
 }  // namespace
@@ -441,6 +448,7 @@ struct lrx_handle_s {
     // stats
     lrx_stats_t stats{};
     std::vector<int32_t> ranks, rank_level, rank_j;
+    std::vector<int32_t> comp_rows, comp_cols;   // stored stacked rows M and columns c per compression
     std::vector<double> tails;          // per compression: |R11|, ||R22||_F for k = 0..r
     std::vector<int64_t> tail_off;
     double max_tail_ratio = 0.0;
@@ -709,11 +717,11 @@ void FactorRun::setup(const lrx_csr* A, const double* val_dev, hipStream_t st) {
     if (A->nnz > 0) {
         // the driver synchronizes before these temporaries are released
         d_idx.ensure(idx.size() * 8);
-        HIPCHK(hipMemcpy(d_idx.p, idx.data(), idx.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(copy_sync(d_idx.p, idx.data(), idx.size() * 8, hipMemcpyHostToDevice));
         const double* src = val_dev;
         if (!src) {
             d_val.ensure((size_t)A->nnz * 8);
-            HIPCHK(hipMemcpy(d_val.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice));
+            HIPCHK(copy_sync(d_val.p, A->val, (size_t)A->nnz * 8, hipMemcpyHostToDevice));
             src = d_val.as<double>();
         }
         HIPCHK(launch_scatter(base, d_idx.as<int64_t>(), src, A->nnz, st));
@@ -863,6 +871,8 @@ void FactorRun::take_ranks(const int32_t* rk, const double* tails_h, hipStream_t
         }
         h->max_tail_ratio = std::max(h->max_tail_ratio, ratio);
         h->rank_level.push_back(cs.level);
+        h->comp_rows.push_back(T.M);
+        h->comp_cols.push_back(T.c);
         h->rank_j.push_back(ns.j);
         // flops of the stacked QR and the Jacobi SVD (sweeps reported by the
         // kernel after the c + 1 singular-value slots), or of the pivoted QR
@@ -1187,9 +1197,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             // for tall blocks, M c >= 3e5: the tall QR in multi-work-group panels,
             // the rest in one work-group; 10 / 11 for c > 192 or M c >= 1e6: QRs in
             // panels and the Jacobi in multi-work-group block rounds; key 2 when the
-            // LDS of the large kernel does not fit), pivoted QR (key 4), randomized
-            // range finder with c <= 64 (20: FP64 sketch, 21: BF16 sketch); each
-            // task takes its own variant whatever the others are
+            // LDS of the large kernel does not fit; 26 / 27 and 28 / 29: R1 through
+            // the FP64 Gram matrix and its pivoted Cholesky, then as 12 / 13 and
+            // 10 / 11), pivoted QR (key 4), randomized range finder with c <= 64
+            // (20: FP64 sketch, 21: BF16 sketch); each task takes its own variant
+            // whatever the others are
             struct Group {
                 int key; std::vector<DCompress> t; std::vector<int> q;
                 int max_c = 1, max_M = 1; double fl = 0, by = 0; size_t off = 0;
@@ -1205,10 +1217,15 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 } else if (all[q].c <= 64) key = (fp32_of[q] & 1) | (all[q].c > 32 ? 16 : 0);
                 else if (compress_large_fits(all[q].M, all[q].c)) {
                     const int64_t mc = (int64_t)all[q].M * all[q].c;
+                    const bool split = all[q].c > 192 || mc >= 1000000;
                     // (odd keys drop pivoted-QR rows below epsilon / 100 relative to
                     // sigma_0: not under the absolute threshold of the Frobenius rule)
-                    key = (all[q].c > 192 || mc >= 1000000 ? 10 : mc >= 300000 ? 12 : 8) |
-                          ((fp32_of[q] & 1) && !all[q].tau ? 1 : 0);
+                    const int drop = (fp32_of[q] & 1) && !all[q].tau ? 1 : 0;
+                    if ((fp32_of[q] & 16) && !all[q].tau) {
+                        key = (split ? 28 : 26) | drop;  // R1 from the Gram matrix
+                        owner[q].first->gram_task[owner[q].second] = 1;
+                    } else
+                        key = (split ? 10 : mc >= 300000 ? 12 : 8) | drop;
                 } else key = 2;
                 size_t g = 0;
                 while (g < groups.size() && groups[g].key != key) ++g;
@@ -1223,7 +1240,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 const double M = all[q].M, cc = all[q].c;
                 if (M > 0 && cc > 0 && key < 20)     // (randomized: counted per sketch width)
                     G.fl += key == 4 ? 4.0 * M * cc * cc : qr_flops(M, cc) + svd_pre_flops(cc);
-                else if (M > 0 && cc > 0 && (key == 24 || key == 25))
+                else if (M > 0 && cc > 0 && key >= 24 && key <= 29)
                     G.fl += M * cc * (cc + 1.0) + cc * cc * cc / 3.0 + svd_pre_flops(cc) * 2.0 / 3.0;
                 G.by += 8.0 * M * cc;        // the stacked pieces, read once (V is added after the read-back)
             }
@@ -1326,26 +1343,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 };
                 auto run_group = [&](Group& G, hipStream_t gs) {
                     const DCompress* dt = (const DCompress*)(d_desc_c.as<char>() + G.off);
-                    LaunchTimer tm(G.key == 24 || G.key == 25 ? LRX_K_COMPRESS_GRAM : LRX_K_COMPRESS, gs, G.by, G.fl);
-                    if (G.key == 4)
-                        HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, gs));
-                    else if (G.key == 8 || G.key == 9) {
-                        HIPCHK(launch_compress_large(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
-                                                     (G.key & 1) ? 0.01 : 0.0, 0, gs));
-                    } else if (G.key == 12 || G.key == 13) {
-                        const int nt = (int)G.t.size();
-                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
-                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 7, gs));
-                    } else if (G.key == 10 || G.key == 11) {
-                        // QRs, then sweeps of block-Jacobi rounds over all tasks until
-                        // none rotates, then the singular values and V
-                        const int nt = (int)G.t.size();
-                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
-                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, gs));
+                    LaunchTimer tm(G.key >= 24 && G.key <= 29 ? LRX_K_COMPRESS_GRAM : LRX_K_COMPRESS, gs, G.by, G.fl);
+                    // after the state mode 5 (or 8) leaves: the LQ and Q2 in panels, then
+                    // sweeps of block-Jacobi rounds over all tasks until none rotates,
+                    // then the singular values and V
+                    auto split_rest = [&](const DCompress* dt, int nt, double trunc) {
                         HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 1, gs));
                         HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 2, gs));
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 6, gs));
@@ -1365,6 +1367,37 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                             if (!go) break;
                         }
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 2, gs));
+                    };
+                    if (G.key == 4)
+                        HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, gs));
+                    else if (G.key == 8 || G.key == 9) {
+                        HIPCHK(launch_compress_large(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
+                                                     (G.key & 1) ? 0.01 : 0.0, 0, gs));
+                    } else if (G.key == 12 || G.key == 13) {
+                        const int nt = (int)G.t.size();
+                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 7, gs));
+                    } else if (G.key == 10 || G.key == 11) {
+                        const int nt = (int)G.t.size();
+                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, gs));
+                        split_rest(dt, nt, trunc);
+                    } else if (G.key >= 26 && G.key <= 29) {
+                        // Gram matrix and pivoted Cholesky for R1; the rest in one
+                        // work-group per task (26, 27) or split as above (28, 29)
+                        const int nt = (int)G.t.size();
+                        const double trunc = (G.key & 1) ? 0.01 : 0.0;
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_gram_chol(dt, nt, G.max_c, trunc, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 8, gs));
+                        if (G.key < 28)
+                            HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 9, gs));
+                        else
+                            split_rest(dt, nt, trunc);
                     } else if (G.key == 20 || G.key == 21) {
                         run_rand(G.t, G.q, G.key & 1, gs);
                     } else if (G.key == 24 || G.key == 25) {
@@ -1379,7 +1412,9 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                                                    G.key >= 16 ? g_tune.compress_nt_mid : g_tune.compress_nt_small,
                                                    gs));
                 };
-                auto host_driven = [](int key) { return key == 10 || key == 11 || key == 20 || key == 21; };
+                auto host_driven = [](int key) {
+                    return key == 10 || key == 11 || key == 20 || key == 21 || key == 28 || key == 29;
+                };
                 std::vector<hipStream_t> gsv(groups.size(), st);
                 AuxStreams* ax = groups.size() > 1 ? aux_streams() : nullptr;
                 bool used[2] = {false, false};
@@ -1499,7 +1534,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
     }
     sync();
     std::vector<int32_t> info(std::max(info_total, 1));
-    HIPCHK(hipMemcpy(info.data(), d_info.p, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(copy_sync(info.data(), d_info.p, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < runs.size(); ++i) {
         FactorRun& r = *runs[i];
         for (int32_t q = 0; q < r.info_count; ++q)
@@ -1513,7 +1548,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
         r.h->stats.flops_project = r.fl_project;
         if (r.frob) {
             double st_h[35];
-            HIPCHK(hipMemcpy(st_h, r.d_norm.p, sizeof(st_h), hipMemcpyDeviceToHost));
+            HIPCHK(copy_sync(st_h, r.d_norm.p, sizeof(st_h), hipMemcpyDeviceToHost));
             for (int lv = 0; lv < 32 && lv <= r.P.depth; ++lv) r.h->stats.level_norm_by_level[lv] = st_h[2 + lv];
         }
         r.h->t_sync_ms += t_sync;
@@ -1592,7 +1627,7 @@ void build_solve_program(lrx_handle h) {
         DevBuf dsegs;
         dsegs.ensure(std::max<size_t>(segs.size(), 1) * sizeof(DConv));
         if (!segs.empty()) {
-            HIPCHK(hipMemcpy(dsegs.p, segs.data(), segs.size() * sizeof(DConv), hipMemcpyHostToDevice));
+            HIPCHK(copy_sync(dsegs.p, segs.data(), segs.size() * sizeof(DConv), hipMemcpyHostToDevice));
             HIPCHK(launch_to_f32(dsegs.as<DConv>(), (int)segs.size(), h->stream));
         }
         HIPCHK(hipStreamSynchronize(h->stream));      // dsegs is released at scope end
@@ -1706,13 +1741,13 @@ void build_solve_program(lrx_handle h) {
     h->d_swnodes.ensure(std::max<size_t>(2 * nn, 1) * sizeof(SwNode));
     h->d_swprog.ensure(std::max<size_t>(words.size(), 1) * sizeof(int32_t));
     if (!words.empty())
-        HIPCHK(hipMemcpy(h->d_swprog.p, words.data(), words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(copy_sync(h->d_swprog.p, words.data(), words.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     h->sw_host.resize(2 * nn);
     for (size_t i = 0; i < 2 * nn; ++i)
         h->sw_host[i] = SwNode{h->d_swprog.as<int32_t>() + both[i].desc, nullptr, nullptr, both[i].words0,
                               both[i].nstage};
     if (nn)
-        HIPCHK(hipMemcpy(h->d_swnodes.p, h->sw_host.data(), h->sw_host.size() * sizeof(SwNode),
+        HIPCHK(copy_sync(h->d_swnodes.p, h->sw_host.data(), h->sw_host.size() * sizeof(SwNode),
                          hipMemcpyHostToDevice));
     for (size_t si = 0; si < P.steps.size(); ++si) {
         h->ssteps[si].height = P.depth - P.steps[si].level;
@@ -1835,8 +1870,8 @@ void solve_batch_dev(int k, const lrx_handle* hs, int nrhs, const double* const*
     h0->batch_nodes.ensure(std::max<size_t>(2 * nf.size(), 1) * sizeof(SwNode));
     SwNode* dn = h0->batch_nodes.as<SwNode>();
     if (!nf.empty()) {
-        HIPCHK(hipMemcpy(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+        HIPCHK(copy_sync(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+        HIPCHK(copy_sync(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
     }
     for (int i = 0; i < k; ++i) {
         const lrx_handle h = hs[i];
@@ -1950,9 +1985,9 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
     const size_t o_ch = ((size_t)K * sizeof(DKry) + 255) & ~(size_t)255;
     const size_t o_act = (o_ch + chunks.size() * sizeof(DKryChunk) + 255) & ~(size_t)255;
     h0->kry_tab.ensure(o_act + (size_t)K * 4);
-    HIPCHK(hipMemcpy(h0->kry_tab.p, sys.data(), (size_t)K * sizeof(DKry), hipMemcpyHostToDevice));
+    HIPCHK(copy_sync(h0->kry_tab.p, sys.data(), (size_t)K * sizeof(DKry), hipMemcpyHostToDevice));
     if (!chunks.empty())
-        HIPCHK(hipMemcpy(h0->kry_tab.as<char>() + o_ch, chunks.data(), chunks.size() * sizeof(DKryChunk),
+        HIPCHK(copy_sync(h0->kry_tab.as<char>() + o_ch, chunks.data(), chunks.size() * sizeof(DKryChunk),
                          hipMemcpyHostToDevice));
     int32_t* act_dev = (int32_t*)(h0->kry_tab.as<char>() + o_act);
     // pinned mirror: scalars of every system, then act
@@ -2008,8 +2043,8 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
     h0->batch_nodes.ensure(std::max<size_t>(2 * nf.size(), 1) * sizeof(SwNode));
     SwNode* dn = h0->batch_nodes.as<SwNode>();
     if (!nf.empty()) {
-        HIPCHK(hipMemcpy(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+        HIPCHK(copy_sync(dn, nf.data(), nf.size() * sizeof(SwNode), hipMemcpyHostToDevice));
+        HIPCHK(copy_sync(dn + nf.size(), nb.data(), nb.size() * sizeof(SwNode), hipMemcpyHostToDevice));
     }
     auto sweep_launches = [&](bool timed) {
         for (size_t q = 0; q + 1 < k0f.size(); ++q)
@@ -2275,7 +2310,7 @@ void check_symmetric(const lrx_csr* A, const double* val_dev) {
     const double* v = A->val;
     if (val_dev) {
         vh.resize((size_t)A->nnz);
-        if (A->nnz) HIPCHK(hipMemcpy(vh.data(), val_dev, (size_t)A->nnz * 8, hipMemcpyDeviceToHost));
+        if (A->nnz) HIPCHK(copy_sync(vh.data(), val_dev, (size_t)A->nnz * 8, hipMemcpyDeviceToHost));
         v = vh.data();
     }
     for (int32_t r = 0; r < A->n; ++r)
@@ -2420,6 +2455,8 @@ void finish_stats(lrx_handle h, double t_plan_ms, double t_factor_ms) {
     S.t_solve_prog_ms = h->t_solve_prog_ms;
 }
 
+constexpr int kPlanThreads = 8;
+
 // Factorization of k systems (k = 1: lrx_factor); see lrx_factor_batch.
 void factor_many(int32_t k, const lrx_csr* A, const double* const* val_dev, const lrx_tree* T, const lrx_opts* o,
                  lrx_handle* out) {
@@ -2443,8 +2480,9 @@ void factor_many(int32_t k, const lrx_csr* A, const double* const* val_dev, cons
             for (int32_t i; (i = next.fetch_add(1)) < k;) {
                 const double ta = now_ms();
                 try {
+                    // one system: its planner spreads the leaf phases over host threads
                     errs[i] = build_plan(A[i].n, A[i].nnz, A[i].row_ptr, A[i].col_idx, T[i].depth, T[i].perm,
-                                         T[i].leaf_ptr, o->order, hs[i]->plan);
+                                         T[i].leaf_ptr, o->order, hs[i]->plan, k == 1 ? kPlanThreads : 1);
                 } catch (const std::exception& e) {
                     errs[i] = std::string("planner: ") + e.what();
                 }
@@ -2515,7 +2553,7 @@ lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order, 
         if (A->n < 1 || A->nnz < 0 || !A->row_ptr || !A->col_idx) fail(LRX_EINVAL, "bad CSR");
         Plan P;
         std::string err = build_plan(A->n, A->nnz, A->row_ptr, A->col_idx, T->depth, T->perm,
-                                     T->leaf_ptr, order, P);
+                                     T->leaf_ptr, order, P, kPlanThreads);
         if (!err.empty()) fail(LRX_EINVAL, err);
         std::memset(info, 0, sizeof(*info));
         info->depth = P.depth;
@@ -2822,6 +2860,16 @@ lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t
         const int64_t b = (idx + 1 < (int32_t)h->tail_off.size()) ? h->tail_off[idx + 1] : (int64_t)h->tails.size();
         *len = (int32_t)(b - a);
         if (out) for (int64_t i = a; i < b && i - a < cap; ++i) out[i - a] = h->tails[i];
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_compression_shape(lrx_handle h, int32_t idx, int32_t* rows, int32_t* cols) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (idx < 0 || idx >= (int32_t)h->ranks.size() || !rows || !cols) fail(LRX_EINVAL, "bad compression index");
+        *rows = h->comp_rows[idx];
+        *cols = h->comp_cols[idx];
         return LRX_OK;
     });
 }

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <numeric>
+#include <thread>
 #include <utility>
 
 namespace lrx {
@@ -158,11 +159,22 @@ struct Builder {
     }
 };
 
+// fn(t, nt) on nt host threads (t = 0 on the calling thread)
+template <class Fn>
+void on_threads(int nt, Fn&& fn) {
+    if (nt <= 1) { fn(0, 1); return; }
+    std::vector<std::thread> th;
+    th.reserve((size_t)nt - 1);
+    for (int t = 1; t < nt; ++t) th.emplace_back([&fn, t, nt]() { fn(t, nt); });
+    fn(0, nt);
+    for (auto& x : th) x.join();
+}
+
 }  // namespace
 
 std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                        int32_t depth, const int32_t* perm, const int32_t* leaf_ptr,
-                       int32_t order, Plan& P) {
+                       int32_t order, Plan& P, int nthreads) {
     char msg[256];
     if (n < 1) return "n must be >= 1";
     if (depth < 1 || depth > 30) return "depth must be in [1, 30]";
@@ -170,14 +182,31 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
     if (nleaf > n) return "more leaves than rows (2^depth > n)";
     if (!row_ptr || !col_idx || !perm || !leaf_ptr) return "null CSR or tree array";
     if (row_ptr[0] != 0 || row_ptr[n] != nnz) return "row_ptr[0] must be 0 and row_ptr[n] = nnz";
-    for (int32_t r = 0; r < n; ++r) {
-        if (row_ptr[r + 1] < row_ptr[r]) return "row_ptr is not non-decreasing";
-        for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-            int32_t c = col_idx[e];
-            if (c < 0 || c >= n) { snprintf(msg, sizeof msg, "column index out of range in row %d", r); return msg; }
-            if (e > row_ptr[r] && col_idx[e - 1] >= c) {
-                snprintf(msg, sizeof msg, "columns not sorted/unique in row %d", r); return msg;
+    // the rows in nt ranges; the error of the lowest row is reported
+    const int nt = n >= 8192 ? std::max(1, nthreads) : 1;
+    {
+        std::vector<int32_t> bad_row(nt, -1);
+        std::vector<int> bad_kind(nt, 0);
+        on_threads(nt, [&](int t, int T) {
+            const int32_t r0 = (int32_t)((int64_t)n * t / T), r1 = (int32_t)((int64_t)n * (t + 1) / T);
+            for (int32_t r = r0; r < r1; ++r) {
+                int kind = 0;
+                if (row_ptr[r + 1] < row_ptr[r]) kind = 1;
+                else
+                    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+                        const int32_t c = col_idx[e];
+                        if (c < 0 || c >= n) { kind = 2; break; }
+                        if (e > row_ptr[r] && col_idx[e - 1] >= c) { kind = 3; break; }
+                    }
+                if (kind) { bad_row[t] = r; bad_kind[t] = kind; return; }
             }
+        });
+        for (int t = 0; t < nt; ++t) {
+            if (bad_row[t] < 0) continue;
+            if (bad_kind[t] == 1) return "row_ptr is not non-decreasing";
+            snprintf(msg, sizeof msg, bad_kind[t] == 2 ? "column index out of range in row %d"
+                                                       : "columns not sorted/unique in row %d", bad_row[t]);
+            return msg;
         }
     }
     if (order != 0 && order != 1) return "order must be LRX_COLORED or LRX_NATURAL";
@@ -212,19 +241,25 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
     {
         // distinct pairs of leaf clusters joined by an entry of A, found cluster
         // by cluster (rows of a cluster are consecutive tree positions)
-        std::vector<std::pair<int32_t, int32_t>> lp;
-        std::vector<int32_t> seen((size_t)nleaf, -1);
-        for (int32_t a = 0; a < (int32_t)nleaf; ++a) {
-            for (int32_t t = leaf_ptr[a]; t < leaf_ptr[a + 1]; ++t) {
-                const int32_t r = perm[t];
-                for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-                    const int32_t b = leaf_of[P.pos[col_idx[e]]];
-                    if (b == a || seen[b] == a) continue;
-                    seen[b] = a;
-                    lp.push_back({std::min(a, b), std::max(a, b)});
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> lpt(nt);
+        on_threads(nt, [&](int th, int T) {
+            std::vector<int32_t> seen((size_t)nleaf, -1);
+            auto& lp = lpt[th];
+            const int32_t a0 = (int32_t)(nleaf * th / T), a1 = (int32_t)(nleaf * (th + 1) / T);
+            for (int32_t a = a0; a < a1; ++a) {
+                for (int32_t t = leaf_ptr[a]; t < leaf_ptr[a + 1]; ++t) {
+                    const int32_t r = perm[t];
+                    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+                        const int32_t b = leaf_of[P.pos[col_idx[e]]];
+                        if (b == a || seen[b] == a) continue;
+                        seen[b] = a;
+                        lp.push_back({std::min(a, b), std::max(a, b)});
+                    }
                 }
             }
-        }
+        });
+        std::vector<std::pair<int32_t, int32_t>> lp;
+        for (auto& v : lpt) lp.insert(lp.end(), v.begin(), v.end());
         std::sort(lp.begin(), lp.end());
         lp.erase(std::unique(lp.begin(), lp.end()), lp.end());
         B.cadj.assign(l + 1, {});
@@ -259,36 +294,48 @@ std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int
         // are sorted and deduplicated per block; edges are then created in
         // (source, destination) order
         struct Grp { int32_t src, dst; std::vector<int32_t> rows, cols; };
-        std::vector<Grp> grps;
-        grps.reserve((size_t)nsl * 12);
-        std::vector<int32_t> slot(nsl, -1);               // group of a source for the current destination
-        std::vector<int32_t> touched;
-        for (int32_t sd = 0; sd < nsl; ++sd) {
-            const PNode& dn = P.nodes[L0.supers[sd]];
-            touched.clear();
-            for (int32_t lr = 0; lr < dn.static_size; ++lr) {
-                const int32_t r = perm[dn.dof0 + lr];
-                for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
-                    const int32_t tc = P.pos[col_idx[e]];
-                    const int32_t ss = leaf_of[tc] >> 1;
-                    int32_t g = slot[ss];
-                    if (g < 0) {
-                        g = slot[ss] = (int32_t)grps.size();
-                        grps.push_back(Grp{ss, sd, {}, {}});
-                        touched.push_back(ss);
+        std::vector<std::vector<Grp>> grpt(nt);
+        on_threads(nt, [&](int th, int T) {
+            std::vector<Grp>& grps = grpt[th];
+            const int32_t sd0 = (int32_t)((int64_t)nsl * th / T), sd1 = (int32_t)((int64_t)nsl * (th + 1) / T);
+            grps.reserve((size_t)(sd1 - sd0) * 12);
+            std::vector<int32_t> slot(nsl, -1);           // group of a source for the current destination
+            std::vector<int32_t> touched;
+            for (int32_t sd = sd0; sd < sd1; ++sd) {
+                const PNode& dn = P.nodes[L0.supers[sd]];
+                touched.clear();
+                for (int32_t lr = 0; lr < dn.static_size; ++lr) {
+                    const int32_t r = perm[dn.dof0 + lr];
+                    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+                        const int32_t tc = P.pos[col_idx[e]];
+                        const int32_t ss = leaf_of[tc] >> 1;
+                        int32_t g = slot[ss];
+                        if (g < 0) {
+                            g = slot[ss] = (int32_t)grps.size();
+                            grps.push_back(Grp{ss, sd, {}, {}});
+                            touched.push_back(ss);
+                        }
+                        if (ss == sd) continue;                // the pivot block is full
+                        Grp& G = grps[g];
+                        if (G.rows.empty() || G.rows.back() != lr) G.rows.push_back(lr);
+                        G.cols.push_back(tc - P.nodes[L0.supers[ss]].dof0);
                     }
-                    if (ss == sd) continue;                    // the pivot block is full
-                    Grp& G = grps[g];
-                    if (G.rows.empty() || G.rows.back() != lr) G.rows.push_back(lr);
-                    G.cols.push_back(tc - P.nodes[L0.supers[ss]].dof0);
+                }
+                for (int32_t ss : touched) {
+                    Grp& G = grps[slot[ss]];
+                    std::sort(G.cols.begin(), G.cols.end());
+                    G.cols.erase(std::unique(G.cols.begin(), G.cols.end()), G.cols.end());
+                    slot[ss] = -1;
                 }
             }
-            for (int32_t ss : touched) {
-                Grp& G = grps[slot[ss]];
-                std::sort(G.cols.begin(), G.cols.end());
-                G.cols.erase(std::unique(G.cols.begin(), G.cols.end()), G.cols.end());
-                slot[ss] = -1;
-            }
+        });
+        std::vector<Grp> grps;
+        {
+            size_t tot = 0;
+            for (auto& v : grpt) tot += v.size();
+            grps.reserve(tot);
+            for (auto& v : grpt)
+                for (auto& g : v) grps.push_back(std::move(g));
         }
         std::vector<int32_t> order_g(grps.size());
         for (size_t g = 0; g < grps.size(); ++g) order_g[g] = (int32_t)g;

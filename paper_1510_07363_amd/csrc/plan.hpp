@@ -107,9 +107,11 @@ struct Plan {
 };
 
 // Checks the CSR and tree and builds the plan; returns "" or an error message.
+// nthreads > 1: the CSR checks, the leaf-cluster adjacency and the leaf blocks
+// are computed on that many host threads (same plan).
 std::string build_plan(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                        int32_t depth, const int32_t* perm, const int32_t* leaf_ptr,
-                       int32_t order, Plan& out);
+                       int32_t order, Plan& out, int nthreads = 1);
 
 // Position of every element of `sub` inside `sup` (both supports of the same
 // node); empty vector when both are full; the single value -1 when sub is not

@@ -70,3 +70,56 @@ def test_graph_replays_equal_direct_launches(env):
                     A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n))
                     X, B = xg.cpu().numpy().T, bs[i].cpu().numpy().T
                     assert (np.linalg.norm(A @ X - B, axis=0) / np.linalg.norm(B, axis=0) <= TOL).all()
+
+
+def test_capture_beside_factorizations_in_another_thread(env):
+    """A serving process factors in one thread while another solves: the
+    factorization's synchronous host copies (null stream) must wait for a graph
+    capture in progress instead of failing.  Factorizations (host values, so
+    each one copies them) run back to back in a worker thread while this thread
+    runs GMRES calls that each capture their preconditioner; every call
+    succeeds and reaches the true residual."""
+    import threading
+    lx, torch = env
+    csr, n, perm, lp, depth, rng = grid("varcoef2d", 64, 32, 3)
+    A = sp.csr_matrix((csr[2], csr[1], csr[0]), shape=(n, n))
+    fs = torch.cuda.Stream()
+    errors, count = [], [0]
+    stop = threading.Event()
+
+    def factor_loop():
+        try:
+            torch.cuda.set_device(0)
+            while not stop.is_set():
+                F = lx.Factor(*csr, perm, lp, depth, 1e-3, stream=fs.cuda_stream, precision="mixed")
+                F.free()
+                count[0] += 1
+        except Exception as e:                      # reported by the main thread
+            errors.append(e)
+
+    ss = torch.cuda.Stream()
+    base = lx.tune_get()
+    lx.tune_set(solve_graph=1)
+    try:
+        with torch.cuda.stream(ss):
+            F = lx.Factor(*csr, perm, lp, depth, 1e-3, stream=ss.cuda_stream, precision="mixed")
+            b = torch.from_numpy(rng.uniform(-1, 1, (2, n))).to("cuda:0")
+            torch.cuda.synchronize()
+            th = threading.Thread(target=factor_loop)
+            th.start()
+            try:
+                for _ in range(30):
+                    x = torch.zeros_like(b)
+                    its, rr, st = F.gmres_dev(b.data_ptr(), x.data_ptr(), 2, tol=TOL, restart=30, maxit=200)
+                    ss.synchronize()
+                    assert st == lx.LRX_OK and min(its) >= 3
+                    X, B = x.cpu().numpy().T, b.cpu().numpy().T
+                    assert (np.linalg.norm(A @ X - B, axis=0) / np.linalg.norm(B, axis=0) <= TOL).all()
+            finally:
+                stop.set()
+                th.join()
+    finally:
+        lx.tune_set(**base)
+    print(f"{count[0]} factorizations beside 30 captured GMRES calls")
+    assert not errors, errors[0]
+    assert count[0] >= 1
