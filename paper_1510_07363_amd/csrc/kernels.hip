@@ -1526,9 +1526,10 @@ static_assert(LH_N <= 8, "the header has 8 doubles");
 constexpr int KK_BLK = 8;                    // columns per block of the multi-work-group Jacobi
 constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold in LDS (16 x 1150 doubles)
 
-// mode 0: the whole pipeline in this work-group; mode 4: assembly and the scaled copy Bw only; mode 5: after the tall QR of Bw
-// by the panel and update launches, the pivoted QR and A2 (the LQ and Q2 follow
-// as launches); mode 6: from A2 factored and W = Q2 formed, L and the state for
+// mode 0: the whole pipeline in this work-group; mode 5: after the assembly and
+// the scaled copy Bw (launch_assemble_large) and the tall QR of Bw by the panel
+// and update launches, the pivoted QR and A2 (the LQ and Q2 follow as
+// launches); mode 6: from A2 factored and W = Q2 formed, L and the state for
 // the block rounds; mode 2: singular values, rank and V after the block rounds;
 // mode 7: mode 0 from the tall QR of Bw done by the panel and update launches;
 // mode 8: after the Gram matrix and its pivoted Cholesky (launch_gram_chol), A2
@@ -1538,7 +1539,8 @@ constexpr int KK_LDS_MAX = 1150;             // rows of L a block pair may hold 
 template <int mode>
 __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restrict__ tasks,
                                                         const DPiece* __restrict__ pieces,
-                                                        const int32_t* __restrict__ imap, double trunc_rel) {
+                                                        const int32_t* __restrict__ imap, double trunc_rel,
+                                                        double jac_u) {
     const DCompress T = tasks[blockIdx.x];
     const int M = T.M, c = T.c, tid = threadIdx.x;
     const int lane = tid % WAVE, wv = tid / WAVE;
@@ -1619,14 +1621,9 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
     const double inv_scale = ldexp(1.0, -bexp);
     scale = ldexp(1.0, bexp);
-    // ---- 1. tall QR of B / 2^e on the copy Bw (mode 4: the copy only; the QR
-    // then runs as panel and update launches over many work-groups)
+    // ---- 1. tall QR of B / 2^e on the copy Bw
     for (int64_t e = tid; e < (int64_t)M * c; e += NTL) Bw[e] = B[e] * inv_scale;
     __syncthreads();
-    if (mode == 4) {
-        if (tid == 0) hdr[LH_SCALE] = scale;
-        return;
-    }
     for (int j = 0; j < (M < c ? M : c); ++j) {
         double v0;
         hh_step(Bw, M, M, c, j, s_v, s_red, &v0);
@@ -1751,8 +1748,10 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
     // ---- 4. one-sided Jacobi on the kk columns of L; W follows.  Pairs run in
     // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes.
     // In mode 6 it runs here only when L is too tall for the block rounds.
+    // rotation threshold 3.6 jac_u kk (jac_u: FP64 or, in mixed precision, FP32
+    // unit roundoff); the zero-column guard stays at FP64 level
     const double u = 1.1102230246251565e-16;
-    const double tol = 3.6 * u * (double)kk, tol_hi = sqrt(tol);
+    const double tol = 3.6 * jac_u * (double)kk, tol_hi = sqrt(tol);
     double f = 0.0;
     for (int e = tid; e < kk * kk; e += NTL) {
         const double x = X[(e % kk) + (e / kk) * ldc];
@@ -2113,13 +2112,75 @@ __global__ void k_large_flags(const DCompress* __restrict__ tasks, int n, int32_
     out[i] = go;
 }
 
+// ---------------------------------------------------------------- assembly of large stacked blocks
+// B (M x c, column-major, kept for the projection) over many work-groups:
+// zero it, scatter the pieces (a work-group per piece) while the largest |entry|
+// goes to an atomic maximum (non-negative doubles order as their bit patterns),
+// then for the QR route the scaled copy Bw = B / 2^e and the scale in the header
+// (what mode 0 does in one work-group).  The maximum sits in the Cholesky state
+// area (CH_AMAX), which nothing else uses before the Gram matrix is formed.
+constexpr int ASM_T = 256;
+// the Cholesky state of the Gram route (d, then these) at hv + 3 c^2
+enum { CH_J = 0, CH_DONE, CH_R00SQ, CH_STOP, CH_AMAX, CH_N };
+
+__device__ inline unsigned long long* asm_amax(const DCompress& T) {
+    return reinterpret_cast<unsigned long long*>(T.hv + 3 * (size_t)T.c * T.c + T.c + CH_AMAX);
+}
+
+__global__ __launch_bounds__(ASM_T) void k_asm_zero(const DCompress* __restrict__ tasks) {
+    const DCompress T = tasks[blockIdx.y];
+    if (T.M == 0 || T.c == 0) return;
+    const int64_t n = (int64_t)T.M * T.c;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *asm_amax(T) = 0ull;
+    for (int64_t e = (int64_t)blockIdx.x * ASM_T + threadIdx.x; e < n; e += (int64_t)gridDim.x * ASM_T)
+        T.B[e] = 0.0;
+}
+
+__global__ __launch_bounds__(ASM_T) void k_asm_scatter(const DCompress* __restrict__ tasks,
+                                                       const DPiece* __restrict__ pieces,
+                                                       const int32_t* __restrict__ imap) {
+    const DCompress T = tasks[blockIdx.y];
+    if (T.M == 0 || T.c == 0 || (int)blockIdx.x >= T.npieces) return;
+    const DPiece pc = pieces[T.piece0 + blockIdx.x];
+    const int nr = pc.blk.nr, nc = pc.blk.nc, M = T.M;
+    double* __restrict__ B = T.B;
+    double amax = 0.0;
+    for (int e = threadIdx.x; e < nr * nc; e += ASM_T) {
+        const int a = e % nr, b = e / nr;
+        const double v = pc.blk.p[e];
+        amax = fmax(amax, fabs(v));
+        if (!pc.trans) B[(pc.row0 + a) + (int64_t)imap_at(imap, pc.map, b) * M] = v;
+        else           B[(pc.row0 + b) + (int64_t)imap_at(imap, pc.map, a) * M] = v;
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    __shared__ double s_m[ASM_T / WAVE];
+    if (threadIdx.x % WAVE == 0) s_m[threadIdx.x / WAVE] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < ASM_T / WAVE; ++k) amax = fmax(amax, s_m[k]);
+        if (amax > 0.0) atomicMax(asm_amax(T), (unsigned long long)__double_as_longlong(amax));
+    }
+}
+
+__global__ __launch_bounds__(ASM_T) void k_asm_scale(const DCompress* __restrict__ tasks) {
+    const DCompress T = tasks[blockIdx.y];
+    if (T.M == 0 || T.c == 0) return;
+    const double amax = __longlong_as_double((long long)*asm_amax(T));
+    const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
+    const double inv_scale = ldexp(1.0, -bexp);
+    const int64_t n = (int64_t)T.M * T.c;
+    for (int64_t e = (int64_t)blockIdx.x * ASM_T + threadIdx.x; e < n; e += (int64_t)gridDim.x * ASM_T)
+        T.Bw[e] = T.B[e] * inv_scale;
+    if (blockIdx.x == 0 && threadIdx.x == 0) T.hv[4 * (size_t)T.c * T.c + T.c + LH_SCALE] = ldexp(1.0, bexp);
+}
+
 // ---------------------------------------------------------------- large blocks via the Gram matrix
 // R1 and the column order of a stacked block with c > 64 columns from its FP64
 // Gram matrix, in place of the tall QR of Bw and the QRCP of R0 (the LQ, Q2,
 // Jacobi and finish stages follow as on the QR route):
-//   1. G = Bw^T Bw (c x c, both triangles) in the W area, on the matrix cores:
-//      a work-group per 32 x 32 tile of the upper triangle, K (the rows of Bw)
-//      in LDS chunks of GT_KC.
+//   1. G = Bw^T Bw (c x c, both triangles; from B, scaled by 4^-e) in the W
+//      area, on the matrix cores: a work-group per 32 x 32 tile of the upper
+//      triangle, K (the rows of B) in LDS chunks of GT_KC.
 //   2. panels of CHB pivots, a work-group per task: the pivot is the largest
 //      remaining diagonal (lowest column on ties); row J of R over the original
 //      columns is R(J, i) = (S(i, p) - sum of R(J', i) R(J', p) over the
@@ -2137,7 +2198,6 @@ constexpr int GT_T = 256;                    // threads per Gram tile work-group
 constexpr int GT_KC = 64;                    // K chunk of a tile in LDS
 constexpr int GT_LDK = GT_KC + 1;
 constexpr int CHB = 16;                      // pivots per Cholesky panel
-enum { CH_J = 0, CH_DONE, CH_R00SQ, CH_STOP, CH_N };
 typedef double gt_f64x4 __attribute__((ext_vector_type(4)));
 
 // t-th tile (ti, tj), ti <= tj, of the upper triangle, column of tiles by column
@@ -2149,7 +2209,8 @@ __device__ inline void upper_tile(int t, int& ti, int& tj) {
     ti = t - j * (j + 1) / 2;
 }
 
-// CHOL false: S = Bw^T Bw; true: S -= Rp^T Rp for the panel of rows J0 .. CH_J
+// CHOL false: S = B^T B / 4^e (B / 2^e as the QR route's Bw); true: S -= Rp^T Rp
+// for the panel of rows J0 .. CH_J
 // of the task's transposed R.  Operand layout of v_mfma_f64_16x16x4f64 (lane l):
 // A[l % 16][k + l / 16], B[k + l / 16][l % 16], D[l / 16 + 4 v][l % 16].
 template <bool CHOL>
@@ -2164,8 +2225,13 @@ __global__ __launch_bounds__(GT_T) void k_gram_tile(const DCompress* __restrict_
     const double* A;
     int64_t lda;
     int k0, k1;
+    double gscale = 1.0;
     if (!CHOL) {
-        A = T.Bw; lda = M; k0 = 0; k1 = M;            // A(k, i) = Bw[k + i M]
+        // A(k, i) = B[k + i M]; G of B / 2^e, e from the largest |entry| (exact)
+        A = T.B; lda = M; k0 = 0; k1 = M;
+        const double amax = __longlong_as_double((long long)*asm_amax(T));
+        const int bexp = amax > 0.0 ? ilogb(amax) + 1 : 0;
+        gscale = ldexp(1.0, -2 * bexp);
     } else {
         const double* st = T.hv + 3 * (size_t)c * c + c;
         if (st[CH_DONE] != 0.0) return;               // stopped: S is not read again
@@ -2208,7 +2274,7 @@ __global__ __launch_bounds__(GT_T) void k_gram_tile(const DCompress* __restrict_
         const int i = i0 + iq * 16 + lane / 16 + 4 * v;
         if (i >= c) continue;
         double* g = S + i + (int64_t)j * c;
-        const double val = CHOL ? *g - acc[v] : acc[v];
+        const double val = CHOL ? *g - acc[v] : acc[v] * gscale;
         *g = val;
         if (ti != tj) S[j + (int64_t)i * c] = val;
     }
@@ -2242,6 +2308,10 @@ __global__ __launch_bounds__(NTL) void k_chol_panel(const DCompress* __restrict_
         tr = blk_sum_l(tr, s_pv);                       // barriers inside
         stop = 1.1102230246251565e-16 * (double)c * tr;
         r00sq = 0.0;
+        if (tid == 0) {                                 // the scale of B / 2^e
+            const double amax = __longlong_as_double((long long)*asm_amax(T));
+            hdr[LH_SCALE] = ldexp(1.0, amax > 0.0 ? ilogb(amax) + 1 : 0);
+        }
     } else {
         if (st[CH_DONE] != 0.0) return;                 // uniform
         for (int i = tid; i < c; i += NTL) {
@@ -3377,12 +3447,13 @@ hipError_t launch_rand_finish(const DCompress* t, const DRand* rt, const DCompre
 
 template <int mode>
 static void launch_large_mode(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
-                              double trunc_rel, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(k_compress_large<mode>, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel);
+                              double trunc_rel, double jac_u, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_compress_large<mode>, dim3(n), dim3(NTL), lds, st, t, pieces, imap, trunc_rel, jac_u);
 }
 
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
-                                 int max_M, double trunc_rel, int mode, hipStream_t st) {
+                                 int max_M, double trunc_rel, int mode, hipStream_t st, bool jac_f32) {
+    const double jac_u = jac_f32 ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
     if (n == 0) return hipSuccess;
     const size_t lds = compress_large_lds(max_M, max_c);
     if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
@@ -3390,7 +3461,7 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
     if (!attr) {
         hipError_t e = hipSuccess;
         for (const void* f : {(const void*)k_compress_large<0>, (const void*)k_compress_large<2>,
-                              (const void*)k_compress_large<4>, (const void*)k_compress_large<5>,
+                              (const void*)k_compress_large<5>,
                               (const void*)k_compress_large<6>, (const void*)k_compress_large<7>,
                               (const void*)k_compress_large<8>, (const void*)k_compress_large<9>,
                               (const void*)k_large_round})
@@ -3399,17 +3470,34 @@ hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces
         attr = true;
     }
     switch (mode) {
-    case 0: launch_large_mode<0>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 2: launch_large_mode<2>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 4: launch_large_mode<4>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 5: launch_large_mode<5>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 6: launch_large_mode<6>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 7: launch_large_mode<7>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 8: launch_large_mode<8>(t, n, pieces, imap, trunc_rel, lds, st); break;
-    case 9: launch_large_mode<9>(t, n, pieces, imap, trunc_rel, lds, st); break;
+    case 0: launch_large_mode<0>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
+    case 2: launch_large_mode<2>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
+    case 5: launch_large_mode<5>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
+    case 6: launch_large_mode<6>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
+    case 7: launch_large_mode<7>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
+    case 8: launch_large_mode<8>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
+    case 9: launch_large_mode<9>(t, n, pieces, imap, trunc_rel, jac_u, lds, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_assemble_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                                 int64_t max_mc, int max_pieces, bool copy, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int64_t per = (int64_t)ASM_T * 16;                      // elements per work-group and pass
+    const int gx = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (max_mc + per - 1) / per));
+    hipLaunchKernelGGL(k_asm_zero, dim3(gx, n), dim3(ASM_T), 0, st, t);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && max_pieces > 0) {
+        hipLaunchKernelGGL(k_asm_scatter, dim3(max_pieces, n), dim3(ASM_T), 0, st, t, pieces, imap);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && copy) {
+        hipLaunchKernelGGL(k_asm_scale, dim3(gx, n), dim3(ASM_T), 0, st, t);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_gram_chol(const DCompress* t, int n, int max_c, double trunc_rel, hipStream_t st) {

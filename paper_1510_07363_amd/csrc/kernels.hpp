@@ -42,20 +42,30 @@ hipError_t launch_compress_svd(const DCompress* t, int n, const DPiece* pieces, 
 // workspace: hv needs 4 c^2 + c + 8 doubles, Bw M c).  Trailing QRCP rows below
 // trunc_rel * epsilon * |R1[0,0]| (Frobenius) are dropped (0: only exact
 // zeros).  Fits when compress_large_fits(M, c).
-// mode 0: the whole pipeline per work-group; modes 4 + launch_qr_blocked(0) +
-// 5 + launch_qr_blocked(1, 2) + 6: the QRs over many work-groups and the state
-// (Jacobi only for L taller than the block rounds hold), then launch_large_round
-// for rounds 0..large_rounds(max_c)-1 per sweep and launch_large_flags (out[i]
-// = 1: task i goes on) until no task goes on; mode 2: singular values, rank and
-// V; mode 7: after mode 4 and launch_qr_blocked(0), the rest in one work-group;
-// modes 4 + launch_gram_chol + 8 leave what mode 5 leaves through the Gram
-// matrix, and mode 9 then does the rest in one work-group.
+// mode 0: the whole pipeline per work-group; launch_assemble_large(copy =
+// true) + launch_qr_blocked(0) + mode 5 + launch_qr_blocked(1, 2) + mode 6: the
+// QRs over many work-groups and the state (Jacobi only for L taller than the
+// block rounds hold), then launch_large_round for rounds
+// 0..large_rounds(max_c)-1 per sweep and launch_large_flags (out[i] = 1: task i
+// goes on) until no task goes on; mode 2: singular values, rank and V; mode 7:
+// after launch_assemble_large(copy = true) and launch_qr_blocked(0), the rest in
+// one work-group; launch_assemble_large(copy = false) + launch_gram_chol + mode
+// 8 leave what mode 5 leaves through the Gram matrix, and mode 9 then does the
+// rest in one work-group.
+// jac_f32: the one-sided Jacobi stops at the FP32 level (rotation threshold
+// 3.6 u_32 kk instead of 3.6 u_64 kk), for mixed precision.
 hipError_t launch_compress_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap, int max_c,
-                                 int max_M, double trunc_rel, int mode, hipStream_t st);
+                                 int max_M, double trunc_rel, int mode, hipStream_t st, bool jac_f32 = false);
 hipError_t launch_large_round(const DCompress* t, int n, int max_c, int round, hipStream_t st);
-// FP64 Gram matrix of every task's Bw (matrix cores) and its Cholesky
+// Assembly of the stacked blocks B of large tasks over many work-groups (zero,
+// scatter of the pieces, largest |entry|); copy: also Bw = B / 2^e and the
+// scale in the header, for the QR route.
+hipError_t launch_assemble_large(const DCompress* t, int n, const DPiece* pieces, const int32_t* imap,
+                                 int64_t max_mc, int max_pieces, bool copy, hipStream_t st);
+// FP64 Gram matrix of every task's B / 2^e (matrix cores) and its Cholesky
 // factorization with diagonal pivoting in panels, truncated like the QRCP of
-// mode 5 (trunc_rel; and below c u trace(G)): between modes 4 and 8.
+// mode 5 (trunc_rel; and below c u trace(G)): between
+// launch_assemble_large(copy = false) and mode 8.
 hipError_t launch_gram_chol(const DCompress* t, int n, int max_c, double trunc_rel, hipStream_t st);
 // Randomized compression of stacked blocks with at most 64 columns (see
 // k_rand_sketch): the sketch launch (first = 1 also assembles B, ||B||_F^2 and

@@ -1204,7 +1204,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             // whatever the others are
             struct Group {
                 int key; std::vector<DCompress> t; std::vector<int> q;
-                int max_c = 1, max_M = 1; double fl = 0, by = 0; size_t off = 0;
+                int max_c = 1, max_M = 1, max_pieces = 0; int64_t max_mc = 1;
+                double fl = 0, by = 0; size_t off = 0;
             };
             std::vector<Group> groups;
             for (size_t q = 0; q < all.size(); ++q) {
@@ -1235,6 +1236,8 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 G.q.push_back((int)q);
                 G.max_c = std::max(G.max_c, (int)all[q].c);
                 G.max_M = std::max(G.max_M, (int)all[q].M);
+                G.max_mc = std::max(G.max_mc, (int64_t)all[q].M * all[q].c);
+                G.max_pieces = std::max(G.max_pieces, (int)all[q].npieces);
                 // known before the launch: the QRs (RRQR: at full rank, an upper
                 // bound); the Jacobi sweeps are added after the read-back
                 const double M = all[q].M, cc = all[q].c;
@@ -1350,7 +1353,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                     auto split_rest = [&](const DCompress* dt, int nt, double trunc) {
                         HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 1, gs));
                         HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 2, gs));
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 6, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 6, gs, (G.key & 1) != 0));
                         d_flags.ensure((size_t)nt * sizeof(int32_t));
                         pin_flags.ensure((size_t)nt * sizeof(int32_t));
                         const int rounds = large_rounds(G.max_c);
@@ -1372,17 +1375,17 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                         HIPCHK(launch_compress(dt, (int)G.t.size(), dp, dmap, G.max_c, gs));
                     else if (G.key == 8 || G.key == 9) {
                         HIPCHK(launch_compress_large(dt, (int)G.t.size(), dp, dmap, G.max_c, G.max_M,
-                                                     (G.key & 1) ? 0.01 : 0.0, 0, gs));
+                                                     (G.key & 1) ? 0.01 : 0.0, 0, gs, (G.key & 1) != 0));
                     } else if (G.key == 12 || G.key == 13) {
                         const int nt = (int)G.t.size();
                         const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_assemble_large(dt, nt, dp, dmap, G.max_mc, G.max_pieces, true, gs));
                         HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 7, gs));
+                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 7, gs, (G.key & 1) != 0));
                     } else if (G.key == 10 || G.key == 11) {
                         const int nt = (int)G.t.size();
                         const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_assemble_large(dt, nt, dp, dmap, G.max_mc, G.max_pieces, true, gs));
                         HIPCHK(launch_qr_blocked(dt, nt, G.max_c, G.max_M, 0, gs));
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 5, gs));
                         split_rest(dt, nt, trunc);
@@ -1391,11 +1394,11 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                         // work-group per task (26, 27) or split as above (28, 29)
                         const int nt = (int)G.t.size();
                         const double trunc = (G.key & 1) ? 0.01 : 0.0;
-                        HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 4, gs));
+                        HIPCHK(launch_assemble_large(dt, nt, dp, dmap, G.max_mc, G.max_pieces, false, gs));
                         HIPCHK(launch_gram_chol(dt, nt, G.max_c, trunc, gs));
                         HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 8, gs));
                         if (G.key < 28)
-                            HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 9, gs));
+                            HIPCHK(launch_compress_large(dt, nt, dp, dmap, G.max_c, G.max_M, trunc, 9, gs, (G.key & 1) != 0));
                         else
                             split_rest(dt, nt, trunc);
                     } else if (G.key == 20 || G.key == 21) {
