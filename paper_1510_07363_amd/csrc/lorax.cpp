@@ -412,6 +412,7 @@ struct Tune {
     int32_t gemm_grid = 0;          // persistent grid of the MFMA products (0: a work-group per tile)
     int32_t solve_graph = 1;        // 1: GMRES replays its preconditioner as a captured HIP graph
     int32_t compress_gram = 1;      // 1: mixed-precision compression through the FP64 Gram matrix
+    int32_t large_split_c = 192;    // wider blocks take the split (multi-work-group) back end
 };
 Tune g_tune;
 }  // namespace
@@ -1195,9 +1196,9 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             // with c > 64 (even keys: FP64 rows kept, odd: rows below epsilon / 100
             // dropped in mixed precision; 8 / 9: one work-group per task; 12 / 13
             // for tall blocks, M c >= 3e5: the tall QR in multi-work-group panels,
-            // the rest in one work-group; 10 / 11 for c > 192 or M c >= 1e6: QRs in
-            // panels and the Jacobi in multi-work-group block rounds; key 2 when the
-            // LDS of the large kernel does not fit; 26 / 27 and 28 / 29: R1 through
+            // the rest in one work-group; 10 / 11 for c > large_split_c (tuning, 192 by
+            // default) or M c >= 1e6: QRs in panels and the Jacobi in multi-work-group
+            // block rounds; key 2 when the LDS of the large kernel does not fit; 26 / 27 and 28 / 29: R1 through
             // the FP64 Gram matrix and its pivoted Cholesky, then as 12 / 13 and
             // 10 / 11), pivoted QR (key 4), randomized range finder with c <= 64
             // (20: FP64 sketch, 21: BF16 sketch); each task takes its own variant
@@ -1218,7 +1219,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 } else if (all[q].c <= 64) key = (fp32_of[q] & 1) | (all[q].c > 32 ? 16 : 0);
                 else if (compress_large_fits(all[q].M, all[q].c)) {
                     const int64_t mc = (int64_t)all[q].M * all[q].c;
-                    const bool split = all[q].c > 192 || mc >= 1000000;
+                    const bool split = all[q].c > g_tune.large_split_c || mc >= 1000000;
                     // (odd keys drop pivoted-QR rows below epsilon / 100 relative to
                     // sigma_0: not under the absolute threshold of the Frobenius rule)
                     const int drop = (fp32_of[q] & 1) && !all[q].tau ? 1 : 0;
@@ -2637,6 +2638,7 @@ lrx_status lrx_tune_get(lrx_tune* t) {
         t->gemm_grid = g_tune.gemm_grid;
         t->solve_graph = g_tune.solve_graph;
         t->compress_gram = g_tune.compress_gram;
+        t->large_split_c = g_tune.large_split_c;
         return LRX_OK;
     });
 }
@@ -2653,6 +2655,8 @@ lrx_status lrx_tune_set(const lrx_tune* t) {
         if (t->gemm_grid < 0 || t->gemm_grid > 65536) fail(LRX_EINVAL, "gemm_grid must be 0..65536");
         if (t->solve_graph != 0 && t->solve_graph != 1) fail(LRX_EINVAL, "solve_graph must be 0 or 1");
         if (t->compress_gram < 0 || t->compress_gram > 2) fail(LRX_EINVAL, "compress_gram must be 0, 1 or 2");
+        if (t->large_split_c < 65 || t->large_split_c > 65536) fail(LRX_EINVAL, "large_split_c must be 65..65536");
+        g_tune.large_split_c = t->large_split_c;
         g_tune.solve_graph = t->solve_graph;
         g_tune.compress_gram = t->compress_gram;
         g_tune.gemm_kc = t->gemm_kc;

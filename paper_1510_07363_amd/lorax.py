@@ -90,11 +90,11 @@ class PlanInfo(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("gemm_kc", C.c_int32), ("gemm_f64_valu", C.c_int32), ("sweep_nk_max", C.c_int32),
                 ("compress_nt_small", C.c_int32), ("compress_nt_mid", C.c_int32), ("gemm_grid", C.c_int32),
-                ("solve_graph", C.c_int32), ("compress_gram", C.c_int32)]
+                ("solve_graph", C.c_int32), ("compress_gram", C.c_int32), ("large_split_c", C.c_int32)]
 
 
 TUNE_FIELDS = ("gemm_kc", "gemm_f64_valu", "sweep_nk_max", "compress_nt_small", "compress_nt_mid", "gemm_grid",
-               "solve_graph", "compress_gram")
+               "solve_graph", "compress_gram", "large_split_c")
 
 
 # every symbol declared in include/lorax.h

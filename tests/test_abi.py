@@ -113,13 +113,14 @@ def test_tune_table_validation():
     assert base["gemm_kc"] % 16 == 0 and base["sweep_nk_max"] in (1, 2, 4)
     try:
         lorax.tune_set(gemm_kc=64, sweep_nk_max=4, gemm_f64_valu=1, compress_nt_small=256, compress_nt_mid=512,
-                       gemm_grid=1024, solve_graph=0, compress_gram=0)
+                       gemm_grid=1024, solve_graph=0, compress_gram=0, large_split_c=65)
         assert lorax.tune_get() == {"gemm_kc": 64, "gemm_f64_valu": 1, "sweep_nk_max": 4,
                                     "compress_nt_small": 256, "compress_nt_mid": 512, "gemm_grid": 1024,
-                                    "solve_graph": 0, "compress_gram": 0}
+                                    "solve_graph": 0, "compress_gram": 0, "large_split_c": 65}
         for bad in ({"gemm_kc": 24}, {"gemm_kc": 512}, {"sweep_nk_max": 3}, {"sweep_nk_max": 8}, {"gemm_f64_valu": 2},
                     {"compress_nt_small": 128}, {"compress_nt_mid": 2048}, {"gemm_grid": -1},
-                    {"solve_graph": 2}, {"compress_gram": 3}, {"compress_gram": -1}):
+                    {"solve_graph": 2}, {"compress_gram": 3}, {"compress_gram": -1}, {"large_split_c": 64},
+                    {"large_split_c": 65537}):
             with pytest.raises(lorax.LoraxError) as e:
                 lorax.tune_set(**bad)
             assert e.value.status == lorax.LRX_EINVAL
