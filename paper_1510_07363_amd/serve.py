@@ -373,9 +373,17 @@ class Server:
                             self.jobs.remove(k)
                             group.append(k)
                 self.factoring |= set(group)
-            if len(group) == 1 or not self._run_factor_batch(group):
-                for k in group:
-                    self._run_factor_job(k, inline=False)
+            try:
+                if len(group) == 1 or not self._run_factor_batch(group):
+                    for k in group:
+                        self._run_factor_job(k, inline=False)
+            except Exception as e:                          # the worker must not die silently
+                with self._lock:
+                    for k in group:
+                        if k not in self.resident:
+                            self._fail_key(k, e)
+                    self.factoring -= set(group)
+                    self._wake.notify_all()
 
     def _run_factor_batch(self, group) -> bool:
         """One lrx_factor_batch over group; False (nothing admitted) when it does
@@ -389,6 +397,8 @@ class Server:
             hs = self.factor_backend.factor_batch(specs, room)
         except OutOfBudget:
             return False
+        except Exception:                                   # a library error: one by one, each job
+            return False                                    # fails (or succeeds) on its own
         for h in hs:
             if self.factor_backend is not self.backend and hasattr(self.backend, "adopt"):
                 self.backend.adopt(h)

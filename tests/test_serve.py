@@ -230,6 +230,32 @@ def test_queued_factor_jobs_are_batched_by_epsilon():
         assert (f.result()[2] <= 1e-10).all()
 
 
+def test_failing_batched_factorization_falls_back_to_single_jobs():
+    """A library error in a batched factorization (here raised by the backend)
+    neither kills the factor worker nor leaves requests waiting: the jobs run one
+    by one, and a job that fails alone fails only its own requests."""
+    rng = np.random.default_rng(9)
+    srv, be, specs = _server(10_000, max_factor_batch=4)
+
+    def broken_batch(specs_, room):
+        raise RuntimeError("device error in the batch")
+    be.factor_batch = broken_batch
+    single = be.factor
+
+    def factor(spec, room):
+        if spec.key == "b":
+            raise RuntimeError("device error in b")
+        return single(spec, room)
+    be.factor = factor
+    futs = {k: srv.submit(k, rng.uniform(-1, 1, specs[k].n)) for k in ("a", "b", "c")}
+    srv.start()
+    srv.run_until_idle()
+    srv.stop()
+    assert (futs["a"].result()[2] <= 1e-10).all() and (futs["c"].result()[2] <= 1e-10).all()
+    with pytest.raises(RuntimeError):
+        futs["b"].result()
+
+
 def test_submit_validation():
     srv, be, specs = _server(10_000)
     with pytest.raises(KeyError):
