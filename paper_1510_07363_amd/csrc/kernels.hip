@@ -2474,123 +2474,146 @@ constexpr int GJB = 16;                      // panel width
 constexpr int GJB_CW = 64;                   // columns of the trailing update staged at once
 constexpr int GJB_MAX = 1024;                // rows: one per thread in the update
 
-__device__ bool gj_inverse_blocked(double* A, int m, double* sm) {
+// Panel j0 of the blocked inverse (every thread of the work-group): pivot steps
+// on the m x nb panel in LDS Pn, the panel written back, its row swaps applied to
+// the other columns; the pivot rows go to perm[j0 .. j0 + nb).  False: a zero
+// pivot column (singular).
+__device__ bool gj_panel(double* A, int m, int j0, double* sm, int* perm) {
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int nb = min(GJB, m - j0);
     double* Pn = sm;                                         // m x GJB panel, ld m
-    double* Tc = Pn + (size_t)GJB * m;                       // GJB x GJB_CW
-    double* s_bv = Tc + GJB * GJB_CW;                        // NWP
+    double* s_bv = Pn + (size_t)GJB * m + GJB * GJB_CW;      // NWP
     int* s_bi = reinterpret_cast<int*>(s_bv + NWP);          // NWP
-    int* s_perm = s_bi + NWP;                                // m
-    for (int j0 = 0; j0 < m; j0 += GJB) {
-        const int nb = min(GJB, m - j0);
-        for (int e = tid; e < m * nb; e += NTP) {
-            const int i = e % m, t = e / m;
-            Pn[i + t * m] = A[i + (int64_t)(j0 + t) * m];
+    int* s_pp = s_bi + NWP;                                  // GJB pivot rows of this panel
+    for (int e = tid; e < m * nb; e += NTP) {
+        const int i = e % m, t = e / m;
+        Pn[i + t * m] = A[i + (int64_t)(j0 + t) * m];
+    }
+    __syncthreads();
+    for (int kk = 0; kk < nb; ++kk) {
+        const int k = j0 + kk;
+        double best = -1.0;
+        int bi = INT_MAX;
+        for (int i = k + tid; i < m; i += NTP) {
+            const double v = fabs(Pn[i + kk * m]);
+            if (v > best) { best = v; bi = i; }
+        }
+        wave_argmax(best, bi);
+        if (lane == 0) { s_bv[wv] = best; s_bi[wv] = bi; }
+        __syncthreads();
+        best = s_bv[0];
+        bi = s_bi[0];
+        for (int w = 1; w < NWP; ++w)
+            if (s_bv[w] > best || (s_bv[w] == best && s_bi[w] < bi)) { best = s_bv[w]; bi = s_bi[w]; }
+        if (!(best > 0.0)) return false;                     // uniform
+        const int p = bi;
+        if (p != k && tid < nb) {
+            const double a = Pn[k + tid * m];
+            Pn[k + tid * m] = Pn[p + tid * m];
+            Pn[p + tid * m] = a;
+        }
+        if (tid == 0) s_pp[kk] = p;
+        __syncthreads();
+        // the step on the panel columns: row k scaled by d = 1 / pivot, the
+        // other rows minus their column-k entry times the new row k
+        const double d = 1.0 / Pn[k + kk * m];
+        double rowk[GJB];
+#pragma unroll
+        for (int t = 0; t < GJB; ++t) rowk[t] = t < nb ? (t == kk ? d : Pn[k + t * m] * d) : 0.0;
+        __syncthreads();                                     // row k read by every thread
+        for (int i = tid; i < m; i += NTP) {
+            if (i == k) {
+                for (int t = 0; t < nb; ++t) Pn[k + t * m] = rowk[t];
+            } else {
+                const double f = Pn[i + kk * m];
+                for (int t = 0; t < nb; ++t)
+                    Pn[i + t * m] = (t == kk) ? -f * d : Pn[i + t * m] - f * rowk[t];
+            }
         }
         __syncthreads();
+    }
+    for (int e = tid; e < m * nb; e += NTP) {
+        const int i = e % m, t = e / m;
+        A[i + (int64_t)(j0 + t) * m] = Pn[i + t * m];
+    }
+    if (tid < nb) perm[j0 + tid] = s_pp[tid];
+    // the panel's swaps on the other columns, in order (one thread per column)
+    for (int c = tid; c < m; c += NTP) {
+        if (c >= j0 && c < j0 + nb) continue;
+        double* col = A + (int64_t)c * m;
         for (int kk = 0; kk < nb; ++kk) {
-            const int k = j0 + kk;
-            double best = -1.0;
-            int bi = INT_MAX;
-            for (int i = k + tid; i < m; i += NTP) {
-                const double v = fabs(Pn[i + kk * m]);
-                if (v > best) { best = v; bi = i; }
+            const int k = j0 + kk, p = s_pp[kk];
+            if (p != k) {
+                const double a = col[k];
+                col[k] = col[p];
+                col[p] = a;
             }
-            wave_argmax(best, bi);
-            if (lane == 0) { s_bv[wv] = best; s_bi[wv] = bi; }
-            __syncthreads();
-            best = s_bv[0];
-            bi = s_bi[0];
-            for (int w = 1; w < NWP; ++w)
-                if (s_bv[w] > best || (s_bv[w] == best && s_bi[w] < bi)) { best = s_bv[w]; bi = s_bi[w]; }
-            if (!(best > 0.0)) return false;                     // uniform
-            const int p = bi;
-            if (p != k && tid < nb) {
-                const double a = Pn[k + tid * m];
-                Pn[k + tid * m] = Pn[p + tid * m];
-                Pn[p + tid * m] = a;
-            }
-            if (tid == 0) s_perm[k] = p;
-            __syncthreads();
-            // the step on the panel columns: row k scaled by d = 1 / pivot, the
-            // other rows minus their column-k entry times the new row k
-            const double d = 1.0 / Pn[k + kk * m];
-            double rowk[GJB];
-#pragma unroll
-            for (int t = 0; t < GJB; ++t) rowk[t] = t < nb ? (t == kk ? d : Pn[k + t * m] * d) : 0.0;
-            __syncthreads();                                     // row k read by every thread
-            for (int i = tid; i < m; i += NTP) {
-                if (i == k) {
-                    for (int t = 0; t < nb; ++t) Pn[k + t * m] = rowk[t];
-                } else {
-                    const double f = Pn[i + kk * m];
-                    for (int t = 0; t < nb; ++t)
-                        Pn[i + t * m] = (t == kk) ? -f * d : Pn[i + t * m] - f * rowk[t];
-                }
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < m * nb; e += NTP) {
-            const int i = e % m, t = e / m;
-            A[i + (int64_t)(j0 + t) * m] = Pn[i + t * m];
-        }
-        // the panel's swaps on the other columns, in order (one thread per column)
-        for (int c = tid; c < m; c += NTP) {
-            if (c >= j0 && c < j0 + nb) continue;
-            double* col = A + (int64_t)c * m;
-            for (int kk = 0; kk < nb; ++kk) {
-                const int k = j0 + kk, p = s_perm[k];
-                if (p != k) {
-                    const double a = col[k];
-                    col[k] = col[p];
-                    col[p] = a;
-                }
-            }
-        }
-        __syncthreads();
-        // A[:, c] = M A[:, c] = A[:, c] + (M[:, J] - I[:, J]) A[J, c] for c outside J;
-        // thread i keeps row i of M[:, J] - I[:, J] in registers
-        double mh[GJB];
-        const int i = tid;
-#pragma unroll
-        for (int t = 0; t < GJB; ++t)
-            mh[t] = (i < m && t < nb) ? Pn[i + t * m] - (i == j0 + t ? 1.0 : 0.0) : 0.0;
-        for (int c0 = 0; c0 < m; c0 += GJB_CW) {
-            for (int e = tid; e < GJB * GJB_CW; e += NTP) {
-                const int t = e % GJB, cc = e / GJB, c = c0 + cc;
-                Tc[t + cc * GJB] = (t < nb && c < m && (c < j0 || c >= j0 + nb)) ? A[(j0 + t) + (int64_t)c * m] : 0.0;
-            }
-            __syncthreads();
-            if (i < m) {
-                const int cend = min(GJB_CW, m - c0);
-                for (int cc = 0; cc < cend; ++cc) {
-                    const int c = c0 + cc;
-                    if (c >= j0 && c < j0 + nb) continue;
-                    double acc = A[i + (int64_t)c * m];
-#pragma unroll
-                    for (int t = 0; t < GJB; ++t) acc += mh[t] * Tc[t + cc * GJB];
-                    A[i + (int64_t)c * m] = acc;
-                }
-            }
-            __syncthreads();
         }
     }
-    // the stored matrix is the inverse of A with rows permuted: undo by columns
-    for (int i = tid; i < m; i += NTP)
+    __syncthreads();
+    return true;
+}
+
+// The panel's transformation on columns c0 .. c0 + GJB_CW - 1 outside the panel
+// J: A[:, c] = A[:, c] + (M[:, J] - I[:, J]) A[J, c], M[:, J] the panel columns
+// as stored; thread i updates row i.  Each column is read (rows J first, into
+// Tc) before any of its rows is written, so chunks may run in separate
+// work-groups.
+__device__ void gj_update_chunk(double* A, int m, int j0, int c0, double* Tc) {
+    const int tid = threadIdx.x;
+    const int nb = min(GJB, m - j0);
+    for (int e = tid; e < GJB * GJB_CW; e += NTP) {
+        const int t = e % GJB, cc = e / GJB, c = c0 + cc;
+        Tc[t + cc * GJB] = (t < nb && c < m && (c < j0 || c >= j0 + nb)) ? A[(j0 + t) + (int64_t)c * m] : 0.0;
+    }
+    __syncthreads();
+    const int i = tid;
+    if (i < m) {
+        double mh[GJB];
+#pragma unroll
+        for (int t = 0; t < GJB; ++t)
+            mh[t] = t < nb ? A[i + (int64_t)(j0 + t) * m] - (i == j0 + t ? 1.0 : 0.0) : 0.0;
+        const int cend = min(GJB_CW, m - c0);
+        for (int cc = 0; cc < cend; ++cc) {
+            const int c = c0 + cc;
+            if (c >= j0 && c < j0 + nb) continue;
+            double acc = A[i + (int64_t)c * m];
+#pragma unroll
+            for (int t = 0; t < GJB; ++t) acc += mh[t] * Tc[t + cc * GJB];
+            A[i + (int64_t)c * m] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// The stored matrix is the inverse of A with rows permuted: undo by columns
+// (rows i0 + tid).
+__device__ void gj_unperm(double* A, int m, const int* perm, int i0) {
+    for (int i = i0 + threadIdx.x; i < m; i += NTP)
         for (int k = m - 1; k >= 0; --k) {
-            const int p = s_perm[k];
+            const int p = perm[k];
             if (p != k) {
                 const double t = A[i + (int64_t)k * m];
                 A[i + (int64_t)k * m] = A[i + (int64_t)p * m];
                 A[i + (int64_t)p * m] = t;
             }
         }
+}
+
+__device__ bool gj_inverse_blocked(double* A, int m, double* sm) {
+    double* Tc = sm + (size_t)GJB * m;                       // GJB x GJB_CW
+    int* s_perm = reinterpret_cast<int*>(Tc + GJB * GJB_CW + NWP) + NWP + GJB;   // m
+    for (int j0 = 0; j0 < m; j0 += GJB) {
+        if (!gj_panel(A, m, j0, sm, s_perm)) return false;
+        for (int c0 = 0; c0 < m; c0 += GJB_CW) gj_update_chunk(A, m, j0, c0, Tc);
+    }
+    gj_unperm(A, m, s_perm, 0);
     __syncthreads();
     return true;
 }
 
 __host__ __device__ inline size_t gj_blocked_lds(int m) {
-    return ((size_t)GJB * m + GJB * GJB_CW + NWP) * sizeof(double) + (size_t)(NWP + m) * sizeof(int);
+    return ((size_t)GJB * m + GJB * GJB_CW + NWP) * sizeof(double) + (size_t)(NWP + GJB + m) * sizeof(int);
 }
 
 // Register-resident Gauss-Jordan inverse with partial pivoting for m <= MB.
@@ -2705,7 +2728,7 @@ __device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
 __global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tasks,
                                                    const DProj* __restrict__ projs,
                                                    const int32_t* __restrict__ imap,
-                                                   int32_t* __restrict__ info) {
+                                                   int32_t* __restrict__ info, int defer) {
     const DPrep T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
     extern __shared__ double sm[];
@@ -2763,9 +2786,48 @@ __global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tas
     if (m <= 32) ok = gj_inverse_reg<32>(T.piv.p, m, sm);
     else if (m <= 64) ok = gj_inverse_reg<64>(T.piv.p, m, sm);
     else if (m <= 128) ok = gj_inverse_reg<128>(T.piv.p, m, sm);
-    else if (m <= GJB_MAX && gj_blocked_lds(m) <= (size_t)kLdsBudget) ok = gj_inverse_blocked(T.piv.p, m, sm);
+    else if (m <= GJB_MAX && gj_blocked_lds(m) <= (size_t)kLdsBudget)
+        ok = defer ? true : gj_inverse_blocked(T.piv.p, m, sm);   // defer: the multi-work-group launches
     else ok = gj_inverse_global(T.piv.p, m, sm, (int*)(sm + m), sm + 2 * m);
     if (!ok && tid == 0) info[T.info_slot] = 1;
+}
+
+// The blocked inverse of the pivots with 128 < m <= GJB_MAX over many
+// work-groups (k_node_prep with defer leaves them): per panel, one work-group
+// per task runs gj_panel, then one work-group per GJB_CW-column chunk and task
+// applies the panel's transformation; finally the row order is undone.  perm:
+// GJB_MAX ints per task.  A task whose pivot turns out singular gets its info
+// slot set and is skipped from then on.
+__device__ inline bool gj_deferred(const DPrep& T) {
+    const int m = T.piv.nr;
+    return m > 128 && m <= GJB_MAX && gj_blocked_lds(m) <= (size_t)kLdsBudget;
+}
+
+__global__ __launch_bounds__(NTP) void k_gj_panel(const DPrep* __restrict__ tasks, int j0, int* __restrict__ perm,
+                                                  int32_t* __restrict__ info) {
+    const DPrep T = tasks[blockIdx.x];
+    const int m = T.piv.nr;
+    if (!gj_deferred(T) || j0 >= m || info[T.info_slot]) return;   // uniform
+    extern __shared__ double sm[];
+    const bool ok = gj_panel(T.piv.p, m, j0, sm, perm + (size_t)blockIdx.x * GJB_MAX);
+    if (!ok && threadIdx.x == 0) info[T.info_slot] = 1;
+}
+
+__global__ __launch_bounds__(NTP) void k_gj_update(const DPrep* __restrict__ tasks, int j0,
+                                                   const int32_t* __restrict__ info) {
+    const DPrep T = tasks[blockIdx.y];
+    const int m = T.piv.nr;
+    const int c0 = blockIdx.x * GJB_CW;
+    if (!gj_deferred(T) || j0 >= m || c0 >= m || info[T.info_slot]) return;
+    __shared__ double Tc[GJB * GJB_CW];
+    gj_update_chunk(T.piv.p, m, j0, c0, Tc);
+}
+
+__global__ __launch_bounds__(NTP) void k_gj_unperm(const DPrep* __restrict__ tasks, const int* __restrict__ perm,
+                                                   const int32_t* __restrict__ info) {
+    const DPrep T = tasks[blockIdx.x];
+    if (!gj_deferred(T) || info[T.info_slot]) return;
+    gj_unperm(T.piv.p, T.piv.nr, perm + (size_t)blockIdx.x * GJB_MAX, 0);
 }
 
 // Tiled product with gathers and scatters (DGemm): one work-group per 32 x 32
@@ -3589,24 +3651,43 @@ hipError_t launch_large_flags(const DCompress* t, int n, int32_t* out, hipStream
 }
 
 hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,
-                            int32_t* info, hipStream_t st) {
+                            int32_t* info, hipStream_t st, int* gj_perm) {
     if (n == 0) return hipSuccess;
+    const bool defer = gj_perm != nullptr && max_m > 128;
     // LDS: the Gauss-Jordan exchange buffers (4 KiB), or the global variant's
-    // scratch (2 m + 1 doubles)
+    // scratch (2 m + 1 doubles), or the blocked variant's panel when it runs here
     size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
-    if (max_m > 128 && max_m <= GJB_MAX && gj_blocked_lds(max_m) <= (size_t)kLdsBudget)
+    if (!defer && max_m > 128 && max_m <= GJB_MAX && gj_blocked_lds(max_m) <= (size_t)kLdsBudget)
         need = std::max(need, gj_blocked_lds(max_m));
     if (need > (size_t)kLdsBudget) return hipErrorInvalidValue;
     static std::atomic<bool> attr{false};
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_node_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kLdsBudget);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_gj_panel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const size_t lds = need;
-    hipLaunchKernelGGL(k_node_prep, dim3(n), dim3(NTP), lds, st, t, proj, imap, info);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_node_prep, dim3(n), dim3(NTP), need, st, t, proj, imap, info, defer ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !defer) return e;
+    const int mm = max_m < GJB_MAX ? max_m : GJB_MAX;
+    const size_t lds_p = gj_blocked_lds(mm);
+    for (int j0 = 0; j0 < mm && e == hipSuccess; j0 += GJB) {
+        hipLaunchKernelGGL(k_gj_panel, dim3(n), dim3(NTP), lds_p, st, t, j0, gj_perm, info);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_gj_update, dim3((mm + GJB_CW - 1) / GJB_CW, n), dim3(NTP), 0, st, t, j0,
+                               (const int32_t*)info);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gj_unperm, dim3(n), dim3(NTP), 0, st, t, (const int*)gj_perm, (const int32_t*)info);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_gemm_tiles(const DGemm* g, const DTile* tiles, int ntile, int kmax, const int32_t* imap,

@@ -1096,7 +1096,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
     for (FactorRun* r : runs) { r->d_idx.release(); r->d_val.release(); }
 
     PinBuf stage_m, stage_c, stage_n, pin_rt, pin_flags;   // descriptor staging, rank read-back
-    DevBuf d_desc_m, d_desc_c, d_desc_n, d_rt, d_flags;
+    DevBuf d_desc_m, d_desc_c, d_desc_n, d_rt, d_flags, d_gjperm;
     PinBuf pin_rand, pin_rflags;               // randomized compression: attempt descriptors, flags
     DevBuf d_rand, d_rflags;
     int64_t m_epoch = -1;                       // epoch of the last merge upload
@@ -1520,16 +1520,24 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
                 HIPCHK(gemm_products((const DGemm*)(b + o_gp), (const DTile*)(b + o_tp), (int)tps.size(), kps, dmap,
                                      p_proj, st));
             }
+            // pivots above 128 rows: the blocked inverse over many work-groups,
+            // its row order kept in d_gjperm (the previous step's use has completed
+            // at the read-back)
+            int* gjp = nullptr;
+            if (std::max(nb.max_ms, nb.max_mb) > 128) {
+                d_gjperm.ensure((size_t)np * kGjPermInts * sizeof(int32_t));
+                gjp = d_gjperm.as<int32_t>();
+            }
             {
                 LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_s);
                 HIPCHK(launch_node_prep((const DPrep*)(b + o_ps), np, nb.max_ms, (const DProj*)(b + o_pj), dmap,
-                                        inf, st));
+                                        inf, st, gjp));
             }
             gemm(o_g1s, o_t1s, t1s, k1s, 0, GP_F64);
             gemm(o_g2s, o_t2s, t2s, k2s, nb.gf_s, p_schur);
             {
                 LaunchTimer tm(LRX_K_FACTOR_NODE, st, 0.0, (double)nb.pf_b);
-                HIPCHK(launch_node_prep((const DPrep*)(b + o_pb), np, nb.max_mb, nullptr, dmap, inf, st));
+                HIPCHK(launch_node_prep((const DPrep*)(b + o_pb), np, nb.max_mb, nullptr, dmap, inf, st, gjp));
             }
             gemm(o_g1b, o_t1b, t1b, k1b, 0, GP_F64);
             gemm(o_g2b, o_t2b, t2b, k2b, nb.gf_b, p_schur);
@@ -1564,7 +1572,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
         r->h->ws_b.release();
         r->h->ws_w.release();
     }
-    for (DevBuf* d : {&d_imap, &d_info, &d_desc_m, &d_desc_c, &d_desc_n, &d_rt, &d_flags}) d->release();
+    for (DevBuf* d : {&d_imap, &d_info, &d_desc_m, &d_desc_c, &d_desc_n, &d_rt, &d_flags, &d_gjperm}) d->release();
     for (PinBuf* q : {&stage_m, &stage_c, &stage_n, &pin_rt, &pin_flags}) q->release();
 }
 
