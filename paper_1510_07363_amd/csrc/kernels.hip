@@ -1746,7 +1746,8 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
         __syncthreads();
     }
     // ---- 4. one-sided Jacobi on the kk columns of L; W follows.  Pairs run in
-    // groups of 16 lanes (64 at once) up to 256 rows, then 32 and 64 lanes.
+    // groups of 16 lanes (64 at once) up to 128 rows, then 32 up to 256 and 64
+    // beyond (columns longer than 512 in several passes).
     // In mode 6 it runs here only when L is too tall for the block rounds.
     // rotation threshold 3.6 jac_u kk (jac_u: FP64 or, in mixed precision, FP32
     // unit roundoff); the zero-column guard stays at FP64 level
@@ -1786,10 +1787,10 @@ __global__ __launch_bounds__(NTL) void k_compress_large(const DCompress* __restr
             __syncthreads();
             ++sweeps_run;
             for (int t = 0; t < n2 - 1; ++t) {
+                // at most 8 elements of a column per lane (more spill registers)
                 if (kk <= 128) jac_round<16, 8>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
-                else if (kk <= 256) jac_round<16, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
-                else if (kk <= 512) jac_round<32, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
-                else jac_round<64, 16>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
+                else if (kk <= 256) jac_round<32, 8>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
+                else jac_round<64, 8>(X, W, ldc, kk, c, n2, t, tol, tol_hi, tiny2, &s_rot);
                 __syncthreads();
             }
             const int rot = s_rot;
@@ -2074,14 +2075,15 @@ __global__ __launch_bounds__(NTL) void k_large_round(const DCompress* __restrict
         const int sl_ = e / kk, r = e - sl_ * kk;
         X[r + s_col[sl_] * ldc] = sx[e];
     }
-    // W[:, cols] = W[:, cols] Q, one row per thread
+    // W[:, cols] = W[:, cols] Q, one row per thread: the row in registers, Q read
+    // from LDS one output column at a time (unrolling the column loop as well
+    // keeps all of Q in registers and spills)
     for (int r = tid; r < c; r += NTL) {
         double w[16];
 #pragma unroll
         for (int s2 = 0; s2 < 16; ++s2) w[s2] = s2 < ncol ? W[r + s_col[s2] * ldc] : 0.0;
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) {
-            if (s2 >= ncol) continue;
+#pragma unroll 1
+        for (int s2 = 0; s2 < ncol; ++s2) {
             double acc = 0.0;
 #pragma unroll
             for (int s1 = 0; s1 < 16; ++s1) acc += w[s1] * sq[s2 * 16 + s1];
@@ -2469,7 +2471,7 @@ __device__ bool gj_inverse_global(double* A, int m, double* scol, int* sperm, do
 // earlier E columns, so the panel's product is M = I + (M[:, J] - I[:, J]) with
 // M[:, J] the panel columns as stored, and every other column c becomes
 // M (swapped c).  Each element of A is read and written once per panel instead
-// of once per column.  LDS: gj_blocked_lds(m) bytes.
+// of once per column.  LDS of a panel: gj_blocked_lds(m) bytes.
 constexpr int GJB = 16;                      // panel width
 constexpr int GJB_CW = 64;                   // columns of the trailing update staged at once
 constexpr int GJB_MAX = 1024;                // rows: one per thread in the update
@@ -2600,18 +2602,6 @@ __device__ void gj_unperm(double* A, int m, const int* perm, int i0) {
         }
 }
 
-__device__ bool gj_inverse_blocked(double* A, int m, double* sm) {
-    double* Tc = sm + (size_t)GJB * m;                       // GJB x GJB_CW
-    int* s_perm = reinterpret_cast<int*>(Tc + GJB * GJB_CW + NWP) + NWP + GJB;   // m
-    for (int j0 = 0; j0 < m; j0 += GJB) {
-        if (!gj_panel(A, m, j0, sm, s_perm)) return false;
-        for (int c0 = 0; c0 < m; c0 += GJB_CW) gj_update_chunk(A, m, j0, c0, Tc);
-    }
-    gj_unperm(A, m, s_perm, 0);
-    __syncthreads();
-    return true;
-}
-
 __host__ __device__ inline size_t gj_blocked_lds(int m) {
     return ((size_t)GJB * m + GJB * GJB_CW + NWP) * sizeof(double) + (size_t)(NWP + GJB + m) * sizeof(int);
 }
@@ -2728,7 +2718,7 @@ __device__ bool gj_inverse_reg(double* __restrict__ A, int m, double* lds) {
 __global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tasks,
                                                    const DProj* __restrict__ projs,
                                                    const int32_t* __restrict__ imap,
-                                                   int32_t* __restrict__ info, int defer) {
+                                                   int32_t* __restrict__ info) {
     const DPrep T = tasks[blockIdx.x];
     const int tid = threadIdx.x;
     extern __shared__ double sm[];
@@ -2787,13 +2777,14 @@ __global__ __launch_bounds__(NTP) void k_node_prep(const DPrep* __restrict__ tas
     else if (m <= 64) ok = gj_inverse_reg<64>(T.piv.p, m, sm);
     else if (m <= 128) ok = gj_inverse_reg<128>(T.piv.p, m, sm);
     else if (m <= GJB_MAX && gj_blocked_lds(m) <= (size_t)kLdsBudget)
-        ok = defer ? true : gj_inverse_blocked(T.piv.p, m, sm);   // defer: the multi-work-group launches
+        ok = true;                                   // inverted by the k_gj_* launches that follow
     else ok = gj_inverse_global(T.piv.p, m, sm, (int*)(sm + m), sm + 2 * m);
     if (!ok && tid == 0) info[T.info_slot] = 1;
 }
 
 // The blocked inverse of the pivots with 128 < m <= GJB_MAX over many
-// work-groups (k_node_prep with defer leaves them): per panel, one work-group
+// work-groups (k_node_prep leaves them; inlining a one-work-group form there
+// made the whole kernel spill): per panel, one work-group
 // per task runs gj_panel, then one work-group per GJB_CW-column chunk and task
 // applies the panel's transformation; finally the row order is undone.  perm:
 // GJB_MAX ints per task.  A task whose pivot turns out singular gets its info
@@ -3653,12 +3644,11 @@ hipError_t launch_large_flags(const DCompress* t, int n, int32_t* out, hipStream
 hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,
                             int32_t* info, hipStream_t st, int* gj_perm) {
     if (n == 0) return hipSuccess;
-    const bool defer = gj_perm != nullptr && max_m > 128;
+    const bool blocked = max_m > 128;                // some pivot may take the multi-work-group form
+    if (blocked && !gj_perm) return hipErrorInvalidValue;
     // LDS: the Gauss-Jordan exchange buffers (4 KiB), or the global variant's
-    // scratch (2 m + 1 doubles), or the blocked variant's panel when it runs here
-    size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
-    if (!defer && max_m > 128 && max_m <= GJB_MAX && gj_blocked_lds(max_m) <= (size_t)kLdsBudget)
-        need = std::max(need, gj_blocked_lds(max_m));
+    // scratch (2 m + 1 doubles)
+    const size_t need = std::max<size_t>(4096, (size_t)(2 * (size_t)max_m + 8) * sizeof(double));
     if (need > (size_t)kLdsBudget) return hipErrorInvalidValue;
     static std::atomic<bool> attr{false};
     if (!attr) {
@@ -3669,9 +3659,9 @@ hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj,
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_node_prep, dim3(n), dim3(NTP), need, st, t, proj, imap, info, defer ? 1 : 0);
+    hipLaunchKernelGGL(k_node_prep, dim3(n), dim3(NTP), need, st, t, proj, imap, info);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !defer) return e;
+    if (e != hipSuccess || !blocked) return e;
     const int mm = max_m < GJB_MAX ? max_m : GJB_MAX;
     const size_t lds_p = gj_blocked_lds(mm);
     for (int j0 = 0; j0 < mm && e == hipSuccess; j0 += GJB) {

@@ -91,9 +91,9 @@ inline bool compress_large_fits(int M, int c) {
     return (vlen + 4 * (size_t)c) * sizeof(double) + 2 * (size_t)c * sizeof(int) <= 152 * 1024;
 }
 // Projection, rewiring and pivot inverse per task (DPrep); info[slot] = 1 for an
-// exactly singular pivot.  gj_perm (kGjPermInts ints per task, or nullptr):
-// pivots of 129..1024 rows are inverted by panel and update launches over many
-// work-groups instead of one work-group each.
+// exactly singular pivot.  gj_perm (kGjPermInts ints per task; required when
+// max_m > 128): pivots of 129..1024 rows are inverted by panel and update
+// launches over many work-groups.
 constexpr int kGjPermInts = 1024;
 hipError_t launch_node_prep(const DPrep* t, int n, int max_m, const DProj* proj, const int32_t* imap,
                             int32_t* info, hipStream_t st, int* gj_perm = nullptr);
