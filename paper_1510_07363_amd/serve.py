@@ -335,7 +335,22 @@ class Server:
         self.n_evicted += 1
         return True
 
+    def cancel(self, future: cf.Future) -> bool:
+        """Cancels a request that has not completed (Future.cancel has the same
+        effect): a queued solve leaves the queue at the next round, one in a
+        running round is dropped when the round ends (its partial iterate is
+        discarded), a factor request stops waiting (the factorization itself
+        goes on for the other requests of that system).  False if the request
+        has already completed."""
+        ok = future.cancel()
+        if ok:
+            with self._lock:
+                self._wake.notify_all()
+        return ok
+
     def _complete_factor(self, req, nbytes) -> None:
+        if req.future.cancelled():
+            return
         self.latencies["factor"].append(time.perf_counter() - req.arrival)
         req.future.set_result(nbytes)
 
@@ -343,12 +358,14 @@ class Server:
         keep = collections.deque()
         for req in self.pending:
             if req.key == key:
-                req.future.set_exception(exc)
+                if not req.future.cancelled():
+                    req.future.set_exception(exc)
             else:
                 keep.append(req)
         self.pending = keep
         for req in self.factor_waiters.pop(key, []):
-            req.future.set_exception(exc)
+            if not req.future.cancelled():
+                req.future.set_exception(exc)
 
     def _ready_keys(self):
         return [r.key for r in self.pending if r.key in self.resident and r.key not in self.busy]
@@ -504,6 +521,8 @@ class Server:
             width: dict[str, int] = {}
             rest = collections.deque()
             for req in self.pending:
+                if req.future.cancelled():          # cancelled while queued: dropped
+                    continue
                 if req.x is None:                   # first round of this request
                     k = req.cols()
                     req.x = np.zeros((req.b.shape[0], k))
@@ -577,7 +596,8 @@ class Server:
                 self.busy -= set(groups)
                 for key in groups:
                     for req, _ in groups[key]:
-                        req.future.set_exception(e)
+                        if not req.future.cancelled():
+                            req.future.set_exception(e)
                 self._wake.notify_all()
             return 0
         now = time.perf_counter()
@@ -601,6 +621,8 @@ class Server:
                         req.conv[c] = req.rr[c] <= self.tol
                         c0 += 1
                     finished = all(req.conv[c] or req.its[c] >= self.maxit for c in range(req.cols()))
+                    if req.future.cancelled():      # cancelled during the round: dropped
+                        continue
                     if self.cycle is None or finished:
                         x = req.x[:, 0] if req.b.ndim == 1 else req.x.copy()
                         req.future.set_result((x, req.its.astype(np.int32), req.rr.copy()))

@@ -256,6 +256,25 @@ def test_failing_batched_factorization_falls_back_to_single_jobs():
         futs["b"].result()
 
 
+def test_cancelled_requests_leave_the_queue():
+    """A cancelled solve is dropped (its future reports cancelled, no round runs
+    it), a cancelled factor request stops waiting, the other requests complete,
+    and a completed request can no longer be cancelled."""
+    rng = np.random.default_rng(10)
+    srv, be, specs = _server(10_000)
+    f_a = srv.submit("a", rng.uniform(-1, 1, specs["a"].n))
+    f_b = srv.submit("b", rng.uniform(-1, 1, specs["b"].n))
+    f_c = srv.submit("c", rng.uniform(-1, 1, specs["c"].n))
+    f_fac = srv.submit_factor("c")
+    assert srv.cancel(f_b) and f_b.cancelled()
+    assert f_fac.cancel()                             # the plain Future API does the same
+    srv.run_until_idle()
+    assert (f_a.result()[2] <= 1e-10).all() and (f_c.result()[2] <= 1e-10).all()
+    assert f_fac.cancelled()
+    assert all("b" not in keys for keys, _ in be.batches)   # no round carried b's request
+    assert not srv.cancel(f_a)
+
+
 def test_submit_validation():
     srv, be, specs = _server(10_000)
     with pytest.raises(KeyError):
