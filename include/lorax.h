@@ -338,6 +338,15 @@ lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t
  * beyond (or rows c >= 1e6).  LRX_EINVAL for a bad index or NULL outputs. */
 lrx_status lrx_compression_shape(lrx_handle h, int32_t idx, int32_t* rows, int32_t* cols);
 
+/* Residual history of the last lrx_gmres / lrx_gmres_dev / batched GMRES call on
+ * this handle for right-hand side rhs (Sec. 6.2, FGMRES with the solve as
+ * preconditioner): in order, the true relative residual ||b - A x|| / ||b|| at
+ * the start of each restart cycle, then the estimate |g_{j+1}| / ||b|| after
+ * each Arnoldi step j of that cycle.  *len = the number of values (0 before any
+ * GMRES call); at most cap are written to out (host memory, may be NULL).
+ * LRX_EINVAL for rhs outside the last call's right-hand sides. */
+lrx_status lrx_gmres_history(lrx_handle h, int32_t rhs, double* out, int32_t cap, int32_t* len);
+
 /* Host-only symbolic plan of Algorithm 1 for (A, T, order): no device call. */
 lrx_status lrx_plan_inspect(const lrx_csr* A, const lrx_tree* T, int32_t order,
                             lrx_plan_info* info);

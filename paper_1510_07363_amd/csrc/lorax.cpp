@@ -450,6 +450,9 @@ struct lrx_handle_s {
     lrx_stats_t stats{};
     std::vector<int32_t> ranks, rank_level, rank_j;
     std::vector<int32_t> comp_rows, comp_cols;   // stored stacked rows M and columns c per compression
+    // last GMRES call: per right-hand side, the relative residual at each restart
+    // (true residual) and after each Arnoldi step (estimate |g_{j+1}| / ||b||)
+    std::vector<std::vector<double>> gmres_hist;
     std::vector<double> tails;          // per compression: |R11|, ||R22||_F for k = 0..r
     std::vector<int64_t> tail_off;
     double max_tail_ratio = 0.0;
@@ -2105,6 +2108,7 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
     std::vector<double> bnorm(KR, 0.0), relres(KR, 0.0);
     std::vector<int32_t> its(KR, 0), kk(KR, 0);
     std::vector<char> active(KR, 0), conv(KR, 0), done(KR, 1);
+    for (int s = 0; s < K; ++s) hs[s]->gmres_hist.assign((size_t)nrhs, {});
     std::vector<double> H(KR * (m + 1) * m), cs(KR * m), sn(KR * m), g(KR * (m + 1));
     std::vector<char> in_cycle(K, 1);
     for (int s = 0; s < K; ++s) act[s] = 1;
@@ -2145,6 +2149,7 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
                 if (bnorm[q] == 0.0) continue;
                 relres[q] = std::sqrt(n2[k]) / bnorm[q];
                 if (!active[q]) continue;
+                hs[s]->gmres_hist[k].push_back(relres[q]);
                 if (relres[q] <= tol) { active[q] = 0; conv[q] = 1; }
                 else if (its[q] >= maxit) active[q] = 0;
                 if (active[q]) in_cycle[s] = 1;
@@ -2220,6 +2225,7 @@ lrx_status gmres_batch(int K, const lrx_handle* hs, int nrhs, const double* cons
                     gk[j] = ck[j] * gk[j];
                     its[q] += 1;
                     kk[q] = j + 1;
+                    hs[s]->gmres_hist[k].push_back(std::fabs(gk[j + 1]) / bnorm[q]);
                     if (std::fabs(gk[j + 1]) <= tol * bnorm[q] || its[q] >= maxit || den == 0.0) done[q] = 1;
                     else sys_done = false;
                 }
@@ -2875,6 +2881,21 @@ lrx_status lrx_compression_tails(lrx_handle h, int32_t idx, double* out, int32_t
         const int64_t b = (idx + 1 < (int32_t)h->tail_off.size()) ? h->tail_off[idx + 1] : (int64_t)h->tails.size();
         *len = (int32_t)(b - a);
         if (out) for (int64_t i = a; i < b && i - a < cap; ++i) out[i - a] = h->tails[i];
+        return LRX_OK;
+    });
+}
+
+lrx_status lrx_gmres_history(lrx_handle h, int32_t rhs, double* out, int32_t cap, int32_t* len) {
+    return guarded([&]() -> lrx_status {
+        check_handle(h);
+        if (!len) fail(LRX_EINVAL, "null length");
+        if (rhs < 0 || rhs >= (int32_t)h->gmres_hist.size()) {
+            if (h->gmres_hist.empty() && rhs >= 0) { *len = 0; return LRX_OK; }   // no GMRES call yet
+            fail(LRX_EINVAL, "right-hand side index out of range");
+        }
+        const std::vector<double>& v = h->gmres_hist[rhs];
+        *len = (int32_t)v.size();
+        if (out) for (int32_t i = 0; i < *len && i < cap; ++i) out[i] = v[i];
         return LRX_OK;
     });
 }

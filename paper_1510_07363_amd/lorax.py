@@ -100,7 +100,7 @@ TUNE_FIELDS = ("gemm_kc", "gemm_f64_valu", "sweep_nk_max", "compress_nt_small", 
 # every symbol declared in include/lorax.h
 EXPORTS = ("lrx_factor", "lrx_factor_dev", "lrx_factor_batch", "lrx_timing_enable", "lrx_timing_read", "lrx_solve", "lrx_solve_dev",
            "lrx_solve_batch_dev", "lrx_gmres", "lrx_gmres_dev", "lrx_gmres_batch_dev", "lrx_set_stream",
-           "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_compression_shape", "lrx_plan_inspect",
+           "lrx_free", "lrx_stats", "lrx_ranks", "lrx_compression_tails", "lrx_compression_shape", "lrx_gmres_history", "lrx_plan_inspect",
            "lrx_last_error", "lrx_version", "lrx_tune_get", "lrx_tune_set",
            "lrx_solve_dev_noalloc", "lrx_gmres_batch_dev_x0", "lrx_trim")
 
@@ -138,6 +138,7 @@ def _load():
         "lrx_ranks": (C.c_int, [C.c_void_p, i32p, i32p, i32p]),
         "lrx_compression_tails": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int32, i32p]),
         "lrx_compression_shape": (C.c_int, [C.c_void_p, C.c_int32, i32p, i32p]),
+        "lrx_gmres_history": (C.c_int, [C.c_void_p, C.c_int32, f64p, C.c_int32, i32p]),
         "lrx_plan_inspect": (C.c_int, [P(Csr), P(Tree), C.c_int32, P(PlanInfo)]),
         "lrx_last_error": (C.c_char_p, []),
         "lrx_version": (C.c_char_p, []),
@@ -385,6 +386,15 @@ class Factor:
         out = np.zeros(max(n.value, 1))
         _check(_lib.lrx_compression_tails(self._h, int(idx), _ptr(out, C.c_double), n.value,
                                           C.byref(n)))
+        return out[:n.value]
+
+    def gmres_history(self, rhs=0):
+        """Relative residuals of the last GMRES call for one right-hand side: the
+        true one at each restart, then the estimate after each Arnoldi step."""
+        n = C.c_int32()
+        _check(_lib.lrx_gmres_history(self._h, int(rhs), None, 0, C.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        _check(_lib.lrx_gmres_history(self._h, int(rhs), _ptr(out, C.c_double), n.value, C.byref(n)))
         return out[:n.value]
 
     def shape(self, idx):

@@ -207,6 +207,15 @@ def test_gmres_matches_oracle(lx):
         assert res <= TOL and rr[k] <= TOL
         o = oracle.fgmres(A, lambda v: oracle.solve(Fo, v), b[:, k], tol=TOL, restart=30)
         assert abs(int(its[k]) - o["iters"]) <= 1
+        # residual history (lrx_gmres_history): the true residual at the start of
+        # the cycle, an estimate per Arnoldi step, the true residual at the end;
+        # the oracle's FGMRES records the same sequence
+        h, ho = F.gmres_history(k), np.asarray(o["history"])
+        assert h[0] == 1.0 and len(h) >= int(its[k]) + 2 and h[-1] == pytest.approx(rr[k], rel=1e-12)
+        L = min(len(h), len(ho)) - 1
+        assert np.all(np.abs(h[:L] - ho[:L]) <= 1e-6 * ho[:L]), (h[:L], ho[:L])
+    with pytest.raises(lx.LoraxError):
+        F.gmres_history(b.shape[1])
 
 
 def test_gmres_nonconvergence_reported(lx):
