@@ -409,7 +409,7 @@ typedef struct {
                                  sqrt(c u trace(G)) are not resolved.  Blocks of more than 64 columns
                                  form G on the matrix cores and factor it in panels.  0 never, 1 in mixed
                                  precision (default), 2 in mixed and FP64 precision */
-    int32_t large_split_c;    /* stacked blocks with more columns than this (65..65536; default 192), or
+    int32_t large_split_c;    /* stacked blocks with more columns than this (65..65536; default 128), or
                                  with rows x columns >= 1e6, finish their compression in launches over
                                  many work-groups (panel LQ and block-Jacobi rounds); narrower ones
                                  above 64 columns in one work-group per block */

@@ -412,7 +412,7 @@ struct Tune {
     int32_t gemm_grid = 0;          // persistent grid of the MFMA products (0: a work-group per tile)
     int32_t solve_graph = 1;        // 1: GMRES replays its preconditioner as a captured HIP graph
     int32_t compress_gram = 1;      // 1: mixed-precision compression through the FP64 Gram matrix
-    int32_t large_split_c = 192;    // wider blocks take the split (multi-work-group) back end
+    int32_t large_split_c = 128;    // wider blocks take the split (multi-work-group) back end
 };
 Tune g_tune;
 }  // namespace
@@ -1199,7 +1199,7 @@ void run_factor(const std::vector<FactorRun*>& runs, hipStream_t st, const std::
             // with c > 64 (even keys: FP64 rows kept, odd: rows below epsilon / 100
             // dropped in mixed precision; 8 / 9: one work-group per task; 12 / 13
             // for tall blocks, M c >= 3e5: the tall QR in multi-work-group panels,
-            // the rest in one work-group; 10 / 11 for c > large_split_c (tuning, 192 by
+            // the rest in one work-group; 10 / 11 for c > large_split_c (tuning, 128 by
             // default) or M c >= 1e6: QRs in panels and the Jacobi in multi-work-group
             // block rounds; key 2 when the LDS of the large kernel does not fit; 26 / 27 and 28 / 29: R1 through
             // the FP64 Gram matrix and its pivoted Cholesky, then as 12 / 13 and

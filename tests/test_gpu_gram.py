@@ -138,7 +138,7 @@ def test_gram_large_fp64_accuracy(lx, kind, nx, leaf, eps):
     print(f"[gram large fp64] {kind} nx={nx} leaf={leaf} eps={eps}", flush=True)
     base = lx.tune_get()
     try:
-        lx.tune_set(compress_gram=2)
+        lx.tune_set(compress_gram=2, large_split_c=192)     # every back end exercised
         lx.timing_enable(["compress", "compress_gram"])
         lx.timing_read()
         F = lx.Factor(*csr, perm, lp, depth, eps)

@@ -36,7 +36,13 @@ def env():
         pytest.skip("no GPU")
     torch.cuda.set_device(0)
     from paper_1510_07363_amd import lorax
-    return lorax, torch
+    # blocks of 65..192 columns in one work-group (tall ones after the panel QR),
+    # wider ones split: every kernel family is exercised (the default threshold
+    # sends blocks beyond 128 columns to the split form)
+    base = lorax.tune_get()
+    lorax.tune_set(large_split_c=192)
+    yield lorax, torch
+    lorax.tune_set(**base)
 
 
 def _problem(kind, nx, leaf, seed=0):
